@@ -1,0 +1,256 @@
+/*
+ * pf.h - C ABI of the MI355X Newton power-flow library.
+ *
+ * The library solves the power-flow problem stated in Sec. II of
+ * "ExaGridPF: A Parallel Power Flow Solver for Transmission and Unbalanced
+ * Distribution Systems" (arXiv:1711.10579): given the nodal admittance matrix
+ * (eq. 1-3, 11), the specified active and reactive power of every bus (or
+ * phase), the voltage magnitude of voltage-controlled buses and, for
+ * three-phase feeders, the ZIP load coefficients (eq. 12-15), find the
+ * voltage magnitude and angle of every bus (phase).
+ *
+ * Two formulations share one outer Newton iteration (Sec. III):
+ *   - PF_MODEL_POLAR_1PH: single-phase polar mismatch dP/dQ (eq. 4-10),
+ *   - PF_MODEL_CIM_3PH  : three-phase current-injection mismatch dI with ZIP
+ *                         loads (eq. 12-23).
+ * and two inner linear solvers:
+ *   - PF_SOLVER_LU   : sparse LU refactorisation on a fill-reducing ordering
+ *                      with a dense trailing block (Sec. III-A),
+ *   - PF_SOLVER_GMRES: Newton-Krylov, restarted GMRES with an ILU(0) or
+ *                      block-Jacobi preconditioner (Sec. III-B).
+ *
+ * Conventions: all sizes are int32; reals are IEEE double; complex values are
+ * interleaved (re, im) pairs; powers and voltages are per unit; angles are in
+ * radians; injections are positive for generation (eq. 12).  Every pointer
+ * argument of a case description is a HOST pointer; the library copies what
+ * it needs during the call, so the caller may free or reuse its arrays as soon
+ * as the call returns.  Results are written into caller-owned host buffers.
+ *
+ * Errors: call-level failures return a non-zero pf_status and leave a message
+ * for pf_last_error() (per thread).  Numerical outcomes of a solve (converged,
+ * iteration limit, divergence, singular Jacobian, linear-solver failure) are
+ * NOT errors: they are reported in pf_result.status, one per instance.
+ */
+#ifndef PF_H_
+#define PF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_ctx pf_ctx;   /* one per device and stream                     */
+typedef struct pf_case pf_case; /* one grid: device-resident Ybus, factor, state */
+
+typedef enum {
+  PF_OK = 0,
+  PF_E_INVALID = 1, /* malformed input (see pf_create)                   */
+  PF_E_NOMEM = 2,   /* device or host allocation failed                  */
+  PF_E_DEVICE = 3,  /* HIP runtime error or no usable gfx950 device      */
+  PF_E_BUSY = 4,    /* case is queued or running in the serving loop     */
+  PF_E_NOTFOUND = 5 /* unknown ticket                                    */
+} pf_status;
+
+typedef enum {
+  PF_CONVERGED = 0,  /* max-norm of the FP64 mismatch <= tol                   */
+  PF_MAXITER = 1,    /* iteration limit reached                                */
+  PF_DIVERGED = 2,   /* non-finite mismatch or growth beyond 1e6 x initial     */
+  PF_SINGULAR = 3,   /* zero or non-finite pivot in the refactorisation        */
+  PF_LINEAR_FAIL = 4,/* GMRES did not reach its forcing tolerance              */
+  PF_PENDING = 5     /* served request not finished yet                        */
+} pf_solve_status;
+
+typedef enum { PF_MODEL_POLAR_1PH = 0, PF_MODEL_CIM_3PH = 1 } pf_model;
+/* Bus (phase-node) types.  Polar: exactly one PF_SLACK.  CIM: the source
+ * bus's phase-nodes are PF_SLACK (fixed voltage), all others PF_PQ; the paper
+ * adds no PV injection in the three-phase method (Sec. II-B). */
+typedef enum { PF_PQ = 1, PF_PV = 2, PF_SLACK = 3 } pf_bus_type;
+typedef enum { PF_SOLVER_LU = 0, PF_SOLVER_GMRES = 1 } pf_solver;
+typedef enum { PF_PREC_FP64 = 0, PF_PREC_MIXED = 1 } pf_precision;
+typedef enum { PF_PRECOND_ILU0 = 0, PF_PRECOND_BJACOBI = 1 } pf_precond;
+
+/* Case description (all HOST pointers; copied by pf_create).
+ *   n        buses (polar) or phase-nodes (CIM)
+ *   row_ptr  [n+1], col_idx [nnz]: Ybus in CSR, column indices strictly
+ *            increasing within a row, diagonal present, pattern structurally
+ *            symmetric (eq. 3)
+ *   y        [2*nnz] Ybus values, interleaved re/im (eq. 2-3, 11)
+ *   bus_type [n] pf_bus_type
+ *   p_sp, q_sp [n] polar: specified injection P_g - P_l, Q_g - Q_l (eq. 8-9,
+ *            12-13); CIM: generation P_g, Q_g (zero without DG); may be NULL
+ *            for CIM (taken as zero)
+ *   v_mag, v_ang [n] polar: |V| set-point of PV and slack buses and slack
+ *            angle; CIM: source magnitude on PF_SLACK nodes and the nominal
+ *            phase angle (0, -2pi/3, +2pi/3) of every node (flat start)
+ *   zip      CIM [6*n] per node P_Z, P_I, P_P, Q_Z, Q_I, Q_P at |V| = 1
+ *            (eq. 14-15); polar: NULL (constant-power loads only)
+ */
+typedef struct {
+  int32_t model;
+  int32_t n;
+  int32_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* y;
+  const int8_t* bus_type;
+  const double* p_sp;
+  const double* q_sp;
+  const double* v_mag;
+  const double* v_ang;
+  const double* zip;
+} pf_case_desc;
+
+/* Solve options (pf_default_options fills the defaults shown).
+ *   tol        1e-8   stop when the max-norm of the FP64 mismatch <= tol
+ *                     (pu power for polar, pu current for CIM)
+ *   max_iter   20     Newton iteration limit (40 recommended with MIXED)
+ *   solver     LU     PF_SOLVER_LU or PF_SOLVER_GMRES
+ *   precision  FP64   PF_PREC_MIXED: Jacobian factor and inner solves in FP32,
+ *                     mismatch, update and convergence test in FP64
+ *   precond    ILU0   GMRES preconditioner
+ *   gmres_m    30     GMRES restart length
+ *   gmres_max_restarts 10
+ *   eta_max    0.1    GMRES forcing term eta_k = min(eta_max, ||F_k||_inf)
+ *   flat_start 1      0: start from the case's current voltage (warm start)
+ */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t solver;
+  int32_t precision;
+  int32_t precond;
+  int32_t gmres_m;
+  int32_t gmres_max_restarts;
+  int32_t flat_start;
+  double eta_max;
+} pf_options;
+
+typedef struct {
+  int32_t status;       /* pf_solve_status                                   */
+  int32_t iters;        /* Newton steps taken (linear solves)                */
+  int32_t linear_iters; /* total GMRES iterations (0 for LU)                 */
+  int32_t reserved;
+  double mismatch_inf;  /* max-norm of the final FP64 mismatch               */
+  double max_step;      /* max |dx| of the last Newton step (the paper's test)*/
+  double device_ms;     /* device time of the solve (events around it)       */
+} pf_result;
+
+/* Static information about a created case. */
+typedef struct {
+  int32_t n;            /* buses / phase-nodes                               */
+  int32_t n_unknown;    /* nodes with unknowns (2 real unknowns each)        */
+  int32_t n_sparse;     /* nodes eliminated as sparse columns                */
+  int32_t n_dense;      /* nodes in the dense trailing block                 */
+  int32_t levels;       /* refactorisation / forward-solve levels            */
+  int32_t bwd_levels;   /* backward-solve levels                             */
+  int64_t nnz_l_blocks; /* 2x2 blocks of L (equal to U) in the sparse part   */
+  int64_t updates;      /* 2x2 block updates of the sparse refactorisation   */
+  int64_t tail_updates; /* 2x2 block updates into the dense trailing block   */
+  double flops_factor;  /* algorithmic flops of one refactorisation          */
+  size_t device_bytes;  /* device memory held by the case                    */
+  double analysis_ms;   /* host analysis time in pf_create                   */
+} pf_case_info;
+
+/* Device allocator callbacks (e.g. a framework's caching allocator). */
+typedef void* (*pf_alloc_fn)(size_t bytes, void* user);
+typedef void (*pf_free_fn)(void* ptr, void* user);
+
+/* Fill *opt with the defaults listed above. */
+void pf_default_options(pf_options* opt);
+
+/* Create a context on HIP device `device`, launching on `hip_stream` (a
+ * hipStream_t; NULL: the context creates its own stream).  Device memory comes
+ * from `alloc`/`free_` (both NULL: hipMalloc/hipFree).  Returns PF_E_DEVICE if
+ * the device is not a gfx950 GPU or HIP fails.  A context is used from one
+ * host thread at a time (the serving loop of pf_submit runs its own thread). */
+pf_status pf_ctx_create(int32_t device, void* hip_stream, pf_alloc_fn alloc, pf_free_fn free_,
+                        void* user, pf_ctx** out);
+/* Destroy a context; all its cases must have been destroyed. */
+void pf_ctx_destroy(pf_ctx* ctx);
+
+/* Validate a case, run the host symbolic analysis (ordering, symbolic LU,
+ * levels, maps) and upload everything to the device (eq. 1-3 input, Sec.
+ * III-A analysis).  PF_E_INVALID if: n < 1 or nnz < n; CSR not sorted,
+ * duplicated or out of range; a diagonal missing; pattern not structurally
+ * symmetric; non-finite values; polar without exactly one PF_SLACK or with a
+ * type outside {PQ, PV, SLACK}; CIM with a PF_PV node, without a PF_SLACK
+ * node or without zip. */
+pf_status pf_create(pf_ctx* ctx, const pf_case_desc* desc, pf_case** out);
+/* Free a case's device memory.  PF_E_BUSY while it is queued or running. */
+pf_status pf_destroy(pf_case* c);
+pf_status pf_case_info_get(const pf_case* c, pf_case_info* out);
+
+/* Replace the specified injections (same topology): p_sp/q_sp as in
+ * pf_case_desc (NULL keeps the old values), zip [6n] for CIM (NULL keeps). */
+pf_status pf_set_injections(pf_case* c, const double* p_sp, const double* q_sp, const double* zip);
+
+/* Run the Newton iteration of Sec. II-A (polar) or II-B (CIM) to completion on
+ * the context's stream and block until done. */
+pf_status pf_solve(pf_case* c, const pf_options* opt, pf_result* res);
+
+/* Solve `count` cases of one context together: every Newton phase runs as one
+ * batched launch over all still-active instances; converged instances are
+ * masked on the device.  results[i] belongs to cases[i].  Each instance's
+ * arithmetic is identical to pf_solve of that case alone. */
+pf_status pf_solve_batch(pf_ctx* ctx, pf_case* const* cases, int32_t count, const pf_options* opt,
+                         pf_result* results);
+
+/* Serving loop: enqueue a solve of `c` (non-blocking).  Requests are admitted
+ * as device memory and batch slots free up and join the running batch at the
+ * next Newton-step boundary (continuous batching).  *ticket identifies it. */
+pf_status pf_submit(pf_ctx* ctx, pf_case* c, const pf_options* opt, uint64_t* ticket);
+/* Non-blocking: *done = 1 and *out filled when the request has finished
+ * (the ticket is then released), else *done = 0.  PF_E_NOTFOUND for an
+ * unknown ticket. */
+pf_status pf_poll(pf_ctx* ctx, uint64_t ticket, pf_result* out, int32_t* done);
+/* Limit the device bytes that admitted served requests may hold (0: no
+ * limit) and the number of requests in one batch. */
+pf_status pf_serve_config(pf_ctx* ctx, size_t max_bytes, int32_t max_slots);
+
+/* Copy the case's current voltages (rectangular form) into host arrays of n
+ * doubles each. */
+pf_status pf_get_voltage(const pf_case* c, double* re, double* im);
+/* Set the case's current voltages (used by warm starts, flat_start = 0). */
+pf_status pf_set_voltage(pf_case* c, const double* re, const double* im);
+
+/* Kernel timing.  pf_profile_enable(ctx, mask) selects kernel classes by bit
+ * (1 << class; 0 disables, -1 selects all).  Every launch of a selected class
+ * is bracketed by HIP events on the launch stream; pf_kernel_stats returns
+ * the launch count, the summed device milliseconds and the summed
+ * algorithmic flops and bytes of those launches since the last reset. */
+typedef enum {
+  PF_K_MISMATCH = 0,
+  PF_K_JFILL = 1,
+  PF_K_SPARSE_FACTOR = 2,
+  PF_K_TAIL_SCHUR = 3,
+  PF_K_DENSE_PANEL = 4,
+  PF_K_DENSE_UPDATE = 5,
+  PF_K_SPARSE_FWD = 6,
+  PF_K_SPARSE_BWD = 7,
+  PF_K_DENSE_TRSV = 8,
+  PF_K_UPDATE = 9,
+  PF_K_KRYLOV = 10,
+  PF_K_COUNT = 11
+} pf_kernel_class;
+typedef struct {
+  int64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} pf_kernel_stat;
+pf_status pf_profile_enable(pf_ctx* ctx, int32_t class_mask);
+pf_status pf_kernel_stats(pf_ctx* ctx, int32_t kernel_class, pf_kernel_stat* out);
+pf_status pf_profile_reset(pf_ctx* ctx);
+
+/* Message of the last failed call on this thread (never NULL). */
+const char* pf_last_error(void);
+/* Library version string. */
+const char* pf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H_ */

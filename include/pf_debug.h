@@ -1,0 +1,37 @@
+/*
+ * pf_debug.h - host-only self-check of the symbolic analysis.
+ *
+ * Not a compute path: the solve entry points of pf.h never call it, and it
+ * touches no device.  It exists so that the fill-reducing ordering and the
+ * symbolic block LU of Sec. III-A can be tested on a machine without a GPU.
+ */
+#ifndef PF_DEBUG_H_
+#define PF_DEBUG_H_
+
+#include <stdint.h>
+
+#include "pf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Analyse the case described by `desc` exactly as pf_create does (same
+ * validation, PF_E_INVALID on bad input), then replay on the CPU every index
+ * the device kernels derive from that analysis: the Ybus-to-factor map, the
+ * update lists of each refactorisation level, the Schur lists of the dense
+ * block and the row lists of both triangular solves.  Every index is
+ * bounds-checked and every dependency checked against the level schedule
+ * (a failed check returns PF_E_INVALID with the reason in pf_last_error()).
+ * A random diagonally dominant 2x2-block matrix with the Ybus pattern (seeded
+ * by `seed`) is factored through the schedule and one random system solved;
+ * *rel_residual receives ||A x - b||_inf / (||A||_inf ||x||_inf + ||b||_inf)
+ * and *checks the number of index checks made.  Outputs are host pointers. */
+pf_status pf_debug_schedule_check(const pf_case_desc* desc, uint64_t seed, double* rel_residual,
+                                  int64_t* checks);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_DEBUG_H_ */

@@ -1,0 +1,617 @@
+// C ABI: contexts, case creation (validation, host analysis, upload), data
+// access and profiling.  The Newton driver is in newton.cpp, the serving loop
+// in serve.cpp.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace pfi {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define PF_HIP(call)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call); \
+      return PF_E_DEVICE;                                                           \
+    }                                                                               \
+  } while (0)
+
+void* Ctx::dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (alloc) return alloc(bytes, user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void Ctx::dfree(void* p) {
+  if (!p) return;
+  if (freef)
+    freef(p, user);
+  else
+    (void)hipFree(p);
+}
+
+void Ctx::prof_begin(int cls, hipEvent_t* a) {
+  *a = nullptr;
+  if (!(profile_mask & (1 << cls))) return;
+  hipEvent_t e;
+  if (!evpool.empty()) {
+    e = evpool.back();
+    evpool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return;
+  }
+  (void)hipEventRecord(e, stream);
+  *a = e;
+}
+
+void Ctx::prof_end(int cls, hipEvent_t a, double flops, double bytes) {
+  if (!a) return;
+  hipEvent_t b;
+  if (!evpool.empty()) {
+    b = evpool.back();
+    evpool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    evpool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, stream);
+  pending.push_back({cls, a, b, flops, bytes});
+}
+
+void Ctx::prof_flush() {
+  for (auto& p : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      stats[p.cls].launches += 1;
+      stats[p.cls].ms += ms;
+      stats[p.cls].flops += p.flops;
+      stats[p.cls].bytes += p.bytes;
+    }
+    evpool.push_back(p.a);
+    evpool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+pf_status validate_desc(const pf_case_desc* d) {
+  if (!d) {
+    set_error("pf_create: desc is NULL");
+    return PF_E_INVALID;
+  }
+  if (d->model != PF_MODEL_POLAR_1PH && d->model != PF_MODEL_CIM_3PH) {
+    set_error("pf_create: unknown model");
+    return PF_E_INVALID;
+  }
+  const int n = d->n, nnz = d->nnz;
+  if (n < 1 || nnz < n || !d->row_ptr || !d->col_idx || !d->y || !d->bus_type || !d->v_mag || !d->v_ang) {
+    set_error("pf_create: n < 1, nnz < n or a required array is NULL");
+    return PF_E_INVALID;
+  }
+  if (d->model == PF_MODEL_POLAR_1PH && (!d->p_sp || !d->q_sp)) {
+    set_error("pf_create: polar model needs p_sp and q_sp");
+    return PF_E_INVALID;
+  }
+  if (d->model == PF_MODEL_CIM_3PH && !d->zip) {
+    set_error("pf_create: CIM model needs zip");
+    return PF_E_INVALID;
+  }
+  if (d->row_ptr[0] != 0 || d->row_ptr[n] != nnz) {
+    set_error("pf_create: row_ptr must start at 0 and end at nnz");
+    return PF_E_INVALID;
+  }
+  for (int i = 0; i < n; ++i) {
+    int a = d->row_ptr[i], b = d->row_ptr[i + 1];
+    if (b < a) {
+      set_error("pf_create: row_ptr not non-decreasing");
+      return PF_E_INVALID;
+    }
+    bool diag = false;
+    for (int q = a; q < b; ++q) {
+      int j = d->col_idx[q];
+      if (j < 0 || j >= n) {
+        set_error("pf_create: column index out of range");
+        return PF_E_INVALID;
+      }
+      if (q > a && j <= d->col_idx[q - 1]) {
+        set_error("pf_create: columns not strictly increasing within a row (unsorted or duplicate)");
+        return PF_E_INVALID;
+      }
+      if (j == i) diag = true;
+    }
+    if (!diag) {
+      set_error("pf_create: diagonal entry missing in row " + std::to_string(i));
+      return PF_E_INVALID;
+    }
+  }
+  // structural symmetry: every (i,j) has (j,i)
+  for (int i = 0; i < n; ++i)
+    for (int q = d->row_ptr[i]; q < d->row_ptr[i + 1]; ++q) {
+      int j = d->col_idx[q];
+      const int* b = d->col_idx + d->row_ptr[j];
+      const int* e = d->col_idx + d->row_ptr[j + 1];
+      if (!std::binary_search(b, e, i)) {
+        set_error("pf_create: Ybus pattern is not structurally symmetric");
+        return PF_E_INVALID;
+      }
+    }
+  if (!finite_all(d->y, 2LL * nnz) || !finite_all(d->v_mag, n) || !finite_all(d->v_ang, n) ||
+      (d->p_sp && !finite_all(d->p_sp, n)) || (d->q_sp && !finite_all(d->q_sp, n)) ||
+      (d->zip && !finite_all(d->zip, 6LL * n))) {
+    set_error("pf_create: non-finite input value");
+    return PF_E_INVALID;
+  }
+  int nslack = 0;
+  for (int i = 0; i < n; ++i) {
+    int t = d->bus_type[i];
+    if (t != PF_PQ && t != PF_PV && t != PF_SLACK) {
+      set_error("pf_create: bus type outside {PQ, PV, SLACK}");
+      return PF_E_INVALID;
+    }
+    if (t == PF_SLACK) ++nslack;
+    if (d->model == PF_MODEL_CIM_3PH && t == PF_PV) {
+      set_error("pf_create: the current-injection model has no PV nodes");
+      return PF_E_INVALID;
+    }
+  }
+  if (d->model == PF_MODEL_POLAR_1PH && nslack != 1) {
+    set_error("pf_create: polar model needs exactly one slack bus");
+    return PF_E_INVALID;
+  }
+  if (d->model == PF_MODEL_CIM_3PH && nslack < 1) {
+    set_error("pf_create: CIM model needs source (slack) phase-nodes");
+    return PF_E_INVALID;
+  }
+  if (nslack == n) {
+    set_error("pf_create: no unknowns");
+    return PF_E_INVALID;
+  }
+  return PF_OK;
+}
+
+}  // namespace pfi
+
+using namespace pfi;
+
+template <typename X>
+static X* carve(char*& p, int64_t count) {
+  X* r = reinterpret_cast<X*>(p);
+  size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(X);
+  b = (b + 255) & ~(size_t)255;
+  p += b;
+  return r;
+}
+
+template <typename X>
+static size_t carve_size(int64_t count) {
+  size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(X);
+  return (b + 255) & ~(size_t)255;
+}
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+const char* pf_version(void) { return "exagridpf-mi355x 0.1"; }
+
+void pf_default_options(pf_options* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->max_iter = 20;
+  o->solver = PF_SOLVER_LU;
+  o->precision = PF_PREC_FP64;
+  o->precond = PF_PRECOND_ILU0;
+  o->gmres_m = 30;
+  o->gmres_max_restarts = 10;
+  o->flat_start = 1;
+  o->eta_max = 0.1;
+}
+
+pf_status pf_ctx_create(int32_t device, void* hip_stream, pf_alloc_fn alloc, pf_free_fn free_, void* user,
+                        pf_ctx** out) {
+  if (!out) {
+    set_error("pf_ctx_create: out is NULL");
+    return PF_E_INVALID;
+  }
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_ == nullptr)) {
+    set_error("pf_ctx_create: give both allocator callbacks or neither");
+    return PF_E_INVALID;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    set_error("pf_ctx_create: no HIP device");
+    return PF_E_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    set_error("pf_ctx_create: device index out of range");
+    return PF_E_INVALID;
+  }
+  hipDeviceProp_t prop;
+  PF_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("pf_ctx_create: device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return PF_E_DEVICE;
+  }
+  PF_HIP(hipSetDevice(device));
+  auto* c = new pf_ctx();
+  c->device = device;
+  c->alloc = alloc;
+  c->freef = free_;
+  c->user = user;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      set_error("pf_ctx_create: stream creation failed");
+      return PF_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return PF_OK;
+}
+
+void pf_serve_shutdown(pf_ctx* ctx);  // serve.cpp
+
+void pf_ctx_destroy(pf_ctx* ctx) {
+  if (!ctx) return;
+  pf_serve_shutdown(ctx);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->prof_flush();
+  for (auto e : ctx->evpool) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
+  if (!ctx || !out) {
+    set_error("pf_create: NULL context or out");
+    return PF_E_INVALID;
+  }
+  *out = nullptr;
+  pf_status st = validate_desc(d);
+  if (st != PF_OK) return st;
+  PF_HIP(hipSetDevice(ctx->device));
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = d->n, nnz = d->nnz;
+  pfh::GraphInput g;
+  g.n_nodes = n;
+  g.unknown.resize(n);
+  g.adj.resize(n);
+  for (int i = 0; i < n; ++i) {
+    g.unknown[i] = d->bus_type[i] != PF_SLACK;
+    for (int q = d->row_ptr[i]; q < d->row_ptr[i + 1]; ++q)
+      if (d->col_idx[q] != i) g.adj[i].push_back(d->col_idx[q]);
+  }
+  auto* c = new pf_case();
+  c->ctx = ctx;
+  c->model = d->model;
+  c->n = n;
+  c->nnz = nnz;
+  try {
+    c->an = pfh::analyze(g, 0.5, 32, 64);
+  } catch (const std::exception& ex) {
+    delete c;
+    set_error(std::string("pf_create: analysis failed: ") + ex.what());
+    return PF_E_INVALID;
+  }
+  auto& an = c->an;
+  c->nlev = (int)an.col_lev_ptr.size() - 1;
+  c->nbl = (int)an.bwd_lev_ptr.size() - 1;
+  c->ntg = (int64_t)an.ns + 2 * an.nnzl;
+  c->ntt = (int)an.tail_tgt.size();
+  c->M = 2 * an.nt;
+  c->type.assign(d->bus_type, d->bus_type + n);
+
+  // Ybus entry -> LU destination
+  std::vector<int> yrow, jmap;
+  try {
+    pfh::build_jmap(c->an, n, d->row_ptr, d->col_idx, &yrow, &jmap);
+  } catch (const std::exception& ex) {
+    delete c;
+    set_error(std::string("pf_create: ") + ex.what());
+    return PF_E_INVALID;
+  }
+  const int ns = an.ns;
+  // device layout
+  const int nu = an.nu;
+  const int64_t nupd = (int64_t)an.upd_l.size(), ntail = (int64_t)an.tail_l.size();
+  size_t total = 0;
+  total += carve_size<int>(n + 1) + 3 * carve_size<int>(nnz) + carve_size<double>(2LL * nnz);
+  total += carve_size<int8_t>(n) + 4 * carve_size<double>(n) + carve_size<double>(6LL * n);
+  total += carve_size<int>(n) + carve_size<int>(nu);
+  total += 2 * carve_size<double>(n) + 2 * carve_size<double>(2LL * n) + carve_size<double>(2LL * nu);
+  total += carve_size<double>(2LL * nu) + carve_size<double>(c->lu_count()) + carve_size<double>(4LL * ns) +
+           carve_size<double>(c->tail_count());
+  total += carve_size<int>(ns + 1) + carve_size<int>(an.nnzl) + carve_size<int64_t>(c->ntg + 1) +
+           2 * carve_size<int>(nupd) + carve_size<int>(ns);
+  total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
+  total += carve_size<int>(nu + 1) + 2 * carve_size<int>(an.nnzl) + carve_size<int>(ns);
+  total += carve_size<pfd::Red>(1);
+  c->bytes = total;
+  c->base = (char*)ctx->dalloc(total);
+  if (!c->base) {
+    delete c;
+    set_error("pf_create: device allocation failed");
+    return PF_E_NOMEM;
+  }
+  char* p = c->base;
+  c->row_ptr = carve<int>(p, n + 1);
+  c->col = carve<int>(p, nnz);
+  c->yrow = carve<int>(p, nnz);
+  c->jmap = carve<int>(p, nnz);
+  c->y = carve<double>(p, 2LL * nnz);
+  c->dtype = carve<int8_t>(p, n);
+  c->psp = carve<double>(p, n);
+  c->qsp = carve<double>(p, n);
+  c->vmag = carve<double>(p, n);
+  c->vang = carve<double>(p, n);
+  c->zip = carve<double>(p, 6LL * n);
+  c->pos = carve<int>(p, n);
+  c->node = carve<int>(p, nu);
+  c->vm = carve<double>(p, n);
+  c->va = carve<double>(p, n);
+  c->v = carve<double>(p, 2LL * n);
+  c->ibus = carve<double>(p, 2LL * n);
+  c->F = carve<double>(p, 2LL * nu);
+  c->x = carve<double>(p, 2LL * nu);
+  c->lu = carve<double>(p, c->lu_count());
+  c->dinv = carve<double>(p, 4LL * ns);
+  c->tail = carve<double>(p, c->tail_count());
+  c->colptr = carve<int>(p, ns + 1);
+  c->rowidx = carve<int>(p, an.nnzl);
+  c->uptr = carve<int64_t>(p, c->ntg + 1);
+  c->upd_l = carve<int>(p, nupd);
+  c->upd_u = carve<int>(p, nupd);
+  c->col_order = carve<int>(p, ns);
+  c->tail_tgt = carve<int>(p, c->ntt);
+  c->tail_uptr = carve<int64_t>(p, c->ntt + 1);
+  c->tail_l = carve<int>(p, ntail);
+  c->tail_u = carve<int>(p, ntail);
+  c->lrow_ptr = carve<int>(p, nu + 1);
+  c->lrow_blk = carve<int>(p, an.nnzl);
+  c->lrow_col = carve<int>(p, an.nnzl);
+  c->bwd_rows = carve<int>(p, ns);
+  c->red = carve<pfd::Red>(p, 1);
+  if ((size_t)(p - c->base) != total) {
+    ctx->dfree(c->base);
+    delete c;
+    set_error("pf_create: internal layout error");
+    return PF_E_DEVICE;
+  }
+
+  std::vector<double> zeros(n, 0.0);
+  hipStream_t s = ctx->stream;
+  auto up = [&](void* dst, const void* src, size_t b) -> bool {
+    if (b == 0) return true;
+    return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  bool ok = true;
+  ok &= up(c->row_ptr, d->row_ptr, sizeof(int) * (n + 1));
+  ok &= up(c->col, d->col_idx, sizeof(int) * nnz);
+  ok &= up(c->yrow, yrow.data(), sizeof(int) * nnz);
+  ok &= up(c->jmap, jmap.data(), sizeof(int) * nnz);
+  ok &= up(c->y, d->y, sizeof(double) * 2 * nnz);
+  ok &= up(c->dtype, d->bus_type, n);
+  ok &= up(c->psp, d->p_sp ? d->p_sp : zeros.data(), sizeof(double) * n);
+  ok &= up(c->qsp, d->q_sp ? d->q_sp : zeros.data(), sizeof(double) * n);
+  ok &= up(c->vmag, d->v_mag, sizeof(double) * n);
+  ok &= up(c->vang, d->v_ang, sizeof(double) * n);
+  if (d->zip) ok &= up(c->zip, d->zip, sizeof(double) * 6 * n);
+  ok &= up(c->pos, an.pos_of_node.data(), sizeof(int) * n);
+  ok &= up(c->node, an.node_of_pos.data(), sizeof(int) * nu);
+  ok &= up(c->colptr, an.colptr.data(), sizeof(int) * (ns + 1));
+  ok &= up(c->rowidx, an.rowidx.data(), sizeof(int) * an.nnzl);
+  ok &= up(c->uptr, an.uptr.data(), sizeof(int64_t) * (c->ntg + 1));
+  ok &= up(c->upd_l, an.upd_l.data(), sizeof(int) * nupd);
+  ok &= up(c->upd_u, an.upd_u.data(), sizeof(int) * nupd);
+  ok &= up(c->col_order, an.col_order.data(), sizeof(int) * ns);
+  ok &= up(c->tail_tgt, an.tail_tgt.data(), sizeof(int) * c->ntt);
+  ok &= up(c->tail_uptr, an.tail_uptr.data(), sizeof(int64_t) * (c->ntt + 1));
+  ok &= up(c->tail_l, an.tail_l.data(), sizeof(int) * ntail);
+  ok &= up(c->tail_u, an.tail_u.data(), sizeof(int) * ntail);
+  ok &= up(c->lrow_ptr, an.lrow_ptr.data(), sizeof(int) * (nu + 1));
+  ok &= up(c->lrow_blk, an.lrow_blk.data(), sizeof(int) * an.nnzl);
+  ok &= up(c->lrow_col, an.lrow_col.data(), sizeof(int) * an.nnzl);
+  ok &= up(c->bwd_rows, an.bwd_rows.data(), sizeof(int) * ns);
+  ok &= hipMemsetAsync(c->red, 0, sizeof(pfd::Red), s) == hipSuccess;
+  if (c->model == PF_MODEL_POLAR_1PH)
+    pfd::launch_init_polar(s, n, c->dtype, c->vmag, c->vang, c->vm, c->va, c->v, 1);
+  else
+    pfd::launch_init_cim(s, n, c->dtype, c->vmag, c->vang, c->v);
+  ok &= hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    ctx->dfree(c->base);
+    delete c;
+    set_error("pf_create: upload failed");
+    return PF_E_DEVICE;
+  }
+  // the upload is done: drop the host copies the device now owns
+  an.upd_l.clear();
+  an.upd_l.shrink_to_fit();
+  an.upd_u.clear();
+  an.upd_u.shrink_to_fit();
+  an.tail_l.clear();
+  an.tail_l.shrink_to_fit();
+  an.tail_u.clear();
+  an.tail_u.shrink_to_fit();
+  c->analysis_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ctx->ncases++;
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf_destroy(pf_case* c) {
+  if (!c) return PF_OK;
+  if (c->busy.load()) {
+    set_error("pf_destroy: case is queued or running");
+    return PF_E_BUSY;
+  }
+  (void)hipStreamSynchronize(c->ctx->stream);
+  c->ctx->dfree(c->base);
+  c->ctx->ncases--;
+  delete c;
+  return PF_OK;
+}
+
+pf_status pf_case_info_get(const pf_case* c, pf_case_info* o) {
+  if (!c || !o) {
+    set_error("pf_case_info_get: NULL argument");
+    return PF_E_INVALID;
+  }
+  const auto& an = c->an;
+  o->n = c->n;
+  o->n_unknown = an.nu;
+  o->n_sparse = an.ns;
+  o->n_dense = an.nt;
+  o->levels = c->nlev;
+  o->bwd_levels = c->nbl;
+  o->nnz_l_blocks = an.nnzl;
+  o->updates = an.uptr.empty() ? 0 : an.uptr.back();
+  o->tail_updates = an.tail_uptr.empty() ? 0 : an.tail_uptr.back();
+  o->flops_factor = an.flops_sparse + an.flops_tail_schur + an.flops_dense;
+  o->device_bytes = c->bytes;
+  o->analysis_ms = c->analysis_ms;
+  return PF_OK;
+}
+
+pf_status pf_set_injections(pf_case* c, const double* p_sp, const double* q_sp, const double* zip) {
+  if (!c) {
+    set_error("pf_set_injections: NULL case");
+    return PF_E_INVALID;
+  }
+  if (c->busy.load()) {
+    set_error("pf_set_injections: case is queued or running");
+    return PF_E_BUSY;
+  }
+  const int n = c->n;
+  if ((p_sp && !finite_all(p_sp, n)) || (q_sp && !finite_all(q_sp, n)) || (zip && !finite_all(zip, 6LL * n))) {
+    set_error("pf_set_injections: non-finite value");
+    return PF_E_INVALID;
+  }
+  if (zip && c->model != PF_MODEL_CIM_3PH) {
+    set_error("pf_set_injections: zip given for a polar case");
+    return PF_E_INVALID;
+  }
+  hipStream_t s = c->ctx->stream;
+  if (p_sp) PF_HIP(hipMemcpyAsync(c->psp, p_sp, sizeof(double) * n, hipMemcpyHostToDevice, s));
+  if (q_sp) PF_HIP(hipMemcpyAsync(c->qsp, q_sp, sizeof(double) * n, hipMemcpyHostToDevice, s));
+  if (zip) PF_HIP(hipMemcpyAsync(c->zip, zip, sizeof(double) * 6 * n, hipMemcpyHostToDevice, s));
+  PF_HIP(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+pf_status pf_get_voltage(const pf_case* c, double* re, double* im) {
+  if (!c || !re || !im) {
+    set_error("pf_get_voltage: NULL argument");
+    return PF_E_INVALID;
+  }
+  std::vector<double> v(2 * (size_t)c->n);
+  hipStream_t s = c->ctx->stream;
+  PF_HIP(hipMemcpyAsync(v.data(), c->v, sizeof(double) * 2 * c->n, hipMemcpyDeviceToHost, s));
+  PF_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < c->n; ++i) {
+    re[i] = v[2 * i];
+    im[i] = v[2 * i + 1];
+  }
+  return PF_OK;
+}
+
+pf_status pf_set_voltage(pf_case* c, const double* re, const double* im) {
+  if (!c || !re || !im) {
+    set_error("pf_set_voltage: NULL argument");
+    return PF_E_INVALID;
+  }
+  if (c->busy.load()) {
+    set_error("pf_set_voltage: case is queued or running");
+    return PF_E_BUSY;
+  }
+  const int n = c->n;
+  std::vector<double> v(2 * (size_t)n), vm(n), va(n);
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(re[i]) || !std::isfinite(im[i])) {
+      set_error("pf_set_voltage: non-finite value");
+      return PF_E_INVALID;
+    }
+    v[2 * i] = re[i];
+    v[2 * i + 1] = im[i];
+    vm[i] = std::hypot(re[i], im[i]);
+    va[i] = std::atan2(im[i], re[i]);
+  }
+  hipStream_t s = c->ctx->stream;
+  PF_HIP(hipMemcpyAsync(c->v, v.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, s));
+  PF_HIP(hipMemcpyAsync(c->vm, vm.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  PF_HIP(hipMemcpyAsync(c->va, va.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  PF_HIP(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+pf_status pf_profile_enable(pf_ctx* ctx, int32_t class_mask) {
+  if (!ctx) {
+    set_error("pf_profile_enable: NULL context");
+    return PF_E_INVALID;
+  }
+  ctx->profile_mask = class_mask;
+  return PF_OK;
+}
+
+pf_status pf_profile_reset(pf_ctx* ctx) {
+  if (!ctx) {
+    set_error("pf_profile_reset: NULL context");
+    return PF_E_INVALID;
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->prof_flush();
+  for (auto& s : ctx->stats) s = pf_kernel_stat{};
+  return PF_OK;
+}
+
+pf_status pf_kernel_stats(pf_ctx* ctx, int32_t cls, pf_kernel_stat* out) {
+  if (!ctx || !out || cls < 0 || cls >= PF_K_COUNT) {
+    set_error("pf_kernel_stats: bad argument");
+    return PF_E_INVALID;
+  }
+  PF_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->prof_flush();
+  *out = ctx->stats[cls];
+  return PF_OK;
+}
+
+pf_status pf_solve(pf_case* c, const pf_options* opt, pf_result* res) {
+  if (!c || !res) {
+    set_error("pf_solve: NULL argument");
+    return PF_E_INVALID;
+  }
+  if (c->busy.load()) {
+    set_error("pf_solve: case is queued or running");
+    return PF_E_BUSY;
+  }
+  pf_options o;
+  pf_default_options(&o);
+  if (opt) o = *opt;
+  std::lock_guard<std::mutex> lk(c->ctx->launch_mu);
+  return solve_case(c, &o, res);
+}
+
+}  // extern "C"

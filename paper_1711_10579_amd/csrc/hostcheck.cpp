@@ -1,0 +1,284 @@
+// Host self-check of the symbolic analysis (no device involved).
+//
+// Replays, on the CPU and in the same order, every index the device kernels
+// will compute from the analysis of a case: the Ybus-to-factor map, the
+// column levels with their update lists, the Schur lists of the dense block,
+// the row lists of both triangular solves.  Each index is bounds-checked and
+// each dependency is checked against the level schedule.  It then factors a
+// random diagonally dominant 2x2-block matrix with the Ybus pattern through
+// that schedule, solves one system and reports the relative residual.  This
+// is a test of the host analysis; the solve path never calls it.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <random>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pf_debug.h"
+#include "analysis.hpp"
+#include "internal.hpp"
+
+namespace pfi {
+pf_status validate_desc(const pf_case_desc* d);
+}
+
+using namespace pfi;
+
+namespace {
+
+struct Fail : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+void req(bool ok, const char* what) {
+  if (!ok) throw Fail(what);
+}
+
+}  // namespace
+
+extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, uint64_t seed, double* rel_residual,
+                                             int64_t* checks) {
+  if (!rel_residual || !checks) {
+    set_error("pf_debug_schedule_check: NULL output");
+    return PF_E_INVALID;
+  }
+  pf_status st = validate_desc(d);
+  if (st != PF_OK) return st;
+  const int n = d->n;
+  int64_t nchk = 0;
+  try {
+    pfh::GraphInput g;
+    g.n_nodes = n;
+    g.unknown.resize(n);
+    g.adj.resize(n);
+    for (int i = 0; i < n; ++i) {
+      g.unknown[i] = d->bus_type[i] != PF_SLACK;
+      for (int q = d->row_ptr[i]; q < d->row_ptr[i + 1]; ++q)
+        if (d->col_idx[q] != i) g.adj[i].push_back(d->col_idx[q]);
+    }
+    pfh::Analysis an = pfh::analyze(g, 0.5, 32, 64);
+    std::vector<int> yrow, jmap;
+    pfh::build_jmap(an, n, d->row_ptr, d->col_idx, &yrow, &jmap);
+    const int ns = an.ns, nt = an.nt, nu = an.nu, M = 2 * nt, ldt = an.ldt;
+    const int64_t nnzl = an.nnzl;
+    const int64_t nblk = ns + 2 * nnzl;
+    const int64_t ntail = (int64_t)ldt * (M + 1);
+    req(nu == ns + nt, "nu != ns + nt");
+    req(ldt >= M, "ldt < M");
+
+    // level of every sparse column and the column of every L/U block
+    std::vector<int> lev(ns, -1);
+    for (int l = 0; l + 1 < (int)an.col_lev_ptr.size(); ++l)
+      for (int k = an.col_lev_ptr[l]; k < an.col_lev_ptr[l + 1]; ++k) {
+        int j = an.col_order[k];
+        req(j >= 0 && j < ns, "col_order out of range");
+        req(lev[j] == -1, "column listed twice");
+        lev[j] = l;
+      }
+    for (int j = 0; j < ns; ++j) req(lev[j] >= 0, "column missing from the level lists");
+    auto col_of_block = [&](int64_t id) {
+      int64_t q = id < ns + nnzl ? id - ns : id - ns - nnzl;
+      return (int)(std::upper_bound(an.colptr.begin(), an.colptr.end(), (int)q) - an.colptr.begin()) - 1;
+    };
+
+    // random diagonally dominant block matrix on the pattern (position space)
+    std::mt19937_64 rng(seed);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    const int nnz = d->row_ptr[n];
+    std::vector<double> A(4 * (size_t)nnz, 0.0);
+    for (int q = 0; q < nnz; ++q) {
+      for (int r = 0; r < 4; ++r) A[4 * q + r] = U(rng);
+      if (yrow[q] == d->col_idx[q]) {
+        int deg = d->row_ptr[yrow[q] + 1] - d->row_ptr[yrow[q]];
+        A[4 * q + 0] += 4.0 * deg;
+        A[4 * q + 3] += 4.0 * deg;
+      }
+    }
+    std::vector<double> lu(4 * (size_t)nblk, 0.0), dinv(4 * (size_t)ns, 0.0);
+    std::vector<double> tail((size_t)std::max<int64_t>(ntail, 1), 0.0);
+    // scatter (the fill kernel's destinations)
+    for (int q = 0; q < nnz; ++q) {
+      int code = jmap[q];
+      ++nchk;
+      if (code == -1) {
+        req(an.pos_of_node[yrow[q]] < 0 || an.pos_of_node[d->col_idx[q]] < 0, "skipped entry has unknowns");
+        continue;
+      }
+      if (code >= 0) {
+        req(code < nblk, "jmap block id out of range");
+        for (int r = 0; r < 4; ++r) lu[4 * (size_t)code + r] = A[4 * q + r];
+      } else {
+        int t = -2 - code;
+        req(t >= 0 && t < nt * nt, "jmap tail code out of range");
+        int ta = t / nt, tb = t % nt;
+        int64_t base = (int64_t)(2 * tb) * ldt + 2 * ta;
+        req(base + ldt + 1 < ntail, "tail index out of range");
+        tail[base] = A[4 * q + 0];
+        tail[base + 1] = A[4 * q + 2];
+        tail[base + ldt] = A[4 * q + 1];
+        tail[base + ldt + 1] = A[4 * q + 3];
+      }
+    }
+    auto msub = [&](double* acc, const double* X, const double* Y) {
+      acc[0] -= X[0] * Y[0] + X[1] * Y[2];
+      acc[1] -= X[0] * Y[1] + X[1] * Y[3];
+      acc[2] -= X[2] * Y[0] + X[3] * Y[2];
+      acc[3] -= X[2] * Y[1] + X[3] * Y[3];
+    };
+    auto chk_src = [&](int64_t l_id, int64_t u_id, int lev_target) {
+      nchk += 2;
+      req(l_id >= ns && l_id < ns + nnzl, "update L id out of range");
+      req(u_id >= ns + nnzl && u_id < nblk, "update U id out of range");
+      req(lev[col_of_block(l_id)] < lev_target, "update L source not finished at its level");
+      req(lev[col_of_block(u_id)] < lev_target, "update U source not finished at its level");
+    };
+    // sparse refactorisation in level order (k_factor_cols)
+    for (int l = 0; l + 1 < (int)an.col_lev_ptr.size(); ++l)
+      for (int k = an.col_lev_ptr[l]; k < an.col_lev_ptr[l + 1]; ++k) {
+        const int j = an.col_order[k];
+        const int c0 = an.colptr[j], len = an.colptr[j + 1] - c0;
+        const int64_t tb = (int64_t)j + 2LL * c0;
+        req(tb + 2 * len + 1 < (int64_t)an.uptr.size(), "target id out of range");
+        for (int t = 0; t <= len; ++t) {
+          int64_t dest = t == 0 ? j : ns + nnzl + c0 + (t - 1);
+          req(dest < nblk, "factor dest out of range");
+          double* acc = &lu[4 * dest];
+          for (int64_t q = an.uptr[tb + t]; q < an.uptr[tb + t + 1]; ++q) {
+            chk_src(an.upd_l[q], an.upd_u[q], l);
+            msub(acc, &lu[4 * (size_t)an.upd_l[q]], &lu[4 * (size_t)an.upd_u[q]]);
+          }
+        }
+        double* D = &lu[4 * (size_t)j];
+        double det = D[0] * D[3] - D[1] * D[2];
+        req(det != 0.0, "zero pivot block");
+        double* di = &dinv[4 * (size_t)j];
+        di[0] = D[3] / det;
+        di[1] = -D[1] / det;
+        di[2] = -D[2] / det;
+        di[3] = D[0] / det;
+        for (int t = 0; t < len; ++t) {
+          int64_t dest = ns + c0 + t;
+          int64_t tg = tb + 1 + len + t;
+          double acc[4] = {lu[4 * dest], lu[4 * dest + 1], lu[4 * dest + 2], lu[4 * dest + 3]};
+          for (int64_t q = an.uptr[tg]; q < an.uptr[tg + 1]; ++q) {
+            chk_src(an.upd_l[q], an.upd_u[q], l);
+            msub(acc, &lu[4 * (size_t)an.upd_l[q]], &lu[4 * (size_t)an.upd_u[q]]);
+          }
+          lu[4 * dest + 0] = acc[0] * di[0] + acc[1] * di[2];
+          lu[4 * dest + 1] = acc[0] * di[1] + acc[1] * di[3];
+          lu[4 * dest + 2] = acc[2] * di[0] + acc[3] * di[2];
+          lu[4 * dest + 3] = acc[2] * di[1] + acc[3] * di[3];
+        }
+      }
+    // right-hand side in position space
+    std::vector<double> b(2 * (size_t)nu), x(2 * (size_t)nu);
+    for (auto& v : b) v = U(rng);
+    x = b;
+    auto fwd_row = [&](int i, int lev_i) {
+      req(i >= 0 && i < nu, "forward row out of range");
+      for (int q = an.lrow_ptr[i]; q < an.lrow_ptr[i + 1]; ++q) {
+        int id = an.lrow_blk[q], k = an.lrow_col[q];
+        ++nchk;
+        req(id >= ns && id < ns + nnzl && k >= 0 && k < ns, "forward list out of range");
+        req(lev_i < 0 || lev[k] < lev_i, "forward dependency not finished at its level");
+        const double* L = &lu[4 * (size_t)id];
+        x[2 * i] -= L[0] * x[2 * k] + L[1] * x[2 * k + 1];
+        x[2 * i + 1] -= L[2] * x[2 * k] + L[3] * x[2 * k + 1];
+      }
+    };
+    for (int l = 0; l + 1 < (int)an.col_lev_ptr.size(); ++l)
+      for (int k = an.col_lev_ptr[l]; k < an.col_lev_ptr[l + 1]; ++k) fwd_row(an.col_order[k], l);
+    for (int i = ns; i < nu; ++i) fwd_row(i, -1);
+    if (nt > 0) {
+      double* rhs = &tail[(size_t)M * ldt];
+      for (int i = ns; i < nu; ++i) {
+        rhs[2 * (i - ns)] = x[2 * i];
+        rhs[2 * (i - ns) + 1] = x[2 * i + 1];
+      }
+      // Schur complement into the dense block
+      for (size_t t = 0; t < an.tail_tgt.size(); ++t) {
+        int g2 = an.tail_tgt[t];
+        req(g2 >= 0 && g2 < nt * nt, "tail target out of range");
+        double acc[4] = {0, 0, 0, 0};
+        for (int64_t q = an.tail_uptr[t]; q < an.tail_uptr[t + 1]; ++q) {
+          chk_src(an.tail_l[q], an.tail_u[q], 1 << 30);
+          msub(acc, &lu[4 * (size_t)an.tail_l[q]], &lu[4 * (size_t)an.tail_u[q]]);
+        }
+        int ta = g2 / nt, tb = g2 % nt;
+        double* p = &tail[(size_t)(2 * tb) * ldt + 2 * ta];
+        p[0] += acc[0];
+        p[1] += acc[2];
+        p[ldt] += acc[1];
+        p[ldt + 1] += acc[3];
+      }
+      // dense LU with static pivots on [A | rhs]
+      for (int k = 0; k < M; ++k) {
+        double piv = tail[(size_t)k * ldt + k];
+        req(piv != 0.0, "zero dense pivot");
+        for (int r = k + 1; r < M; ++r) tail[(size_t)k * ldt + r] /= piv;
+        for (int c = k + 1; c <= M; ++c) {
+          double u = tail[(size_t)c * ldt + k];
+          for (int r = k + 1; r < M; ++r) tail[(size_t)c * ldt + r] -= tail[(size_t)k * ldt + r] * u;
+        }
+      }
+      for (int r = M - 1; r >= 0; --r) {
+        double v = rhs[r];
+        for (int c = r + 1; c < M; ++c) v -= tail[(size_t)c * ldt + r] * x[2 * ns + c];
+        x[2 * ns + r] = v / tail[(size_t)r * ldt + r];
+      }
+    }
+    // backward rows by level
+    std::vector<int> blev(ns, -1);
+    for (int l = 0; l + 1 < (int)an.bwd_lev_ptr.size(); ++l)
+      for (int k = an.bwd_lev_ptr[l]; k < an.bwd_lev_ptr[l + 1]; ++k) {
+        int i = an.bwd_rows[k];
+        req(i >= 0 && i < ns && blev[i] == -1, "backward row list broken");
+        blev[i] = l;
+      }
+    for (int l = 0; l + 1 < (int)an.bwd_lev_ptr.size(); ++l)
+      for (int k = an.bwd_lev_ptr[l]; k < an.bwd_lev_ptr[l + 1]; ++k) {
+        int i = an.bwd_rows[k];
+        double z0 = x[2 * i], z1 = x[2 * i + 1];
+        for (int q = an.colptr[i]; q < an.colptr[i + 1]; ++q) {
+          int jj = an.rowidx[q];
+          ++nchk;
+          req(jj > i && jj < nu, "backward column out of range");
+          req(jj >= ns || blev[jj] < l, "backward dependency not finished at its level");
+          const double* Ub = &lu[4 * (size_t)(ns + nnzl + q)];
+          z0 -= Ub[0] * x[2 * jj] + Ub[1] * x[2 * jj + 1];
+          z1 -= Ub[2] * x[2 * jj] + Ub[3] * x[2 * jj + 1];
+        }
+        const double* di = &dinv[4 * (size_t)i];
+        x[2 * i] = di[0] * z0 + di[1] * z1;
+        x[2 * i + 1] = di[2] * z0 + di[3] * z1;
+      }
+    // residual of A x = b in position space
+    std::vector<double> r(b.size());
+    for (size_t i = 0; i < r.size(); ++i) r[i] = -b[i];
+    double anorm = 0;
+    for (int q = 0; q < nnz; ++q) {
+      int pi = an.pos_of_node[yrow[q]], pj = an.pos_of_node[d->col_idx[q]];
+      if (pi < 0 || pj < 0) continue;
+      const double* a = &A[4 * (size_t)q];
+      r[2 * pi] += a[0] * x[2 * pj] + a[1] * x[2 * pj + 1];
+      r[2 * pi + 1] += a[2] * x[2 * pj] + a[3] * x[2 * pj + 1];
+      anorm = std::max(anorm, std::fabs(a[0]) + std::fabs(a[1]) + std::fabs(a[2]) + std::fabs(a[3]));
+    }
+    double rn = 0, xn = 0, bn = 0;
+    for (size_t i = 0; i < r.size(); ++i) {
+      rn = std::max(rn, std::fabs(r[i]));
+      xn = std::max(xn, std::fabs(x[i]));
+      bn = std::max(bn, std::fabs(b[i]));
+    }
+    *rel_residual = rn / (anorm * xn + bn);
+  } catch (const std::exception& e) {
+    set_error(std::string("pf_debug_schedule_check: ") + e.what());
+    *checks = nchk;
+    return PF_E_INVALID;
+  }
+  *checks = nchk;
+  return PF_OK;
+}

@@ -1,0 +1,111 @@
+// Internal objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "analysis.hpp"
+#include "device.hpp"
+
+namespace pfi {
+
+void set_error(const std::string& msg);
+
+struct Server;
+
+struct PendingEvent {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  pf_alloc_fn alloc = nullptr;
+  pf_free_fn freef = nullptr;
+  void* user = nullptr;
+  int profile_mask = 0;
+  pf_kernel_stat stats[PF_K_COUNT] = {};
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> evpool;
+  std::atomic<int> ncases{0};
+  std::shared_ptr<Server> server;  // created by serve.cpp (complete type there)
+  std::mutex launch_mu;  // serialises launches of the serving thread and callers
+
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+  void prof_begin(int cls, hipEvent_t* a);
+  void prof_end(int cls, hipEvent_t a, double flops, double bytes);
+  void prof_flush();  // after a stream synchronisation
+};
+
+// One case: device-resident Ybus, set-points, factor storage and state.
+struct Case {
+  Ctx* ctx = nullptr;
+  int model = 0;
+  int n = 0, nnz = 0;
+  pfh::Analysis an;
+  int nlev = 0, nbl = 0;
+  int64_t ntg = 0;
+  int ntt = 0;
+  int M = 0;  // order of the dense block (2 nt)
+  double analysis_ms = 0;
+  std::atomic<int> busy{0};
+
+  // host copies of set-points (for pf_set_injections and the case info)
+  std::vector<int8_t> type;
+
+  // one device allocation, carved into the arrays below
+  char* base = nullptr;
+  size_t bytes = 0;
+
+  int *row_ptr = nullptr, *col = nullptr, *yrow = nullptr, *jmap = nullptr;
+  double* y = nullptr;
+  int8_t* dtype = nullptr;
+  double *psp = nullptr, *qsp = nullptr, *vmag = nullptr, *vang = nullptr, *zip = nullptr;
+  int *pos = nullptr, *node = nullptr;
+  double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
+  void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr;
+  int *colptr = nullptr, *rowidx = nullptr, *upd_l = nullptr, *upd_u = nullptr, *col_order = nullptr;
+  int64_t* uptr = nullptr;
+  int *tail_tgt = nullptr, *tail_l = nullptr, *tail_u = nullptr;
+  int64_t* tail_uptr = nullptr;
+  int *lrow_ptr = nullptr, *lrow_blk = nullptr, *lrow_col = nullptr, *bwd_rows = nullptr;
+  pfd::Red* red = nullptr;
+
+  int64_t lu_count() const { return 4LL * (an.ns + 2 * an.nnzl); }
+  int64_t tail_count() const { return (int64_t)an.ldt * (M + 1); }
+  pfd::Sched sched() const {
+    pfd::Sched s;
+    s.colptr = colptr;
+    s.rowidx = rowidx;
+    s.uptr = uptr;
+    s.upd_l = upd_l;
+    s.upd_u = upd_u;
+    s.ns = an.ns;
+    s.nt = an.nt;
+    s.ldt = an.ldt;
+    s.nnzl = an.nnzl;
+    return s;
+  }
+};
+
+pf_status solve_case(Case* c, const pf_options* opt, pf_result* res);
+
+}  // namespace pfi
+
+struct pf_ctx : pfi::Ctx {};
+struct pf_case : pfi::Case {};

@@ -1,0 +1,195 @@
+"""GPU parity of the Newton power flow against the CPU oracle (through the C ABI).
+
+Acceptance: the GPU reports convergence at max-norm FP64 mismatch <= 1e-8 pu,
+the oracle's own mismatch evaluated at the GPU voltages is <= 1e-8, and every
+voltage (magnitude and angle, in pu / rad) is within 1e-7 of the oracle's root.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import pfgen
+from oracle import cim, polar
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+VTOL = 1e-7
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1711_10579_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.pf_ctx_create(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_solve(B, ctx, case, **opts):
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, **opts)
+    V = B.pf_get_voltage(h)
+    return h, r, V
+
+
+def check_polar(case, r, V, ref=None):
+    assert r.status == 0, (case.name, r.as_dict())
+    assert r.mismatch_inf <= TOL
+    assert polar.mismatch_at(case, V) <= TOL
+    ref = ref or polar.newton(case)
+    assert ref.status == 0
+    dvm = np.max(np.abs(np.abs(V) - ref.vm))
+    dva = np.max(np.abs(np.angle(V) - ref.va))
+    assert dvm <= VTOL and dva <= VTOL, (case.name, dvm, dva)
+    return dvm, dva
+
+
+def check_cim(case, r, V, ref=None):
+    assert r.status == 0, (case.name, r.as_dict())
+    assert r.mismatch_inf <= TOL
+    assert cim.mismatch_at(case, V) <= TOL
+    ref = ref or cim.newton(case)
+    assert ref.status == 0
+    dvm = np.max(np.abs(np.abs(V) - ref.vm))
+    dva = np.max(np.abs(np.angle(V * np.conj(ref.V))))
+    assert dvm <= VTOL and dva <= VTOL, (case.name, dvm, dva)
+    return dvm, dva
+
+
+POLAR_SIZES = [(2, 0, 0), (3, 1, 1), (30, 12, 5), (64, 20, 6), (100, 30, 10), (257, 77, 25),
+               (1000, 300, 100), (3001, 900, 300)]
+
+
+@pytest.mark.parametrize("n,extra,npv", POLAR_SIZES, ids=[f"n{s[0]}" for s in POLAR_SIZES])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_polar_parity_sizes(B, ctx, n, extra, npv, precision):
+    case = pfgen.make_polar_grid(n, extra, npv, 1000 + n, balanced=n > 30)
+    _say(f"polar n={n} precision={precision}")
+    h, r, V = gpu_solve(B, ctx, case, precision=precision, max_iter=40 if precision else 20)
+    check_polar(case, r, V)
+
+
+def test_polar_reference_30_bus(B, ctx):
+    case = pfgen.config_case(0)
+    _say("polar grid30")
+    h, r, V = gpu_solve(B, ctx, case)
+    ref = polar.newton(case)
+    check_polar(case, r, V, ref)
+    # Newton steps until the oracle's mismatch first drops to the tolerance
+    assert r.iters == next(k for k, h in enumerate(ref.history) if h <= TOL)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_polar_reference_10k_bus(B, ctx, precision):
+    case = pfgen.config_case(1)
+    _say(f"polar grid10k precision={precision}")
+    h, r, V = gpu_solve(B, ctx, case, precision=precision, max_iter=40 if precision else 20)
+    info = B.pf_case_info_get(h)
+    assert info["n_dense"] > 100  # the meshed grid has a dense trailing block
+    check_polar(case, r, V)
+
+
+FEEDERS = [(2, 1), (5, 2), (30, 3), (200, 4), (777, 5)]
+
+
+@pytest.mark.parametrize("nb,seed", FEEDERS, ids=[f"nb{f[0]}" for f in FEEDERS])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_cim_parity_sizes(B, ctx, nb, seed, precision):
+    case = pfgen.make_feeder(nb, seed)
+    _say(f"cim nb={nb} precision={precision}")
+    h, r, V = gpu_solve(B, ctx, case, precision=precision, max_iter=40 if precision else 20)
+    check_cim(case, r, V)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_cim_reference_feeder(B, ctx, precision):
+    case = pfgen.config_case(2)
+    _say(f"cim feeder2k precision={precision}")
+    h, r, V = gpu_solve(B, ctx, case, precision=precision, max_iter=40 if precision else 20)
+    check_cim(case, r, V)
+
+
+@pytest.mark.parametrize("mode", ["Z", "I", "P"])
+def test_cim_pure_load_types(B, ctx, mode):
+    case = pfgen.make_feeder(150, 40, zip_mode=mode, load_scale=20.0)
+    _say(f"cim zip={mode}")
+    h, r, V = gpu_solve(B, ctx, case)
+    check_cim(case, r, V)
+    if mode == "Z":
+        assert r.iters == 1  # the mismatch is linear in V
+
+
+def test_statuses(B, ctx):
+    c0 = pfgen.config_case(0)
+    _say("statuses")
+    h, r, V = gpu_solve(B, ctx, c0, max_iter=1)
+    assert r.status == B.PF_MAXITER and r.iters == 1
+    heavy = c0.with_injections(c0.p_sp * 50, c0.q_sp * 50)
+    h, r, V = gpu_solve(B, ctx, heavy)
+    assert r.status in (B.PF_DIVERGED, B.PF_MAXITER)
+    assert polar.newton(heavy).status in (2, 1)
+
+
+def test_singular_islanded_bus(B, ctx):
+    import pins
+
+    c = pins.polar_case(3, [0], [1], [0.02], [0.1], [0.0], [3, 1, 1],
+                        [0, -0.3, -0.1], [0, -0.1, -0.05], [1, 1, 1])
+    c.row_ptr = np.array([0, 2, 4, 5], np.int32)
+    c.col = np.array([0, 1, 0, 1, 2], np.int32)
+    c.y = np.concatenate([c.y, [0j]])
+    _say("singular")
+    h, r, V = gpu_solve(B, ctx, c)
+    assert r.status == B.PF_SINGULAR
+    assert polar.newton(c).status == 3
+
+
+def test_deterministic_and_warm_start(B, ctx):
+    case = pfgen.make_polar_grid(1000, 300, 100, 77, balanced=True)
+    _say("determinism")
+    h = B.pf_create_from(ctx, case)
+    r1 = B.pf_solve(h)
+    V1 = B.pf_get_voltage(h)
+    r2 = B.pf_solve(h)
+    V2 = B.pf_get_voltage(h)
+    assert np.array_equal(V1, V2) and r1.iters == r2.iters
+    r3 = B.pf_solve(h, flat_start=0)
+    assert r3.status == 0 and r3.iters == 0
+
+
+def test_set_injections_matches_oracle(B, ctx):
+    base = pfgen.make_polar_grid(500, 150, 50, 5, balanced=True)
+    pert = pfgen.perturb_loads(base, 9)
+    _say("set_injections")
+    h = B.pf_create_from(ctx, base)
+    B.pf_set_injections(h, pert.p_sp, pert.q_sp)
+    r = B.pf_solve(h)
+    check_polar(pert, r, B.pf_get_voltage(h))
+
+
+def test_torch_allocator_and_stream(B):
+    import torch
+
+    _say("torch allocator")
+    ctx = B.pf_ctx_create(0, use_torch=True)
+    case = pfgen.make_polar_grid(400, 120, 40, 6, balanced=True)
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h)
+    check_polar(case, r, B.pf_get_voltage(h))
+    torch.cuda.synchronize()
+    h.close()
+    ctx.close()

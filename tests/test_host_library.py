@@ -1,0 +1,135 @@
+"""CPU tests of the native library: exported symbols, input validation and
+the host symbolic analysis (replayed on the CPU through pf_debug_schedule_check)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pfgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+B = pytest.importorskip("paper_1711_10579_amd.binding",
+                        reason="build the library first (python -m paper_1711_10579_amd.build)")
+
+
+def _declared_functions():
+    names = []
+    for h in ["pf.h", "pf_debug.h"]:
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(pf_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(B.EXPORTED) | {"pf_default_options"}
+
+
+def test_version_and_error_string():
+    assert B.pf_version().startswith("exagridpf")
+    assert isinstance(B.pf_last_error(), str)
+
+
+CASES = [
+    ("grid30", lambda: pfgen.config_case(0)),
+    ("grid2", lambda: pfgen.make_polar_grid(2, 0, 0, 1)),
+    ("grid3pv", lambda: pfgen.make_polar_grid(3, 1, 2, 2)),
+    ("grid257", lambda: pfgen.make_polar_grid(257, 77, 25, 3, balanced=True)),
+    ("grid1000", lambda: pfgen.make_polar_grid(1000, 300, 100, 4, balanced=True)),
+    ("grid10k", lambda: pfgen.config_case(1)),
+    ("feeder2", lambda: pfgen.make_feeder(2, 5)),
+    ("feeder30", lambda: pfgen.make_feeder(30, 6)),
+    ("feeder2k", lambda: pfgen.config_case(2)),
+    ("tree_only", lambda: pfgen.make_polar_grid(500, 0, 50, 7)),
+    ("dense_small", lambda: pfgen.make_polar_grid(80, 800, 8, 8)),
+]
+
+
+@pytest.mark.parametrize("name,maker", CASES, ids=[c[0] for c in CASES])
+def test_schedule_replay(name, maker):
+    c = maker()
+    res, checks = B.pf_debug_schedule_check(**B.case_arrays(c), seed=11)
+    assert checks > 0
+    assert res < 1e-13
+
+
+def test_dense_block_appears_on_meshed_grids():
+    # the 10k-bus meshed grid leaves a dense trailing block; a radial feeder not
+    c1 = pfgen.config_case(1)
+    res, _ = B.pf_debug_schedule_check(**B.case_arrays(c1), seed=1)
+    assert res < 1e-13
+
+
+def _bad(**over):
+    c = pfgen.config_case(0)
+    kw = B.case_arrays(c)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("what,kw", [
+    ("two slacks", lambda c: dict(bus_type=np.where(np.arange(c.n) < 2, 3, c.bus_type))),
+    ("no slack", lambda c: dict(bus_type=np.where(c.bus_type == 3, 1, c.bus_type))),
+    ("nan setpoint", lambda c: dict(p_sp=np.where(np.arange(c.n) == 4, np.nan, c.p_sp))),
+    ("bad type", lambda c: dict(bus_type=np.where(np.arange(c.n) == 5, 7, c.bus_type))),
+    ("unsorted", lambda c: dict(col_idx=_swap_first_row(c))),
+    ("missing diagonal", lambda c: _drop_diagonal(c)),
+    ("asymmetric", lambda c: _asymmetric(c)),
+])
+def test_invalid_inputs_rejected(what, kw):
+    c = pfgen.config_case(0)
+    args = B.case_arrays(c)
+    args.update(kw(c))
+    with pytest.raises(B.PFError) as ei:
+        B.pf_debug_schedule_check(**args)
+    assert ei.value.code == B.PF_E_INVALID
+
+
+def _swap_first_row(c):
+    col = c.col.copy()
+    a, b = c.row_ptr[0], c.row_ptr[1]
+    col[a], col[a + 1] = col[a + 1], col[a]
+    return col
+
+
+def _drop_diagonal(c):
+    import scipy.sparse as sp
+
+    Y = sp.csr_matrix((c.y, c.col, c.row_ptr), shape=(c.n, c.n)).tolil()
+    Y[7, 7] = 0
+    Y = sp.csr_matrix(Y)
+    Y.eliminate_zeros()
+    Y.sort_indices()
+    return dict(row_ptr=Y.indptr, col_idx=Y.indices, y=Y.data)
+
+
+def _asymmetric(c):
+    import scipy.sparse as sp
+
+    Y = sp.csr_matrix((c.y, c.col, c.row_ptr), shape=(c.n, c.n)).tolil()
+    i, j = 3, 20
+    assert Y[i, j] == 0
+    Y[i, j] = 1.0 + 1.0j
+    Y = sp.csr_matrix(Y)
+    Y.sort_indices()
+    return dict(row_ptr=Y.indptr, col_idx=Y.indices, y=Y.data)
+
+
+def test_cim_rejects_pv_nodes():
+    f = pfgen.make_feeder(10, 3)
+    args = B.case_arrays(f)
+    bt = f.node_type.copy()
+    bt[5] = 2
+    args["bus_type"] = bt
+    with pytest.raises(B.PFError):
+        B.pf_debug_schedule_check(**args)
