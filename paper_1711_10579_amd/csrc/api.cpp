@@ -323,6 +323,46 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->ntt = (int)an.tail_tgt.size();
   c->M = 2 * an.nt;
   c->type.assign(d->bus_type, d->bus_type + n);
+  {
+    auto pick = [](int64_t m) {
+      int g = 1;
+      while (g < 64 && 4LL * g < m) g *= 2;
+      return g;
+    };
+    c->fac_g.resize(c->nlev);
+    c->fwd_g.resize(c->nlev);
+    c->fac_flops.resize(c->nlev);
+    c->fac_bytes.resize(c->nlev);
+    for (int l = 0; l < c->nlev; ++l) {
+      int64_t mf = 0, mr = 0;
+      double upd = 0, blocks = 0;
+      for (int k = an.col_lev_ptr[l]; k < an.col_lev_ptr[l + 1]; ++k) {
+        int j = an.col_order[k];
+        int len = an.colptr[j + 1] - an.colptr[j];
+        int64_t t0 = j + 2LL * an.colptr[j];
+        for (int t = 0; t <= 2 * len; ++t) mf = std::max(mf, an.uptr[t0 + t + 1] - an.uptr[t0 + t]);
+        mr = std::max<int64_t>(mr, an.lrow_ptr[j + 1] - an.lrow_ptr[j]);
+        upd += (double)(an.uptr[t0 + 1 + 2 * len] - an.uptr[t0]);
+        blocks += 1 + 2 * len;
+      }
+      c->fac_g[l] = pick(mf);
+      c->fwd_g[l] = pick(mr);
+      c->fac_flops[l] = 16.0 * upd + 40.0 * blocks;
+      c->fac_bytes[l] = 8.0 * upd + 2 * 32.0 * blocks;  // index pairs + read/write of target blocks (FP64)
+    }
+    int64_t mt = 0;
+    for (int i = an.ns; i < an.nu; ++i) mt = std::max<int64_t>(mt, an.lrow_ptr[i + 1] - an.lrow_ptr[i]);
+    c->tailfwd_g = pick(mt);
+    c->bwd_g.resize(c->nbl);
+    for (int l = 0; l < c->nbl; ++l) {
+      int64_t m = 0;
+      for (int k = an.bwd_lev_ptr[l]; k < an.bwd_lev_ptr[l + 1]; ++k) {
+        int i = an.bwd_rows[k];
+        m = std::max<int64_t>(m, an.colptr[i + 1] - an.colptr[i]);
+      }
+      c->bwd_g[l] = pick(m);
+    }
+  }
 
   // Ybus entry -> LU destination
   std::vector<int> yrow, jmap;
@@ -343,12 +383,12 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   total += carve_size<int>(n) + carve_size<int>(nu);
   total += 2 * carve_size<double>(n) + 2 * carve_size<double>(2LL * n) + carve_size<double>(2LL * nu);
   total += carve_size<double>(2LL * nu) + carve_size<double>(c->lu_count()) + carve_size<double>(4LL * ns) +
-           carve_size<double>(c->tail_count());
+           carve_size<double>(c->tail_count()) + 2 * carve_size<double>(c->dfac_count()) + carve_size<int>(c->nblk());
   total += carve_size<int>(ns + 1) + carve_size<int>(an.nnzl) + carve_size<int64_t>(c->ntg + 1) +
            2 * carve_size<int>(nupd) + carve_size<int>(ns);
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
   total += carve_size<int>(nu + 1) + 2 * carve_size<int>(an.nnzl) + carve_size<int>(ns);
-  total += carve_size<pfd::Red>(1);
+  total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1);
   c->bytes = total;
   c->base = (char*)ctx->dalloc(total);
   if (!c->base) {
@@ -379,6 +419,9 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->lu = carve<double>(p, c->lu_count());
   c->dinv = carve<double>(p, 4LL * ns);
   c->tail = carve<double>(p, c->tail_count());
+  c->dfac = carve<double>(p, c->dfac_count());
+  c->dinvu = carve<double>(p, c->dfac_count());
+  c->dflags = carve<int>(p, c->nblk());
   c->colptr = carve<int>(p, ns + 1);
   c->rowidx = carve<int>(p, an.nnzl);
   c->uptr = carve<int64_t>(p, c->ntg + 1);
@@ -394,6 +437,7 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->lrow_col = carve<int>(p, an.nnzl);
   c->bwd_rows = carve<int>(p, ns);
   c->red = carve<pfd::Red>(p, 1);
+  c->d_inst = carve<pfd::Inst>(p, 1);
   if ((size_t)(p - c->base) != total) {
     ctx->dfree(c->base);
     delete c;
@@ -436,10 +480,83 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   ok &= up(c->lrow_col, an.lrow_col.data(), sizeof(int) * an.nnzl);
   ok &= up(c->bwd_rows, an.bwd_rows.data(), sizeof(int) * ns);
   ok &= hipMemsetAsync(c->red, 0, sizeof(pfd::Red), s) == hipSuccess;
-  if (c->model == PF_MODEL_POLAR_1PH)
-    pfd::launch_init_polar(s, n, c->dtype, c->vmag, c->vang, c->vm, c->va, c->v, 1);
-  else
-    pfd::launch_init_cim(s, n, c->dtype, c->vmag, c->vang, c->v);
+  ok &= hipMemsetAsync(c->dflags, 0, sizeof(int) * std::max(c->nblk(), 1), s) == hipSuccess;
+  {
+    pfd::Inst hi;
+    std::memset(&hi, 0, sizeof hi);
+    hi.model = c->model;
+    hi.n = n;
+    hi.nnz = nnz;
+    hi.nu = nu;
+    hi.ns = ns;
+    hi.nt = an.nt;
+    hi.ldt = an.ldt;
+    hi.M = c->M;
+    hi.ntt = c->ntt;
+    hi.nblk = c->nblk();
+    hi.nnzl = an.nnzl;
+    hi.lu_count = c->lu_count();
+    hi.tail_count = an.nt > 0 ? c->tail_count() : 0;
+    hi.row_ptr = c->row_ptr;
+    hi.col = c->col;
+    hi.yrow = c->yrow;
+    hi.jmap = c->jmap;
+    hi.y = c->y;
+    hi.type = c->dtype;
+    hi.psp = c->psp;
+    hi.qsp = c->qsp;
+    hi.vmag = c->vmag;
+    hi.vang = c->vang;
+    hi.zip = c->zip;
+    hi.pos = c->pos;
+    hi.node = c->node;
+    hi.vm = c->vm;
+    hi.va = c->va;
+    hi.v = c->v;
+    hi.ibus = c->ibus;
+    hi.F = c->F;
+    hi.x = c->x;
+    hi.lu = c->lu;
+    hi.dinv = c->dinv;
+    hi.tail = c->tail;
+    hi.dfac = c->dfac;
+    hi.dinvu = c->dinvu;
+    hi.dflags = c->dflags;
+    hi.colptr = c->colptr;
+    hi.rowidx = c->rowidx;
+    hi.upd_l = c->upd_l;
+    hi.upd_u = c->upd_u;
+    hi.uptr = c->uptr;
+    hi.tail_tgt = c->tail_tgt;
+    hi.tail_l = c->tail_l;
+    hi.tail_u = c->tail_u;
+    hi.tail_uptr = c->tail_uptr;
+    hi.lrow_ptr = c->lrow_ptr;
+    hi.lrow_blk = c->lrow_blk;
+    hi.lrow_col = c->lrow_col;
+    hi.red = c->red;
+    ok &= up(c->d_inst, &hi, sizeof hi);
+    // flat-start voltages so that pf_get_voltage is defined before a solve
+    std::vector<double> v0(2 * (size_t)n), vm0(n), va0(n);
+    for (int i = 0; i < n; ++i) {
+      const int t = d->bus_type[i];
+      double m, a;
+      if (c->model == PF_MODEL_POLAR_1PH) {
+        m = t == PF_PQ ? 1.0 : d->v_mag[i];
+        a = t == PF_SLACK ? d->v_ang[i] : 0.0;
+      } else {
+        m = t == PF_SLACK ? d->v_mag[i] : 1.0;
+        a = d->v_ang[i];
+      }
+      vm0[i] = m;
+      va0[i] = a;
+      v0[2 * i] = m * std::cos(a);
+      v0[2 * i + 1] = m * std::sin(a);
+    }
+    ok &= up(c->v, v0.data(), sizeof(double) * 2 * n);
+    ok &= up(c->vm, vm0.data(), sizeof(double) * n);
+    ok &= up(c->va, va0.data(), sizeof(double) * n);
+  }
   ok &= hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
     ctx->dfree(c->base);
@@ -469,6 +586,8 @@ pf_status pf_destroy(pf_case* c) {
     return PF_E_BUSY;
   }
   (void)hipStreamSynchronize(c->ctx->stream);
+  delete c->single;
+  c->single = nullptr;
   c->ctx->dfree(c->base);
   c->ctx->ncases--;
   delete c;

@@ -23,6 +23,7 @@ namespace pfi {
 void set_error(const std::string& msg);
 
 struct Server;
+struct Batch;
 
 struct PendingEvent {
   int cls;
@@ -67,6 +68,11 @@ struct Case {
 
   // host copies of set-points (for pf_set_injections and the case info)
   std::vector<int8_t> type;
+  // lanes per list (power of two) of each level, and the per-level
+  // algorithmic flops / bytes of the refactorisation (profiling)
+  std::vector<int> fac_g, fwd_g, bwd_g;
+  int tailfwd_g = 1;
+  std::vector<double> fac_flops, fac_bytes;
 
   // one device allocation, carved into the arrays below
   char* base = nullptr;
@@ -78,31 +84,57 @@ struct Case {
   double *psp = nullptr, *qsp = nullptr, *vmag = nullptr, *vang = nullptr, *zip = nullptr;
   int *pos = nullptr, *node = nullptr;
   double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
-  void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr;
+  void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dfac = nullptr, *dinvu = nullptr;
+  int* dflags = nullptr;  // per 64-row block of the dense block: backward-solve flags
   int *colptr = nullptr, *rowidx = nullptr, *upd_l = nullptr, *upd_u = nullptr, *col_order = nullptr;
   int64_t* uptr = nullptr;
   int *tail_tgt = nullptr, *tail_l = nullptr, *tail_u = nullptr;
   int64_t* tail_uptr = nullptr;
   int *lrow_ptr = nullptr, *lrow_blk = nullptr, *lrow_col = nullptr, *bwd_rows = nullptr;
   pfd::Red* red = nullptr;
+  pfd::Inst* d_inst = nullptr;  // device descriptor
+  Batch* single = nullptr;      // cached batch of this case alone
 
   int64_t lu_count() const { return 4LL * (an.ns + 2 * an.nnzl); }
   int64_t tail_count() const { return (int64_t)an.ldt * (M + 1); }
-  pfd::Sched sched() const {
-    pfd::Sched s;
-    s.colptr = colptr;
-    s.rowidx = rowidx;
-    s.uptr = uptr;
-    s.upd_l = upd_l;
-    s.upd_u = upd_u;
-    s.ns = an.ns;
-    s.nt = an.nt;
-    s.ldt = an.ldt;
-    s.nnzl = an.nnzl;
-    return s;
-  }
+  int nblk() const { return (M + 63) / 64; }
+  int64_t dfac_count() const { return (int64_t)nblk() * 64 * 64; }
 };
 
+// One kernel launch of the linear-solve sequence of a batch.
+struct Launch {
+  int kind;        // Launch kinds below
+  int G;           // lanes per list
+  int k0;          // dense panel step
+  int cls;         // pf_kernel_class for profiling
+  int64_t off;     // first work item
+  int count;       // work items
+  double flops, bytes;
+};
+enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_GEMM, L_TRSV, L_BWD };
+
+// A batch of cases: device instance table, flattened work lists and the
+// launch sequence of one Newton step's LU solve.  Each item's arithmetic
+// depends only on its own instance.
+struct Batch {
+  Ctx* ctx = nullptr;
+  std::vector<Case*> cases;
+  int nslots = 0;
+  char* dmem = nullptr;  // instance pointer table, work items, Red gather buffer
+  const pfd::Inst* const* d_insts = nullptr;
+  int2* d_work = nullptr;
+  pfd::Red* d_reds = nullptr;
+  std::vector<Launch> seq;
+  int max_n = 0, max_nnz = 0, max_nu = 0;
+  int64_t max_lu = 0, max_tail = 0;
+  int trsv_single = 0;
+
+  ~Batch();
+  bool build(Ctx* ctx, const std::vector<Case*>& cs);
+};
+
+// Run the Newton iteration of every case of a built batch to completion.
+pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);
 pf_status solve_case(Case* c, const pf_options* opt, pf_result* res);
 
 }  // namespace pfi

@@ -1,14 +1,15 @@
 // HIP kernels of the Newton power-flow iteration for gfx950 (wave64).
 //
 // Per Newton step (Sec. II-A and II-B iteration tables, Sec. III-A solve):
-//   mismatch (FP64) -> Jacobian fill into LU storage -> sparse block
+//   convergence test -> Jacobian fill into LU storage -> sparse block
 //   refactorisation by elimination-tree levels -> forward solve -> Schur
 //   update of the dense trailing block -> dense LU of that block with the
-//   right-hand side appended -> dense backward solve -> sparse backward
-//   solve -> voltage update (FP64).
+//   right-hand side appended (dense.hip) -> dense backward solve -> sparse
+//   backward solve -> voltage update -> mismatch.
 // Value type T of the factor and the inner solves is double (plain) or float
 // (mixed precision); the mismatch, the update and the convergence test are
-// always double.
+// always double.  Every kernel takes the batch's instance table; instances
+// whose Newton iteration has finished are skipped.
 
 #include <hip/hip_runtime.h>
 
@@ -26,6 +27,14 @@ namespace pfd {
 __device__ inline void atomic_max_nonneg(unsigned long long* slot, double v) {
   // |x| and NaN (positive quiet NaN bits) both order correctly as integers
   atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double wave_max(double local) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(local, off, 64);
+    local = (o > local || o != o) ? o : local;
+  }
+  return local;
 }
 
 template <typename T>
@@ -72,51 +81,115 @@ __device__ inline Blk<T> blk_mul(const Blk<T>& X, const Blk<T>& Y) {
   return r;
 }
 
+template <typename T, int G>
+__device__ inline Blk<T> group_sum(Blk<T> v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    v.a += __shfl_xor(v.a, off, 64);
+    v.b += __shfl_xor(v.b, off, 64);
+    v.c += __shfl_xor(v.c, off, 64);
+    v.d += __shfl_xor(v.d, off, 64);
+  }
+  return v;
+}
+
+__device__ inline bool inactive(const Inst& I) { return I.red->active == 0; }
+
 // ---------------------------------------------------------------------------
-// state initialisation and update
+// Newton driver on the device
 
-// Polar flat start: |V| = 1 on PQ buses, set-point elsewhere; angle 0 but the
-// slack's set-point.  Also writes the rectangular voltage v[2i], v[2i+1].
-__global__ void k_init_polar(int n, const int8_t* __restrict__ type, const double* __restrict__ vmag,
-                             const double* __restrict__ vang, double* vm, double* va, double* v,
-                             int flat) {
+// Start of a solve: flat start (polar: |V| = 1 on PQ buses, set-point
+// elsewhere, angle 0 but the slack's set-point; CIM: magnitude 1, source
+// set-point on source nodes, at the node's nominal phase angle) or the
+// stored voltage, and the rectangular voltage v.
+__global__ void k_init(const Inst* const* insts, int flat) {
+  const Inst& I = *insts[blockIdx.y];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= I.n) return;
   double m, a;
-  if (flat) {
-    m = type[i] == 1 ? 1.0 : vmag[i];
-    a = type[i] == 3 ? vang[i] : 0.0;
-    vm[i] = m;
-    va[i] = a;
+  if (I.model == 0) {
+    if (flat) {
+      m = I.type[i] == 1 ? 1.0 : I.vmag[i];
+      a = I.type[i] == 3 ? I.vang[i] : 0.0;
+      I.vm[i] = m;
+      I.va[i] = a;
+    } else {
+      m = I.vm[i];
+      a = I.va[i];
+    }
+    double s, c;
+    sincos(a, &s, &c);
+    I.v[2 * i] = m * c;
+    I.v[2 * i + 1] = m * s;
+  } else if (flat) {
+    m = I.type[i] == 3 ? I.vmag[i] : 1.0;
+    double s, c;
+    sincos(I.vang[i], &s, &c);
+    I.v[2 * i] = m * c;
+    I.v[2 * i + 1] = m * s;
+  }
+}
+
+__global__ void k_start(const Inst* const* insts, int nslots) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  Red& r = *insts[s]->red;
+  r.norm_bits = 0ull;
+  r.step_bits = 0ull;
+  r.norm0 = 0.0;
+  r.last_norm = 0.0;
+  r.last_step = 0.0;
+  r.singular = 0;
+  r.timeout = 0;
+  r.it = 0;
+  r.status = 5;  // pending
+  r.active = 1;
+  r.linear_iters = 0;
+}
+
+// Convergence test of the Newton iteration (the loop condition of both
+// iteration tables, on the FP64 mismatch max-norm), divergence and limits.
+// Sets status and active; prepares the step counters for the next step.
+__global__ void k_decide(const Inst* const* insts, int nslots, DevOpts o) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  Red& r = *insts[s]->red;
+  if (!r.active) return;
+  const double norm = __longlong_as_double((long long)r.norm_bits);
+  const double step = __longlong_as_double((long long)r.step_bits);
+  const int it = r.it;
+  r.last_norm = norm;
+  if (it > 0) r.last_step = step;
+  int status = -1;
+  if (it > 0 && r.singular) {
+    status = 3;
+  } else if (!isfinite(norm) || (it > 0 && !isfinite(step))) {
+    status = 2;
   } else {
-    m = vm[i];
-    a = va[i];
+    if (it == 0) r.norm0 = norm;
+    if (norm <= o.tol)
+      status = 0;
+    else if (it > 0 && norm > 1e6 * r.norm0)
+      status = 2;
+    else if (it >= o.max_iter)
+      status = 1;
   }
-  double s, c;
-  sincos(a, &s, &c);
-  v[2 * i] = m * c;
-  v[2 * i + 1] = m * s;
+  if (status >= 0) {
+    r.status = status;
+    r.active = 0;
+    return;
+  }
+  r.it = it + 1;
+  r.epoch += 1;
+  r.singular = 0;
+  r.norm_bits = 0ull;
+  r.step_bits = 0ull;
 }
 
-// CIM flat start: |V| = 1 (source magnitude on source nodes) at the node's
-// nominal phase angle.
-__global__ void k_init_cim(int n, const int8_t* __restrict__ type, const double* __restrict__ vmag,
-                           const double* __restrict__ vang, double* v) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double m = type[i] == 3 ? vmag[i] : 1.0;
-  double s, c;
-  sincos(vang[i], &s, &c);
-  v[2 * i] = m * c;
-  v[2 * i + 1] = m * s;
-}
-
-__global__ void k_reset_red(Red* r) {
-  if (threadIdx.x == 0) {
-    r->norm_bits = 0ull;
-    r->step_bits = 0ull;
-    r->singular = 0;
-  }
+// copy every instance's state into one contiguous array for the host
+__global__ void k_gather_red(const Inst* const* insts, int nslots, Red* out) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslots) out[s] = *insts[s]->red;
 }
 
 // ---------------------------------------------------------------------------
@@ -125,512 +198,493 @@ __global__ void k_reset_red(Red* r) {
 // Polar: I = Y V (eq. 1), S = V conj(I) (eq. 5 conjugated), dP = P_sp - Re S
 // for non-slack buses, dQ = Q_sp - Im S for PQ buses (eq. 8-9).  F is written
 // at the bus's LU position (2 rows per node); the |V| row of a PV bus is 0.
-__global__ void k_mismatch_polar(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                                 const double2* __restrict__ y, const double2* __restrict__ v,
-                                 const int8_t* __restrict__ type, const double* __restrict__ psp,
-                                 const double* __restrict__ qsp, const int* __restrict__ pos,
-                                 double2* ibus, double* F, Red* red) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double local = 0.0;
-  if (i < n) {
-    double ir = 0.0, ii = 0.0;
-    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
-      double2 yy = y[q];
-      double2 vv = v[col[q]];
-      ir += yy.x * vv.x - yy.y * vv.y;
-      ii += yy.x * vv.y + yy.y * vv.x;
-    }
-    ibus[i] = make_double2(ir, ii);
-    int p = pos[i];
-    if (p >= 0) {
-      double2 vi = v[i];
-      double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
-      double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
-      double dp = psp[i] - sr;
-      double dq = type[i] == 1 ? qsp[i] - si : 0.0;
-      F[2 * p] = dp;
-      F[2 * p + 1] = dq;
-      local = fmax(fabs(dp), fabs(dq));
-      if (!(dp == dp) || !(dq == dq)) local = __longlong_as_double(0x7ff8000000000000ll);
-    }
-  }
-  // wave max then one atomic per wave
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(local, off, 64);
-    local = (o > local || o != o) ? o : local;
-  }
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&red->norm_bits, local);
-}
-
 // CIM: I_calc = sum_j Y_ij V_j (eq. 18); P_l, Q_l from the ZIP model (eq.
 // 14-15); P_sp = P_g - P_l (eq. 12-13); I_sp = conj((P_sp + jQ_sp)/V)
-// (eq. 17); dI = I_sp - I_calc (eq. 16).  Rows per node: [Im dI, Re dI]
-// (eq. 19 order within the node).
-__global__ void k_mismatch_cim(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
-                               const double2* __restrict__ y, const double2* __restrict__ v,
-                               const double* __restrict__ pg, const double* __restrict__ qg,
-                               const double* __restrict__ zip, const int* __restrict__ pos, double* F,
-                               Red* red) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// (eq. 17); dI = I_sp - I_calc (eq. 16); rows per node [Im dI, Re dI].
+__global__ void k_mismatch(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double local = 0.0;
-  if (i < n) {
-    int p = pos[i];
-    if (p >= 0) {
+  if (i < I.n) {
+    const double2* y = (const double2*)I.y;
+    const double2* v = (const double2*)I.v;
+    const int p = I.pos[i];
+    if (I.model == 0 || p >= 0) {
       double ir = 0.0, ii = 0.0;
-      for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+      for (int q = I.row_ptr[i]; q < I.row_ptr[i + 1]; ++q) {
         double2 yy = y[q];
-        double2 vv = v[col[q]];
+        double2 vv = v[I.col[q]];
         ir += yy.x * vv.x - yy.y * vv.y;
         ii += yy.x * vv.y + yy.y * vv.x;
       }
-      double2 vi = v[i];
-      double w = vi.x * vi.x + vi.y * vi.y;
-      double vm = sqrt(w);
-      const double* z = zip + 6 * i;
-      double pl = z[2] + z[1] * vm + z[0] * w;
-      double ql = z[5] + z[4] * vm + z[3] * w;
-      double ps = pg[i] - pl, qs = qg[i] - ql;
-      // conj((ps + j qs) / V) = (ps - j qs) / conj(V) = (ps - j qs) V / w
-      double spr = (ps * vi.x + qs * vi.y) / w;
-      double spi = (ps * vi.y - qs * vi.x) / w;
-      double dr = spr - ir, di = spi - ii;
-      F[2 * p] = di;
-      F[2 * p + 1] = dr;
-      local = fmax(fabs(dr), fabs(di));
-      if (!(dr == dr) || !(di == di)) local = __longlong_as_double(0x7ff8000000000000ll);
+      const double2 vi = v[i];
+      if (I.model == 0) {
+        ((double2*)I.ibus)[i] = make_double2(ir, ii);
+        if (p >= 0) {
+          double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
+          double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
+          double dp = I.psp[i] - sr;
+          double dq = I.type[i] == 1 ? I.qsp[i] - si : 0.0;
+          I.F[2 * p] = dp;
+          I.F[2 * p + 1] = dq;
+          local = fmax(fabs(dp), fabs(dq));
+          if (!(dp == dp) || !(dq == dq)) local = __longlong_as_double(0x7ff8000000000000ll);
+        }
+      } else {
+        double w = vi.x * vi.x + vi.y * vi.y;
+        double vm = sqrt(w);
+        const double* z = I.zip + 6 * i;
+        double pl = z[2] + z[1] * vm + z[0] * w;
+        double ql = z[5] + z[4] * vm + z[3] * w;
+        double ps = I.psp[i] - pl, qs = I.qsp[i] - ql;
+        // conj((ps + j qs) / V) = (ps - j qs) V / |V|^2
+        double spr = (ps * vi.x + qs * vi.y) / w;
+        double spi = (ps * vi.y - qs * vi.x) / w;
+        double dr = spr - ir, di = spi - ii;
+        I.F[2 * p] = di;
+        I.F[2 * p + 1] = dr;
+        local = fmax(fabs(dr), fabs(di));
+        if (!(dr == dr) || !(di == di)) local = __longlong_as_double(0x7ff8000000000000ll);
+      }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(local, off, 64);
-    local = (o > local || o != o) ? o : local;
-  }
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&red->norm_bits, local);
+  local = wave_max(local);
+  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
 }
 
 // ---------------------------------------------------------------------------
 // Jacobian fill into LU storage
 
 template <typename T>
-__global__ void k_zero(T* p, int64_t count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) p[i] = T(0);
+__global__ void k_zero_lu(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  T* p = (T*)I.lu;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.lu_count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
 }
 
 template <typename T>
-__device__ inline void jstore(T* lu, T* tail, int ldt, int nt, int code, double a, double b, double c,
-                              double d) {
+__global__ void k_zero_tail(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  T* p = (T*)I.tail;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.tail_count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+template <typename T>
+__global__ void k_copy_rhs(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * I.nu) ((T*)I.x)[i] = (T)I.F[i];
+}
+
+template <typename T>
+__device__ inline void jstore(const Inst& I, int code, double a, double b, double c, double d) {
   if (code >= 0) {
-    T* q = lu + 4 * (int64_t)code;
+    T* q = (T*)I.lu + 4 * (int64_t)code;
     q[0] = (T)a;
     q[1] = (T)b;
     q[2] = (T)c;
     q[3] = (T)d;
   } else if (code <= -2) {
     int t = -2 - code;
-    int ta = t / nt, tb = t - ta * nt;
-    T* q = tail + (int64_t)(2 * tb) * ldt + 2 * ta;
+    int ta = t / I.nt, tb = t - ta * I.nt;
+    T* q = (T*)I.tail + (int64_t)(2 * tb) * I.ldt + 2 * ta;
     q[0] = (T)a;
     q[1] = (T)c;
-    q[ldt] = (T)b;
-    q[ldt + 1] = (T)d;
+    q[I.ldt] = (T)b;
+    q[I.ldt + 1] = (T)d;
   }
 }
 
+// The 2x2 Jacobian block of Ybus entry e (row i, column j).
+//
 // Polar J (eq. 10) from the rectangular form of eq. 6-7.  For j != i, with
 // W = V_i conj(Y_ij V_j):  dS_i/dangle_j = -jW,  dS_i/d|V_j| = W/|V_j|.
 // Diagonal, with W_d = |V_i|^2 conj(Y_ii):  dS_i/dangle_i = j(S_i - W_d),
 // dS_i/d|V_i| = (S_i + W_d)/|V_i|.  Block = [[Re dS/dangle, Re dS/d|V|],
 // [Im dS/dangle, Im dS/d|V|]]; the |V| row and column of a PV bus are
 // replaced by the identity (that unknown is fixed).
-template <typename T>
-__global__ void k_jfill_polar(int nnz, const int* __restrict__ yrow, const int* __restrict__ col,
-                              const double2* __restrict__ y, const double2* __restrict__ v,
-                              const double2* __restrict__ ibus, const double* __restrict__ vm,
-                              const int8_t* __restrict__ type, const int* __restrict__ jmap, T* lu,
-                              T* tail, int ldt, int nt) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  int code = jmap[e];
-  if (code == -1) return;
-  int i = yrow[e], j = col[e];
-  double2 yy = y[e];
-  double2 vi = v[i];
-  double a, b, c, d;
-  if (i != j) {
-    double2 vj = v[j];
-    double tr = yy.x * vj.x - yy.y * vj.y;  // Y_ij V_j
-    double ti = yy.x * vj.y + yy.y * vj.x;
-    double wr = vi.x * tr + vi.y * ti;  // V_i conj(t)
-    double wi = vi.y * tr - vi.x * ti;
-    double inv = 1.0 / vm[j];
-    a = wi;
-    b = wr * inv;
-    c = -wr;
-    d = wi * inv;
-  } else {
-    double2 ii = ibus[i];
-    double sr = vi.x * ii.x + vi.y * ii.y;
-    double si = vi.y * ii.x - vi.x * ii.y;
-    double w = vm[i] * vm[i];
-    double wdr = w * yy.x, wdi = -w * yy.y;
-    double inv = 1.0 / vm[i];
-    a = -(si - wdi);
-    c = sr - wdr;
-    b = (sr + wdr) * inv;
-    d = (si + wdi) * inv;
-  }
-  if (type[i] == 2) {  // PV row: |V| equation is the identity
-    c = 0.0;
-    d = (i == j) ? 1.0 : 0.0;
-  }
-  if (type[j] == 2) {  // PV column
-    b = 0.0;
-    if (i != j) d = 0.0;
-  }
-  jstore(lu, tail, ldt, nt, code, a, b, c, d);
-}
-
+//
 // CIM J (eq. 21-23): [[B, G], [G, -B]] for every admittance entry between
 // unknown nodes, minus the ZIP adjustments a, b, c, d on the node's own
 // diagonal (derived: a load component with coefficient s and exponent e
 // draws I = conj(s) V |V|^(e-2)).
-template <typename T>
-__global__ void k_jfill_cim(int nnz, const int* __restrict__ yrow, const int* __restrict__ col,
-                            const double2* __restrict__ y, const double2* __restrict__ v,
-                            const double* __restrict__ pg, const double* __restrict__ qg,
-                            const double* __restrict__ zip, const int* __restrict__ jmap, T* lu,
-                            T* tail, int ldt, int nt) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  int code = jmap[e];
-  if (code == -1) return;
-  int i = yrow[e], j = col[e];
-  double2 yy = y[e];
-  double G = yy.x, B = yy.y;
-  double a = B, b = G, c = G, d = -B;
-  if (i == j) {
-    double2 vv = v[i];
-    double w = vv.x * vv.x + vv.y * vv.y;
-    const double* z = zip + 6 * i;
-    // components (s_re, s_im, exponent): loads enter with a minus sign
-    double sr[4] = {-z[0], -z[1], -z[2], pg[i]};
-    double sim[4] = {-z[3], -z[4], -z[5], qg[i]};
-    double ex[4] = {2.0, 1.0, 0.0, 0.0};
-    double drr = 0, dri = 0, dir = 0, dii = 0;  // dI/dVre (re, im), dI/dVim (re, im)
-    for (int k = 0; k < 4; ++k) {
-      double g = pow(w, 0.5 * (ex[k] - 2.0));
-      double gp = 0.5 * (ex[k] - 2.0) * pow(w, 0.5 * (ex[k] - 4.0));
-      double cr = sr[k], ci = -sim[k];  // conj(s)
-      // dI/dVre = conj(s) * (g + 2 Vre V g')
-      double ur = g + 2.0 * vv.x * vv.x * gp, ui = 2.0 * vv.x * vv.y * gp;
-      drr += cr * ur - ci * ui;
-      dri += cr * ui + ci * ur;
-      // dI/dVim = conj(s) * (j g + 2 Vim V g')
-      double tr = 2.0 * vv.y * vv.x * gp, ti = g + 2.0 * vv.y * vv.y * gp;
-      dir += cr * tr - ci * ti;
-      dii += cr * ti + ci * tr;
+__device__ inline void jblock(const Inst& I, int e, double* out) {
+  const int i = I.yrow[e], j = I.col[e];
+  const double2 yy = ((const double2*)I.y)[e];
+  const double2* v = (const double2*)I.v;
+  double a, b, c, d;
+  if (I.model == 0) {
+    const double2 vi = v[i];
+    if (i != j) {
+      double2 vj = v[j];
+      double tr = yy.x * vj.x - yy.y * vj.y;  // Y_ij V_j
+      double ti = yy.x * vj.y + yy.y * vj.x;
+      double wr = vi.x * tr + vi.y * ti;  // V_i conj(t)
+      double wi = vi.y * tr - vi.x * ti;
+      double inv = 1.0 / I.vm[j];
+      a = wi;
+      b = wr * inv;
+      c = -wr;
+      d = wi * inv;
+    } else {
+      double2 ii = ((const double2*)I.ibus)[i];
+      double sr = vi.x * ii.x + vi.y * ii.y;
+      double si = vi.y * ii.x - vi.x * ii.y;
+      double w = I.vm[i] * I.vm[i];
+      double wdr = w * yy.x, wdi = -w * yy.y;
+      double inv = 1.0 / I.vm[i];
+      a = -(si - wdi);
+      c = sr - wdr;
+      b = (sr + wdr) * inv;
+      d = (si + wdi) * inv;
     }
-    a -= dri;  // Im dI/dVre
-    b -= dii;  // Im dI/dVim
-    c -= drr;  // Re dI/dVre
-    d -= dir;  // Re dI/dVim
+    if (I.type[i] == 2) {  // PV row: the |V| equation is the identity
+      c = 0.0;
+      d = (i == j) ? 1.0 : 0.0;
+    }
+    if (I.type[j] == 2) {  // PV column
+      b = 0.0;
+      if (i != j) d = 0.0;
+    }
+  } else {
+    const double G = yy.x, Bv = yy.y;
+    a = Bv;
+    b = G;
+    c = G;
+    d = -Bv;
+    if (i == j) {
+      double2 vv = v[i];
+      double w = vv.x * vv.x + vv.y * vv.y;
+      const double* z = I.zip + 6 * i;
+      // components (s_re, s_im, exponent): loads enter with a minus sign
+      double sr[4] = {-z[0], -z[1], -z[2], I.psp[i]};
+      double sim[4] = {-z[3], -z[4], -z[5], I.qsp[i]};
+      double ex[4] = {2.0, 1.0, 0.0, 0.0};
+      double drr = 0, dri = 0, dir = 0, dii = 0;  // dI/dVre (re, im), dI/dVim (re, im)
+      for (int k = 0; k < 4; ++k) {
+        double g = pow(w, 0.5 * (ex[k] - 2.0));
+        double gp = 0.5 * (ex[k] - 2.0) * pow(w, 0.5 * (ex[k] - 4.0));
+        double cr = sr[k], ci = -sim[k];  // conj(s)
+        // dI/dVre = conj(s) (g + 2 Vre V g')
+        double ur = g + 2.0 * vv.x * vv.x * gp, ui = 2.0 * vv.x * vv.y * gp;
+        drr += cr * ur - ci * ui;
+        dri += cr * ui + ci * ur;
+        // dI/dVim = conj(s) (j g + 2 Vim V g')
+        double tr = 2.0 * vv.y * vv.x * gp, ti = g + 2.0 * vv.y * vv.y * gp;
+        dir += cr * tr - ci * ti;
+        dii += cr * ti + ci * tr;
+      }
+      a -= dri;  // Im dI/dVre
+      b -= dii;  // Im dI/dVim
+      c -= drr;  // Re dI/dVre
+      d -= dir;  // Re dI/dVim
+    }
   }
-  jstore(lu, tail, ldt, nt, code, a, b, c, d);
+  out[0] = a;
+  out[1] = b;
+  out[2] = c;
+  out[3] = d;
+}
+
+template <typename T>
+__global__ void k_jfill(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= I.nnz) return;
+  int code = I.jmap[e];
+  if (code == -1) return;
+  double blk[4];
+  jblock(I, e, blk);
+  jstore<T>(I, code, blk[0], blk[1], blk[2], blk[3]);
 }
 
 // ---------------------------------------------------------------------------
-// sparse block refactorisation: one work-group per column of a level
+// sparse block refactorisation: one work-group per (instance, column) of a
+// level; each target block (D_j, U(j, .), L(., j)) is reduced by a group of G
+// lanes that split its update list (lane-strided partial sums, fixed-order
+// tree).
 
-template <typename T>
-__global__ void k_factor_cols(const int* __restrict__ cols, Sched s, T* lu, T* dinv, Red* red) {
+template <typename T, int G>
+__device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest, int64_t tg, int lane) {
+  Blk<T> acc = {T(0), T(0), T(0), T(0)};
+  if (lane == 0) acc = ld_blk(lu, dest);
+  for (int64_t q = I.uptr[tg] + lane; q < I.uptr[tg + 1]; q += G)
+    blk_msub(acc, ld_blk(lu, I.upd_l[q]), ld_blk(lu, I.upd_u[q]));
+  return group_sum<T, G>(acc);
+}
+
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_factor_cols(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ T sdinv[4];
-  const int j = cols[blockIdx.x];
-  const int c0 = s.colptr[j];
-  const int len = s.colptr[j + 1] - c0;
+  const int2 w = work[blockIdx.x];
+  const Inst& I = *insts[w.x];
+  if (inactive(I)) return;
+  T* lu = (T*)I.lu;
+  const int j = w.y;
+  const int c0 = I.colptr[j];
+  const int len = I.colptr[j + 1] - c0;
   const int64_t tb = (int64_t)j + 2LL * c0;
-  // D_j and U(j, .): gather their updates
-  for (int t = threadIdx.x; t <= len; t += blockDim.x) {
-    int64_t dest = t == 0 ? (int64_t)j : (int64_t)s.ns + s.nnzl + c0 + (t - 1);
-    Blk<T> acc = ld_blk(lu, dest);
-    for (int64_t q = s.uptr[tb + t]; q < s.uptr[tb + t + 1]; ++q)
-      blk_msub(acc, ld_blk(lu, s.upd_l[q]), ld_blk(lu, s.upd_u[q]));
-    st_blk(lu, dest, acc);
-    if (t == 0) {
-      T det = acc.a * acc.d - acc.b * acc.c;
-      bool bad = !(det != T(0)) || !isfinite((double)det);
-      if (bad) {
-        red->singular = 1;
-        det = T(1);
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
+  // D_j and U(j, .)
+  for (int t = grp; t <= len; t += ngrp) {
+    int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
+    Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
+    if (lane == 0) {
+      st_blk(lu, dest, acc);
+      if (t == 0) {
+        T det = acc.a * acc.d - acc.b * acc.c;
+        bool bad = !(det != T(0)) || !isfinite((double)det);
+        if (bad) {
+          I.red->singular = 1;
+          det = T(1);
+        }
+        T r = T(1) / det;
+        sdinv[0] = acc.d * r;
+        sdinv[1] = -acc.b * r;
+        sdinv[2] = -acc.c * r;
+        sdinv[3] = acc.a * r;
+        T* q = (T*)I.dinv + 4 * (int64_t)j;
+        q[0] = sdinv[0];
+        q[1] = sdinv[1];
+        q[2] = sdinv[2];
+        q[3] = sdinv[3];
       }
-      T r = T(1) / det;
-      sdinv[0] = acc.d * r;
-      sdinv[1] = -acc.b * r;
-      sdinv[2] = -acc.c * r;
-      sdinv[3] = acc.a * r;
-      T* q = dinv + 4 * (int64_t)j;
-      q[0] = sdinv[0];
-      q[1] = sdinv[1];
-      q[2] = sdinv[2];
-      q[3] = sdinv[3];
     }
   }
   __syncthreads();
-  Blk<T> di = {sdinv[0], sdinv[1], sdinv[2], sdinv[3]};
-  for (int t = threadIdx.x; t < len; t += blockDim.x) {
-    int64_t dest = (int64_t)s.ns + c0 + t;
-    int64_t tg = tb + 1 + len + t;
-    Blk<T> acc = ld_blk(lu, dest);
-    for (int64_t q = s.uptr[tg]; q < s.uptr[tg + 1]; ++q)
-      blk_msub(acc, ld_blk(lu, s.upd_l[q]), ld_blk(lu, s.upd_u[q]));
-    st_blk(lu, dest, blk_mul(acc, di));
+  const Blk<T> di = {sdinv[0], sdinv[1], sdinv[2], sdinv[3]};
+  for (int t = grp; t < len; t += ngrp) {
+    int64_t dest = (int64_t)I.ns + c0 + t;
+    Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + 1 + len + t, lane);
+    if (lane == 0) st_blk(lu, dest, blk_mul(acc, di));
   }
 }
 
 // Schur complement of the sparse part into the dense trailing block:
-// T(a,b) -= sum_k L(a,k) U(k,b)
+// T(a,b) -= sum_k L(a,k) U(k,b); work item = (instance, first target of a
+// chunk of 256).
 template <typename T>
-__global__ void k_tail_schur(int ntt, const int* __restrict__ tgt, const int64_t* __restrict__ uptr,
-                             const int* __restrict__ ul, const int* __restrict__ uu, const T* __restrict__ lu,
-                             T* tail, int ldt, int nt) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntt) return;
+__global__ void k_tail_schur(const Inst* const* insts, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const Inst& I = *insts[w.x];
+  if (inactive(I)) return;
+  const int t = w.y + threadIdx.x;
+  if (t >= I.ntt) return;
+  const T* lu = (const T*)I.lu;
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  for (int64_t q = uptr[t]; q < uptr[t + 1]; ++q) blk_msub(acc, ld_blk(lu, ul[q]), ld_blk(lu, uu[q]));
-  int g = tgt[t];
-  int ta = g / nt, tb = g - ta * nt;
-  T* p = tail + (int64_t)(2 * tb) * ldt + 2 * ta;
+  for (int64_t q = I.tail_uptr[t]; q < I.tail_uptr[t + 1]; ++q)
+    blk_msub(acc, ld_blk(lu, I.tail_l[q]), ld_blk(lu, I.tail_u[q]));
+  int g = I.tail_tgt[t];
+  int ta = g / I.nt, tb = g - ta * I.nt;
+  T* p = (T*)I.tail + (int64_t)(2 * tb) * I.ldt + 2 * ta;
   p[0] += acc.a;
   p[1] += acc.c;
-  p[ldt] += acc.b;
-  p[ldt + 1] += acc.d;
+  p[I.ldt] += acc.b;
+  p[I.ldt + 1] += acc.d;
 }
 
 // ---------------------------------------------------------------------------
 // triangular solves over sparse rows
 
-template <typename T>
-__global__ void k_copy_rhs(int m, const double* __restrict__ F, T* x) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) x[i] = (T)F[i];
-}
-
-// y_i = b_i - sum_k L(i,k) y_k for the rows of one level (in place in x); rows
-// of the dense block also copy their result into the appended RHS column.
-template <typename T>
-__global__ void k_fwd_rows(const int* __restrict__ rows, int nrows, int row_base,
-                           const int* __restrict__ lrow_ptr, const int* __restrict__ lrow_blk,
-                           const int* __restrict__ lrow_col, const T* __restrict__ lu, T* x, T* tail_rhs,
-                           int ns) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  int i = rows ? rows[r] : row_base + r;
-  T y0 = x[2 * i], y1 = x[2 * i + 1];
-  for (int q = lrow_ptr[i]; q < lrow_ptr[i + 1]; ++q) {
-    Blk<T> L = ld_blk(lu, lrow_blk[q]);
-    int k = lrow_col[q];
+// y_i = b_i - sum_k L(i,k) y_k for one (instance, row) per group of G lanes
+// (in place in x); rows of the dense block also copy their result into the
+// appended RHS column.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, const int2* __restrict__ work,
+                                                  int nwork) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G, lane = threadIdx.x % G;
+  if (gid >= nwork) return;  // whole groups leave together
+  const int2 w = work[gid];
+  const Inst& I = *insts[w.x];
+  if (inactive(I)) return;
+  const T* lu = (const T*)I.lu;
+  T* x = (T*)I.x;
+  const int i = w.y;
+  Blk<T> acc = {T(0), T(0), T(0), T(0)};  // (a, c) carry the 2-vector
+  if (lane == 0) {
+    acc.a = x[2 * i];
+    acc.c = x[2 * i + 1];
+  }
+  for (int q = I.lrow_ptr[i] + lane; q < I.lrow_ptr[i + 1]; q += G) {
+    Blk<T> L = ld_blk(lu, I.lrow_blk[q]);
+    int k = I.lrow_col[q];
     T x0 = x[2 * k], x1 = x[2 * k + 1];
-    y0 -= L.a * x0 + L.b * x1;
-    y1 -= L.c * x0 + L.d * x1;
+    acc.a -= L.a * x0 + L.b * x1;
+    acc.c -= L.c * x0 + L.d * x1;
   }
-  x[2 * i] = y0;
-  x[2 * i + 1] = y1;
-  if (tail_rhs && i >= ns) {
-    tail_rhs[2 * (i - ns)] = y0;
-    tail_rhs[2 * (i - ns) + 1] = y1;
+  acc = group_sum<T, G>(acc);
+  if (lane == 0) {
+    x[2 * i] = acc.a;
+    x[2 * i + 1] = acc.c;
+    if (i >= I.ns) {
+      T* rhs = (T*)I.tail + (int64_t)I.M * I.ldt;
+      rhs[2 * (i - I.ns)] = acc.a;
+      rhs[2 * (i - I.ns) + 1] = acc.c;
+    }
   }
 }
 
-// x_i = D_i^{-1} (y_i - sum_j U(i,j) x_j) for the rows of one level
-template <typename T>
-__global__ void k_bwd_rows(const int* __restrict__ rows, int nrows, Sched s, const T* __restrict__ lu,
-                           const T* __restrict__ dinv, T* x) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  int i = rows[r];
-  T z0 = x[2 * i], z1 = x[2 * i + 1];
-  for (int q = s.colptr[i]; q < s.colptr[i + 1]; ++q) {
-    Blk<T> U = ld_blk(lu, (int64_t)s.ns + s.nnzl + q);
-    int j = s.rowidx[q];
-    T x0 = x[2 * j], x1 = x[2 * j + 1];
-    z0 -= U.a * x0 + U.b * x1;
-    z1 -= U.c * x0 + U.d * x1;
+// x_i = D_i^{-1} (y_i - sum_j U(i,j) x_j) for one (instance, row) per group
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_bwd_rows(const Inst* const* insts, const int2* __restrict__ work,
+                                                  int nwork) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G, lane = threadIdx.x % G;
+  if (gid >= nwork) return;
+  const int2 w = work[gid];
+  const Inst& I = *insts[w.x];
+  if (inactive(I)) return;
+  const T* lu = (const T*)I.lu;
+  T* x = (T*)I.x;
+  const int i = w.y;
+  Blk<T> acc = {T(0), T(0), T(0), T(0)};
+  if (lane == 0) {
+    acc.a = x[2 * i];
+    acc.c = x[2 * i + 1];
   }
-  Blk<T> D = ld_blk(dinv, i);
-  x[2 * i] = D.a * z0 + D.b * z1;
-  x[2 * i + 1] = D.c * z0 + D.d * z1;
+  for (int q = I.colptr[i] + lane; q < I.colptr[i + 1]; q += G) {
+    Blk<T> U = ld_blk(lu, (int64_t)I.ns + I.nnzl + q);
+    int j = I.rowidx[q];
+    T x0 = x[2 * j], x1 = x[2 * j + 1];
+    acc.a -= U.a * x0 + U.b * x1;
+    acc.c -= U.c * x0 + U.d * x1;
+  }
+  acc = group_sum<T, G>(acc);
+  if (lane == 0) {
+    Blk<T> D = ld_blk((const T*)I.dinv, i);
+    x[2 * i] = D.a * acc.a + D.b * acc.c;
+    x[2 * i + 1] = D.c * acc.a + D.d * acc.c;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // voltage update (FP64)
 
-// Polar: angle += dx[2p] (non-slack), |V| += dx[2p+1] (PQ only); refresh the
-// rectangular voltage.
+// Polar: angle += dx[2p] (non-slack), |V| += dx[2p+1] (PQ only) (single-phase
+// iteration table, update line); CIM: Re V += dx[2p], Im V += dx[2p+1]
+// (eq. 20 pairing; three-phase iteration table, update and complex-form
+// lines).  Refreshes the rectangular voltage and records max |dx|.
 template <typename T>
-__global__ void k_update_polar(int nu, const int* __restrict__ node, const int8_t* __restrict__ type,
-                               const T* __restrict__ x, double* vm, double* va, double2* v, Red* red) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_update(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   double local = 0.0;
-  if (p < nu) {
-    int i = node[p];
-    double da = (double)x[2 * p];
-    double dm = type[i] == 1 ? (double)x[2 * p + 1] : 0.0;
-    double a = va[i] + da, m = vm[i] + dm;
-    va[i] = a;
-    vm[i] = m;
-    double s, c;
-    sincos(a, &s, &c);
-    v[i] = make_double2(m * c, m * s);
-    local = fmax(fabs(da), fabs(dm));
+  if (p < I.nu) {
+    const T* x = (const T*)I.x;
+    const int i = I.node[p];
+    double d0 = (double)x[2 * p], d1 = (double)x[2 * p + 1];
+    if (I.model == 0) {
+      if (I.type[i] != 1) d1 = 0.0;
+      double a = I.va[i] + d0, m = I.vm[i] + d1;
+      I.va[i] = a;
+      I.vm[i] = m;
+      double s, c;
+      sincos(a, &s, &c);
+      ((double2*)I.v)[i] = make_double2(m * c, m * s);
+    } else {
+      double2 vv = ((double2*)I.v)[i];
+      ((double2*)I.v)[i] = make_double2(vv.x + d0, vv.y + d1);
+    }
+    local = fmax(fabs(d0), fabs(d1));
     if (!(local == local)) local = __longlong_as_double(0x7ff8000000000000ll);
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(local, off, 64);
-    local = (o > local || o != o) ? o : local;
-  }
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&red->step_bits, local);
-}
-
-// CIM: Re V += dx[2p], Im V += dx[2p+1] (eq. 20 pairing; Alg. steps 6-7).
-template <typename T>
-__global__ void k_update_cim(int nu, const int* __restrict__ node, const T* __restrict__ x, double2* v,
-                             Red* red) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  double local = 0.0;
-  if (p < nu) {
-    int i = node[p];
-    double dr = (double)x[2 * p], di = (double)x[2 * p + 1];
-    double2 vv = v[i];
-    v[i] = make_double2(vv.x + dr, vv.y + di);
-    local = fmax(fabs(dr), fabs(di));
-    if (!(local == local)) local = __longlong_as_double(0x7ff8000000000000ll);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_xor(local, off, 64);
-    local = (o > local || o != o) ? o : local;
-  }
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&red->step_bits, local);
+  local = wave_max(local);
+  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&I.red->step_bits, local);
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 
-#define PF_GRID(n, b) dim3((unsigned)(((n) + (b)-1) / (b)))
+static inline dim3 grid2(int64_t count, int nslots, int block = 256, int64_t cap = 1 << 20) {
+  int64_t gx = (count + block - 1) / block;
+  if (gx < 1) gx = 1;
+  if (gx > cap) gx = cap;
+  return dim3((unsigned)gx, (unsigned)nslots);
+}
 
-void launch_init_polar(hipStream_t st, int n, const int8_t* type, const double* vmag, const double* vang,
-                       double* vm, double* va, double* v, int flat) {
-  if (n <= 0) return;
-  k_init_polar<<<PF_GRID(n, 256), 256, 0, st>>>(n, type, vmag, vang, vm, va, v, flat);
+void launch_init(hipStream_t st, const Inst* const* insts, int nslots, int max_n, int flat) {
+  k_init<<<grid2(max_n, nslots), 256, 0, st>>>(insts, flat);
 }
-void launch_init_cim(hipStream_t st, int n, const int8_t* type, const double* vmag, const double* vang,
-                     double* v) {
-  if (n <= 0) return;
-  k_init_cim<<<PF_GRID(n, 256), 256, 0, st>>>(n, type, vmag, vang, v);
+void launch_start(hipStream_t st, const Inst* const* insts, int nslots) {
+  k_start<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots);
 }
-void launch_reset_red(hipStream_t st, Red* r) { k_reset_red<<<1, 64, 0, st>>>(r); }
-
-void launch_mismatch_polar(hipStream_t st, int n, const int* row_ptr, const int* col, const double* y,
-                           const double* v, const int8_t* type, const double* psp, const double* qsp,
-                           const int* pos, double* ibus, double* F, Red* red) {
-  k_mismatch_polar<<<PF_GRID(n, 256), 256, 0, st>>>(n, row_ptr, col, (const double2*)y, (const double2*)v,
-                                                    type, psp, qsp, pos, (double2*)ibus, F, red);
+void launch_decide(hipStream_t st, const Inst* const* insts, int nslots, DevOpts o) {
+  k_decide<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, o);
 }
-void launch_mismatch_cim(hipStream_t st, int n, const int* row_ptr, const int* col, const double* y,
-                         const double* v, const double* pg, const double* qg, const double* zip,
-                         const int* pos, double* F, Red* red) {
-  k_mismatch_cim<<<PF_GRID(n, 256), 256, 0, st>>>(n, row_ptr, col, (const double2*)y, (const double2*)v, pg,
-                                                  qg, zip, pos, F, red);
+void launch_gather_red(hipStream_t st, const Inst* const* insts, int nslots, Red* out) {
+  k_gather_red<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, out);
+}
+void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int max_n) {
+  k_mismatch<<<grid2(max_n, nslots), 256, 0, st>>>(insts);
 }
 
 template <typename T>
-void launch_zero(hipStream_t st, T* p, int64_t count) {
-  if (count <= 0) return;
-  int64_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  k_zero<T><<<dim3((unsigned)blocks), 256, 0, st>>>(p, count);
+void launch_fill(hipStream_t st, const Inst* const* insts, int nslots, int max_nu2, int64_t max_lu,
+                 int64_t max_tail, int max_nnz) {
+  k_copy_rhs<T><<<grid2(max_nu2, nslots), 256, 0, st>>>(insts);
+  k_zero_lu<T><<<grid2(max_lu, nslots, 256, 2048), 256, 0, st>>>(insts);
+  if (max_tail > 0) k_zero_tail<T><<<grid2(max_tail, nslots, 256, 4096), 256, 0, st>>>(insts);
+  k_jfill<T><<<grid2(max_nnz, nslots), 256, 0, st>>>(insts);
+}
+
+#define PF_GSWITCH(G, CALL)                         \
+  switch (G) {                                      \
+    case 1: { constexpr int GG = 1; CALL; } break;   \
+    case 2: { constexpr int GG = 2; CALL; } break;   \
+    case 4: { constexpr int GG = 4; CALL; } break;   \
+    case 8: { constexpr int GG = 8; CALL; } break;   \
+    case 16: { constexpr int GG = 16; CALL; } break; \
+    case 32: { constexpr int GG = 32; CALL; } break; \
+    default: { constexpr int GG = 64; CALL; } break; \
+  }
+
+template <typename T>
+void launch_factor_cols(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
+  if (nwork <= 0) return;
+  PF_GSWITCH(G, (k_factor_cols<T, GG><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work)));
 }
 
 template <typename T>
-void launch_jfill_polar(hipStream_t st, int nnz, const int* yrow, const int* col, const double* y,
-                        const double* v, const double* ibus, const double* vm, const int8_t* type,
-                        const int* jmap, T* lu, T* tail, int ldt, int nt) {
-  k_jfill_polar<T><<<PF_GRID(nnz, 256), 256, 0, st>>>(nnz, yrow, col, (const double2*)y, (const double2*)v,
-                                                      (const double2*)ibus, vm, type, jmap, lu, tail, ldt,
-                                                      nt);
-}
-template <typename T>
-void launch_jfill_cim(hipStream_t st, int nnz, const int* yrow, const int* col, const double* y,
-                      const double* v, const double* pg, const double* qg, const double* zip,
-                      const int* jmap, T* lu, T* tail, int ldt, int nt) {
-  k_jfill_cim<T><<<PF_GRID(nnz, 256), 256, 0, st>>>(nnz, yrow, col, (const double2*)y, (const double2*)v, pg,
-                                                    qg, zip, jmap, lu, tail, ldt, nt);
+void launch_tail_schur(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
+  if (nwork <= 0) return;
+  k_tail_schur<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
 }
 
 template <typename T>
-void launch_factor_cols(hipStream_t st, const int* cols, int ncols, const Sched& s, T* lu, T* dinv,
-                        Red* red) {
-  if (ncols <= 0) return;
-  k_factor_cols<T><<<dim3((unsigned)ncols), 64, 0, st>>>(cols, s, lu, dinv, red);
+void launch_fwd_rows(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
+  if (nwork <= 0) return;
+  PF_GSWITCH(G, (k_fwd_rows<T, GG><<<dim3((unsigned)(((int64_t)nwork * GG + 255) / 256)), 256, 0, st>>>(
+                    insts, work, nwork)));
 }
 
 template <typename T>
-void launch_tail_schur(hipStream_t st, int ntt, const int* tgt, const int64_t* uptr, const int* ul,
-                       const int* uu, const T* lu, T* tail, int ldt, int nt) {
-  if (ntt <= 0) return;
-  k_tail_schur<T><<<PF_GRID(ntt, 256), 256, 0, st>>>(ntt, tgt, uptr, ul, uu, lu, tail, ldt, nt);
+void launch_bwd_rows(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
+  if (nwork <= 0) return;
+  PF_GSWITCH(G, (k_bwd_rows<T, GG><<<dim3((unsigned)(((int64_t)nwork * GG + 255) / 256)), 256, 0, st>>>(
+                    insts, work, nwork)));
 }
 
 template <typename T>
-void launch_copy_rhs(hipStream_t st, int m, const double* F, T* x) {
-  if (m <= 0) return;
-  k_copy_rhs<T><<<PF_GRID(m, 256), 256, 0, st>>>(m, F, x);
+void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max_nu) {
+  k_update<T><<<grid2(max_nu, nslots), 256, 0, st>>>(insts);
 }
 
-template <typename T>
-void launch_fwd_rows(hipStream_t st, const int* rows, int nrows, int row_base, const int* lrow_ptr,
-                     const int* lrow_blk, const int* lrow_col, const T* lu, T* x, T* tail_rhs, int ns) {
-  if (nrows <= 0) return;
-  k_fwd_rows<T><<<PF_GRID(nrows, 64), 64, 0, st>>>(rows, nrows, row_base, lrow_ptr, lrow_blk, lrow_col, lu, x,
-                                                   tail_rhs, ns);
-}
-
-template <typename T>
-void launch_bwd_rows(hipStream_t st, const int* rows, int nrows, const Sched& s, const T* lu, const T* dinv,
-                     T* x) {
-  if (nrows <= 0) return;
-  k_bwd_rows<T><<<PF_GRID(nrows, 64), 64, 0, st>>>(rows, nrows, s, lu, dinv, x);
-}
-
-template <typename T>
-void launch_update_polar(hipStream_t st, int nu, const int* node, const int8_t* type, const T* x, double* vm,
-                         double* va, double* v, Red* red) {
-  if (nu <= 0) return;
-  k_update_polar<T><<<PF_GRID(nu, 256), 256, 0, st>>>(nu, node, type, x, vm, va, (double2*)v, red);
-}
-template <typename T>
-void launch_update_cim(hipStream_t st, int nu, const int* node, const T* x, double* v, Red* red) {
-  if (nu <= 0) return;
-  k_update_cim<T><<<PF_GRID(nu, 256), 256, 0, st>>>(nu, node, x, (double2*)v, red);
-}
-
-#define PF_INST(T)                                                                                          \
-  template void launch_zero<T>(hipStream_t, T*, int64_t);                                                   \
-  template void launch_jfill_polar<T>(hipStream_t, int, const int*, const int*, const double*, const double*, \
-                                      const double*, const double*, const int8_t*, const int*, T*, T*, int,  \
-                                      int);                                                                 \
-  template void launch_jfill_cim<T>(hipStream_t, int, const int*, const int*, const double*, const double*,   \
-                                    const double*, const double*, const double*, const int*, T*, T*, int,    \
-                                    int);                                                                   \
-  template void launch_factor_cols<T>(hipStream_t, const int*, int, const Sched&, T*, T*, Red*);            \
-  template void launch_tail_schur<T>(hipStream_t, int, const int*, const int64_t*, const int*, const int*,   \
-                                     const T*, T*, int, int);                                               \
-  template void launch_copy_rhs<T>(hipStream_t, int, const double*, T*);                                    \
-  template void launch_fwd_rows<T>(hipStream_t, const int*, int, int, const int*, const int*, const int*,    \
-                                   const T*, T*, T*, int);                                                  \
-  template void launch_bwd_rows<T>(hipStream_t, const int*, int, const Sched&, const T*, const T*, T*);     \
-  template void launch_update_polar<T>(hipStream_t, int, const int*, const int8_t*, const T*, double*,       \
-                                       double*, double*, Red*);                                             \
-  template void launch_update_cim<T>(hipStream_t, int, const int*, const T*, double*, Red*);
+#define PF_INST(T)                                                                                         \
+  template void launch_fill<T>(hipStream_t, const Inst* const*, int, int, int64_t, int64_t, int);          \
+  template void launch_factor_cols<T>(hipStream_t, const Inst* const*, const int2*, int, int);             \
+  template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int);                   \
+  template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
+  template void launch_bwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
+  template void launch_update<T>(hipStream_t, const Inst* const*, int, int);
 
 PF_INST(double)
 PF_INST(float)

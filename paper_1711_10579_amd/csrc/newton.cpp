@@ -1,11 +1,14 @@
-// The outer Newton iteration (Sec. II-A and II-B iteration tables; both
-// solvers share it, Sec. III) and the LU inner solve (Sec. III-A).
+// The outer Newton iteration (Sec. II-A and II-B iteration tables; both inner
+// solvers share it, Sec. III) run on the device for a batch of cases, and the
+// launch sequence of the LU inner solve (Sec. III-A).
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
 
 #include "internal.hpp"
@@ -14,12 +17,6 @@
 namespace pfi {
 
 namespace {
-
-double bits_to_double(unsigned long long b) {
-  double d;
-  std::memcpy(&d, &b, sizeof d);
-  return d;
-}
 
 struct Prof {
   Ctx* ctx;
@@ -32,118 +29,212 @@ struct Prof {
   ~Prof() { ctx->prof_end(cls, a, flops, bytes); }
 };
 
-template <typename T>
-void lu_solve(Case* c) {
-  Ctx* ctx = c->ctx;
-  hipStream_t s = ctx->stream;
-  const auto& an = c->an;
-  const int ns = an.ns, nt = an.nt, nu = an.nu, M = c->M, ldt = an.ldt;
-  T* x = (T*)c->x;
-  T* lu = (T*)c->lu;
-  T* dinv = (T*)c->dinv;
-  T* tail = (T*)c->tail;
-  const double tb = sizeof(T);
-  pfd::Sched sc = c->sched();
+constexpr int NB = 64;
 
+}  // namespace
+
+Batch::~Batch() {
+  if (dmem && ctx) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dfree(dmem);
+  }
+}
+
+bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
+  ctx = cx;
+  cases = cs;
+  nslots = (int)cs.size();
+  std::vector<int2> work;
+  seq.clear();
+  auto emit = [&](int kind, int cls, int G, int k0, const std::vector<int2>& items, double flops, double bytes) {
+    if (items.empty()) return;
+    Launch l;
+    l.kind = kind;
+    l.cls = cls;
+    l.G = G;
+    l.k0 = k0;
+    l.off = (int64_t)work.size();
+    l.count = (int)items.size();
+    l.flops = flops;
+    l.bytes = bytes;
+    work.insert(work.end(), items.begin(), items.end());
+    seq.push_back(l);
+  };
+  max_n = max_nnz = max_nu = 0;
+  max_lu = max_tail = 0;
+  int max_lev = 0, max_blev = 0, max_M = 0;
+  for (Case* c : cs) {
+    max_n = std::max(max_n, c->n);
+    max_nnz = std::max(max_nnz, c->nnz);
+    max_nu = std::max(max_nu, c->an.nu);
+    max_lu = std::max(max_lu, c->lu_count());
+    if (c->an.nt > 0) max_tail = std::max(max_tail, c->tail_count());
+    max_lev = std::max(max_lev, c->nlev);
+    max_blev = std::max(max_blev, c->nbl);
+    max_M = std::max(max_M, c->M);
+  }
+  // sparse refactorisation and forward solve, level by level, one launch per
+  // lane-group size
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = 0; l < max_lev; ++l) {
+      std::map<int, std::vector<int2>> byG;
+      std::map<int, double> fl, by;
+      for (int s = 0; s < nslots; ++s) {
+        Case* c = cs[s];
+        if (l >= c->nlev) continue;
+        const int G = pass == 0 ? c->fac_g[l] : c->fwd_g[l];
+        auto& v = byG[G];
+        for (int k = c->an.col_lev_ptr[l]; k < c->an.col_lev_ptr[l + 1]; ++k) v.push_back(make_int2(s, c->an.col_order[k]));
+        if (pass == 0) {
+          fl[G] += c->fac_flops[l];
+          by[G] += c->fac_bytes[l];
+        }
+      }
+      for (auto& kv : byG)
+        emit(pass == 0 ? L_FACTOR : L_FWD, pass == 0 ? PF_K_SPARSE_FACTOR : PF_K_SPARSE_FWD, kv.first, 0, kv.second,
+             fl[kv.first], by[kv.first]);
+    }
+  }
+  // forward rows of the dense block, then the Schur complement into it
   {
-    Prof p(ctx, PF_K_JFILL, 0.0, tb * (c->lu_count() + c->tail_count()) + 28.0 * c->nnz + 16.0 * nu);
-    pfd::launch_copy_rhs<T>(s, 2 * nu, c->F, x);
-    pfd::launch_zero<T>(s, lu, c->lu_count());
-    if (nt > 0) pfd::launch_zero<T>(s, tail, c->tail_count());
-    if (c->model == PF_MODEL_POLAR_1PH)
-      pfd::launch_jfill_polar<T>(s, c->nnz, c->yrow, c->col, c->y, c->v, c->ibus, c->vm, c->dtype, c->jmap,
-                                 lu, tail, ldt, nt);
-    else
-      pfd::launch_jfill_cim<T>(s, c->nnz, c->yrow, c->col, c->y, c->v, c->psp, c->qsp, c->zip, c->jmap, lu,
-                               tail, ldt, nt);
-  }
-  // sparse refactorisation by elimination-tree level
-  for (int l = 0; l < c->nlev; ++l) {
-    int b = an.col_lev_ptr[l], e = an.col_lev_ptr[l + 1];
-    double upd = 0, blocks = 0;
-    for (int k = b; k < e; ++k) {
-      int j = an.col_order[k];
-      int64_t t0 = j + 2LL * an.colptr[j];
-      int len = an.colptr[j + 1] - an.colptr[j];
-      upd += (double)(an.uptr[t0 + 1 + 2 * len] - an.uptr[t0]);
-      blocks += 1 + 2 * len;
+    std::map<int, std::vector<int2>> byG;
+    std::vector<int2> schur;
+    double sfl = 0, sby = 0;
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      if (c->an.nt == 0) continue;
+      auto& v = byG[c->tailfwd_g];
+      for (int i = c->an.ns; i < c->an.nu; ++i) v.push_back(make_int2(s, i));
+      for (int t = 0; t < c->ntt; t += 256) schur.push_back(make_int2(s, t));
+      double nupd = (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
+      sfl += 16.0 * nupd;
+      sby += 8.0 * nupd + 64.0 * nupd + 64.0 * c->ntt;
     }
-    Prof p(ctx, PF_K_SPARSE_FACTOR, 16.0 * upd + 40.0 * blocks, tb * 4 * (2 * upd + 2 * blocks) + 8.0 * upd);
-    pfd::launch_factor_cols<T>(s, c->col_order + b, e - b, sc, lu, dinv, c->red);
+    for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
+    emit(L_SCHUR, PF_K_TAIL_SCHUR, 0, 0, schur, sfl, sby);
   }
-  // forward solve over sparse rows (same levels as the factorisation)
-  for (int l = 0; l < c->nlev; ++l) {
-    int b = an.col_lev_ptr[l], e = an.col_lev_ptr[l + 1];
-    Prof p(ctx, PF_K_SPARSE_FWD, 0.0, 0.0);
-    pfd::launch_fwd_rows<T>(s, c->col_order + b, e - b, 0, c->lrow_ptr, c->lrow_blk, c->lrow_col, lu, x,
-                            nullptr, ns);
-  }
-  if (nt > 0) {
-    T* rhs = tail + (int64_t)M * ldt;
-    {
-      Prof p(ctx, PF_K_SPARSE_FWD, 0.0, 0.0);
-      pfd::launch_fwd_rows<T>(s, nullptr, nt, ns, c->lrow_ptr, c->lrow_blk, c->lrow_col, lu, x, rhs, ns);
-    }
-    {
-      double nupd = (double)(an.tail_uptr.empty() ? 0 : an.tail_uptr.back());
-      Prof p(ctx, PF_K_TAIL_SCHUR, 16.0 * nupd, tb * (8.0 * nupd + 8.0 * c->ntt) + 8.0 * nupd);
-      pfd::launch_tail_schur<T>(s, c->ntt, c->tail_tgt, c->tail_uptr, c->tail_l, c->tail_u, lu, tail, ldt, nt);
-    }
-    for (int k0 = 0; k0 < M; k0 += 64) {
-      const double kb = std::min(64, M - k0);
+  // dense block: panel + trailing update per 64-wide step
+  for (int k0 = 0; k0 < max_M; k0 += NB) {
+    std::vector<int2> panel, gemm;
+    double pfl = 0, pby = 0, gfl = 0, gby = 0;
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      const int M = c->M;
+      if (M <= k0) continue;
+      const int kb = std::min(NB, M - k0);
+      const int nrt = (M - (k0 + kb) + NB - 1) / NB;
+      const int nct = (M + 1 - (k0 + kb) + NB - 1) / NB;
+      for (int g = 0; g < 1 + nrt + nct; ++g) panel.push_back(make_int2(s, g));
       const double rr = M - (k0 + kb), rc = M + 1 - (k0 + kb);
-      {
-        Prof p(ctx, PF_K_DENSE_PANEL, (2.0 / 3.0) * kb * kb * kb + kb * kb * (rr + rc),
-               tb * (2 * kb * kb + 2 * kb * (rr + rc)));
-        pfd::launch_dense_lu_step<T>(s, tail, ldt, M, k0, c->red, 0);
-        pfd::launch_dense_lu_step<T>(s, tail, ldt, M, k0, c->red, 1);
-      }
-      if (rr > 0) {
-        Prof p(ctx, PF_K_DENSE_UPDATE, 2.0 * rr * rc * kb, tb * (rr * kb + kb * rc + 2.0 * rr * rc));
-        pfd::launch_dense_lu_step<T>(s, tail, ldt, M, k0, c->red, 2);
+      pfl += (2.0 / 3.0) * kb * kb * kb + (double)kb * kb * (rr + rc);
+      pby += 8.0 * (kb * kb + 2.0 * kb * (rr + rc));
+      if (nrt > 0 && nct > 0) {
+        for (int t = 0; t < nrt * nct; ++t) gemm.push_back(make_int2(s, t));
+        gfl += 2.0 * rr * rc * kb;
+        gby += 8.0 * (rr * kb + kb * rc + 2.0 * rr * rc);
       }
     }
-    {
-      Prof p(ctx, PF_K_DENSE_TRSV, (double)M * M, tb * ((double)M * M / 2 + 2.0 * M));
-      pfd::launch_dense_trsv_upper<T>(s, tail, ldt, M, x + 2 * ns);
+    emit(L_PANEL, PF_K_DENSE_PANEL, 0, k0, panel, pfl, pby);
+    emit(L_GEMM, PF_K_DENSE_UPDATE, 0, k0, gemm, gfl, gby);
+  }
+  // dense backward solve: flag mode while every work-group fits at once
+  {
+    int total = 0;
+    for (Case* c : cs) total += c->M > 0 ? c->nblk() : 0;
+    trsv_single = total > 256 ? 1 : 0;
+    std::vector<int2> tr;
+    double tfl = 0, tby = 0;
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      if (c->M == 0) continue;
+      if (trsv_single)
+        tr.push_back(make_int2(s, 0));
+      else
+        for (int w = 0; w < c->nblk(); ++w) tr.push_back(make_int2(s, w));
+      tfl += (double)c->M * c->M;
+      tby += 8.0 * ((double)c->M * c->M / 2 + 2.0 * c->M);
     }
+    emit(L_TRSV, PF_K_DENSE_TRSV, 0, 0, tr, tfl, tby);
   }
-  for (int l = 0; l < c->nbl; ++l) {
-    int b = an.bwd_lev_ptr[l], e = an.bwd_lev_ptr[l + 1];
-    Prof p(ctx, PF_K_SPARSE_BWD, 0.0, 0.0);
-    pfd::launch_bwd_rows<T>(s, c->bwd_rows + b, e - b, sc, lu, dinv, x);
+  // sparse backward solve by level
+  for (int l = 0; l < max_blev; ++l) {
+    std::map<int, std::vector<int2>> byG;
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      if (l >= c->nbl) continue;
+      auto& v = byG[c->bwd_g[l]];
+      for (int k = c->an.bwd_lev_ptr[l]; k < c->an.bwd_lev_ptr[l + 1]; ++k) v.push_back(make_int2(s, c->an.bwd_rows[k]));
+    }
+    for (auto& kv : byG) emit(L_BWD, PF_K_SPARSE_BWD, kv.first, 0, kv.second, 0, 0);
   }
+
+  // device buffer: instance table | work items | Red gather
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_tab = al(sizeof(void*) * std::max(nslots, 1));
+  const size_t b_work = al(sizeof(int2) * std::max<size_t>(work.size(), 1));
+  const size_t b_red = al(sizeof(pfd::Red) * std::max(nslots, 1));
+  dmem = (char*)ctx->dalloc(b_tab + b_work + b_red);
+  if (!dmem) return false;
+  d_insts = (const pfd::Inst* const*)dmem;
+  d_work = (int2*)(dmem + b_tab);
+  d_reds = (pfd::Red*)(dmem + b_tab + b_work);
+  std::vector<const pfd::Inst*> tab(nslots);
+  for (int s = 0; s < nslots; ++s) tab[s] = cs[s]->d_inst;
+  hipStream_t st = ctx->stream;
+  bool ok = hipMemcpyAsync((void*)d_insts, tab.data(), sizeof(void*) * nslots, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!work.empty())
+    ok &= hipMemcpyAsync(d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  return ok;
 }
+
+namespace {
 
 template <typename T>
-void update(Case* c) {
-  Ctx* ctx = c->ctx;
+void lu_solve(Batch* b) {
+  Ctx* ctx = b->ctx;
   hipStream_t s = ctx->stream;
-  Prof p(ctx, PF_K_UPDATE, 0.0, 2.0 * sizeof(T) * c->an.nu + 48.0 * c->an.nu);
-  if (c->model == PF_MODEL_POLAR_1PH)
-    pfd::launch_update_polar<T>(s, c->an.nu, c->node, c->dtype, (const T*)c->x, c->vm, c->va, c->v, c->red);
-  else
-    pfd::launch_update_cim<T>(s, c->an.nu, c->node, (const T*)c->x, c->v, c->red);
-}
-
-void mismatch(Case* c) {
-  Ctx* ctx = c->ctx;
-  hipStream_t s = ctx->stream;
-  Prof p(ctx, PF_K_MISMATCH, 8.0 * c->nnz, 24.0 * c->nnz + 60.0 * c->n + 16.0 * c->an.nu);
-  if (c->model == PF_MODEL_POLAR_1PH)
-    pfd::launch_mismatch_polar(s, c->n, c->row_ptr, c->col, c->y, c->v, c->dtype, c->psp, c->qsp, c->pos,
-                               c->ibus, c->F, c->red);
-  else
-    pfd::launch_mismatch_cim(s, c->n, c->row_ptr, c->col, c->y, c->v, c->psp, c->qsp, c->zip, c->pos, c->F,
-                             c->red);
+  const auto* I = b->d_insts;
+  {
+    Prof p(ctx, PF_K_JFILL, 0.0, 0.0);
+    pfd::launch_fill<T>(s, I, b->nslots, 2 * b->max_nu, b->max_lu, b->max_tail, b->max_nnz);
+  }
+  for (const Launch& l : b->seq) {
+    Prof p(ctx, l.cls, l.flops, l.bytes * sizeof(T) / 8.0);
+    const int2* w = b->d_work + l.off;
+    switch (l.kind) {
+      case L_FACTOR:
+        pfd::launch_factor_cols<T>(s, I, w, l.count, l.G);
+        break;
+      case L_FWD:
+        pfd::launch_fwd_rows<T>(s, I, w, l.count, l.G);
+        break;
+      case L_SCHUR:
+        pfd::launch_tail_schur<T>(s, I, w, l.count);
+        break;
+      case L_PANEL:
+        pfd::launch_dense_panel<T>(s, I, w, l.count, l.k0);
+        break;
+      case L_GEMM:
+        pfd::launch_dense_gemm<T>(s, I, w, l.count, l.k0);
+        break;
+      case L_TRSV:
+        pfd::launch_dense_trsv<T>(s, I, w, l.count, b->trsv_single);
+        break;
+      case L_BWD:
+        pfd::launch_bwd_rows<T>(s, I, w, l.count, l.G);
+        break;
+    }
+  }
+  {
+    Prof p(ctx, PF_K_UPDATE, 0.0, 0.0);
+    pfd::launch_update<T>(s, I, b->nslots, b->max_nu);
+  }
 }
 
 }  // namespace
 
-pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
-  Ctx* ctx = c->ctx;
-  hipStream_t s = ctx->stream;
-  std::memset(res, 0, sizeof *res);
+static pf_status check_opts(const pf_options* opt) {
   if (opt->solver != PF_SOLVER_LU) {
     set_error("pf_solve: only the LU inner solver is available in this build");
     return PF_E_INVALID;
@@ -152,6 +243,74 @@ pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
     set_error("pf_solve: tol must be > 0 and max_iter >= 0");
     return PF_E_INVALID;
   }
+  return PF_OK;
+}
+
+static pfd::DevOpts dev_opts(const pf_options* opt) {
+  pfd::DevOpts d;
+  d.tol = opt->tol;
+  d.max_iter = opt->max_iter;
+  d.pad = 0;
+  return d;
+}
+
+// Start of the iteration: initial voltages, state reset, first mismatch and
+// its convergence test.
+pf_status start_batch(Batch* b, const pf_options* opt) {
+  pf_status st = check_opts(opt);
+  if (st != PF_OK) return st;
+  hipStream_t s = b->ctx->stream;
+  pfd::launch_init(s, b->d_insts, b->nslots, b->max_n, opt->flat_start ? 1 : 0);
+  pfd::launch_start(s, b->d_insts, b->nslots);
+  {
+    Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
+    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
+  }
+  pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
+  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+}
+
+// One Newton step of every active instance: linear solve, update, mismatch
+// and the convergence test.
+pf_status step_batch(Batch* b, const pf_options* opt) {
+  hipStream_t s = b->ctx->stream;
+  if (opt->precision == PF_PREC_MIXED)
+    lu_solve<float>(b);
+  else
+    lu_solve<double>(b);
+  {
+    Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
+    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
+  }
+  pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
+  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+}
+
+// Copy every instance's state to the host (synchronises the stream).
+pf_status read_batch(Batch* b, std::vector<pfd::Red>* h) {
+  hipStream_t s = b->ctx->stream;
+  h->resize(b->nslots);
+  pfd::launch_gather_red(s, b->d_insts, b->nslots, b->d_reds);
+  if (hipMemcpyAsync(h->data(), b->d_reds, sizeof(pfd::Red) * b->nslots, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error("pf_solve: device failure during the Newton iteration");
+    return PF_E_DEVICE;
+  }
+  b->ctx->prof_flush();
+  for (const auto& r : *h)
+    if (r.timeout) {
+      set_error("pf_solve: an inter-work-group wait on the device timed out");
+      return PF_E_DEVICE;
+    }
+  return PF_OK;
+}
+
+pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
+  Ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  const int B = b->nslots;
+  for (int i = 0; i < B; ++i) std::memset(&results[i], 0, sizeof(pf_result));
+  if (B == 0) return PF_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) {
     set_error("pf_solve: hipSetDevice failed");
     return PF_E_DEVICE;
@@ -162,60 +321,15 @@ pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
     return PF_E_DEVICE;
   }
   (void)hipEventRecord(e0, s);
-  if (opt->flat_start) {
-    if (c->model == PF_MODEL_POLAR_1PH)
-      pfd::launch_init_polar(s, c->n, c->dtype, c->vmag, c->vang, c->vm, c->va, c->v, 1);
-    else
-      pfd::launch_init_cim(s, c->n, c->dtype, c->vmag, c->vang, c->v);
-  }
-  const bool mixed = opt->precision == PF_PREC_MIXED;
-  pfd::launch_reset_red(s, c->red);
-  mismatch(c);
-  double norm0 = 0;
-  int status = PF_MAXITER;
-  int it = 0;
-  pfd::Red h;
-  for (;; ++it) {
-    if (hipMemcpyAsync(&h, c->red, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      set_error("pf_solve: device failure during the Newton iteration");
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return PF_E_DEVICE;
-    }
-    double norm = bits_to_double(h.norm_bits);
-    res->mismatch_inf = norm;
-    if (it > 0) res->max_step = bits_to_double(h.step_bits);
-    if (it > 0 && h.singular) {
-      status = PF_SINGULAR;
-      break;
-    }
-    if (!std::isfinite(norm) || (it > 0 && !std::isfinite(res->max_step))) {
-      status = PF_DIVERGED;
-      break;
-    }
-    if (it == 0) norm0 = norm;
-    if (norm <= opt->tol) {
-      status = PF_CONVERGED;
-      break;
-    }
-    if (it > 0 && norm > 1e6 * norm0) {
-      status = PF_DIVERGED;
-      break;
-    }
-    if (it >= opt->max_iter) {
-      status = PF_MAXITER;
-      break;
-    }
-    pfd::launch_reset_red(s, c->red);
-    if (mixed) {
-      lu_solve<float>(c);
-      update<float>(c);
-    } else {
-      lu_solve<double>(c);
-      update<double>(c);
-    }
-    mismatch(c);
+  pf_status st = start_batch(b, opt);
+  std::vector<pfd::Red> h;
+  for (int guard = 0; st == PF_OK && guard <= opt->max_iter + 1; ++guard) {
+    st = read_batch(b, &h);
+    if (st != PF_OK) break;
+    bool any = false;
+    for (const auto& r : h) any |= r.active != 0;
+    if (!any) break;
+    st = step_batch(b, opt);
   }
   (void)hipEventRecord(e1, s);
   (void)hipEventSynchronize(e1);
@@ -224,10 +338,29 @@ pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ctx->prof_flush();
-  res->status = status;
-  res->iters = it;
-  res->device_ms = ms;
+  if (st != PF_OK) return st;
+  for (int i = 0; i < B; ++i) {
+    results[i].status = h[i].status;
+    results[i].iters = h[i].it;
+    results[i].linear_iters = h[i].linear_iters;
+    results[i].mismatch_inf = h[i].last_norm;
+    results[i].max_step = h[i].last_step;
+    results[i].device_ms = ms;
+  }
   return PF_OK;
+}
+
+pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
+  if (!c->single) {
+    auto* b = new Batch();
+    if (!b->build(c->ctx, {c})) {
+      delete b;
+      set_error("pf_solve: batch set-up failed");
+      return PF_E_NOMEM;
+    }
+    c->single = b;
+  }
+  return run_batch(c->single, opt, res);
 }
 
 }  // namespace pfi

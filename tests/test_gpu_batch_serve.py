@@ -1,0 +1,195 @@
+"""GPU tests of the batched and served forms: every instance's result is
+bit-identical alone, in a batch and in the serving mix, and matches the
+CPU oracle."""
+
+import random
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import pfgen
+from oracle import cim, polar
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+VTOL = 1e-7
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1711_10579_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.pf_ctx_create(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mix():
+    cases = [pfgen.config_case(0)]
+    rng = np.random.default_rng(5)
+    for i in range(9):
+        n = int(np.exp(rng.uniform(np.log(100), np.log(3000))))
+        base = pfgen.make_polar_grid(n, int(0.3 * n), max(1, n // 10), 500 + i, balanced=True)
+        cases.append(pfgen.perturb_loads(base, 900 + i))
+    cases.append(pfgen.make_feeder(120, 7))
+    cases.append(pfgen.perturb_loads(pfgen.make_feeder(400, 8), 3))
+    return cases
+
+
+def _check(case, r, V):
+    assert r.status == 0, (case.name, r.as_dict())
+    if hasattr(case, "bus_type"):
+        assert polar.mismatch_at(case, V) <= TOL
+        ref = polar.newton(case)
+        assert np.max(np.abs(np.abs(V) - ref.vm)) <= VTOL
+        assert np.max(np.abs(np.angle(V) - ref.va)) <= VTOL
+    else:
+        assert cim.mismatch_at(case, V) <= TOL
+        ref = cim.newton(case)
+        assert np.max(np.abs(V - ref.V)) <= VTOL
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_bit_identical_to_alone_and_matches_oracle(B, ctx, precision):
+    cases = _mix()
+    _say(f"batch precision={precision}")
+    handles = [B.pf_create_from(ctx, c) for c in cases]
+    opts = dict(precision=precision, max_iter=40 if precision else 20)
+    alone, Va = [], []
+    for h in handles:
+        alone.append(B.pf_solve(h, **opts))
+        Va.append(B.pf_get_voltage(h))
+    res = B.pf_solve_batch(ctx, handles, **opts)
+    for c, h, ra, va, rb in zip(cases, handles, alone, Va, res):
+        vb = B.pf_get_voltage(h)
+        assert rb.status == ra.status and rb.iters == ra.iters, c.name
+        assert np.array_equal(va, vb), c.name
+        assert rb.mismatch_inf == ra.mismatch_inf
+        _check(c, rb, vb)
+    for h in handles:
+        h.close()
+
+
+def test_batch_isolates_failures(B, ctx):
+    import pins
+
+    good = [pfgen.make_polar_grid(300, 90, 30, 41, balanced=True), pfgen.make_feeder(60, 2)]
+    c0 = pfgen.config_case(0)
+    heavy = c0.with_injections(c0.p_sp * 50, c0.q_sp * 50)
+    island = pins.polar_case(3, [0], [1], [0.02], [0.1], [0.0], [3, 1, 1],
+                             [0, -0.3, -0.1], [0, -0.1, -0.05], [1, 1, 1])
+    island.row_ptr = np.array([0, 2, 4, 5], np.int32)
+    island.col = np.array([0, 1, 0, 1, 2], np.int32)
+    island.y = np.concatenate([island.y, [0j]])
+    cases = [good[0], heavy, island, good[1]]
+    _say("batch failures")
+    hs = [B.pf_create_from(ctx, c) for c in cases]
+    alone = []
+    for h in hs:
+        alone.append((B.pf_solve(h), B.pf_get_voltage(h)))
+    res = B.pf_solve_batch(ctx, hs)
+    assert res[1].status in (B.PF_DIVERGED, B.PF_MAXITER)
+    assert res[2].status == B.PF_SINGULAR
+    for i in (0, 3):
+        assert res[i].status == 0
+        assert np.array_equal(B.pf_get_voltage(hs[i]), alone[i][1])
+    for h in hs:
+        h.close()
+
+
+def test_batch_many_small_instances_single_mode_trsv(B, ctx):
+    # enough dense blocks that the backward solve runs one work-group per
+    # instance; results must not change
+    cases = [pfgen.perturb_loads(pfgen.make_polar_grid(1500, 450, 150, 60 + i, balanced=True), i)
+             for i in range(24)]
+    _say("batch 24 x 1500")
+    hs = [B.pf_create_from(ctx, c) for c in cases]
+    alone = []
+    for h in hs:
+        B.pf_solve(h)
+        alone.append(B.pf_get_voltage(h))
+    res = B.pf_solve_batch(ctx, hs)
+    for c, h, va, r in zip(cases, hs, alone, res):
+        assert r.status == 0
+        assert np.array_equal(B.pf_get_voltage(h), va), c.name
+    _check(cases[0], res[0], alone[0])
+    for h in hs:
+        h.close()
+
+
+def test_serving_continuous_batching_mix(B, ctx):
+    cases = _mix() + [pfgen.perturb_loads(pfgen.config_case(2), 11)]
+    _say("serving")
+    hs = [B.pf_create_from(ctx, c) for c in cases]
+    alone = []
+    for h in hs:
+        r = B.pf_solve(h)
+        alone.append((r, B.pf_get_voltage(h)))
+    B.pf_serve_config(ctx, max_bytes=0, max_slots=8)
+    rng = random.Random(3)
+    tickets = {}
+    t_submit = {}
+
+    def producer():
+        order = list(range(len(hs)))
+        rng.shuffle(order)
+        for i in order:
+            tickets[i] = B.pf_submit(ctx, hs[i])
+            t_submit[i] = time.perf_counter()
+            time.sleep(rng.expovariate(1 / 0.004))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    got = {}
+    t0 = time.perf_counter()
+    while len(got) < len(hs):
+        for i, t in list(tickets.items()):
+            if i in got:
+                continue
+            done, r = B.pf_poll(ctx, t)
+            if done:
+                got[i] = (r, time.perf_counter() - t_submit[i])
+        assert time.perf_counter() - t0 < 120
+        time.sleep(0.0005)
+    th.join()
+    lat = []
+    for i, h in enumerate(hs):
+        r, dt = got[i]
+        lat.append(dt)
+        assert r.status == alone[i][0].status and r.iters == alone[i][0].iters
+        assert np.array_equal(B.pf_get_voltage(h), alone[i][1]), cases[i].name
+    _say(f"serving latency p50={np.percentile(lat, 50) * 1e3:.2f} ms p99={np.percentile(lat, 99) * 1e3:.2f} ms")
+    with pytest.raises(B.PFError):
+        B.pf_poll(ctx, 10 ** 9)
+    for h in hs:
+        h.close()
+
+
+def test_destroy_of_queued_case_is_busy(B, ctx):
+    big = pfgen.config_case(1)
+    h = B.pf_create_from(ctx, big)
+    t = B.pf_submit(ctx, h)
+    with pytest.raises(B.PFError) as ei:
+        h.close()
+    assert ei.value.code in (B.PF_E_BUSY,)
+    while True:
+        done, r = B.pf_poll(ctx, t)
+        if done:
+            break
+        time.sleep(0.001)
+    assert r.status == 0
+    h.close()
