@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--breakdown", action="store_true",
                     help="time every kernel class in an extra untimed pass (stderr)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="scenarios of the batched form (seeded +-20%% load perturbations)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -130,6 +132,33 @@ def main():
 
     mism = polar.mismatch_at(case, V)
 
+    # batched form: the same grid under seeded load scenarios, one
+    # pf_solve_batch per step
+    batched = None
+    if args.batch > 1:
+        scen = [pfgen.perturb_loads(case, 7000 + i) for i in range(args.batch)]
+        hb = [B.pf_create_from(ctx, sc) for sc in scen]
+        for _ in range(max(1, args.warmup)):
+            B.pf_solve_batch(ctx, hb, opts)
+        bsteps = max(2, args.steps // 4)
+        torch.cuda.synchronize()
+        blat, bconv = [], 0
+        t0 = time.perf_counter()
+        for _ in range(bsteps):
+            s0 = time.perf_counter()
+            rs = B.pf_solve_batch(ctx, hb, opts)
+            blat.append(time.perf_counter() - s0)
+            bconv += sum(r.status == B.PF_CONVERGED for r in rs)
+        torch.cuda.synchronize()
+        bel = time.perf_counter() - t0
+        Vb = B.pf_get_voltage(hb[-1])
+        batched = {"instances": args.batch, "value": bconv / bel, "unit": "solves/s",
+                   "batch_latency_ms": {"p50": 1000 * _pct(blat, 50), "p99": 1000 * _pct(blat, 99)},
+                   "steps": bsteps, "converged": bconv,
+                   "final_mismatch_oracle": polar.mismatch_at(scen[-1], Vb)}
+        for x in hb:
+            x.close()
+
     avg_ms = st["ms"] / max(st["launches"], 1)
     flops_per_launch = st["flops"] / max(st["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
@@ -163,6 +192,7 @@ def main():
         "converged": conv,
         "final_mismatch_oracle": mism,
         "roofline": roofline,
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)

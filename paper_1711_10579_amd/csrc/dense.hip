@@ -25,6 +25,18 @@ namespace pfd {
 
 constexpr int NB = 64;
 
+// Reciprocal from the hardware estimate refined by Newton steps
+// r <- r + r (1 - x r) (two for FP64, one for FP32).
+__device__ inline double fast_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline float fast_recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename T>
 struct Tile {
   T v[4][4];
@@ -59,35 +71,97 @@ __device__ inline void tile_store(const Tile<T>& t, T* A, int ld, int r0, int c0
     }
 }
 
-// LU without pivoting of the 64x64 register tile d (padded with identity).
-// Step k applies the rank-1 update with multipliers and pivot row zeroed
-// outside the active part, so each element costs one FMA; the pivot column
-// is kept unscaled and divided by its pivot at the end.  On return d (and
-// the LDS copy s) hold unit-lower L below the diagonal and U.
+// Panel step k0 of every instance in the work list: item (slot, g).
+//
+// Every work-group factors the 64x64 diagonal block A_kk (identity-padded)
+// in registers, one pivot per step: the pivot row and column go through
+// double-buffered LDS, and each element update is one FMA with multipliers
+// and pivot row zeroed outside the active part.  Row k of U and column k of L
+// are final at step k, so in the same step each work-group also advances its
+// own triangular solve:
+//   g = 0:        Y = U^{-T} by forward substitution (U^T Y = I; row k of Y
+//                 is final at step k); the factored block goes to dfac and
+//                 U^{-1} = Y^T to dinvu (the other work-groups still read the
+//                 unfactored block from A);
+//   g in 1..nrt:  a 64-row tile below the block, x U = a (L_ik = A_ik U^{-1});
+//   g > nrt:      a 64-column tile right of it, the last one holding the RHS
+//                 column M, L y = a (U_kj = L_kk^{-1} A_kj).
+// Divisions by U_kk are applied once after the loop (columns of L and of x,
+// rows of Y are not touched after their step).
 template <typename T>
-__device__ inline void tile_lu(Tile<T>& d, T (*s)[NB + 1], T (*col)[NB], T (*row)[NB], int tx, int ty,
-                               int* bad) {
-  const int tid = ty * 16 + tx;
-  if (tx == 0) {
+__global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
+                                                     int k0) {
+  __shared__ T row[2][NB], col[2][NB];    // pivot row / column of the block
+  __shared__ T trow[2][NB], tcol[2][NB];  // published row / column of the tile
+  __shared__ T rdiag[NB];
+  __shared__ int bad;
+  const int2 w = work[blockIdx.x];
+  const Inst& I = *insts[w.x];
+  if (I.red->active == 0) return;
+  T* A = (T*)I.tail;
+  const int ld = I.ldt, M = I.M;
+  // the launch is uniform per work-group: keep these in scalar registers
+  const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
+  const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
+  const int g = __builtin_amdgcn_readfirstlane(w.y);
+  const int role = g == 0 ? 0 : (g <= nrt ? 1 : 2);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16, tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  if (tid < NB) rdiag[tid] = T(1);
+  Tile<T> d, t;
+  tile_load(d, A, ld, k0, k0, kb, kb, tx, ty, true);
+  int r0 = 0, c0 = 0, nr = 0, nc = 0;
+  if (role == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) col[0][ty + 16 * i] = d.v[i][0];
-  }
-  if (ty == 0) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) row[0][tx + 16 * j] = d.v[0][j];
+      for (int j = 0; j < 4; ++j) t.v[i][j] = (ty + 16 * i == tx + 16 * j) ? T(1) : T(0);
+  } else if (role == 1) {
+    r0 = k0 + kb + (g - 1) * NB;
+    nr = min(NB, M - r0);
+    tile_load(t, A, ld, r0, k0, nr, kb, tx, ty, false);
+  } else {
+    c0 = k0 + kb + (g - 1 - nrt) * NB;
+    nc = min(NB, M + 1 - c0);
+    tile_load(t, A, ld, k0, c0, kb, nc, tx, ty, false);
   }
+  // publish step 0: row/column 0 of the block, row 0 (roles 0, 2) or column 0
+  // (role 1) of the tile
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ty + 16 * i, c = tx + 16 * j;
+      if (c == 0) col[0][r] = d.v[i][j];
+      if (r == 0) row[0][c] = d.v[i][j];
+      if (role == 1 && c == 0) tcol[0][r] = t.v[i][j];
+      if (role != 1 && r == 0) trow[0][c] = t.v[i][j];
+    }
   __syncthreads();
-  for (int k = 0; k < NB; ++k) {
+  for (int k = 0; k < kb; ++k) {
     const int b = k & 1, nb = b ^ 1;
-    T rv[4], cv[4];
+    T rv[4], cv[4], tv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) rv[j] = row[b][tx + 16 * j];
 #pragma unroll
     for (int i = 0; i < 4; ++i) cv[i] = col[b][ty + 16 * i];
+    if (role == 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tv[i] = tcol[b][ty + 16 * i];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tv[j] = trow[b][tx + 16 * j];
+    }
+    T ur[4];
+    if (role == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ur[i] = row[b][ty + 16 * i];
+    }
     T piv = row[b][k];
-    if (tid == 0 && (!(piv != T(0)) || !isfinite((double)piv))) *bad = 1;
+    if (tid == 0 && (!(piv != T(0)) || !isfinite((double)piv))) bad = 1;
     piv = (piv != T(0)) ? piv : T(1);
-    const T rinv = T(1) / piv;
+    const T rinv = fast_recip(piv);
+    if (tid == 0) rdiag[k] = rinv;
     T l[4], u[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) l[i] = (ty + 16 * i > k) ? cv[i] * rinv : T(0);
@@ -97,192 +171,96 @@ __device__ inline void tile_lu(Tile<T>& d, T (*s)[NB + 1], T (*col)[NB], T (*row
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) d.v[i][j] = fma(-l[i], u[j], d.v[i][j]);
+    if (role == 0) {
+      // rows r > k of Y: Y(r,:) -= U(k,r) Y(k,:), Y(k,:) = Yacc(k,:) / U_kk
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T m = (ty + 16 * i > k) ? ur[i] : T(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-m, tv[j] * rinv, t.v[i][j]);
+      }
+    } else if (role == 1) {
+      // columns c > k of x: a(:,c) -= x(:,k) U(k,c), x(:,k) = a(:,k) / U_kk
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T xk = tv[i] * rinv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-xk, u[j], t.v[i][j]);
+      }
+    } else {
+      // rows r > k of y: a(r,:) -= L(r,k) y(k,:)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-l[i], tv[j], t.v[i][j]);
+    }
+    // publish row and column k+1 of the block and of the tile.  Their owners
+    // are the threads with tx (ty) == (k+1) % 16, register column (row)
+    // (k+1) / 16 (uniform); entries outside the active part are stored too:
+    // they are finite and the next step masks them out.
     const int k1 = k + 1;
+    if (k1 < kb) {
+      const bool own_c = tx == (k1 & 15), own_r = ty == (k1 & 15);
+#define PF_PUB(J)                                                                  \
+  {                                                                                \
+    if (own_c) {                                                                   \
+      for (int i = 0; i < 4; ++i) col[nb][ty + 16 * i] = d.v[i][J];                \
+      if (role == 1)                                                               \
+        for (int i = 0; i < 4; ++i) tcol[nb][ty + 16 * i] = t.v[i][J];             \
+    }                                                                              \
+    if (own_r) {                                                                   \
+      for (int j = 0; j < 4; ++j) row[nb][tx + 16 * j] = d.v[J][j];                \
+      if (role != 1)                                                               \
+        for (int j = 0; j < 4; ++j) trow[nb][tx + 16 * j] = t.v[J][j];             \
+    }                                                                              \
+  }
+      switch (k1 >> 4) {
+        case 0:
+          PF_PUB(0);
+          break;
+        case 1:
+          PF_PUB(1);
+          break;
+        case 2:
+          PF_PUB(2);
+          break;
+        default:
+          PF_PUB(3);
+          break;
+      }
+#undef PF_PUB
+    }
+    __syncthreads();
+  }
+  if (role == 0) {
+    // L below the diagonal: divide the stored columns by their pivots
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = ty + 16 * i, c = tx + 16 * j;
-        if (c == k1 && r > k) col[nb][r] = d.v[i][j];
-        if (r == k1 && c > k) row[nb][c] = d.v[i][j];
+        if (r > c) d.v[i][j] *= rdiag[c];
       }
-    __syncthreads();
-  }
+    tile_store(d, (T*)I.dfac + (int64_t)(k0 / NB) * NB * NB, NB, 0, 0, NB, NB, tx, ty);
+    if (tid == 0 && bad) I.red->singular = 1;
+    // U^{-1} = Y^T, rows of Y divided by their pivots
+    T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 16 * i;
+      const T sc = rdiag[r];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s[ty + 16 * i][tx + 16 * j] = d.v[i][j];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) ui[(int64_t)r * NB + tx + 16 * j] = t.v[i][j] * sc;
+    }
+  } else if (role == 1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = ty + 16 * i, c = tx + 16 * j;
-      if (r > c) {
-        T dc = s[c][c];
-        dc = (dc != T(0)) ? dc : T(1);
-        d.v[i][j] = d.v[i][j] / dc;
-      }
-    }
-  __syncthreads();
+      const T sc = rdiag[tx + 16 * j];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (ty + 16 * i > tx + 16 * j) s[ty + 16 * i][tx + 16 * j] = d.v[i][j];
-  __syncthreads();
-}
-
-// Inverse of the upper triangle held in s (identity-padded): U X = I solved
-// by rows from the bottom (row r of X is final once the rows below it have
-// been applied; it is divided by U_rr at the end).  X is returned in x.
-template <typename T>
-__device__ inline void tile_upper_inverse(Tile<T>& x, T (*s)[NB + 1], T (*row)[NB], int tx, int ty) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) x.v[i][j] = (ty + 16 * i == tx + 16 * j) ? T(1) : T(0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (ty + 16 * i == NB - 1) row[0][tx + 16 * j] = x.v[i][j];
-  __syncthreads();
-  for (int st = 0; st < NB; ++st) {
-    const int r = NB - 1 - st;
-    const int b = st & 1, nb = b ^ 1;
-    T urr = s[r][r];
-    urr = (urr != T(0)) ? urr : T(1);
-    const T rinv = T(1) / urr;
-    T xv[4], ul[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = row[b][tx + 16 * j] * rinv;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ul[i] = (ty + 16 * i < r) ? s[ty + 16 * i][r] : T(0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) x.v[i][j] = fma(-ul[i], xv[j], x.v[i][j]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (r > 0 && ty + 16 * i == r - 1) row[nb][tx + 16 * j] = x.v[i][j];
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    T urr = s[ty + 16 * i][ty + 16 * i];
-    urr = (urr != T(0)) ? urr : T(1);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) x.v[i][j] = x.v[i][j] / urr;
-  }
-}
-
-// Panel step k0 of every instance in the work list: item (slot, g).  g = 0
-// writes the factored diagonal block to dfac and the inverse of its U to dinvu
-// (the other work-groups still read the unfactored block from A); g in
-// 1..nrt takes a 64-row tile below it (L_ik = A_ik U_kk^{-1}); the rest take
-// 64-column tiles right of it, the last one holding the RHS column M
-// (U_kj = L_kk^{-1} A_kj).
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
-                                                     int k0) {
-  __shared__ T s[NB][NB + 1];
-  __shared__ T col[2][NB];
-  __shared__ T row[2][NB];
-  __shared__ int bad;
-  const int2 w = work[blockIdx.x];
-  const Inst& I = *insts[w.x];
-  if (I.red->active == 0) return;
-  T* A = (T*)I.tail;
-  const int ld = I.ldt, M = I.M;
-  const int kb = min(NB, M - k0);
-  const int nrt = (M - (k0 + kb) + NB - 1) / NB;
-  T* dfac = (T*)I.dfac + (int64_t)(k0 / NB) * NB * NB;
-  T* dinvu = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  if (threadIdx.x == 0) bad = 0;
-  Tile<T> d;
-  tile_load(d, A, ld, k0, k0, kb, kb, tx, ty, true);
-  tile_lu(d, s, col, row, tx, ty, &bad);
-  const int b = w.y;
-  if (b == 0) {
-    tile_store(d, dfac, NB, 0, 0, NB, NB, tx, ty);
-    if (threadIdx.x == 0 && bad) I.red->singular = 1;
-    Tile<T> xi;
-    tile_upper_inverse(xi, s, row, tx, ty);
-    tile_store(xi, dinvu, NB, 0, 0, NB, NB, tx, ty);
-    return;
-  }
-  Tile<T> t;
-  if (b <= nrt) {
-    // rows r0..r0+nr-1: x U = a by a column sweep on the unscaled columns
-    const int r0 = k0 + kb + (b - 1) * NB;
-    const int nr = min(NB, M - r0);
-    tile_load(t, A, ld, r0, k0, nr, kb, tx, ty, false);
-    if (tx == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) col[0][ty + 16 * i] = t.v[i][0];
-    }
-    __syncthreads();
-    for (int c = 0; c < kb; ++c) {
-      const int bb = c & 1, nb2 = bb ^ 1;
-      T ucc = s[c][c];
-      ucc = (ucc != T(0)) ? ucc : T(1);
-      const T rinv = T(1) / ucc;
-      T xc[4], u[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xc[i] = col[bb][ty + 16 * i] * rinv;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = (tx + 16 * j > c) ? s[c][tx + 16 * j] : T(0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-xc[i], u[j], t.v[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (tx + 16 * j == c + 1) col[nb2][ty + 16 * i] = t.v[i][j];
-      __syncthreads();
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      T ucc = s[tx + 16 * j][tx + 16 * j];
-      ucc = (ucc != T(0)) ? ucc : T(1);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) t.v[i][j] = t.v[i][j] / ucc;
+      for (int i = 0; i < 4; ++i) t.v[i][j] *= sc;
     }
     tile_store(t, A, ld, r0, k0, nr, kb, tx, ty);
   } else {
-    // columns c0..c0+nc-1: L y = a (unit lower) by a row sweep
-    const int c0 = k0 + kb + (b - 1 - nrt) * NB;
-    const int nc = min(NB, M + 1 - c0);
-    tile_load(t, A, ld, k0, c0, kb, nc, tx, ty, false);
-    if (ty == 0) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) row[0][tx + 16 * j] = t.v[0][j];
-    }
-    __syncthreads();
-    for (int r = 0; r < kb; ++r) {
-      const int bb = r & 1, nb2 = bb ^ 1;
-      T yv[4], l[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) yv[j] = row[bb][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) l[i] = (ty + 16 * i > r) ? s[ty + 16 * i][r] : T(0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-l[i], yv[j], t.v[i][j]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (ty + 16 * i == r + 1) row[nb2][tx + 16 * j] = t.v[i][j];
-      __syncthreads();
-    }
     tile_store(t, A, ld, k0, c0, kb, nc, tx, ty);
   }
 }
@@ -325,8 +303,8 @@ __global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, co
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
-  const int kb = min(NB, M - k0);
-  const int nrt = (M - (k0 + kb) + NB - 1) / NB;
+  const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
+  const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
   const int tid = threadIdx.x;
   const int r0 = k0 + kb + (wk.y % nrt) * NB;
   const int c0 = k0 + kb + (wk.y / nrt) * NB;
