@@ -1,28 +1,40 @@
 #!/usr/bin/env python3
 """Throughput of converged Newton power-flow solves on one MI355X.
 
-A step is one complete power-flow solve (flat start to max-norm FP64 mismatch
-<= 1e-8 pu) of the 10,000-bus meshed transmission grid (seeded synthetic;
-tree + 3,000 uniform chords, 1,000 PV buses, balanced dispatch), with every
-Newton phase on the GPU: mismatch, Jacobian fill, sparse refactorisation with
-its dense trailing block, triangular solves and voltage update.  Inputs are
-resident in device memory before the timed region.
+Default workload: a step is one complete power-flow solve (flat start to
+max-norm FP64 mismatch <= 1e-8 pu) of the 10,000-bus meshed transmission grid
+(seeded synthetic; tree + 3,000 uniform chords, 1,000 PV buses, balanced
+dispatch), with every Newton phase on the GPU: mismatch, Jacobian fill, sparse
+refactorisation with its dense trailing block, triangular solves, voltage
+update and the convergence test.  Inputs are resident in device memory before
+the timed region.  Prints one JSON line with solves/s, latency percentiles,
+the batched form on the same grid, the roofline of the dominant kernel (timed
+with HIP events inside the timed region) and the CPU oracle timed on a
+bounded sample of the same work.
 
-Prints one JSON line (rank 0) with solves/s, latency percentiles, the
-roofline figures of the dominant kernel (timed with HIP events inside the
-timed region) and the CPU oracle timed on a bounded sample of the same work.
+Other modes (each prints its own JSON line):
+  --workload scenarios512   512 grids of 100-5,000 buses, FP32 inner solves,
+                            one pf_solve_batch per step
+  --workload served         Poisson-arriving requests on a pool of single- and
+                            three-phase grids through pf_submit/pf_poll
+  --calibrate-copy          a plain 256 MiB device copy (for scaling the
+                            FETCH_SIZE / WRITE_SIZE counters)
 """
 
 import argparse
 import json
 import os
+import random
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_tflops": 157.3}
+# MI355X peaks: HBM 8 TB/s; FP64 vector and FP64 matrix 78.6 TFLOP/s (vector:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz); FP32 matrix 157.3 TFLOP/s
+# (FP32 vector is 78.6 without packed FP32, which this build does not use)
+PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_mfma_tflops": 157.3, "fp32_valu_tflops": 78.6}
 METRIC = "converged PF solves/s at 1e-8 pu mismatch, batched vs plain; p50/p99 latency"
 
 
@@ -55,28 +67,67 @@ def cpu_baseline(case, budget_s=20.0):
                       f"{el:.1f} s, FP64 NumPy/SciPy SuperLU, 1 thread"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--breakdown", action="store_true",
-                    help="time every kernel class in an extra untimed pass (stderr)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=16,
-                    help="scenarios of the batched form (seeded +-20%% load perturbations)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(independent power-flow instances shard across GPUs without collectives)",
-              file=sys.stderr)
-        sys.exit(2)
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary (already scaled by the plain-copy calibration), or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
 
+    path = os.path.join(ROOT, "profiles", "k_dense_panel_grid10k_pmc.md")
+    src = os.path.join(ROOT, "paper_1711_10579_amd", "csrc", "dense.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    val, cap = None, None
+    for line in text.splitlines():
+        if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
+            val = float(line.split(":")[1])
+        if line.startswith("dense.hip sha256 prefix at capture:"):
+            cap = line.split(":")[1].strip()
+    return val if cap == sha else None
+
+
+def _roof(st, bound, peak, unit, kernel):
+    n = max(st["launches"], 1)
+    avg_ms = st["ms"] / n
+    if bound == "hbm":
+        per = st["bytes"] / n
+        achieved = per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    else:
+        per = st["flops"] / n
+        achieved = per / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "kernel": kernel,
+            "avg_launch_ms": avg_ms, "launches": st["launches"],
+            ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): per}
+
+
+def calibrate_copy():
+    import torch
+
+    nbytes = 256 << 20
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"mode": "calibrate-copy", "bytes_read_per_copy": nbytes,
+                      "bytes_written_per_copy": nbytes, "copies": reps,
+                      "GBps": 2 * nbytes * reps / el / 1e9}), flush=True)
+
+
+def bench_grid10k(args):
     import numpy as np
     import torch
 
     import pfgen
+    from oracle import polar
     from paper_1711_10579_amd import binding as B
 
     case = pfgen.config_case(1)
@@ -105,12 +156,12 @@ def main():
             if s["launches"]:
                 print(f"[breakdown] {name:14s} launches/solve={s['launches'] / 3:8.1f} "
                       f"ms/solve={s['ms'] / 3:8.4f} ({100 * s['ms'] / tot:5.1f}%) "
-                      f"GFLOP/s={s['flops'] / max(s['ms'], 1e-12) / 1e6:9.1f} "
-                      f"GB/s={s['bytes'] / max(s['ms'], 1e-12) / 1e6:9.1f}", file=sys.stderr)
+                      f"GFLOP/s={s['flops'] / max(s['ms'], 1e-12) / 1e6:9.1f}", file=sys.stderr)
         B.pf_profile_enable(ctx, 0)
 
-    # dominant kernel: the trailing-block update of the dense LU
-    dom = B.PF_K_DENSE_UPDATE
+    # the dominant kernel (panel steps of the dense block LU) is timed with
+    # HIP events on the library's stream inside the timed region
+    dom, sec = B.PF_K_DENSE_PANEL, B.PF_K_DENSE_UPDATE
     B.pf_profile_enable(ctx, 1 << dom)
     B.pf_profile_reset(ctx)
     torch.cuda.synchronize()
@@ -124,13 +175,16 @@ def main():
         iters.append(r.iters)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    st = B.pf_kernel_stats(ctx, dom)
+    st_dom = B.pf_kernel_stats(ctx, dom)
+    # the matrix-core trailing update, timed the same way in two extra solves
+    # after the timed region
+    B.pf_profile_enable(ctx, 1 << sec)
+    B.pf_profile_reset(ctx)
+    for _ in range(2):
+        B.pf_solve(h, opts)
+    st_sec = B.pf_kernel_stats(ctx, sec)
     B.pf_profile_enable(ctx, 0)
-
-    V = B.pf_get_voltage(h)
-    from oracle import polar
-
-    mism = polar.mismatch_at(case, V)
+    mism = polar.mismatch_at(case, B.pf_get_voltage(h))
 
     # batched form: the same grid under seeded load scenarios, one
     # pf_solve_batch per step
@@ -151,24 +205,15 @@ def main():
             bconv += sum(r.status == B.PF_CONVERGED for r in rs)
         torch.cuda.synchronize()
         bel = time.perf_counter() - t0
-        Vb = B.pf_get_voltage(hb[-1])
         batched = {"instances": args.batch, "value": bconv / bel, "unit": "solves/s",
                    "batch_latency_ms": {"p50": 1000 * _pct(blat, 50), "p99": 1000 * _pct(blat, 99)},
                    "steps": bsteps, "converged": bconv,
-                   "final_mismatch_oracle": polar.mismatch_at(scen[-1], Vb)}
+                   "final_mismatch_oracle": polar.mismatch_at(scen[-1], B.pf_get_voltage(hb[-1]))}
         for x in hb:
             x.close()
 
-    avg_ms = st["ms"] / max(st["launches"], 1)
-    flops_per_launch = st["flops"] / max(st["launches"], 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    peak = PEAK["fp32_tflops"] if mixed else PEAK["fp64_tflops"]
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "k_dense_gemm (trailing update of the dense block LU)",
-                "avg_launch_ms": avg_ms, "launches": st["launches"],
-                "flops_per_launch": flops_per_launch}
-
+    valu_peak = PEAK["fp32_valu_tflops"] if mixed else PEAK["fp64_tflops"]
+    mfma_peak = PEAK["fp32_mfma_tflops"] if mixed else PEAK["fp64_tflops"]
     out = {
         "metric": METRIC,
         "value": conv / elapsed,
@@ -191,12 +236,190 @@ def main():
         "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
         "converged": conv,
         "final_mismatch_oracle": mism,
-        "roofline": roofline,
+        "roofline": dict(_roof(st_dom, "alu", valu_peak, "TFLOP/s",
+                               "k_dense_panel (diagonal-block LU + tile solves of the dense block)"),
+                         traffic=None if mixed else _measured_traffic("k_dense_panel")),
+        "roofline_secondary": _roof(st_sec, "mfma", mfma_peak, "TFLOP/s",
+                                    "k_dense_gemm (matrix-core trailing update of the dense block)"),
         "batched": batched,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
+
+
+def bench_scenarios512(args):
+    import numpy as np
+    import torch
+
+    import pfgen
+    from oracle import polar
+    from paper_1711_10579_amd import binding as B
+
+    t0 = time.perf_counter()
+    scen = pfgen.c3_scenarios(args.instances)
+    t_gen = time.perf_counter() - t0
+    ctx = B.pf_ctx_create(0)
+    t0 = time.perf_counter()
+    hs = [B.pf_create_from(ctx, c) for c in scen]
+    t_setup = time.perf_counter() - t0
+    mixed = args.precision != "fp64"
+    opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
+    B.pf_solve_batch(ctx, hs, opts)
+    torch.cuda.synchronize()
+    conv, steps = 0, max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rs = B.pf_solve_batch(ctx, hs, opts)
+        conv += sum(r.status == B.PF_CONVERGED for r in rs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # FP64-oracle error on a sample of scenarios (the oracle's own roots)
+    rng = np.random.default_rng(1)
+    sample = sorted(rng.choice(len(scen), size=min(args.oracle_sample, len(scen)), replace=False))
+    errs = []
+    for i in sample:
+        V = B.pf_get_voltage(hs[i])
+        ref = polar.newton(scen[i])
+        errs.append(float(max(np.max(np.abs(np.abs(V) - ref.vm)), np.max(np.abs(np.angle(V) - ref.va)))))
+    out = {"mode": "scenarios512", "metric": METRIC, "value": conv / el, "unit": "solves/s",
+           "instances": len(scen), "steps": steps, "converged": conv,
+           "sum_buses": int(sum(c.n for c in scen)), "ms_per_batch": 1000 * el / steps,
+           "precision": args.precision, "setup_s": t_setup, "generate_s": t_gen,
+           "iters": {"p50": float(np.median([r.iters for r in rs])), "max": int(max(r.iters for r in rs))},
+           "oracle_err_max": max(errs), "oracle_sample": len(sample),
+           "final_mismatch_max": float(max(r.mismatch_inf for r in rs))}
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    import numpy as np
+
+    import pfgen
+    from paper_1711_10579_amd import binding as B
+
+    pool = pfgen.c4_pool(n_polar=args.pool_polar, n_feeder=args.pool_feeder)
+    ctx = B.pf_ctx_create(0)
+    reps = 2
+    cases = [[B.pf_create_from(ctx, g) for _ in range(reps)] for g in pool]
+    mixed = args.precision != "fp64"
+    opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
+    rng = random.Random(11)
+    n_req = args.requests
+    # request stream: 70 % single-phase, 30 % feeders, fresh perturbation each
+    n_pol = args.pool_polar
+    reqs = []
+    for k in range(n_req):
+        g = rng.randrange(n_pol) if rng.random() < 0.7 else n_pol + rng.randrange(args.pool_feeder)
+        reqs.append((g, 50000 + k))
+    pert = [pfgen.perturb_loads(pool[g], s) for g, s in reqs]
+
+    def prepare(h, p):
+        if hasattr(p, "bus_type"):
+            B.pf_set_injections(h, p.p_sp, p.q_sp)
+        else:
+            B.pf_set_injections(h, None, None, p.zip)
+
+    # plain serial baseline: one pf_solve at a time over the same requests
+    t0 = time.perf_counter()
+    serial_lat = []
+    for (g, _), p in zip(reqs, pert):
+        h = cases[g][0]
+        s0 = time.perf_counter()
+        prepare(h, p)
+        B.pf_solve(h, opts)
+        serial_lat.append(time.perf_counter() - s0)
+    serial_el = time.perf_counter() - t0
+    serial_rate = n_req / serial_el
+    lam = args.load_factor * serial_rate if args.rate <= 0 else args.rate
+
+    B.pf_serve_config(ctx, max_bytes=args.max_bytes, max_slots=args.slots)
+    free = {g: list(range(reps)) for g in range(len(pool))}
+    inflight = {}
+    lat, conv, done_n = [], 0, 0
+    arrivals = []
+    t = 0.0
+    for _ in range(n_req):
+        t += rng.expovariate(lam)
+        arrivals.append(t)
+    waiting = []  # arrived but no free replica yet
+    start = time.perf_counter()
+    nxt = 0
+    while done_n < n_req:
+        now = time.perf_counter() - start
+        while nxt < n_req and arrivals[nxt] <= now:
+            waiting.append(nxt)
+            nxt += 1
+        still = []
+        for k in waiting:
+            g = reqs[k][0]
+            if free[g]:
+                r_ = free[g].pop()
+                h = cases[g][r_]
+                prepare(h, pert[k])
+                inflight[B.pf_submit(ctx, h, opts)] = (k, g, r_)
+            else:
+                still.append(k)
+        waiting = still
+        for tk in list(inflight):
+            d, res = B.pf_poll(ctx, tk)
+            if d:
+                k, g, r_ = inflight.pop(tk)
+                free[g].append(r_)
+                lat.append(time.perf_counter() - start - arrivals[k])
+                conv += res.status == B.PF_CONVERGED
+                done_n += 1
+        time.sleep(0.0002)
+    el = time.perf_counter() - start
+    out = {"mode": "served", "metric": METRIC, "value": conv / el, "unit": "solves/s",
+           "requests": n_req, "converged": conv, "arrival_rate_per_s": lam,
+           "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
+           "plain_serial": {"value": serial_rate, "latency_ms": {"p50": 1000 * _pct(serial_lat, 50),
+                                                                 "p99": 1000 * _pct(serial_lat, 99)}},
+           "pool": {"single_phase": args.pool_polar, "feeders": args.pool_feeder},
+           "slots": args.slots, "precision": args.precision}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--breakdown", action="store_true",
+                    help="time every kernel class in an extra untimed pass (stderr)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="scenarios of the batched form (seeded +-20%% load perturbations)")
+    ap.add_argument("--workload", choices=["grid10k", "scenarios512", "served"], default="grid10k")
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--oracle-sample", type=int, default=8)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--pool-polar", type=int, default=32)
+    ap.add_argument("--pool-feeder", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--max-bytes", type=int, default=0)
+    ap.add_argument("--rate", type=float, default=0.0, help="arrivals/s (0: load factor x serial rate)")
+    ap.add_argument("--load-factor", type=float, default=0.8)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent power-flow instances shard across GPUs without collectives)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+    elif args.workload == "grid10k":
+        args.precision = args.precision or "fp64"
+        bench_grid10k(args)
+    elif args.workload == "scenarios512":
+        args.precision = args.precision or "mixed"
+        bench_scenarios512(args)
+    else:
+        args.precision = args.precision or "mixed"
+        bench_served(args)
 
 
 if __name__ == "__main__":

@@ -137,11 +137,13 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     emit(L_PANEL, PF_K_DENSE_PANEL, 0, k0, panel, pfl, pby);
     emit(L_GEMM, PF_K_DENSE_UPDATE, 0, k0, gemm, gfl, gby);
   }
-  // dense backward solve: flag mode while every work-group fits at once
+  // dense backward solve: flag mode while every work-group of the launch is
+  // resident at once (256 CUs x 8 work-groups of 4 waves; half of that is
+  // allowed), else one work-group per instance
   {
     int total = 0;
     for (Case* c : cs) total += c->M > 0 ? c->nblk() : 0;
-    trsv_single = total > 256 ? 1 : 0;
+    trsv_single = total > 1024 ? 1 : 0;
     std::vector<int2> tr;
     double tfl = 0, tby = 0;
     for (int s = 0; s < nslots; ++s) {
