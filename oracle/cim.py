@@ -27,7 +27,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import linalg
-from .result import OracleResult, CONVERGED, MAXITER, DIVERGED, SINGULAR
+from .result import OracleResult, CONVERGED, MAXITER, DIVERGED, SINGULAR, LINEAR_FAIL
 from .ybus import as_csr
 
 SLACK = 3
@@ -136,17 +136,26 @@ def jacobian(case, V):
     return J
 
 
-def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=None):
+def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=None, **krylov_opts):
     """The three-phase Newton-Raphson (CIM) iteration of Sec. II-B: mismatch
     by eq. 12-20, Jacobian by eq. 21-23, solve, add dV to the real and
     imaginary parts (eq. 20 order) and convert back to complex form.  Stops on
     the max-norm of the current mismatch (and at the rounding floor as in the
-    single-phase loop)."""
+    single-phase loop).  ``linear="gmres"`` solves each step inexactly as in
+    the single-phase loop (Sec. III-B)."""
     unknown, _, _, col_re, col_im, _ = unknown_layout(case)
     u = np.flatnonzero(unknown)
     V = flat_start(case) if V0 is None else np.array(V0, np.complex128)
-    history, steps = [], []
+    history, steps, lin = [], [], []
     status = MAXITER
+    if linear == "gmres":
+        from . import krylov
+
+        node_of = np.empty(2 * u.shape[0], np.int64)
+        comp_of = np.empty(2 * u.shape[0], np.int64)
+        node_of[col_re[u]], comp_of[col_re[u]] = u, 0
+        node_of[col_im[u]], comp_of[col_im[u]] = u, 1
+        graph = as_csr(case)
     for k in range(max_iter + 1):
         F = mismatch(case, V)
         nrm = float(np.max(np.abs(F))) if F.size else 0.0
@@ -166,11 +175,22 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
             status = MAXITER
             break
         J = jacobian(case, V)
-        try:
-            dx = linalg.solve(J, F, linear)
-        except linalg.SingularError:
-            status = SINGULAR
-            break
+        if linear == "gmres":
+            try:
+                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, **krylov_opts)
+            except (ArithmeticError, np.linalg.LinAlgError):
+                status = SINGULAR
+                break
+            lin.append(info["iters"])
+            if not info["met"] and not info["rel"] <= krylov_opts.get("eta_max", 0.1):
+                status = LINEAR_FAIL
+                break
+        else:
+            try:
+                dx = linalg.solve(J, F, linear)
+            except linalg.SingularError:
+                status = SINGULAR
+                break
         steps.append(float(np.max(np.abs(dx))))
         vr = V.real.copy()
         vi = V.imag.copy()
@@ -178,7 +198,7 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
         vi[u] += dx[col_im[u]]
         V = vr + 1j * vi
     return OracleResult(status=status, iters=len(steps), V=V, history=history,
-                        steps=steps, mismatch_inf=history[-1])
+                        steps=steps, mismatch_inf=history[-1], linear_iters=lin)
 
 
 def mismatch_at(case, V):

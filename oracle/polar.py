@@ -11,7 +11,7 @@ element by element below.
 import numpy as np
 
 from . import linalg
-from .result import OracleResult, CONVERGED, MAXITER, DIVERGED, SINGULAR
+from .result import OracleResult, CONVERGED, MAXITER, DIVERGED, SINGULAR, LINEAR_FAIL
 from .ybus import as_csr
 
 PQ, PV, SLACK = 1, 2, 3
@@ -102,7 +102,7 @@ def jacobian(case, vm, va):
     return sp.bmat([[J1, J2], [J3, J4]], format="csr")
 
 
-def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=None, va0=None):
+def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=None, va0=None, **krylov_opts):
     """The single-phase Newton-Raphson iteration of Sec. II-A.
 
     Each step evaluates the mismatch (eq. 8-9), stops if its max-norm is at
@@ -111,6 +111,12 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
     stops at the rounding floor: once the max-norm is at most ``floor_tol`` and
     two steps in a row bring no tenfold decrease below the best earlier norm,
     the result is reported as converged.
+
+    ``linear="gmres"`` makes it the Newton-Krylov iteration of Sec. III-B:
+    the step is solved inexactly by ``krylov.inexact_step`` (options
+    ``precond``, ``m``, ``max_restarts``, ``eta_max``); a step whose relative
+    residual misses its forcing term but is at most ``eta_max`` is taken, a
+    worse one ends the iteration with status LINEAR_FAIL.
     """
     pvpq, pq = index_sets(case)
     npv = pvpq.shape[0]
@@ -118,8 +124,14 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
     if vm0 is not None:
         vm = np.array(vm0, np.float64)
         va = np.array(va0, np.float64)
-    history, steps = [], []
+    history, steps, lin = [], [], []
     status = MAXITER
+    if linear == "gmres":
+        from . import krylov
+
+        node_of = np.concatenate([pvpq, pq])
+        comp_of = np.concatenate([np.zeros(npv, np.int64), np.ones(pq.shape[0], np.int64)])
+        graph = as_csr(case)
     for k in range(max_iter + 1):
         F = mismatch(case, vm, va)
         nrm = float(np.max(np.abs(F))) if F.size else 0.0
@@ -139,17 +151,28 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
             status = MAXITER
             break
         J = jacobian(case, vm, va)
-        try:
-            dx = linalg.solve(J, F, linear)
-        except linalg.SingularError:
-            status = SINGULAR
-            break
+        if linear == "gmres":
+            try:
+                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, **krylov_opts)
+            except (ArithmeticError, np.linalg.LinAlgError):
+                status = SINGULAR
+                break
+            lin.append(info["iters"])
+            if not info["met"] and not info["rel"] <= krylov_opts.get("eta_max", 0.1):
+                status = LINEAR_FAIL
+                break
+        else:
+            try:
+                dx = linalg.solve(J, F, linear)
+            except linalg.SingularError:
+                status = SINGULAR
+                break
         steps.append(float(np.max(np.abs(dx))))
         va[pvpq] += dx[:npv]
         vm[pq] += dx[npv:]
     V = vm * np.exp(1j * va)
     return OracleResult(status=status, iters=len(steps), V=V, history=history,
-                        steps=steps, mismatch_inf=history[-1])
+                        steps=steps, mismatch_inf=history[-1], linear_iters=lin)
 
 
 def mismatch_at(case, V):

@@ -4,7 +4,7 @@ import dataclasses
 
 import numpy as np
 
-CONVERGED, MAXITER, DIVERGED, SINGULAR = 0, 1, 2, 3
+CONVERGED, MAXITER, DIVERGED, SINGULAR, LINEAR_FAIL = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass
@@ -15,6 +15,7 @@ class OracleResult:
     history: list              # max-norm of the mismatch before each step
     steps: list                # max |dx| of each Newton step (the paper's stop test)
     mismatch_inf: float        # max-norm of the final mismatch
+    linear_iters: list = dataclasses.field(default_factory=list)  # Krylov steps per Newton step
 
     @property
     def vm(self):
