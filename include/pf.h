@@ -231,8 +231,10 @@ typedef enum {
   PF_K_SPARSE_BWD = 7,
   PF_K_DENSE_TRSV = 8,
   PF_K_UPDATE = 9,
-  PF_K_KRYLOV = 10,
-  PF_K_COUNT = 11
+  PF_K_KRYLOV = 10,        /* GMRES: begin, SpMV + dots, orthogonalisation, rotations, restarts */
+  PF_K_PRECOND_SETUP = 11, /* ILU(0) factor by levels or block-Jacobi inverses            */
+  PF_K_PRECOND_APPLY = 12, /* ILU(0) triangular solves or block-Jacobi products           */
+  PF_K_COUNT = 13
 } pf_kernel_class;
 typedef struct {
   int64_t launches;

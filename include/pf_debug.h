@@ -30,6 +30,19 @@ extern "C" {
 pf_status pf_debug_schedule_check(const pf_case_desc* desc, uint64_t seed, double* rel_residual,
                                   int64_t* checks);
 
+/* The same for the Newton-Krylov inner solve (Sec. III-B): analyse the case
+ * as pf_create does, check every index of the Krylov analysis (ordering,
+ * 2x2-block pattern, Ybus-to-block map, ILU(0) update lists, the forward and
+ * backward level schedules, block-Jacobi groups), then factor a random
+ * diagonally dominant matrix on that pattern with block ILU(0) through the
+ * update lists in level order and apply it through both schedules.
+ * *ilu_deviation receives max |(L U - A)_ij| / max |A_ij| over the pattern
+ * (ILU(0) reproduces A there), *rel_residual the relative residual of
+ * L U z = v, *checks the number of checks.  PF_E_INVALID on a failed check
+ * (reason in pf_last_error()).  Outputs are host pointers. */
+pf_status pf_debug_krylov_check(const pf_case_desc* desc, uint64_t seed, double* ilu_deviation,
+                                double* rel_residual, int64_t* checks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,10 +45,10 @@ PF_PREC_FP64, PF_PREC_MIXED = 0, 1
 PF_PRECOND_ILU0, PF_PRECOND_BJACOBI = 0, 1
 (PF_K_MISMATCH, PF_K_JFILL, PF_K_SPARSE_FACTOR, PF_K_TAIL_SCHUR, PF_K_DENSE_PANEL,
  PF_K_DENSE_UPDATE, PF_K_SPARSE_FWD, PF_K_SPARSE_BWD, PF_K_DENSE_TRSV, PF_K_UPDATE,
- PF_K_KRYLOV, PF_K_COUNT) = range(12)
+ PF_K_KRYLOV, PF_K_PRECOND_SETUP, PF_K_PRECOND_APPLY, PF_K_COUNT) = range(14)
 KERNEL_CLASS_NAMES = ["mismatch", "jfill", "sparse_factor", "tail_schur", "dense_panel",
                       "dense_update", "sparse_fwd", "sparse_bwd", "dense_trsv", "update",
-                      "krylov"]
+                      "krylov", "precond_setup", "precond_apply"]
 
 STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "diverged", 3: "singular",
                 4: "linear_fail", 5: "pending"}
@@ -121,6 +121,8 @@ _sig = {
     "pf_profile_reset": (C.c_int, [_P]),
     "pf_debug_schedule_check": (C.c_int, [C.POINTER(pf_case_desc), C.c_uint64,
                                           C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pf_debug_krylov_check": (C.c_int, [C.POINTER(pf_case_desc), C.c_uint64, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pf_last_error": (C.c_char_p, []),
     "pf_version": (C.c_char_p, []),
 }
@@ -288,6 +290,20 @@ def pf_debug_schedule_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, 
            "pf_debug_schedule_check")
     del keep
     return res.value, chk.value
+
+
+def pf_debug_krylov_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None,
+                          q_sp=None, zip=None, seed=0):
+    """Host-only check of the Krylov analysis (include/pf_debug.h).
+    Returns (ILU(0) deviation on the pattern, relative residual, checks)."""
+    d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
+    dev = C.c_double()
+    res = C.c_double()
+    chk = C.c_int64()
+    _check(_lib.pf_debug_krylov_check(C.byref(d), C.c_uint64(seed), C.byref(dev), C.byref(res),
+                                      C.byref(chk)), "pf_debug_krylov_check")
+    del keep
+    return dev.value, res.value, chk.value
 
 
 def pf_create_from(ctx, case):

@@ -25,8 +25,12 @@ SOURCES = [
     "newton.cpp",
     "serve.cpp",
     "hostcheck.cpp",
+    "krylov_analysis.cpp",
+    "nk.cpp",
+    "krylov_check.cpp",
     "kernels.hip",
     "dense.hip",
+    "krylov.hip",
 ]
 
 ARCH = "gfx950"

@@ -81,3 +81,49 @@ void build_jmap(const Analysis& an, int n, const int* row_ptr, const int* col, s
                 std::vector<int>* jmap);
 
 }  // namespace pfh
+
+namespace pfh {
+
+// Host analysis of the Newton-Krylov inner solve (Sec. III-B), once per
+// topology.  The Krylov vectors hold the two unknowns of every node with
+// unknowns, nodes in reverse Cuthill-McKee order of the node graph (row r).
+// The Jacobian is kept as 2x2 blocks on that graph's pattern (block CSR,
+// sorted columns); ILU(0) works on the same pattern.
+struct KAnalysis {
+  int nu = 0;
+  std::vector<int> p_of_r, r_of_p;       // Krylov row <-> factor position of the node
+  std::vector<int> row_ptr, col, diag;   // block CSR pattern in Krylov order
+  // ILU(0) in its IKJ form: lower entry q of row r (column k < r) is
+  // followed by the updates A(r, j) -= L(r, k) U(k, j) for the listed pairs
+  // (t = position of (r, j), s = position of (k, j)), j > k
+  std::vector<int> up_ptr;               // [nnz+1], non-empty only for lower entries
+  std::vector<int> up_t, up_s;
+  // rows by level: a row's lower neighbours are in earlier levels (factor
+  // and forward solve); its upper neighbours are in earlier levels of the
+  // backward order
+  std::vector<int> lev_ptr, lev_rows, ulev_ptr, ulev_rows;
+  // block-Jacobi blocks: connected groups of at most bj_cap nodes grown
+  // breadth-first from seeds in Krylov order; rows of each block in that
+  // growth order, dense (2s)x(2s) inverse at bj_off[b]
+  std::vector<int> bj_ptr, bj_rows, bj_loc;
+  std::vector<int64_t> bj_off;
+  int bj_max = 0;
+  int64_t nnz() const { return (int64_t)col.size(); }
+  int64_t nup() const { return (int64_t)up_t.size(); }
+  int nblocks() const { return (int)bj_ptr.size() - 1; }
+};
+
+// The reverse Cuthill-McKee order of an undirected graph (adjacency lists,
+// no self loops): breadth-first from a pseudo-peripheral start in every
+// connected component, neighbours taken by increasing degree, the whole
+// sequence reversed.  Returns order[r] = vertex.
+std::vector<int> rcm_order(const std::vector<std::vector<int>>& adj);
+
+KAnalysis analyze_krylov(const Analysis& an, int n, const int* row_ptr, const int* col, int bj_cap);
+
+// Ybus entry -> block position in the Krylov pattern, -1 when the row or the
+// column node has no unknowns.
+void build_kmap(const Analysis& an, const KAnalysis& ka, int n, const int* row_ptr, const int* col,
+                std::vector<int>* kmap);
+
+}  // namespace pfh

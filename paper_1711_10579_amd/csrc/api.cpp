@@ -373,6 +373,14 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
     set_error(std::string("pf_create: ") + ex.what());
     return PF_E_INVALID;
   }
+  try {
+    c->ka.reset(new pfh::KAnalysis(pfh::analyze_krylov(an, n, d->row_ptr, d->col_idx, 32)));
+    pfh::build_kmap(an, *c->ka, n, d->row_ptr, d->col_idx, &c->kmap_host);
+  } catch (const std::exception& ex) {
+    delete c;
+    set_error(std::string("pf_create: Krylov analysis failed: ") + ex.what());
+    return PF_E_INVALID;
+  }
   const int ns = an.ns;
   // device layout
   const int nu = an.nu;
@@ -535,6 +543,7 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
     hi.lrow_blk = c->lrow_blk;
     hi.lrow_col = c->lrow_col;
     hi.red = c->red;
+    c->hinst = hi;
     ok &= up(c->d_inst, &hi, sizeof hi);
     // flat-start voltages so that pf_get_voltage is defined before a solve
     std::vector<double> v0(2 * (size_t)n), vm0(n), va0(n);
@@ -588,6 +597,7 @@ pf_status pf_destroy(pf_case* c) {
   (void)hipStreamSynchronize(c->ctx->stream);
   delete c->single;
   c->single = nullptr;
+  free_krylov(c);
   c->ctx->dfree(c->base);
   c->ctx->ncases--;
   delete c;

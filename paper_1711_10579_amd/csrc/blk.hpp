@@ -1,0 +1,68 @@
+// 2x2 blocks of the Jacobian (row-major [a b; c d]) and their arithmetic,
+// shared by the factor and Krylov kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pfd {
+
+template <typename T>
+struct Blk {
+  T a, b, c, d;  // [[a b] [c d]]
+};
+
+template <typename T>
+__device__ inline Blk<T> ld_blk(const T* p, int64_t id) {
+  const T* q = p + 4 * id;
+  Blk<T> r;
+  r.a = q[0];
+  r.b = q[1];
+  r.c = q[2];
+  r.d = q[3];
+  return r;
+}
+
+template <typename T>
+__device__ inline void st_blk(T* p, int64_t id, const Blk<T>& v) {
+  T* q = p + 4 * id;
+  q[0] = v.a;
+  q[1] = v.b;
+  q[2] = v.c;
+  q[3] = v.d;
+}
+
+// acc -= X * Y
+template <typename T>
+__device__ inline void blk_msub(Blk<T>& acc, const Blk<T>& X, const Blk<T>& Y) {
+  acc.a -= X.a * Y.a + X.b * Y.c;
+  acc.b -= X.a * Y.b + X.b * Y.d;
+  acc.c -= X.c * Y.a + X.d * Y.c;
+  acc.d -= X.c * Y.b + X.d * Y.d;
+}
+
+template <typename T>
+__device__ inline Blk<T> blk_mul(const Blk<T>& X, const Blk<T>& Y) {
+  Blk<T> r;
+  r.a = X.a * Y.a + X.b * Y.c;
+  r.b = X.a * Y.b + X.b * Y.d;
+  r.c = X.c * Y.a + X.d * Y.c;
+  r.d = X.c * Y.b + X.d * Y.d;
+  return r;
+}
+
+// inverse of a 2x2 block (determinant in FP64); false when it is zero or
+// not finite
+template <typename T>
+__device__ inline bool blk_inv(const Blk<T>& m, Blk<T>* out) {
+  const double det = (double)m.a * (double)m.d - (double)m.b * (double)m.c;
+  if (!(det != 0.0) || !isfinite(det)) return false;
+  const double id = 1.0 / det;
+  out->a = (T)((double)m.d * id);
+  out->b = (T)(-(double)m.b * id);
+  out->c = (T)(-(double)m.c * id);
+  out->d = (T)((double)m.a * id);
+  return true;
+}
+
+}  // namespace pfd

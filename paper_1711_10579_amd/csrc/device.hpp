@@ -40,6 +40,8 @@ struct Red {
 // len + p; updates of target t: [uptr[t], uptr[t+1]).  The dense trailing
 // block (positions ns..nu-1) is a column-major scalar matrix of order M = 2 nt
 // with leading dimension ldt and the right-hand side in column M.
+struct KState;
+
 struct Inst {
   int model, n, nnz, nu, ns, nt, ldt, M, ntt, nblk;
   int64_t nnzl;
@@ -57,12 +59,51 @@ struct Inst {
   const int *tail_tgt, *tail_l, *tail_u;
   const int64_t* tail_uptr;
   const int *lrow_ptr, *lrow_blk, *lrow_col;
-  // Krylov (NK) storage: J in CSR over block rows (same pattern as Ybus on
-  // the unknowns), its ILU(0) / block-Jacobi factor and the GMRES basis
-  const int *jrow_ptr, *jcol, *jdiag, *jmap_k;
-  void *jval, *pval, *kry, *kh;
+  // Newton-Krylov storage (allocated on the first Krylov solve of the case;
+  // null before).  Krylov vectors: 2 values per node with unknowns, nodes in
+  // Krylov order r (kp_of_r[r] = factor position); the Jacobian as 2x2
+  // blocks on the block CSR pattern krow_ptr/kcol (diagonal at kdiag), its
+  // ILU(0) factor on the same pattern (pval) with the inverted diagonal
+  // blocks (pdinv), or the block-Jacobi inverses (bjinv, bj_off).
+  int km;        // restart length the basis storage holds
+  int kchunks;   // vector chunks of KCH rows
+  int knb;       // block-Jacobi blocks
+  int pad2;
+  const int *kp_of_r, *krow_ptr, *kcol, *kdiag, *kmap, *kup_ptr, *kup_t, *kup_s;
+  const int *bj_ptr, *bj_rows, *bj_loc;
+  const int64_t* bj_off;
+  void *jval, *pval, *pdinv, *bjinv;
+  void *kv;      // basis [(km+1) x 2 nu]
+  void *kw, *kz, *kx;  // work vectors [2 nu]
+  double* kh;    // H [(km+1) x km] row-major, cs [km], sn [km], g [km+1], y [km]
+  double* kpart; // partial sums [3][kchunks][km+1]
+  KState* ks;
   Red* red;
 };
+
+// Per-instance state of the Krylov inner solve of the current Newton step.
+struct KState {
+  double bnorm;  // ||F||_2
+  double eta;    // forcing term (relative residual target)
+  double scale;  // factor that normalises the next basis vector
+  double rel;    // residual estimate relative to bnorm
+  int j;         // Arnoldi steps of the current cycle
+  int cycle;     // restarts done
+  int state;     // KS_* below
+  int met;       // forcing term met
+  int total;     // Arnoldi steps of this Newton step
+  int pad;
+};
+enum { KS_DONE = 0, KS_ITER = 1, KS_CYCLE = 2, KS_RESTART = 3, KS_FINISH = 4 };
+
+// Options of the Krylov inner solve.
+struct KOpts {
+  double eta_max, eta_floor;
+  int m, max_restarts;
+};
+
+// rows of a Krylov vector chunk (one work-group of KCH threads)
+constexpr int KCH = 256;
 
 // Options the device-side convergence test needs.
 struct DevOpts {

@@ -93,7 +93,15 @@ struct Case {
   int *lrow_ptr = nullptr, *lrow_blk = nullptr, *lrow_col = nullptr, *bwd_rows = nullptr;
   pfd::Red* red = nullptr;
   pfd::Inst* d_inst = nullptr;  // device descriptor
+  pfd::Inst hinst;              // host copy of the descriptor
   Batch* single = nullptr;      // cached batch of this case alone
+
+  // Newton-Krylov storage, created by the first Krylov solve of the case
+  std::unique_ptr<pfh::KAnalysis> ka;
+  std::vector<int> kmap_host;  // Ybus entry -> Krylov block position
+  char* kbase = nullptr;
+  size_t kbytes = 0;
+  int km = 0;  // restart length the storage holds
 
   int64_t lu_count() const { return 4LL * (an.ns + 2 * an.nnzl); }
   int64_t tail_count() const { return (int64_t)an.ldt * (M + 1); }
@@ -129,9 +137,42 @@ struct Batch {
   int64_t max_lu = 0, max_tail = 0;
   int trsv_single = 0;
 
+  // Krylov launch lists (built on the first Krylov step of the batch): rows
+  // by ILU level (factor and forward solve), by backward level, and the
+  // block-Jacobi blocks, as (offset, count) ranges of d_kwork
+  bool kbuilt = false;
+  char* kmem = nullptr;
+  int2* d_kwork = nullptr;
+  int* d_kstate = nullptr;
+  std::vector<std::pair<int64_t, int>> k_lev, k_ulev;
+  std::pair<int64_t, int> k_blocks{0, 0};
+  int max_kchunks = 0;
+
   ~Batch();
   bool build(Ctx* ctx, const std::vector<Case*>& cs);
+  bool build_krylov();
 };
+
+// Kernel-class timing of the launches issued while it lives.
+struct Prof {
+  Ctx* ctx;
+  int cls;
+  hipEvent_t a;
+  double flops, bytes;
+  Prof(Ctx* c, int k, double f, double b) : ctx(c), cls(k), a(nullptr), flops(f), bytes(b) {
+    ctx->prof_begin(cls, &a);
+  }
+  ~Prof() { ctx->prof_end(cls, a, flops, bytes); }
+};
+
+// Krylov storage of a case for restart length m (allocates on first use or
+// when m grows); false on failure with the error set.
+bool ensure_krylov(Case* c, int m);
+void free_krylov(Case* c);
+// Validation of solve options (PF_E_INVALID with the error set).
+pf_status check_opts(const pf_options* opt);
+// The Newton step's linear solve by GMRES and the voltage update.
+pf_status nk_step(Batch* b, const pf_options* opt);
 
 // Run the Newton iteration of every case of a built batch to completion.
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "blk.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -35,50 +36,6 @@ __device__ inline double wave_max(double local) {
     local = (o > local || o != o) ? o : local;
   }
   return local;
-}
-
-template <typename T>
-struct Blk {
-  T a, b, c, d;  // [[a b] [c d]]
-};
-
-template <typename T>
-__device__ inline Blk<T> ld_blk(const T* p, int64_t id) {
-  const T* q = p + 4 * id;
-  Blk<T> r;
-  r.a = q[0];
-  r.b = q[1];
-  r.c = q[2];
-  r.d = q[3];
-  return r;
-}
-
-template <typename T>
-__device__ inline void st_blk(T* p, int64_t id, const Blk<T>& v) {
-  T* q = p + 4 * id;
-  q[0] = v.a;
-  q[1] = v.b;
-  q[2] = v.c;
-  q[3] = v.d;
-}
-
-// acc -= X * Y
-template <typename T>
-__device__ inline void blk_msub(Blk<T>& acc, const Blk<T>& X, const Blk<T>& Y) {
-  acc.a -= X.a * Y.a + X.b * Y.c;
-  acc.b -= X.a * Y.b + X.b * Y.d;
-  acc.c -= X.c * Y.a + X.d * Y.c;
-  acc.d -= X.c * Y.b + X.d * Y.d;
-}
-
-template <typename T>
-__device__ inline Blk<T> blk_mul(const Blk<T>& X, const Blk<T>& Y) {
-  Blk<T> r;
-  r.a = X.a * Y.a + X.b * Y.c;
-  r.b = X.a * Y.b + X.b * Y.d;
-  r.c = X.c * Y.a + X.d * Y.c;
-  r.d = X.c * Y.b + X.d * Y.d;
-  return r;
 }
 
 template <typename T, int G>
@@ -407,6 +364,33 @@ __global__ void k_jfill(const Inst* const* insts) {
   jstore<T>(I, code, blk[0], blk[1], blk[2], blk[3]);
 }
 
+// Jacobian fill for the Krylov inner solve: every Ybus entry between nodes
+// with unknowns gives one 2x2 block of the block CSR Jacobian; with ILU(0)
+// the block is also the starting value of the factor.
+template <typename T>
+__global__ void k_kfill(const Inst* const* insts, int ilu) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= I.nnz) return;
+  const int q = I.kmap[e];
+  if (q < 0) return;
+  double b[4];
+  jblock(I, e, b);
+  T* jv = (T*)I.jval + 4 * (int64_t)q;
+  jv[0] = (T)b[0];
+  jv[1] = (T)b[1];
+  jv[2] = (T)b[2];
+  jv[3] = (T)b[3];
+  if (ilu) {
+    T* pv = (T*)I.pval + 4 * (int64_t)q;
+    pv[0] = (T)b[0];
+    pv[1] = (T)b[1];
+    pv[2] = (T)b[2];
+    pv[3] = (T)b[3];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // sparse block refactorisation: one work-group per (instance, column) of a
 // level; each target block (D_j, U(j, .), L(., j)) is reduced by a group of G
@@ -636,6 +620,11 @@ void launch_fill(hipStream_t st, const Inst* const* insts, int nslots, int max_n
   k_jfill<T><<<grid2(max_nnz, nslots), 256, 0, st>>>(insts);
 }
 
+template <typename T>
+void launch_kfill(hipStream_t st, const Inst* const* insts, int nslots, int max_nnz, int ilu) {
+  k_kfill<T><<<grid2(max_nnz, nslots), 256, 0, st>>>(insts, ilu);
+}
+
 #define PF_GSWITCH(G, CALL)                         \
   switch (G) {                                      \
     case 1: { constexpr int GG = 1; CALL; } break;   \
@@ -684,7 +673,8 @@ void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max
   template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int);                   \
   template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
   template void launch_bwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
-  template void launch_update<T>(hipStream_t, const Inst* const*, int, int);
+  template void launch_update<T>(hipStream_t, const Inst* const*, int, int);                                \
+  template void launch_kfill<T>(hipStream_t, const Inst* const*, int, int, int);
 
 PF_INST(double)
 PF_INST(float)

@@ -41,4 +41,31 @@ void launch_dense_gemm(hipStream_t, const Inst* const* insts, const int2* work, 
 template <typename T>
 void launch_dense_trsv(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int single);
 
+// Newton-Krylov inner solve (krylov.hip); mode 0 = Arnoldi step, 1 = end of
+// cycle
+template <typename T>
+void launch_kfill(hipStream_t, const Inst* const* insts, int nslots, int max_nnz, int ilu);
+template <typename T>
+void launch_ilu_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork);
+template <typename T>
+void launch_bj_inv(hipStream_t, const Inst* const* insts, const int2* work, int nwork);
+template <typename T>
+void launch_ilu_fwd(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int mode);
+template <typename T>
+void launch_ilu_bwd(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int mode);
+template <typename T>
+void launch_bj_apply(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int mode);
+template <typename T>
+void launch_karnoldi(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+template <typename T>
+void launch_kbegin(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+template <typename T>
+void launch_kycomb(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
+template <typename T>
+void launch_kcycle_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+template <typename T>
+void launch_kfinish(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
+void launch_kgather(hipStream_t, const Inst* const* insts, int nslots, int* out);
+int krylov_max_restart();
+
 }  // namespace pfd

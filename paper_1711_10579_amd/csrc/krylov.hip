@@ -1,0 +1,740 @@
+// HIP kernels of the Newton-Krylov inner solve (Sec. III-B) for gfx950.
+//
+// Right-preconditioned restarted GMRES(m) on the 2x2-block Jacobian, batched
+// over instances: every kernel takes the instance table and skips instances
+// whose Krylov state is not the one the kernel serves, so one launch
+// sequence drives instances that need different numbers of steps.
+//
+// One Arnoldi step (state KS_ITER):
+//   z = M^{-1} (scale * w), writing the normalised basis vector v_j on the
+//   way (ILU(0) forward/backward rows by level, or block-Jacobi) ->
+//   w = J z with the partial dots <w, v_i> (k_kspmv_dot) -> two classical
+//   Gram-Schmidt passes (k_korth; the second re-orthogonalises and yields
+//   ||w||) -> Givens rotation and residual estimate (k_karnoldi_end).
+// End of a cycle (KS_CYCLE): u = V y, z = M^{-1} u, x += z; then either the
+// result is final (KS_FINISH) or the true residual F - J x starts the next
+// cycle (KS_RESTART).
+//
+// Value type T of the Jacobian, the preconditioner and the basis is double
+// (plain) or float (mixed precision); dot products, norms, the Hessenberg
+// matrix and the rotations are double.  Partial sums are reduced in a fixed
+// order, so an instance's arithmetic does not depend on the batch.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "blk.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace pfd {
+
+namespace {
+
+constexpr int KMAX = 128;  // largest restart length the kernels accept
+
+__device__ inline bool kstate_is(const Inst& I, int want) { return I.red->active && I.ks->state == want; }
+
+__device__ inline double* kh_H(const Inst& I) { return I.kh; }
+__device__ inline double* kh_cs(const Inst& I) { return I.kh + (int64_t)(I.km + 1) * I.km; }
+__device__ inline double* kh_sn(const Inst& I) { return kh_cs(I) + I.km; }
+__device__ inline double* kh_g(const Inst& I) { return kh_sn(I) + I.km; }
+__device__ inline double* kh_y(const Inst& I) { return kh_g(I) + I.km + 1; }
+__device__ inline double* kpart(const Inst& I, int pass, int chunk) {
+  return I.kpart + ((int64_t)pass * I.kchunks + chunk) * (I.km + 1);
+}
+
+// The inner solve failed: the Newton iteration of the instance ends with
+// status linear failure and the step is not taken (not counted).
+__device__ inline void linear_failure(const Inst& I) {
+  I.red->status = 4;
+  I.red->active = 0;
+  I.red->it -= 1;
+  I.ks->state = KS_DONE;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums over the KCH threads of a work-group of the values f(i) for i <
+// count, written to out[i] (thread-uniform count).  Fixed reduction order.
+template <typename F>
+__device__ inline void block_sums(int count, F f, double (*red)[KCH / 64], double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = 0; i < count; ++i) {
+    double s = wave_sum(f(i));
+    if (lane == 0) red[i][wave] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += KCH) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < KCH / 64; ++w) s += red[i][w];
+    out[i] = s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// preconditioner set-up
+
+// ILU(0) rows of one level (IKJ form): each lower block of row r becomes
+// L(r,k) = A(r,k) U(k,k)^{-1}, followed by its listed updates
+// A(r,j) -= L(r,k) U(k,j); then the row's diagonal block is inverted.  One
+// thread per row; rows of earlier levels are final.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, const int2* __restrict__ work, int nwork) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nwork) return;
+  const int2 wk = work[idx];
+  const Inst& I = *insts[wk.x];
+  if (!I.red->active) return;
+  const int r = wk.y;
+  T* P = (T*)I.pval;
+  T* D = (T*)I.pdinv;
+  const int qd = I.kdiag[r];
+  for (int q = I.krow_ptr[r]; q < qd; ++q) {
+    const Blk<T> L = blk_mul(ld_blk(P, q), ld_blk((const T*)D, I.kcol[q]));
+    st_blk(P, q, L);
+    for (int u = I.kup_ptr[q]; u < I.kup_ptr[q + 1]; ++u) {
+      const int t = I.kup_t[u];
+      Blk<T> a = ld_blk(P, t);
+      blk_msub(a, L, ld_blk(P, I.kup_s[u]));
+      st_blk(P, t, a);
+    }
+  }
+  Blk<T> inv;
+  if (!blk_inv(ld_blk(P, qd), &inv)) {
+    I.red->singular = 1;
+    inv.a = inv.b = inv.c = inv.d = T(0);
+  }
+  st_blk(D, r, inv);
+}
+
+// Block-Jacobi: inverse of the diagonal block of one node group (order N =
+// 2 x nodes <= 64) by Gauss-Jordan elimination with partial pivoting on
+// [A | I] in LDS (FP64), stored row-major at bj_off[b].
+template <typename T>
+__global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
+  __shared__ double A[64][129];
+  __shared__ int piv;
+  __shared__ int bad;
+  const int2 wk = work[blockIdx.x];
+  const Inst& I = *insts[wk.x];
+  if (!I.red->active) return;
+  const int b = wk.y;
+  const int r0 = I.bj_ptr[b];
+  const int s = I.bj_ptr[b + 1] - r0;
+  const int N = 2 * s;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 128; e += 256) {
+    const int i = e >> 7, c = e & 127;
+    A[i][c] = (c >= 64 && c - 64 == i) ? 1.0 : 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // gather the block: member a (local), its row's entries in the same group
+  for (int a = tid; a < s; a += 256) {
+    const int r = I.bj_rows[r0 + a];
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const int c = I.kcol[q];
+      const int l = I.bj_loc[c];
+      if (l < s && I.bj_rows[r0 + l] == c) {
+        const T* v = (const T*)I.jval + 4 * (int64_t)q;
+        A[2 * a][2 * l] = (double)v[0];
+        A[2 * a][2 * l + 1] = (double)v[1];
+        A[2 * a + 1][2 * l] = (double)v[2];
+        A[2 * a + 1][2 * l + 1] = (double)v[3];
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    if (tid < 64) {  // pivot search by the first wave
+      double best = (tid >= k && tid < N) ? fabs(A[tid][k]) : -1.0;
+      int who = tid;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int ow = __shfl_xor(who, off, 64);
+        if (ob > best || (ob == best && ow < who)) {
+          best = ob;
+          who = ow;
+        }
+      }
+      if (tid == 0) {
+        piv = who;
+        if (!(best > 0.0) || !isfinite(best)) bad = 1;
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const int p = piv;
+    if (p != k)
+      for (int c = tid; c < 128; c += 256) {
+        double t = A[k][c];
+        A[k][c] = A[p][c];
+        A[p][c] = t;
+      }
+    __syncthreads();
+    const double ip = 1.0 / A[k][k];
+    __syncthreads();
+    for (int c = tid; c < 128; c += 256) A[k][c] *= ip;
+    __syncthreads();
+    // eliminate column k from every other row
+    for (int e = tid; e < 64 * 128; e += 256) {
+      const int i = e >> 7, c = e & 127;
+      if (i != k && i < N && c != k) A[i][c] -= A[i][k] * A[k][c];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += 256)
+      if (i != k) A[i][k] = 0.0;
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) I.red->singular = 1;
+    return;
+  }
+  T* out = (T*)I.bjinv + I.bj_off[b];
+  for (int e = tid; e < N * N; e += 256) {
+    const int i = e / N, c = e - i * N;
+    out[e] = (T)A[i][64 + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner application
+
+// ILU(0) forward rows of one level: y_r = s w_r - sum_{k<r} L(r,k) y_k.  In
+// an Arnoldi step (mode 0) the scaled input is also stored as basis vector
+// v_j.  In the end-of-cycle solve (mode 1) the input is u and s = 1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_fwd(const Inst* const* insts, const int2* __restrict__ work, int nwork,
+                                                 int mode) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nwork) return;
+  const int2 wk = work[idx];
+  const Inst& I = *insts[wk.x];
+  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  const int r = wk.y;
+  const T* w = (const T*)I.kw;
+  T* z = (T*)I.kz;
+  const T* P = (const T*)I.pval;
+  T v0 = w[2 * r], v1 = w[2 * r + 1];
+  if (mode == 0) {
+    const double sc = I.ks->scale;
+    v0 = (T)((double)v0 * sc);
+    v1 = (T)((double)v1 * sc);
+    T* vj = (T*)I.kv + (int64_t)I.ks->j * 2 * I.nu;
+    vj[2 * r] = v0;
+    vj[2 * r + 1] = v1;
+  }
+  double y0 = (double)v0, y1 = (double)v1;
+  for (int q = I.krow_ptr[r]; q < I.kdiag[r]; ++q) {
+    const Blk<T> L = ld_blk(P, q);
+    const int k = I.kcol[q];
+    const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
+    y0 -= (double)L.a * a + (double)L.b * b;
+    y1 -= (double)L.c * a + (double)L.d * b;
+  }
+  z[2 * r] = (T)y0;
+  z[2 * r + 1] = (T)y1;
+}
+
+// ILU(0) backward rows of one level: z_r = U(r,r)^{-1} (y_r - sum_{j>r}
+// U(r,j) z_j), in place over y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const int2* __restrict__ work, int nwork,
+                                                 int mode) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nwork) return;
+  const int2 wk = work[idx];
+  const Inst& I = *insts[wk.x];
+  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  const int r = wk.y;
+  T* z = (T*)I.kz;
+  const T* P = (const T*)I.pval;
+  double s0 = (double)z[2 * r], s1 = (double)z[2 * r + 1];
+  for (int q = I.kdiag[r] + 1; q < I.krow_ptr[r + 1]; ++q) {
+    const Blk<T> U = ld_blk(P, q);
+    const int k = I.kcol[q];
+    const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
+    s0 -= (double)U.a * a + (double)U.b * b;
+    s1 -= (double)U.c * a + (double)U.d * b;
+  }
+  const Blk<T> D = ld_blk((const T*)I.pdinv, r);
+  z[2 * r] = (T)((double)D.a * s0 + (double)D.b * s1);
+  z[2 * r + 1] = (T)((double)D.c * s0 + (double)D.d * s1);
+}
+
+// Block-Jacobi application: one wave per node group, z_b = A_bb^{-1} (s w_b)
+// (mode 0 also stores s w_b as basis vector v_j).
+template <typename T>
+__global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const int2* __restrict__ work, int mode) {
+  __shared__ double v[64];
+  const int2 wk = work[blockIdx.x];
+  const Inst& I = *insts[wk.x];
+  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  const int b = wk.y;
+  const int r0 = I.bj_ptr[b];
+  const int N = 2 * (I.bj_ptr[b + 1] - r0);
+  const int t = threadIdx.x;
+  const T* w = (const T*)I.kw;
+  if (t < N) {
+    const int r = I.bj_rows[r0 + (t >> 1)];
+    T x = w[2 * r + (t & 1)];
+    if (mode == 0) {
+      x = (T)((double)x * I.ks->scale);
+      ((T*)I.kv)[(int64_t)I.ks->j * 2 * I.nu + 2 * r + (t & 1)] = x;
+    }
+    v[t] = (double)x;
+  }
+  __syncthreads();
+  if (t < N) {
+    const T* inv = (const T*)I.bjinv + I.bj_off[b] + (int64_t)t * N;
+    double s = 0.0;
+    for (int c = 0; c < N; ++c) s += (double)inv[c] * v[c];
+    const int r = I.bj_rows[r0 + (t >> 1)];
+    ((T*)I.kz)[2 * r + (t & 1)] = (T)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi step
+
+// w = J z for the rows of one chunk, then the partial dots <w, v_i>, i <= j.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kspmv_dot(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
+  const int j = I.ks->j;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  const int64_t n2 = 2 * (int64_t)I.nu;
+  double w0 = 0.0, w1 = 0.0;
+  if (r < I.nu) {
+    const T* J = (const T*)I.jval;
+    const T* z = (const T*)I.kz;
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const Blk<T> B = ld_blk(J, q);
+      const int c = I.kcol[q];
+      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
+      w0 += (double)B.a * a + (double)B.b * b;
+      w1 += (double)B.c * a + (double)B.d * b;
+    }
+    T* w = (T*)I.kw;
+    w[2 * r] = (T)w0;
+    w[2 * r + 1] = (T)w1;
+    w0 = (double)(T)w0;
+    w1 = (double)(T)w1;
+  }
+  const T* V = (const T*)I.kv;
+  block_sums(
+      j + 1,
+      [&](int i) {
+        if (r >= I.nu) return 0.0;
+        const T* vi = V + i * n2;
+        return w0 * (double)vi[2 * r] + w1 * (double)vi[2 * r + 1];
+      },
+      red, kpart(I, 0, blockIdx.x));
+}
+
+// One classical Gram-Schmidt pass: h = sum over chunks of the partial dots
+// of pass p; w -= V h; column j of H gets h (p = 0) or h added (p = 1).
+// Pass 0 leaves the partial dots of the re-orthogonalisation, pass 1 the
+// partial squared norm of w.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pass) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  __shared__ double h[KMAX + 1];
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
+  const int j = I.ks->j;
+  for (int i = threadIdx.x; i <= j; i += KCH) {
+    double s = 0.0;
+    for (int c = 0; c < I.kchunks; ++c) s += kpart(I, pass, c)[i];
+    h[i] = s;
+    if (blockIdx.x == 0) {
+      double* H = kh_H(I) + (int64_t)i * I.km + j;
+      *H = pass == 0 ? s : *H + s;
+    }
+  }
+  __syncthreads();
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  const int64_t n2 = 2 * (int64_t)I.nu;
+  const T* V = (const T*)I.kv;
+  double w0 = 0.0, w1 = 0.0;
+  if (r < I.nu) {
+    T* w = (T*)I.kw;
+    w0 = (double)w[2 * r];
+    w1 = (double)w[2 * r + 1];
+    for (int i = 0; i <= j; ++i) {
+      const T* vi = V + i * n2;
+      w0 -= h[i] * (double)vi[2 * r];
+      w1 -= h[i] * (double)vi[2 * r + 1];
+    }
+    w[2 * r] = (T)w0;
+    w[2 * r + 1] = (T)w1;
+    w0 = (double)(T)w0;
+    w1 = (double)(T)w1;
+  }
+  if (pass == 0) {
+    block_sums(
+        j + 1,
+        [&](int i) {
+          if (r >= I.nu) return 0.0;
+          const T* vi = V + i * n2;
+          return w0 * (double)vi[2 * r] + w1 * (double)vi[2 * r + 1];
+        },
+        red, kpart(I, 1, blockIdx.x));
+  } else {
+    block_sums(
+        1, [&](int) { return w0 * w0 + w1 * w1; }, red, kpart(I, 2, blockIdx.x));
+  }
+}
+
+// Per instance: h_{j+1,j} = ||w||, the earlier rotations and a new one on
+// column j of H, the residual estimate |g_{j+1}| / ||F||.  The cycle ends
+// when the forcing term is met, the basis is full or w vanished; then
+// y = H^{-1} g by back substitution.
+__global__ void k_karnoldi_end(const Inst* const* insts, int nslots, KOpts o) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  if (!kstate_is(I, KS_ITER)) return;
+  KState& ks = *I.ks;
+  const int j = ks.j, m = I.km;
+  double hn2 = 0.0;
+  for (int c = 0; c < I.kchunks; ++c) hn2 += kpart(I, 2, c)[0];
+  const double h = sqrt(hn2);
+  double* H = kh_H(I);
+  double* cs = kh_cs(I);
+  double* sn = kh_sn(I);
+  double* g = kh_g(I);
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
+    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double hjj = H[(int64_t)j * m + j];
+  const double d = hypot(hjj, h);
+  if (!isfinite(d) || !(d > 0.0)) {
+    linear_failure(I);
+    return;
+  }
+  cs[j] = hjj / d;
+  sn[j] = h / d;
+  H[(int64_t)j * m + j] = d;
+  H[(int64_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  const double rel = fabs(g[j + 1]) / ks.bnorm;
+  ks.rel = rel;
+  ks.j = j + 1;
+  ks.total += 1;
+  I.red->linear_iters += 1;
+  if (rel <= ks.eta || j + 1 >= o.m || !(h > 0.0)) {
+    double* y = kh_y(I);
+    const int k = j + 1;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < k; ++c) s -= H[(int64_t)i * m + c] * y[c];
+      y[i] = s / H[(int64_t)i * m + i];
+    }
+    ks.met = rel <= ks.eta;
+    ks.state = KS_CYCLE;
+  } else {
+    ks.scale = 1.0 / h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// start, end of cycle, restart, result
+
+// Start of the inner solve: w = F in Krylov order, x = 0, partial ||F||^2.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kbegin(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  const Inst& I = *insts[blockIdx.y];
+  if (!I.red->active || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  double f0 = 0.0, f1 = 0.0;
+  if (r < I.nu) {
+    const int p = I.kp_of_r[r];
+    f0 = I.F[2 * p];
+    f1 = I.F[2 * p + 1];
+    T* w = (T*)I.kw;
+    T* x = (T*)I.kx;
+    w[2 * r] = (T)f0;
+    w[2 * r + 1] = (T)f1;
+    x[2 * r] = T(0);
+    x[2 * r + 1] = T(0);
+  }
+  block_sums(
+      1, [&](int) { return f0 * f0 + f1 * f1; }, red, kpart(I, 2, blockIdx.x));
+}
+
+// Per instance: ||F||_2, the forcing term eta = max(min(eta_max,
+// ||F||_inf), eta_floor) and the first cycle.  A singular preconditioner
+// ends the instance's Newton iteration with status singular.
+__global__ void k_kbegin_fin(const Inst* const* insts, int nslots, KOpts o) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  if (!I.red->active) return;
+  KState& ks = *I.ks;
+  if (I.red->singular) {
+    I.red->status = 3;
+    I.red->active = 0;
+    ks.state = KS_DONE;
+    return;
+  }
+  double s = 0.0;
+  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, 2, c)[0];
+  const double bn = sqrt(s);
+  ks.bnorm = bn;
+  ks.eta = fmax(fmin(o.eta_max, I.red->last_norm), o.eta_floor);
+  ks.j = 0;
+  ks.cycle = 0;
+  ks.met = 0;
+  ks.total = 0;
+  ks.rel = 1.0;
+  kh_g(I)[0] = bn;
+  if (bn > 0.0) {
+    ks.scale = 1.0 / bn;
+    ks.state = KS_ITER;
+  } else {
+    ks.rel = 0.0;
+    ks.met = 1;
+    ks.state = KS_FINISH;
+  }
+}
+
+// u = V y over the basis of the finished cycle (into w).
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kycomb(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_CYCLE) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  if (r >= I.nu) return;
+  const int k = I.ks->j;
+  const double* y = kh_y(I);
+  const int64_t n2 = 2 * (int64_t)I.nu;
+  const T* V = (const T*)I.kv;
+  double u0 = 0.0, u1 = 0.0;
+  for (int i = 0; i < k; ++i) {
+    u0 += y[i] * (double)V[i * n2 + 2 * r];
+    u1 += y[i] * (double)V[i * n2 + 2 * r + 1];
+  }
+  T* w = (T*)I.kw;
+  w[2 * r] = (T)u0;
+  w[2 * r + 1] = (T)u1;
+}
+
+// x += z (the preconditioned correction of the cycle).
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kxadd(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_CYCLE) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  if (r >= I.nu) return;
+  T* x = (T*)I.kx;
+  const T* z = (const T*)I.kz;
+  x[2 * r] = (T)((double)x[2 * r] + (double)z[2 * r]);
+  x[2 * r + 1] = (T)((double)x[2 * r + 1] + (double)z[2 * r + 1]);
+}
+
+// Per instance, after a cycle: done when the forcing term is met; after the
+// last allowed cycle the step is still taken when its relative residual is
+// at most eta_max, else the Newton iteration ends with a linear failure;
+// otherwise restart.
+__global__ void k_kcycle_fin(const Inst* const* insts, int nslots, KOpts o) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  if (!kstate_is(I, KS_CYCLE)) return;
+  KState& ks = *I.ks;
+  if (ks.met) {
+    ks.state = KS_FINISH;
+  } else if (ks.cycle >= o.max_restarts) {
+    if (ks.rel <= o.eta_max)
+      ks.state = KS_FINISH;
+    else
+      linear_failure(I);
+  } else {
+    ks.cycle += 1;
+    ks.state = KS_RESTART;
+  }
+}
+
+// Restart: w = F - J x for the rows of one chunk, partial ||w||^2.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kresid(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_RESTART) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  double w0 = 0.0, w1 = 0.0;
+  if (r < I.nu) {
+    const int p = I.kp_of_r[r];
+    w0 = I.F[2 * p];
+    w1 = I.F[2 * p + 1];
+    const T* J = (const T*)I.jval;
+    const T* x = (const T*)I.kx;
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const Blk<T> B = ld_blk(J, q);
+      const int c = I.kcol[q];
+      const double a = (double)x[2 * c], b = (double)x[2 * c + 1];
+      w0 -= (double)B.a * a + (double)B.b * b;
+      w1 -= (double)B.c * a + (double)B.d * b;
+    }
+    T* w = (T*)I.kw;
+    w[2 * r] = (T)w0;
+    w[2 * r + 1] = (T)w1;
+    w0 = (double)(T)w0;
+    w1 = (double)(T)w1;
+  }
+  block_sums(
+      1, [&](int) { return w0 * w0 + w1 * w1; }, red, kpart(I, 2, blockIdx.x));
+}
+
+// Per instance: the true residual starts the next cycle, or ends the solve
+// when it already meets the forcing term.
+__global__ void k_krestart_fin(const Inst* const* insts, int nslots) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  if (!kstate_is(I, KS_RESTART)) return;
+  KState& ks = *I.ks;
+  double s = 0.0;
+  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, 2, c)[0];
+  const double beta = sqrt(s);
+  ks.rel = beta / ks.bnorm;
+  if (ks.rel <= ks.eta || !(beta > 0.0)) {
+    ks.met = 1;
+    ks.state = KS_FINISH;
+    return;
+  }
+  kh_g(I)[0] = beta;
+  ks.j = 0;
+  ks.scale = 1.0 / beta;
+  ks.state = KS_ITER;
+}
+
+// The Newton step in the factor layout that the voltage update reads.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_kfinish(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_FINISH) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  if (r >= I.nu) return;
+  const int p = I.kp_of_r[r];
+  const T* x = (const T*)I.kx;
+  T* out = (T*)I.x;
+  out[2 * p] = x[2 * r];
+  out[2 * p + 1] = x[2 * r + 1];
+}
+
+// Per instance: a written result retires the solve (KS_FINISH -> KS_DONE).
+__global__ void k_kretire(const Inst* const* insts, int nslots) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  if (kstate_is(I, KS_FINISH)) I.ks->state = KS_DONE;
+}
+
+// Krylov state of every instance for the host (KS_DONE once the Newton
+// iteration of the instance has ended).
+__global__ void k_kgather(const Inst* const* insts, int nslots, int* out) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslots) return;
+  const Inst& I = *insts[sl];
+  out[sl] = I.red->active ? I.ks->state : KS_DONE;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+
+static inline dim3 chunk_grid(int max_chunks, int nslots) {
+  return dim3((unsigned)(max_chunks > 0 ? max_chunks : 1), (unsigned)nslots);
+}
+static inline dim3 slot_grid(int nslots) { return dim3((unsigned)((nslots + 63) / 64)); }
+static inline dim3 item_grid(int nwork) { return dim3((unsigned)((nwork + 255) / 256)); }
+
+template <typename T>
+void launch_ilu_rows(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
+  if (nwork > 0) k_ilu_rows<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork);
+}
+template <typename T>
+void launch_bj_inv(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
+  if (nwork > 0) k_bj_inv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
+}
+template <typename T>
+void launch_ilu_fwd(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
+  if (nwork > 0) k_ilu_fwd<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork, mode);
+}
+template <typename T>
+void launch_ilu_bwd(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
+  if (nwork > 0) k_ilu_bwd<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork, mode);
+}
+template <typename T>
+void launch_bj_apply(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
+  if (nwork > 0) k_bj_apply<T><<<dim3((unsigned)nwork), 64, 0, st>>>(insts, work, mode);
+}
+template <typename T>
+void launch_karnoldi(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  const dim3 g = chunk_grid(max_chunks, nslots);
+  k_kspmv_dot<T><<<g, KCH, 0, st>>>(insts);
+  k_korth<T><<<g, KCH, 0, st>>>(insts, 0);
+  k_korth<T><<<g, KCH, 0, st>>>(insts, 1);
+  k_karnoldi_end<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
+}
+template <typename T>
+void launch_kbegin(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  k_kbegin<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
+  k_kbegin_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
+}
+template <typename T>
+void launch_kycomb(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks) {
+  k_kycomb<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
+}
+template <typename T>
+void launch_kcycle_end(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  const dim3 g = chunk_grid(max_chunks, nslots);
+  k_kxadd<T><<<g, KCH, 0, st>>>(insts);
+  k_kcycle_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
+  k_kresid<T><<<g, KCH, 0, st>>>(insts);
+  k_krestart_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots);
+}
+template <typename T>
+void launch_kfinish(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks) {
+  k_kfinish<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
+  k_kretire<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots);
+}
+void launch_kgather(hipStream_t st, const Inst* const* insts, int nslots, int* out) {
+  k_kgather<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, out);
+}
+int krylov_max_restart() { return KMAX; }
+
+#define PF_KINST(T)                                                                    \
+  template void launch_ilu_rows<T>(hipStream_t, const Inst* const*, const int2*, int);      \
+  template void launch_bj_inv<T>(hipStream_t, const Inst* const*, const int2*, int);        \
+  template void launch_ilu_fwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
+  template void launch_ilu_bwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
+  template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
+  template void launch_karnoldi<T>(hipStream_t, const Inst* const*, int, int, KOpts);       \
+  template void launch_kbegin<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
+  template void launch_kycomb<T>(hipStream_t, const Inst* const*, int, int);                \
+  template void launch_kcycle_end<T>(hipStream_t, const Inst* const*, int, int, KOpts);     \
+  template void launch_kfinish<T>(hipStream_t, const Inst* const*, int, int);
+
+PF_KINST(double)
+PF_KINST(float)
+
+}  // namespace pfd

@@ -18,25 +18,15 @@ namespace pfi {
 
 namespace {
 
-struct Prof {
-  Ctx* ctx;
-  int cls;
-  hipEvent_t a;
-  double flops, bytes;
-  Prof(Ctx* c, int k, double f, double b) : ctx(c), cls(k), a(nullptr), flops(f), bytes(b) {
-    ctx->prof_begin(cls, &a);
-  }
-  ~Prof() { ctx->prof_end(cls, a, flops, bytes); }
-};
-
 constexpr int NB = 64;
 
 }  // namespace
 
 Batch::~Batch() {
-  if (dmem && ctx) {
+  if ((dmem || kmem) && ctx) {
     (void)hipStreamSynchronize(ctx->stream);
-    ctx->dfree(dmem);
+    if (dmem) ctx->dfree(dmem);
+    if (kmem) ctx->dfree(kmem);
   }
 }
 
@@ -236,14 +226,27 @@ void lu_solve(Batch* b) {
 
 }  // namespace
 
-static pf_status check_opts(const pf_options* opt) {
-  if (opt->solver != PF_SOLVER_LU) {
-    set_error("pf_solve: only the LU inner solver is available in this build");
+pf_status check_opts(const pf_options* opt) {
+  if (opt->solver != PF_SOLVER_LU && opt->solver != PF_SOLVER_GMRES) {
+    set_error("pf_solve: unknown solver");
+    return PF_E_INVALID;
+  }
+  if (opt->precision != PF_PREC_FP64 && opt->precision != PF_PREC_MIXED) {
+    set_error("pf_solve: unknown precision");
     return PF_E_INVALID;
   }
   if (!(opt->tol > 0) || opt->max_iter < 0) {
     set_error("pf_solve: tol must be > 0 and max_iter >= 0");
     return PF_E_INVALID;
+  }
+  if (opt->solver == PF_SOLVER_GMRES) {
+    if (opt->gmres_m < 1 || opt->gmres_m > pfd::krylov_max_restart() || opt->gmres_max_restarts < 0 ||
+        !(opt->eta_max > 0 && opt->eta_max < 1) ||
+        (opt->precond != PF_PRECOND_ILU0 && opt->precond != PF_PRECOND_BJACOBI)) {
+      set_error("pf_solve: GMRES needs 1 <= gmres_m <= 128, gmres_max_restarts >= 0, 0 < eta_max < 1 and a known "
+                "preconditioner");
+      return PF_E_INVALID;
+    }
   }
   return PF_OK;
 }
@@ -261,6 +264,14 @@ static pfd::DevOpts dev_opts(const pf_options* opt) {
 pf_status start_batch(Batch* b, const pf_options* opt) {
   pf_status st = check_opts(opt);
   if (st != PF_OK) return st;
+  if (opt->solver == PF_SOLVER_GMRES) {
+    for (Case* c : b->cases)
+      if (!ensure_krylov(c, opt->gmres_m)) return PF_E_NOMEM;
+    if (!b->kbuilt && !b->build_krylov()) {
+      set_error("pf_solve: Krylov batch set-up failed");
+      return PF_E_NOMEM;
+    }
+  }
   hipStream_t s = b->ctx->stream;
   pfd::launch_init(s, b->d_insts, b->nslots, b->max_n, opt->flat_start ? 1 : 0);
   pfd::launch_start(s, b->d_insts, b->nslots);
@@ -276,10 +287,14 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
 // and the convergence test.
 pf_status step_batch(Batch* b, const pf_options* opt) {
   hipStream_t s = b->ctx->stream;
-  if (opt->precision == PF_PREC_MIXED)
+  if (opt->solver == PF_SOLVER_GMRES) {
+    pf_status st = nk_step(b, opt);
+    if (st != PF_OK) return st;
+  } else if (opt->precision == PF_PREC_MIXED) {
     lu_solve<float>(b);
-  else
+  } else {
     lu_solve<double>(b);
+  }
   {
     Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
     pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);

@@ -1,0 +1,299 @@
+// Newton-Krylov inner solve (Sec. III-B) on the host side: the case's Krylov
+// storage, the batch's launch lists, and the Newton step that drives the
+// batched GMRES kernels (krylov.hip).
+//
+// The number of Arnoldi steps an instance needs is decided on the device.
+// After every step the host reads the instances' Krylov states: it ends the
+// cycle of the instances that asked for it (solution update, restart or
+// result) and launches the next step for the others, until none iterates.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace pfi {
+
+namespace {
+
+template <typename T>
+size_t carve_bytes(int64_t count) {
+  return ((size_t)std::max<int64_t>(count, 0) * sizeof(T) + 255) & ~(size_t)255;
+}
+
+template <typename T>
+T* carve(char*& p, int64_t count) {
+  T* r = (T*)p;
+  p += carve_bytes<T>(count);
+  return r;
+}
+
+}  // namespace
+
+void free_krylov(Case* c) {
+  if (c->kbase) {
+    c->ctx->dfree(c->kbase);
+    c->bytes -= c->kbytes;
+    c->kbase = nullptr;
+    c->kbytes = 0;
+    c->km = 0;
+  }
+}
+
+bool ensure_krylov(Case* c, int m) {
+  if (c->kbase && c->km >= m) return true;
+  if (!c->ka) {
+    set_error("pf_solve: the case has no Krylov analysis");
+    return false;
+  }
+  Ctx* ctx = c->ctx;
+  const pfh::KAnalysis& ka = *c->ka;
+  const int km = std::max(m, 30);
+  const int nu = ka.nu;
+  const int64_t knnz = ka.nnz(), nup = ka.nup();
+  const int nb = ka.nblocks();
+  const int kchunks = (nu + pfd::KCH - 1) / pfd::KCH;
+  const int64_t n2 = 2LL * nu;
+  const int64_t nh = (int64_t)(km + 1) * km + 2LL * km + (km + 1) + km;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    set_error("pf_solve: device failure before the Krylov set-up");
+    return false;
+  }
+  free_krylov(c);
+
+  size_t total = carve_bytes<int>(nu) + carve_bytes<int>(nu + 1) + carve_bytes<int>(knnz) + carve_bytes<int>(nu) +
+                 carve_bytes<int>(c->nnz) + carve_bytes<int>(knnz + 1) + 2 * carve_bytes<int>(nup) +
+                 carve_bytes<int>(nb + 1) + 2 * carve_bytes<int>(nu) + carve_bytes<int64_t>(nb + 1);
+  total += 2 * carve_bytes<double>(4 * knnz) + carve_bytes<double>(4LL * nu) + carve_bytes<double>(ka.bj_off.back()) +
+           carve_bytes<double>((km + 1) * n2) + 3 * carve_bytes<double>(n2);
+  total += carve_bytes<double>(nh) + carve_bytes<double>(3LL * std::max(kchunks, 1) * (km + 1)) +
+           carve_bytes<pfd::KState>(1);
+  char* base = (char*)ctx->dalloc(total);
+  if (!base) {
+    set_error("pf_solve: device allocation of the Krylov storage failed");
+    return false;
+  }
+  char* p = base;
+  pfd::Inst& h = c->hinst;
+  int* kp_of_r = carve<int>(p, nu);
+  int* krow_ptr = carve<int>(p, nu + 1);
+  int* kcol = carve<int>(p, knnz);
+  int* kdiag = carve<int>(p, nu);
+  int* kmap = carve<int>(p, c->nnz);
+  int* kup_ptr = carve<int>(p, knnz + 1);
+  int* kup_t = carve<int>(p, nup);
+  int* kup_s = carve<int>(p, nup);
+  int* bj_ptr = carve<int>(p, nb + 1);
+  int* bj_rows = carve<int>(p, nu);
+  int* bj_loc = carve<int>(p, nu);
+  int64_t* bj_off = carve<int64_t>(p, nb + 1);
+  h.jval = carve<double>(p, 4 * knnz);
+  h.pval = carve<double>(p, 4 * knnz);
+  h.pdinv = carve<double>(p, 4LL * nu);
+  h.bjinv = carve<double>(p, ka.bj_off.back());
+  h.kv = carve<double>(p, (km + 1) * n2);
+  h.kw = carve<double>(p, n2);
+  h.kz = carve<double>(p, n2);
+  h.kx = carve<double>(p, n2);
+  h.kh = carve<double>(p, nh);
+  h.kpart = carve<double>(p, 3LL * std::max(kchunks, 1) * (km + 1));
+  h.ks = carve<pfd::KState>(p, 1);
+  if ((size_t)(p - base) != total) {
+    ctx->dfree(base);
+    set_error("pf_solve: internal Krylov layout error");
+    return false;
+  }
+  h.km = km;
+  h.kchunks = kchunks;
+  h.knb = nb;
+  h.kp_of_r = kp_of_r;
+  h.krow_ptr = krow_ptr;
+  h.kcol = kcol;
+  h.kdiag = kdiag;
+  h.kmap = kmap;
+  h.kup_ptr = kup_ptr;
+  h.kup_t = kup_t;
+  h.kup_s = kup_s;
+  h.bj_ptr = bj_ptr;
+  h.bj_rows = bj_rows;
+  h.bj_loc = bj_loc;
+  h.bj_off = bj_off;
+
+  hipStream_t s = ctx->stream;
+  bool ok = true;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes) ok &= hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  up(kp_of_r, ka.p_of_r.data(), sizeof(int) * nu);
+  up(krow_ptr, ka.row_ptr.data(), sizeof(int) * (nu + 1));
+  up(kcol, ka.col.data(), sizeof(int) * knnz);
+  up(kdiag, ka.diag.data(), sizeof(int) * nu);
+  up(kmap, c->kmap_host.data(), sizeof(int) * c->nnz);
+  up(kup_ptr, ka.up_ptr.data(), sizeof(int) * (knnz + 1));
+  up(kup_t, ka.up_t.data(), sizeof(int) * nup);
+  up(kup_s, ka.up_s.data(), sizeof(int) * nup);
+  up(bj_ptr, ka.bj_ptr.data(), sizeof(int) * (nb + 1));
+  up(bj_rows, ka.bj_rows.data(), sizeof(int) * nu);
+  up(bj_loc, ka.bj_loc.data(), sizeof(int) * nu);
+  up(bj_off, ka.bj_off.data(), sizeof(int64_t) * (nb + 1));
+  ok &= hipMemsetAsync(h.ks, 0, sizeof(pfd::KState), s) == hipSuccess;
+  up(c->d_inst, &h, sizeof h);
+  ok &= hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    ctx->dfree(base);
+    set_error("pf_solve: upload of the Krylov storage failed");
+    return false;
+  }
+  c->kbase = base;
+  c->kbytes = total;
+  c->km = km;
+  c->bytes += total;
+  return true;
+}
+
+bool Batch::build_krylov() {
+  std::vector<int2> work;
+  k_lev.clear();
+  k_ulev.clear();
+  max_kchunks = 0;
+  size_t max_l = 0, max_u = 0;
+  for (Case* c : cases) {
+    if (!c->ka || !c->kbase) return false;
+    max_l = std::max(max_l, c->ka->lev_ptr.size() - 1);
+    max_u = std::max(max_u, c->ka->ulev_ptr.size() - 1);
+    max_kchunks = std::max(max_kchunks, c->hinst.kchunks);
+  }
+  auto levels = [&](bool upper, size_t nl, std::vector<std::pair<int64_t, int>>* out) {
+    for (size_t l = 0; l < nl; ++l) {
+      const int64_t off = (int64_t)work.size();
+      for (int s = 0; s < nslots; ++s) {
+        const pfh::KAnalysis& ka = *cases[s]->ka;
+        const auto& ptr = upper ? ka.ulev_ptr : ka.lev_ptr;
+        const auto& rows = upper ? ka.ulev_rows : ka.lev_rows;
+        if (l + 1 >= ptr.size()) continue;
+        for (int k = ptr[l]; k < ptr[l + 1]; ++k) work.push_back(make_int2(s, rows[k]));
+      }
+      out->emplace_back(off, (int)((int64_t)work.size() - off));
+    }
+  };
+  levels(false, max_l, &k_lev);
+  levels(true, max_u, &k_ulev);
+  {
+    const int64_t off = (int64_t)work.size();
+    for (int s = 0; s < nslots; ++s)
+      for (int b = 0; b < cases[s]->ka->nblocks(); ++b) work.push_back(make_int2(s, b));
+    k_blocks = {off, (int)((int64_t)work.size() - off)};
+  }
+  const size_t bw = (sizeof(int2) * std::max<size_t>(work.size(), 1) + 255) & ~(size_t)255;
+  const size_t bs = sizeof(int) * std::max(nslots, 1);
+  if (kmem) ctx->dfree(kmem);
+  kmem = (char*)ctx->dalloc(bw + bs);
+  if (!kmem) return false;
+  d_kwork = (int2*)kmem;
+  d_kstate = (int*)(kmem + bw);
+  hipStream_t st = ctx->stream;
+  bool ok = true;
+  if (!work.empty())
+    ok &= hipMemcpyAsync(d_kwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  kbuilt = ok;
+  return ok;
+}
+
+namespace {
+
+template <typename T>
+pf_status nk_step_t(Batch* b, const pf_options* opt) {
+  Ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  const auto* I = b->d_insts;
+  for (Case* c : b->cases)
+    if (!ensure_krylov(c, opt->gmres_m)) return PF_E_NOMEM;
+  if (!b->kbuilt && !b->build_krylov()) {
+    set_error("pf_solve: Krylov batch set-up failed");
+    return PF_E_NOMEM;
+  }
+  pfd::KOpts ko;
+  ko.eta_max = opt->eta_max;
+  ko.eta_floor = opt->precision == PF_PREC_MIXED ? 1e-6 : 1e-12;
+  ko.m = opt->gmres_m;
+  ko.max_restarts = opt->gmres_max_restarts;
+  const bool ilu = opt->precond == PF_PRECOND_ILU0;
+  const int ns = b->nslots, mc = b->max_kchunks;
+  const int2* kw = b->d_kwork;
+  {
+    Prof p(ctx, PF_K_JFILL, 0.0, 0.0);
+    pfd::launch_kfill<T>(s, I, ns, b->max_nnz, ilu ? 1 : 0);
+  }
+  {
+    Prof p(ctx, PF_K_PRECOND_SETUP, 0.0, 0.0);
+    if (ilu)
+      for (const auto& l : b->k_lev) pfd::launch_ilu_rows<T>(s, I, kw + l.first, l.second);
+    else
+      pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second);
+  }
+  {
+    Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+    pfd::launch_kbegin<T>(s, I, ns, mc, ko);
+    pfd::launch_kfinish<T>(s, I, ns, mc);
+  }
+  auto apply = [&](int mode) {
+    Prof p(ctx, PF_K_PRECOND_APPLY, 0.0, 0.0);
+    if (ilu) {
+      for (const auto& l : b->k_lev) pfd::launch_ilu_fwd<T>(s, I, kw + l.first, l.second, mode);
+      for (const auto& l : b->k_ulev) pfd::launch_ilu_bwd<T>(s, I, kw + l.first, l.second, mode);
+    } else {
+      pfd::launch_bj_apply<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second, mode);
+    }
+  };
+  std::vector<int> st(ns);
+  const int64_t guard_max = (int64_t)(opt->gmres_max_restarts + 1) * (opt->gmres_m + 2) + 4;
+  for (int64_t guard = 0;; ++guard) {
+    if (guard > guard_max) {
+      set_error("pf_solve: the Krylov inner solve did not settle");
+      return PF_E_DEVICE;
+    }
+    pfd::launch_kgather(s, I, ns, b->d_kstate);
+    if (hipMemcpyAsync(st.data(), b->d_kstate, sizeof(int) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("pf_solve: device failure in the Krylov inner solve");
+      return PF_E_DEVICE;
+    }
+    bool iter = false, cyc = false;
+    for (int v : st) {
+      iter |= v == pfd::KS_ITER;
+      cyc |= v == pfd::KS_CYCLE;
+    }
+    if (cyc) {
+      {
+        Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+        pfd::launch_kycomb<T>(s, I, ns, mc);
+      }
+      apply(1);
+      Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+      pfd::launch_kcycle_end<T>(s, I, ns, mc, ko);
+      pfd::launch_kfinish<T>(s, I, ns, mc);
+      continue;
+    }
+    if (!iter) break;
+    apply(0);
+    Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+    pfd::launch_karnoldi<T>(s, I, ns, mc, ko);
+  }
+  {
+    Prof p(ctx, PF_K_UPDATE, 0.0, 0.0);
+    pfd::launch_update<T>(s, I, ns, b->max_nu);
+  }
+  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+}
+
+}  // namespace
+
+pf_status nk_step(Batch* b, const pf_options* opt) {
+  return opt->precision == PF_PREC_MIXED ? nk_step_t<float>(b, opt) : nk_step_t<double>(b, opt);
+}
+
+}  // namespace pfi

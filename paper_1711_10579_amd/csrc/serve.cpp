@@ -236,10 +236,7 @@ pf_status pf_submit(pf_ctx* ctx, pf_case* c, const pf_options* opt, uint64_t* ti
   pf_options o;
   pf_default_options(&o);
   if (opt) o = *opt;
-  if (o.solver != PF_SOLVER_LU || !(o.tol > 0) || o.max_iter < 0) {
-    set_error("pf_submit: unsupported options");
-    return PF_E_INVALID;
-  }
+  if (check_opts(&o) != PF_OK) return PF_E_INVALID;
   int expect = 0;
   if (!c->busy.compare_exchange_strong(expect, 1)) {
     set_error("pf_submit: case already queued or running");

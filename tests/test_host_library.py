@@ -63,6 +63,17 @@ def test_schedule_replay(name, maker):
     assert res < 1e-13
 
 
+@pytest.mark.parametrize("name,maker", CASES, ids=[c[0] for c in CASES])
+def test_krylov_analysis_replay(name, maker):
+    # every index of the Newton-Krylov analysis, and block ILU(0) through its
+    # update lists and level schedules reproduces A on the pattern
+    c = maker()
+    dev, res, checks = B.pf_debug_krylov_check(**B.case_arrays(c), seed=5)
+    assert checks > 0
+    assert dev < 1e-13
+    assert res < 1e-12
+
+
 def test_dense_block_appears_on_meshed_grids():
     # the 10k-bus meshed grid leaves a dense trailing block; a radial feeder not
     c1 = pfgen.config_case(1)
