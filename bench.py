@@ -104,6 +104,23 @@ def _roof(st, bound, peak, unit, kernel):
             ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): per}
 
 
+def _breakdown(B, ctx, h, opts, tag, solves=3):
+    """Every kernel class timed with HIP events over a few extra solves
+    (stderr)."""
+    B.pf_profile_enable(ctx, -1)
+    B.pf_profile_reset(ctx)
+    for _ in range(solves):
+        B.pf_solve(h, opts)
+    rows = [(name, B.pf_kernel_stats(ctx, k)) for k, name in enumerate(B.KERNEL_CLASS_NAMES)]
+    tot = sum(s["ms"] for _, s in rows)
+    for name, s in rows:
+        if s["launches"]:
+            print(f"[breakdown {tag}] {name:14s} launches/solve={s['launches'] / solves:8.1f} "
+                  f"ms/solve={s['ms'] / solves:8.4f} ({100 * s['ms'] / tot:5.1f}%) "
+                  f"GFLOP/s={s['flops'] / max(s['ms'], 1e-12) / 1e6:9.1f}", file=sys.stderr)
+    B.pf_profile_enable(ctx, 0)
+
+
 def calibrate_copy():
     import torch
 
@@ -142,22 +159,7 @@ def bench_grid10k(args):
         assert r.status == B.PF_CONVERGED, r.as_dict()
 
     if args.breakdown:
-        B.pf_profile_enable(ctx, -1)
-        B.pf_profile_reset(ctx)
-        for _ in range(3):
-            B.pf_solve(h, opts)
-        tot = 0.0
-        rows = []
-        for k, name in enumerate(B.KERNEL_CLASS_NAMES):
-            s = B.pf_kernel_stats(ctx, k)
-            tot += s["ms"]
-            rows.append((name, s))
-        for name, s in rows:
-            if s["launches"]:
-                print(f"[breakdown] {name:14s} launches/solve={s['launches'] / 3:8.1f} "
-                      f"ms/solve={s['ms'] / 3:8.4f} ({100 * s['ms'] / tot:5.1f}%) "
-                      f"GFLOP/s={s['flops'] / max(s['ms'], 1e-12) / 1e6:9.1f}", file=sys.stderr)
-        B.pf_profile_enable(ctx, 0)
+        _breakdown(B, ctx, h, opts, "lu")
 
     # the dominant kernel (panel steps of the dense block LU) is timed with
     # HIP events on the library's stream inside the timed region
@@ -185,6 +187,34 @@ def bench_grid10k(args):
     st_sec = B.pf_kernel_stats(ctx, sec)
     B.pf_profile_enable(ctx, 0)
     mism = polar.mismatch_at(case, B.pf_get_voltage(h))
+
+    # Newton-Krylov on the same grid: GMRES(30) right-preconditioned with
+    # block ILU(0), forcing term min(0.1, ||F||_inf)
+    nk = None
+    if args.nk_steps > 0:
+        nopts = B.pf_default_options(solver=B.PF_SOLVER_GMRES, precision=int(mixed), max_iter=40)
+        for _ in range(max(1, args.warmup)):
+            r = B.pf_solve(h, nopts)
+            assert r.status == B.PF_CONVERGED, r.as_dict()
+        if args.breakdown:
+            _breakdown(B, ctx, h, nopts, "nk")
+        torch.cuda.synchronize()
+        nlat, nconv, nlin, nit = [], 0, [], []
+        t0 = time.perf_counter()
+        for _ in range(args.nk_steps):
+            s0 = time.perf_counter()
+            r = B.pf_solve(h, nopts)
+            nlat.append(time.perf_counter() - s0)
+            nconv += r.status == B.PF_CONVERGED
+            nlin.append(r.linear_iters)
+            nit.append(r.iters)
+        torch.cuda.synchronize()
+        nel = time.perf_counter() - t0
+        nk = {"value": nconv / nel, "unit": "solves/s", "steps": args.nk_steps, "converged": nconv,
+              "latency_ms": {"p50": 1000 * _pct(nlat, 50), "p99": 1000 * _pct(nlat, 99)},
+              "solver": "gmres(30)+ilu0", "newton_iters": int(np.median(nit)),
+              "gmres_iters_per_solve": int(np.median(nlin)),
+              "final_mismatch_oracle": polar.mismatch_at(case, B.pf_get_voltage(h))}
 
     # batched form: the same grid under seeded load scenarios, one
     # pf_solve_batch per step
@@ -242,6 +272,7 @@ def bench_grid10k(args):
         "roofline_secondary": _roof(st_sec, "mfma", mfma_peak, "TFLOP/s",
                                     "k_dense_gemm (matrix-core trailing update of the dense block)"),
         "batched": batched,
+        "newton_krylov": nk,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
@@ -390,6 +421,8 @@ def main():
     ap.add_argument("--breakdown", action="store_true",
                     help="time every kernel class in an extra untimed pass (stderr)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nk-steps", type=int, default=10,
+                    help="solves of the Newton-Krylov (GMRES + ILU(0)) leg on the same grid")
     ap.add_argument("--batch", type=int, default=16,
                     help="scenarios of the batched form (seeded +-20%% load perturbations)")
     ap.add_argument("--workload", choices=["grid10k", "scenarios512", "served"], default="grid10k")
