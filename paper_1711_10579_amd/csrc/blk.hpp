@@ -7,10 +7,52 @@
 
 namespace pfd {
 
+// Pointers into device (global) memory.  Memory reached through the
+// instance descriptors is otherwise accessed through generic pointers, whose
+// loads the compiler issues as flat loads; flat loads are also counted by the
+// LDS wait counter, so every LDS wait or barrier would wait for them too.
+#define PF_AS1 __attribute__((address_space(1)))
+template <typename T>
+__device__ inline PF_AS1 T* gp(T* p) {
+  return (PF_AS1 T*)p;
+}
+template <typename T>
+__device__ inline const PF_AS1 T* gp(const T* p) {
+  return (const PF_AS1 T*)p;
+}
+
+// four ints as a native vector (loadable through any address space)
+typedef int i4v __attribute__((ext_vector_type(4)));
+
 template <typename T>
 struct Blk {
   T a, b, c, d;  // [[a b] [c d]]
 };
+
+template <typename T, typename Ptr>
+__device__ inline Blk<T> ld_blk_as(Ptr p, int64_t id) {
+  const auto q = p + 4 * id;
+  Blk<T> r;
+  r.a = q[0];
+  r.b = q[1];
+  r.c = q[2];
+  r.d = q[3];
+  return r;
+}
+
+template <typename T>
+__device__ inline Blk<T> ld_blk(const PF_AS1 T* p, int64_t id) {
+  return ld_blk_as<T>(p, id);
+}
+
+template <typename T>
+__device__ inline void st_blk(PF_AS1 T* p, int64_t id, const Blk<T>& v) {
+  PF_AS1 T* q = p + 4 * id;
+  q[0] = v.a;
+  q[1] = v.b;
+  q[2] = v.c;
+  q[3] = v.d;
+}
 
 template <typename T>
 __device__ inline Blk<T> ld_blk(const T* p, int64_t id) {

@@ -68,8 +68,13 @@ struct Inst {
   int km;        // restart length the basis storage holds
   int kchunks;   // vector chunks of KCH rows
   int knb;       // block-Jacobi blocks
-  int pad2;
+  int knl, knul; // ILU(0) forward and backward levels
   const int *kp_of_r, *krow_ptr, *kcol, *kdiag, *kmap, *kup_ptr, *kup_t, *kup_s;
+  // rows by forward / backward level: level pointers, and per position
+  // {row, first, end, 0} of the row's lower (forward) or upper (backward)
+  // entries
+  const int *kl_ptr, *ku_ptr;
+  const int4 *kl_info, *ku_info;
   const int *bj_ptr, *bj_rows, *bj_loc;
   const int64_t* bj_off;
   void *jval, *pval, *pdinv, *bjinv;

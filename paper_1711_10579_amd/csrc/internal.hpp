@@ -147,6 +147,8 @@ struct Batch {
   std::vector<std::pair<int64_t, int>> k_lev, k_ulev;
   std::pair<int64_t, int> k_blocks{0, 0};
   int max_kchunks = 0;
+  int k_max_nu = 0;
+  bool k_wide = false;  // some ILU(0) level is wider than one work-group pass
 
   ~Batch();
   bool build(Ctx* ctx, const std::vector<Case*>& cs);

@@ -273,6 +273,200 @@ __global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const
   z[2 * r + 1] = (T)((double)D.c * s0 + (double)D.d * s1);
 }
 
+// The whole ILU(0) factor of an instance in one work-group: the rows of
+// each level as in k_ilu_rows, a barrier between levels.  Used when the
+// instance's levels are short (one launch instead of one per level).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ilu_factor_wg(const Inst* const* insts) {
+  const auto& I = *gp(insts[blockIdx.x]);
+  if (!gp(I.red)->active) return;
+  auto P = gp((T*)I.pval);
+  auto D = gp((T*)I.pdinv);
+  const auto kl_ptr = gp(I.kl_ptr), kcol = gp(I.kcol), kup_ptr = gp(I.kup_ptr), kup_t = gp(I.kup_t),
+             kup_s = gp(I.kup_s);
+  const auto kl_info = (const PF_AS1 i4v*)I.kl_info;
+  bool bad = false;
+  for (int l = 0; l < I.knl; ++l) {
+    const int k1 = kl_ptr[l + 1];
+    for (int k = kl_ptr[l] + (int)threadIdx.x; k < k1; k += 1024) {
+      const i4v inf = kl_info[k];
+      const int r = inf.x, qd = inf.z;
+      for (int q = inf.y; q < qd; ++q) {
+        const Blk<T> L = blk_mul(ld_blk<T>(P, q), ld_blk<T>(D, kcol[q]));
+        st_blk(P, q, L);
+        for (int u = kup_ptr[q]; u < kup_ptr[q + 1]; ++u) {
+          const int t = kup_t[u];
+          Blk<T> a = ld_blk<T>(P, t);
+          blk_msub(a, L, ld_blk<T>(P, kup_s[u]));
+          st_blk(P, t, a);
+        }
+      }
+      Blk<T> inv;
+      if (!blk_inv(ld_blk<T>(P, qd), &inv)) {
+        bad = true;
+        inv.a = inv.b = inv.c = inv.d = T(0);
+      }
+      st_blk(D, r, inv);
+    }
+    __syncthreads();
+  }
+  if (bad) gp(I.red)->singular = 1;
+}
+
+namespace {
+
+constexpr int LPM = 256;  // level pointers kept in LDS (z takes the rest)
+
+// One row of a sweep with its first two off-diagonal entries, loaded ahead
+// of the level that needs it.
+template <typename T>
+struct SweepRow {
+  i4v inf;  // {row, first, end, 0}; row < 0: none
+  T w0, w1;  // forward: right-hand side; backward: unused
+  Blk<T> E[2];
+  int c[2];
+};
+
+template <typename T>
+__device__ inline void sweep_load(const PF_AS1 i4v* info, const PF_AS1 T* P, const PF_AS1 int* kcol,
+                                  const PF_AS1 T* w, int k, int k1, SweepRow<T>* s) {
+  s->inf.x = -1;
+  if (k >= k1) return;
+  s->inf = info[k];
+  if (w) {
+    s->w0 = w[2 * s->inf.x];
+    s->w1 = w[2 * s->inf.x + 1];
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+    if (s->inf.y + e < s->inf.z) {
+      s->E[e] = ld_blk<T>(P, s->inf.y + e);
+      s->c[e] = kcol[s->inf.y + e];
+    }
+}
+
+}  // namespace
+
+// The ILU(0) application z = U^{-1} L^{-1} (s w) of an instance in one
+// work-group, level by level with a barrier between levels (rows as in
+// k_ilu_fwd / k_ilu_bwd).  Each thread loads its row of the next level while
+// the current level is computed.  ZV > 0: the work-group keeps z in LDS
+// (instances with 2 nu <= ZV values) and writes it out at the end; ZV = 0: z
+// lives in device memory.  Instances of the other sizes are skipped.
+template <typename T, int ZV>
+__global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts, int mode, int zmin) {
+  __shared__ T zl[ZV > 0 ? ZV : 1];
+  __shared__ int lpf[LPM + 1], lpb[LPM + 1];
+  const auto& I = *gp(insts[blockIdx.x]);
+  const auto ks = gp(I.ks);
+  if (!gp(I.red)->active || ks->state != (mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  const int nu = I.nu;
+  if (2 * nu <= zmin || (ZV > 0 && 2 * nu > ZV)) return;
+  T* z = ZV > 0 ? zl : (T*)I.kz;
+  const auto P = gp((const T*)I.pval);
+  const auto Dinv = gp((const T*)I.pdinv);
+  const auto kcol = gp(I.kcol);
+  const auto w = gp((const T*)I.kw);
+  const auto kl_info = (const PF_AS1 i4v*)I.kl_info, ku_info = (const PF_AS1 i4v*)I.ku_info;
+  const auto kl_ptr = gp(I.kl_ptr), ku_ptr = gp(I.ku_ptr);
+  const int tid = threadIdx.x;
+  const int nl = I.knl, nul = I.knul;
+  const bool lds_ptr = nl <= LPM && nul <= LPM;
+  if (lds_ptr) {
+    for (int i = tid; i <= nl; i += 1024) lpf[i] = kl_ptr[i];
+    for (int i = tid; i <= nul; i += 1024) lpb[i] = ku_ptr[i];
+  }
+  const double sc = mode == 0 ? ks->scale : 1.0;
+  const auto vj = gp((T*)I.kv + (int64_t)ks->j * 2 * nu);
+  __syncthreads();
+  auto fp = [&](int l) { return lds_ptr ? lpf[l] : kl_ptr[l]; };
+  auto bp = [&](int l) { return lds_ptr ? lpb[l] : ku_ptr[l]; };
+
+  // forward: y_r = s w_r - sum_{k<r} L(r,k) y_k
+  auto fwd_row = [&](const SweepRow<T>& s) {
+    const int r = s.inf.x;
+    T v0 = s.w0, v1 = s.w1;
+    if (mode == 0) {
+      v0 = (T)((double)v0 * sc);
+      v1 = (T)((double)v1 * sc);
+      vj[2 * r] = v0;
+      vj[2 * r + 1] = v1;
+    }
+    double y0 = (double)v0, y1 = (double)v1;
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (s.inf.y + e < s.inf.z) {
+        const double a = (double)z[2 * s.c[e]], b = (double)z[2 * s.c[e] + 1];
+        y0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
+        y1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
+      }
+    for (int q = s.inf.y + 2; q < s.inf.z; ++q) {
+      const Blk<T> L = ld_blk<T>(P, q);
+      const int c = kcol[q];
+      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
+      y0 -= (double)L.a * a + (double)L.b * b;
+      y1 -= (double)L.c * a + (double)L.d * b;
+    }
+    z[2 * r] = (T)y0;
+    z[2 * r + 1] = (T)y1;
+  };
+  SweepRow<T> cur, nxt;
+  if (nl > 0) sweep_load<T>(kl_info, P, kcol, w, fp(0) + tid, fp(1), &cur);
+  for (int l = 0; l < nl; ++l) {
+    const int k0 = fp(l), k1 = fp(l + 1);
+    if (l + 1 < nl) sweep_load<T>(kl_info, P, kcol, w, k1 + tid, fp(l + 2), &nxt);
+    if (cur.inf.x >= 0) fwd_row(cur);
+    for (int k = k0 + tid + 1024; k < k1; k += 1024) {
+      SweepRow<T> x;
+      sweep_load<T>(kl_info, P, kcol, w, k, k1, &x);
+      fwd_row(x);
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+
+  // backward: z_r = U(r,r)^{-1} (y_r - sum_{j>r} U(r,j) z_j)
+  auto bwd_row = [&](const SweepRow<T>& s) {
+    const int r = s.inf.x;
+    double s0 = (double)z[2 * r], s1 = (double)z[2 * r + 1];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (s.inf.y + e < s.inf.z) {
+        const double a = (double)z[2 * s.c[e]], b = (double)z[2 * s.c[e] + 1];
+        s0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
+        s1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
+      }
+    for (int q = s.inf.y + 2; q < s.inf.z; ++q) {
+      const Blk<T> U = ld_blk<T>(P, q);
+      const int c = kcol[q];
+      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
+      s0 -= (double)U.a * a + (double)U.b * b;
+      s1 -= (double)U.c * a + (double)U.d * b;
+    }
+    const Blk<T> Dv = ld_blk<T>(Dinv, r);
+    z[2 * r] = (T)((double)Dv.a * s0 + (double)Dv.b * s1);
+    z[2 * r + 1] = (T)((double)Dv.c * s0 + (double)Dv.d * s1);
+  };
+  const PF_AS1 T* nw = nullptr;
+  if (nul > 0) sweep_load<T>(ku_info, P, kcol, nw, bp(0) + tid, bp(1), &cur);
+  for (int l = 0; l < nul; ++l) {
+    const int k0 = bp(l), k1 = bp(l + 1);
+    if (l + 1 < nul) sweep_load<T>(ku_info, P, kcol, nw, k1 + tid, bp(l + 2), &nxt);
+    if (cur.inf.x >= 0) bwd_row(cur);
+    for (int k = k0 + tid + 1024; k < k1; k += 1024) {
+      SweepRow<T> x;
+      sweep_load<T>(ku_info, P, kcol, nw, k, k1, &x);
+      bwd_row(x);
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+  if (ZV > 0) {
+    const auto zg = gp((T*)I.kz);
+    for (int i = tid; i < 2 * nu; i += 1024) zg[i] = zl[i];
+  }
+}
+
 // Block-Jacobi application: one wave per node group, z_b = A_bb^{-1} (s w_b)
 // (mode 0 also stores s w_b as basis vector v_j).
 template <typename T>
@@ -684,6 +878,21 @@ void launch_ilu_bwd(hipStream_t st, const Inst* const* insts, const int2* work, 
   if (nwork > 0) k_ilu_bwd<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork, mode);
 }
 template <typename T>
+void launch_ilu_factor_wg(hipStream_t st, const Inst* const* insts, int nslots) {
+  k_ilu_factor_wg<T><<<dim3((unsigned)nslots), 1024, 0, st>>>(insts);
+}
+// z in LDS up to 160,000 bytes of values per work-group, in two sizes so that
+// small instances keep several work-groups per CU
+template <typename T>
+void launch_ilu_apply_wg(hipStream_t st, const Inst* const* insts, int nslots, int mode, int max_nu) {
+  constexpr int small = 8192 / sizeof(T) * 4;   // 32 KiB
+  constexpr int big = 160000 / sizeof(T);
+  const dim3 g((unsigned)nslots);
+  k_ilu_apply_wg<T, small><<<g, 1024, 0, st>>>(insts, mode, 0);
+  if (2 * max_nu > small) k_ilu_apply_wg<T, big><<<g, 1024, 0, st>>>(insts, mode, small);
+  if (2 * max_nu > big) k_ilu_apply_wg<T, 0><<<g, 1024, 0, st>>>(insts, mode, big);
+}
+template <typename T>
 void launch_bj_apply(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
   if (nwork > 0) k_bj_apply<T><<<dim3((unsigned)nwork), 64, 0, st>>>(insts, work, mode);
 }
@@ -728,6 +937,8 @@ int krylov_max_restart() { return KMAX; }
   template void launch_ilu_fwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_ilu_bwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
+  template void launch_ilu_factor_wg<T>(hipStream_t, const Inst* const*, int);              \
+  template void launch_ilu_apply_wg<T>(hipStream_t, const Inst* const*, int, int, int);     \
   template void launch_karnoldi<T>(hipStream_t, const Inst* const*, int, int, KOpts);       \
   template void launch_kbegin<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
   template void launch_kycomb<T>(hipStream_t, const Inst* const*, int, int);                \

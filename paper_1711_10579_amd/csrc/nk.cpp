@@ -64,9 +64,11 @@ bool ensure_krylov(Case* c, int m) {
   }
   free_krylov(c);
 
+  const int nl = (int)ka.lev_ptr.size() - 1, nul = (int)ka.ulev_ptr.size() - 1;
   size_t total = carve_bytes<int>(nu) + carve_bytes<int>(nu + 1) + carve_bytes<int>(knnz) + carve_bytes<int>(nu) +
                  carve_bytes<int>(c->nnz) + carve_bytes<int>(knnz + 1) + 2 * carve_bytes<int>(nup) +
                  carve_bytes<int>(nb + 1) + 2 * carve_bytes<int>(nu) + carve_bytes<int64_t>(nb + 1);
+  total += carve_bytes<int>(nl + 1) + carve_bytes<int>(nul + 1) + 2 * carve_bytes<int4>(nu);
   total += 2 * carve_bytes<double>(4 * knnz) + carve_bytes<double>(4LL * nu) + carve_bytes<double>(ka.bj_off.back()) +
            carve_bytes<double>((km + 1) * n2) + 3 * carve_bytes<double>(n2);
   total += carve_bytes<double>(nh) + carve_bytes<double>(3LL * std::max(kchunks, 1) * (km + 1)) +
@@ -90,6 +92,10 @@ bool ensure_krylov(Case* c, int m) {
   int* bj_rows = carve<int>(p, nu);
   int* bj_loc = carve<int>(p, nu);
   int64_t* bj_off = carve<int64_t>(p, nb + 1);
+  int* kl_ptr = carve<int>(p, nl + 1);
+  int* ku_ptr = carve<int>(p, nul + 1);
+  int4* kl_info = carve<int4>(p, nu);
+  int4* ku_info = carve<int4>(p, nu);
   h.jval = carve<double>(p, 4 * knnz);
   h.pval = carve<double>(p, 4 * knnz);
   h.pdinv = carve<double>(p, 4LL * nu);
@@ -121,6 +127,12 @@ bool ensure_krylov(Case* c, int m) {
   h.bj_rows = bj_rows;
   h.bj_loc = bj_loc;
   h.bj_off = bj_off;
+  h.knl = nl;
+  h.knul = nul;
+  h.kl_ptr = kl_ptr;
+  h.kl_info = kl_info;
+  h.ku_ptr = ku_ptr;
+  h.ku_info = ku_info;
 
   hipStream_t s = ctx->stream;
   bool ok = true;
@@ -139,6 +151,17 @@ bool ensure_krylov(Case* c, int m) {
   up(bj_rows, ka.bj_rows.data(), sizeof(int) * nu);
   up(bj_loc, ka.bj_loc.data(), sizeof(int) * nu);
   up(bj_off, ka.bj_off.data(), sizeof(int64_t) * (nb + 1));
+  up(kl_ptr, ka.lev_ptr.data(), sizeof(int) * (nl + 1));
+  up(ku_ptr, ka.ulev_ptr.data(), sizeof(int) * (nul + 1));
+  std::vector<int4> linfo(nu), uinfo(nu);
+  for (int k = 0; k < nu; ++k) {
+    const int r = ka.lev_rows[k];
+    linfo[k] = make_int4(r, ka.row_ptr[r], ka.diag[r], 0);
+    const int u = ka.ulev_rows[k];
+    uinfo[k] = make_int4(u, ka.diag[u] + 1, ka.row_ptr[u + 1], 0);
+  }
+  up(kl_info, linfo.data(), sizeof(int4) * nu);
+  up(ku_info, uinfo.data(), sizeof(int4) * nu);
   ok &= hipMemsetAsync(h.ks, 0, sizeof(pfd::KState), s) == hipSuccess;
   up(c->d_inst, &h, sizeof h);
   ok &= hipStreamSynchronize(s) == hipSuccess;
@@ -160,11 +183,17 @@ bool Batch::build_krylov() {
   k_ulev.clear();
   max_kchunks = 0;
   size_t max_l = 0, max_u = 0;
+  k_max_nu = 0;
+  k_wide = false;
   for (Case* c : cases) {
     if (!c->ka || !c->kbase) return false;
-    max_l = std::max(max_l, c->ka->lev_ptr.size() - 1);
-    max_u = std::max(max_u, c->ka->ulev_ptr.size() - 1);
+    const pfh::KAnalysis& ka = *c->ka;
+    max_l = std::max(max_l, ka.lev_ptr.size() - 1);
+    max_u = std::max(max_u, ka.ulev_ptr.size() - 1);
     max_kchunks = std::max(max_kchunks, c->hinst.kchunks);
+    k_max_nu = std::max(k_max_nu, ka.nu);
+    for (size_t l = 0; l + 1 < ka.lev_ptr.size(); ++l) k_wide |= ka.lev_ptr[l + 1] - ka.lev_ptr[l] > 4096;
+    for (size_t l = 0; l + 1 < ka.ulev_ptr.size(); ++l) k_wide |= ka.ulev_ptr[l + 1] - ka.ulev_ptr[l] > 4096;
   }
   auto levels = [&](bool upper, size_t nl, std::vector<std::pair<int64_t, int>>* out) {
     for (size_t l = 0; l < nl; ++l) {
@@ -230,7 +259,9 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   }
   {
     Prof p(ctx, PF_K_PRECOND_SETUP, 0.0, 0.0);
-    if (ilu)
+    if (ilu && !b->k_wide)
+      pfd::launch_ilu_factor_wg<T>(s, I, ns);
+    else if (ilu)
       for (const auto& l : b->k_lev) pfd::launch_ilu_rows<T>(s, I, kw + l.first, l.second);
     else
       pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second);
@@ -242,7 +273,9 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   }
   auto apply = [&](int mode) {
     Prof p(ctx, PF_K_PRECOND_APPLY, 0.0, 0.0);
-    if (ilu) {
+    if (ilu && !b->k_wide) {
+      pfd::launch_ilu_apply_wg<T>(s, I, ns, mode, b->k_max_nu);
+    } else if (ilu) {
       for (const auto& l : b->k_lev) pfd::launch_ilu_fwd<T>(s, I, kw + l.first, l.second, mode);
       for (const auto& l : b->k_ulev) pfd::launch_ilu_bwd<T>(s, I, kw + l.first, l.second, mode);
     } else {
