@@ -153,12 +153,39 @@ typedef struct {
   double analysis_ms;   /* host analysis time in pf_create                   */
 } pf_case_info;
 
+/* Schedule of a case: choices of the host analysis and of the launch sequence
+ * that change the work's order but not what is computed (the Sec. III-A
+ * solve mapped onto the device).  pf_autotune chooses them by timing. */
+typedef struct {
+  double dense_switch; /* elimination switches to the dense trailing block once
+                          every remaining node is adjacent to at least this
+                          fraction of the others, 0 < x <= 1               */
+  int32_t min_dense;   /* ... and at least this many nodes remain, >= 1      */
+  int32_t lane_scale;  /* lanes per sparse update / solve list: 1, 2 or 4
+                          times the default choice (at most one wave)       */
+  int32_t trsv_mode;   /* dense backward solve: 0 automatic, 1 flag-
+                          synchronised work-groups, 2 one work-group per
+                          instance                                          */
+  int32_t reserved;
+} pf_schedule;
+
+/* Tuning summary of pf_autotune. */
+typedef struct {
+  int32_t candidates;  /* schedules timed                                   */
+  int32_t trials;      /* timed solves per schedule                         */
+  double default_ms;   /* median device time of a solve, default schedule   */
+  double best_ms;      /* median device time of a solve, chosen schedule    */
+} pf_tune_report;
+
 /* Device allocator callbacks (e.g. a framework's caching allocator). */
 typedef void* (*pf_alloc_fn)(size_t bytes, void* user);
 typedef void (*pf_free_fn)(void* ptr, void* user);
 
 /* Fill *opt with the defaults listed above. */
 void pf_default_options(pf_options* opt);
+/* Fill *s with the default schedule: dense_switch 0.5, min_dense 32,
+ * lane_scale 1, trsv_mode 0. */
+void pf_default_schedule(pf_schedule* s);
 
 /* Create a context on HIP device `device`, launching on `hip_stream` (a
  * hipStream_t; NULL: the context creates its own stream).  Device memory comes
@@ -178,6 +205,23 @@ void pf_ctx_destroy(pf_ctx* ctx);
  * type outside {PQ, PV, SLACK}; CIM with a PF_PV node, without a PF_SLACK
  * node or without zip. */
 pf_status pf_create(pf_ctx* ctx, const pf_case_desc* desc, pf_case** out);
+/* The same under an explicit schedule (PF_E_INVALID if a field is out of
+ * range).  pf_create uses the schedule pf_autotune stored in the context for
+ * the topology of `desc` (Ybus pattern and node types), else the default. */
+pf_status pf_create_scheduled(pf_ctx* ctx, const pf_case_desc* desc, const pf_schedule* sched,
+                              pf_case** out);
+/* The schedule a case was created with. */
+pf_status pf_case_schedule(const pf_case* c, pf_schedule* out);
+/* Autotuner: times `trials` solves (options `opt`, NULL: defaults) of the case
+ * `desc` per candidate schedule in a coordinate search -- dense_switch over
+ * {0.5, 0.3, 0.4, 0.65, 0.8}, then lane_scale over {1, 2, 4}, then trsv_mode
+ * over {0, 1, 2} -- keeping a candidate when its median device time beats the
+ * current choice by 2 %.  Candidates whose solve does not converge are
+ * skipped.  The chosen schedule goes to *best and is stored in the context
+ * for this topology.  `rep` may be NULL.  Uses the context's stream; cases
+ * are created and destroyed internally. */
+pf_status pf_autotune(pf_ctx* ctx, const pf_case_desc* desc, const pf_options* opt, int32_t trials,
+                      pf_schedule* best, pf_tune_report* rep);
 /* Free a case's device memory.  PF_E_BUSY while it is queued or running. */
 pf_status pf_destroy(pf_case* c);
 pf_status pf_case_info_get(const pf_case* c, pf_case_info* out);

@@ -16,8 +16,9 @@
 extern "C" {
 #endif
 
-/* Analyse the case described by `desc` exactly as pf_create does (same
- * validation, PF_E_INVALID on bad input), then replay on the CPU every index
+/* Analyse the case described by `desc` exactly as pf_create_scheduled does
+ * under `sched` (NULL: the default schedule; same validation, PF_E_INVALID on
+ * bad input), then replay on the CPU every index
  * the device kernels derive from that analysis: the Ybus-to-factor map, the
  * update lists of each refactorisation level, the Schur lists of the dense
  * block and the row lists of both triangular solves.  Every index is
@@ -27,8 +28,8 @@ extern "C" {
  * by `seed`) is factored through the schedule and one random system solved;
  * *rel_residual receives ||A x - b||_inf / (||A||_inf ||x||_inf + ||b||_inf)
  * and *checks the number of index checks made.  Outputs are host pointers. */
-pf_status pf_debug_schedule_check(const pf_case_desc* desc, uint64_t seed, double* rel_residual,
-                                  int64_t* checks);
+pf_status pf_debug_schedule_check(const pf_case_desc* desc, const pf_schedule* sched, uint64_t seed,
+                                  double* rel_residual, int64_t* checks);
 
 /* The same for the Newton-Krylov inner solve (Sec. III-B): analyse the case
  * as pf_create does, check every index of the Krylov analysis (ordering,

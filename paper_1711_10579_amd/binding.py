@@ -79,6 +79,22 @@ class pf_result(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class pf_schedule(C.Structure):
+    _fields_ = [("dense_switch", C.c_double), ("min_dense", C.c_int32), ("lane_scale", C.c_int32),
+                ("trsv_mode", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class pf_tune_report(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("trials", C.c_int32), ("default_ms", C.c_double),
+                ("best_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class pf_case_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_unknown", C.c_int32), ("n_sparse", C.c_int32),
                 ("n_dense", C.c_int32), ("levels", C.c_int32), ("bwd_levels", C.c_int32),
@@ -104,6 +120,11 @@ _sig = {
     "pf_ctx_create": (C.c_int, [C.c_int32, _P, ALLOC_FN, FREE_FN, _P, C.POINTER(_P)]),
     "pf_ctx_destroy": (None, [_P]),
     "pf_create": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(_P)]),
+    "pf_default_schedule": (None, [C.POINTER(pf_schedule)]),
+    "pf_create_scheduled": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(pf_schedule), C.POINTER(_P)]),
+    "pf_case_schedule": (C.c_int, [_P, C.POINTER(pf_schedule)]),
+    "pf_autotune": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(pf_options), C.c_int32,
+                              C.POINTER(pf_schedule), C.POINTER(pf_tune_report)]),
     "pf_destroy": (C.c_int, [_P]),
     "pf_case_info_get": (C.c_int, [_P, C.POINTER(pf_case_info)]),
     "pf_set_injections": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -119,7 +140,7 @@ _sig = {
     "pf_profile_enable": (C.c_int, [_P, C.c_int32]),
     "pf_kernel_stats": (C.c_int, [_P, C.c_int32, C.POINTER(pf_kernel_stat)]),
     "pf_profile_reset": (C.c_int, [_P]),
-    "pf_debug_schedule_check": (C.c_int, [C.POINTER(pf_case_desc), C.c_uint64,
+    "pf_debug_schedule_check": (C.c_int, [C.POINTER(pf_case_desc), C.POINTER(pf_schedule), C.c_uint64,
                                           C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pf_debug_krylov_check": (C.c_int, [C.POINTER(pf_case_desc), C.c_uint64, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -258,10 +279,27 @@ def _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip):
     return d, n, keep
 
 
+def pf_default_schedule(**kw):
+    sc = pf_schedule()
+    _lib.pf_default_schedule(C.byref(sc))
+    for k, v in kw.items():
+        if not hasattr(sc, k):
+            raise TypeError(f"unknown schedule field {k}")
+        setattr(sc, k, v)
+    return sc
+
+
 def pf_create(ctx, model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None, q_sp=None,
-              zip=None):
-    """Create a case from host arrays (Ybus CSR with complex values ``y``)."""
+              zip=None, schedule=None):
+    """Create a case from host arrays (Ybus CSR with complex values ``y``);
+    ``schedule`` (a pf_schedule) selects pf_create_scheduled."""
     d, n, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
+    if schedule is not None:
+        h = _P()
+        _check(_lib.pf_create_scheduled(ctx.handle, C.byref(d), C.byref(schedule), C.byref(h)),
+               "pf_create_scheduled")
+        del keep
+        return Case(ctx, h, n, model)
     h = C.c_void_p()
     _check(_lib.pf_create(ctx.handle, C.byref(d), C.byref(h)), "pf_create")
     del keep
@@ -280,13 +318,14 @@ def case_arrays(case):
 
 
 def pf_debug_schedule_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None,
-                            q_sp=None, zip=None, seed=0):
+                            q_sp=None, zip=None, seed=0, schedule=None):
     """Host-only replay of the analysis schedule (include/pf_debug.h).
     Returns (relative residual, number of index checks)."""
     d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
     res = C.c_double()
     chk = C.c_int64()
-    _check(_lib.pf_debug_schedule_check(C.byref(d), C.c_uint64(seed), C.byref(res), C.byref(chk)),
+    sp_ = C.byref(schedule) if schedule is not None else None
+    _check(_lib.pf_debug_schedule_check(C.byref(d), sp_, C.c_uint64(seed), C.byref(res), C.byref(chk)),
            "pf_debug_schedule_check")
     del keep
     return res.value, chk.value
@@ -306,9 +345,28 @@ def pf_debug_krylov_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_
     return dev.value, res.value, chk.value
 
 
-def pf_create_from(ctx, case):
+def pf_create_from(ctx, case, schedule=None):
     """Convenience: create from a seeded grid object (single-phase or feeder)."""
-    return pf_create(ctx, **case_arrays(case))
+    return pf_create(ctx, **case_arrays(case), schedule=schedule)
+
+
+def pf_case_schedule(case):
+    sc = pf_schedule()
+    _check(_lib.pf_case_schedule(case.handle, C.byref(sc)), "pf_case_schedule")
+    return sc
+
+
+def pf_autotune(ctx, case, options=None, trials=3, **kw):
+    """Autotune the schedule of a seeded grid object's topology (stored in the
+    context for later pf_create calls).  Returns (pf_schedule, report dict)."""
+    o = options if options is not None else pf_default_options(**kw)
+    d, _, keep = _desc(**case_arrays(case))
+    best = pf_schedule()
+    rep = pf_tune_report()
+    _check(_lib.pf_autotune(ctx.handle, C.byref(d), C.byref(o), int(trials), C.byref(best), C.byref(rep)),
+           "pf_autotune")
+    del keep
+    return best, rep.as_dict()
 
 
 def pf_destroy(case):

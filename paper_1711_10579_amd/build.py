@@ -28,6 +28,7 @@ SOURCES = [
     "krylov_analysis.cpp",
     "nk.cpp",
     "krylov_check.cpp",
+    "tune.cpp",
     "kernels.hip",
     "dense.hip",
     "krylov.hip",

@@ -284,14 +284,35 @@ void pf_ctx_destroy(pf_ctx* ctx) {
   delete ctx;
 }
 
-pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
-  if (!ctx || !out) {
-    set_error("pf_create: NULL context or out");
-    return PF_E_INVALID;
-  }
+}  // extern "C"
+
+namespace pfi {
+
+bool valid_schedule(const pf_schedule& s) {
+  return s.dense_switch > 0 && s.dense_switch <= 1 && s.min_dense >= 1 &&
+         (s.lane_scale == 1 || s.lane_scale == 2 || s.lane_scale == 4) && s.trsv_mode >= 0 && s.trsv_mode <= 2;
+}
+
+uint64_t topology_hash(const pf_case_desc* d) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  auto mix = [&](const void* p, size_t bytes) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < bytes; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(&d->model, sizeof d->model);
+  mix(&d->n, sizeof d->n);
+  mix(&d->nnz, sizeof d->nnz);
+  mix(d->row_ptr, sizeof(int32_t) * ((size_t)d->n + 1));
+  mix(d->col_idx, sizeof(int32_t) * (size_t)d->nnz);
+  mix(d->bus_type, (size_t)d->n);
+  return h;
+}
+
+pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched, Case** out) {
   *out = nullptr;
-  pf_status st = validate_desc(d);
-  if (st != PF_OK) return st;
   PF_HIP(hipSetDevice(ctx->device));
   auto t0 = std::chrono::steady_clock::now();
   const int n = d->n, nnz = d->nnz;
@@ -309,8 +330,9 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->model = d->model;
   c->n = n;
   c->nnz = nnz;
+  c->sched = sched;
   try {
-    c->an = pfh::analyze(g, 0.5, 32, 64);
+    c->an = pfh::analyze(g, sched.dense_switch, sched.min_dense, 64);
   } catch (const std::exception& ex) {
     delete c;
     set_error(std::string("pf_create: analysis failed: ") + ex.what());
@@ -324,10 +346,10 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->M = 2 * an.nt;
   c->type.assign(d->bus_type, d->bus_type + n);
   {
-    auto pick = [](int64_t m) {
+    auto pick = [&](int64_t m) {
       int g = 1;
       while (g < 64 && 4LL * g < m) g *= 2;
-      return g;
+      return std::min(64, g * sched.lane_scale);
     };
     c->fac_g.resize(c->nlev);
     c->fwd_g.resize(c->nlev);
@@ -585,6 +607,69 @@ pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
   c->analysis_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   ctx->ncases++;
   *out = c;
+  return PF_OK;
+}
+
+}  // namespace pfi
+
+extern "C" {
+
+void pf_default_schedule(pf_schedule* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof *s);
+  s->dense_switch = 0.5;
+  s->min_dense = 32;
+  s->lane_scale = 1;
+  s->trsv_mode = 0;
+}
+
+pf_status pf_create_scheduled(pf_ctx* ctx, const pf_case_desc* d, const pf_schedule* sched, pf_case** out) {
+  if (!ctx || !out || !sched) {
+    set_error("pf_create_scheduled: NULL argument");
+    return PF_E_INVALID;
+  }
+  *out = nullptr;
+  if (!valid_schedule(*sched)) {
+    set_error("pf_create_scheduled: schedule out of range");
+    return PF_E_INVALID;
+  }
+  pf_status st = validate_desc(d);
+  if (st != PF_OK) return st;
+  Case* c = nullptr;
+  st = create_case(ctx, d, *sched, &c);
+  *out = static_cast<pf_case*>(c);
+  return st;
+}
+
+pf_status pf_create(pf_ctx* ctx, const pf_case_desc* d, pf_case** out) {
+  if (!ctx || !out) {
+    set_error("pf_create: NULL context or out");
+    return PF_E_INVALID;
+  }
+  *out = nullptr;
+  pf_status st = validate_desc(d);
+  if (st != PF_OK) return st;
+  pf_schedule sc;
+  pf_default_schedule(&sc);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    if (!ctx->tuned.empty()) {
+      auto it = ctx->tuned.find(topology_hash(d));
+      if (it != ctx->tuned.end()) sc = it->second;
+    }
+  }
+  Case* c = nullptr;
+  st = create_case(ctx, d, sc, &c);
+  *out = static_cast<pf_case*>(c);
+  return st;
+}
+
+pf_status pf_case_schedule(const pf_case* c, pf_schedule* out) {
+  if (!c || !out) {
+    set_error("pf_case_schedule: NULL argument");
+    return PF_E_INVALID;
+  }
+  *out = c->sched;
   return PF_OK;
 }
 

@@ -39,10 +39,17 @@ void req(bool ok, const char* what) {
 
 }  // namespace
 
-extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, uint64_t seed, double* rel_residual,
-                                             int64_t* checks) {
+extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, const pf_schedule* sched, uint64_t seed,
+                                             double* rel_residual, int64_t* checks) {
   if (!rel_residual || !checks) {
     set_error("pf_debug_schedule_check: NULL output");
+    return PF_E_INVALID;
+  }
+  pf_schedule sc;
+  pf_default_schedule(&sc);
+  if (sched) sc = *sched;
+  if (!valid_schedule(sc)) {
+    set_error("pf_debug_schedule_check: schedule out of range");
     return PF_E_INVALID;
   }
   pf_status st = validate_desc(d);
@@ -59,7 +66,7 @@ extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, uint64_t see
       for (int q = d->row_ptr[i]; q < d->row_ptr[i + 1]; ++q)
         if (d->col_idx[q] != i) g.adj[i].push_back(d->col_idx[q]);
     }
-    pfh::Analysis an = pfh::analyze(g, 0.5, 32, 64);
+    pfh::Analysis an = pfh::analyze(g, sc.dense_switch, sc.min_dense, 64);
     std::vector<int> yrow, jmap;
     pfh::build_jmap(an, n, d->row_ptr, d->col_idx, &yrow, &jmap);
     const int ns = an.ns, nt = an.nt, nu = an.nu, M = 2 * nt, ldt = an.ldt;

@@ -45,6 +45,8 @@ struct Ctx {
   std::atomic<int> ncases{0};
   std::shared_ptr<Server> server;  // created by serve.cpp (complete type there)
   std::mutex launch_mu;  // serialises launches of the serving thread and callers
+  std::mutex tune_mu;
+  std::map<uint64_t, pf_schedule> tuned;  // topology hash -> autotuned schedule
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -64,6 +66,7 @@ struct Case {
   int ntt = 0;
   int M = 0;  // order of the dense block (2 nt)
   double analysis_ms = 0;
+  pf_schedule sched;
   std::atomic<int> busy{0};
 
   // host copies of set-points (for pf_set_injections and the case info)
@@ -171,6 +174,11 @@ struct Prof {
 // when m grows); false on failure with the error set.
 bool ensure_krylov(Case* c, int m);
 void free_krylov(Case* c);
+// Case creation under a schedule (api.cpp), the schedule's validation and
+// the topology hash that keys the autotuner's choices.
+pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched, Case** out);
+bool valid_schedule(const pf_schedule& s);
+uint64_t topology_hash(const pf_case_desc* d);
 // Validation of solve options (PF_E_INVALID with the error set).
 pf_status check_opts(const pf_options* opt);
 // The Newton step's linear solve by GMRES and the voltage update.

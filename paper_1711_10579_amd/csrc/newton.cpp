@@ -133,7 +133,10 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   {
     int total = 0;
     for (Case* c : cs) total += c->M > 0 ? c->nblk() : 0;
-    trsv_single = total > 1024 ? 1 : 0;
+    int mode = cs.empty() ? 0 : cs[0]->sched.trsv_mode;
+    for (Case* c : cs)
+      if (c->sched.trsv_mode != mode) mode = 0;
+    trsv_single = mode == 1 ? 0 : mode == 2 ? 1 : (total > 1024 ? 1 : 0);
     std::vector<int2> tr;
     double tfl = 0, tby = 0;
     for (int s = 0; s < nslots; ++s) {

@@ -63,6 +63,27 @@ def test_schedule_replay(name, maker):
     assert res < 1e-13
 
 
+@pytest.mark.parametrize("ds,md", [(0.3, 32), (0.8, 32), (1.0, 1), (0.5, 1000000)],
+                         ids=["switch0.3", "switch0.8", "switch1", "no_dense"])
+@pytest.mark.parametrize("name", ["grid257", "grid1000", "grid10k", "feeder2k", "dense_small"])
+def test_schedule_replay_under_other_schedules(name, ds, md):
+    # every schedule the autotuner may choose gives a valid analysis
+    c = dict(CASES)[name]()
+    sc = B.pf_default_schedule(dense_switch=ds, min_dense=md)
+    res, checks = B.pf_debug_schedule_check(**B.case_arrays(c), seed=3, schedule=sc)
+    assert checks > 0
+    assert res < 1e-12
+
+
+@pytest.mark.parametrize("bad", [dict(dense_switch=0.0), dict(dense_switch=1.5), dict(min_dense=0),
+                                 dict(lane_scale=3), dict(trsv_mode=3)])
+def test_schedule_validation(bad):
+    sc = B.pf_default_schedule(**bad)
+    with pytest.raises(B.PFError) as ei:
+        B.pf_debug_schedule_check(**B.case_arrays(pfgen.config_case(0)), schedule=sc)
+    assert ei.value.code == B.PF_E_INVALID
+
+
 @pytest.mark.parametrize("name,maker", CASES, ids=[c[0] for c in CASES])
 def test_krylov_analysis_replay(name, maker):
     # every index of the Newton-Krylov analysis, and block ILU(0) through its
