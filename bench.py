@@ -149,10 +149,17 @@ def bench_grid10k(args):
 
     case = pfgen.config_case(1)
     ctx = B.pf_ctx_create(0)
-    h = B.pf_create_from(ctx, case)
-    info = B.pf_case_info_get(h)
     mixed = args.precision == "mixed"
     opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
+    # the autotuner picks this topology's schedule (set-up, outside the timed
+    # region); pf_create then uses it
+    tuned = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, rep = B.pf_autotune(ctx, case, opts, trials=3)
+        tuned = {"schedule": best.as_dict(), "report": rep, "tune_s": time.perf_counter() - t0}
+    h = B.pf_create_from(ctx, case)
+    info = B.pf_case_info_get(h)
 
     for _ in range(args.warmup):
         r = B.pf_solve(h, opts)
@@ -273,6 +280,7 @@ def bench_grid10k(args):
                                     "k_dense_gemm (matrix-core trailing update of the dense block)"),
         "batched": batched,
         "newton_krylov": nk,
+        "autotune": tuned,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
@@ -421,6 +429,8 @@ def main():
     ap.add_argument("--breakdown", action="store_true",
                     help="time every kernel class in an extra untimed pass (stderr)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default schedule instead of the autotuned one")
     ap.add_argument("--nk-steps", type=int, default=10,
                     help="solves of the Newton-Krylov (GMRES + ILU(0)) leg on the same grid")
     ap.add_argument("--batch", type=int, default=16,

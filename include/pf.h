@@ -196,6 +196,11 @@ pf_status pf_ctx_create(int32_t device, void* hip_stream, pf_alloc_fn alloc, pf_
                         void* user, pf_ctx** out);
 /* Destroy a context; all its cases must have been destroyed. */
 void pf_ctx_destroy(pf_ctx* ctx);
+/* Replay the LU Newton step of reused batches (repeated pf_solve of a case,
+ * repeated pf_solve_batch over the same cases) from a captured HIP graph:
+ * on (default) or off.  Results are identical either way; graphs are not used
+ * while kernel timing (pf_profile_enable) is on. */
+pf_status pf_ctx_use_graphs(pf_ctx* ctx, int32_t on);
 
 /* Validate a case, run the host symbolic analysis (ordering, symbolic LU,
  * levels, maps) and upload everything to the device (eq. 1-3 input, Sec.
@@ -237,7 +242,9 @@ pf_status pf_solve(pf_case* c, const pf_options* opt, pf_result* res);
 /* Solve `count` cases of one context together: every Newton phase runs as one
  * batched launch over all still-active instances; converged instances are
  * masked on the device.  results[i] belongs to cases[i].  Each instance's
- * arithmetic is identical to pf_solve of that case alone. */
+ * arithmetic is identical to pf_solve of that case alone.  The launch plan of
+ * a call is kept for the next calls over the same cases (a few plans per
+ * context; destroying a case drops the plans that hold it). */
 pf_status pf_solve_batch(pf_ctx* ctx, pf_case* const* cases, int32_t count, const pf_options* opt,
                          pf_result* results);
 

@@ -121,6 +121,7 @@ _sig = {
     "pf_ctx_destroy": (None, [_P]),
     "pf_create": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(_P)]),
     "pf_default_schedule": (None, [C.POINTER(pf_schedule)]),
+    "pf_ctx_use_graphs": (C.c_int, [_P, C.c_int32]),
     "pf_create_scheduled": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(pf_schedule), C.POINTER(_P)]),
     "pf_case_schedule": (C.c_int, [_P, C.POINTER(pf_schedule)]),
     "pf_autotune": (C.c_int, [_P, C.POINTER(pf_case_desc), C.POINTER(pf_options), C.c_int32,
@@ -277,6 +278,10 @@ def _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip):
                      zip=_dptr(zp))
     keep = (rp, ci, yv, bt, vm, va, ps, qs, zp)
     return d, n, keep
+
+
+def pf_ctx_use_graphs(ctx, on):
+    _check(_lib.pf_ctx_use_graphs(ctx.handle, int(bool(on))), "pf_ctx_use_graphs")
 
 
 def pf_default_schedule(**kw):

@@ -278,10 +278,22 @@ void pf_ctx_destroy(pf_ctx* ctx) {
   if (!ctx) return;
   pf_serve_shutdown(ctx);
   (void)hipStreamSynchronize(ctx->stream);
+  for (Batch* b : ctx->bcache) delete b;
+  ctx->bcache.clear();
   ctx->prof_flush();
   for (auto e : ctx->evpool) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
+}
+
+pf_status pf_ctx_use_graphs(pf_ctx* ctx, int32_t on) {
+  if (!ctx) {
+    set_error("pf_ctx_use_graphs: NULL context");
+    return PF_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(ctx->launch_mu);
+  ctx->use_graphs = on != 0;
+  return PF_OK;
 }
 
 }  // extern "C"
@@ -680,6 +692,19 @@ pf_status pf_destroy(pf_case* c) {
     return PF_E_BUSY;
   }
   (void)hipStreamSynchronize(c->ctx->stream);
+  {
+    // cached batches that hold the case go with it
+    std::lock_guard<std::mutex> lk(c->ctx->launch_mu);
+    auto& bc = c->ctx->bcache;
+    for (size_t i = 0; i < bc.size();) {
+      if (std::find(bc[i]->cases.begin(), bc[i]->cases.end(), static_cast<Case*>(c)) != bc[i]->cases.end()) {
+        delete bc[i];
+        bc.erase(bc.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
   delete c->single;
   c->single = nullptr;
   free_krylov(c);

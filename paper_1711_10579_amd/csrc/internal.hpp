@@ -47,6 +47,8 @@ struct Ctx {
   std::mutex launch_mu;  // serialises launches of the serving thread and callers
   std::mutex tune_mu;
   std::map<uint64_t, pf_schedule> tuned;  // topology hash -> autotuned schedule
+  bool use_graphs = true;                 // replay reused batches' Newton steps from HIP graphs
+  std::vector<Batch*> bcache;             // batches of recent pf_solve_batch calls, newest first
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -143,6 +145,16 @@ struct Batch {
   // Krylov launch lists (built on the first Krylov step of the batch): rows
   // by ILU level (factor and forward solve), by backward level, and the
   // block-Jacobi blocks, as (offset, count) ranges of d_kwork
+  // the Newton step of the LU inner solve captured as a HIP graph, per
+  // precision, with the convergence-test options baked into it
+  bool allow_graph = false;
+  bool graph_failed = false;
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    double tol = 0;
+    int max_iter = -1;
+  } graphs[2];
+
   bool kbuilt = false;
   char* kmem = nullptr;
   int2* d_kwork = nullptr;

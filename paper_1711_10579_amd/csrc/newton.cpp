@@ -28,6 +28,8 @@ Batch::~Batch() {
     if (dmem) ctx->dfree(dmem);
     if (kmem) ctx->dfree(kmem);
   }
+  for (auto& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
 }
 
 bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
@@ -288,21 +290,67 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
 
 // One Newton step of every active instance: linear solve, update, mismatch
 // and the convergence test.
-pf_status step_batch(Batch* b, const pf_options* opt) {
+static void enqueue_lu_step(Batch* b, const pf_options* opt) {
   hipStream_t s = b->ctx->stream;
-  if (opt->solver == PF_SOLVER_GMRES) {
-    pf_status st = nk_step(b, opt);
-    if (st != PF_OK) return st;
-  } else if (opt->precision == PF_PREC_MIXED) {
+  if (opt->precision == PF_PREC_MIXED)
     lu_solve<float>(b);
-  } else {
+  else
     lu_solve<double>(b);
-  }
   {
     Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
     pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
   }
   pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
+}
+
+// The LU Newton step of a reused batch as a HIP graph: captured on first use
+// (kernels only), then replayed.  Off while kernel timing is on.
+static bool graph_step(Batch* b, const pf_options* opt) {
+  Ctx* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  if (!b->allow_graph || b->graph_failed || !ctx->use_graphs || ctx->profile_mask != 0 || s == nullptr)
+    return false;
+  Batch::Graph& g = b->graphs[opt->precision == PF_PREC_MIXED ? 1 : 0];
+  if (g.exec && (g.tol != opt->tol || g.max_iter != opt->max_iter)) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+  if (!g.exec) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      b->graph_failed = true;
+      return false;
+    }
+    enqueue_lu_step(b, opt);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || !graph || hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      g.exec = nullptr;
+      b->graph_failed = true;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (b->graph_failed) {
+      (void)hipGetLastError();
+      return false;
+    }
+    g.tol = opt->tol;
+    g.max_iter = opt->max_iter;
+  }
+  return hipGraphLaunch(g.exec, s) == hipSuccess;
+}
+
+pf_status step_batch(Batch* b, const pf_options* opt) {
+  if (opt->solver == PF_SOLVER_GMRES) {
+    pf_status st = nk_step(b, opt);
+    if (st != PF_OK) return st;
+    {
+      Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
+      pfd::launch_mismatch(b->ctx->stream, b->d_insts, b->nslots, b->max_n);
+    }
+    pfd::launch_decide(b->ctx->stream, b->d_insts, b->nslots, dev_opts(opt));
+  } else if (!graph_step(b, opt)) {
+    enqueue_lu_step(b, opt);
+  }
   return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
 }
 
@@ -378,6 +426,7 @@ pf_status solve_case(Case* c, const pf_options* opt, pf_result* res) {
       set_error("pf_solve: batch set-up failed");
       return PF_E_NOMEM;
     }
+    b->allow_graph = true;
     c->single = b;
   }
   return run_batch(c->single, opt, res);

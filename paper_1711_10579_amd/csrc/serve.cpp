@@ -19,6 +19,8 @@ namespace pfi {
 
 namespace {
 
+constexpr size_t kBatchCache = 4;  // batches of recent pf_solve_batch calls kept
+
 struct Request {
   uint64_t ticket;
   Case* c;
@@ -208,12 +210,30 @@ pf_status pf_solve_batch(pf_ctx* ctx, pf_case* const* cases, int32_t count, cons
   }
   if (count == 0) return PF_OK;
   std::lock_guard<std::mutex> lk(ctx->launch_mu);
-  Batch b;
-  if (!b.build(ctx, cs)) {
-    set_error("pf_solve_batch: batch set-up failed");
-    return PF_E_NOMEM;
+  // reuse the batch of an earlier call over the same cases (its work lists,
+  // Krylov lists and captured graphs), else build one and keep it
+  Batch* b = nullptr;
+  for (size_t i = 0; i < ctx->bcache.size(); ++i)
+    if (ctx->bcache[i]->cases == cs) {
+      b = ctx->bcache[i];
+      ctx->bcache.erase(ctx->bcache.begin() + i);
+      break;
+    }
+  if (!b) {
+    b = new Batch();
+    if (!b->build(ctx, cs)) {
+      delete b;
+      set_error("pf_solve_batch: batch set-up failed");
+      return PF_E_NOMEM;
+    }
+    b->allow_graph = true;
   }
-  return run_batch(&b, &o, results);
+  ctx->bcache.insert(ctx->bcache.begin(), b);
+  while (ctx->bcache.size() > kBatchCache) {
+    delete ctx->bcache.back();
+    ctx->bcache.pop_back();
+  }
+  return run_batch(b, &o, results);
 }
 
 pf_status pf_serve_config(pf_ctx* ctx, size_t max_bytes, int32_t max_slots) {

@@ -193,3 +193,39 @@ def test_destroy_of_queued_case_is_busy(B, ctx):
         time.sleep(0.001)
     assert r.status == 0
     h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_graph_replays_match_eager(B, ctx, precision):
+    # the captured Newton step replayed over several solves, with eager work
+    # and synchronisations in between, gives the eager results bit for bit
+    cases = _mix()[:6]
+    hs = [B.pf_create_from(ctx, c) for c in cases]
+    opts = dict(precision=precision, max_iter=40 if precision else 20)
+    _say(f"graphs precision={precision}")
+    B.pf_ctx_use_graphs(ctx, 0)
+    eager = []
+    for h in hs:
+        r = B.pf_solve(h, **opts)
+        eager.append((r.status, r.iters, B.pf_get_voltage(h)))
+    eager_batch = [(r.status, r.iters) for r in B.pf_solve_batch(ctx, hs, **opts)]
+    eager_batch_v = [B.pf_get_voltage(h) for h in hs]
+    B.pf_ctx_use_graphs(ctx, 1)
+    for rep in range(3):
+        for h, (st, it, v) in zip(hs, eager):
+            r = B.pf_solve(h, **opts)
+            assert (r.status, r.iters) == (st, it)
+            assert np.array_equal(B.pf_get_voltage(h), v)
+        # eager work between replays: a solve of another case with graphs off
+        B.pf_ctx_use_graphs(ctx, 0)
+        B.pf_solve(hs[0], tol=1e-6)
+        B.pf_ctx_use_graphs(ctx, 1)
+        res = B.pf_solve_batch(ctx, hs, **opts)
+        assert [(r.status, r.iters) for r in res] == eager_batch
+        for h, v in zip(hs, eager_batch_v):
+            assert np.array_equal(B.pf_get_voltage(h), v)
+    # a different tolerance is captured anew
+    r = B.pf_solve(hs[1], tol=1e-6, **{k: v for k, v in opts.items()})
+    assert r.status == 0 and r.mismatch_inf <= 1e-6
+    for h in hs:
+        h.close()
