@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 # MI355X peaks: HBM 8 TB/s; FP64 vector and FP64 matrix 78.6 TFLOP/s (vector:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz); FP32 matrix 157.3 TFLOP/s
-# (FP32 vector is 78.6 without packed FP32, which this build does not use)
+# (FP32 vector is 78.6 without packed FP32, which this build does not use).
+# The dominant kernel's flops are mostly its matrix-core update; its time is
+# set by the panel's 64 dependent pivot steps.
 PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_mfma_tflops": 157.3, "fp32_valu_tflops": 78.6}
 METRIC = "converged PF solves/s at 1e-8 pu mismatch, batched vs plain; p50/p99 latency"
 
@@ -67,26 +69,34 @@ def cpu_baseline(case, budget_s=20.0):
                       f"{el:.1f} s, FP64 NumPy/SciPy SuperLU, 1 thread"}
 
 
-def _measured_traffic(kernel):
+def _schedule_key(sc):
+    return (f"dense_switch={sc['dense_switch']:g} min_dense={sc['min_dense']} "
+            f"lane_scale={sc['lane_scale']} trsv_mode={sc['trsv_mode']}")
+
+
+def _measured_traffic(kernel, schedule):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE summary (already scaled by the plain-copy calibration), or None
-    when the kernel source changed since the counters were taken."""
+    when the kernel source or the case's schedule (which sets the dense block's
+    size) differ from those the counters were taken with."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_dense_panel_grid10k_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_grid10k_pmc.md")
     src = os.path.join(ROOT, "paper_1711_10579_amd", "csrc", "dense.hip")
     try:
         text = open(path).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    val, cap = None, None
+    val, cap, sched = None, None, None
     for line in text.splitlines():
         if line.startswith(f"traffic_bytes_per_launch {kernel}:"):
             val = float(line.split(":")[1])
         if line.startswith("dense.hip sha256 prefix at capture:"):
             cap = line.split(":")[1].strip()
-    return val if cap == sha else None
+        if line.startswith("schedule at capture:"):
+            sched = line.split(":", 1)[1].strip()
+    return val if cap == sha and sched == _schedule_key(schedule) else None
 
 
 def _roof(st, bound, peak, unit, kernel):
@@ -154,12 +164,18 @@ def bench_grid10k(args):
     # the autotuner picks this topology's schedule (set-up, outside the timed
     # region); pf_create then uses it
     tuned = None
-    if not args.no_autotune:
+    fixed = None
+    if args.schedule:
+        ds, md, ls, tm = args.schedule.split(",")
+        fixed = B.pf_default_schedule(dense_switch=float(ds), min_dense=int(md), lane_scale=int(ls),
+                                      trsv_mode=int(tm))
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         best, rep = B.pf_autotune(ctx, case, opts, trials=3)
         tuned = {"schedule": best.as_dict(), "report": rep, "tune_s": time.perf_counter() - t0}
-    h = B.pf_create_from(ctx, case)
+    h = B.pf_create_from(ctx, case, schedule=fixed)
     info = B.pf_case_info_get(h)
+    sched = B.pf_case_schedule(h).as_dict()
 
     for _ in range(args.warmup):
         r = B.pf_solve(h, opts)
@@ -269,15 +285,17 @@ def bench_grid10k(args):
                    "buses": case.n, "branches": case.m, "pv_buses": int((case.bus_type == 2).sum()),
                    "solver": "lu", "precision": args.precision,
                    "dense_block": info["n_dense"], "levels": info["levels"],
+                   "schedule": _schedule_key(sched),
                    "newton_iters": int(np.median(iters))},
         "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
         "converged": conv,
         "final_mismatch_oracle": mism,
-        "roofline": dict(_roof(st_dom, "alu", valu_peak, "TFLOP/s",
-                               "k_dense_panel (diagonal-block LU + tile solves of the dense block)"),
-                         traffic=None if mixed else _measured_traffic("k_dense_panel")),
+        "roofline": dict(_roof(st_dom, "mfma", mfma_peak, "TFLOP/s",
+                               "k_dense_panel_gemm (panel of step k: diagonal-block LU + tile solves, "
+                               "beside the matrix-core trailing update of step k-1)"),
+                         traffic=None if mixed else _measured_traffic("k_dense_panel_gemm", sched)),
         "roofline_secondary": _roof(st_sec, "mfma", mfma_peak, "TFLOP/s",
-                                    "k_dense_gemm (matrix-core trailing update of the dense block)"),
+                                    "k_dense_gemm (matrix-core update of the next panel's block row and column)"),
         "batched": batched,
         "newton_krylov": nk,
         "autotune": tuned,
@@ -340,9 +358,12 @@ def bench_served(args):
     pool = pfgen.c4_pool(n_polar=args.pool_polar, n_feeder=args.pool_feeder)
     ctx = B.pf_ctx_create(0)
     reps = 2
+    t0 = time.perf_counter()
     cases = [[B.pf_create_from(ctx, g) for _ in range(reps)] for g in pool]
+    setup_s = time.perf_counter() - t0
     mixed = args.precision != "fp64"
     opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
+    plain = B.pf_default_options(precision=0, max_iter=20)
     rng = random.Random(11)
     n_req = args.requests
     # request stream: 70 % single-phase, 30 % feeders, fresh perturbation each
@@ -359,63 +380,81 @@ def bench_served(args):
         else:
             B.pf_set_injections(h, None, None, p.zip)
 
-    # plain serial baseline: one pf_solve at a time over the same requests
-    t0 = time.perf_counter()
-    serial_lat = []
+    for row in cases:  # warm every case once (device code, cached launch plans)
+        B.pf_solve(row[0], plain)
+    # the plain FP64 one-at-a-time GPU Newton over the same requests: service
+    # times (host clock around each pf_solve, injections included)
+    service, serial_conv = [], 0
     for (g, _), p in zip(reqs, pert):
         h = cases[g][0]
         s0 = time.perf_counter()
         prepare(h, p)
-        B.pf_solve(h, opts)
-        serial_lat.append(time.perf_counter() - s0)
-    serial_el = time.perf_counter() - t0
-    serial_rate = n_req / serial_el
+        r = B.pf_solve(h, plain)
+        service.append(time.perf_counter() - s0)
+        serial_conv += r.status == B.PF_CONVERGED
+    serial_rate = n_req / sum(service)
     lam = args.load_factor * serial_rate if args.rate <= 0 else args.rate
-
-    B.pf_serve_config(ctx, max_bytes=args.max_bytes, max_slots=args.slots)
-    free = {g: list(range(reps)) for g in range(len(pool))}
-    inflight = {}
-    lat, conv, done_n = [], 0, 0
     arrivals = []
     t = 0.0
     for _ in range(n_req):
         t += rng.expovariate(lam)
         arrivals.append(t)
-    waiting = []  # arrived but no free replica yet
-    start = time.perf_counter()
-    nxt = 0
-    while done_n < n_req:
-        now = time.perf_counter() - start
-        while nxt < n_req and arrivals[nxt] <= now:
-            waiting.append(nxt)
-            nxt += 1
-        still = []
-        for k in waiting:
-            g = reqs[k][0]
-            if free[g]:
-                r_ = free[g].pop()
-                h = cases[g][r_]
-                prepare(h, pert[k])
-                inflight[B.pf_submit(ctx, h, opts)] = (k, g, r_)
-            else:
-                still.append(k)
-        waiting = still
-        for tk in list(inflight):
-            d, res = B.pf_poll(ctx, tk)
-            if d:
-                k, g, r_ = inflight.pop(tk)
-                free[g].append(r_)
-                lat.append(time.perf_counter() - start - arrivals[k])
-                conv += res.status == B.PF_CONVERGED
-                done_n += 1
-        time.sleep(0.0002)
-    el = time.perf_counter() - start
+    # that serial server under the same arrivals: FIFO, one solve at a time
+    done_t, q_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        done_t = max(done_t, a) + sv
+        q_lat.append(done_t - a)
+
+    B.pf_serve_config(ctx, max_bytes=args.max_bytes, max_slots=args.slots)
+
+    def run(arr):
+        free = {g: list(range(reps)) for g in range(len(pool))}
+        inflight = {}
+        lat, conv, done_n = [], 0, 0
+        waiting = []  # arrived but no free replica yet
+        start = time.perf_counter()
+        nxt = 0
+        while done_n < n_req:
+            now = time.perf_counter() - start
+            while nxt < n_req and arr[nxt] <= now:
+                waiting.append(nxt)
+                nxt += 1
+            still = []
+            for k in waiting:
+                g = reqs[k][0]
+                if free[g]:
+                    r_ = free[g].pop()
+                    h = cases[g][r_]
+                    prepare(h, pert[k])
+                    inflight[B.pf_submit(ctx, h, opts)] = (k, g, r_)
+                else:
+                    still.append(k)
+            waiting = still
+            for tk in list(inflight):
+                d, res = B.pf_poll(ctx, tk)
+                if d:
+                    k, g, r_ = inflight.pop(tk)
+                    free[g].append(r_)
+                    lat.append(time.perf_counter() - start - arr[k])
+                    conv += res.status == B.PF_CONVERGED
+                    done_n += 1
+            time.sleep(0.0002)
+        return conv, time.perf_counter() - start, lat
+
+    conv, el, lat = run(arrivals)
+    # saturation: every request arrives at once (replicas still bound a grid's
+    # concurrency)
+    sconv, sel, _ = run([0.0] * n_req)
     out = {"mode": "served", "metric": METRIC, "value": conv / el, "unit": "solves/s",
            "requests": n_req, "converged": conv, "arrival_rate_per_s": lam,
            "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
-           "plain_serial": {"value": serial_rate, "latency_ms": {"p50": 1000 * _pct(serial_lat, 50),
-                                                                 "p99": 1000 * _pct(serial_lat, 99)}},
-           "pool": {"single_phase": args.pool_polar, "feeders": args.pool_feeder},
+           "saturation": {"value": sconv / sel, "converged": sconv},
+           "plain_fp64_serial": {"value": serial_rate, "converged": serial_conv,
+                                 "service_ms": {"p50": 1000 * _pct(service, 50), "p99": 1000 * _pct(service, 99)},
+                                 "queued_latency_ms_same_arrivals": {"p50": 1000 * _pct(q_lat, 50),
+                                                                     "p99": 1000 * _pct(q_lat, 99)}},
+           "pool": {"single_phase": args.pool_polar, "feeders": args.pool_feeder, "replicas": reps,
+                    "setup_s": setup_s},
            "slots": args.slots, "precision": args.precision}
     print(json.dumps(out), flush=True)
 
@@ -431,6 +470,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default schedule instead of the autotuned one")
+    ap.add_argument("--schedule", default="",
+                    help="fixed schedule 'dense_switch,min_dense,lane_scale,trsv_mode' (no autotuning)")
     ap.add_argument("--nk-steps", type=int, default=10,
                     help="solves of the Newton-Krylov (GMRES + ILU(0)) leg on the same grid")
     ap.add_argument("--batch", type=int, default=16,

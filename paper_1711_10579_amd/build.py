@@ -29,6 +29,7 @@ SOURCES = [
     "nk.cpp",
     "krylov_check.cpp",
     "tune.cpp",
+    "dense_plan.cpp",
     "kernels.hip",
     "dense.hip",
     "krylov.hip",

@@ -6,9 +6,11 @@
 // along and that column ends up as L^{-1} b.  A backward solve with U
 // finishes the block.
 //
-// Per panel step two launches: the panel kernel (every work-group factors the
+// Per panel step two launches: the panel (every work-group factors the
 // diagonal block in LDS, then solves one 64-row tile of L or one 64-column
-// tile of U) and the trailing update.  Inside a 64x64 tile each of the 256
+// tile of U) together with the previous step's trailing update away from the
+// panel's block row and column, then the update of the next panel's block row
+// and column (look-ahead: the bulk of the update runs beside the next panel).  Inside a 64x64 tile each of the 256
 // threads keeps a 4x4 register block (rows ty+16i, columns tx+16j), and the
 // pivot row / column of each elimination step goes through double-buffered
 // LDS, so one barrier separates consecutive steps.
@@ -89,13 +91,11 @@ __device__ inline void tile_store(const Tile<T>& t, T* A, int ld, int r0, int c0
 // Divisions by U_kk are applied once after the loop (columns of L and of x,
 // rows of Y are not touched after their step).
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
-                                                     int k0) {
+__device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0) {
   __shared__ T row[2][NB], col[2][NB];    // pivot row / column of the block
   __shared__ T trow[2][NB], tcol[2][NB];  // published row / column of the tile
   __shared__ T rdiag[NB];
   __shared__ int bad;
-  const int2 w = work[blockIdx.x];
   const Inst& I = *insts[w.x];
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
@@ -265,6 +265,12 @@ __global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, c
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
+                                                     int k0) {
+  panel_step<T>(insts, work[blockIdx.x], k0);
+}
+
 // Matrix-core 16x16x4 step: D = A B + C on a wave, one value of A and of B per
 // lane (lane l holds A[l%16][l/16] and B[l/16][l%16]).  Element e of lane l
 // of the result is D[row(l, e)][l%16]: row (l/16) + 4e for FP64, 4(l/16) + e
@@ -294,11 +300,9 @@ struct Mfma<float> {
 // steps of 4 (zero-padded past kb).  Both operands sit k-major in LDS so that
 // each quarter-wave reads 16 consecutive values.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, const int2* __restrict__ work,
-                                                    int k0) {
+__device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0) {
   __shared__ T sa[NB][NB + 2];  // [k][row]
   __shared__ T sb[NB][NB + 2];  // [k][col]
-  const int2 wk = work[blockIdx.x];
   const Inst& I = *insts[wk.x];
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
@@ -348,6 +352,26 @@ __global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, co
         if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[bi][bj][e];
       }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, const int2* __restrict__ work,
+                                                    int k0) {
+  gemm_tile<T>(insts, work[blockIdx.x], k0);
+}
+
+// Look-ahead: the panel of step k0 (items [0, npanel)) together with the
+// trailing update of step k0 - 64 outside the block row and column of panel
+// k0 (the other items).  The two touch disjoint tiles: the panel reads and
+// writes only its block row and column, which the previous launch brought up
+// to date; the update writes only tiles right of and below them.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
+                                                          int npanel, int k0) {
+  if ((int)blockIdx.x < npanel)
+    panel_step<T>(insts, work[blockIdx.x], k0);
+  else
+    gemm_tile<T>(insts, work[blockIdx.x], k0 - NB);
 }
 
 // Backward solve U x = z (z in column M, U upper with its diagonal) by 64-row
@@ -449,6 +473,13 @@ void launch_dense_gemm(hipStream_t st, const Inst* const* insts, const int2* wor
 }
 
 template <typename T>
+void launch_dense_panel_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel,
+                             int k0) {
+  if (nwork <= 0) return;
+  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
+}
+
+template <typename T>
 void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int single) {
   if (nwork <= 0) return;
   k_dense_trsv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, single);
@@ -457,6 +488,7 @@ void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* wor
 #define PF_DINST(T)                                                                        \
   template void launch_dense_panel<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
   template void launch_dense_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
+  template void launch_dense_panel_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int, int); \
   template void launch_dense_trsv<T>(hipStream_t, const Inst* const*, const int2*, int, int);
 
 PF_DINST(double)

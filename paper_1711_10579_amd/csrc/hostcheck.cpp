@@ -10,6 +10,9 @@
 // is a test of the host analysis; the solve path never calls it.
 
 #include <algorithm>
+#include <map>
+#include <tuple>
+#include <set>
 #include <cmath>
 #include <cstdint>
 #include <random>
@@ -35,6 +38,98 @@ struct Fail : std::runtime_error {
 
 void req(bool ok, const char* what) {
   if (!ok) throw Fail(what);
+}
+
+// Replays the dense block's launch plan over instances of dense orders Ms
+// on a tile state machine.  Tiles are named by the (row, column) offsets the
+// kernels compute; updates are counted on the 64-aligned block holding a
+// tile's first element (only the last, partial step starts a tile off the
+// grid: its right-hand-side tile, which earlier steps updated as part of the
+// diagonal block).  An aligned block (a, b) needs the trailing updates of
+// steps 0..min(a,b)-1, then panel min(a,b) finishes it.  Every item of a
+// launch is checked against the state before the launch (items of a launch
+// run concurrently): a panel item needs its tile and the diagonal tile
+// updated through the previous step; an update item of step k needs its tile
+// updated through step k-1 and the L and U tiles of panel k finished; no two
+// items of a launch write one tile, and no item reads a tile that another
+// item of the launch writes.  At the end every block must be finished.
+void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
+  typedef std::tuple<int, int, int> Key;  // (slot, row offset, column offset)
+  std::map<Key, int> cnt;                 // aligned blocks -> updates applied
+  std::set<Key> fin;                      // finished tiles
+  auto aligned = [](const Key& k) { return Key(std::get<0>(k), std::get<1>(k) / 64 * 64, std::get<2>(k) / 64 * 64); };
+  const int ns = (int)Ms.size();
+  int maxM = 0;
+  for (int s = 0; s < ns; ++s) maxM = std::max(maxM, Ms[s]);
+  std::vector<int2> comb, next;
+  auto run = [&](const std::vector<int2>& items, int npanel, int k0, int kupd) {
+    std::vector<Key> tile(items.size());
+    std::map<Key, size_t> writer;
+    std::vector<std::vector<Key>> rd(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      const int s = items[i].x;
+      const bool panel = (int)i < npanel;
+      const int k = panel ? k0 : kupd;
+      req(s >= 0 && s < ns && Ms[s] > k, "dense plan: item of a finished instance");
+      int kb, nrt, nct;
+      dense_grid(Ms[s], k, &kb, &nrt, &nct);
+      const int p = k / 64;
+      ++*nchk;
+      bool writes_a = true;
+      if (panel) {
+        const int g = items[i].y;
+        req(g >= 0 && g < 1 + nrt + nct, "dense plan: panel item out of range");
+        const Key d(s, k, k);
+        Key own = d;
+        if (g >= 1 && g <= nrt) own = Key(s, k + kb + 64 * (g - 1), k);
+        if (g > nrt) own = Key(s, k, k + kb + 64 * (g - 1 - nrt));
+        req(std::get<1>(own) < Ms[s] && std::get<2>(own) <= Ms[s], "dense plan: tile out of range");
+        req(cnt[aligned(d)] == p && !fin.count(d), "dense plan: diagonal block not up to date");
+        req(cnt[aligned(own)] == p && !fin.count(own), "dense plan: panel tile not up to date");
+        rd[i] = {d, own};
+        tile[i] = own;
+        writes_a = g != 0;  // the diagonal work-group stores its factor apart
+      } else {
+        const int t = items[i].y;
+        req(t >= 0 && t < nrt * nct, "dense plan: update item out of range");
+        const int r0 = k + kb + 64 * (t % nrt), c0 = k + kb + 64 * (t / nrt);
+        req(r0 < Ms[s] && c0 <= Ms[s] && r0 % 64 == 0 && c0 % 64 == 0, "dense plan: update tile off the grid");
+        const Key x(s, r0, c0), l(s, r0, k), u(s, k, c0);
+        req(cnt[x] == p && !fin.count(x), "dense plan: updated tile not up to date");
+        req(fin.count(l) && fin.count(u), "dense plan: update before its panel");
+        rd[i] = {l, u, x};
+        tile[i] = x;
+      }
+      if (writes_a) req(writer.emplace(tile[i], i).second, "dense plan: two items of a launch write one tile");
+    }
+    for (size_t j = 0; j < items.size(); ++j)
+      for (const Key& r : rd[j]) {
+        auto it = writer.find(r);
+        req(it == writer.end() || it->second == j, "dense plan: an item reads a tile written in its launch");
+      }
+    for (size_t i = 0; i < items.size(); ++i) {
+      if ((int)i < npanel)
+        fin.insert(tile[i]);
+      else
+        cnt[tile[i]] += 1;
+    }
+  };
+  for (int k0 = 0; k0 < maxM; k0 += 64) {
+    int npanel = 0;
+    dense_plan_step(Ms, k0, &comb, &npanel, &next);
+    run(comb, npanel, k0, k0 - 64);
+    run(next, 0, k0, k0);
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int R = (Ms[s] + 63) / 64, C = (Ms[s] + 1 + 63) / 64;
+    for (int a = 0; a < R; ++a)
+      for (int b = 0; b < C; ++b) {
+        const Key x(s, 64 * a, 64 * b);
+        req(fin.count(x) && cnt[x] == std::min(a, b), "dense plan: a block is not finished");
+      }
+    const int kl = (Ms[s] - 1) / 64 * 64;
+    req(fin.count(Key(s, kl, Ms[s])) || Ms[s] % 64 == 0, "dense plan: right-hand side of the last step");
+  }
 }
 
 }  // namespace
@@ -281,6 +376,11 @@ extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, const pf_sch
       bn = std::max(bn, std::fabs(b[i]));
     }
     *rel_residual = rn / (anorm * xn + bn);
+    // the dense block's launch plan, alone and batched with other orders
+    if (M > 0) {
+      check_dense_plan({M}, &nchk);
+      check_dense_plan({M, std::max(1, M / 2), 64, 65, 1, M + 64}, &nchk);
+    }
   } catch (const std::exception& e) {
     set_error(std::string("pf_debug_schedule_check: ") + e.what());
     *checks = nchk;

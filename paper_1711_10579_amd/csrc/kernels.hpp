@@ -39,6 +39,9 @@ void launch_dense_panel(hipStream_t, const Inst* const* insts, const int2* work,
 template <typename T>
 void launch_dense_gemm(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int k0);
 template <typename T>
+void launch_dense_panel_gemm(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int npanel,
+                             int k0);
+template <typename T>
 void launch_dense_trsv(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int single);
 
 // Newton-Krylov inner solve (krylov.hip); mode 0 = Arnoldi step, 1 = end of

@@ -105,29 +105,40 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
     emit(L_SCHUR, PF_K_TAIL_SCHUR, 0, 0, schur, sfl, sby);
   }
-  // dense block: panel + trailing update per 64-wide step
-  for (int k0 = 0; k0 < max_M; k0 += NB) {
-    std::vector<int2> panel, gemm;
-    double pfl = 0, pby = 0, gfl = 0, gby = 0;
-    for (int s = 0; s < nslots; ++s) {
-      Case* c = cs[s];
-      const int M = c->M;
-      if (M <= k0) continue;
-      const int kb = std::min(NB, M - k0);
-      const int nrt = (M - (k0 + kb) + NB - 1) / NB;
-      const int nct = (M + 1 - (k0 + kb) + NB - 1) / NB;
-      for (int g = 0; g < 1 + nrt + nct; ++g) panel.push_back(make_int2(s, g));
-      const double rr = M - (k0 + kb), rc = M + 1 - (k0 + kb);
-      pfl += (2.0 / 3.0) * kb * kb * kb + (double)kb * kb * (rr + rc);
-      pby += 8.0 * (kb * kb + 2.0 * kb * (rr + rc));
-      if (nrt > 0 && nct > 0) {
-        for (int t = 0; t < nrt * nct; ++t) gemm.push_back(make_int2(s, t));
-        gfl += 2.0 * rr * rc * kb;
-        gby += 8.0 * (rr * kb + kb * rc + 2.0 * rr * rc);
+  // dense block, per 64-wide step k0: one launch with the panel of step k0
+  // and the trailing update of step k0 - 64 away from the panel's block row
+  // and column, then the update of the next panel's block row and column
+  // (tiles a = 0 or b = 0 of the step's row x column tile grid)
+  {
+    std::vector<int> Ms(nslots);
+    for (int s = 0; s < nslots; ++s) Ms[s] = cs[s]->M;
+    std::vector<int2> comb, next;
+    for (int k0 = 0; k0 < max_M; k0 += NB) {
+      int npanel = 0;
+      dense_plan_step(Ms, k0, &comb, &npanel, &next);
+      double pfl = 0, pby = 0, gfl = 0, gby = 0, nfl = 0, nby = 0;
+      int kb, nrt, nct;
+      for (int s = 0; s < nslots; ++s) {
+        if (Ms[s] <= k0) continue;
+        dense_grid(Ms[s], k0, &kb, &nrt, &nct);
+        const double rr = Ms[s] - (k0 + kb), rc = Ms[s] + 1 - (k0 + kb);
+        pfl += (2.0 / 3.0) * kb * kb * kb + (double)kb * kb * (rr + rc);
+        pby += 8.0 * (kb * kb + 2.0 * kb * (rr + rc));
       }
+      // update tiles: 2 kb NB^2 flops, read A_ik, A_kj, read+write A_ij
+      for (size_t i = npanel; i < comb.size(); ++i) {
+        dense_grid(Ms[comb[i].x], k0 - NB, &kb, &nrt, &nct);
+        gfl += 2.0 * NB * NB * kb;
+        gby += 8.0 * 4.0 * NB * NB;
+      }
+      for (const int2& it : next) {
+        dense_grid(Ms[it.x], k0, &kb, &nrt, &nct);
+        nfl += 2.0 * NB * NB * kb;
+        nby += 8.0 * 4.0 * NB * NB;
+      }
+      emit(L_PANEL, PF_K_DENSE_PANEL, npanel, k0, comb, pfl + gfl, pby + gby);
+      emit(L_GEMM, PF_K_DENSE_UPDATE, 0, k0, next, nfl, nby);
     }
-    emit(L_PANEL, PF_K_DENSE_PANEL, 0, k0, panel, pfl, pby);
-    emit(L_GEMM, PF_K_DENSE_UPDATE, 0, k0, gemm, gfl, gby);
   }
   // dense backward solve: flag mode while every work-group of the launch is
   // resident at once (256 CUs x 8 work-groups of 4 waves; half of that is
@@ -210,7 +221,7 @@ void lu_solve(Batch* b) {
         pfd::launch_tail_schur<T>(s, I, w, l.count);
         break;
       case L_PANEL:
-        pfd::launch_dense_panel<T>(s, I, w, l.count, l.k0);
+        pfd::launch_dense_panel_gemm<T>(s, I, w, l.count, l.G, l.k0);
         break;
       case L_GEMM:
         pfd::launch_dense_gemm<T>(s, I, w, l.count, l.k0);
