@@ -138,6 +138,8 @@ struct Batch {
   int2* d_work = nullptr;
   pfd::Red* d_reds = nullptr;
   std::vector<Launch> seq;
+  int64_t zero_off = 0;  // zeroing chunks of the factor storage: work items [zero_off, +nzero)
+  int nzero = 0;
   int max_n = 0, max_nnz = 0, max_nu = 0;
   int64_t max_lu = 0, max_tail = 0;
   int trsv_single = 0;

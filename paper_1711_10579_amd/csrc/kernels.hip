@@ -213,24 +213,23 @@ __global__ void k_mismatch(const Inst* const* insts) {
 // ---------------------------------------------------------------------------
 // Jacobian fill into LU storage
 
-template <typename T>
-__global__ void k_zero_lu(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
-  if (inactive(I)) return;
-  T* p = (T*)I.lu;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.lu_count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = T(0);
-}
+// Zero the factor storage by chunks of ZCH values: item (slot, c) clears
+// chunk c of the sparse factor values, item (slot, -1 - c) chunk c of the
+// dense block.  The batch lists each instance's own chunks, so the grid is
+// proportional to the storage actually cleared.
+constexpr int ZCH = 8192;
 
 template <typename T>
-__global__ void k_zero_tail(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+__global__ __launch_bounds__(256) void k_zero_chunks(const Inst* const* insts, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const Inst& I = *insts[w.x];
   if (inactive(I)) return;
-  T* p = (T*)I.tail;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I.tail_count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = T(0);
+  const bool tail = w.y < 0;
+  const int64_t c = tail ? -1 - (int64_t)w.y : (int64_t)w.y;
+  T* p = (T*)(tail ? I.tail : I.lu);
+  const int64_t n = tail ? I.tail_count : I.lu_count;
+  const int64_t b = c * ZCH, e = min(n, b + ZCH);
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) p[i] = T(0);
 }
 
 template <typename T>
@@ -612,13 +611,14 @@ void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int m
 }
 
 template <typename T>
-void launch_fill(hipStream_t st, const Inst* const* insts, int nslots, int max_nu2, int64_t max_lu,
-                 int64_t max_tail, int max_nnz) {
+void launch_fill(hipStream_t st, const Inst* const* insts, int nslots, int max_nu2, const int2* zero_work,
+                 int nzero, int max_nnz) {
   k_copy_rhs<T><<<grid2(max_nu2, nslots), 256, 0, st>>>(insts);
-  k_zero_lu<T><<<grid2(max_lu, nslots, 256, 2048), 256, 0, st>>>(insts);
-  if (max_tail > 0) k_zero_tail<T><<<grid2(max_tail, nslots, 256, 4096), 256, 0, st>>>(insts);
+  if (nzero > 0) k_zero_chunks<T><<<dim3((unsigned)nzero), 256, 0, st>>>(insts, zero_work);
   k_jfill<T><<<grid2(max_nnz, nslots), 256, 0, st>>>(insts);
 }
+
+int zero_chunk_values() { return ZCH; }
 
 template <typename T>
 void launch_kfill(hipStream_t st, const Inst* const* insts, int nslots, int max_nnz, int ilu) {
@@ -668,7 +668,7 @@ void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max
 }
 
 #define PF_INST(T)                                                                                         \
-  template void launch_fill<T>(hipStream_t, const Inst* const*, int, int, int64_t, int64_t, int);          \
+  template void launch_fill<T>(hipStream_t, const Inst* const*, int, int, const int2*, int, int);          \
   template void launch_factor_cols<T>(hipStream_t, const Inst* const*, const int2*, int, int);             \
   template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int);                   \
   template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \

@@ -18,10 +18,12 @@ void launch_mismatch(hipStream_t, const Inst* const* insts, int nslots, int max_
 template <typename T>
 void launch_update(hipStream_t, const Inst* const* insts, int nslots, int max_nu);
 
-// Jacobian fill: RHS copy, zero the factor storage, scatter J
+// Jacobian fill: RHS copy, zero the factor storage (chunk items, see
+// zero_chunk_values), scatter J
 template <typename T>
-void launch_fill(hipStream_t, const Inst* const* insts, int nslots, int max_nu2, int64_t max_lu,
-                 int64_t max_tail, int max_nnz);
+void launch_fill(hipStream_t, const Inst* const* insts, int nslots, int max_nu2, const int2* zero_work, int nzero,
+                 int max_nnz);
+int zero_chunk_values();
 
 // sparse part (work items (slot, column) or (slot, row); G lanes per list)
 template <typename T>

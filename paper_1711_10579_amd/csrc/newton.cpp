@@ -176,6 +176,18 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     for (auto& kv : byG) emit(L_BWD, PF_K_SPARSE_BWD, kv.first, 0, kv.second, 0, 0);
   }
 
+  // zeroing chunks of every instance's factor storage
+  {
+    const int64_t z = pfd::zero_chunk_values();
+    zero_off = (int64_t)work.size();
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      for (int64_t k = 0; k * z < c->lu_count(); ++k) work.push_back(make_int2(s, (int)k));
+      if (c->an.nt > 0)
+        for (int64_t k = 0; k * z < c->tail_count(); ++k) work.push_back(make_int2(s, (int)(-1 - k)));
+    }
+    nzero = (int)((int64_t)work.size() - zero_off);
+  }
   // device buffer: instance table | work items | Red gather
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t b_tab = al(sizeof(void*) * std::max(nslots, 1));
@@ -205,7 +217,7 @@ void lu_solve(Batch* b) {
   const auto* I = b->d_insts;
   {
     Prof p(ctx, PF_K_JFILL, 0.0, 0.0);
-    pfd::launch_fill<T>(s, I, b->nslots, 2 * b->max_nu, b->max_lu, b->max_tail, b->max_nnz);
+    pfd::launch_fill<T>(s, I, b->nslots, 2 * b->max_nu, b->d_work + b->zero_off, b->nzero, b->max_nnz);
   }
   for (const Launch& l : b->seq) {
     Prof p(ctx, l.cls, l.flops, l.bytes * sizeof(T) / 8.0);
