@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "blk.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -48,17 +49,21 @@ struct Tile {
 template <typename T>
 __device__ inline void tile_load(Tile<T>& t, const T* A, int ld, int r0, int c0, int nr, int nc, int tx, int ty,
                                  bool ident_pad) {
+  // every load issued at once (addresses clamped into the tile), then masked
+  const auto G = gp(A);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int r = ty + 16 * i, c = tx + 16 * j;
-      T x = T(0);
-      if (r < nr && c < nc)
-        x = A[(int64_t)(c0 + c) * ld + r0 + r];
-      else if (ident_pad && r == c)
-        x = T(1);
-      t.v[i][j] = x;
+      const int r = ty + 16 * i, c = tx + 16 * j;
+      t.v[i][j] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + r0 + min(r, nr - 1)];
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ty + 16 * i, c = tx + 16 * j;
+      if (!(r < nr && c < nc)) t.v[i][j] = (ident_pad && r == c) ? T(1) : T(0);
     }
 }
 
@@ -76,11 +81,11 @@ __device__ inline void tile_store(const Tile<T>& t, T* A, int ld, int r0, int c0
 // Panel step k0 of every instance in the work list: item (slot, g).
 //
 // Every work-group factors the 64x64 diagonal block A_kk (identity-padded)
-// in registers, one pivot per step: the pivot row and column go through
-// double-buffered LDS, and each element update is one FMA with multipliers
-// and pivot row zeroed outside the active part.  Row k of U and column k of L
-// are final at step k, so in the same step each work-group also advances its
-// own triangular solve:
+// in registers, two pivots per step: the pivot rows and columns go through
+// double-buffered LDS, and each element update is two FMAs with multipliers
+// and pivot rows zeroed outside the active part.  Rows k, k+1 of U and
+// columns k, k+1 of L are final after the step, so in the same step each
+// work-group also advances its own triangular solve:
 //   g = 0:        Y = U^{-T} by forward substitution (U^T Y = I; row k of Y
 //                 is final at step k); the factored block goes to dfac and
 //                 U^{-1} = Y^T to dinvu (the other work-groups still read the
@@ -92,8 +97,9 @@ __device__ inline void tile_store(const Tile<T>& t, T* A, int ld, int r0, int c0
 // rows of Y are not touched after their step).
 template <typename T>
 __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0) {
-  __shared__ T row[2][NB], col[2][NB];    // pivot row / column of the block
-  __shared__ T trow[2][NB], tcol[2][NB];  // published row / column of the tile
+  // rows / columns k and k+1 of the block and of the tile, double-buffered
+  __shared__ T row[2][2][NB], col[2][2][NB];
+  __shared__ T trow[2][2][NB], tcol[2][2][NB];
   __shared__ T rdiag[NB];
   __shared__ int bad;
   const Inst& I = *insts[w.x];
@@ -125,96 +131,144 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     nc = min(NB, M + 1 - c0);
     tile_load(t, A, ld, k0, c0, kb, nc, tx, ty, false);
   }
-  // publish step 0: row/column 0 of the block, row 0 (roles 0, 2) or column 0
-  // (role 1) of the tile
+  // publish rows / columns 0 and 1 of the block, and rows (roles 0, 2) or
+  // columns (role 1) 0 and 1 of the tile
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = ty + 16 * i, c = tx + 16 * j;
-      if (c == 0) col[0][r] = d.v[i][j];
-      if (r == 0) row[0][c] = d.v[i][j];
-      if (role == 1 && c == 0) tcol[0][r] = t.v[i][j];
-      if (role != 1 && r == 0) trow[0][c] = t.v[i][j];
+      if (c < 2) col[0][c][r] = d.v[i][j];
+      if (r < 2) row[0][r][c] = d.v[i][j];
+      if (role == 1 && c < 2) tcol[0][c][r] = t.v[i][j];
+      if (role != 1 && r < 2) trow[0][r][c] = t.v[i][j];
     }
   __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const int b = k & 1, nb = b ^ 1;
-    T rv[4], cv[4], tv[4];
+  // Pivots k and k+1 per step (one barrier per pair).  With a = the block
+  // before step k: l0(r) = a(r,k)/a(k,k), u0(c) = a(k,c) (r, c > k); after
+  // pivot k the row and column k+1 are a'(k+1,c) = a(k+1,c) - l0(k+1) a(k,c)
+  // and a'(r,k+1) = a(r,k+1) - l0(r) a(k,k+1), with pivot a'(k+1,k+1) =
+  // det / a(k,k), det = a(k,k) a(k+1,k+1) - a(k+1,k) a(k,k+1); l1(r) =
+  // a'(r,k+1)/a'(k+1,k+1), u1(c) = a'(k+1,c) (r, c > k+1); the block takes the
+  // rank-2 update a -= l0 u0 + l1 u1.  The two reciprocals 1/a(k,k) and 1/det
+  // are independent.  An odd kb pairs its last pivot with the identity
+  // padding, which leaves everything unchanged.
+  const int kpair = (kb + 1) & ~1;
+  for (int k = 0; k < kpair; k += 2) {
+    const int b = (k >> 1) & 1, nb = b ^ 1;
+    T rv0[4], rv1[4], cv0[4], cv1[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rv[j] = row[b][tx + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) cv[i] = col[b][ty + 16 * i];
-    if (role == 1) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) tv[i] = tcol[b][ty + 16 * i];
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) tv[j] = trow[b][tx + 16 * j];
+    for (int j = 0; j < 4; ++j) {
+      rv0[j] = row[b][0][tx + 16 * j];
+      rv1[j] = row[b][1][tx + 16 * j];
     }
-    T ur[4];
-    if (role == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ur[i] = row[b][ty + 16 * i];
+    for (int i = 0; i < 4; ++i) {
+      cv0[i] = col[b][0][ty + 16 * i];
+      cv1[i] = col[b][1][ty + 16 * i];
     }
-    T piv = row[b][k];
-    if (tid == 0 && (!(piv != T(0)) || !isfinite((double)piv))) bad = 1;
-    piv = (piv != T(0)) ? piv : T(1);
-    const T rinv = fast_recip(piv);
-    if (tid == 0) rdiag[k] = rinv;
-    T l[4], u[4];
+    T a00 = row[b][0][k], a01 = row[b][0][k + 1], a10 = col[b][0][k + 1], a11 = row[b][1][k + 1];
+    const T det = a00 * a11 - a10 * a01;
+    if (tid == 0 && (!(a00 != T(0)) || !isfinite((double)a00) || !(det != T(0)) || !isfinite((double)det)))
+      bad = 1;
+    const T p0 = (a00 != T(0)) ? a00 : T(1);
+    const T dd = (det != T(0)) ? det : T(1);
+    const T rinv0 = fast_recip(p0);
+    const T rinv1 = p0 * fast_recip(dd);
+    if (tid == 0) {
+      rdiag[k] = rinv0;
+      rdiag[k + 1] = rinv1;
+    }
+    const T lk1 = a10 * rinv0;  // l0(k+1)
+    T l0[4], l1[4], u0[4], u1[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) l[i] = (ty + 16 * i > k) ? cv[i] * rinv : T(0);
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 16 * i;
+      l0[i] = r > k ? cv0[i] * rinv0 : T(0);
+      l1[i] = r > k + 1 ? (cv1[i] - l0[i] * a01) * rinv1 : T(0);
+    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) u[j] = (tx + 16 * j > k) ? rv[j] : T(0);
+    for (int j = 0; j < 4; ++j) {
+      const int c = tx + 16 * j;
+      u0[j] = c > k ? rv0[j] : T(0);
+      u1[j] = c > k + 1 ? rv1[j] - lk1 * rv0[j] : T(0);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) d.v[i][j] = fma(-l[i], u[j], d.v[i][j]);
+      for (int j = 0; j < 4; ++j) d.v[i][j] = fma(-l1[i], u1[j], fma(-l0[i], u0[j], d.v[i][j]));
     if (role == 0) {
-      // rows r > k of Y: Y(r,:) -= U(k,r) Y(k,:), Y(k,:) = Yacc(k,:) / U_kk
+      // Y = U^{-T}: rows k, k+1 final (y0 = Y(k,:)/U_kk, y1 = (Y(k+1,:) -
+      // U(k,k+1) y0)/U'_{k+1,k+1}); rows r > k take -U(k,r) y0, rows r > k+1
+      // also -U'(k+1,r) y1
+      T ur0[4], ur1[4], y0[4], y1[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const T m = (ty + 16 * i > k) ? ur[i] : T(0);
+        ur0[i] = row[b][0][ty + 16 * i];
+        ur1[i] = row[b][1][ty + 16 * i];
+      }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-m, tv[j] * rinv, t.v[i][j]);
+      for (int j = 0; j < 4; ++j) {
+        y0[j] = trow[b][0][tx + 16 * j] * rinv0;
+        y1[j] = (trow[b][1][tx + 16 * j] - a01 * y0[j]) * rinv1;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = ty + 16 * i;
+        const T m0 = r > k ? ur0[i] : T(0);
+        const T m1 = r > k + 1 ? ur1[i] - lk1 * ur0[i] : T(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-m1, y1[j], fma(-m0, y0[j], t.v[i][j]));
       }
     } else if (role == 1) {
-      // columns c > k of x: a(:,c) -= x(:,k) U(k,c), x(:,k) = a(:,k) / U_kk
+      // x U = a: x(:,k) = a(:,k)/U_kk, x(:,k+1) = (a(:,k+1) - x(:,k) U(k,k+1))
+      // / U'_{k+1,k+1}; columns c > k take -x(:,k) u0, c > k+1 also -x(:,k+1) u1
+      T x0[4], x1[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const T xk = tv[i] * rinv;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-xk, u[j], t.v[i][j]);
+        x0[i] = tcol[b][0][ty + 16 * i] * rinv0;
+        x1[i] = (tcol[b][1][ty + 16 * i] - x0[i] * a01) * rinv1;
       }
-    } else {
-      // rows r > k of y: a(r,:) -= L(r,k) y(k,:)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-l[i], tv[j], t.v[i][j]);
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-x1[i], u1[j], fma(-x0[i], u0[j], t.v[i][j]));
+    } else {
+      // L y = a: rows r > k take -L(r,k) y(k,:), rows r > k+1 also
+      // -L(r,k+1) y(k+1,:) with y(k+1,:) = a(k+1,:) - L(k+1,k) y(k,:)
+      T y0[4], y1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        y0[j] = trow[b][0][tx + 16 * j];
+        y1[j] = trow[b][1][tx + 16 * j] - lk1 * y0[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-l1[i], y1[j], fma(-l0[i], y0[j], t.v[i][j]));
     }
-    // publish row and column k+1 of the block and of the tile.  Their owners
-    // are the threads with tx (ty) == (k+1) % 16, register column (row)
-    // (k+1) / 16 (uniform); entries outside the active part are stored too:
-    // they are finite and the next step masks them out.
-    const int k1 = k + 1;
-    if (k1 < kb) {
-      const bool own_c = tx == (k1 & 15), own_r = ty == (k1 & 15);
-#define PF_PUB(J)                                                                  \
-  {                                                                                \
-    if (own_c) {                                                                   \
-      for (int i = 0; i < 4; ++i) col[nb][ty + 16 * i] = d.v[i][J];                \
-      if (role == 1)                                                               \
-        for (int i = 0; i < 4; ++i) tcol[nb][ty + 16 * i] = t.v[i][J];             \
-    }                                                                              \
-    if (own_r) {                                                                   \
-      for (int j = 0; j < 4; ++j) row[nb][tx + 16 * j] = d.v[J][j];                \
-      if (role != 1)                                                               \
-        for (int j = 0; j < 4; ++j) trow[nb][tx + 16 * j] = t.v[J][j];             \
-    }                                                                              \
+    // publish rows and columns k+2 and k+3 (same register index (k+2) / 16,
+    // owners tx or ty == (k+2) % 16 and (k+3) % 16)
+    const int k2 = k + 2;
+    if (k2 < kpair) {
+      const int s0 = k2 & 15;
+      const bool c_0 = tx == s0, c_1 = tx == s0 + 1, r_0 = ty == s0, r_1 = ty == s0 + 1;
+#define PF_PUB(J)                                                                           \
+  {                                                                                         \
+    if (c_0 || c_1) {                                                                       \
+      const int q = c_1 ? 1 : 0;                                                            \
+      for (int i = 0; i < 4; ++i) col[nb][q][ty + 16 * i] = d.v[i][J];                     \
+      if (role == 1)                                                                        \
+        for (int i = 0; i < 4; ++i) tcol[nb][q][ty + 16 * i] = t.v[i][J];                   \
+    }                                                                                       \
+    if (r_0 || r_1) {                                                                       \
+      const int q = r_1 ? 1 : 0;                                                            \
+      for (int j = 0; j < 4; ++j) row[nb][q][tx + 16 * j] = d.v[J][j];                      \
+      if (role != 1)                                                                        \
+        for (int j = 0; j < 4; ++j) trow[nb][q][tx + 16 * j] = t.v[J][j];                   \
+    }                                                                                       \
   }
-      switch (k1 >> 4) {
+      switch (k2 >> 4) {
         case 0:
           PF_PUB(0);
           break;
@@ -314,13 +368,35 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   const int c0 = k0 + kb + (wk.y / nrt) * NB;
   const int nr = min(NB, M - r0);
   const int nc = min(NB, M + 1 - c0);
-  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-    int r = idx % NB, k = idx / NB;
-    sa[k][r] = (r < nr && k < kb) ? A[(int64_t)(k0 + k) * ld + r0 + r] : T(0);
-  }
-  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-    int k = idx % NB, c = idx / NB;
-    sb[k][c] = (c < nc && k < kb) ? A[(int64_t)(c0 + c) * ld + k0 + k] : T(0);
+  {
+    // all 32 loads of a thread in flight before the LDS stores (addresses
+    // clamped into the tile, values masked afterwards)
+    const auto G = gp((const T*)A);
+    T va[16], vb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx % NB, k = idx / NB;
+      va[q] = G[(int64_t)(k0 + min(k, kb - 1)) * ld + r0 + min(r, nr - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx % NB, c = idx / NB;
+      vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + k0 + min(k, kb - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx % NB, k = idx / NB;
+      sa[k][r] = (r < nr && k < kb) ? va[q] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx % NB, c = idx / NB;
+      sb[k][c] = (c < nc && k < kb) ? vb[q] : T(0);
+    }
   }
   __syncthreads();
   const int lane = tid % 64, w = tid / 64;
@@ -332,23 +408,27 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{T(0), T(0), T(0), T(0)};
+  // the transposed product (A_ik A_kj)^T = A_kj^T A_ik^T: the matrix core's
+  // first operand is the column block, so a lane's result row is a tile
+  // column and its lane index within 16 a tile row -- consecutive lanes then
+  // update consecutive rows of the column-major tile
 #pragma unroll 4
   for (int ks = 0; ks < NB; ks += 4) {
     T a0 = sa[ks + lk][rb + li], a1 = sa[ks + lk][rb + 16 + li];
     T b0 = sb[ks + lk][cb + li], b1 = sb[ks + lk][cb + 16 + li];
-    acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-    acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-    acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-    acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+    acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
+    acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
+    acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
+    acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const int c = cb + bj * 16 + li;
+      const int r = rb + bi * 16 + li;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = rb + bi * 16 + Mfma<T>::row(lane, e);
+        const int c = cb + bj * 16 + Mfma<T>::row(lane, e);
         if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[bi][bj][e];
       }
     }
