@@ -405,6 +405,61 @@ __device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest,
   return group_sum<T, G>(acc);
 }
 
+// One column per wave (four per work-group) for levels whose columns have at
+// most 64/G targets: the targets of a column then take one pass of the
+// wave's lane groups, and the diagonal inverse goes to the wave by a
+// shuffle instead of a work-group barrier.  Same arithmetic as k_factor_cols.
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* insts, const int2* __restrict__ work,
+                                                          int nwork) {
+  const int item = blockIdx.x * 4 + (int)(threadIdx.x / 64);
+  if (item >= nwork) return;
+  const int2 w = work[item];
+  const Inst& I = *insts[w.x];
+  if (inactive(I)) return;
+  T* lu = (T*)I.lu;
+  const int j = w.y;
+  const int c0 = I.colptr[j];
+  const int len = I.colptr[j + 1] - c0;
+  const int64_t tb = (int64_t)j + 2LL * c0;
+  const int wl = threadIdx.x % 64;
+  const int lane = wl % G, grp = wl / G;
+  constexpr int ngrp = 64 / G;
+  T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+  for (int t = grp; t <= len; t += ngrp) {
+    int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
+    Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
+    if (lane == 0) {
+      st_blk(lu, dest, acc);
+      if (t == 0) {
+        T det = acc.a * acc.d - acc.b * acc.c;
+        bool bad = !(det != T(0)) || !isfinite((double)det);
+        if (bad) {
+          I.red->singular = 1;
+          det = T(1);
+        }
+        T r = T(1) / det;
+        d0 = acc.d * r;
+        d1 = -acc.b * r;
+        d2 = -acc.c * r;
+        d3 = acc.a * r;
+        T* q = (T*)I.dinv + 4 * (int64_t)j;
+        q[0] = d0;
+        q[1] = d1;
+        q[2] = d2;
+        q[3] = d3;
+      }
+    }
+  }
+  // the diagonal target was group 0's first, lane 0 of the wave holds it
+  const Blk<T> di = {__shfl(d0, 0, 64), __shfl(d1, 0, 64), __shfl(d2, 0, 64), __shfl(d3, 0, 64)};
+  for (int t = grp; t < len; t += ngrp) {
+    int64_t dest = (int64_t)I.ns + c0 + t;
+    Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + 1 + len + t, lane);
+    if (lane == 0) st_blk(lu, dest, blk_mul(acc, di));
+  }
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_factor_cols(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ T sdinv[4];
@@ -455,17 +510,22 @@ __global__ __launch_bounds__(256) void k_factor_cols(const Inst* const* insts, c
 // Schur complement of the sparse part into the dense trailing block:
 // T(a,b) -= sum_k L(a,k) U(k,b); work item = (instance, first target of a
 // chunk of 256).
-template <typename T>
-__global__ void k_tail_schur(const Inst* const* insts, const int2* __restrict__ work) {
+template <typename T, int G>
+__global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
   const Inst& I = *insts[w.x];
   if (inactive(I)) return;
-  const int t = w.y + threadIdx.x;
-  if (t >= I.ntt) return;
+  // G lanes per target split its update list (lane-strided, fixed-order tree)
+  const int lane = threadIdx.x % G;
+  const int t = w.y + (int)threadIdx.x / G;
+  const bool live = t < I.ntt;
   const T* lu = (const T*)I.lu;
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  for (int64_t q = I.tail_uptr[t]; q < I.tail_uptr[t + 1]; ++q)
-    blk_msub(acc, ld_blk(lu, I.tail_l[q]), ld_blk(lu, I.tail_u[q]));
+  if (live)
+    for (int64_t q = I.tail_uptr[t] + lane; q < I.tail_uptr[t + 1]; q += G)
+      blk_msub(acc, ld_blk(lu, I.tail_l[q]), ld_blk(lu, I.tail_u[q]));
+  acc = group_sum<T, G>(acc);
+  if (!live || lane != 0) return;
   int g = I.tail_tgt[t];
   int ta = g / I.nt, tb = g - ta * I.nt;
   T* p = (T*)I.tail + (int64_t)(2 * tb) * I.ldt + 2 * ta;
@@ -643,9 +703,15 @@ void launch_factor_cols(hipStream_t st, const Inst* const* insts, const int2* wo
 }
 
 template <typename T>
-void launch_tail_schur(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
+void launch_tail_schur(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
   if (nwork <= 0) return;
-  k_tail_schur<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
+  PF_GSWITCH(G, (k_tail_schur<T, GG><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work)));
+}
+
+template <typename T>
+void launch_factor_cols_wave(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
+  if (nwork <= 0) return;
+  PF_GSWITCH(G, (k_factor_cols_wave<T, GG><<<dim3((unsigned)((nwork + 3) / 4)), 256, 0, st>>>(insts, work, nwork)));
 }
 
 template <typename T>
@@ -670,7 +736,8 @@ void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max
 #define PF_INST(T)                                                                                         \
   template void launch_fill<T>(hipStream_t, const Inst* const*, int, int, const int2*, int, int);          \
   template void launch_factor_cols<T>(hipStream_t, const Inst* const*, const int2*, int, int);             \
-  template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int);                   \
+  template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int, int);              \
+  template void launch_factor_cols_wave<T>(hipStream_t, const Inst* const*, const int2*, int, int);        \
   template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
   template void launch_bwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
   template void launch_update<T>(hipStream_t, const Inst* const*, int, int);                                \

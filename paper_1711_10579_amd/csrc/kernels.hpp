@@ -33,7 +33,10 @@ void launch_fwd_rows(hipStream_t, const Inst* const* insts, const int2* work, in
 template <typename T>
 void launch_bwd_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
 template <typename T>
-void launch_tail_schur(hipStream_t, const Inst* const* insts, const int2* work, int nwork);
+void launch_tail_schur(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
+// one column per wave; for levels whose columns have at most 64/G targets
+template <typename T>
+void launch_factor_cols_wave(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
 
 // dense trailing block
 template <typename T>

@@ -67,43 +67,61 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   }
   // sparse refactorisation and forward solve, level by level, one launch per
   // lane-group size
+  // (factor launches whose columns all fit one wave's lane groups in one
+  // pass run a column per wave: k0 = 1)
   for (int pass = 0; pass < 2; ++pass) {
     for (int l = 0; l < max_lev; ++l) {
       std::map<int, std::vector<int2>> byG;
       std::map<int, double> fl, by;
+      std::map<int, int> maxt;  // most targets (1 + column length) of a column
       for (int s = 0; s < nslots; ++s) {
         Case* c = cs[s];
         if (l >= c->nlev) continue;
         const int G = pass == 0 ? c->fac_g[l] : c->fwd_g[l];
         auto& v = byG[G];
-        for (int k = c->an.col_lev_ptr[l]; k < c->an.col_lev_ptr[l + 1]; ++k) v.push_back(make_int2(s, c->an.col_order[k]));
+        int& mt = maxt[G];
+        for (int k = c->an.col_lev_ptr[l]; k < c->an.col_lev_ptr[l + 1]; ++k) {
+          const int j = c->an.col_order[k];
+          v.push_back(make_int2(s, j));
+          mt = std::max(mt, 1 + c->an.colptr[j + 1] - c->an.colptr[j]);
+        }
         if (pass == 0) {
           fl[G] += c->fac_flops[l];
           by[G] += c->fac_bytes[l];
         }
       }
-      for (auto& kv : byG)
-        emit(pass == 0 ? L_FACTOR : L_FWD, pass == 0 ? PF_K_SPARSE_FACTOR : PF_K_SPARSE_FWD, kv.first, 0, kv.second,
-             fl[kv.first], by[kv.first]);
+      for (auto& kv : byG) {
+        const int wave = pass == 0 && maxt[kv.first] * kv.first <= 64 ? 1 : 0;
+        emit(pass == 0 ? L_FACTOR : L_FWD, pass == 0 ? PF_K_SPARSE_FACTOR : PF_K_SPARSE_FWD, kv.first, wave,
+             kv.second, fl[kv.first], by[kv.first]);
+      }
     }
   }
   // forward rows of the dense block, then the Schur complement into it
   {
     std::map<int, std::vector<int2>> byG;
     std::vector<int2> schur;
-    double sfl = 0, sby = 0;
+    double sfl = 0, sby = 0, nupd_all = 0, ntt_all = 0;
+    for (Case* c : cs) {
+      nupd_all += (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
+      ntt_all += c->ntt;
+    }
+    // lanes per Schur target from the batch's mean update-list length
+    int gs = 1;
+    while (gs < 32 && 4.0 * gs * ntt_all < nupd_all) gs *= 2;
+    const int per_wg = 256 / gs;
     for (int s = 0; s < nslots; ++s) {
       Case* c = cs[s];
       if (c->an.nt == 0) continue;
       auto& v = byG[c->tailfwd_g];
       for (int i = c->an.ns; i < c->an.nu; ++i) v.push_back(make_int2(s, i));
-      for (int t = 0; t < c->ntt; t += 256) schur.push_back(make_int2(s, t));
+      for (int t = 0; t < c->ntt; t += per_wg) schur.push_back(make_int2(s, t));
       double nupd = (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
       sfl += 16.0 * nupd;
       sby += 8.0 * nupd + 64.0 * nupd + 64.0 * c->ntt;
     }
     for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
-    emit(L_SCHUR, PF_K_TAIL_SCHUR, 0, 0, schur, sfl, sby);
+    emit(L_SCHUR, PF_K_TAIL_SCHUR, gs, 0, schur, sfl, sby);
   }
   // dense block, per 64-wide step k0: one launch with the panel of step k0
   // and the trailing update of step k0 - 64 away from the panel's block row
@@ -224,13 +242,16 @@ void lu_solve(Batch* b) {
     const int2* w = b->d_work + l.off;
     switch (l.kind) {
       case L_FACTOR:
-        pfd::launch_factor_cols<T>(s, I, w, l.count, l.G);
+        if (l.k0)
+          pfd::launch_factor_cols_wave<T>(s, I, w, l.count, l.G);
+        else
+          pfd::launch_factor_cols<T>(s, I, w, l.count, l.G);
         break;
       case L_FWD:
         pfd::launch_fwd_rows<T>(s, I, w, l.count, l.G);
         break;
       case L_SCHUR:
-        pfd::launch_tail_schur<T>(s, I, w, l.count);
+        pfd::launch_tail_schur<T>(s, I, w, l.count, l.G);
         break;
       case L_PANEL:
         pfd::launch_dense_panel_gemm<T>(s, I, w, l.count, l.G, l.k0);
