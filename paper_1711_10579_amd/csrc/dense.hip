@@ -486,6 +486,13 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
   for (int b = bfirst; b >= blast; --b) {
     const int b0 = b * NB;
     const int bl = min(NB, M - b0);
+    // this block's U^{-1} entries (independent of the solve): loaded first
+    T uiv[16];
+    {
+      const T* ui = (const T*)I.dinvu + (int64_t)b * NB * NB;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) uiv[q] = ui[(int64_t)(quarter + 4 * q) * NB + lane_r];
+    }
     __syncthreads();
     if (tid < NB) acc[tid] = tid < bl ? A[(int64_t)M * ld + b0 + tid] : T(0);
     __syncthreads();
@@ -500,14 +507,16 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
       }
       if (!single) {
         if (tid == 0) {
+          // poll without ordering, then one acquire once the flag is seen
           long spins = 0;
-          while (__hip_atomic_load(&I.dflags[cb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+          while (__hip_atomic_load(&I.dflags[cb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
             if (++spins > (1l << 24)) {
               abort_flag = 1;
               break;
             }
             __builtin_amdgcn_s_sleep(1);
           }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (abort_flag) break;
@@ -527,9 +536,9 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
       if (tid == 0) I.red->timeout = 1;
       return;
     }
-    const T* ui = (const T*)I.dinvu + (int64_t)b * NB * NB;
     T sum = T(0);
-    for (int c = quarter; c < NB; c += 4) sum += ui[(int64_t)c * NB + lane_r] * acc[c];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sum += uiv[q] * acc[quarter + 4 * q];
     part[quarter][lane_r] = sum;
     __syncthreads();
     if (tid < bl) out[b0 + tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
