@@ -111,25 +111,33 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
   const int g = __builtin_amdgcn_readfirstlane(w.y);
   const int role = g == 0 ? 0 : (g <= nrt ? 1 : 2);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16, tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  if (tid < NB) rdiag[tid] = T(1);
-  Tile<T> d, t;
-  tile_load(d, A, ld, k0, k0, kb, kb, tx, ty, true);
+  // threads 0..255 hold the diagonal block, threads 256..511 the tile (each
+  // a 4x4 register block of rows ty+16i, columns tx+16j)
+  const bool blk = threadIdx.x < 256;
+  const int tid = threadIdx.x & 255;
+  const int tx = tid % 16, ty = tid / 16;
+  if (threadIdx.x == 0) bad = 0;
+  if (threadIdx.x < NB) rdiag[threadIdx.x] = T(1);
+  Tile<T> v;
   int r0 = 0, c0 = 0, nr = 0, nc = 0;
-  if (role == 0) {
+  if (role == 1) {
+    r0 = k0 + kb + (g - 1) * NB;
+    nr = min(NB, M - r0);
+  } else if (role == 2) {
+    c0 = k0 + kb + (g - 1 - nrt) * NB;
+    nc = min(NB, M + 1 - c0);
+  }
+  if (blk) {
+    tile_load(v, A, ld, k0, k0, kb, kb, tx, ty, true);
+  } else if (role == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) t.v[i][j] = (ty + 16 * i == tx + 16 * j) ? T(1) : T(0);
+      for (int j = 0; j < 4; ++j) v.v[i][j] = (ty + 16 * i == tx + 16 * j) ? T(1) : T(0);
   } else if (role == 1) {
-    r0 = k0 + kb + (g - 1) * NB;
-    nr = min(NB, M - r0);
-    tile_load(t, A, ld, r0, k0, nr, kb, tx, ty, false);
+    tile_load(v, A, ld, r0, k0, nr, kb, tx, ty, false);
   } else {
-    c0 = k0 + kb + (g - 1 - nrt) * NB;
-    nc = min(NB, M + 1 - c0);
-    tile_load(t, A, ld, k0, c0, kb, nc, tx, ty, false);
+    tile_load(v, A, ld, k0, c0, kb, nc, tx, ty, false);
   }
   // publish rows / columns 0 and 1 of the block, and rows (roles 0, 2) or
   // columns (role 1) 0 and 1 of the tile
@@ -138,10 +146,13 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r = ty + 16 * i, c = tx + 16 * j;
-      if (c < 2) col[0][c][r] = d.v[i][j];
-      if (r < 2) row[0][r][c] = d.v[i][j];
-      if (role == 1 && c < 2) tcol[0][c][r] = t.v[i][j];
-      if (role != 1 && r < 2) trow[0][r][c] = t.v[i][j];
+      if (blk) {
+        if (c < 2) col[0][c][r] = v.v[i][j];
+        if (r < 2) row[0][r][c] = v.v[i][j];
+      } else {
+        if (role == 1 && c < 2) tcol[0][c][r] = v.v[i][j];
+        if (role != 1 && r < 2) trow[0][r][c] = v.v[i][j];
+      }
     }
   __syncthreads();
   // Pivots k and k+1 per step (one barrier per pair).  With a = the block
@@ -156,57 +167,50 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   const int kpair = (kb + 1) & ~1;
   for (int k = 0; k < kpair; k += 2) {
     const int b = (k >> 1) & 1, nb = b ^ 1;
-    T rv0[4], rv1[4], cv0[4], cv1[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      rv0[j] = row[b][0][tx + 16 * j];
-      rv1[j] = row[b][1][tx + 16 * j];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cv0[i] = col[b][0][ty + 16 * i];
-      cv1[i] = col[b][1][ty + 16 * i];
-    }
-    T a00 = row[b][0][k], a01 = row[b][0][k + 1], a10 = col[b][0][k + 1], a11 = row[b][1][k + 1];
+    const T a00 = row[b][0][k], a01 = row[b][0][k + 1], a10 = col[b][0][k + 1], a11 = row[b][1][k + 1];
     const T det = a00 * a11 - a10 * a01;
-    if (tid == 0 && (!(a00 != T(0)) || !isfinite((double)a00) || !(det != T(0)) || !isfinite((double)det)))
-      bad = 1;
     const T p0 = (a00 != T(0)) ? a00 : T(1);
     const T dd = (det != T(0)) ? det : T(1);
     const T rinv0 = fast_recip(p0);
     const T rinv1 = p0 * fast_recip(dd);
-    if (tid == 0) {
-      rdiag[k] = rinv0;
-      rdiag[k + 1] = rinv1;
-    }
     const T lk1 = a10 * rinv0;  // l0(k+1)
-    T l0[4], l1[4], u0[4], u1[4];
+    // multipliers of the thread's rows / new U rows of its columns
+    auto lmult = [&](T (&l0)[4], T (&l1)[4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ty + 16 * i;
-      l0[i] = r > k ? cv0[i] * rinv0 : T(0);
-      l1[i] = r > k + 1 ? (cv1[i] - l0[i] * a01) * rinv1 : T(0);
-    }
+      for (int i = 0; i < 4; ++i) {
+        const int r = ty + 16 * i;
+        const T cv0 = col[b][0][r], cv1 = col[b][1][r];
+        l0[i] = r > k ? cv0 * rinv0 : T(0);
+        l1[i] = r > k + 1 ? (cv1 - l0[i] * a01) * rinv1 : T(0);
+      }
+    };
+    auto urows = [&](T (&u0)[4], T (&u1)[4]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = tx + 16 * j;
-      u0[j] = c > k ? rv0[j] : T(0);
-      u1[j] = c > k + 1 ? rv1[j] - lk1 * rv0[j] : T(0);
-    }
+      for (int j = 0; j < 4; ++j) {
+        const int c = tx + 16 * j;
+        const T rv0 = row[b][0][c], rv1 = row[b][1][c];
+        u0[j] = c > k ? rv0 : T(0);
+        u1[j] = c > k + 1 ? rv1 - lk1 * rv0 : T(0);
+      }
+    };
+    if (blk) {
+      if (tid == 0) {
+        if (!(a00 != T(0)) || !isfinite((double)a00) || !(det != T(0)) || !isfinite((double)det)) bad = 1;
+        rdiag[k] = rinv0;
+        rdiag[k + 1] = rinv1;
+      }
+      T l0[4], l1[4], u0[4], u1[4];
+      lmult(l0, l1);
+      urows(u0, u1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) d.v[i][j] = fma(-l1[i], u1[j], fma(-l0[i], u0[j], d.v[i][j]));
-    if (role == 0) {
+        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-l1[i], u1[j], fma(-l0[i], u0[j], v.v[i][j]));
+    } else if (role == 0) {
       // Y = U^{-T}: rows k, k+1 final (y0 = Y(k,:)/U_kk, y1 = (Y(k+1,:) -
       // U(k,k+1) y0)/U'_{k+1,k+1}); rows r > k take -U(k,r) y0, rows r > k+1
       // also -U'(k+1,r) y1
-      T ur0[4], ur1[4], y0[4], y1[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ur0[i] = row[b][0][ty + 16 * i];
-        ur1[i] = row[b][1][ty + 16 * i];
-      }
+      T y0[4], y1[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         y0[j] = trow[b][0][tx + 16 * j] * rinv0;
@@ -215,15 +219,17 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = ty + 16 * i;
-        const T m0 = r > k ? ur0[i] : T(0);
-        const T m1 = r > k + 1 ? ur1[i] - lk1 * ur0[i] : T(0);
+        const T ur0 = row[b][0][r], ur1 = row[b][1][r];
+        const T m0 = r > k ? ur0 : T(0);
+        const T m1 = r > k + 1 ? ur1 - lk1 * ur0 : T(0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-m1, y1[j], fma(-m0, y0[j], t.v[i][j]));
+        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-m1, y1[j], fma(-m0, y0[j], v.v[i][j]));
       }
     } else if (role == 1) {
       // x U = a: x(:,k) = a(:,k)/U_kk, x(:,k+1) = (a(:,k+1) - x(:,k) U(k,k+1))
       // / U'_{k+1,k+1}; columns c > k take -x(:,k) u0, c > k+1 also -x(:,k+1) u1
-      T x0[4], x1[4];
+      T u0[4], u1[4], x0[4], x1[4];
+      urows(u0, u1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         x0[i] = tcol[b][0][ty + 16 * i] * rinv0;
@@ -232,11 +238,12 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-x1[i], u1[j], fma(-x0[i], u0[j], t.v[i][j]));
+        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-x1[i], u1[j], fma(-x0[i], u0[j], v.v[i][j]));
     } else {
       // L y = a: rows r > k take -L(r,k) y(k,:), rows r > k+1 also
       // -L(r,k+1) y(k+1,:) with y(k+1,:) = a(k+1,:) - L(k+1,k) y(k,:)
-      T y0[4], y1[4];
+      T l0[4], l1[4], y0[4], y1[4];
+      lmult(l0, l1);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         y0[j] = trow[b][0][tx + 16 * j];
@@ -245,28 +252,25 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t.v[i][j] = fma(-l1[i], y1[j], fma(-l0[i], y0[j], t.v[i][j]));
+        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-l1[i], y1[j], fma(-l0[i], y0[j], v.v[i][j]));
     }
     // publish rows and columns k+2 and k+3 (same register index (k+2) / 16,
-    // owners tx or ty == (k+2) % 16 and (k+3) % 16)
+    // owners tx or ty == (k+2) % 16 and (k+3) % 16): the block half its rows
+    // and columns, the tile half its rows (roles 0, 2) or columns (role 1)
     const int k2 = k + 2;
     if (k2 < kpair) {
       const int s0 = k2 & 15;
       const bool c_0 = tx == s0, c_1 = tx == s0 + 1, r_0 = ty == s0, r_1 = ty == s0 + 1;
-#define PF_PUB(J)                                                                           \
-  {                                                                                         \
-    if (c_0 || c_1) {                                                                       \
-      const int q = c_1 ? 1 : 0;                                                            \
-      for (int i = 0; i < 4; ++i) col[nb][q][ty + 16 * i] = d.v[i][J];                     \
-      if (role == 1)                                                                        \
-        for (int i = 0; i < 4; ++i) tcol[nb][q][ty + 16 * i] = t.v[i][J];                   \
-    }                                                                                       \
-    if (r_0 || r_1) {                                                                       \
-      const int q = r_1 ? 1 : 0;                                                            \
-      for (int j = 0; j < 4; ++j) row[nb][q][tx + 16 * j] = d.v[J][j];                      \
-      if (role != 1)                                                                        \
-        for (int j = 0; j < 4; ++j) trow[nb][q][tx + 16 * j] = t.v[J][j];                   \
-    }                                                                                       \
+      const bool pc = blk ? (c_0 || c_1) : (role == 1 && (c_0 || c_1));
+      const bool pr = blk ? (r_0 || r_1) : (role != 1 && (r_0 || r_1));
+      T* cdst = blk ? &col[nb][c_1 ? 1 : 0][0] : &tcol[nb][c_1 ? 1 : 0][0];
+      T* rdst = blk ? &row[nb][r_1 ? 1 : 0][0] : &trow[nb][r_1 ? 1 : 0][0];
+#define PF_PUB(J)                                                       \
+  {                                                                     \
+    if (pc)                                                             \
+      for (int i = 0; i < 4; ++i) cdst[ty + 16 * i] = v.v[i][J];        \
+    if (pr)                                                             \
+      for (int j = 0; j < 4; ++j) rdst[tx + 16 * j] = v.v[J][j];        \
   }
       switch (k2 >> 4) {
         case 0:
@@ -286,17 +290,9 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     }
     __syncthreads();
   }
-  if (role == 0) {
-    // L below the diagonal: divide the stored columns by their pivots
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = ty + 16 * i, c = tx + 16 * j;
-        if (r > c) d.v[i][j] *= rdiag[c];
-      }
-    tile_store(d, (T*)I.dfac + (int64_t)(k0 / NB) * NB * NB, NB, 0, 0, NB, NB, tx, ty);
-    if (tid == 0 && bad) I.red->singular = 1;
+  if (blk) {
+    if (role == 0 && tid == 0 && bad) I.red->singular = 1;
+  } else if (role == 0) {
     // U^{-1} = Y^T, rows of Y divided by their pivots
     T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
 #pragma unroll
@@ -304,23 +300,23 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       const int r = ty + 16 * i;
       const T sc = rdiag[r];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) ui[(int64_t)r * NB + tx + 16 * j] = t.v[i][j] * sc;
+      for (int j = 0; j < 4; ++j) ui[(int64_t)r * NB + tx + 16 * j] = v.v[i][j] * sc;
     }
   } else if (role == 1) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const T sc = rdiag[tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) t.v[i][j] *= sc;
+      for (int i = 0; i < 4; ++i) v.v[i][j] *= sc;
     }
-    tile_store(t, A, ld, r0, k0, nr, kb, tx, ty);
+    tile_store(v, A, ld, r0, k0, nr, kb, tx, ty);
   } else {
-    tile_store(t, A, ld, k0, c0, kb, nc, tx, ty);
+    tile_store(v, A, ld, k0, c0, kb, nc, tx, ty);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
+__global__ __launch_bounds__(512) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
                                                      int k0) {
   panel_step<T>(insts, work[blockIdx.x], k0);
 }
@@ -368,7 +364,10 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   const int c0 = k0 + kb + (wk.y / nrt) * NB;
   const int nr = min(NB, M - r0);
   const int nc = min(NB, M + 1 - c0);
-  {
+  // in a 512-thread launch (beside the panel) threads 256.. only take the
+  // barrier
+  const bool work = threadIdx.x < 256;
+  if (work) {
     // all 32 loads of a thread in flight before the LDS stores (addresses
     // clamped into the tile, values masked afterwards)
     const auto G = gp((const T*)A);
@@ -399,6 +398,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
     }
   }
   __syncthreads();
+  if (!work) return;
   const int lane = tid % 64, w = tid / 64;
   const int rb = (w / 2) * 32, cb = (w % 2) * 32;
   const int li = lane % 16, lk = lane / 16;
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, co
 // writes only its block row and column, which the previous launch brought up
 // to date; the update writes only tiles right of and below them.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
+__global__ __launch_bounds__(512) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
                                                           int npanel, int k0) {
   if ((int)blockIdx.x < npanel)
     panel_step<T>(insts, work[blockIdx.x], k0);
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
 template <typename T>
 void launch_dense_panel(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int k0) {
   if (nwork <= 0) return;
-  k_dense_panel<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, k0);
+  k_dense_panel<T><<<dim3((unsigned)nwork), 512, 0, st>>>(insts, work, k0);
 }
 
 template <typename T>
@@ -565,7 +565,7 @@ template <typename T>
 void launch_dense_panel_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel,
                              int k0) {
   if (nwork <= 0) return;
-  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
+  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 512, 0, st>>>(insts, work, npanel, k0);
 }
 
 template <typename T>
