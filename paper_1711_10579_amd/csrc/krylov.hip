@@ -547,12 +547,24 @@ template <typename T>
 __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pass) {
   __shared__ double red[KMAX + 1][KCH / 64];
   __shared__ double h[KMAX + 1];
+  __shared__ double hg[8][KMAX + 1];
   const Inst& I = *insts[blockIdx.y];
   if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
   const int j = I.ks->j;
+  // h_i = sum over chunks of the pass's partial dots: 8 interleaved groups
+  // of chunks, then the groups in order
+  const int ni = j + 1;
+  for (int idx = threadIdx.x; idx < 8 * ni; idx += KCH) {
+    const int i = idx % ni, grp = idx / ni;
+    double s = 0.0;
+    for (int c = grp; c < I.kchunks; c += 8) s += kpart(I, pass, c)[i];
+    hg[grp][i] = s;
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i <= j; i += KCH) {
     double s = 0.0;
-    for (int c = 0; c < I.kchunks; ++c) s += kpart(I, pass, c)[i];
+#pragma unroll
+    for (int grp = 0; grp < 8; ++grp) s += hg[grp][i];
     h[i] = s;
     if (blockIdx.x == 0) {
       double* H = kh_H(I) + (int64_t)i * I.km + j;
@@ -597,55 +609,78 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
 // column j of H, the residual estimate |g_{j+1}| / ||F||.  The cycle ends
 // when the forcing term is met, the basis is full or w vanished; then
 // y = H^{-1} g by back substitution.
-__global__ void k_karnoldi_end(const Inst* const* insts, int nslots, KOpts o) {
-  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
+// One wave per instance: the chunk partial sums are reduced across the
+// lanes (fixed order), the Hessenberg column and the rotations are staged in
+// LDS for lane 0's sequential part, and the back substitution runs row by
+// row with a wave reduction.
+__global__ __launch_bounds__(64) void k_karnoldi_end(const Inst* const* insts, KOpts o) {
+  __shared__ double hc[KMAX + 1], scs[KMAX], ssn[KMAX], y[KMAX];
+  __shared__ int fin;
+  const Inst& I = *insts[blockIdx.x];
   if (!kstate_is(I, KS_ITER)) return;
   KState& ks = *I.ks;
+  const int lane = threadIdx.x;
   const int j = ks.j, m = I.km;
-  double hn2 = 0.0;
-  for (int c = 0; c < I.kchunks; ++c) hn2 += kpart(I, 2, c)[0];
-  const double h = sqrt(hn2);
+  double part = 0.0;
+  for (int c = lane; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
+  const double h = sqrt(wave_sum(part));
   double* H = kh_H(I);
   double* cs = kh_cs(I);
   double* sn = kh_sn(I);
   double* g = kh_g(I);
-  for (int i = 0; i < j; ++i) {
-    const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
-    H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
-    H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-  }
-  const double hjj = H[(int64_t)j * m + j];
-  const double d = hypot(hjj, h);
-  if (!isfinite(d) || !(d > 0.0)) {
-    linear_failure(I);
-    return;
-  }
-  cs[j] = hjj / d;
-  sn[j] = h / d;
-  H[(int64_t)j * m + j] = d;
-  H[(int64_t)(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  const double rel = fabs(g[j + 1]) / ks.bnorm;
-  ks.rel = rel;
-  ks.j = j + 1;
-  ks.total += 1;
-  I.red->linear_iters += 1;
-  if (rel <= ks.eta || j + 1 >= o.m || !(h > 0.0)) {
-    double* y = kh_y(I);
-    const int k = j + 1;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int c = i + 1; c < k; ++c) s -= H[(int64_t)i * m + c] * y[c];
-      y[i] = s / H[(int64_t)i * m + i];
+  for (int i = lane; i <= j; i += 64) {
+    hc[i] = H[(int64_t)i * m + j];
+    if (i < j) {
+      scs[i] = cs[i];
+      ssn[i] = sn[i];
     }
-    ks.met = rel <= ks.eta;
-    ks.state = KS_CYCLE;
-  } else {
-    ks.scale = 1.0 / h;
   }
+  __syncthreads();
+  if (lane == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double a = hc[i], b = hc[i + 1];
+      hc[i] = scs[i] * a + ssn[i] * b;
+      hc[i + 1] = -ssn[i] * a + scs[i] * b;
+    }
+    const double hjj = hc[j];
+    const double d = hypot(hjj, h);
+    if (!isfinite(d) || !(d > 0.0)) {
+      linear_failure(I);
+      fin = -1;
+    } else {
+      cs[j] = hjj / d;
+      sn[j] = h / d;
+      hc[j] = d;
+      H[(int64_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      const double rel = fabs(g[j + 1]) / ks.bnorm;
+      ks.rel = rel;
+      ks.j = j + 1;
+      ks.total += 1;
+      I.red->linear_iters += 1;
+      fin = (rel <= ks.eta || j + 1 >= o.m || !(h > 0.0)) ? 1 : 0;
+      if (fin) ks.met = rel <= ks.eta;
+      else ks.scale = 1.0 / h;
+    }
+  }
+  __syncthreads();
+  if (fin < 0) return;
+  for (int i = lane; i <= j; i += 64) H[(int64_t)i * m + j] = hc[i];
+  if (fin == 0) return;
+  // end of the cycle: y = H^{-1} g over the k = j + 1 columns (H upper)
+  const int k = j + 1;
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    double p = 0.0;
+    for (int c = i + 1 + lane; c < k; c += 64) p += H[(int64_t)i * m + c] * y[c];
+    p = wave_sum(p);
+    if (lane == 0) y[i] = (g[i] - p) / (i == j ? hc[j] : H[(int64_t)i * m + i]);
+    __syncthreads();
+  }
+  double* yo = kh_y(I);
+  for (int i = lane; i < k; i += 64) yo[i] = y[i];
+  if (lane == 0) ks.state = KS_CYCLE;
 }
 
 // ---------------------------------------------------------------------------
@@ -677,21 +712,22 @@ __global__ __launch_bounds__(KCH) void k_kbegin(const Inst* const* insts) {
 // Per instance: ||F||_2, the forcing term eta = max(min(eta_max,
 // ||F||_inf), eta_floor) and the first cycle.  A singular preconditioner
 // ends the instance's Newton iteration with status singular.
-__global__ void k_kbegin_fin(const Inst* const* insts, int nslots, KOpts o) {
-  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
+__global__ __launch_bounds__(64) void k_kbegin_fin(const Inst* const* insts, KOpts o) {
+  const Inst& I = *insts[blockIdx.x];
   if (!I.red->active) return;
   KState& ks = *I.ks;
   if (I.red->singular) {
-    I.red->status = 3;
-    I.red->active = 0;
-    ks.state = KS_DONE;
+    if (threadIdx.x == 0) {
+      I.red->status = 3;
+      I.red->active = 0;
+      ks.state = KS_DONE;
+    }
     return;
   }
-  double s = 0.0;
-  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, 2, c)[0];
-  const double bn = sqrt(s);
+  double part = 0.0;
+  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
+  const double bn = sqrt(wave_sum(part));
+  if (threadIdx.x != 0) return;
   ks.bnorm = bn;
   ks.eta = fmax(fmin(o.eta_max, I.red->last_norm), o.eta_floor);
   ks.j = 0;
@@ -800,15 +836,14 @@ __global__ __launch_bounds__(KCH) void k_kresid(const Inst* const* insts) {
 
 // Per instance: the true residual starts the next cycle, or ends the solve
 // when it already meets the forcing term.
-__global__ void k_krestart_fin(const Inst* const* insts, int nslots) {
-  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
+__global__ __launch_bounds__(64) void k_krestart_fin(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.x];
   if (!kstate_is(I, KS_RESTART)) return;
   KState& ks = *I.ks;
-  double s = 0.0;
-  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, 2, c)[0];
-  const double beta = sqrt(s);
+  double part = 0.0;
+  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
+  const double beta = sqrt(wave_sum(part));
+  if (threadIdx.x != 0) return;
   ks.rel = beta / ks.bnorm;
   if (ks.rel <= ks.eta || !(beta > 0.0)) {
     ks.met = 1;
@@ -902,12 +937,12 @@ void launch_karnoldi(hipStream_t st, const Inst* const* insts, int nslots, int m
   k_kspmv_dot<T><<<g, KCH, 0, st>>>(insts);
   k_korth<T><<<g, KCH, 0, st>>>(insts, 0);
   k_korth<T><<<g, KCH, 0, st>>>(insts, 1);
-  k_karnoldi_end<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
+  k_karnoldi_end<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
 }
 template <typename T>
 void launch_kbegin(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
   k_kbegin<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
-  k_kbegin_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
+  k_kbegin_fin<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
 }
 template <typename T>
 void launch_kycomb(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks) {
@@ -919,7 +954,7 @@ void launch_kcycle_end(hipStream_t st, const Inst* const* insts, int nslots, int
   k_kxadd<T><<<g, KCH, 0, st>>>(insts);
   k_kcycle_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, o);
   k_kresid<T><<<g, KCH, 0, st>>>(insts);
-  k_krestart_fin<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots);
+  k_krestart_fin<<<dim3((unsigned)nslots), 64, 0, st>>>(insts);
 }
 template <typename T>
 void launch_kfinish(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks) {
