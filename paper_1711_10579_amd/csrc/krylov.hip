@@ -317,31 +317,38 @@ namespace {
 
 constexpr int LPM = 256;  // level pointers kept in LDS (z takes the rest)
 
-// One row of a sweep with its first two off-diagonal entries, loaded ahead
-// of the level that needs it.
+// Data of one row of a sweep with its first two off-diagonal entries.
 template <typename T>
-struct SweepRow {
-  i4v inf;  // {row, first, end, 0}; row < 0: none
+struct SweepData {
   T w0, w1;  // forward: right-hand side; backward: unused
   Blk<T> E[2];
   int c[2];
 };
 
+// the row info {row, first, end, 0} at position k of a level list, or row -1
+__device__ inline i4v sweep_info(const PF_AS1 i4v* info, int k, int k1) {
+  if (k < k1) return info[k];
+  i4v none;
+  none.x = -1;
+  none.y = 0;
+  none.z = 0;
+  none.w = 0;
+  return none;
+}
+
 template <typename T>
-__device__ inline void sweep_load(const PF_AS1 i4v* info, const PF_AS1 T* P, const PF_AS1 int* kcol,
-                                  const PF_AS1 T* w, int k, int k1, SweepRow<T>* s) {
-  s->inf.x = -1;
-  if (k >= k1) return;
-  s->inf = info[k];
+__device__ inline void sweep_data(const i4v& inf, const PF_AS1 T* P, const PF_AS1 int* kcol, const PF_AS1 T* w,
+                                  SweepData<T>* s) {
+  if (inf.x < 0) return;
   if (w) {
-    s->w0 = w[2 * s->inf.x];
-    s->w1 = w[2 * s->inf.x + 1];
+    s->w0 = w[2 * inf.x];
+    s->w1 = w[2 * inf.x + 1];
   }
 #pragma unroll
   for (int e = 0; e < 2; ++e)
-    if (s->inf.y + e < s->inf.z) {
-      s->E[e] = ld_blk<T>(P, s->inf.y + e);
-      s->c[e] = kcol[s->inf.y + e];
+    if (inf.y + e < inf.z) {
+      s->E[e] = ld_blk<T>(P, inf.y + e);
+      s->c[e] = kcol[inf.y + e];
     }
 }
 
@@ -349,10 +356,12 @@ __device__ inline void sweep_load(const PF_AS1 i4v* info, const PF_AS1 T* P, con
 
 // The ILU(0) application z = U^{-1} L^{-1} (s w) of an instance in one
 // work-group, level by level with a barrier between levels (rows as in
-// k_ilu_fwd / k_ilu_bwd).  Each thread loads its row of the next level while
-// the current level is computed.  ZV > 0: the work-group keeps z in LDS
-// (instances with 2 nu <= ZV values) and writes it out at the end; ZV = 0: z
-// lives in device memory.  Instances of the other sizes are skipped.
+// k_ilu_fwd / k_ilu_bwd).  Each thread's first row of a level is fetched in
+// two stages: its row info two levels ahead, its data one level ahead, so
+// that each dependent load has a level's time to arrive.  ZV > 0: the
+// work-group keeps z in LDS (instances with 2 nu <= ZV values) and writes it
+// out at the end; ZV = 0: z lives in device memory.  Instances of the other
+// sizes are skipped.
 template <typename T, int ZV>
 __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts, int mode, int zmin) {
   __shared__ T zl[ZV > 0 ? ZV : 1];
@@ -383,8 +392,8 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
   auto bp = [&](int l) { return lds_ptr ? lpb[l] : ku_ptr[l]; };
 
   // forward: y_r = s w_r - sum_{k<r} L(r,k) y_k
-  auto fwd_row = [&](const SweepRow<T>& s) {
-    const int r = s.inf.x;
+  auto fwd_row = [&](const i4v& inf, const SweepData<T>& s) {
+    const int r = inf.x;
     T v0 = s.w0, v1 = s.w1;
     if (mode == 0) {
       v0 = (T)((double)v0 * sc);
@@ -395,12 +404,12 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
     double y0 = (double)v0, y1 = (double)v1;
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      if (s.inf.y + e < s.inf.z) {
+      if (inf.y + e < inf.z) {
         const double a = (double)z[2 * s.c[e]], b = (double)z[2 * s.c[e] + 1];
         y0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
         y1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
       }
-    for (int q = s.inf.y + 2; q < s.inf.z; ++q) {
+    for (int q = inf.y + 2; q < inf.z; ++q) {
       const Blk<T> L = ld_blk<T>(P, q);
       const int c = kcol[q];
       const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
@@ -410,33 +419,18 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
     z[2 * r] = (T)y0;
     z[2 * r + 1] = (T)y1;
   };
-  SweepRow<T> cur, nxt;
-  if (nl > 0) sweep_load<T>(kl_info, P, kcol, w, fp(0) + tid, fp(1), &cur);
-  for (int l = 0; l < nl; ++l) {
-    const int k0 = fp(l), k1 = fp(l + 1);
-    if (l + 1 < nl) sweep_load<T>(kl_info, P, kcol, w, k1 + tid, fp(l + 2), &nxt);
-    if (cur.inf.x >= 0) fwd_row(cur);
-    for (int k = k0 + tid + 1024; k < k1; k += 1024) {
-      SweepRow<T> x;
-      sweep_load<T>(kl_info, P, kcol, w, k, k1, &x);
-      fwd_row(x);
-    }
-    __syncthreads();
-    cur = nxt;
-  }
-
   // backward: z_r = U(r,r)^{-1} (y_r - sum_{j>r} U(r,j) z_j)
-  auto bwd_row = [&](const SweepRow<T>& s) {
-    const int r = s.inf.x;
+  auto bwd_row = [&](const i4v& inf, const SweepData<T>& s) {
+    const int r = inf.x;
     double s0 = (double)z[2 * r], s1 = (double)z[2 * r + 1];
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      if (s.inf.y + e < s.inf.z) {
+      if (inf.y + e < inf.z) {
         const double a = (double)z[2 * s.c[e]], b = (double)z[2 * s.c[e] + 1];
         s0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
         s1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
       }
-    for (int q = s.inf.y + 2; q < s.inf.z; ++q) {
+    for (int q = inf.y + 2; q < inf.z; ++q) {
       const Blk<T> U = ld_blk<T>(P, q);
       const int c = kcol[q];
       const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
@@ -447,20 +441,34 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
     z[2 * r] = (T)((double)Dv.a * s0 + (double)Dv.b * s1);
     z[2 * r + 1] = (T)((double)Dv.c * s0 + (double)Dv.d * s1);
   };
-  const PF_AS1 T* nw = nullptr;
-  if (nul > 0) sweep_load<T>(ku_info, P, kcol, nw, bp(0) + tid, bp(1), &cur);
-  for (int l = 0; l < nul; ++l) {
-    const int k0 = bp(l), k1 = bp(l + 1);
-    if (l + 1 < nul) sweep_load<T>(ku_info, P, kcol, nw, k1 + tid, bp(l + 2), &nxt);
-    if (cur.inf.x >= 0) bwd_row(cur);
-    for (int k = k0 + tid + 1024; k < k1; k += 1024) {
-      SweepRow<T> x;
-      sweep_load<T>(ku_info, P, kcol, nw, k, k1, &x);
-      bwd_row(x);
+  // one sweep over the levels of a list with the two-stage fetch
+  auto sweep = [&](const PF_AS1 i4v* info, auto ptr, int nlev, const PF_AS1 T* wsrc, auto row_fn) {
+    if (nlev <= 0) return;
+    i4v i0 = sweep_info(info, ptr(0) + tid, ptr(1));
+    i4v i1 = nlev > 1 ? sweep_info(info, ptr(1) + tid, ptr(2)) : i0;
+    SweepData<T> d0, d1;
+    sweep_data<T>(i0, P, kcol, wsrc, &d0);
+    for (int l = 0; l < nlev; ++l) {
+      const int k0 = ptr(l), k1 = ptr(l + 1);
+      i4v i2 = i1;
+      if (l + 2 < nlev) i2 = sweep_info(info, ptr(l + 2) + tid, ptr(l + 3));
+      if (l + 1 < nlev) sweep_data<T>(i1, P, kcol, wsrc, &d1);
+      if (i0.x >= 0) row_fn(i0, d0);
+      for (int k = k0 + tid + 1024; k < k1; k += 1024) {
+        const i4v ix = info[k];
+        SweepData<T> dx;
+        sweep_data<T>(ix, P, kcol, wsrc, &dx);
+        row_fn(ix, dx);
+      }
+      __syncthreads();
+      i0 = i1;
+      d0 = d1;
+      i1 = i2;
     }
-    __syncthreads();
-    cur = nxt;
-  }
+  };
+  sweep(kl_info, fp, nl, w, fwd_row);
+  const PF_AS1 T* nw = nullptr;
+  sweep(ku_info, bp, nul, nw, bwd_row);
   if (ZV > 0) {
     const auto zg = gp((T*)I.kz);
     for (int i = tid; i < 2 * nu; i += 1024) zg[i] = zl[i];
