@@ -1,19 +1,21 @@
 // Dense trailing block of the factorisation (the nearly complete graph left
-// by the minimum-degree elimination): right-looking blocked LU with static
-// diagonal pivots and 64-wide panels.  The block is a column-major scalar
-// matrix A of order M with leading dimension ld; column M holds the
-// right-hand side, so the trailing updates carry the forward substitution
-// along and that column ends up as L^{-1} b.  A backward solve with U
+// by the minimum-degree elimination): right-looking block LU with static
+// pivots and 64-wide blocks in block-LDU form -- the diagonal blocks are
+// inverted outright and the block-lower factor keeps identity diagonal
+// blocks:
+//   P_k = A_kk^{-1},  L_ik = A_ik P_k (i > k),  A_ij -= L_ik A_kj (i, j > k),
+// the block row A_kj (j > k) staying as it is.  The block is a column-major
+// scalar matrix A of order M with leading dimension ld; column M holds the
+// right-hand side, so the trailing updates carry the block forward
+// substitution along.  The backward solve x_k = P_k (z_k - sum_{j>k} A_kj x_j)
 // finishes the block.
 //
-// Per panel step two launches: the panel (every work-group factors the
-// diagonal block in LDS, then solves one 64-row tile of L or one 64-column
-// tile of U) together with the previous step's trailing update away from the
-// panel's block row and column, then the update of the next panel's block row
-// and column (look-ahead: the bulk of the update runs beside the next panel).  Inside a 64x64 tile each of the 256
-// threads keeps a 4x4 register block (rows ty+16i, columns tx+16j), and the
-// pivot row / column of each elimination step goes through double-buffered
-// LDS, so one barrier separates consecutive steps.
+// Per 64-wide step two launches: the panel (every work-group inverts the
+// diagonal block on the matrix cores, block Gauss-Jordan over 16x16 blocks,
+// then multiplies one 64-row tile below it by the inverse) together with the
+// previous step's trailing update away from the panel's block column and
+// the next block row, then the update of the next panel's block row and
+// column (look-ahead: the bulk of the update runs beside the next panel).
 
 #include <hip/hip_runtime.h>
 
@@ -40,287 +42,6 @@ __device__ inline float fast_recip(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
-template <typename T>
-struct Tile {
-  T v[4][4];
-};
-
-// load a (nr x nc) tile at (r0, c0) into registers; outside -> identity pad
-template <typename T>
-__device__ inline void tile_load(Tile<T>& t, const T* A, int ld, int r0, int c0, int nr, int nc, int tx, int ty,
-                                 bool ident_pad) {
-  // every load issued at once (addresses clamped into the tile), then masked
-  const auto G = gp(A);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = ty + 16 * i, c = tx + 16 * j;
-      t.v[i][j] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + r0 + min(r, nr - 1)];
-    }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = ty + 16 * i, c = tx + 16 * j;
-      if (!(r < nr && c < nc)) t.v[i][j] = (ident_pad && r == c) ? T(1) : T(0);
-    }
-}
-
-template <typename T>
-__device__ inline void tile_store(const Tile<T>& t, T* A, int ld, int r0, int c0, int nr, int nc, int tx, int ty) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int r = ty + 16 * i, c = tx + 16 * j;
-      if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] = t.v[i][j];
-    }
-}
-
-// Panel step k0 of every instance in the work list: item (slot, g).
-//
-// Every work-group factors the 64x64 diagonal block A_kk (identity-padded)
-// in registers, two pivots per step: the pivot rows and columns go through
-// double-buffered LDS, and each element update is two FMAs with multipliers
-// and pivot rows zeroed outside the active part.  Rows k, k+1 of U and
-// columns k, k+1 of L are final after the step, so in the same step each
-// work-group also advances its own triangular solve:
-//   g = 0:        Y = U^{-T} by forward substitution (U^T Y = I; row k of Y
-//                 is final at step k); the factored block goes to dfac and
-//                 U^{-1} = Y^T to dinvu (the other work-groups still read the
-//                 unfactored block from A);
-//   g in 1..nrt:  a 64-row tile below the block, x U = a (L_ik = A_ik U^{-1});
-//   g > nrt:      a 64-column tile right of it, the last one holding the RHS
-//                 column M, L y = a (U_kj = L_kk^{-1} A_kj).
-// Divisions by U_kk are applied once after the loop (columns of L and of x,
-// rows of Y are not touched after their step).
-template <typename T>
-__device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0) {
-  // rows / columns k and k+1 of the block and of the tile, double-buffered
-  __shared__ T row[2][2][NB], col[2][2][NB];
-  __shared__ T trow[2][2][NB], tcol[2][2][NB];
-  __shared__ T rdiag[NB];
-  __shared__ int bad;
-  const Inst& I = *insts[w.x];
-  if (I.red->active == 0) return;
-  T* A = (T*)I.tail;
-  const int ld = I.ldt, M = I.M;
-  // the launch is uniform per work-group: keep these in scalar registers
-  const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
-  const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
-  const int g = __builtin_amdgcn_readfirstlane(w.y);
-  const int role = g == 0 ? 0 : (g <= nrt ? 1 : 2);
-  // threads 0..255 hold the diagonal block, threads 256..511 the tile (each
-  // a 4x4 register block of rows ty+16i, columns tx+16j)
-  const bool blk = threadIdx.x < 256;
-  const int tid = threadIdx.x & 255;
-  const int tx = tid % 16, ty = tid / 16;
-  if (threadIdx.x == 0) bad = 0;
-  if (threadIdx.x < NB) rdiag[threadIdx.x] = T(1);
-  Tile<T> v;
-  int r0 = 0, c0 = 0, nr = 0, nc = 0;
-  if (role == 1) {
-    r0 = k0 + kb + (g - 1) * NB;
-    nr = min(NB, M - r0);
-  } else if (role == 2) {
-    c0 = k0 + kb + (g - 1 - nrt) * NB;
-    nc = min(NB, M + 1 - c0);
-  }
-  if (blk) {
-    tile_load(v, A, ld, k0, k0, kb, kb, tx, ty, true);
-  } else if (role == 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v.v[i][j] = (ty + 16 * i == tx + 16 * j) ? T(1) : T(0);
-  } else if (role == 1) {
-    tile_load(v, A, ld, r0, k0, nr, kb, tx, ty, false);
-  } else {
-    tile_load(v, A, ld, k0, c0, kb, nc, tx, ty, false);
-  }
-  // publish rows / columns 0 and 1 of the block, and rows (roles 0, 2) or
-  // columns (role 1) 0 and 1 of the tile
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = ty + 16 * i, c = tx + 16 * j;
-      if (blk) {
-        if (c < 2) col[0][c][r] = v.v[i][j];
-        if (r < 2) row[0][r][c] = v.v[i][j];
-      } else {
-        if (role == 1 && c < 2) tcol[0][c][r] = v.v[i][j];
-        if (role != 1 && r < 2) trow[0][r][c] = v.v[i][j];
-      }
-    }
-  __syncthreads();
-  // Pivots k and k+1 per step (one barrier per pair).  With a = the block
-  // before step k: l0(r) = a(r,k)/a(k,k), u0(c) = a(k,c) (r, c > k); after
-  // pivot k the row and column k+1 are a'(k+1,c) = a(k+1,c) - l0(k+1) a(k,c)
-  // and a'(r,k+1) = a(r,k+1) - l0(r) a(k,k+1), with pivot a'(k+1,k+1) =
-  // det / a(k,k), det = a(k,k) a(k+1,k+1) - a(k+1,k) a(k,k+1); l1(r) =
-  // a'(r,k+1)/a'(k+1,k+1), u1(c) = a'(k+1,c) (r, c > k+1); the block takes the
-  // rank-2 update a -= l0 u0 + l1 u1.  The two reciprocals 1/a(k,k) and 1/det
-  // are independent.  An odd kb pairs its last pivot with the identity
-  // padding, which leaves everything unchanged.
-  const int kpair = (kb + 1) & ~1;
-  for (int k = 0; k < kpair; k += 2) {
-    const int b = (k >> 1) & 1, nb = b ^ 1;
-    const T a00 = row[b][0][k], a01 = row[b][0][k + 1], a10 = col[b][0][k + 1], a11 = row[b][1][k + 1];
-    const T det = a00 * a11 - a10 * a01;
-    const T p0 = (a00 != T(0)) ? a00 : T(1);
-    const T dd = (det != T(0)) ? det : T(1);
-    const T rinv0 = fast_recip(p0);
-    const T rinv1 = p0 * fast_recip(dd);
-    const T lk1 = a10 * rinv0;  // l0(k+1)
-    // multipliers of the thread's rows / new U rows of its columns
-    auto lmult = [&](T (&l0)[4], T (&l1)[4]) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = ty + 16 * i;
-        const T cv0 = col[b][0][r], cv1 = col[b][1][r];
-        l0[i] = r > k ? cv0 * rinv0 : T(0);
-        l1[i] = r > k + 1 ? (cv1 - l0[i] * a01) * rinv1 : T(0);
-      }
-    };
-    auto urows = [&](T (&u0)[4], T (&u1)[4]) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = tx + 16 * j;
-        const T rv0 = row[b][0][c], rv1 = row[b][1][c];
-        u0[j] = c > k ? rv0 : T(0);
-        u1[j] = c > k + 1 ? rv1 - lk1 * rv0 : T(0);
-      }
-    };
-    if (blk) {
-      if (tid == 0) {
-        if (!(a00 != T(0)) || !isfinite((double)a00) || !(det != T(0)) || !isfinite((double)det)) bad = 1;
-        rdiag[k] = rinv0;
-        rdiag[k + 1] = rinv1;
-      }
-      T l0[4], l1[4], u0[4], u1[4];
-      lmult(l0, l1);
-      urows(u0, u1);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-l1[i], u1[j], fma(-l0[i], u0[j], v.v[i][j]));
-    } else if (role == 0) {
-      // Y = U^{-T}: rows k, k+1 final (y0 = Y(k,:)/U_kk, y1 = (Y(k+1,:) -
-      // U(k,k+1) y0)/U'_{k+1,k+1}); rows r > k take -U(k,r) y0, rows r > k+1
-      // also -U'(k+1,r) y1
-      T y0[4], y1[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        y0[j] = trow[b][0][tx + 16 * j] * rinv0;
-        y1[j] = (trow[b][1][tx + 16 * j] - a01 * y0[j]) * rinv1;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = ty + 16 * i;
-        const T ur0 = row[b][0][r], ur1 = row[b][1][r];
-        const T m0 = r > k ? ur0 : T(0);
-        const T m1 = r > k + 1 ? ur1 - lk1 * ur0 : T(0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-m1, y1[j], fma(-m0, y0[j], v.v[i][j]));
-      }
-    } else if (role == 1) {
-      // x U = a: x(:,k) = a(:,k)/U_kk, x(:,k+1) = (a(:,k+1) - x(:,k) U(k,k+1))
-      // / U'_{k+1,k+1}; columns c > k take -x(:,k) u0, c > k+1 also -x(:,k+1) u1
-      T u0[4], u1[4], x0[4], x1[4];
-      urows(u0, u1);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        x0[i] = tcol[b][0][ty + 16 * i] * rinv0;
-        x1[i] = (tcol[b][1][ty + 16 * i] - x0[i] * a01) * rinv1;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-x1[i], u1[j], fma(-x0[i], u0[j], v.v[i][j]));
-    } else {
-      // L y = a: rows r > k take -L(r,k) y(k,:), rows r > k+1 also
-      // -L(r,k+1) y(k+1,:) with y(k+1,:) = a(k+1,:) - L(k+1,k) y(k,:)
-      T l0[4], l1[4], y0[4], y1[4];
-      lmult(l0, l1);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        y0[j] = trow[b][0][tx + 16 * j];
-        y1[j] = trow[b][1][tx + 16 * j] - lk1 * y0[j];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v.v[i][j] = fma(-l1[i], y1[j], fma(-l0[i], y0[j], v.v[i][j]));
-    }
-    // publish rows and columns k+2 and k+3 (same register index (k+2) / 16,
-    // owners tx or ty == (k+2) % 16 and (k+3) % 16): the block half its rows
-    // and columns, the tile half its rows (roles 0, 2) or columns (role 1)
-    const int k2 = k + 2;
-    if (k2 < kpair) {
-      const int s0 = k2 & 15;
-      const bool c_0 = tx == s0, c_1 = tx == s0 + 1, r_0 = ty == s0, r_1 = ty == s0 + 1;
-      const bool pc = blk ? (c_0 || c_1) : (role == 1 && (c_0 || c_1));
-      const bool pr = blk ? (r_0 || r_1) : (role != 1 && (r_0 || r_1));
-      T* cdst = blk ? &col[nb][c_1 ? 1 : 0][0] : &tcol[nb][c_1 ? 1 : 0][0];
-      T* rdst = blk ? &row[nb][r_1 ? 1 : 0][0] : &trow[nb][r_1 ? 1 : 0][0];
-#define PF_PUB(J)                                                       \
-  {                                                                     \
-    if (pc)                                                             \
-      for (int i = 0; i < 4; ++i) cdst[ty + 16 * i] = v.v[i][J];        \
-    if (pr)                                                             \
-      for (int j = 0; j < 4; ++j) rdst[tx + 16 * j] = v.v[J][j];        \
-  }
-      switch (k2 >> 4) {
-        case 0:
-          PF_PUB(0);
-          break;
-        case 1:
-          PF_PUB(1);
-          break;
-        case 2:
-          PF_PUB(2);
-          break;
-        default:
-          PF_PUB(3);
-          break;
-      }
-#undef PF_PUB
-    }
-    __syncthreads();
-  }
-  if (blk) {
-    if (role == 0 && tid == 0 && bad) I.red->singular = 1;
-  } else if (role == 0) {
-    // U^{-1} = Y^T, rows of Y divided by their pivots
-    T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ty + 16 * i;
-      const T sc = rdiag[r];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ui[(int64_t)r * NB + tx + 16 * j] = v.v[i][j] * sc;
-    }
-  } else if (role == 1) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const T sc = rdiag[tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v.v[i][j] *= sc;
-    }
-    tile_store(v, A, ld, r0, k0, nr, kb, tx, ty);
-  } else {
-    tile_store(v, A, ld, k0, c0, kb, nc, tx, ty);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(512) void k_dense_panel(const Inst* const* insts, const int2* __restrict__ work,
-                                                     int k0) {
-  panel_step<T>(insts, work[blockIdx.x], k0);
-}
-
 // Matrix-core 16x16x4 step: D = A B + C on a wave, one value of A and of B per
 // lane (lane l holds A[l%16][l/16] and B[l/16][l%16]).  Element e of lane l
 // of the result is D[row(l, e)][l%16]: row (l/16) + 4e for FP64, 4(l/16) + e
@@ -334,6 +55,9 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ inline int row(int lane, int e) { return lane / 16 + 4 * e; }
+  // the lane group and element holding row k
+  static constexpr int grp(int k) { return k & 3; }
+  static constexpr int elem(int k) { return k >> 2; }
 };
 template <>
 struct Mfma<float> {
@@ -342,17 +66,241 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ inline int row(int lane, int e) { return 4 * (lane / 16) + e; }
+  static constexpr int grp(int k) { return k >> 2; }
+  static constexpr int elem(int k) { return k & 3; }
 };
 
-// Trailing update A_ij -= A_ik A_kj on 64x64 tiles (rows and columns after
+// ---------------------------------------------------------------------------
+// 16x16 blocks on one wave.  The N-form of a block Z is the layout of a
+// matrix-core result: lane l, element e holds Z[row(l, e)][l % 16].  Taking
+// the summation index of k-step s in lane group g as row(16 g, s), element s
+// of the N-form of Y is the right operand of that k-step of a product X Y,
+// and element s of the N-form of X^T its left operand; the product comes out
+// in N-form.
+
+template <typename T>
+using V4 = typename Mfma<T>::v4;
+
+// C + X Y from the N-forms of X^T and of Y
+template <typename T>
+__device__ inline V4<T> mm16(const V4<T>& xt, const V4<T>& y, V4<T> c) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) c = Mfma<T>::run(xt[s], y[s], c);
+  return c;
+}
+
+// a 16x16 block staged in LDS, row stride 17
+constexpr int kStage = 16 * 17;
+template <typename T>
+__device__ inline void blk_put(T* st, const V4<T>& z, int lane) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) st[Mfma<T>::row(lane, e) * 17 + (lane & 15)] = z[e];
+}
+// N-form of the transpose of a staged block
+template <typename T>
+__device__ inline V4<T> blk_get_t(const T* st, int lane) {
+  V4<T> z;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) z[e] = st[(lane & 15) * 17 + Mfma<T>::row(lane, e)];
+  return z;
+}
+
+// value of lane `src` in every lane (src uniform)
+__device__ inline double lane_read(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float lane_read(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+// value of lane K of each 16-lane row in the whole row (DPP row broadcast)
+template <int K>
+__device__ inline double row_bcast(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int K>
+__device__ inline float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf,
+                                                                false));
+}
+
+// Gauss-Jordan step K (pivot K, no pivoting) on a 16x16 block in N-form:
+// with piv = Z(K,K): Z(r,c) -= Z(r,K) Z(K,c) / piv off row and column K,
+// Z(K,c) /= piv, Z(r,K) = -Z(r,K) / piv, Z(K,K) = 1 / piv.  After steps
+// 0..15 the block holds its inverse.  A zero or non-finite pivot sets `bad`.
+template <int K, typename T>
+__device__ __forceinline__ void gj_step(V4<T>& z, int lane, bool& bad) {
+  constexpr int ek = Mfma<T>::elem(K), gk = Mfma<T>::grp(K);
+  const int c = lane & 15;
+  const T piv = lane_read(z[ek], gk * 16 + K);
+  const T prow = __shfl(z[ek], gk * 16 + c);  // Z(K, c)
+  T m[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) m[e] = row_bcast<K>(z[e]);  // Z(row(lane, e), K)
+  bad = bad || !(piv != T(0)) || !isfinite((double)piv);
+  const T inv = fast_recip(piv != T(0) ? piv : T(1));
+  const T pr = prow * inv;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    T nz = c == K ? -m[e] * inv : fma(-m[e], pr, z[e]);
+    if (Mfma<T>::row(lane, e) == K) nz = c == K ? inv : pr;
+    z[e] = nz;
+  }
+}
+
+template <typename T>
+__device__ inline void blk_inverse(V4<T>& z, int lane, bool& bad) {
+  gj_step<0, T>(z, lane, bad);
+  gj_step<1, T>(z, lane, bad);
+  gj_step<2, T>(z, lane, bad);
+  gj_step<3, T>(z, lane, bad);
+  gj_step<4, T>(z, lane, bad);
+  gj_step<5, T>(z, lane, bad);
+  gj_step<6, T>(z, lane, bad);
+  gj_step<7, T>(z, lane, bad);
+  gj_step<8, T>(z, lane, bad);
+  gj_step<9, T>(z, lane, bad);
+  gj_step<10, T>(z, lane, bad);
+  gj_step<11, T>(z, lane, bad);
+  gj_step<12, T>(z, lane, bad);
+  gj_step<13, T>(z, lane, bad);
+  gj_step<14, T>(z, lane, bad);
+  gj_step<15, T>(z, lane, bad);
+}
+
+// LDS of a dense launch (elements of T): the larger of the panel's (row tile
+// + staged blocks) and the update's (two operand tiles)
+constexpr int kPanelTileLd = NB + 1;
+constexpr int kGemmLd = NB + 2;
+constexpr int kDenseSmem = 2 * NB * kGemmLd > NB * kPanelTileLd + 8 * kStage ? 2 * NB * kGemmLd
+                                                                              : NB * kPanelTileLd + 8 * kStage;
+
+// Panel step k0 of every instance in the work list: item (slot, g), four
+// waves.  Every work-group inverts the diagonal block D = A_kk (identity-
+// padded to 64x64) by block Gauss-Jordan over 4x4 blocks of 16: wave j keeps
+// block column j in N-form; at pivot block p wave p inverts D_pp (P) and
+// stages P and its other blocks D_ip in LDS, then after one barrier every
+// other wave j forms D_pj <- P D_pj and D_ij -= D_ip D_pj (i != p) and wave p
+// D_ip <- -D_ip P.  Then
+//   g = 0:        P is stored (column-major) for the backward solve;
+//   g in 1..nrt:  row tile i = g - 1 below the block: L_ik = A_ik P,
+//                 computed transposed (P^T A_ik^T) so that consecutive lanes
+//                 store consecutive rows.
+template <typename T>
+__device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0, T* smem) {
+  T* xs = smem;                           // the row tile, column-major [NB][kPanelTileLd]
+  T* stage = smem + NB * kPanelTileLd;    // two sets of four staged blocks
+  const Inst& I = *insts[w.x];
+  if (I.red->active == 0) return;
+  T* A = (T*)I.tail;
+  const int ld = I.ldt, M = I.M;
+  // the launch is uniform per work-group: keep these in scalar registers
+  const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
+  const int g = __builtin_amdgcn_readfirstlane(w.y);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, c = lane & 15;
+  const auto G = gp((const T*)A);
+  // the diagonal block's column block wv, identity outside kb x kb
+  V4<T> d[4];
+  {
+    const int cc = 16 * wv + c;
+    const int64_t cb = (int64_t)(k0 + min(cc, kb - 1)) * ld + k0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[i][e] = G[cb + min(16 * i + Mfma<T>::row(lane, e), kb - 1)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * i + Mfma<T>::row(lane, e);
+        if (!(r < kb && cc < kb)) d[i][e] = r == cc ? T(1) : T(0);
+      }
+  }
+  // the row tile (zero outside nr x kb), staged column-major
+  int r0 = 0, nr = 0;
+  if (g > 0) {
+    r0 = k0 + kb + (g - 1) * NB;
+    nr = min(NB, M - r0);
+    const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = G[(int64_t)(k0 + min(tc + 4 * q, kb - 1)) * ld + r0 + min(tr, nr - 1)];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = tc + 4 * q;
+      xs[cc * kPanelTileLd + tr] = (tr < nr && cc < kb) ? v[q] : T(0);
+    }
+  }
+  bool bad = false;
+  const V4<T> zero = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    T* st = stage + (p & 1) * 4 * kStage;
+    if (wv == p) {
+      blk_inverse<T>(d[p], lane, bad);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) blk_put<T>(st + i * kStage, d[i], lane);
+    }
+    // one barrier per pivot block: a set of staged blocks is rewritten two
+    // pivot blocks later, after every wave has passed the barrier between
+    __syncthreads();
+    if (wv == p) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), d[p], zero);
+    } else {
+      const V4<T> npj = mm16<T>(blk_get_t<T>(st + p * kStage, lane), d[p], zero);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
+      d[p] = npj;
+    }
+  }
+  // d[i] = P_{i,wv}
+  if (g == 0) {
+    if (bad && lane == 0) I.red->singular = 1;
+    T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ui[(int64_t)(16 * wv + c) * NB + 16 * i + Mfma<T>::row(lane, e)] = d[i][e];
+    return;
+  }
+  // (A_ik P)_{i', wv}^T = sum_q P_{q,wv}^T (A_ik)_{i',q}^T for row block i'
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    V4<T> acc = zero;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V4<T> xn;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c];
+      acc = mm16<T>(d[q], xn, acc);
+    }
+    const int rr = 16 * i + c;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int cc = 16 * wv + Mfma<T>::row(lane, e);
+      if (rr < nr && cc < kb) A[(int64_t)(k0 + cc) * ld + r0 + rr] = acc[e];
+    }
+  }
+}
+
+// Trailing update A_ij -= L_ik A_kj on 64x64 tiles (rows and columns after
 // the panel, the right-hand side column included), on the matrix cores: four
 // waves, each a 32x32 quarter of the tile as 2x2 blocks of 16x16, K = 64 in
 // steps of 4 (zero-padded past kb).  Both operands sit k-major in LDS so that
-// each quarter-wave reads 16 consecutive values.
+// each quarter-wave reads 16 consecutive values; the tile A_ij is loaded with
+// them, straight into the accumulators, and L_ik is staged negated.
 template <typename T>
-__device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0) {
-  __shared__ T sa[NB][NB + 2];  // [k][row]
-  __shared__ T sb[NB][NB + 2];  // [k][col]
+__device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0, T* smem) {
+  T(*sa)[kGemmLd] = (T(*)[kGemmLd])smem;              // [k][row]
+  T(*sb)[kGemmLd] = (T(*)[kGemmLd])(smem + NB * kGemmLd);  // [k][col]
   const Inst& I = *insts[wk.x];
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
@@ -364,51 +312,50 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   const int c0 = k0 + kb + (wk.y / nrt) * NB;
   const int nr = min(NB, M - r0);
   const int nc = min(NB, M + 1 - c0);
-  // in a 512-thread launch (beside the panel) threads 256.. only take the
-  // barrier
-  const bool work = threadIdx.x < 256;
-  if (work) {
-    // all 32 loads of a thread in flight before the LDS stores (addresses
-    // clamped into the tile, values masked afterwards)
-    const auto G = gp((const T*)A);
-    T va[16], vb[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx % NB, k = idx / NB;
-      va[q] = G[(int64_t)(k0 + min(k, kb - 1)) * ld + r0 + min(r, nr - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int k = idx % NB, c = idx / NB;
-      vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + k0 + min(k, kb - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx % NB, k = idx / NB;
-      sa[k][r] = (r < nr && k < kb) ? va[q] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int k = idx % NB, c = idx / NB;
-      sb[k][c] = (c < nc && k < kb) ? vb[q] : T(0);
-    }
-  }
-  __syncthreads();
-  if (!work) return;
   const int lane = tid % 64, w = tid / 64;
   const int rb = (w / 2) * 32, cb = (w % 2) * 32;
   const int li = lane % 16, lk = lane / 16;
   typedef typename Mfma<T>::v4 v4;
+  const auto G = gp((const T*)A);
+  // every load of a thread in flight at once (addresses clamped into the
+  // tile, values masked afterwards)
   v4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4{T(0), T(0), T(0), T(0)};
-  // the transposed product (A_ik A_kj)^T = A_kj^T A_ik^T: the matrix core's
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rb + bi * 16 + li, c = cb + bj * 16 + Mfma<T>::row(lane, e);
+        acc[bi][bj][e] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + r0 + min(r, nr - 1)];
+      }
+  T va[16], vb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx % NB, k = idx / NB;
+    va[q] = G[(int64_t)(k0 + min(k, kb - 1)) * ld + r0 + min(r, nr - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int k = idx % NB, c = idx / NB;
+    vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + k0 + min(k, kb - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx % NB, k = idx / NB;
+    sa[k][r] = (r < nr && k < kb) ? -va[q] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int k = idx % NB, c = idx / NB;
+    sb[k][c] = (c < nc && k < kb) ? vb[q] : T(0);
+  }
+  __syncthreads();
+  // the transposed product (L_ik A_kj)^T = A_kj^T L_ik^T: the matrix core's
   // first operand is the column block, so a lane's result row is a tile
   // column and its lane index within 16 a tile row -- consecutive lanes then
   // update consecutive rows of the column-major tile
@@ -429,7 +376,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int c = cb + bj * 16 + Mfma<T>::row(lane, e);
-        if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] -= acc[bi][bj][e];
+        if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] = acc[bi][bj][e];
       }
     }
 }
@@ -437,26 +384,28 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, const int2* __restrict__ work,
                                                     int k0) {
-  gemm_tile<T>(insts, work[blockIdx.x], k0);
+  __shared__ T smem[2 * NB * kGemmLd];
+  gemm_tile<T>(insts, work[blockIdx.x], k0, smem);
 }
 
 // Look-ahead: the panel of step k0 (items [0, npanel)) together with the
 // trailing update of step k0 - 64 outside the block row and column of panel
-// k0 (the other items).  The two touch disjoint tiles: the panel reads and
-// writes only its block row and column, which the previous launch brought up
-// to date; the update writes only tiles right of and below them.
+// k0 (the other items).  The two touch disjoint tiles: the panel reads only
+// its block column, which the previous launch brought up to date, and writes
+// its row tiles; the update writes only tiles right of and below them.
 template <typename T>
-__global__ __launch_bounds__(512) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
+__global__ __launch_bounds__(256) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
                                                           int npanel, int k0) {
+  __shared__ T smem[kDenseSmem];
   if ((int)blockIdx.x < npanel)
-    panel_step<T>(insts, work[blockIdx.x], k0);
+    panel_step<T>(insts, work[blockIdx.x], k0, smem);
   else
-    gemm_tile<T>(insts, work[blockIdx.x], k0 - NB);
+    gemm_tile<T>(insts, work[blockIdx.x], k0 - NB, smem);
 }
 
-// Backward solve U x = z (z in column M, U upper with its diagonal) by 64-row
-// blocks: acc = z_b - sum_{c > b} U_bc x_c (columns taken from the last block
-// down), then x_b = U_bb^{-1} acc through the inverse made by the panel step.
+// Block backward solve (z in column M): by 64-row blocks, acc = z_b -
+// sum_{c > b} A_bc x_c (columns taken from the last block down), then x_b =
+// P_b acc with the diagonal block's inverse made by the panel step.
 // Flag mode, item (slot, w): work-group w owns block b = nblk-1-w and waits
 // only for blocks of the same instance listed before it (all work-groups of
 // the launch are resident); results are published with an agent-scope
@@ -550,12 +499,6 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void launch_dense_panel(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int k0) {
-  if (nwork <= 0) return;
-  k_dense_panel<T><<<dim3((unsigned)nwork), 512, 0, st>>>(insts, work, k0);
-}
-
-template <typename T>
 void launch_dense_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int k0) {
   if (nwork <= 0) return;
   k_dense_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, k0);
@@ -565,7 +508,7 @@ template <typename T>
 void launch_dense_panel_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel,
                              int k0) {
   if (nwork <= 0) return;
-  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 512, 0, st>>>(insts, work, npanel, k0);
+  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
 }
 
 template <typename T>
@@ -575,7 +518,6 @@ void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* wor
 }
 
 #define PF_DINST(T)                                                                        \
-  template void launch_dense_panel<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
   template void launch_dense_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_dense_panel_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int, int); \
   template void launch_dense_trsv<T>(hipStream_t, const Inst* const*, const int2*, int, int);

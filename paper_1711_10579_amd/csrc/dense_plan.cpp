@@ -22,7 +22,7 @@ void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* comb
   for (int s = 0; s < ns; ++s) {
     if (Ms[s] <= k0) continue;
     dense_grid(Ms[s], k0, &kb, &nrt, &nct);
-    for (int g = 0; g < 1 + nrt + nct; ++g) comb->push_back(make_int2(s, g));
+    for (int g = 0; g < 1 + nrt; ++g) comb->push_back(make_int2(s, g));
   }
   *npanel = (int)comb->size();
   if (k0 >= kDenseNB)

@@ -66,6 +66,7 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
     std::vector<Key> tile(items.size());
     std::map<Key, size_t> writer;
     std::vector<std::vector<Key>> rd(items.size());
+    std::vector<size_t> diag_of;  // the items g = 0 of the launch
     for (size_t i = 0; i < items.size(); ++i) {
       const int s = items[i].x;
       const bool panel = (int)i < npanel;
@@ -78,17 +79,17 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
       bool writes_a = true;
       if (panel) {
         const int g = items[i].y;
-        req(g >= 0 && g < 1 + nrt + nct, "dense plan: panel item out of range");
+        req(g >= 0 && g < 1 + nrt, "dense plan: panel item out of range");
         const Key d(s, k, k);
         Key own = d;
-        if (g >= 1 && g <= nrt) own = Key(s, k + kb + 64 * (g - 1), k);
-        if (g > nrt) own = Key(s, k, k + kb + 64 * (g - 1 - nrt));
-        req(std::get<1>(own) < Ms[s] && std::get<2>(own) <= Ms[s], "dense plan: tile out of range");
+        if (g >= 1) own = Key(s, k + kb + 64 * (g - 1), k);
+        req(std::get<1>(own) < Ms[s], "dense plan: tile out of range");
         req(cnt[aligned(d)] == p && !fin.count(d), "dense plan: diagonal block not up to date");
         req(cnt[aligned(own)] == p && !fin.count(own), "dense plan: panel tile not up to date");
         rd[i] = {d, own};
         tile[i] = own;
-        writes_a = g != 0;  // the diagonal work-group stores its factor apart
+        writes_a = g != 0;  // the diagonal work-group stores its inverse apart
+        if (g == 0) diag_of.push_back(i);
       } else {
         const int t = items[i].y;
         req(t >= 0 && t < nrt * nct, "dense plan: update item out of range");
@@ -112,6 +113,18 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
         fin.insert(tile[i]);
       else
         cnt[tile[i]] += 1;
+    }
+    // the block row right of a factored diagonal block is final as it
+    // stands: it must have every earlier step's update
+    for (size_t i : diag_of) {
+      const int s = items[i].x;
+      int kb, nrt, nct;
+      dense_grid(Ms[s], k0, &kb, &nrt, &nct);
+      for (int j = 0; j < nct; ++j) {
+        const Key u(s, k0, k0 + kb + 64 * j);
+        req(cnt[aligned(u)] == k0 / 64 && !fin.count(u), "dense plan: block row not up to date");
+        fin.insert(u);
+      }
     }
   };
   for (int k0 = 0; k0 < maxM; k0 += 64) {

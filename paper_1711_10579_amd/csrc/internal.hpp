@@ -198,14 +198,15 @@ pf_status check_opts(const pf_options* opt);
 // The Newton step's linear solve by GMRES and the voltage update.
 pf_status nk_step(Batch* b, const pf_options* opt);
 
-// Launch plan of the dense block's blocked LU (dense_plan.cpp).  Step k of an
-// instance with dense order M has a kb-wide panel, nrt row tiles below it and
-// nct column tiles right of it (the last holding the right-hand side column
-// M).  Per step k0 over instances of orders Ms: `comb` lists the panel items
-// (slot, g) of step k0 (the first *npanel) followed by the trailing-update
-// tiles (slot, t) of step k0 - 64 away from panel k0's block row and column;
-// `next` lists the update tiles of step k0 in the next panel's block row or
-// column.  Tile t of a step is row tile t % nrt, column tile t / nrt.
+// Launch plan of the dense block's block LU (dense_plan.cpp).  Step k of an
+// instance with dense order M has a kb-wide diagonal block, nrt row tiles
+// below it and nct column tiles right of it (the last holding the right-hand
+// side column M).  Per step k0 over instances of orders Ms: `comb` lists the
+// panel items (slot, g) of step k0 (the first *npanel: g = 0 the diagonal
+// block, g = 1..nrt its row tiles) followed by the trailing-update tiles
+// (slot, t) of step k0 - 64 away from panel k0's block row and column; `next`
+// lists the update tiles of step k0 in the next panel's block row or column.
+// Tile t of a step is row tile t % nrt, column tile t / nrt.
 constexpr int kDenseNB = 64;
 void dense_grid(int M, int k, int* kb, int* nrt, int* nct);
 void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* comb, int* npanel,

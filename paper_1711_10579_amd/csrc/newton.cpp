@@ -139,9 +139,12 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
       for (int s = 0; s < nslots; ++s) {
         if (Ms[s] <= k0) continue;
         dense_grid(Ms[s], k0, &kb, &nrt, &nct);
-        const double rr = Ms[s] - (k0 + kb), rc = Ms[s] + 1 - (k0 + kb);
-        pfl += (2.0 / 3.0) * kb * kb * kb + (double)kb * kb * (rr + rc);
-        pby += 8.0 * (kb * kb + 2.0 * kb * (rr + rc));
+        const double rr = Ms[s] - (k0 + kb);
+        // inverse of the diagonal block (Gauss-Jordan, 2 kb^3) and the row
+        // tiles times it; reads the block once, reads and writes the row
+        // tiles, writes the inverse
+        pfl += 2.0 * kb * kb * kb + 2.0 * kb * kb * rr;
+        pby += 8.0 * (2.0 * kb * kb + 2.0 * kb * rr);
       }
       // update tiles: 2 kb NB^2 flops, read A_ik, A_kj, read+write A_ij
       for (size_t i = npanel; i < comb.size(); ++i) {
