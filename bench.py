@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 # (FP32 vector is 78.6 without packed FP32, which this build does not use).
 # The dominant kernel's flops are mostly its matrix-core update; its time is
 # set by the panel's 64 dependent pivot steps.
-PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_mfma_tflops": 157.3, "fp32_valu_tflops": 78.6}
+PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_mfma_tflops": 157.3, "fp32_valu_tflops": 157.3}
 METRIC = "converged PF solves/s at 1e-8 pu mismatch, batched vs plain; p50/p99 latency"
 
 
@@ -114,6 +114,15 @@ def _roof(st, bound, peak, unit, kernel):
             ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): per}
 
 
+def _with_hbm(roof):
+    """Add the HBM rate the measured traffic implies (bytes per launch over
+    the average launch time) against the 8 TB/s peak."""
+    if roof.get("traffic") and roof.get("avg_launch_ms"):
+        gbs = roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9
+        roof["hbm"] = {"achieved": gbs, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": gbs / PEAK["hbm_gbs"]}
+    return roof
+
+
 def _breakdown(B, ctx, h, opts, tag, solves=3):
     """Every kernel class timed with HIP events over a few extra solves
     (stderr)."""
@@ -184,10 +193,13 @@ def bench_grid10k(args):
     if args.breakdown:
         _breakdown(B, ctx, h, opts, "lu")
 
-    # the dominant kernel (panel steps of the dense block LU) is timed with
-    # HIP events on the library's stream inside the timed region
-    dom, sec = B.PF_K_DENSE_PANEL, B.PF_K_DENSE_UPDATE
-    B.pf_profile_enable(ctx, 1 << dom)
+    # the dominant kernel (the dense block's step launches) is timed with HIP
+    # events on the library's stream inside the timed region (captured into
+    # the replayed Newton-step graph with the kernels)
+    dom = B.PF_K_DENSE_PANEL
+    # one event pair around each Newton step's run of block-step launches
+    # (its time includes the short gaps between them inside the graph)
+    B.pf_profile_enable(ctx, (1 << dom) | B.PF_PROFILE_SPANS)
     B.pf_profile_reset(ctx)
     torch.cuda.synchronize()
     lat, conv, iters = [], 0, []
@@ -201,13 +213,6 @@ def bench_grid10k(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st_dom = B.pf_kernel_stats(ctx, dom)
-    # the matrix-core trailing update, timed the same way in two extra solves
-    # after the timed region
-    B.pf_profile_enable(ctx, 1 << sec)
-    B.pf_profile_reset(ctx)
-    for _ in range(2):
-        B.pf_solve(h, opts)
-    st_sec = B.pf_kernel_stats(ctx, sec)
     B.pf_profile_enable(ctx, 0)
     mism = polar.mismatch_at(case, B.pf_get_voltage(h))
 
@@ -290,12 +295,14 @@ def bench_grid10k(args):
         "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
         "converged": conv,
         "final_mismatch_oracle": mism,
-        "roofline": dict(_roof(st_dom, "mfma", mfma_peak, "TFLOP/s",
-                               "k_dense_panel_gemm (panel of step k: diagonal-block LU + tile solves, "
-                               "beside the matrix-core trailing update of step k-1)"),
-                         traffic=None if mixed else _measured_traffic("k_dense_panel_gemm", sched)),
-        "roofline_secondary": _roof(st_sec, "mfma", mfma_peak, "TFLOP/s",
-                                    "k_dense_gemm (matrix-core update of the next panel's block row and column)"),
+        "roofline": _with_hbm(dict(_roof(st_dom, "mfma", mfma_peak, "TFLOP/s",
+                                         "k_dense_step (block step k of the dense block: diagonal-block inverse "
+                                         "by block Gauss-Jordan, row tiles times it, and the matrix-core trailing "
+                                         "update)"),
+                                   traffic=None if mixed else _measured_traffic("k_dense_step", sched),
+                                   timing="HIP events on the library stream around each Newton step's run of "
+                                          "k_dense_step launches inside the replayed graph; per launch = span / "
+                                          "launches (includes the gaps between them)")),
         "batched": batched,
         "newton_krylov": nk,
         "autotune": tuned,

@@ -267,17 +267,22 @@ pf_status pf_get_voltage(const pf_case* c, double* re, double* im);
 pf_status pf_set_voltage(pf_case* c, const double* re, const double* im);
 
 /* Kernel timing.  pf_profile_enable(ctx, mask) selects kernel classes by bit
- * (1 << class; 0 disables, -1 selects all).  Every launch of a selected class
- * is bracketed by HIP events on the launch stream; pf_kernel_stats returns
- * the launch count, the summed device milliseconds and the summed
- * algorithmic flops and bytes of those launches since the last reset. */
+ * (1 << class; 0 disables, -1 selects every class).  Every launch of a selected class
+ * is bracketed by HIP events on the launch stream (inside the captured graph
+ * when a Newton step is replayed from one); pf_kernel_stats returns the
+ * launch count, the summed device milliseconds and the summed algorithmic
+ * flops and bytes of those launches since the last reset.  With
+ * PF_PROFILE_SPANS in the mask, a run of consecutive launches of one class
+ * in the refactorisation is bracketed as a whole instead (two events per
+ * run; its time then includes the gaps between those launches). */
+#define PF_PROFILE_SPANS (1 << 30)
 typedef enum {
   PF_K_MISMATCH = 0,
   PF_K_JFILL = 1,
   PF_K_SPARSE_FACTOR = 2,
   PF_K_TAIL_SCHUR = 3,
-  PF_K_DENSE_PANEL = 4,
-  PF_K_DENSE_UPDATE = 5,
+  PF_K_DENSE_PANEL = 4,    /* dense block step: diagonal-block inverse, row tiles, trailing update */
+  PF_K_DENSE_UPDATE = 5,   /* not launched: the dense trailing update runs in the block-step launch */
   PF_K_SPARSE_FWD = 6,
   PF_K_SPARSE_BWD = 7,
   PF_K_DENSE_TRSV = 8,

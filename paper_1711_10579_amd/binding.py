@@ -440,8 +440,12 @@ def pf_set_voltage(case, V):
     _check(_lib.pf_set_voltage(case.handle, _dptr(re), _dptr(im)), "pf_set_voltage")
 
 
+PF_PROFILE_SPANS = 1 << 30
+
+
 def pf_profile_enable(ctx, mask=-1):
-    """Instrument the kernel classes whose bit (1 << class) is set in mask."""
+    """Instrument the kernel classes whose bit (1 << class) is set in mask
+    (with PF_PROFILE_SPANS: one event pair per run of consecutive launches)."""
     _check(_lib.pf_profile_enable(ctx.handle, int(mask)), "pf_profile_enable")
 
 

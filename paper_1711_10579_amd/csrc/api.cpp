@@ -49,43 +49,79 @@ void Ctx::prof_begin(int cls, hipEvent_t* a) {
   *a = nullptr;
   if (!(profile_mask & (1 << cls))) return;
   hipEvent_t e;
-  if (!evpool.empty()) {
+  if (capture) {
+    if (cap_pool.empty()) {
+      capture_bad = true;
+      return;
+    }
+    e = cap_pool.back();
+    cap_pool.pop_back();
+  } else if (!evpool.empty()) {
     e = evpool.back();
     evpool.pop_back();
   } else if (hipEventCreate(&e) != hipSuccess) {
     return;
   }
-  (void)hipEventRecord(e, stream);
+  // inside a stream capture the record becomes an event node of the graph
+  if (capture) {
+    if (hipEventRecordWithFlags(e, stream, hipEventRecordExternal) != hipSuccess) capture_bad = true;
+  } else {
+    (void)hipEventRecord(e, stream);
+  }
   *a = e;
 }
 
-void Ctx::prof_end(int cls, hipEvent_t a, double flops, double bytes) {
+void Ctx::prof_end(int cls, hipEvent_t a, double flops, double bytes, int nl) {
   if (!a) return;
   hipEvent_t b;
-  if (!evpool.empty()) {
+  if (capture) {
+    if (cap_pool.empty()) {
+      capture_bad = true;
+      cap_pool.push_back(a);
+      return;
+    }
+    b = cap_pool.back();
+    cap_pool.pop_back();
+  } else if (!evpool.empty()) {
     b = evpool.back();
     evpool.pop_back();
   } else if (hipEventCreate(&b) != hipSuccess) {
     evpool.push_back(a);
     return;
   }
-  (void)hipEventRecord(b, stream);
-  pending.push_back({cls, a, b, flops, bytes});
+  if (capture) {
+    if (hipEventRecordWithFlags(b, stream, hipEventRecordExternal) != hipSuccess) capture_bad = true;
+    capture->push_back({cls, a, b, flops, bytes, false, nl});
+  } else {
+    (void)hipEventRecord(b, stream);
+    pending.push_back({cls, a, b, flops, bytes, true, nl});
+  }
 }
 
 void Ctx::prof_flush() {
   for (auto& p : pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      stats[p.cls].launches += 1;
+      stats[p.cls].launches += p.nl;
       stats[p.cls].ms += ms;
       stats[p.cls].flops += p.flops;
       stats[p.cls].bytes += p.bytes;
+    } else {
+      (void)hipGetLastError();  // an unread pair is dropped, not a device failure
     }
-    evpool.push_back(p.a);
-    evpool.push_back(p.b);
+    if (p.pooled) {
+      evpool.push_back(p.a);
+      evpool.push_back(p.b);
+    }
   }
   pending.clear();
+}
+
+pf_status launch_status(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) return PF_OK;
+  set_error(std::string(where) + ": device error " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+  return PF_E_DEVICE;
 }
 
 bool finite_all(const double* p, int64_t n) {
@@ -425,7 +461,8 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   total += carve_size<int>(n) + carve_size<int>(nu);
   total += 2 * carve_size<double>(n) + 2 * carve_size<double>(2LL * n) + carve_size<double>(2LL * nu);
   total += carve_size<double>(2LL * nu) + carve_size<double>(c->lu_count()) + carve_size<double>(4LL * ns) +
-           carve_size<double>(c->tail_count()) + 2 * carve_size<double>(c->dfac_count()) + carve_size<int>(c->nblk());
+           carve_size<double>(c->tail_count()) + carve_size<double>(c->dinvu_count()) + carve_size<int>(c->nblk()) +
+           carve_size<unsigned long long>(c->nblk());
   total += carve_size<int>(ns + 1) + carve_size<int>(an.nnzl) + carve_size<int64_t>(c->ntg + 1) +
            2 * carve_size<int>(nupd) + carve_size<int>(ns);
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
@@ -461,9 +498,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   c->lu = carve<double>(p, c->lu_count());
   c->dinv = carve<double>(p, 4LL * ns);
   c->tail = carve<double>(p, c->tail_count());
-  c->dfac = carve<double>(p, c->dfac_count());
-  c->dinvu = carve<double>(p, c->dfac_count());
+  c->dinvu = carve<double>(p, c->dinvu_count());
   c->dflags = carve<int>(p, c->nblk());
+  c->pflags = carve<unsigned long long>(p, c->nblk());
   c->colptr = carve<int>(p, ns + 1);
   c->rowidx = carve<int>(p, an.nnzl);
   c->uptr = carve<int64_t>(p, c->ntg + 1);
@@ -523,6 +560,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   ok &= up(c->bwd_rows, an.bwd_rows.data(), sizeof(int) * ns);
   ok &= hipMemsetAsync(c->red, 0, sizeof(pfd::Red), s) == hipSuccess;
   ok &= hipMemsetAsync(c->dflags, 0, sizeof(int) * std::max(c->nblk(), 1), s) == hipSuccess;
+  ok &= hipMemsetAsync(c->pflags, 0, sizeof(unsigned long long) * std::max(c->nblk(), 1), s) == hipSuccess;
   {
     pfd::Inst hi;
     std::memset(&hi, 0, sizeof hi);
@@ -561,9 +599,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     hi.lu = c->lu;
     hi.dinv = c->dinv;
     hi.tail = c->tail;
-    hi.dfac = c->dfac;
     hi.dinvu = c->dinvu;
     hi.dflags = c->dflags;
+    hi.pflags = c->pflags;
     hi.colptr = c->colptr;
     hi.rowidx = c->rowidx;
     hi.upd_l = c->upd_l;
@@ -811,7 +849,8 @@ pf_status pf_profile_enable(pf_ctx* ctx, int32_t class_mask) {
     set_error("pf_profile_enable: NULL context");
     return PF_E_INVALID;
   }
-  ctx->profile_mask = class_mask;
+  // -1: every class, one event pair per launch
+  ctx->profile_mask = class_mask == -1 ? (1 << PF_K_COUNT) - 1 : class_mask;
   return PF_OK;
 }
 

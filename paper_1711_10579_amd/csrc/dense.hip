@@ -179,6 +179,13 @@ constexpr int kGemmLd = NB + 2;
 constexpr int kDenseSmem = 2 * NB * kGemmLd > NB * kPanelTileLd + 8 * kStage ? 2 * NB * kGemmLd
                                                                               : NB * kPanelTileLd + 8 * kStage;
 
+// Value of a row block's panel flag once the panel of block step k0 has
+// stored its tile in Newton step `epoch` (epochs only grow, so every earlier
+// value is smaller).
+__device__ inline unsigned long long panel_flag(int epoch, int k0) {
+  return ((unsigned long long)(unsigned)epoch << 20) | (unsigned long long)(k0 / NB + 1);
+}
+
 // Panel step k0 of every instance in the work list: item (slot, g), four
 // waves.  Every work-group inverts the diagonal block D = A_kk (identity-
 // padded to 64x64) by block Gauss-Jordan over 4x4 blocks of 16: wave j keeps
@@ -189,7 +196,7 @@ constexpr int kDenseSmem = 2 * NB * kGemmLd > NB * kPanelTileLd + 8 * kStage ? 2
 //   g = 0:        P is stored (column-major) for the backward solve;
 //   g in 1..nrt:  row tile i = g - 1 below the block: L_ik = A_ik P,
 //                 computed transposed (P^T A_ik^T) so that consecutive lanes
-//                 store consecutive rows.
+//                 store consecutive rows; then the row block's flag is set.
 template <typename T>
 __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0, T* smem) {
   T* xs = smem;                           // the row tile, column-major [NB][kPanelTileLd]
@@ -289,27 +296,43 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       if (rr < nr && cc < kb) A[(int64_t)(k0 + cc) * ld + r0 + rr] = acc[e];
     }
   }
+  // publish the tile to the update work-groups of the same launch that wait
+  // for it: every wave's stores are released before the flag is set
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&I.pflags[r0 / NB], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Trailing update A_ij -= L_ik A_kj on 64x64 tiles (rows and columns after
-// the panel, the right-hand side column included), on the matrix cores: four
+// Trailing update of one 64x64 tile A_ij (rows and columns after the panel
+// of step k0, the right-hand side column included) on the matrix cores: four
 // waves, each a 32x32 quarter of the tile as 2x2 blocks of 16x16, K = 64 in
-// steps of 4 (zero-padded past kb).  Both operands sit k-major in LDS so that
-// each quarter-wave reads 16 consecutive values; the tile A_ij is loaded with
-// them, straight into the accumulators, and L_ik is staged negated.
+// steps of 4 (zero-padded past the panel width).  Item (slot, t | mode << 24),
+// tile t = row tile t % nrt, column tile t / nrt of step k0's grid:
+//   mode bit 0:  A_ij -= L_{i,k-1} A_{k-1,j} (the previous step's update);
+//   mode bit 1:  A_ij -= L_ik A_kj once the panel work-group of row block i
+//                in the same launch has set its flag (the tiles of the next
+//                panel's block row and column).
+// The tile is loaded with the first operands, straight into the
+// accumulators; operands sit k-major in LDS (L negated) so that each
+// quarter-wave reads 16 consecutive values.
 template <typename T>
 __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0, T* smem) {
-  T(*sa)[kGemmLd] = (T(*)[kGemmLd])smem;              // [k][row]
+  T(*sa)[kGemmLd] = (T(*)[kGemmLd])smem;                   // [k][row]
   T(*sb)[kGemmLd] = (T(*)[kGemmLd])(smem + NB * kGemmLd);  // [k][col]
+  __shared__ int abort_wait;
   const Inst& I = *insts[wk.x];
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
   const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
   const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
+  const int t = __builtin_amdgcn_readfirstlane(wk.y & 0xffffff);
+  const int mode = __builtin_amdgcn_readfirstlane(wk.y >> 24);
   const int tid = threadIdx.x;
-  const int r0 = k0 + kb + (wk.y % nrt) * NB;
-  const int c0 = k0 + kb + (wk.y / nrt) * NB;
+  const int r0 = k0 + kb + (t % nrt) * NB;
+  const int c0 = k0 + kb + (t / nrt) * NB;
   const int nr = min(NB, M - r0);
   const int nc = min(NB, M + 1 - c0);
   const int lane = tid % 64, w = tid / 64;
@@ -318,7 +341,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   typedef typename Mfma<T>::v4 v4;
   const auto G = gp((const T*)A);
   // every load of a thread in flight at once (addresses clamped into the
-  // tile, values masked afterwards)
+  // tiles, values masked afterwards)
   v4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -329,44 +352,88 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
         const int r = rb + bi * 16 + li, c = cb + bj * 16 + Mfma<T>::row(lane, e);
         acc[bi][bj][e] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + r0 + min(r, nr - 1)];
       }
-  T va[16], vb[16];
+  // operands of the step at column kp (width kw): L rows r0.., columns
+  // kp..; U rows kp.., columns c0..
+  auto load_l = [&](int kp, int kw, T (&va)[16]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q;
-    const int r = idx % NB, k = idx / NB;
-    va[q] = G[(int64_t)(k0 + min(k, kb - 1)) * ld + r0 + min(r, nr - 1)];
-  }
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx % NB, k = idx / NB;
+      va[q] = G[(int64_t)(kp + min(k, kw - 1)) * ld + r0 + min(r, nr - 1)];
+    }
+  };
+  auto load_u = [&](int kp, int kw, T (&vb)[16]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q;
-    const int k = idx % NB, c = idx / NB;
-    vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + k0 + min(k, kb - 1)];
-  }
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx % NB, c = idx / NB;
+      vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + kp + min(k, kw - 1)];
+    }
+  };
+  auto stage = [&](int kw, const T (&va)[16], const T (&vb)[16]) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q;
-    const int r = idx % NB, k = idx / NB;
-    sa[k][r] = (r < nr && k < kb) ? -va[q] : T(0);
-  }
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx % NB, k = idx / NB;
+      sa[k][r] = (r < nr && k < kw) ? -va[q] : T(0);
+    }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q;
-    const int k = idx % NB, c = idx / NB;
-    sb[k][c] = (c < nc && k < kb) ? vb[q] : T(0);
-  }
-  __syncthreads();
-  // the transposed product (L_ik A_kj)^T = A_kj^T L_ik^T: the matrix core's
-  // first operand is the column block, so a lane's result row is a tile
-  // column and its lane index within 16 a tile row -- consecutive lanes then
-  // update consecutive rows of the column-major tile
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q;
+      const int k = idx % NB, c = idx / NB;
+      sb[k][c] = (c < nc && k < kw) ? vb[q] : T(0);
+    }
+  };
+  // the transposed product (L U)^T = U^T L^T: the matrix core's first
+  // operand is the column block, so a lane's result row is a tile column and
+  // its lane index within 16 a tile row -- consecutive lanes then update
+  // consecutive rows of the column-major tile
+  auto mma = [&]() {
 #pragma unroll 4
-  for (int ks = 0; ks < NB; ks += 4) {
-    T a0 = sa[ks + lk][rb + li], a1 = sa[ks + lk][rb + 16 + li];
-    T b0 = sb[ks + lk][cb + li], b1 = sb[ks + lk][cb + 16 + li];
-    acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
-    acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
-    acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
-    acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
+    for (int ks = 0; ks < NB; ks += 4) {
+      T a0 = sa[ks + lk][rb + li], a1 = sa[ks + lk][rb + 16 + li];
+      T b0 = sb[ks + lk][cb + li], b1 = sb[ks + lk][cb + 16 + li];
+      acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
+      acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
+      acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
+      acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
+    }
+  };
+  T va[16], vb[16], vu[16];
+  // this step's U tile is final before the launch: fetched at once
+  if (mode & 2) load_u(k0, kb, vu);
+  if (mode & 1) {
+    load_l(k0 - NB, NB, va);
+    load_u(k0 - NB, NB, vb);
+    stage(NB, va, vb);
+    __syncthreads();
+    mma();
+  }
+  if (mode & 2) {
+    if (tid == 0) {
+      // poll without ordering, then one acquire once the flag is seen;
+      // bounded: on expiry the instance records a timeout
+      const unsigned long long want = panel_flag(I.red->epoch, k0);
+      long spins = 0;
+      int ab = 0;
+      while (__hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        if (++spins > (1l << 22)) {
+          ab = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      abort_wait = ab;
+      if (ab) I.red->timeout = 1;
+    }
+    // also separates the previous product's LDS reads from the new stores
+    __syncthreads();
+    if (abort_wait) return;
+    load_l(k0, kb, va);
+    stage(kb, va, vu);
+    __syncthreads();
+    mma();
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -381,26 +448,22 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
     }
 }
 
+// Block step k0 in one launch: the panel of step k0 (items [0, npanel)),
+// then the trailing-update tiles right of and below it -- the previous
+// step's update and, for the next panel's block row and column, this step's
+// too.  Those wait for the panel work-groups of their row block, which come
+// first in the launch (work-groups start in index order), so every wait ends.
+// Apart from those flagged tiles the items touch disjoint tiles: the panel
+// reads its block column, brought up to date by the previous launch, and
+// writes its row tiles; the updates write only tiles right of that column.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_gemm(const Inst* const* insts, const int2* __restrict__ work,
-                                                    int k0) {
-  __shared__ T smem[2 * NB * kGemmLd];
-  gemm_tile<T>(insts, work[blockIdx.x], k0, smem);
-}
-
-// Look-ahead: the panel of step k0 (items [0, npanel)) together with the
-// trailing update of step k0 - 64 outside the block row and column of panel
-// k0 (the other items).  The two touch disjoint tiles: the panel reads only
-// its block column, which the previous launch brought up to date, and writes
-// its row tiles; the update writes only tiles right of and below them.
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_panel_gemm(const Inst* const* insts, const int2* __restrict__ work,
-                                                          int npanel, int k0) {
+__global__ __launch_bounds__(256) void k_dense_step(const Inst* const* insts, const int2* __restrict__ work,
+                                                    int npanel, int k0) {
   __shared__ T smem[kDenseSmem];
   if ((int)blockIdx.x < npanel)
     panel_step<T>(insts, work[blockIdx.x], k0, smem);
   else
-    gemm_tile<T>(insts, work[blockIdx.x], k0 - NB, smem);
+    gemm_tile<T>(insts, work[blockIdx.x], k0, smem);
 }
 
 // Block backward solve (z in column M): by 64-row blocks, acc = z_b -
@@ -499,16 +562,9 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void launch_dense_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int k0) {
+void launch_dense_step(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel, int k0) {
   if (nwork <= 0) return;
-  k_dense_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, k0);
-}
-
-template <typename T>
-void launch_dense_panel_gemm(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel,
-                             int k0) {
-  if (nwork <= 0) return;
-  k_dense_panel_gemm<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
+  k_dense_step<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
 }
 
 template <typename T>
@@ -518,8 +574,7 @@ void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* wor
 }
 
 #define PF_DINST(T)                                                                        \
-  template void launch_dense_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
-  template void launch_dense_panel_gemm<T>(hipStream_t, const Inst* const*, const int2*, int, int, int); \
+  template void launch_dense_step<T>(hipStream_t, const Inst* const*, const int2*, int, int, int); \
   template void launch_dense_trsv<T>(hipStream_t, const Inst* const*, const int2*, int, int);
 
 PF_DINST(double)

@@ -13,32 +13,29 @@ void dense_grid(int M, int k, int* kb, int* nrt, int* nct) {
   *nct = (M + 1 - (k + *kb) + kDenseNB - 1) / kDenseNB;
 }
 
-void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* comb, int* npanel,
-                     std::vector<int2>* next) {
-  comb->clear();
-  next->clear();
+void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* npanel) {
+  items->clear();
   const int ns = (int)Ms.size();
   int kb, nrt, nct;
   for (int s = 0; s < ns; ++s) {
     if (Ms[s] <= k0) continue;
     dense_grid(Ms[s], k0, &kb, &nrt, &nct);
-    for (int g = 0; g < 1 + nrt; ++g) comb->push_back(make_int2(s, g));
+    for (int g = 0; g < 1 + nrt; ++g) items->push_back(make_int2(s, g));
   }
-  *npanel = (int)comb->size();
-  if (k0 >= kDenseNB)
+  *npanel = (int)items->size();
+  // tiles of the next panel's block row and column first (they wait for the
+  // panel), then the rest of the previous step's update
+  for (int pass = 0; pass < 2; ++pass)
     for (int s = 0; s < ns; ++s) {
-      const int k = k0 - kDenseNB;
-      if (Ms[s] <= k) continue;
-      dense_grid(Ms[s], k, &kb, &nrt, &nct);
-      for (int t = 0; t < nrt * nct; ++t)
-        if (t % nrt >= 1 && t / nrt >= 1) comb->push_back(make_int2(s, t));
+      if (Ms[s] <= k0) continue;
+      dense_grid(Ms[s], k0, &kb, &nrt, &nct);
+      for (int t = 0; t < nrt * nct; ++t) {
+        const bool next = t % nrt == 0 || t / nrt == 0;
+        if (next != (pass == 0)) continue;
+        const int mode = (k0 >= kDenseNB ? kDenseUpdPrev : 0) | (next ? kDenseUpdThis : 0);
+        if (mode) items->push_back(make_int2(s, t | mode << 24));
+      }
     }
-  for (int s = 0; s < ns; ++s) {
-    if (Ms[s] <= k0) continue;
-    dense_grid(Ms[s], k0, &kb, &nrt, &nct);
-    for (int t = 0; t < nrt * nct; ++t)
-      if (t % nrt == 0 || t / nrt == 0) next->push_back(make_int2(s, t));
-  }
 }
 
 }  // namespace pfi

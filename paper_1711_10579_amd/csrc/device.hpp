@@ -52,8 +52,11 @@ struct Inst {
   const double *psp, *qsp, *vmag, *vang, *zip;
   const int *pos, *node;
   double *vm, *va, *v, *ibus, *F;
-  void *x, *lu, *dinv, *tail, *dfac, *dinvu;
+  void *x, *lu, *dinv, *tail, *dinvu;
   int* dflags;
+  // per 64-row block i of the dense block: (epoch << 20) | (k + 1) once the
+  // panel of block step k has stored its tile L_ik
+  unsigned long long* pflags;
   const int *colptr, *rowidx, *upd_l, *upd_u;
   const int64_t* uptr;
   const int *tail_tgt, *tail_l, *tail_u;

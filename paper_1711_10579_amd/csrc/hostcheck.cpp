@@ -61,77 +61,93 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
   const int ns = (int)Ms.size();
   int maxM = 0;
   for (int s = 0; s < ns; ++s) maxM = std::max(maxM, Ms[s]);
-  std::vector<int2> comb, next;
-  auto run = [&](const std::vector<int2>& items, int npanel, int k0, int kupd) {
-    std::vector<Key> tile(items.size());
-    std::map<Key, size_t> writer;
+  std::vector<int2> items;
+  for (int k0 = 0; k0 < maxM; k0 += 64) {
+    int npanel = 0;
+    dense_plan_step(Ms, k0, &items, &npanel);
+    const int p = k0 / 64;
+    std::map<Key, size_t> writer;               // tile -> item writing it
+    std::map<std::pair<int, int>, size_t> pan;  // (slot, row) -> panel item of that row tile
     std::vector<std::vector<Key>> rd(items.size());
-    std::vector<size_t> diag_of;  // the items g = 0 of the launch
+    std::vector<std::pair<Key, size_t>> flag_rd;  // tiles read after a flag, with the reader
+    std::vector<Key> upd;                         // tiles updated, once per update applied
+    std::set<int> diag_slots;
     for (size_t i = 0; i < items.size(); ++i) {
       const int s = items[i].x;
-      const bool panel = (int)i < npanel;
-      const int k = panel ? k0 : kupd;
-      req(s >= 0 && s < ns && Ms[s] > k, "dense plan: item of a finished instance");
+      req(s >= 0 && s < ns && Ms[s] > k0, "dense plan: item of a finished instance");
       int kb, nrt, nct;
-      dense_grid(Ms[s], k, &kb, &nrt, &nct);
-      const int p = k / 64;
+      dense_grid(Ms[s], k0, &kb, &nrt, &nct);
       ++*nchk;
-      bool writes_a = true;
-      if (panel) {
+      if ((int)i < npanel) {
         const int g = items[i].y;
         req(g >= 0 && g < 1 + nrt, "dense plan: panel item out of range");
-        const Key d(s, k, k);
-        Key own = d;
-        if (g >= 1) own = Key(s, k + kb + 64 * (g - 1), k);
-        req(std::get<1>(own) < Ms[s], "dense plan: tile out of range");
+        const Key d(s, k0, k0);
         req(cnt[aligned(d)] == p && !fin.count(d), "dense plan: diagonal block not up to date");
+        if (g == 0) {
+          req(diag_slots.insert(s).second, "dense plan: two diagonal items of an instance");
+          rd[i] = {d};
+          continue;
+        }
+        const Key own(s, k0 + kb + 64 * (g - 1), k0);
+        req(std::get<1>(own) < Ms[s], "dense plan: tile out of range");
         req(cnt[aligned(own)] == p && !fin.count(own), "dense plan: panel tile not up to date");
         rd[i] = {d, own};
-        tile[i] = own;
-        writes_a = g != 0;  // the diagonal work-group stores its inverse apart
-        if (g == 0) diag_of.push_back(i);
-      } else {
-        const int t = items[i].y;
-        req(t >= 0 && t < nrt * nct, "dense plan: update item out of range");
-        const int r0 = k + kb + 64 * (t % nrt), c0 = k + kb + 64 * (t / nrt);
-        req(r0 < Ms[s] && c0 <= Ms[s] && r0 % 64 == 0 && c0 % 64 == 0, "dense plan: update tile off the grid");
-        const Key x(s, r0, c0), l(s, r0, k), u(s, k, c0);
-        req(cnt[x] == p && !fin.count(x), "dense plan: updated tile not up to date");
-        req(fin.count(l) && fin.count(u), "dense plan: update before its panel");
-        rd[i] = {l, u, x};
-        tile[i] = x;
+        req(writer.emplace(own, i).second, "dense plan: two items of a launch write one tile");
+        pan[{s, std::get<1>(own)}] = i;
+        continue;
       }
-      if (writes_a) req(writer.emplace(tile[i], i).second, "dense plan: two items of a launch write one tile");
+      const int t = items[i].y & 0xffffff, mode = items[i].y >> 24;
+      req(t >= 0 && t < nrt * nct && mode >= 1 && mode <= 3, "dense plan: update item out of range");
+      const int r0 = k0 + kb + 64 * (t % nrt), c0 = k0 + kb + 64 * (t / nrt);
+      req(r0 < Ms[s] && c0 <= Ms[s] && r0 % 64 == 0 && c0 % 64 == 0, "dense plan: update tile off the grid");
+      const Key x(s, r0, c0);
+      req(cnt[x] == p - ((mode & kDenseUpdPrev) ? 1 : 0) && !fin.count(x), "dense plan: updated tile not up to date");
+      rd[i].push_back(x);
+      if (mode & kDenseUpdPrev) {
+        req(k0 >= 64, "dense plan: update of a step before the first");
+        const Key l(s, r0, k0 - 64), u(s, k0 - 64, c0);
+        req(fin.count(l) && fin.count(u), "dense plan: update before its panel");
+        rd[i].push_back(l);
+        rd[i].push_back(u);
+        upd.push_back(x);
+      }
+      if (mode & kDenseUpdThis) {
+        req(t % nrt == 0 || t / nrt == 0, "dense plan: early update away from the next panel");
+        const Key u(s, k0, c0);
+        req(cnt[aligned(u)] == p && !fin.count(u), "dense plan: block row not up to date");
+        rd[i].push_back(u);
+        flag_rd.push_back({Key(s, r0, k0), i});
+        upd.push_back(x);
+      }
+      req(writer.emplace(x, i).second, "dense plan: two items of a launch write one tile");
     }
+    // plain reads see no tile written in the launch; a tile read after a
+    // flag is the row tile of a panel work-group listed earlier
     for (size_t j = 0; j < items.size(); ++j)
       for (const Key& r : rd[j]) {
         auto it = writer.find(r);
         req(it == writer.end() || it->second == j, "dense plan: an item reads a tile written in its launch");
       }
-    for (size_t i = 0; i < items.size(); ++i) {
-      if ((int)i < npanel)
-        fin.insert(tile[i]);
-      else
-        cnt[tile[i]] += 1;
+    for (const auto& fr : flag_rd) {
+      auto it = pan.find({std::get<0>(fr.first), std::get<1>(fr.first)});
+      req(it != pan.end() && it->second < fr.second, "dense plan: a flag wait on a later or missing work-group");
     }
-    // the block row right of a factored diagonal block is final as it
-    // stands: it must have every earlier step's update
-    for (size_t i : diag_of) {
-      const int s = items[i].x;
+    for (const auto& kv : writer)
+      if ((int)kv.second < npanel) fin.insert(kv.first);
+    for (int s : diag_slots) {
       int kb, nrt, nct;
       dense_grid(Ms[s], k0, &kb, &nrt, &nct);
+      fin.insert(Key(s, k0, k0));
+      // the block row right of the diagonal block is final as it stands
       for (int j = 0; j < nct; ++j) {
         const Key u(s, k0, k0 + kb + 64 * j);
-        req(cnt[aligned(u)] == k0 / 64 && !fin.count(u), "dense plan: block row not up to date");
+        req(cnt[aligned(u)] == p && !fin.count(u), "dense plan: block row not up to date");
         fin.insert(u);
       }
     }
-  };
-  for (int k0 = 0; k0 < maxM; k0 += 64) {
-    int npanel = 0;
-    dense_plan_step(Ms, k0, &comb, &npanel, &next);
-    run(comb, npanel, k0, k0 - 64);
-    run(next, 0, k0, k0);
+    for (int s = 0; s < ns; ++s)
+      req(Ms[s] <= k0 || diag_slots.count(s), "dense plan: an instance misses its panel");
+    for (const Key& x : upd) cnt[x] += 1;
   }
   for (int s = 0; s < ns; ++s) {
     const int R = (Ms[s] + 63) / 64, C = (Ms[s] + 1 + 63) / 64;

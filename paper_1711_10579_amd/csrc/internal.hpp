@@ -21,6 +21,8 @@
 namespace pfi {
 
 void set_error(const std::string& msg);
+// PF_OK, or PF_E_DEVICE with the last HIP error named (and cleared)
+pf_status launch_status(const char* where);
 
 struct Server;
 struct Batch;
@@ -29,6 +31,8 @@ struct PendingEvent {
   int cls;
   hipEvent_t a, b;
   double flops, bytes;
+  bool pooled;  // events return to the pool once read (else a graph owns them)
+  int nl;       // launches between the two events
 };
 
 struct Ctx {
@@ -42,6 +46,12 @@ struct Ctx {
   pf_kernel_stat stats[PF_K_COUNT] = {};
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> evpool;
+  // while a graph is captured: timing events come from cap_pool (made
+  // before the capture) and are listed here instead of in `pending`;
+  // capture_bad records a failed record or an empty pool
+  std::vector<PendingEvent>* capture = nullptr;
+  std::vector<hipEvent_t> cap_pool;
+  bool capture_bad = false;
   std::atomic<int> ncases{0};
   std::shared_ptr<Server> server;  // created by serve.cpp (complete type there)
   std::mutex launch_mu;  // serialises launches of the serving thread and callers
@@ -53,7 +63,7 @@ struct Ctx {
   void* dalloc(size_t bytes);
   void dfree(void* p);
   void prof_begin(int cls, hipEvent_t* a);
-  void prof_end(int cls, hipEvent_t a, double flops, double bytes);
+  void prof_end(int cls, hipEvent_t a, double flops, double bytes, int nl = 1);
   void prof_flush();  // after a stream synchronisation
 };
 
@@ -89,8 +99,9 @@ struct Case {
   double *psp = nullptr, *qsp = nullptr, *vmag = nullptr, *vang = nullptr, *zip = nullptr;
   int *pos = nullptr, *node = nullptr;
   double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
-  void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dfac = nullptr, *dinvu = nullptr;
+  void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dinvu = nullptr;
   int* dflags = nullptr;  // per 64-row block of the dense block: backward-solve flags
+  unsigned long long* pflags = nullptr;  // per 64-row block: panel-tile flags
   int *colptr = nullptr, *rowidx = nullptr, *upd_l = nullptr, *upd_u = nullptr, *col_order = nullptr;
   int64_t* uptr = nullptr;
   int *tail_tgt = nullptr, *tail_l = nullptr, *tail_u = nullptr;
@@ -111,7 +122,7 @@ struct Case {
   int64_t lu_count() const { return 4LL * (an.ns + 2 * an.nnzl); }
   int64_t tail_count() const { return (int64_t)an.ldt * (M + 1); }
   int nblk() const { return (M + 63) / 64; }
-  int64_t dfac_count() const { return (int64_t)nblk() * 64 * 64; }
+  int64_t dinvu_count() const { return (int64_t)nblk() * 64 * 64; }
 };
 
 // One kernel launch of the linear-solve sequence of a batch.
@@ -124,7 +135,7 @@ struct Launch {
   int count;       // work items
   double flops, bytes;
 };
-enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_GEMM, L_TRSV, L_BWD };
+enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_TRSV, L_BWD };
 
 // A batch of cases: device instance table, flattened work lists and the
 // launch sequence of one Newton step's LU solve.  Each item's arithmetic
@@ -155,6 +166,9 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     double tol = 0;
     int max_iter = -1;
+    int prof_mask = 0;                // kernel classes timed inside the graph
+    std::vector<PendingEvent> prof;  // their event pairs, owned by the graph
+    void reset();
   } graphs[2];
 
   bool kbuilt = false;
@@ -198,19 +212,21 @@ pf_status check_opts(const pf_options* opt);
 // The Newton step's linear solve by GMRES and the voltage update.
 pf_status nk_step(Batch* b, const pf_options* opt);
 
-// Launch plan of the dense block's block LU (dense_plan.cpp).  Step k of an
-// instance with dense order M has a kb-wide diagonal block, nrt row tiles
-// below it and nct column tiles right of it (the last holding the right-hand
-// side column M).  Per step k0 over instances of orders Ms: `comb` lists the
-// panel items (slot, g) of step k0 (the first *npanel: g = 0 the diagonal
-// block, g = 1..nrt its row tiles) followed by the trailing-update tiles
-// (slot, t) of step k0 - 64 away from panel k0's block row and column; `next`
-// lists the update tiles of step k0 in the next panel's block row or column.
-// Tile t of a step is row tile t % nrt, column tile t / nrt.
+// Launch plan of the dense block's block LU (dense_plan.cpp), one launch per
+// 64-wide block step.  Step k of an instance with dense order M has a
+// kb-wide diagonal block, nrt row tiles below it and nct column tiles right
+// of it (the last holding the right-hand side column M); tile t of the step
+// is row tile t % nrt, column tile t / nrt.  Per step k0 over instances of
+// orders Ms, `items` lists the panel items (slot, g) of step k0 (the first
+// *npanel: g = 0 the diagonal block, g = 1..nrt its row tiles), then the
+// update items (slot, t | mode << 24): mode kDenseUpdPrev applies step
+// k0 - 64's update to the tile, kDenseUpdThis step k0's (after the panel of
+// the tile's row block, in the same launch; the tiles of the next panel's
+// block row and column, listed first).
 constexpr int kDenseNB = 64;
+constexpr int kDenseUpdPrev = 1, kDenseUpdThis = 2;
 void dense_grid(int M, int k, int* kb, int* nrt, int* nct);
-void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* comb, int* npanel,
-                     std::vector<int2>* next);
+void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* npanel);
 
 // Run the Newton iteration of every case of a built batch to completion.
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);

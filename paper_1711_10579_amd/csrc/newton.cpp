@@ -23,13 +23,24 @@ constexpr int NB = 64;
 }  // namespace
 
 Batch::~Batch() {
-  if ((dmem || kmem) && ctx) {
+  if (ctx) {
+    // the graphs' timing events may still be queued for reading
     (void)hipStreamSynchronize(ctx->stream);
+    ctx->prof_flush();
     if (dmem) ctx->dfree(dmem);
     if (kmem) ctx->dfree(kmem);
   }
-  for (auto& g : graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : graphs) g.reset();
+}
+
+void Batch::Graph::reset() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  exec = nullptr;
+  for (auto& p : prof) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  prof.clear();
 }
 
 bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
@@ -123,18 +134,17 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
     emit(L_SCHUR, PF_K_TAIL_SCHUR, gs, 0, schur, sfl, sby);
   }
-  // dense block, per 64-wide step k0: one launch with the panel of step k0
-  // and the trailing update of step k0 - 64 away from the panel's block row
-  // and column, then the update of the next panel's block row and column
-  // (tiles a = 0 or b = 0 of the step's row x column tile grid)
+  // dense block, per 64-wide step k0: one launch with the panel of step k0,
+  // the previous step's update of every tile right of and below it, and
+  // this step's update of the next panel's block row and column
   {
     std::vector<int> Ms(nslots);
     for (int s = 0; s < nslots; ++s) Ms[s] = cs[s]->M;
-    std::vector<int2> comb, next;
+    std::vector<int2> items;
     for (int k0 = 0; k0 < max_M; k0 += NB) {
       int npanel = 0;
-      dense_plan_step(Ms, k0, &comb, &npanel, &next);
-      double pfl = 0, pby = 0, gfl = 0, gby = 0, nfl = 0, nby = 0;
+      dense_plan_step(Ms, k0, &items, &npanel);
+      double fl = 0, by = 0;
       int kb, nrt, nct;
       for (int s = 0; s < nslots; ++s) {
         if (Ms[s] <= k0) continue;
@@ -143,22 +153,25 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
         // inverse of the diagonal block (Gauss-Jordan, 2 kb^3) and the row
         // tiles times it; reads the block once, reads and writes the row
         // tiles, writes the inverse
-        pfl += 2.0 * kb * kb * kb + 2.0 * kb * kb * rr;
-        pby += 8.0 * (2.0 * kb * kb + 2.0 * kb * rr);
+        fl += 2.0 * kb * kb * kb + 2.0 * kb * kb * rr;
+        by += 8.0 * (2.0 * kb * kb + 2.0 * kb * rr);
       }
-      // update tiles: 2 kb NB^2 flops, read A_ik, A_kj, read+write A_ij
-      for (size_t i = npanel; i < comb.size(); ++i) {
-        dense_grid(Ms[comb[i].x], k0 - NB, &kb, &nrt, &nct);
-        gfl += 2.0 * NB * NB * kb;
-        gby += 8.0 * 4.0 * NB * NB;
+      // per update of a tile: 2 kb NB^2 flops, read L_ik and A_kj, read and
+      // write A_ij (once per item)
+      for (size_t i = npanel; i < items.size(); ++i) {
+        const int mode = items[i].y >> 24;
+        if (mode & kDenseUpdPrev) {
+          fl += 2.0 * NB * NB * NB;
+          by += 8.0 * 2.0 * NB * NB;
+        }
+        if (mode & kDenseUpdThis) {
+          dense_grid(Ms[items[i].x], k0, &kb, &nrt, &nct);
+          fl += 2.0 * NB * NB * kb;
+          by += 8.0 * 2.0 * NB * kb;
+        }
+        by += 8.0 * 2.0 * NB * NB;
       }
-      for (const int2& it : next) {
-        dense_grid(Ms[it.x], k0, &kb, &nrt, &nct);
-        nfl += 2.0 * NB * NB * kb;
-        nby += 8.0 * 4.0 * NB * NB;
-      }
-      emit(L_PANEL, PF_K_DENSE_PANEL, npanel, k0, comb, pfl + gfl, pby + gby);
-      emit(L_GEMM, PF_K_DENSE_UPDATE, 0, k0, next, nfl, nby);
+      emit(L_PANEL, PF_K_DENSE_PANEL, npanel, k0, items, fl, by);
     }
   }
   // dense backward solve: flag mode while every work-group of the launch is
@@ -240,8 +253,7 @@ void lu_solve(Batch* b) {
     Prof p(ctx, PF_K_JFILL, 0.0, 0.0);
     pfd::launch_fill<T>(s, I, b->nslots, 2 * b->max_nu, b->d_work + b->zero_off, b->nzero, b->max_nnz);
   }
-  for (const Launch& l : b->seq) {
-    Prof p(ctx, l.cls, l.flops, l.bytes * sizeof(T) / 8.0);
+  auto launch = [&](const Launch& l) {
     const int2* w = b->d_work + l.off;
     switch (l.kind) {
       case L_FACTOR:
@@ -257,10 +269,7 @@ void lu_solve(Batch* b) {
         pfd::launch_tail_schur<T>(s, I, w, l.count, l.G);
         break;
       case L_PANEL:
-        pfd::launch_dense_panel_gemm<T>(s, I, w, l.count, l.G, l.k0);
-        break;
-      case L_GEMM:
-        pfd::launch_dense_gemm<T>(s, I, w, l.count, l.k0);
+        pfd::launch_dense_step<T>(s, I, w, l.count, l.G, l.k0);
         break;
       case L_TRSV:
         pfd::launch_dense_trsv<T>(s, I, w, l.count, b->trsv_single);
@@ -269,6 +278,24 @@ void lu_solve(Batch* b) {
         pfd::launch_bwd_rows<T>(s, I, w, l.count, l.G);
         break;
     }
+  };
+  const bool spans = (ctx->profile_mask & PF_PROFILE_SPANS) != 0;
+  for (size_t i = 0; i < b->seq.size();) {
+    const int cls = b->seq[i].cls;
+    size_t j = i + 1;
+    if (spans && (ctx->profile_mask & (1 << cls)))
+      while (j < b->seq.size() && b->seq[j].cls == cls) ++j;
+    // one event pair around launches i..j-1 (one launch unless spans are on)
+    hipEvent_t ev;
+    ctx->prof_begin(cls, &ev);
+    double fl = 0, by = 0;
+    for (size_t q = i; q < j; ++q) {
+      launch(b->seq[q]);
+      fl += b->seq[q].flops;
+      by += b->seq[q].bytes * sizeof(T) / 8.0;
+    }
+    ctx->prof_end(cls, ev, fl, by, (int)(j - i));
+    i = j;
   }
   {
     Prof p(ctx, PF_K_UPDATE, 0.0, 0.0);
@@ -332,7 +359,7 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
     pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
   }
   pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
-  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+  return launch_status("pf_solve");
 }
 
 // One Newton step of every active instance: linear solve, update, mismatch
@@ -351,39 +378,65 @@ static void enqueue_lu_step(Batch* b, const pf_options* opt) {
 }
 
 // The LU Newton step of a reused batch as a HIP graph: captured on first use
-// (kernels only), then replayed.  Off while kernel timing is on.
+// (kernels, and the timing events of the classes being timed), then
+// replayed; each replay queues the graph's event pairs for reading.
 static bool graph_step(Batch* b, const pf_options* opt) {
   Ctx* ctx = b->ctx;
   hipStream_t s = ctx->stream;
-  if (!b->allow_graph || b->graph_failed || !ctx->use_graphs || ctx->profile_mask != 0 || s == nullptr)
-    return false;
+  if (!b->allow_graph || b->graph_failed || !ctx->use_graphs || s == nullptr) return false;
   Batch::Graph& g = b->graphs[opt->precision == PF_PREC_MIXED ? 1 : 0];
-  if (g.exec && (g.tol != opt->tol || g.max_iter != opt->max_iter)) {
-    (void)hipGraphExecDestroy(g.exec);
-    g.exec = nullptr;
+  if (g.exec && (g.tol != opt->tol || g.max_iter != opt->max_iter || g.prof_mask != ctx->profile_mask)) {
+    if (!ctx->pending.empty()) {
+      (void)hipStreamSynchronize(s);
+      ctx->prof_flush();
+    }
+    g.reset();
   }
   if (!g.exec) {
+    // timing events for the graph, made before the capture (two per timed
+    // launch at most)
+    ctx->cap_pool.clear();
+    if (ctx->profile_mask != 0)
+      for (size_t i = 0; i < 2 * (b->seq.size() + 8); ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        ctx->cap_pool.push_back(e);
+      }
+    auto drop_pool = [&]() {
+      for (auto e : ctx->cap_pool) (void)hipEventDestroy(e);
+      ctx->cap_pool.clear();
+    };
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
+      drop_pool();
       b->graph_failed = true;
       return false;
     }
+    ctx->capture = &g.prof;
+    ctx->capture_bad = false;
     enqueue_lu_step(b, opt);
+    ctx->capture = nullptr;
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &graph);
-    if (e != hipSuccess || !graph || hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (e != hipSuccess || !graph || ctx->capture_bad ||
+        hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
       g.exec = nullptr;
       b->graph_failed = true;
     }
+    drop_pool();
     if (graph) (void)hipGraphDestroy(graph);
     if (b->graph_failed) {
+      g.reset();
       (void)hipGetLastError();
       return false;
     }
     g.tol = opt->tol;
     g.max_iter = opt->max_iter;
+    g.prof_mask = ctx->profile_mask;
   }
-  return hipGraphLaunch(g.exec, s) == hipSuccess;
+  if (hipGraphLaunch(g.exec, s) != hipSuccess) return false;
+  for (const auto& p : g.prof) ctx->pending.push_back(p);
+  return true;
 }
 
 pf_status step_batch(Batch* b, const pf_options* opt) {
@@ -398,7 +451,7 @@ pf_status step_batch(Batch* b, const pf_options* opt) {
   } else if (!graph_step(b, opt)) {
     enqueue_lu_step(b, opt);
   }
-  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+  return launch_status("pf_solve");
 }
 
 // Copy every instance's state to the host (synchronises the stream).

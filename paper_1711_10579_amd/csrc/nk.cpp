@@ -320,7 +320,7 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
     Prof p(ctx, PF_K_UPDATE, 0.0, 0.0);
     pfd::launch_update<T>(s, I, ns, b->max_nu);
   }
-  return hipGetLastError() == hipSuccess ? PF_OK : PF_E_DEVICE;
+  return launch_status("pf_solve");
 }
 
 }  // namespace
