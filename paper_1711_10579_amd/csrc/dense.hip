@@ -105,71 +105,97 @@ __device__ inline V4<T> blk_get_t(const T* st, int lane) {
   return z;
 }
 
-// value of lane `src` in every lane (src uniform)
-__device__ inline double lane_read(double v, int src) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ inline float lane_read(float v, int src) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
-}
-// value of lane K of each 16-lane row in the whole row (DPP row broadcast)
+// value of lane K of each 16-lane row in the whole row (DPP row broadcast;
+// every lane's source is valid, so no old value is kept)
 template <int K>
 __device__ inline double row_bcast(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+  const long long b = __builtin_amdgcn_update_dpp(0ll, __builtin_bit_cast(long long, v), 0x150 + K, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, b);
 }
 template <int K>
 __device__ inline float row_bcast(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf,
-                                                                false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf, true));
 }
 
-// Gauss-Jordan step K (pivot K, no pivoting) on a 16x16 block in N-form:
+// value of 16-lane row R (R static) in every row of the wave, through the
+// two lane-swap instructions
+template <int R>
+__device__ inline int grp_bcast32(int x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows (0,0,2,2) | (1,1,3,3)
+  const int h = (R & 1) ? a[1] : a[0];
+  const auto b = __builtin_amdgcn_permlane32_swap(h, h, false, false);  // rows (r,r,r,r) | (r+2,...)
+  return (R & 2) ? b[1] : b[0];
+}
+template <int R>
+__device__ inline double grp_bcast(double v) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = grp_bcast32<R>((int)u), hi = grp_bcast32<R>((int)(u >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int R>
+__device__ inline float grp_bcast(float v) {
+  return __builtin_bit_cast(float, grp_bcast32<R>(__builtin_bit_cast(int, v)));
+}
+// row K of a block in N-form, for this lane's column, in every lane
+template <int K, typename T>
+__device__ inline T block_row(const V4<T>& z) {
+  return grp_bcast<Mfma<T>::grp(K)>(z[Mfma<T>::elem(K)]);
+}
+
+// Gauss-Jordan step K (pivot K, no pivoting) on a 16x16 block Z in N-form:
 // with piv = Z(K,K): Z(r,c) -= Z(r,K) Z(K,c) / piv off row and column K,
 // Z(K,c) /= piv, Z(r,K) = -Z(r,K) / piv, Z(K,K) = 1 / piv.  After steps
-// 0..15 the block holds its inverse.  A zero or non-finite pivot sets `bad`.
+// 0..15 the block holds its inverse.  Every lane carries the pivot row P =
+// Z(K, c) and the next row Q = Z(K+1, c) of its column c; the step forms the
+// next pivot row from them with the arithmetic the row's owners use, so the
+// exchange of a row between lane groups happens a step ahead of its use.  A
+// zero or non-finite pivot sets `bad`.
 template <int K, typename T>
-__device__ __forceinline__ void gj_step(V4<T>& z, int lane, bool& bad) {
+__device__ __forceinline__ void gj_step(V4<T>& z, T& P, T& Q, int lane, bool& bad) {
   constexpr int ek = Mfma<T>::elem(K), gk = Mfma<T>::grp(K);
-  const int c = lane & 15;
-  const T piv = lane_read(z[ek], gk * 16 + K);
-  const T prow = __shfl(z[ek], gk * 16 + c);  // Z(K, c)
+  const bool ck = (lane & 15) == K;
+  const T piv = row_bcast<K>(P);  // Z(K,K)
+  const T mq = row_bcast<K>(Q);   // Z(K+1,K)
   T m[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) m[e] = row_bcast<K>(z[e]);  // Z(row(lane, e), K)
   bad = bad || !(piv != T(0)) || !isfinite((double)piv);
-  const T inv = fast_recip(piv != T(0) ? piv : T(1));
-  const T pr = prow * inv;
+  const T inv = fast_recip(piv);
+  // the new row K: Z(K,c) / piv, and 1 / piv in column K
+  const T sel = ck ? inv : P * inv;
+  const T al = ck ? T(0) : T(1);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    T nz = c == K ? -m[e] * inv : fma(-m[e], pr, z[e]);
-    if (Mfma<T>::row(lane, e) == K) nz = c == K ? inv : pr;
-    z[e] = nz;
+  for (int e = 0; e < 4; ++e) z[e] = fma(-m[e], sel, al * z[e]);
+  if ((lane >> 4) == gk) z[ek] = sel;
+  if (K < 15) {
+    P = fma(-mq, sel, al * Q);
+    // row K + 2 for the step after next: an LDS permute, off the chain
+    if (K < 14) {
+      constexpr int K2 = K < 14 ? K + 2 : 0;
+      Q = __shfl(z[Mfma<T>::elem(K2)], Mfma<T>::grp(K2) * 16 + (lane & 15));
+    }
   }
 }
 
 template <typename T>
 __device__ inline void blk_inverse(V4<T>& z, int lane, bool& bad) {
-  gj_step<0, T>(z, lane, bad);
-  gj_step<1, T>(z, lane, bad);
-  gj_step<2, T>(z, lane, bad);
-  gj_step<3, T>(z, lane, bad);
-  gj_step<4, T>(z, lane, bad);
-  gj_step<5, T>(z, lane, bad);
-  gj_step<6, T>(z, lane, bad);
-  gj_step<7, T>(z, lane, bad);
-  gj_step<8, T>(z, lane, bad);
-  gj_step<9, T>(z, lane, bad);
-  gj_step<10, T>(z, lane, bad);
-  gj_step<11, T>(z, lane, bad);
-  gj_step<12, T>(z, lane, bad);
-  gj_step<13, T>(z, lane, bad);
-  gj_step<14, T>(z, lane, bad);
-  gj_step<15, T>(z, lane, bad);
+  T P = block_row<0, T>(z), Q = block_row<1, T>(z);
+  gj_step<0, T>(z, P, Q, lane, bad);
+  gj_step<1, T>(z, P, Q, lane, bad);
+  gj_step<2, T>(z, P, Q, lane, bad);
+  gj_step<3, T>(z, P, Q, lane, bad);
+  gj_step<4, T>(z, P, Q, lane, bad);
+  gj_step<5, T>(z, P, Q, lane, bad);
+  gj_step<6, T>(z, P, Q, lane, bad);
+  gj_step<7, T>(z, P, Q, lane, bad);
+  gj_step<8, T>(z, P, Q, lane, bad);
+  gj_step<9, T>(z, P, Q, lane, bad);
+  gj_step<10, T>(z, P, Q, lane, bad);
+  gj_step<11, T>(z, P, Q, lane, bad);
+  gj_step<12, T>(z, P, Q, lane, bad);
+  gj_step<13, T>(z, P, Q, lane, bad);
+  gj_step<14, T>(z, P, Q, lane, bad);
+  gj_step<15, T>(z, P, Q, lane, bad);
 }
 
 // LDS of a dense launch (elements of T): the larger of the panel's (row tile

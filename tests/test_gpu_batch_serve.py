@@ -229,3 +229,33 @@ def test_graph_replays_match_eager(B, ctx, precision):
     assert r.status == 0 and r.mismatch_inf <= 1e-6
     for h in hs:
         h.close()
+
+
+def test_kernel_timing_inside_replayed_graphs(B, ctx):
+    # timing a class inside the captured Newton step (event nodes of the
+    # graph) counts the same launches as eager timing, with positive times;
+    # spans bracket each run of consecutive launches once and count them all
+    case = pfgen.make_polar_grid(3000, 900, 300, 61, balanced=True)
+    h = B.pf_create_from(ctx, case)
+    dense = B.PF_K_DENSE_PANEL
+    stats = {}
+    for mode, graphs, mask in [("eager", 0, 1 << dense), ("graph", 1, 1 << dense),
+                               ("spans", 1, (1 << dense) | B.PF_PROFILE_SPANS)]:
+        B.pf_ctx_use_graphs(ctx, graphs)
+        B.pf_profile_enable(ctx, mask)
+        B.pf_solve(h)  # captures the graph (graphs on) with this mask
+        B.pf_profile_reset(ctx)
+        r = B.pf_solve(h)
+        assert r.status == 0
+        stats[mode] = B.pf_kernel_stats(ctx, dense)
+        _say(f"timing {mode}: {stats[mode]}")
+    B.pf_profile_enable(ctx, 0)
+    B.pf_ctx_use_graphs(ctx, 1)
+    assert stats["eager"]["launches"] > 0
+    for mode in ("graph", "spans"):
+        assert stats[mode]["launches"] == stats["eager"]["launches"]
+        assert stats[mode]["flops"] == stats["eager"]["flops"]
+        assert stats[mode]["ms"] > 0
+    # the other classes stay untimed
+    assert B.pf_kernel_stats(ctx, B.PF_K_MISMATCH)["launches"] == 0
+    h.close()
