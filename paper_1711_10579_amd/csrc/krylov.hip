@@ -323,6 +323,7 @@ struct SweepData {
   T w0, w1;  // forward: right-hand side; backward: unused
   Blk<T> E[2];
   int c[2];
+  Blk<T> D;  // backward: the inverted diagonal block
 };
 
 // the row info {row, first, end, 0} at position k of a level list, or row -1
@@ -338,12 +339,13 @@ __device__ inline i4v sweep_info(const PF_AS1 i4v* info, int k, int k1) {
 
 template <typename T>
 __device__ inline void sweep_data(const i4v& inf, const PF_AS1 T* P, const PF_AS1 int* kcol, const PF_AS1 T* w,
-                                  SweepData<T>* s) {
+                                  const PF_AS1 T* dinv, SweepData<T>* s) {
   if (inf.x < 0) return;
   if (w) {
     s->w0 = w[2 * inf.x];
     s->w1 = w[2 * inf.x + 1];
   }
+  if (dinv) s->D = ld_blk<T>(dinv, inf.x);
 #pragma unroll
   for (int e = 0; e < 2; ++e)
     if (inf.y + e < inf.z) {
@@ -391,6 +393,27 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
   auto fp = [&](int l) { return lds_ptr ? lpf[l] : kl_ptr[l]; };
   auto bp = [&](int l) { return lds_ptr ? lpb[l] : ku_ptr[l]; };
 
+  // entries [q0, q1) of a row: (y0, y1) -= B(q) z(col(q)) in order of q, the
+  // loads issued four at a time
+  auto sub_entries = [&](int q0, int q1, double& y0, double& y1) {
+    for (int q = q0; q < q1; q += 4) {
+      Blk<T> B[4];
+      int cq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u < q1) {
+          B[u] = ld_blk<T>(P, q + u);
+          cq[u] = kcol[q + u];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u < q1) {
+          const double a = (double)z[2 * cq[u]], b = (double)z[2 * cq[u] + 1];
+          y0 -= (double)B[u].a * a + (double)B[u].b * b;
+          y1 -= (double)B[u].c * a + (double)B[u].d * b;
+        }
+    }
+  };
   // forward: y_r = s w_r - sum_{k<r} L(r,k) y_k
   auto fwd_row = [&](const i4v& inf, const SweepData<T>& s) {
     const int r = inf.x;
@@ -409,13 +432,7 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
         y0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
         y1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
       }
-    for (int q = inf.y + 2; q < inf.z; ++q) {
-      const Blk<T> L = ld_blk<T>(P, q);
-      const int c = kcol[q];
-      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
-      y0 -= (double)L.a * a + (double)L.b * b;
-      y1 -= (double)L.c * a + (double)L.d * b;
-    }
+    sub_entries(inf.y + 2, inf.z, y0, y1);
     z[2 * r] = (T)y0;
     z[2 * r + 1] = (T)y1;
   };
@@ -430,34 +447,29 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
         s0 -= (double)s.E[e].a * a + (double)s.E[e].b * b;
         s1 -= (double)s.E[e].c * a + (double)s.E[e].d * b;
       }
-    for (int q = inf.y + 2; q < inf.z; ++q) {
-      const Blk<T> U = ld_blk<T>(P, q);
-      const int c = kcol[q];
-      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
-      s0 -= (double)U.a * a + (double)U.b * b;
-      s1 -= (double)U.c * a + (double)U.d * b;
-    }
-    const Blk<T> Dv = ld_blk<T>(Dinv, r);
+    sub_entries(inf.y + 2, inf.z, s0, s1);
+    const Blk<T> Dv = s.D;
     z[2 * r] = (T)((double)Dv.a * s0 + (double)Dv.b * s1);
     z[2 * r + 1] = (T)((double)Dv.c * s0 + (double)Dv.d * s1);
   };
   // one sweep over the levels of a list with the two-stage fetch
-  auto sweep = [&](const PF_AS1 i4v* info, auto ptr, int nlev, const PF_AS1 T* wsrc, auto row_fn) {
+  auto sweep = [&](const PF_AS1 i4v* info, auto ptr, int nlev, const PF_AS1 T* wsrc, const PF_AS1 T* dsrc,
+                   auto row_fn) {
     if (nlev <= 0) return;
     i4v i0 = sweep_info(info, ptr(0) + tid, ptr(1));
     i4v i1 = nlev > 1 ? sweep_info(info, ptr(1) + tid, ptr(2)) : i0;
     SweepData<T> d0, d1;
-    sweep_data<T>(i0, P, kcol, wsrc, &d0);
+    sweep_data<T>(i0, P, kcol, wsrc, dsrc, &d0);
     for (int l = 0; l < nlev; ++l) {
       const int k0 = ptr(l), k1 = ptr(l + 1);
       i4v i2 = i1;
       if (l + 2 < nlev) i2 = sweep_info(info, ptr(l + 2) + tid, ptr(l + 3));
-      if (l + 1 < nlev) sweep_data<T>(i1, P, kcol, wsrc, &d1);
+      if (l + 1 < nlev) sweep_data<T>(i1, P, kcol, wsrc, dsrc, &d1);
       if (i0.x >= 0) row_fn(i0, d0);
       for (int k = k0 + tid + 1024; k < k1; k += 1024) {
         const i4v ix = info[k];
         SweepData<T> dx;
-        sweep_data<T>(ix, P, kcol, wsrc, &dx);
+        sweep_data<T>(ix, P, kcol, wsrc, dsrc, &dx);
         row_fn(ix, dx);
       }
       __syncthreads();
@@ -466,9 +478,9 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
       i1 = i2;
     }
   };
-  sweep(kl_info, fp, nl, w, fwd_row);
-  const PF_AS1 T* nw = nullptr;
-  sweep(ku_info, bp, nul, nw, bwd_row);
+  const PF_AS1 T* none = nullptr;
+  sweep(kl_info, fp, nl, w, none, fwd_row);
+  sweep(ku_info, bp, nul, none, Dinv, bwd_row);
   if (ZV > 0) {
     const auto zg = gp((T*)I.kz);
     for (int i = tid; i < 2 * nu; i += 1024) zg[i] = zl[i];
