@@ -396,12 +396,36 @@ __global__ void k_kfill(const Inst* const* insts, int ilu) {
 // lanes that split its update list (lane-strided partial sums, fixed-order
 // tree).
 
+// acc -= sum over updates q = q0, q0 + G, ... < q1 of L(q) U(q) (block ids
+// from il / iu), in that order, the loads of four updates issued at once
+template <typename T, int G>
+__device__ inline void sub_updates(Blk<T>& acc, const T* lu, const int* il, const int* iu, int64_t q0, int64_t q1) {
+  for (int64_t q = q0; q < q1; q += 4 * G) {
+    int a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) {
+        a[u] = il[q + u * G];
+        b[u] = iu[q + u * G];
+      }
+    Blk<T> L[4], U[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) {
+        L[u] = ld_blk(lu, a[u]);
+        U[u] = ld_blk(lu, b[u]);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) blk_msub(acc, L[u], U[u]);
+  }
+}
+
 template <typename T, int G>
 __device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest, int64_t tg, int lane) {
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
   if (lane == 0) acc = ld_blk(lu, dest);
-  for (int64_t q = I.uptr[tg] + lane; q < I.uptr[tg + 1]; q += G)
-    blk_msub(acc, ld_blk(lu, I.upd_l[q]), ld_blk(lu, I.upd_u[q]));
+  sub_updates<T, G>(acc, lu, I.upd_l, I.upd_u, I.uptr[tg] + lane, I.uptr[tg + 1]);
   return group_sum<T, G>(acc);
 }
 
@@ -521,9 +545,7 @@ __global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, co
   const bool live = t < I.ntt;
   const T* lu = (const T*)I.lu;
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  if (live)
-    for (int64_t q = I.tail_uptr[t] + lane; q < I.tail_uptr[t + 1]; q += G)
-      blk_msub(acc, ld_blk(lu, I.tail_l[q]), ld_blk(lu, I.tail_u[q]));
+  if (live) sub_updates<T, G>(acc, lu, I.tail_l, I.tail_u, I.tail_uptr[t] + lane, I.tail_uptr[t + 1]);
   acc = group_sum<T, G>(acc);
   if (!live || lane != 0) return;
   int g = I.tail_tgt[t];
@@ -557,12 +579,33 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, cons
     acc.a = x[2 * i];
     acc.c = x[2 * i + 1];
   }
-  for (int q = I.lrow_ptr[i] + lane; q < I.lrow_ptr[i + 1]; q += G) {
-    Blk<T> L = ld_blk(lu, I.lrow_blk[q]);
-    int k = I.lrow_col[q];
-    T x0 = x[2 * k], x1 = x[2 * k + 1];
-    acc.a -= L.a * x0 + L.b * x1;
-    acc.c -= L.c * x0 + L.d * x1;
+  {
+    // four entries' loads at once, applied in order
+    const int q1 = I.lrow_ptr[i + 1];
+    for (int q = I.lrow_ptr[i] + lane; q < q1; q += 4 * G) {
+      int bk[4], kk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          bk[u] = I.lrow_blk[q + u * G];
+          kk[u] = I.lrow_col[q + u * G];
+        }
+      Blk<T> L[4];
+      T x0[4], x1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          L[u] = ld_blk(lu, bk[u]);
+          x0[u] = x[2 * kk[u]];
+          x1[u] = x[2 * kk[u] + 1];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          acc.a -= L[u].a * x0[u] + L[u].b * x1[u];
+          acc.c -= L[u].c * x0[u] + L[u].d * x1[u];
+        }
+    }
   }
   acc = group_sum<T, G>(acc);
   if (lane == 0) {
@@ -593,16 +636,38 @@ __global__ __launch_bounds__(256) void k_bwd_rows(const Inst* const* insts, cons
     acc.a = x[2 * i];
     acc.c = x[2 * i + 1];
   }
-  for (int q = I.colptr[i] + lane; q < I.colptr[i + 1]; q += G) {
-    Blk<T> U = ld_blk(lu, (int64_t)I.ns + I.nnzl + q);
-    int j = I.rowidx[q];
-    T x0 = x[2 * j], x1 = x[2 * j + 1];
-    acc.a -= U.a * x0 + U.b * x1;
-    acc.c -= U.c * x0 + U.d * x1;
+  // the inverted diagonal block first (it does not depend on the solve)
+  Blk<T> D = {T(0), T(0), T(0), T(0)};
+  if (lane == 0) D = ld_blk((const T*)I.dinv, i);
+  {
+    // four entries' loads at once, applied in order
+    const int q1 = I.colptr[i + 1];
+    for (int q = I.colptr[i] + lane; q < q1; q += 4 * G) {
+      int jj[4];
+      Blk<T> U[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          jj[u] = I.rowidx[q + u * G];
+          U[u] = ld_blk(lu, (int64_t)I.ns + I.nnzl + q + u * G);
+        }
+      T x0[4], x1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          x0[u] = x[2 * jj[u]];
+          x1[u] = x[2 * jj[u] + 1];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u * G < q1) {
+          acc.a -= U[u].a * x0[u] + U[u].b * x1[u];
+          acc.c -= U[u].c * x0[u] + U[u].d * x1[u];
+        }
+    }
   }
   acc = group_sum<T, G>(acc);
   if (lane == 0) {
-    Blk<T> D = ld_blk((const T*)I.dinv, i);
     x[2 * i] = D.a * acc.a + D.b * acc.c;
     x[2 * i + 1] = D.c * acc.a + D.d * acc.c;
   }
