@@ -484,8 +484,8 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
   }
 }
 
-template <typename T, int G>
-__global__ __launch_bounds__(256) void k_factor_cols(const Inst* const* insts, const int2* __restrict__ work) {
+template <typename T, int G, int NT>
+__global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ T sdinv[4];
   const int2 w = work[blockIdx.x];
   const Inst& I = *insts[w.x];
@@ -762,9 +762,13 @@ void launch_kfill(hipStream_t st, const Inst* const* insts, int nslots, int max_
   }
 
 template <typename T>
-void launch_factor_cols(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
+void launch_factor_cols(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G, int wide) {
   if (nwork <= 0) return;
-  PF_GSWITCH(G, (k_factor_cols<T, GG><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work)));
+  if (wide) {
+    PF_GSWITCH(G, (k_factor_cols<T, GG, 1024><<<dim3((unsigned)nwork), 1024, 0, st>>>(insts, work)));
+  } else {
+    PF_GSWITCH(G, (k_factor_cols<T, GG, 256><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work)));
+  }
 }
 
 template <typename T>
@@ -800,7 +804,7 @@ void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max
 
 #define PF_INST(T)                                                                                         \
   template void launch_fill<T>(hipStream_t, const Inst* const*, int, int, const int2*, int, int);          \
-  template void launch_factor_cols<T>(hipStream_t, const Inst* const*, const int2*, int, int);             \
+  template void launch_factor_cols<T>(hipStream_t, const Inst* const*, const int2*, int, int, int);        \
   template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int, int);              \
   template void launch_factor_cols_wave<T>(hipStream_t, const Inst* const*, const int2*, int, int);        \
   template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \

@@ -26,8 +26,10 @@ void launch_fill(hipStream_t, const Inst* const* insts, int nslots, int max_nu2,
 int zero_chunk_values();
 
 // sparse part (work items (slot, column) or (slot, row); G lanes per list)
+// (wide: 1024 threads per column instead of 256, for levels of few columns
+// with many targets each)
 template <typename T>
-void launch_factor_cols(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
+void launch_factor_cols(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G, int wide);
 template <typename T>
 void launch_fwd_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
 template <typename T>

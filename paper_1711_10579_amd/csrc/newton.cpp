@@ -102,7 +102,11 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
         }
       }
       for (auto& kv : byG) {
-        const int wave = pass == 0 && maxt[kv.first] * kv.first <= 64 ? 1 : 0;
+        // k0 = 1: a column per wave when its targets fit one pass of the
+        // wave's lane groups; 2: 1024 threads per column when the level has
+        // few columns and they need several passes of 256 threads
+        int wave = pass == 0 && maxt[kv.first] * kv.first <= 64 ? 1 : 0;
+        if (pass == 0 && !wave && kv.second.size() < 128 && maxt[kv.first] * kv.first > 256) wave = 2;
         emit(pass == 0 ? L_FACTOR : L_FWD, pass == 0 ? PF_K_SPARSE_FACTOR : PF_K_SPARSE_FWD, kv.first, wave,
              kv.second, fl[kv.first], by[kv.first]);
       }
@@ -257,10 +261,10 @@ void lu_solve(Batch* b) {
     const int2* w = b->d_work + l.off;
     switch (l.kind) {
       case L_FACTOR:
-        if (l.k0)
+        if (l.k0 == 1)
           pfd::launch_factor_cols_wave<T>(s, I, w, l.count, l.G);
         else
-          pfd::launch_factor_cols<T>(s, I, w, l.count, l.G);
+          pfd::launch_factor_cols<T>(s, I, w, l.count, l.G, l.k0 == 2);
         break;
       case L_FWD:
         pfd::launch_fwd_rows<T>(s, I, w, l.count, l.G);
