@@ -32,10 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X peaks: HBM 8 TB/s; FP64 vector and FP64 matrix 78.6 TFLOP/s (vector:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz); FP32 matrix 157.3 TFLOP/s
-# (FP32 vector is 78.6 without packed FP32, which this build does not use).
-# The dominant kernel's flops are mostly its matrix-core update; its time is
-# set by the panel's 64 dependent pivot steps.
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz); FP32 matrix and FP32
+# vector (packed) 157.3 TFLOP/s.  The dominant kernel's flops are mostly its
+# matrix-core products; its time is set by the dependent chain of the
+# diagonal block's inverse and of the next panel's tiles.
 PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_mfma_tflops": 157.3, "fp32_valu_tflops": 157.3}
 METRIC = "converged PF solves/s at 1e-8 pu mismatch, batched vs plain; p50/p99 latency"
 
