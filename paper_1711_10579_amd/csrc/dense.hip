@@ -10,12 +10,15 @@
 // substitution along.  The backward solve x_k = P_k (z_k - sum_{j>k} A_kj x_j)
 // finishes the block.
 //
-// Per 64-wide step two launches: the panel (every work-group inverts the
-// diagonal block on the matrix cores, block Gauss-Jordan over 16x16 blocks,
-// then multiplies one 64-row tile below it by the inverse) together with the
-// previous step's trailing update away from the panel's block column and
-// the next block row, then the update of the next panel's block row and
-// column (look-ahead: the bulk of the update runs beside the next panel).
+// One launch per 64-wide block step k: the previous step's update of the
+// tiles right of the diagonal block and below its block row (k-1 <- the
+// tiles' last but one step), beside the panel of step k: every panel
+// work-group inverts the diagonal block on the matrix cores (block
+// Gauss-Jordan over 16x16 blocks), multiplies one 64-row tile below it by
+// the inverse and applies this step's update to that row's tile of the next
+// block column, so that the next launch's panel finds its block column up
+// to date.  The rest of this step's update runs in the next launch, beside
+// the next panel.
 
 #include <hip/hip_runtime.h>
 
@@ -222,7 +225,10 @@ __device__ inline unsigned long long panel_flag(int epoch, int k0) {
 //   g = 0:        P is stored (column-major) for the backward solve;
 //   g in 1..nrt:  row tile i = g - 1 below the block: L_ik = A_ik P,
 //                 computed transposed (P^T A_ik^T) so that consecutive lanes
-//                 store consecutive rows; then the row block's flag is set.
+//                 store consecutive rows; then the row's tile C of the next
+//                 block column takes this step's update, C -= L_ik A_{k,k+1},
+//                 once the previous step's update of C and of A_{k,k+1} is
+//                 stored (flags of work-groups earlier in the launch).
 template <typename T>
 __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0, T* smem) {
   T* xs = smem;                           // the row tile, column-major [NB][kPanelTileLd]
@@ -304,7 +310,48 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       for (int e = 0; e < 4; ++e) ui[(int64_t)(16 * wv + c) * NB + 16 * i + Mfma<T>::row(lane, e)] = d[i][e];
     return;
   }
+  // this row's tile of the next block column: the previous step's update
+  // of it and of the block row's tile there are stored by work-groups
+  // listed before this one in the launch
+  const int c1 = k0 + kb;  // may be the right-hand side column M
+  const int nc = min(NB, M + 1 - c1);
+  if (k0 > 0) {
+    __shared__ int abort_wait;
+    if (threadIdx.x == 0) {
+      // poll without ordering, then one acquire once both flags are seen;
+      // bounded: on expiry the instance records a timeout
+      const unsigned long long want = panel_flag(I.red->epoch, k0);
+      long spins = 0;
+      int ab = 0;
+      while (__hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want ||
+             __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        if (++spins > (1l << 22)) {
+          ab = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      abort_wait = ab;
+      if (ab) I.red->timeout = 1;
+    }
+    __syncthreads();
+    if (abort_wait) return;
+  }
+  // C^T blocks (wv, i') of the tile C = A_{i,k+1} and U blocks (q, wv) of
+  // U = A_{k,k+1}, in N-form, loaded while L_ik is formed
+  V4<T> ct[4], un[4];
+  const int cc = 16 * wv + c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = 16 * wv + Mfma<T>::row(lane, e);
+      ct[i][e] = G[(int64_t)(c1 + min(col, nc - 1)) * ld + r0 + min(16 * i + c, nr - 1)];
+      un[i][e] = G[(int64_t)(c1 + min(cc, nc - 1)) * ld + k0 + 16 * i + Mfma<T>::row(lane, e)];
+    }
   // (A_ik P)_{i', wv}^T = sum_q P_{q,wv}^T (A_ik)_{i',q}^T for row block i'
+  V4<T> y[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     V4<T> acc = zero;
@@ -315,50 +362,64 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       for (int e = 0; e < 4; ++e) xn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c];
       acc = mm16<T>(d[q], xn, acc);
     }
+    y[i] = acc;
     const int rr = 16 * i + c;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int cc = 16 * wv + Mfma<T>::row(lane, e);
-      if (rr < nr && cc < kb) A[(int64_t)(k0 + cc) * ld + r0 + rr] = acc[e];
+      const int col = 16 * wv + Mfma<T>::row(lane, e);
+      if (rr < nr && col < kb) A[(int64_t)(k0 + col) * ld + r0 + rr] = acc[e];
     }
   }
-  // publish the tile to the update work-groups of the same launch that wait
-  // for it: every wave's stores are released before the flag is set
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // L_ik to LDS (column-major, over the row tile once every wave is done
+  // with it), then C -= L_ik U, transposed like the product above
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&I.pflags[r0 / NB], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xs[(16 * wv + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c] = y[i][e];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    V4<T> acc = ct[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V4<T> yn;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c];
+      acc = mm16<T>(-un[q], yn, acc);
+    }
+    const int rr = 16 * i + c;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = 16 * wv + Mfma<T>::row(lane, e);
+      if (rr < nr && col < nc) A[(int64_t)(c1 + col) * ld + r0 + rr] = acc[e];
+    }
+  }
 }
 
-// Trailing update of one 64x64 tile A_ij (rows and columns after the panel
-// of step k0, the right-hand side column included) on the matrix cores: four
-// waves, each a 32x32 quarter of the tile as 2x2 blocks of 16x16, K = 64 in
-// steps of 4 (zero-padded past the panel width).  Item (slot, t | mode << 24),
-// tile t = row tile t % nrt, column tile t / nrt of step k0's grid:
-//   mode bit 0:  A_ij -= L_{i,k-1} A_{k-1,j} (the previous step's update);
-//   mode bit 1:  A_ij -= L_ik A_kj once the panel work-group of row block i
-//                in the same launch has set its flag (the tiles of the next
-//                panel's block row and column).
-// The tile is loaded with the first operands, straight into the
-// accumulators; operands sit k-major in LDS (L negated) so that each
-// quarter-wave reads 16 consecutive values.
+// The previous block step's update of one 64x64 tile, A_ij -= L_{i,k-1}
+// A_{k-1,j} (k-1 at column k0 - 64; the tile's columns may include the
+// right-hand side column M), on the matrix cores: four waves, each a 32x32
+// quarter of the tile as 2x2 blocks of 16x16, K = 64 in steps of 4.  Item
+// (slot, j | i << 12 | flag << 24) for block row i and block column j; with
+// the flag the tile is announced in pflags[i] once stored.  The tile is
+// loaded with the operands, straight into the accumulators; operands sit
+// k-major in LDS (L negated) so that each quarter-wave reads 16 consecutive
+// values.
 template <typename T>
 __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0, T* smem) {
   T(*sa)[kGemmLd] = (T(*)[kGemmLd])smem;                   // [k][row]
   T(*sb)[kGemmLd] = (T(*)[kGemmLd])(smem + NB * kGemmLd);  // [k][col]
-  __shared__ int abort_wait;
   const Inst& I = *insts[wk.x];
   if (I.red->active == 0) return;
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
-  const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
-  const int nrt = __builtin_amdgcn_readfirstlane((M - (k0 + kb) + NB - 1) / NB);
-  const int t = __builtin_amdgcn_readfirstlane(wk.y & 0xffffff);
-  const int mode = __builtin_amdgcn_readfirstlane(wk.y >> 24);
+  const int bi0 = __builtin_amdgcn_readfirstlane((wk.y >> 12) & 0xfff);
+  const int bj0 = __builtin_amdgcn_readfirstlane(wk.y & 0xfff);
+  const bool flag = (wk.y >> 24) != 0;
+  const int kp = k0 - NB;
   const int tid = threadIdx.x;
-  const int r0 = k0 + kb + (t % nrt) * NB;
-  const int c0 = k0 + kb + (t / nrt) * NB;
+  const int r0 = bi0 * NB, c0 = bj0 * NB;
   const int nr = min(NB, M - r0);
   const int nc = min(NB, M + 1 - c0);
   const int lane = tid % 64, w = tid / 64;
@@ -378,88 +439,44 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
         const int r = rb + bi * 16 + li, c = cb + bj * 16 + Mfma<T>::row(lane, e);
         acc[bi][bj][e] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + r0 + min(r, nr - 1)];
       }
-  // operands of the step at column kp (width kw): L rows r0.., columns
-  // kp..; U rows kp.., columns c0..
-  auto load_l = [&](int kp, int kw, T (&va)[16]) {
+  T va[16], vb[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx % NB, k = idx / NB;
-      va[q] = G[(int64_t)(kp + min(k, kw - 1)) * ld + r0 + min(r, nr - 1)];
-    }
-  };
-  auto load_u = [&](int kp, int kw, T (&vb)[16]) {
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx % NB, k = idx / NB;
+    va[q] = G[(int64_t)(kp + k) * ld + r0 + min(r, nr - 1)];
+  }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int k = idx % NB, c = idx / NB;
-      vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + kp + min(k, kw - 1)];
-    }
-  };
-  auto stage = [&](int kw, const T (&va)[16], const T (&vb)[16]) {
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int k = idx % NB, c = idx / NB;
+    vb[q] = G[(int64_t)(c0 + min(c, nc - 1)) * ld + kp + k];
+  }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int r = idx % NB, k = idx / NB;
-      sa[k][r] = (r < nr && k < kw) ? -va[q] : T(0);
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int r = idx % NB, k = idx / NB;
+    sa[k][r] = r < nr ? -va[q] : T(0);
+  }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + 256 * q;
-      const int k = idx % NB, c = idx / NB;
-      sb[k][c] = (c < nc && k < kw) ? vb[q] : T(0);
-    }
-  };
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q;
+    const int k = idx % NB, c = idx / NB;
+    sb[k][c] = c < nc ? vb[q] : T(0);
+  }
+  __syncthreads();
   // the transposed product (L U)^T = U^T L^T: the matrix core's first
   // operand is the column block, so a lane's result row is a tile column and
   // its lane index within 16 a tile row -- consecutive lanes then update
   // consecutive rows of the column-major tile
-  auto mma = [&]() {
 #pragma unroll 4
-    for (int ks = 0; ks < NB; ks += 4) {
-      T a0 = sa[ks + lk][rb + li], a1 = sa[ks + lk][rb + 16 + li];
-      T b0 = sb[ks + lk][cb + li], b1 = sb[ks + lk][cb + 16 + li];
-      acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
-      acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
-      acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
-      acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
-    }
-  };
-  T va[16], vb[16], vu[16];
-  // this step's U tile is final before the launch: fetched at once
-  if (mode & 2) load_u(k0, kb, vu);
-  if (mode & 1) {
-    load_l(k0 - NB, NB, va);
-    load_u(k0 - NB, NB, vb);
-    stage(NB, va, vb);
-    __syncthreads();
-    mma();
-  }
-  if (mode & 2) {
-    if (tid == 0) {
-      // poll without ordering, then one acquire once the flag is seen;
-      // bounded: on expiry the instance records a timeout
-      const unsigned long long want = panel_flag(I.red->epoch, k0);
-      long spins = 0;
-      int ab = 0;
-      while (__hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-        if (++spins > (1l << 22)) {
-          ab = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      abort_wait = ab;
-      if (ab) I.red->timeout = 1;
-    }
-    // also separates the previous product's LDS reads from the new stores
-    __syncthreads();
-    if (abort_wait) return;
-    load_l(k0, kb, va);
-    stage(kb, va, vu);
-    __syncthreads();
-    mma();
+  for (int ks = 0; ks < NB; ks += 4) {
+    T a0 = sa[ks + lk][rb + li], a1 = sa[ks + lk][rb + 16 + li];
+    T b0 = sb[ks + lk][cb + li], b1 = sb[ks + lk][cb + 16 + li];
+    acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
+    acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
+    acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
+    acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -472,24 +489,32 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
         if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] = acc[bi][bj][e];
       }
     }
+  if (flag) {
+    // every wave's stores are released before the flag is set
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// Block step k0 in one launch: the panel of step k0 (items [0, npanel)),
-// then the trailing-update tiles right of and below it -- the previous
-// step's update and, for the next panel's block row and column, this step's
-// too.  Those wait for the panel work-groups of their row block, which come
-// first in the launch (work-groups start in index order), so every wait ends.
-// Apart from those flagged tiles the items touch disjoint tiles: the panel
-// reads its block column, brought up to date by the previous launch, and
-// writes its row tiles; the updates write only tiles right of that column.
+// Block step k0 in one launch: items [0, nflag) the previous step's update
+// of the tiles of the next block column (and of the block row's tile
+// there), which announce themselves; [nflag, nflag + npanel) the panel of
+// step k0, whose work-groups wait for those; then the rest of the previous
+// step's update.  Work-groups start in index order, so every wait is on a
+// work-group that already runs.  The items write disjoint tiles except the
+// next block column's, written by its flagged update and then, after the
+// flag, by its panel work-group.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_step(const Inst* const* insts, const int2* __restrict__ work,
-                                                    int npanel, int k0) {
+                                                    int nflag, int npanel, int k0) {
   __shared__ T smem[kDenseSmem];
-  if ((int)blockIdx.x < npanel)
-    panel_step<T>(insts, work[blockIdx.x], k0, smem);
+  const int b = blockIdx.x;
+  if (b >= nflag && b < nflag + npanel)
+    panel_step<T>(insts, work[b], k0, smem);
   else
-    gemm_tile<T>(insts, work[blockIdx.x], k0, smem);
+    gemm_tile<T>(insts, work[b], k0, smem);
 }
 
 // Block backward solve (z in column M): by 64-row blocks, acc = z_b -
@@ -588,9 +613,10 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
 // ---------------------------------------------------------------------------
 
 template <typename T>
-void launch_dense_step(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int npanel, int k0) {
+void launch_dense_step(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int nflag, int npanel,
+                       int k0) {
   if (nwork <= 0) return;
-  k_dense_step<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, npanel, k0);
+  k_dense_step<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, nflag, npanel, k0);
 }
 
 template <typename T>
@@ -600,7 +626,7 @@ void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* wor
 }
 
 #define PF_DINST(T)                                                                        \
-  template void launch_dense_step<T>(hipStream_t, const Inst* const*, const int2*, int, int, int); \
+  template void launch_dense_step<T>(hipStream_t, const Inst* const*, const int2*, int, int, int, int); \
   template void launch_dense_trsv<T>(hipStream_t, const Inst* const*, const int2*, int, int);
 
 PF_DINST(double)

@@ -13,29 +13,35 @@ void dense_grid(int M, int k, int* kb, int* nrt, int* nct) {
   *nct = (M + 1 - (k + *kb) + kDenseNB - 1) / kDenseNB;
 }
 
-void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* npanel) {
+void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* nflag, int* npanel) {
   items->clear();
   const int ns = (int)Ms.size();
+  const int p = k0 / kDenseNB;
   int kb, nrt, nct;
+  // the previous step's update of the tiles right of its next block column
+  // (that column was updated by the previous step's panel): pass 0 the
+  // tiles of column p + 1, flagged, pass 1 the rest
+  auto prev = [&](int pass) {
+    if (k0 < kDenseNB) return;
+    for (int s = 0; s < ns; ++s) {
+      if (Ms[s] <= k0) continue;
+      dense_grid(Ms[s], k0 - kDenseNB, &kb, &nrt, &nct);
+      for (int t = 0; t < nrt * nct; ++t) {
+        const int rb = p + t % nrt, cb = p + t / nrt;
+        if (cb == p || (cb == p + 1) != (pass == 0)) continue;
+        items->push_back(make_int2(s, cb | rb << 12 | (pass == 0 ? 1 : 0) << 24));
+      }
+    }
+  };
+  prev(0);
+  *nflag = (int)items->size();
   for (int s = 0; s < ns; ++s) {
     if (Ms[s] <= k0) continue;
     dense_grid(Ms[s], k0, &kb, &nrt, &nct);
     for (int g = 0; g < 1 + nrt; ++g) items->push_back(make_int2(s, g));
   }
-  *npanel = (int)items->size();
-  // tiles of the next panel's block row and column first (they wait for the
-  // panel), then the rest of the previous step's update
-  for (int pass = 0; pass < 2; ++pass)
-    for (int s = 0; s < ns; ++s) {
-      if (Ms[s] <= k0) continue;
-      dense_grid(Ms[s], k0, &kb, &nrt, &nct);
-      for (int t = 0; t < nrt * nct; ++t) {
-        const bool next = t % nrt == 0 || t / nrt == 0;
-        if (next != (pass == 0)) continue;
-        const int mode = (k0 >= kDenseNB ? kDenseUpdPrev : 0) | (next ? kDenseUpdThis : 0);
-        if (mode) items->push_back(make_int2(s, t | mode << 24));
-      }
-    }
+  *npanel = (int)items->size() - *nflag;
+  prev(1);
 }
 
 }  // namespace pfi

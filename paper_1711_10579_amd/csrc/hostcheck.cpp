@@ -50,8 +50,12 @@ void req(bool ok, const char* what) {
 // launch is checked against the state before the launch (items of a launch
 // run concurrently): a panel item needs its tile and the diagonal tile
 // updated through the previous step; an update item of step k needs its tile
-// updated through step k-1 and the L and U tiles of panel k finished; no two
-// items of a launch write one tile, and no item reads a tile that another
+// updated through step k-1 and the L and U tiles of panel k finished.  The
+// one ordering inside a launch is the row flag: a panel item's update of its
+// row's tile in the next block column reads that tile and the block row's
+// tile there after the flags of their rows, each set by the one flagged item
+// of that row, listed earlier, which wrote the tile.  Apart from that no two
+// items of a launch write one tile and no item reads a tile that another
 // item of the launch writes.  At the end every block must be finished.
 void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
   typedef std::tuple<int, int, int> Key;  // (slot, row offset, column offset)
@@ -63,14 +67,15 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
   for (int s = 0; s < ns; ++s) maxM = std::max(maxM, Ms[s]);
   std::vector<int2> items;
   for (int k0 = 0; k0 < maxM; k0 += 64) {
-    int npanel = 0;
-    dense_plan_step(Ms, k0, &items, &npanel);
+    int nflag = 0, npanel = 0;
+    dense_plan_step(Ms, k0, &items, &nflag, &npanel);
+    req(nflag >= 0 && npanel >= 0 && nflag + npanel <= (int)items.size(), "dense plan: item counts");
     const int p = k0 / 64;
-    std::map<Key, size_t> writer;               // tile -> item writing it
-    std::map<std::pair<int, int>, size_t> pan;  // (slot, row) -> panel item of that row tile
+    std::map<Key, std::vector<size_t>> writers;   // tile -> items writing it, in order
+    std::map<std::pair<int, int>, size_t> flagged;  // (slot, row offset) -> flagged item
     std::vector<std::vector<Key>> rd(items.size());
-    std::vector<std::pair<Key, size_t>> flag_rd;  // tiles read after a flag, with the reader
-    std::vector<Key> upd;                         // tiles updated, once per update applied
+    std::vector<std::pair<Key, size_t>> flag_rd;  // tiles read after their row's flag, with the reader
+    std::vector<Key> upd, own;                    // tiles updated (once per update); panel tiles
     std::set<int> diag_slots;
     for (size_t i = 0; i < items.size(); ++i) {
       const int s = items[i].x;
@@ -78,7 +83,7 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
       int kb, nrt, nct;
       dense_grid(Ms[s], k0, &kb, &nrt, &nct);
       ++*nchk;
-      if ((int)i < npanel) {
+      if ((int)i >= nflag && (int)i < nflag + npanel) {
         const int g = items[i].y;
         req(g >= 0 && g < 1 + nrt, "dense plan: panel item out of range");
         const Key d(s, k0, k0);
@@ -88,57 +93,77 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
           rd[i] = {d};
           continue;
         }
-        const Key own(s, k0 + kb + 64 * (g - 1), k0);
-        req(std::get<1>(own) < Ms[s], "dense plan: tile out of range");
-        req(cnt[aligned(own)] == p && !fin.count(own), "dense plan: panel tile not up to date");
-        rd[i] = {d, own};
-        req(writer.emplace(own, i).second, "dense plan: two items of a launch write one tile");
-        pan[{s, std::get<1>(own)}] = i;
+        const int r0 = k0 + kb + 64 * (g - 1), c1 = k0 + kb;
+        const Key o(s, r0, k0);
+        req(r0 < Ms[s] && c1 <= Ms[s], "dense plan: tile out of range");
+        req(cnt[aligned(o)] == p && !fin.count(o), "dense plan: panel tile not up to date");
+        rd[i] = {d, o};
+        writers[o].push_back(i);
+        own.push_back(o);
+        // this step's update of the row's tile in the next block column
+        const Key nx(s, r0, c1), u(s, k0, c1);
+        if (k0 == 0) {
+          req(cnt[aligned(nx)] == 0 && cnt[aligned(u)] == 0 && !fin.count(nx) && !fin.count(u),
+              "dense plan: next block column not up to date");
+          rd[i].push_back(nx);
+          rd[i].push_back(u);
+        } else {
+          flag_rd.push_back({nx, i});
+          flag_rd.push_back({u, i});
+        }
+        writers[nx].push_back(i);
+        upd.push_back(nx);
         continue;
       }
-      const int t = items[i].y & 0xffffff, mode = items[i].y >> 24;
-      req(t >= 0 && t < nrt * nct && mode >= 1 && mode <= 3, "dense plan: update item out of range");
-      const int r0 = k0 + kb + 64 * (t % nrt), c0 = k0 + kb + 64 * (t / nrt);
-      req(r0 < Ms[s] && c0 <= Ms[s] && r0 % 64 == 0 && c0 % 64 == 0, "dense plan: update tile off the grid");
-      const Key x(s, r0, c0);
-      req(cnt[x] == p - ((mode & kDenseUpdPrev) ? 1 : 0) && !fin.count(x), "dense plan: updated tile not up to date");
-      rd[i].push_back(x);
-      if (mode & kDenseUpdPrev) {
-        req(k0 >= 64, "dense plan: update of a step before the first");
-        const Key l(s, r0, k0 - 64), u(s, k0 - 64, c0);
-        req(fin.count(l) && fin.count(u), "dense plan: update before its panel");
-        rd[i].push_back(l);
-        rd[i].push_back(u);
-        upd.push_back(x);
+      // the previous step's update of a tile
+      const int y = items[i].y, cb = y & 0xfff, rb = (y >> 12) & 0xfff, fl = y >> 24;
+      req(fl == ((int)i < nflag ? 1 : 0), "dense plan: flag of an update item");
+      req(k0 >= 64, "dense plan: update of a step before the first");
+      const int r0 = 64 * rb, c0 = 64 * cb;
+      req(r0 >= k0 && r0 < Ms[s] && c0 > k0 && c0 <= Ms[s], "dense plan: update tile off the grid");
+      const Key x(s, r0, c0), l(s, r0, k0 - 64), u(s, k0 - 64, c0);
+      req(cnt[x] == p - 1 && !fin.count(x), "dense plan: updated tile not up to date");
+      req(fin.count(l) && fin.count(u), "dense plan: update before its panel");
+      rd[i] = {x, l, u};
+      writers[x].push_back(i);
+      upd.push_back(x);
+      if (fl) {
+        req(c0 == k0 + 64, "dense plan: flagged update away from the next block column");
+        req(flagged.emplace(std::make_pair(s, r0), i).second, "dense plan: two flagged items of one row block");
       }
-      if (mode & kDenseUpdThis) {
-        req(t % nrt == 0 || t / nrt == 0, "dense plan: early update away from the next panel");
-        const Key u(s, k0, c0);
-        req(cnt[aligned(u)] == p && !fin.count(u), "dense plan: block row not up to date");
-        rd[i].push_back(u);
-        flag_rd.push_back({Key(s, r0, k0), i});
-        upd.push_back(x);
-      }
-      req(writer.emplace(x, i).second, "dense plan: two items of a launch write one tile");
     }
-    // plain reads see no tile written in the launch; a tile read after a
-    // flag is the row tile of a panel work-group listed earlier
+    // a tile read after a flag was written by that row's flagged item,
+    // listed before the reader, and otherwise only by the reader
+    std::set<std::pair<Key, size_t>> flag_ok;
+    for (const auto& fr : flag_rd) {
+      const Key& x = fr.first;
+      auto f = flagged.find({std::get<0>(x), std::get<1>(x)});
+      req(f != flagged.end() && f->second < fr.second, "dense plan: a flag wait on a later or missing work-group");
+      const auto& w = writers[x];
+      req(!w.empty() && w[0] == f->second, "dense plan: a flag that does not cover the tile read");
+      for (size_t q = 1; q < w.size(); ++q) req(w[q] == fr.second, "dense plan: a tile read after a flag is written by another item");
+      flag_ok.insert({x, fr.second});
+    }
+    for (const auto& kv : writers) {
+      const auto& w = kv.second;
+      req(w.size() == 1 || (w.size() == 2 && flag_ok.count({kv.first, w[1]})),
+          "dense plan: two items of a launch write one tile");
+    }
     for (size_t j = 0; j < items.size(); ++j)
       for (const Key& r : rd[j]) {
-        auto it = writer.find(r);
-        req(it == writer.end() || it->second == j, "dense plan: an item reads a tile written in its launch");
+        auto it = writers.find(r);
+        // (a flagged item reads its own tile before the flag)
+        req(it == writers.end() ||
+                (it->second[0] == j && (it->second.size() == 1 || flag_ok.count({r, it->second[1]}))),
+            "dense plan: an item reads a tile written in its launch");
       }
-    for (const auto& fr : flag_rd) {
-      auto it = pan.find({std::get<0>(fr.first), std::get<1>(fr.first)});
-      req(it != pan.end() && it->second < fr.second, "dense plan: a flag wait on a later or missing work-group");
-    }
-    for (const auto& kv : writer)
-      if ((int)kv.second < npanel) fin.insert(kv.first);
+    for (const Key& o : own) fin.insert(o);
+    for (const Key& x : upd) cnt[aligned(x)] += 1;
     for (int s : diag_slots) {
       int kb, nrt, nct;
       dense_grid(Ms[s], k0, &kb, &nrt, &nct);
       fin.insert(Key(s, k0, k0));
-      // the block row right of the diagonal block is final as it stands
+      // the block row right of the diagonal block is final after the launch
       for (int j = 0; j < nct; ++j) {
         const Key u(s, k0, k0 + kb + 64 * j);
         req(cnt[aligned(u)] == p && !fin.count(u), "dense plan: block row not up to date");
@@ -147,7 +172,6 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
     }
     for (int s = 0; s < ns; ++s)
       req(Ms[s] <= k0 || diag_slots.count(s), "dense plan: an instance misses its panel");
-    for (const Key& x : upd) cnt[x] += 1;
   }
   for (int s = 0; s < ns; ++s) {
     const int R = (Ms[s] + 63) / 64, C = (Ms[s] + 1 + 63) / 64;

@@ -130,6 +130,7 @@ struct Launch {
   int kind;        // Launch kinds below
   int G;           // lanes per list
   int k0;          // dense panel step
+  int nflag;       // dense step: flagged update items listed first
   int cls;         // pf_kernel_class for profiling
   int64_t off;     // first work item
   int count;       // work items
@@ -215,18 +216,17 @@ pf_status nk_step(Batch* b, const pf_options* opt);
 // Launch plan of the dense block's block LU (dense_plan.cpp), one launch per
 // 64-wide block step.  Step k of an instance with dense order M has a
 // kb-wide diagonal block, nrt row tiles below it and nct column tiles right
-// of it (the last holding the right-hand side column M); tile t of the step
-// is row tile t % nrt, column tile t / nrt.  Per step k0 over instances of
-// orders Ms, `items` lists the panel items (slot, g) of step k0 (the first
-// *npanel: g = 0 the diagonal block, g = 1..nrt its row tiles), then the
-// update items (slot, t | mode << 24): mode kDenseUpdPrev applies step
-// k0 - 64's update to the tile, kDenseUpdThis step k0's (after the panel of
-// the tile's row block, in the same launch; the tiles of the next panel's
-// block row and column, listed first).
+// of it (the last holding the right-hand side column M).  Per step k0 over
+// instances of orders Ms, `items` lists first the *nflag update items of the
+// next block column, then the *npanel panel items (slot, g) of step k0 (g = 0
+// the diagonal block, g = 1..nrt its row tiles, each also applying step k0's
+// update to its row's tile of the next block column), then the other update
+// items.  An update item (slot, j | i << 12 | flag << 24) applies step
+// k0 - 64's update to tile (i, j) in 64-blocks; a flagged one then sets its
+// row block's flag, which the panel items of rows i and k0 / 64 wait for.
 constexpr int kDenseNB = 64;
-constexpr int kDenseUpdPrev = 1, kDenseUpdThis = 2;
 void dense_grid(int M, int k, int* kb, int* nrt, int* nct);
-void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* npanel);
+void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* nflag, int* npanel);
 
 // Run the Newton iteration of every case of a built batch to completion.
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);

@@ -42,7 +42,8 @@ void launch_factor_cols_wave(hipStream_t, const Inst* const* insts, const int2* 
 
 // dense trailing block
 template <typename T>
-void launch_dense_step(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int npanel, int k0);
+void launch_dense_step(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int nflag, int npanel,
+                       int k0);
 template <typename T>
 void launch_dense_trsv(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int single);
 

@@ -56,6 +56,7 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     l.cls = cls;
     l.G = G;
     l.k0 = k0;
+    l.nflag = 0;
     l.off = (int64_t)work.size();
     l.count = (int)items.size();
     l.flops = flops;
@@ -138,44 +139,38 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
     emit(L_SCHUR, PF_K_TAIL_SCHUR, gs, 0, schur, sfl, sby);
   }
-  // dense block, per 64-wide step k0: one launch with the panel of step k0,
-  // the previous step's update of every tile right of and below it, and
-  // this step's update of the next panel's block row and column
+  // dense block, per 64-wide step k0: one launch with the panel of step k0
+  // (which also applies step k0's update to the next block column) and the
+  // previous step's update of every other tile right of and below it
   {
     std::vector<int> Ms(nslots);
     for (int s = 0; s < nslots; ++s) Ms[s] = cs[s]->M;
     std::vector<int2> items;
     for (int k0 = 0; k0 < max_M; k0 += NB) {
-      int npanel = 0;
-      dense_plan_step(Ms, k0, &items, &npanel);
+      int nflag = 0, npanel = 0;
+      dense_plan_step(Ms, k0, &items, &nflag, &npanel);
       double fl = 0, by = 0;
       int kb, nrt, nct;
       for (int s = 0; s < nslots; ++s) {
         if (Ms[s] <= k0) continue;
         dense_grid(Ms[s], k0, &kb, &nrt, &nct);
         const double rr = Ms[s] - (k0 + kb);
-        // inverse of the diagonal block (Gauss-Jordan, 2 kb^3) and the row
-        // tiles times it; reads the block once, reads and writes the row
-        // tiles, writes the inverse
-        fl += 2.0 * kb * kb * kb + 2.0 * kb * kb * rr;
-        by += 8.0 * (2.0 * kb * kb + 2.0 * kb * rr);
+        const double nc = std::min(NB, Ms[s] + 1 - (k0 + kb));
+        // inverse of the diagonal block (Gauss-Jordan, 2 kb^3), the row
+        // tiles times it and the next block column's update; reads the
+        // block once, reads and writes the row tiles and the next block
+        // column, reads its block row tile once per row tile, writes the
+        // inverse
+        fl += 2.0 * kb * kb * kb + 2.0 * kb * kb * rr + 2.0 * rr * kb * nc;
+        by += 8.0 * (2.0 * kb * kb + 2.0 * kb * rr + 2.0 * rr * nc + nrt * kb * nc);
       }
-      // per update of a tile: 2 kb NB^2 flops, read L_ik and A_kj, read and
+      // per update of a tile: 2 NB^3 flops, read L_ik and A_kj, read and
       // write A_ij (once per item)
-      for (size_t i = npanel; i < items.size(); ++i) {
-        const int mode = items[i].y >> 24;
-        if (mode & kDenseUpdPrev) {
-          fl += 2.0 * NB * NB * NB;
-          by += 8.0 * 2.0 * NB * NB;
-        }
-        if (mode & kDenseUpdThis) {
-          dense_grid(Ms[items[i].x], k0, &kb, &nrt, &nct);
-          fl += 2.0 * NB * NB * kb;
-          by += 8.0 * 2.0 * NB * kb;
-        }
-        by += 8.0 * 2.0 * NB * NB;
-      }
+      const double nupd = (double)(items.size() - npanel);
+      fl += nupd * 2.0 * NB * NB * NB;
+      by += nupd * 8.0 * 4.0 * NB * NB;
       emit(L_PANEL, PF_K_DENSE_PANEL, npanel, k0, items, fl, by);
+      if (!items.empty()) seq.back().nflag = nflag;
     }
   }
   // dense backward solve: flag mode while every work-group of the launch is
@@ -273,7 +268,7 @@ void lu_solve(Batch* b) {
         pfd::launch_tail_schur<T>(s, I, w, l.count, l.G);
         break;
       case L_PANEL:
-        pfd::launch_dense_step<T>(s, I, w, l.count, l.G, l.k0);
+        pfd::launch_dense_step<T>(s, I, w, l.count, l.nflag, l.G, l.k0);
         break;
       case L_TRSV:
         pfd::launch_dense_trsv<T>(s, I, w, l.count, b->trsv_single);
