@@ -201,48 +201,73 @@ __device__ inline void blk_inverse(V4<T>& z, int lane, bool& bad) {
   gj_step<15, T>(z, P, Q, lane, bad);
 }
 
-// LDS of a dense launch (elements of T): the larger of the panel's (row tile
-// + staged blocks) and the update's (two operand tiles)
-constexpr int kPanelTileLd = NB + 1;
+// LDS of a dense launch (elements of T): the larger of the panel's (staged
+// blocks, a quarter row tile and its L rows) and the update's (two operand
+// tiles)
+constexpr int kQuarterLd = 17;
 constexpr int kGemmLd = NB + 2;
-constexpr int kDenseSmem = 2 * NB * kGemmLd > NB * kPanelTileLd + 8 * kStage ? 2 * NB * kGemmLd
-                                                                              : NB * kPanelTileLd + 8 * kStage;
+constexpr int kPanelSmem = 8 * kStage + 2 * NB * kQuarterLd;
+constexpr int kDenseSmem = 2 * NB * kGemmLd > kPanelSmem ? 2 * NB * kGemmLd : kPanelSmem;
 
-// Value of a row block's panel flag once the panel of block step k0 has
-// stored its tile in Newton step `epoch` (epochs only grow, so every earlier
-// value is smaller).
+// Value of a row block's flag once the previous step's update of its tile
+// in the next block column of step k0 is stored, in Newton step `epoch`
+// (epochs only grow, so every earlier value is smaller).
 __device__ inline unsigned long long panel_flag(int epoch, int k0) {
   return ((unsigned long long)(unsigned)epoch << 20) | (unsigned long long)(k0 / NB + 1);
 }
 
-// Panel step k0 of every instance in the work list: item (slot, g), four
-// waves.  Every work-group inverts the diagonal block D = A_kk (identity-
-// padded to 64x64) by block Gauss-Jordan over 4x4 blocks of 16: wave j keeps
-// block column j in N-form; at pivot block p wave p inverts D_pp (P) and
-// stages P and its other blocks D_ip in LDS, then after one barrier every
-// other wave j forms D_pj <- P D_pj and D_ij -= D_ip D_pj (i != p) and wave p
-// D_ip <- -D_ip P.  Then
-//   g = 0:        P is stored (column-major) for the backward solve;
-//   g in 1..nrt:  row tile i = g - 1 below the block: L_ik = A_ik P,
-//                 computed transposed (P^T A_ik^T) so that consecutive lanes
-//                 store consecutive rows; then the row's tile C of the next
-//                 block column takes this step's update, C -= L_ik A_{k,k+1},
-//                 once the previous step's update of C and of A_{k,k+1} is
-//                 stored (flags of work-groups earlier in the launch).
+// Panel step k0 of every instance in the work list: item (slot, g), one of
+// four work-groups h of four waves.  Every work-group inverts the diagonal
+// block D = A_kk (identity-padded to 64x64) by block Gauss-Jordan over 4x4
+// blocks of 16: wave j keeps block column j in N-form; at pivot block p wave
+// p inverts D_pp (P) and stages P and its other blocks D_ip in LDS, then
+// after one barrier every other wave j forms D_pj <- P D_pj and
+// D_ij -= D_ip D_pj (i != p) and wave p D_ip <- -D_ip P.  Then
+//   g = 0:        (h = 0 only) P is stored, column-major, for the backward
+//                 solve;
+//   g in 1..nrt:  rows 16h..16h+15 of row tile i = g - 1 below the block:
+//                 L_ik = A_ik P, computed transposed (P^T A_ik^T) so that
+//                 consecutive lanes store consecutive rows; then the same
+//                 rows of the row's tile C in the next block column take this
+//                 step's update, C -= L_ik A_{k,k+1}, once the previous step's
+//                 update of C and of A_{k,k+1} is stored (the flags of both
+//                 row blocks, set by work-groups earlier in the launch).  Each
+//                 wave reads the flags as it starts and loads its part of C
+//                 and A_{k,k+1} as soon as both are seen, while the inverse
+//                 is still being formed.
 template <typename T>
-__device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int k0, T* smem) {
-  T* xs = smem;                           // the row tile, column-major [NB][kPanelTileLd]
-  T* stage = smem + NB * kPanelTileLd;    // two sets of four staged blocks
+__device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 w, int h, int k0, T* smem) {
+  T* stage = smem;                    // two sets of four staged blocks
+  T* xs = smem + 8 * kStage;          // the work-group's rows of A_ik, column-major [NB][kQuarterLd]
+  T* ls = xs + NB * kQuarterLd;       // the same rows of L_ik
   const Inst& I = *insts[w.x];
   if (I.red->active == 0) return;
+  // the launch is uniform per work-group: keep these in scalar registers
+  const int g = __builtin_amdgcn_readfirstlane(w.y);
+  if (g == 0 && h != 0) return;
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
-  // the launch is uniform per work-group: keep these in scalar registers
   const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
-  const int g = __builtin_amdgcn_readfirstlane(w.y);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, c = lane & 15;
+  int r0 = 0, nr = 0;  // this work-group's rows, nr <= 16
+  if (g > 0) {
+    r0 = k0 + kb + (g - 1) * NB + 16 * h;
+    nr = M - r0 < 16 ? M - r0 : 16;
+    if (nr <= 0) return;
+  }
+  const int c1 = k0 + kb;  // the next block column; may be the right-hand side column M
+  const int nc = min(NB, M + 1 - c1);
   const auto G = gp((const T*)A);
+  // the flags of this row block and of the block row (relaxed: the acquire
+  // follows once both are seen); reread after the inverse if not yet set
+  const bool wait = g > 0 && k0 > 0;
+  unsigned long long want = 0, f1 = 0, f2 = 0;
+  if (wait) {
+    want = panel_flag(I.red->epoch, k0);
+    f1 = __hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    f2 = __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   // the diagonal block's column block wv, identity outside kb x kb
   V4<T> d[4];
   {
@@ -260,20 +285,35 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
         if (!(r < kb && cc < kb)) d[i][e] = r == cc ? T(1) : T(0);
       }
   }
-  // the row tile (zero outside nr x kb), staged column-major
-  int r0 = 0, nr = 0;
+  // the rows of A_ik (zero outside nr x kb), staged column-major
   if (g > 0) {
-    r0 = k0 + kb + (g - 1) * NB;
-    nr = min(NB, M - r0);
-    const int tr = threadIdx.x & 63, tc = threadIdx.x >> 6;
-    T v[16];
+    const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+    T v[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = G[(int64_t)(k0 + min(tc + 4 * q, kb - 1)) * ld + r0 + min(tr, nr - 1)];
+    for (int q = 0; q < 4; ++q) v[q] = G[(int64_t)(k0 + min(tc + 16 * q, kb - 1)) * ld + r0 + min(tr, nr - 1)];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = tc + 4 * q;
-      xs[cc * kPanelTileLd + tr] = (tr < nr && cc < kb) ? v[q] : T(0);
+    for (int q = 0; q < 4; ++q) {
+      const int cc = tc + 16 * q;
+      xs[cc * kQuarterLd + tr] = (tr < nr && cc < kb) ? v[q] : T(0);
     }
+  }
+  // this wave's part of the update: C^T block (wv) of the rows, N-form, and
+  // the blocks (q, wv) of U = A_{k,k+1}, N-form
+  V4<T> ct, un[4];
+  auto fetch = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      ct[e] = G[(int64_t)(c1 + min(16 * wv + Mfma<T>::row(lane, e), nc - 1)) * ld + r0 + min(c, nr - 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        un[q][e] = G[(int64_t)(c1 + min(16 * wv + c, nc - 1)) * ld + k0 + min(16 * q + Mfma<T>::row(lane, e), kb - 1)];
+  };
+  bool have = false;
+  if (g > 0 && !wait) {
+    fetch();
+    have = true;
   }
   bool bad = false;
   const V4<T> zero = {T(0), T(0), T(0), T(0)};
@@ -299,6 +339,12 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
         if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
       d[p] = npj;
     }
+    if (p == 1 && wait &&
+        __builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      fetch();
+      have = true;
+    }
   }
   // d[i] = P_{i,wv}
   if (g == 0) {
@@ -310,91 +356,56 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       for (int e = 0; e < 4; ++e) ui[(int64_t)(16 * wv + c) * NB + 16 * i + Mfma<T>::row(lane, e)] = d[i][e];
     return;
   }
-  // this row's tile of the next block column: the previous step's update
-  // of it and of the block row's tile there are stored by work-groups
-  // listed before this one in the launch
-  const int c1 = k0 + kb;  // may be the right-hand side column M
-  const int nc = min(NB, M + 1 - c1);
-  if (k0 > 0) {
-    __shared__ int abort_wait;
-    if (threadIdx.x == 0) {
-      // poll without ordering, then one acquire once both flags are seen;
-      // bounded: on expiry the instance records a timeout
-      const unsigned long long want = panel_flag(I.red->epoch, k0);
-      long spins = 0;
-      int ab = 0;
-      while (__hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want ||
-             __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-        if (++spins > (1l << 22)) {
-          ab = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+  bool expired = false;
+  if (!have) {
+    // bounded: on expiry the instance records a timeout and the update is
+    // not stored
+    long spins = 0;
+    for (;;) {
+      f1 = __hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      f2 = __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) break;
+      if (++spins > (1l << 22)) {
+        expired = true;
+        if (lane == 0) I.red->timeout = 1;
+        break;
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      abort_wait = ab;
-      if (ab) I.red->timeout = 1;
+      __builtin_amdgcn_s_sleep(1);
     }
-    __syncthreads();
-    if (abort_wait) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    fetch();
   }
-  // C^T blocks (wv, i') of the tile C = A_{i,k+1} and U blocks (q, wv) of
-  // U = A_{k,k+1}, in N-form, loaded while L_ik is formed
-  V4<T> ct[4], un[4];
-  const int cc = 16 * wv + c;
+  // (A_ik P)_{wv}^T = sum_q P_{q,wv}^T (A_ik)_q^T over the rows
+  V4<T> acc = zero;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int q = 0; q < 4; ++q) {
+    V4<T> xn;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int col = 16 * wv + Mfma<T>::row(lane, e);
-      ct[i][e] = G[(int64_t)(c1 + min(col, nc - 1)) * ld + r0 + min(16 * i + c, nr - 1)];
-      un[i][e] = G[(int64_t)(c1 + min(cc, nc - 1)) * ld + k0 + 16 * i + Mfma<T>::row(lane, e)];
-    }
-  // (A_ik P)_{i', wv}^T = sum_q P_{q,wv}^T (A_ik)_{i',q}^T for row block i'
-  V4<T> y[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    V4<T> acc = zero;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      V4<T> xn;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) xn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c];
-      acc = mm16<T>(d[q], xn, acc);
-    }
-    y[i] = acc;
-    const int rr = 16 * i + c;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int col = 16 * wv + Mfma<T>::row(lane, e);
-      if (rr < nr && col < kb) A[(int64_t)(k0 + col) * ld + r0 + rr] = acc[e];
-    }
+    for (int e = 0; e < 4; ++e) xn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kQuarterLd + c];
+    acc = mm16<T>(d[q], xn, acc);
   }
-  // L_ik to LDS (column-major, over the row tile once every wave is done
-  // with it), then C -= L_ik U, transposed like the product above
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int col = 16 * wv + Mfma<T>::row(lane, e);
+    if (c < nr && col < kb) A[(int64_t)(k0 + col) * ld + r0 + c] = acc[e];
+    ls[col * kQuarterLd + c] = acc[e];
+  }
   __syncthreads();
+  // C -= L_ik U, transposed like the product above
+  V4<T> cu = ct;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int q = 0; q < 4; ++q) {
+    V4<T> yn;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xs[(16 * wv + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c] = y[i][e];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    V4<T> acc = ct[i];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      V4<T> yn;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) yn[e] = xs[(16 * q + Mfma<T>::row(lane, e)) * kPanelTileLd + 16 * i + c];
-      acc = mm16<T>(-un[q], yn, acc);
-    }
-    const int rr = 16 * i + c;
+    for (int e = 0; e < 4; ++e) yn[e] = ls[(16 * q + Mfma<T>::row(lane, e)) * kQuarterLd + c];
+    cu = mm16<T>(-un[q], yn, cu);
+  }
+  if (!expired)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int col = 16 * wv + Mfma<T>::row(lane, e);
-      if (rr < nr && col < nc) A[(int64_t)(c1 + col) * ld + r0 + rr] = acc[e];
+      if (c < nr && col < nc) A[(int64_t)(c1 + col) * ld + r0 + c] = cu[e];
     }
-  }
 }
 
 // The previous block step's update of one 64x64 tile, A_ij -= L_{i,k-1}
@@ -500,21 +511,23 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 
 // Block step k0 in one launch: items [0, nflag) the previous step's update
 // of the tiles of the next block column (and of the block row's tile
-// there), which announce themselves; [nflag, nflag + npanel) the panel of
-// step k0, whose work-groups wait for those; then the rest of the previous
-// step's update.  Work-groups start in index order, so every wait is on a
-// work-group that already runs.  The items write disjoint tiles except the
-// next block column's, written by its flagged update and then, after the
-// flag, by its panel work-group.
+// there), which announce themselves; then the npanel panel items of step
+// k0, four work-groups each (a quarter of the item's row tile apiece), which
+// wait for those; then the rest of the previous step's update.  Work-groups
+// start in index order, so every wait is on a work-group that already runs.
+// The items write disjoint tiles except the next block column's, written by
+// its flagged update and then, after the flag, by its panel work-groups.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_step(const Inst* const* insts, const int2* __restrict__ work,
                                                     int nflag, int npanel, int k0) {
   __shared__ T smem[kDenseSmem];
   const int b = blockIdx.x;
-  if (b >= nflag && b < nflag + npanel)
-    panel_step<T>(insts, work[b], k0, smem);
-  else
+  if (b < nflag)
     gemm_tile<T>(insts, work[b], k0, smem);
+  else if (b < nflag + 4 * npanel)
+    panel_step<T>(insts, work[nflag + (b - nflag) / 4], (b - nflag) % 4, k0, smem);
+  else
+    gemm_tile<T>(insts, work[b - 3 * npanel], k0, smem);
 }
 
 // Block backward solve (z in column M): by 64-row blocks, acc = z_b -
@@ -616,7 +629,7 @@ template <typename T>
 void launch_dense_step(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int nflag, int npanel,
                        int k0) {
   if (nwork <= 0) return;
-  k_dense_step<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, nflag, npanel, k0);
+  k_dense_step<T><<<dim3((unsigned)(nwork + 3 * npanel)), 256, 0, st>>>(insts, work, nflag, npanel, k0);
 }
 
 template <typename T>
