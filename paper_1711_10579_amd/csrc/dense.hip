@@ -216,6 +216,26 @@ __device__ inline unsigned long long panel_flag(int epoch, int k0) {
   return ((unsigned long long)(unsigned)epoch << 20) | (unsigned long long)(k0 / NB + 1);
 }
 
+// A tile handed over inside a launch goes through device-coherent accesses
+// (relaxed atomics at agent scope: stores write through, loads bypass the
+// caches not coherent across the device), so no cache of any compute unit
+// is written back or invalidated.  The writer waits for its stores to
+// complete before the flag is set; the reader loads after seeing the flag.
+template <typename T>
+__device__ inline T ld_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long flag_ld(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// s_waitcnt vmcnt(0): every vector memory access of the wave, stores
+// included, has completed
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Panel step k0 of every instance in the work list: item (slot, g), one of
 // four work-groups h of four waves.  Every work-group inverts the diagonal
 // block D = A_kk (identity-padded to 64x64) by block Gauss-Jordan over 4x4
@@ -245,6 +265,9 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   // the launch is uniform per work-group: keep these in scalar registers
   const int g = __builtin_amdgcn_readfirstlane(w.y);
   if (g == 0 && h != 0) return;
+  // the panel is the launch's critical path: its waves issue first on a
+  // SIMD shared with update work-groups
+  __builtin_amdgcn_s_setprio(3);
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
   const int kb = __builtin_amdgcn_readfirstlane(min(NB, M - k0));
@@ -259,14 +282,14 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   const int c1 = k0 + kb;  // the next block column; may be the right-hand side column M
   const int nc = min(NB, M + 1 - c1);
   const auto G = gp((const T*)A);
-  // the flags of this row block and of the block row (relaxed: the acquire
-  // follows once both are seen); reread after the inverse if not yet set
+  // the flags of this row block and of the block row, read as each phase
+  // of the inverse starts and tested as it ends, then polled after it
   const bool wait = g > 0 && k0 > 0;
   unsigned long long want = 0, f1 = 0, f2 = 0;
   if (wait) {
     want = panel_flag(I.red->epoch, k0);
-    f1 = __hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    f2 = __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    f1 = flag_ld(&I.pflags[r0 / NB]);
+    f2 = flag_ld(&I.pflags[k0 / NB]);
   }
   // the diagonal block's column block wv, identity outside kb x kb
   V4<T> d[4];
@@ -301,14 +324,15 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   // the blocks (q, wv) of U = A_{k,k+1}, N-form
   V4<T> ct, un[4];
   auto fetch = [&]() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      ct[e] = G[(int64_t)(c1 + min(16 * wv + Mfma<T>::row(lane, e), nc - 1)) * ld + r0 + min(c, nr - 1)];
+      ct[e] = ld_dev(&A[(int64_t)(c1 + min(16 * wv + Mfma<T>::row(lane, e), nc - 1)) * ld + r0 + min(c, nr - 1)]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        un[q][e] = G[(int64_t)(c1 + min(16 * wv + c, nc - 1)) * ld + k0 + min(16 * q + Mfma<T>::row(lane, e), kb - 1)];
+        un[q][e] = ld_dev(&A[(int64_t)(c1 + min(16 * wv + c, nc - 1)) * ld + k0 + min(16 * q + Mfma<T>::row(lane, e), kb - 1)]);
   };
   bool have = false;
   if (g > 0 && !wait) {
@@ -320,6 +344,10 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     T* st = stage + (p & 1) * 4 * kStage;
+    if (p > 0 && wait && !have) {
+      f1 = flag_ld(&I.pflags[r0 / NB]);
+      f2 = flag_ld(&I.pflags[k0 / NB]);
+    }
     if (wv == p) {
       blk_inverse<T>(d[p], lane, bad);
 #pragma unroll
@@ -339,9 +367,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
         if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
       d[p] = npj;
     }
-    if (p == 1 && wait &&
-        __builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (wait && !have && __builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) {
       fetch();
       have = true;
     }
@@ -362,8 +388,8 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     // not stored
     long spins = 0;
     for (;;) {
-      f1 = __hip_atomic_load(&I.pflags[r0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      f2 = __hip_atomic_load(&I.pflags[k0 / NB], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      f1 = flag_ld(&I.pflags[r0 / NB]);
+      f2 = flag_ld(&I.pflags[k0 / NB]);
       if (__builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) break;
       if (++spins > (1l << 22)) {
         expired = true;
@@ -372,7 +398,6 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     fetch();
   }
   // (A_ik P)_{wv}^T = sum_q P_{q,wv}^T (A_ik)_q^T over the rows
@@ -428,6 +453,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
   const int bi0 = __builtin_amdgcn_readfirstlane((wk.y >> 12) & 0xfff);
   const int bj0 = __builtin_amdgcn_readfirstlane(wk.y & 0xfff);
   const bool flag = (wk.y >> 24) != 0;
+  if (flag) __builtin_amdgcn_s_setprio(2);
   const int kp = k0 - NB;
   const int tid = threadIdx.x;
   const int r0 = bi0 * NB, c0 = bj0 * NB;
@@ -497,15 +523,20 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int c = cb + bj * 16 + Mfma<T>::row(lane, e);
-        if (r < nr && c < nc) A[(int64_t)(c0 + c) * ld + r0 + r] = acc[bi][bj][e];
+        T* dst = &A[(int64_t)(c0 + c) * ld + r0 + r];
+        if (r < nr && c < nc) {
+          if (flag)
+            st_dev(dst, acc[bi][bj][e]);
+          else
+            *dst = acc[bi][bj][e];
+        }
       }
     }
   if (flag) {
-    // every wave's stores are released before the flag is set
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave's stores have completed before the flag is set
+    wait_vmem();
     __syncthreads();
-    if (tid == 0)
-      __hip_atomic_store(&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -518,7 +549,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 // The items write disjoint tiles except the next block column's, written by
 // its flagged update and then, after the flag, by its panel work-groups.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_step(const Inst* const* insts, const int2* __restrict__ work,
+__global__ __launch_bounds__(256, 2) void k_dense_step(const Inst* const* insts, const int2* __restrict__ work,
                                                     int nflag, int npanel, int k0) {
   __shared__ T smem[kDenseSmem];
   const int b = blockIdx.x;

@@ -103,6 +103,29 @@ def test_polar_reference_10k_bus(B, ctx, precision):
     check_polar(case, r, V)
 
 
+# A Newton iterate before convergence is the linear solve's result itself
+# (Newton's later steps would correct an inexact one): the GPU's first
+# iterates from the flat start equal the oracle's, whose steps come from a
+# sparse FP64 LU, to the rounding of two different elimination orders.
+ITER_TOL = 1e-11
+
+
+@pytest.mark.parametrize("iters", [1, 2, 3])
+@pytest.mark.parametrize("n,extra,npv", [(3001, 900, 300), (10000, 2999, 1000)], ids=["n3001", "grid10k"])
+def test_newton_iterates_match_oracle(B, ctx, n, extra, npv, iters):
+    case = pfgen.config_case(1) if n == 10000 else pfgen.make_polar_grid(n, extra, npv, 7, balanced=True)
+    _say(f"polar iterates n={n} iters={iters}")
+    h, r, V = gpu_solve(B, ctx, case, precision=0, max_iter=iters)
+    assert r.iters == iters, r.as_dict()
+    if n == 10000:
+        assert B.pf_case_info_get(h)["n_dense"] > 100
+    ref = polar.newton(case, max_iter=iters)
+    assert ref.iters == iters
+    d = float(np.max(np.abs(V - ref.V)))
+    _say(f"  max |V - V_oracle| = {d:.3e}")
+    assert d <= ITER_TOL, d
+
+
 FEEDERS = [(2, 1), (5, 2), (30, 3), (200, 4), (777, 5)]
 
 
