@@ -152,9 +152,10 @@ __device__ inline T block_row(const V4<T>& z) {
 // Z(K, c) and the next row Q = Z(K+1, c) of its column c; the step forms the
 // next pivot row from them with the arithmetic the row's owners use, so the
 // exchange of a row between lane groups happens a step ahead of its use.  A
-// zero or non-finite pivot sets `bad`.
+// zero or non-finite pivot makes the reciprocal and with it every later
+// value non-finite (the caller tests the result).
 template <int K, typename T>
-__device__ __forceinline__ void gj_step(V4<T>& z, T& P, T& Q, int lane, bool& bad) {
+__device__ __forceinline__ void gj_step(V4<T>& z, T& P, T& Q, int lane) {
   constexpr int ek = Mfma<T>::elem(K), gk = Mfma<T>::grp(K);
   const bool ck = (lane & 15) == K;
   const T piv = row_bcast<K>(P);  // Z(K,K)
@@ -162,7 +163,6 @@ __device__ __forceinline__ void gj_step(V4<T>& z, T& P, T& Q, int lane, bool& ba
   T m[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) m[e] = row_bcast<K>(z[e]);  // Z(row(lane, e), K)
-  bad = bad || !(piv != T(0)) || !isfinite((double)piv);
   const T inv = fast_recip(piv);
   // the new row K: Z(K,c) / piv, and 1 / piv in column K
   const T sel = ck ? inv : P * inv;
@@ -181,24 +181,24 @@ __device__ __forceinline__ void gj_step(V4<T>& z, T& P, T& Q, int lane, bool& ba
 }
 
 template <typename T>
-__device__ inline void blk_inverse(V4<T>& z, int lane, bool& bad) {
+__device__ inline void blk_inverse(V4<T>& z, int lane) {
   T P = block_row<0, T>(z), Q = block_row<1, T>(z);
-  gj_step<0, T>(z, P, Q, lane, bad);
-  gj_step<1, T>(z, P, Q, lane, bad);
-  gj_step<2, T>(z, P, Q, lane, bad);
-  gj_step<3, T>(z, P, Q, lane, bad);
-  gj_step<4, T>(z, P, Q, lane, bad);
-  gj_step<5, T>(z, P, Q, lane, bad);
-  gj_step<6, T>(z, P, Q, lane, bad);
-  gj_step<7, T>(z, P, Q, lane, bad);
-  gj_step<8, T>(z, P, Q, lane, bad);
-  gj_step<9, T>(z, P, Q, lane, bad);
-  gj_step<10, T>(z, P, Q, lane, bad);
-  gj_step<11, T>(z, P, Q, lane, bad);
-  gj_step<12, T>(z, P, Q, lane, bad);
-  gj_step<13, T>(z, P, Q, lane, bad);
-  gj_step<14, T>(z, P, Q, lane, bad);
-  gj_step<15, T>(z, P, Q, lane, bad);
+  gj_step<0, T>(z, P, Q, lane);
+  gj_step<1, T>(z, P, Q, lane);
+  gj_step<2, T>(z, P, Q, lane);
+  gj_step<3, T>(z, P, Q, lane);
+  gj_step<4, T>(z, P, Q, lane);
+  gj_step<5, T>(z, P, Q, lane);
+  gj_step<6, T>(z, P, Q, lane);
+  gj_step<7, T>(z, P, Q, lane);
+  gj_step<8, T>(z, P, Q, lane);
+  gj_step<9, T>(z, P, Q, lane);
+  gj_step<10, T>(z, P, Q, lane);
+  gj_step<11, T>(z, P, Q, lane);
+  gj_step<12, T>(z, P, Q, lane);
+  gj_step<13, T>(z, P, Q, lane);
+  gj_step<14, T>(z, P, Q, lane);
+  gj_step<15, T>(z, P, Q, lane);
 }
 
 // LDS of a dense launch (elements of T): the larger of the panel's (staged
@@ -339,7 +339,6 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     fetch();
     have = true;
   }
-  bool bad = false;
   const V4<T> zero = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
@@ -349,7 +348,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       f2 = flag_ld(&I.pflags[k0 / NB]);
     }
     if (wv == p) {
-      blk_inverse<T>(d[p], lane, bad);
+      blk_inverse<T>(d[p], lane);
 #pragma unroll
       for (int i = 0; i < 4; ++i) blk_put<T>(st + i * kStage, d[i], lane);
     }
@@ -374,7 +373,13 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   }
   // d[i] = P_{i,wv}
   if (g == 0) {
-    if (bad && lane == 0) I.red->singular = 1;
+    // a zero or non-finite pivot anywhere leaves no finite value in P
+    bool bad = false;
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bad = bad || !isfinite((double)d[ib][e]);
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) I.red->singular = 1;
     T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
