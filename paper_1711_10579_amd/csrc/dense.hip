@@ -417,7 +417,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int col = 16 * wv + Mfma<T>::row(lane, e);
-    if (c < nr && col < kb) A[(int64_t)(k0 + col) * ld + r0 + c] = acc[e];
+    if (c < nr && col < kb) st_dev(&A[(int64_t)(k0 + col) * ld + r0 + c], acc[e]);
     ls[col * kQuarterLd + c] = acc[e];
   }
   __syncthreads();
@@ -434,7 +434,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int col = 16 * wv + Mfma<T>::row(lane, e);
-      if (c < nr && col < nc) A[(int64_t)(c1 + col) * ld + r0 + c] = cu[e];
+      if (c < nr && col < nc) st_dev(&A[(int64_t)(c1 + col) * ld + r0 + c], cu[e]);
     }
 }
 
@@ -528,13 +528,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int c = cb + bj * 16 + Mfma<T>::row(lane, e);
-        T* dst = &A[(int64_t)(c0 + c) * ld + r0 + r];
-        if (r < nr && c < nc) {
-          if (flag)
-            st_dev(dst, acc[bi][bj][e]);
-          else
-            *dst = acc[bi][bj][e];
-        }
+        if (r < nr && c < nc) st_dev(&A[(int64_t)(c0 + c) * ld + r0 + r], acc[bi][bj][e]);
       }
     }
   if (flag) {
