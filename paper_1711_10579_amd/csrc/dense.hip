@@ -340,6 +340,15 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     have = true;
   }
   const V4<T> zero = {T(0), T(0), T(0), T(0)};
+  // the pivot wave of each phase has inverted its block before the phase:
+  // wave 0 here, wave p + 1 during phase p, right after the update of its
+  // own block and together with its other updates (matrix-core work beside
+  // the inverse's vector work), its other blocks staged before the inverse
+  if (wv == 0) {
+    blk_inverse<T>(d[0], lane);
+#pragma unroll
+    for (int i = 1; i < 4; ++i) blk_put<T>(stage + i * kStage, d[i], lane);
+  }
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     T* st = stage + (p & 1) * 4 * kStage;
@@ -347,13 +356,10 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       f1 = flag_ld(&I.pflags[r0 / NB]);
       f2 = flag_ld(&I.pflags[k0 / NB]);
     }
-    if (wv == p) {
-      blk_inverse<T>(d[p], lane);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) blk_put<T>(st + i * kStage, d[i], lane);
-    }
-    // one barrier per pivot block: a set of staged blocks is rewritten two
-    // pivot blocks later, after every wave has passed the barrier between
+    if (wv == p) blk_put<T>(st + p * kStage, d[p], lane);
+    // one barrier per pivot block: a set of staged blocks is rewritten
+    // (from the phase before its next use) after every wave has passed the
+    // barrier of the phase that read it
     __syncthreads();
     if (wv == p) {
 #pragma unroll
@@ -361,10 +367,23 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
         if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), d[p], zero);
     } else {
       const V4<T> npj = mm16<T>(blk_get_t<T>(st + p * kStage, lane), d[p], zero);
+      if (wv == p + 1) {
+        T* sn = stage + ((p + 1) & 1) * 4 * kStage;
+        d[p + 1] = mm16<T>(-blk_get_t<T>(st + (p + 1) * kStage, lane), npj, d[p + 1]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
-      d[p] = npj;
+        for (int i = 0; i < 4; ++i)
+          if (i != p && i != p + 1) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
+        d[p] = npj;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i != p + 1) blk_put<T>(sn + i * kStage, d[i], lane);
+        blk_inverse<T>(d[p + 1], lane);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i != p) d[i] = mm16<T>(-blk_get_t<T>(st + i * kStage, lane), npj, d[i]);
+        d[p] = npj;
+      }
     }
     if (wait && !have && __builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) {
       fetch();
