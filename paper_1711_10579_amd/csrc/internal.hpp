@@ -149,6 +149,7 @@ struct Batch {
   const pfd::Inst* const* d_insts = nullptr;
   int2* d_work = nullptr;
   pfd::Red* d_reds = nullptr;
+  int lu_steps = 0;  // Newton steps of the batch's last LU solve (queued ahead of the first read-back)
   std::vector<Launch> seq;
   int64_t zero_off = 0;  // zeroing chunks of the factor storage: work items [zero_off, +nzero)
   int nzero = 0;

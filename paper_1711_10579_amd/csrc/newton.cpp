@@ -489,8 +489,16 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   }
   (void)hipEventRecord(e0, s);
   pf_status st = start_batch(b, opt);
+  // LU Newton steps queued ahead of the first read-back of the instances'
+  // state: as many as the batch's last LU solve took.  The device masks the
+  // instances that finish earlier, so a step past convergence changes no
+  // result; the loop below then reads and continues as long as any instance
+  // is active.
+  int queued = 0;
+  if (opt->solver != PF_SOLVER_GMRES)
+    for (; st == PF_OK && queued < std::min(b->lu_steps, opt->max_iter); ++queued) st = step_batch(b, opt);
   std::vector<pfd::Red> h;
-  for (int guard = 0; st == PF_OK && guard <= opt->max_iter + 1; ++guard) {
+  for (int guard = queued; st == PF_OK && guard <= opt->max_iter + 1; ++guard) {
     st = read_batch(b, &h);
     if (st != PF_OK) break;
     bool any = false;
@@ -506,6 +514,11 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   (void)hipEventDestroy(e1);
   ctx->prof_flush();
   if (st != PF_OK) return st;
+  if (opt->solver != PF_SOLVER_GMRES) {
+    int most = 0;
+    for (const auto& r : h) most = std::max(most, r.it);
+    b->lu_steps = most;
+  }
   for (int i = 0; i < B; ++i) {
     results[i].status = h[i].status;
     results[i].iters = h[i].it;
