@@ -194,6 +194,41 @@ def test_deterministic_and_warm_start(B, ctx):
     assert r3.status == 0 and r3.iters == 0
 
 
+def test_queued_steps_leave_results_unchanged(B, ctx):
+    """A reused case queues as many Newton steps as its last solve took before
+    reading its state back; steps past convergence are masked on the device.
+    Solves with too many queued steps (a warm start, a lighter loading) and
+    too few (a heavier loading) match a fresh case's solve bit for bit."""
+    case = pfgen.make_polar_grid(1000, 300, 100, 78, balanced=True)
+    _say("queued steps")
+    h = B.pf_create_from(ctx, case)
+    r0 = B.pf_solve(h)
+    assert r0.status == 0 and r0.iters >= 3
+    V0 = B.pf_get_voltage(h)
+    # warm start: converged at once, every queued step masked
+    rw = B.pf_solve(h, flat_start=0)
+    assert rw.status == 0 and rw.iters == 0
+    assert np.array_equal(B.pf_get_voltage(h), V0)
+    counts = set()
+    for scale, flat in ((1.001, 0), (1.6, 1), (1.9, 1)):
+        p_sp, q_sp = case.p_sp * scale, case.q_sp * scale
+        B.pf_set_injections(h, p_sp=p_sp, q_sp=q_sp)
+        start = B.pf_get_voltage(h)
+        B.pf_set_voltage(h, start)  # both cases start from the same values
+        r = B.pf_solve(h, flat_start=flat)
+        V = B.pf_get_voltage(h)
+        fresh = B.pf_create_from(ctx, case)
+        B.pf_set_injections(fresh, p_sp=p_sp, q_sp=q_sp)
+        B.pf_set_voltage(fresh, start)
+        rf = B.pf_solve(fresh, flat_start=flat)
+        assert r.status == rf.status and r.iters == rf.iters, (scale, r.as_dict(), rf.as_dict())
+        assert np.array_equal(V, B.pf_get_voltage(fresh), equal_nan=True), scale
+        _say(f"  scale {scale} flat {flat}: status {r.status}, {r.iters} steps (queued {r0.iters})")
+        counts.add((r.iters > r0.iters) - (r.iters < r0.iters))
+        r0 = r
+    assert {-1, 1} <= counts, counts
+
+
 def test_set_injections_matches_oracle(B, ctx):
     base = pfgen.make_polar_grid(500, 150, 50, 5, balanced=True)
     pert = pfgen.perturb_loads(base, 9)
