@@ -282,6 +282,8 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       pfd::launch_bj_apply<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second, mode);
     }
   };
+  // Arnoldi steps queued per read of the instances' Krylov states
+  constexpr int kStepsPerRead = 8;
   std::vector<int> st(ns);
   const int64_t guard_max = (int64_t)(opt->gmres_max_restarts + 1) * (opt->gmres_m + 2) + 4;
   for (int64_t guard = 0;; ++guard) {
@@ -300,21 +302,24 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       iter |= v == pfd::KS_ITER;
       cyc |= v == pfd::KS_CYCLE;
     }
-    if (cyc) {
-      {
-        Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-        pfd::launch_kycomb<T>(s, I, ns, mc);
-      }
-      apply(1);
+    if (!iter && !cyc) break;
+    // a run of Arnoldi steps, then the end of every cycle they complete,
+    // between two reads of the states: each kernel acts only on the
+    // instances in the state it serves, so an instance whose cycle ends
+    // within the run skips its remaining steps
+    for (int i = 0; iter && i < kStepsPerRead; ++i) {
+      apply(0);
       Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-      pfd::launch_kcycle_end<T>(s, I, ns, mc, ko);
-      pfd::launch_kfinish<T>(s, I, ns, mc);
-      continue;
+      pfd::launch_karnoldi<T>(s, I, ns, mc, ko);
     }
-    if (!iter) break;
-    apply(0);
+    {
+      Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+      pfd::launch_kycomb<T>(s, I, ns, mc);
+    }
+    apply(1);
     Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-    pfd::launch_karnoldi<T>(s, I, ns, mc, ko);
+    pfd::launch_kcycle_end<T>(s, I, ns, mc, ko);
+    pfd::launch_kfinish<T>(s, I, ns, mc);
   }
   {
     Prof p(ctx, PF_K_UPDATE, 0.0, 0.0);
