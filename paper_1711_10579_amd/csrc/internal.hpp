@@ -145,10 +145,13 @@ struct Batch {
   Ctx* ctx = nullptr;
   std::vector<Case*> cases;
   int nslots = 0;
-  char* dmem = nullptr;  // instance pointer table, work items, Red gather buffer
+  char* dmem = nullptr;  // instance pointer table, work items
   const pfd::Inst* const* d_insts = nullptr;
   int2* d_work = nullptr;
-  pfd::Red* d_reds = nullptr;
+  // pinned host memory that the state gathers write into directly: the
+  // instances' Newton states, then their Krylov states
+  pfd::Red* h_reds = nullptr;
+  int* h_kstate = nullptr;
   int lu_steps = 0;  // Newton steps of the batch's last LU solve (queued ahead of the first read-back)
   std::vector<Launch> seq;
   int64_t zero_off = 0;  // zeroing chunks of the factor storage: work items [zero_off, +nzero)
@@ -176,7 +179,6 @@ struct Batch {
   bool kbuilt = false;
   char* kmem = nullptr;
   int2* d_kwork = nullptr;
-  int* d_kstate = nullptr;
   std::vector<std::pair<int64_t, int>> k_lev, k_ulev;
   std::pair<int64_t, int> k_blocks{0, 0};
   int max_kchunks = 0;

@@ -30,6 +30,7 @@ Batch::~Batch() {
     if (dmem) ctx->dfree(dmem);
     if (kmem) ctx->dfree(kmem);
   }
+  if (h_reds) (void)hipHostFree(h_reds);
   for (auto& g : graphs) g.reset();
 }
 
@@ -221,16 +222,21 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     }
     nzero = (int)((int64_t)work.size() - zero_off);
   }
-  // device buffer: instance table | work items | Red gather
+  // device buffer: instance table | work items
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t b_tab = al(sizeof(void*) * std::max(nslots, 1));
   const size_t b_work = al(sizeof(int2) * std::max<size_t>(work.size(), 1));
-  const size_t b_red = al(sizeof(pfd::Red) * std::max(nslots, 1));
-  dmem = (char*)ctx->dalloc(b_tab + b_work + b_red);
+  dmem = (char*)ctx->dalloc(b_tab + b_work);
   if (!dmem) return false;
   d_insts = (const pfd::Inst* const*)dmem;
   d_work = (int2*)(dmem + b_tab);
-  d_reds = (pfd::Red*)(dmem + b_tab + b_work);
+  {
+    void* hp = nullptr;
+    const size_t hr = al(sizeof(pfd::Red) * std::max(nslots, 1));
+    if (hipHostMalloc(&hp, hr + sizeof(int) * std::max(nslots, 1), hipHostMallocCoherent) != hipSuccess) return false;
+    h_reds = (pfd::Red*)hp;
+    h_kstate = (int*)((char*)hp + hr);
+  }
   std::vector<const pfd::Inst*> tab(nslots);
   for (int s = 0; s < nslots; ++s) tab[s] = cs[s]->d_inst;
   hipStream_t st = ctx->stream;
@@ -457,12 +463,13 @@ pf_status step_batch(Batch* b, const pf_options* opt) {
 pf_status read_batch(Batch* b, std::vector<pfd::Red>* h) {
   hipStream_t s = b->ctx->stream;
   h->resize(b->nslots);
-  pfd::launch_gather_red(s, b->d_insts, b->nslots, b->d_reds);
-  if (hipMemcpyAsync(h->data(), b->d_reds, sizeof(pfd::Red) * b->nslots, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
+  // the gather writes straight into pinned host memory
+  pfd::launch_gather_red(s, b->d_insts, b->nslots, b->h_reds);
+  if (hipStreamSynchronize(s) != hipSuccess) {
     set_error("pf_solve: device failure during the Newton iteration");
     return PF_E_DEVICE;
   }
+  std::memcpy(h->data(), b->h_reds, sizeof(pfd::Red) * b->nslots);
   b->ctx->prof_flush();
   for (const auto& r : *h)
     if (r.timeout) {

@@ -217,12 +217,10 @@ bool Batch::build_krylov() {
     k_blocks = {off, (int)((int64_t)work.size() - off)};
   }
   const size_t bw = (sizeof(int2) * std::max<size_t>(work.size(), 1) + 255) & ~(size_t)255;
-  const size_t bs = sizeof(int) * std::max(nslots, 1);
   if (kmem) ctx->dfree(kmem);
-  kmem = (char*)ctx->dalloc(bw + bs);
+  kmem = (char*)ctx->dalloc(bw);
   if (!kmem) return false;
   d_kwork = (int2*)kmem;
-  d_kstate = (int*)(kmem + bw);
   hipStream_t st = ctx->stream;
   bool ok = true;
   if (!work.empty())
@@ -291,12 +289,13 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       set_error("pf_solve: the Krylov inner solve did not settle");
       return PF_E_DEVICE;
     }
-    pfd::launch_kgather(s, I, ns, b->d_kstate);
-    if (hipMemcpyAsync(st.data(), b->d_kstate, sizeof(int) * ns, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    // the gather writes straight into pinned host memory
+    pfd::launch_kgather(s, I, ns, b->h_kstate);
+    if (hipStreamSynchronize(s) != hipSuccess) {
       set_error("pf_solve: device failure in the Krylov inner solve");
       return PF_E_DEVICE;
     }
+    std::memcpy(st.data(), b->h_kstate, sizeof(int) * ns);
     bool iter = false, cyc = false;
     for (int v : st) {
       iter |= v == pfd::KS_ITER;
