@@ -141,14 +141,14 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
     by eq. 12-20, Jacobian by eq. 21-23, solve, add dV to the real and
     imaginary parts (eq. 20 order) and convert back to complex form.  Stops on
     the max-norm of the current mismatch (and at the rounding floor as in the
-    single-phase loop).  ``linear="gmres"`` solves each step inexactly as in
+    single-phase loop).  ``linear="gmres"`` or ``"bicgstab"`` solves each step inexactly as in
     the single-phase loop (Sec. III-B)."""
     unknown, _, _, col_re, col_im, _ = unknown_layout(case)
     u = np.flatnonzero(unknown)
     V = flat_start(case) if V0 is None else np.array(V0, np.complex128)
     history, steps, lin = [], [], []
     status = MAXITER
-    if linear == "gmres":
+    if linear in ("gmres", "bicgstab"):
         from . import krylov
 
         node_of = np.empty(2 * u.shape[0], np.int64)
@@ -175,9 +175,10 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
             status = MAXITER
             break
         J = jacobian(case, V)
-        if linear == "gmres":
+        if linear in ("gmres", "bicgstab"):
             try:
-                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, **krylov_opts)
+                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, method=linear,
+                                               **krylov_opts)
             except (ArithmeticError, np.linalg.LinAlgError):
                 status = SINGULAR
                 break

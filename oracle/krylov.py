@@ -1,18 +1,20 @@
 """Newton-Krylov inner solve (Sec. III-B): the Jacobian system of each Newton
 step is solved only approximately, by an iterative Krylov method.
 
-The paper names the Krylov family and its parallel building blocks (sparse
-matrix-vector products and vector updates) but neither the method's variant
-nor a preconditioner.  The reading taken here is restarted GMRES(m) with
-right preconditioning, the preconditioner being either ILU(0) or
-block-Jacobi, and the inner tolerance being the forcing term
-eta_k = min(eta_max, ||F_k||_inf) of inexact Newton methods (Dembo,
-Eisenstat and Steihaug; Eisenstat and Walker) relative to ||F_k||_2.
+The paper tested the bi-conjugate gradient stabilized method (BiCGStab, its
+reference [20]) and names the parallel building blocks (sparse
+matrix-vector products and vector updates), but no preconditioner.  Two
+methods are given here: BiCGStab and restarted GMRES(m), both with right
+preconditioning, the preconditioner being either ILU(0) or block-Jacobi, and
+the inner tolerance being the forcing term eta_k = min(eta_max,
+||F_k||_inf) of inexact Newton methods (Dembo, Eisenstat and Steihaug;
+Eisenstat and Walker) relative to ||F_k||_2.
 
 Written from the textbook definitions (Saad, "Iterative Methods for Sparse
 Linear Systems": GMRES with modified Gram-Schmidt Arnoldi and Givens
-rotations, right-preconditioned; ILU(0) in its IKJ form), for clarity rather
-than speed.  Test infrastructure only: nothing on the GPU path imports it.
+rotations, and BiCGStab as van der Vorst gave it, both right-preconditioned;
+ILU(0) in its IKJ form), for clarity rather than speed.  Test infrastructure
+only: nothing on the GPU path imports it.
 """
 
 from collections import deque
@@ -202,8 +204,84 @@ def gmres(A, b, apply_m, m, rtol, max_restarts):
     return x, total, rel, False, hist
 
 
+def bicgstab(A, b, apply_m, rtol, max_iter, record=None):
+    """Right-preconditioned BiCGStab from x0 = 0 (van der Vorst): the shadow
+    residual is r0 = b; each iteration takes a bi-conjugate gradient step
+    along the preconditioned direction and then a one-dimensional minimal
+    residual step, and stops once the residual's 2-norm is at most rtol
+    ||b||_2 -- already after the first half when that half's residual s
+    meets it.  At most max_iter iterations; a zero <r0, r>, <r0, v> or
+    <t, t> ends the solve as it stands.  Returns x, the iterations begun, the
+    final relative residual of the recurrence, whether rtol was met and the
+    relative residual after every iteration.  ``record``: a list that
+    receives, per completed iteration, the vectors s and t and the step
+    omega (for tests)."""
+    A = sp.csr_matrix(A)
+    b = np.asarray(b, dtype=np.float64)
+    N = b.shape[0]
+    x = np.zeros(N)
+    bnorm = float(np.linalg.norm(b))
+    hist = []
+    if bnorm == 0.0:
+        return x, 0, 0.0, True, hist
+    r = b.copy()
+    rs = b.copy()  # shadow residual
+    p = np.zeros(N)
+    v = np.zeros(N)
+    rho_prev = alpha = omega = 1.0
+    rel = 1.0
+    its = 0
+    for i in range(max_iter):
+        rho = float(rs @ r)
+        if rho == 0.0:
+            break
+        its = i + 1
+        if i == 0:
+            p = r.copy()
+        else:
+            beta = (rho / rho_prev) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+        ph = apply_m(p)
+        v = A @ ph
+        sv = float(rs @ v)
+        if sv == 0.0:
+            break
+        alpha = rho / sv
+        s = r - alpha * v
+        srel = float(np.linalg.norm(s)) / bnorm
+        if srel <= rtol:
+            x = x + alpha * ph
+            rel = srel
+            hist.append(rel)
+            return x, its, rel, True, hist
+        sh = apply_m(s)
+        t = A @ sh
+        tt = float(t @ t)
+        if tt == 0.0:
+            break
+        omega = float(t @ s) / tt
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        rel = float(np.linalg.norm(r)) / bnorm
+        hist.append(rel)
+        if record is not None:
+            record.append({"s": s, "t": t, "omega": omega})
+        if rel <= rtol:
+            return x, its, rel, True, hist
+        if omega == 0.0:
+            break
+        rho_prev = rho
+    return x, its, rel, False, hist
+
+
 # ---------------------------------------------------------------------------
 # the inexact Newton step
+
+def bicgstab_max_iter(m, max_restarts):
+    """BiCGStab's iteration limit: two products with J per iteration, as many
+    products in all as GMRES(m) with max_restarts restarts may take."""
+    return max(1, (1 + max_restarts) * m // 2)
+
 
 def forcing(nrm_inf, eta_max):
     """eta_k = min(eta_max, ||F_k||_inf)."""
@@ -211,10 +289,12 @@ def forcing(nrm_inf, eta_max):
 
 
 def inexact_step(J, F, nrm_inf, node_of_unknown, comp_of_unknown, node_graph, precond="ilu0", m=30,
-                 max_restarts=10, eta_max=0.1, bj_cap=32):
+                 max_restarts=10, eta_max=0.1, bj_cap=32, method="gmres"):
     """Solve J dx = F to the relative residual eta_k with right-preconditioned
-    GMRES(m) in the node-interleaved reverse Cuthill-McKee order.  Returns dx
-    (in the original unknown order) and an info dict with the iterations, the
+    GMRES(m) (at most 1 + max_restarts cycles) or BiCGStab (at most
+    (1 + max_restarts) m / 2 iterations: the same number of products with
+    J) in the node-interleaved reverse Cuthill-McKee order.  Returns dx (in
+    the original unknown order) and an info dict with the iterations, the
     forcing term, the achieved relative residual and whether it was met."""
     perm, node_rank = unknown_order(node_of_unknown, comp_of_unknown, node_graph)
     A = sp.csr_matrix(J)[perm][:, perm]
@@ -232,7 +312,12 @@ def inexact_step(J, F, nrm_inf, node_of_unknown, comp_of_unknown, node_graph, pr
     else:
         raise ValueError(precond)
     eta = forcing(nrm_inf, eta_max)
-    y, its, rel, ok, hist = gmres(A, rhs, apply_m, m, eta, max_restarts)
+    if method == "gmres":
+        y, its, rel, ok, hist = gmres(A, rhs, apply_m, m, eta, max_restarts)
+    elif method == "bicgstab":
+        y, its, rel, ok, hist = bicgstab(A, rhs, apply_m, eta, bicgstab_max_iter(m, max_restarts))
+    else:
+        raise ValueError(method)
     dx = np.empty_like(y)
     dx[perm] = y
     return dx, {"iters": its, "eta": eta, "rel": rel, "met": ok, "history": hist}

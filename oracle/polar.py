@@ -112,8 +112,9 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
     two steps in a row bring no tenfold decrease below the best earlier norm,
     the result is reported as converged.
 
-    ``linear="gmres"`` makes it the Newton-Krylov iteration of Sec. III-B:
-    the step is solved inexactly by ``krylov.inexact_step`` (options
+    ``linear="gmres"`` or ``"bicgstab"`` makes it the Newton-Krylov
+    iteration of Sec. III-B: the step is solved inexactly by
+    ``krylov.inexact_step`` with that method (options
     ``precond``, ``m``, ``max_restarts``, ``eta_max``); a step whose relative
     residual misses its forcing term but is at most ``eta_max`` is taken, a
     worse one ends the iteration with status LINEAR_FAIL.
@@ -126,7 +127,7 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
         va = np.array(va0, np.float64)
     history, steps, lin = [], [], []
     status = MAXITER
-    if linear == "gmres":
+    if linear in ("gmres", "bicgstab"):
         from . import krylov
 
         node_of = np.concatenate([pvpq, pq])
@@ -151,9 +152,10 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
             status = MAXITER
             break
         J = jacobian(case, vm, va)
-        if linear == "gmres":
+        if linear in ("gmres", "bicgstab"):
             try:
-                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, **krylov_opts)
+                dx, info = krylov.inexact_step(J, F, nrm, node_of, comp_of, graph, method=linear,
+                                               **krylov_opts)
             except (ArithmeticError, np.linalg.LinAlgError):
                 status = SINGULAR
                 break

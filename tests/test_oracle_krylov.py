@@ -175,3 +175,73 @@ def test_linear_fail_status_when_the_inner_solve_cannot_progress():
     case = pfgen.make_polar_grid(300, 90, 30, 12, balanced=True)
     r = polar.newton(case, linear="gmres", precond="none", m=1, max_restarts=0, eta_max=1e-6)
     assert r.status == LINEAR_FAIL
+
+
+# ---------------------------------------------------------------------------
+# BiCGStab
+
+
+def _exact_solver(A):
+    lu = sp.linalg.splu(sp.csc_matrix(A))
+    return lu.solve
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (5, 2), (8, 3), (12, 4)])
+def test_bicgstab_finite_termination(n, seed):
+    # a bi-conjugate gradient method ends within n steps in exact
+    # arithmetic: on small well-conditioned systems the residual is at
+    # rounding level after n iterations at most
+    A = _random_pattern_matrix(n, 3 * n, seed, dominance=1.0).toarray()
+    b = np.random.default_rng(seed).uniform(-1, 1, n)
+    x, its, rel, ok, _ = krylov.bicgstab(A, b, lambda v: v, 1e-13, n)
+    assert ok and its <= n, (its, rel)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-10 * np.max(np.abs(x)))
+
+
+def test_bicgstab_with_the_exact_inverse_ends_in_one_half_step():
+    # right preconditioning by A^{-1}: v = A A^{-1} p = r, so alpha = 1,
+    # s = 0 and x = A^{-1} b after the first half of the first iteration
+    A = _random_pattern_matrix(60, 120, 5)
+    b = np.random.default_rng(5).uniform(-1, 1, 60)
+    x, its, rel, ok, hist = krylov.bicgstab(A, b, _exact_solver(A), 1e-10, 10)
+    assert ok and its == 1 and len(hist) == 1 and rel <= 1e-12
+    assert np.allclose(A @ x, b, atol=1e-12)
+
+
+def test_bicgstab_recurrence_is_the_true_residual_and_omega_minimises_it():
+    A = _random_pattern_matrix(150, 400, 6, dominance=0.8)
+    b = np.random.default_rng(6).uniform(-1, 1, 150)
+    L, U = krylov.ilu0(A)
+    rec = []
+    x, its, rel, ok, hist = krylov.bicgstab(A, b, krylov.ilu0_apply(L, U), 1e-9, 200, record=rec)
+    assert ok and its >= 2
+    true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert abs(true_rel - rel) <= 1e-9
+    # the second half-step minimises ||s - omega t||: the new residual is
+    # orthogonal to t, and moving omega either way makes it longer
+    for it in rec:
+        s, t, w = it["s"], it["t"], it["omega"]
+        r = s - w * t
+        assert abs(t @ r) <= 1e-10 * np.linalg.norm(t) * np.linalg.norm(s)
+        for dw in (1e-3, -1e-3):
+            assert np.linalg.norm(s - (w + dw) * t) > np.linalg.norm(r)
+    # residuals after each iteration are those the history reports
+    assert len(hist) == its
+
+
+@pytest.mark.parametrize("precond", ["ilu0", "bjacobi"])
+def test_bicgstab_newton_reaches_the_direct_root(precond):
+    case = pfgen.make_polar_grid(300, 90, 30, 11, balanced=True)
+    ref = polar.newton(case)
+    res = polar.newton(case, linear="bicgstab", precond=precond)
+    assert ref.status == CONVERGED and res.status == CONVERGED
+    assert np.max(np.abs(res.V - ref.V)) <= 1e-8
+    assert all(k >= 1 for k in res.linear_iters)
+
+
+def test_bicgstab_cim_newton_reaches_the_direct_root():
+    case = pfgen.make_feeder(80, 4)
+    ref = cim.newton(case)
+    res = cim.newton(case, linear="bicgstab")
+    assert ref.status == CONVERGED and res.status == CONVERGED
+    assert np.max(np.abs(res.V - ref.V)) <= 1e-8
