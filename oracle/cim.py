@@ -136,17 +136,20 @@ def jacobian(case, V):
     return J
 
 
-def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=None, **krylov_opts):
+def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=None, fallback=False,
+           **krylov_opts):
     """The three-phase Newton-Raphson (CIM) iteration of Sec. II-B: mismatch
     by eq. 12-20, Jacobian by eq. 21-23, solve, add dV to the real and
     imaginary parts (eq. 20 order) and convert back to complex form.  Stops on
     the max-norm of the current mismatch (and at the rounding floor as in the
     single-phase loop).  ``linear="gmres"`` or ``"bicgstab"`` solves each step inexactly as in
-    the single-phase loop (Sec. III-B)."""
+    the single-phase loop (Sec. III-B), with the same ``fallback`` to the
+    direct solve."""
     unknown, _, _, col_re, col_im, _ = unknown_layout(case)
     u = np.flatnonzero(unknown)
     V = flat_start(case) if V0 is None else np.array(V0, np.complex128)
     history, steps, lin = [], [], []
+    fell_back = False
     status = MAXITER
     if linear in ("gmres", "bicgstab"):
         from . import krylov
@@ -184,9 +187,13 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
                 break
             lin.append(info["iters"])
             if not info["met"] and not info["rel"] <= krylov_opts.get("eta_max", 0.1):
-                status = LINEAR_FAIL
-                break
-        else:
+                if not fallback:
+                    status = LINEAR_FAIL
+                    break
+                # the direct method takes over from the failed step on
+                # (Sec. III-A: it solves where the Krylov method fails)
+                linear, fell_back = "sparse", True
+        if linear not in ("gmres", "bicgstab"):
             try:
                 dx = linalg.solve(J, F, linear)
             except linalg.SingularError:
@@ -199,7 +206,7 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, V0=Non
         vi[u] += dx[col_im[u]]
         V = vr + 1j * vi
     return OracleResult(status=status, iters=len(steps), V=V, history=history,
-                        steps=steps, mismatch_inf=history[-1], linear_iters=lin)
+                        steps=steps, mismatch_inf=history[-1], linear_iters=lin, lu_fallback=fell_back)
 
 
 def mismatch_at(case, V):

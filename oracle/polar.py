@@ -102,7 +102,8 @@ def jacobian(case, vm, va):
     return sp.bmat([[J1, J2], [J3, J4]], format="csr")
 
 
-def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=None, va0=None, **krylov_opts):
+def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=None, va0=None, fallback=False,
+           **krylov_opts):
     """The single-phase Newton-Raphson iteration of Sec. II-A.
 
     Each step evaluates the mismatch (eq. 8-9), stops if its max-norm is at
@@ -117,7 +118,8 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
     ``krylov.inexact_step`` with that method (options
     ``precond``, ``m``, ``max_restarts``, ``eta_max``); a step whose relative
     residual misses its forcing term but is at most ``eta_max`` is taken, a
-    worse one ends the iteration with status LINEAR_FAIL.
+    worse one ends the iteration with status LINEAR_FAIL, or, with
+    ``fallback``, hands the iteration to the direct solve from that step on.
     """
     pvpq, pq = index_sets(case)
     npv = pvpq.shape[0]
@@ -126,6 +128,7 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
         vm = np.array(vm0, np.float64)
         va = np.array(va0, np.float64)
     history, steps, lin = [], [], []
+    fell_back = False
     status = MAXITER
     if linear in ("gmres", "bicgstab"):
         from . import krylov
@@ -161,9 +164,13 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
                 break
             lin.append(info["iters"])
             if not info["met"] and not info["rel"] <= krylov_opts.get("eta_max", 0.1):
-                status = LINEAR_FAIL
-                break
-        else:
+                if not fallback:
+                    status = LINEAR_FAIL
+                    break
+                # the direct method takes over from the failed step on
+                # (Sec. III-A: it solves where the Krylov method fails)
+                linear, fell_back = "sparse", True
+        if linear not in ("gmres", "bicgstab"):
             try:
                 dx = linalg.solve(J, F, linear)
             except linalg.SingularError:
@@ -174,7 +181,7 @@ def newton(case, tol=1e-12, max_iter=20, linear="sparse", floor_tol=1e-8, vm0=No
         vm[pq] += dx[npv:]
     V = vm * np.exp(1j * va)
     return OracleResult(status=status, iters=len(steps), V=V, history=history,
-                        steps=steps, mismatch_inf=history[-1], linear_iters=lin)
+                        steps=steps, mismatch_inf=history[-1], linear_iters=lin, lu_fallback=fell_back)
 
 
 def mismatch_at(case, V):

@@ -16,6 +16,7 @@ class OracleResult:
     steps: list                # max |dx| of each Newton step (the paper's stop test)
     mismatch_inf: float        # max-norm of the final mismatch
     linear_iters: list = dataclasses.field(default_factory=list)  # Krylov steps per Newton step
+    lu_fallback: bool = False  # a Krylov step failed and direct solves finished the iteration
 
     @property
     def vm(self):

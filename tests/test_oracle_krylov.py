@@ -245,3 +245,20 @@ def test_bicgstab_cim_newton_reaches_the_direct_root():
     res = cim.newton(case, linear="bicgstab")
     assert ref.status == CONVERGED and res.status == CONVERGED
     assert np.max(np.abs(res.V - ref.V)) <= 1e-8
+
+
+@pytest.mark.parametrize("linear", ["gmres", "bicgstab"])
+def test_fallback_finishes_a_failed_krylov_iteration_at_the_direct_root(linear):
+    # a starved inner solve (one Krylov step, no restarts, a forcing term
+    # the step cannot meet) fails the first Newton step; with the fallback
+    # the direct solve takes that step and the rest and reaches the same
+    # root as direct Newton from the flat start
+    case = pfgen.make_polar_grid(300, 90, 30, 11, balanced=True)
+    opts = dict(precond="bjacobi", m=2, max_restarts=0, eta_max=1e-3)
+    bad = polar.newton(case, linear=linear, **opts)
+    assert bad.status == LINEAR_FAIL and not bad.lu_fallback
+    res = polar.newton(case, linear=linear, fallback=True, **opts)
+    ref = polar.newton(case)
+    assert res.status == CONVERGED and res.lu_fallback
+    assert np.max(np.abs(res.V - ref.V)) <= 1e-8
+    assert res.iters == ref.iters  # the failed step is not taken, the direct ones are the same
