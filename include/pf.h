@@ -13,11 +13,15 @@
  *   - PF_MODEL_POLAR_1PH: single-phase polar mismatch dP/dQ (eq. 4-10),
  *   - PF_MODEL_CIM_3PH  : three-phase current-injection mismatch dI with ZIP
  *                         loads (eq. 12-23).
- * and two inner linear solvers:
- *   - PF_SOLVER_LU   : sparse LU refactorisation on a fill-reducing ordering
- *                      with a dense trailing block (Sec. III-A),
- *   - PF_SOLVER_GMRES: Newton-Krylov, restarted GMRES with an ILU(0) or
- *                      block-Jacobi preconditioner (Sec. III-B).
+ * and three inner linear solvers:
+ *   - PF_SOLVER_LU      : sparse LU refactorisation on a fill-reducing
+ *                         ordering with a dense trailing block (Sec. III-A),
+ *   - PF_SOLVER_GMRES   : Newton-Krylov, restarted GMRES with an ILU(0) or
+ *                         block-Jacobi preconditioner (Sec. III-B),
+ *   - PF_SOLVER_BICGSTAB: Newton-Krylov with BiCGStab, the Krylov method the
+ *                         paper tested (Sec. III-B), same preconditioners.
+ * A Newton-Krylov solve may fall back to LU when an inner solve fails (the
+ * direct method's robustness, Sec. III-A).
  *
  * Conventions: all sizes are int32; reals are IEEE double; complex values are
  * interleaved (re, im) pairs; powers and voltages are per unit; angles are in
@@ -58,7 +62,7 @@ typedef enum {
   PF_MAXITER = 1,    /* iteration limit reached                                */
   PF_DIVERGED = 2,   /* non-finite mismatch or growth beyond 1e6 x initial     */
   PF_SINGULAR = 3,   /* zero or non-finite pivot in the refactorisation        */
-  PF_LINEAR_FAIL = 4,/* GMRES did not reach its forcing tolerance              */
+  PF_LINEAR_FAIL = 4,/* the Krylov solve did not reach its forcing tolerance */
   PF_PENDING = 5     /* served request not finished yet                        */
 } pf_solve_status;
 
@@ -67,7 +71,7 @@ typedef enum { PF_MODEL_POLAR_1PH = 0, PF_MODEL_CIM_3PH = 1 } pf_model;
  * bus's phase-nodes are PF_SLACK (fixed voltage), all others PF_PQ; the paper
  * adds no PV injection in the three-phase method (Sec. II-B). */
 typedef enum { PF_PQ = 1, PF_PV = 2, PF_SLACK = 3 } pf_bus_type;
-typedef enum { PF_SOLVER_LU = 0, PF_SOLVER_GMRES = 1 } pf_solver;
+typedef enum { PF_SOLVER_LU = 0, PF_SOLVER_GMRES = 1, PF_SOLVER_BICGSTAB = 2 } pf_solver;
 typedef enum { PF_PREC_FP64 = 0, PF_PREC_MIXED = 1 } pf_precision;
 typedef enum { PF_PRECOND_ILU0 = 0, PF_PRECOND_BJACOBI = 1 } pf_precond;
 
@@ -106,14 +110,18 @@ typedef struct {
  *   tol        1e-8   stop when the max-norm of the FP64 mismatch <= tol
  *                     (pu power for polar, pu current for CIM)
  *   max_iter   20     Newton iteration limit (40 recommended with MIXED)
- *   solver     LU     PF_SOLVER_LU or PF_SOLVER_GMRES
+ *   solver     LU     PF_SOLVER_LU, PF_SOLVER_GMRES or PF_SOLVER_BICGSTAB
  *   precision  FP64   PF_PREC_MIXED: Jacobian factor and inner solves in FP32,
  *                     mismatch, update and convergence test in FP64
- *   precond    ILU0   GMRES preconditioner
+ *   precond    ILU0   Krylov preconditioner
  *   gmres_m    30     GMRES restart length
- *   gmres_max_restarts 10
- *   eta_max    0.1    GMRES forcing term eta_k = min(eta_max, ||F_k||_inf)
+ *   gmres_max_restarts 10  (BiCGStab: at most (1 + gmres_max_restarts) *
+ *                     gmres_m / 2 iterations, as many products with J)
+ *   eta_max    0.1    Krylov forcing term eta_k = min(eta_max, ||F_k||_inf)
  *   flat_start 1      0: start from the case's current voltage (warm start)
+ *   nk_fallback 0     1: when a Krylov step fails (PF_LINEAR_FAIL), the
+ *                     Newton iteration continues with LU from the voltage
+ *                     it has reached (pf_result.lu_fallback = 1)
  */
 typedef struct {
   double tol;
@@ -124,14 +132,15 @@ typedef struct {
   int32_t gmres_m;
   int32_t gmres_max_restarts;
   int32_t flat_start;
+  int32_t nk_fallback;
   double eta_max;
 } pf_options;
 
 typedef struct {
   int32_t status;       /* pf_solve_status                                   */
   int32_t iters;        /* Newton steps taken (linear solves)                */
-  int32_t linear_iters; /* total GMRES iterations (0 for LU)                 */
-  int32_t reserved;
+  int32_t linear_iters; /* total Krylov iterations (0 for LU)                */
+  int32_t lu_fallback;  /* 1: a Krylov step failed and LU finished the solve */
   double mismatch_inf;  /* max-norm of the final FP64 mismatch               */
   double max_step;      /* max |dx| of the last Newton step (the paper's test)*/
   double device_ms;     /* device time of the solve (events around it)       */

@@ -40,7 +40,7 @@ PF_OK, PF_E_INVALID, PF_E_NOMEM, PF_E_DEVICE, PF_E_BUSY, PF_E_NOTFOUND = range(6
 PF_CONVERGED, PF_MAXITER, PF_DIVERGED, PF_SINGULAR, PF_LINEAR_FAIL, PF_PENDING = range(6)
 PF_MODEL_POLAR_1PH, PF_MODEL_CIM_3PH = 0, 1
 PF_PQ, PF_PV, PF_SLACK = 1, 2, 3
-PF_SOLVER_LU, PF_SOLVER_GMRES = 0, 1
+PF_SOLVER_LU, PF_SOLVER_GMRES, PF_SOLVER_BICGSTAB = 0, 1, 2
 PF_PREC_FP64, PF_PREC_MIXED = 0, 1
 PF_PRECOND_ILU0, PF_PRECOND_BJACOBI = 0, 1
 (PF_K_MISMATCH, PF_K_JFILL, PF_K_SPARSE_FACTOR, PF_K_TAIL_SCHUR, PF_K_DENSE_PANEL,
@@ -67,16 +67,16 @@ class pf_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("solver", C.c_int32),
                 ("precision", C.c_int32), ("precond", C.c_int32), ("gmres_m", C.c_int32),
                 ("gmres_max_restarts", C.c_int32), ("flat_start", C.c_int32),
-                ("eta_max", C.c_double)]
+                ("nk_fallback", C.c_int32), ("eta_max", C.c_double)]
 
 
 class pf_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("linear_iters", C.c_int32),
-                ("reserved", C.c_int32), ("mismatch_inf", C.c_double), ("max_step", C.c_double),
+                ("lu_fallback", C.c_int32), ("mismatch_inf", C.c_double), ("max_step", C.c_double),
                 ("device_ms", C.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class pf_schedule(C.Structure):

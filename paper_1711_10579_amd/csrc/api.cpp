@@ -259,6 +259,7 @@ void pf_default_options(pf_options* o) {
   o->gmres_m = 30;
   o->gmres_max_restarts = 10;
   o->flat_start = 1;
+  o->nk_fallback = 0;
   o->eta_max = 0.1;
 }
 

@@ -95,14 +95,17 @@ struct KState {
   double eta;    // forcing term (relative residual target)
   double scale;  // factor that normalises the next basis vector
   double rel;    // residual estimate relative to bnorm
-  int j;         // Arnoldi steps of the current cycle
+  double rho, alpha, omega, beta;  // BiCGStab: <r0, r>, and the step factors
+  int j;         // Arnoldi steps of the current cycle (BiCGStab: iterations done)
   int cycle;     // restarts done
   int state;     // KS_* below
   int met;       // forcing term met
   int total;     // Arnoldi steps of this Newton step
   int pad;
 };
-enum { KS_DONE = 0, KS_ITER = 1, KS_CYCLE = 2, KS_RESTART = 3, KS_FINISH = 4 };
+// KS_BP, KS_BS: the two halves of a BiCGStab iteration; KS_BH: the first
+// half met the tolerance (its update of x pending)
+enum { KS_DONE = 0, KS_ITER = 1, KS_CYCLE = 2, KS_RESTART = 3, KS_FINISH = 4, KS_BP = 5, KS_BS = 6, KS_BH = 7 };
 
 // Options of the Krylov inner solve.
 struct KOpts {

@@ -47,8 +47,9 @@ void launch_dense_step(hipStream_t, const Inst* const* insts, const int2* work, 
 template <typename T>
 void launch_dense_trsv(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int single);
 
-// Newton-Krylov inner solve (krylov.hip); mode 0 = Arnoldi step, 1 = end of
-// cycle
+// Newton-Krylov inner solve (krylov.hip); preconditioner mode 0 = Arnoldi
+// step, 1 = end of a GMRES cycle, 2 and 3 = the halves of a BiCGStab
+// iteration
 template <typename T>
 void launch_kfill(hipStream_t, const Inst* const* insts, int nslots, int max_nnz, int ilu);
 template <typename T>
@@ -75,6 +76,16 @@ template <typename T>
 void launch_kcycle_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
 template <typename T>
 void launch_kfinish(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
+// BiCGStab: start, then per iteration the direction, [apply mode 2], the
+// first half and its test, [apply mode 3], the second half and the test
+template <typename T>
+void launch_bcg_begin(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+template <typename T>
+void launch_bcg_dir(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
+template <typename T>
+void launch_bcg_half(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+template <typename T>
+void launch_bcg_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
 void launch_kgather(hipStream_t, const Inst* const* insts, int nslots, int* out);
 int krylov_max_restart();
 

@@ -37,6 +37,13 @@ constexpr int KMAX = 128;  // largest restart length the kernels accept
 
 __device__ inline bool kstate_is(const Inst& I, int want) { return I.red->active && I.ks->state == want; }
 
+// the Krylov state a preconditioner application serves: mode 0 an Arnoldi
+// step (scaled input stored as basis vector), 1 the end of a GMRES cycle,
+// 2 and 3 the first and second half of a BiCGStab iteration
+__device__ inline int apply_state(int mode) {
+  return mode == 0 ? KS_ITER : mode == 1 ? KS_CYCLE : mode == 2 ? KS_BP : KS_BS;
+}
+
 __device__ inline double* kh_H(const Inst& I) { return I.kh; }
 __device__ inline double* kh_cs(const Inst& I) { return I.kh + (int64_t)(I.km + 1) * I.km; }
 __device__ inline double* kh_sn(const Inst& I) { return kh_cs(I) + I.km; }
@@ -221,7 +228,7 @@ __global__ __launch_bounds__(256) void k_ilu_fwd(const Inst* const* insts, const
   if (idx >= nwork) return;
   const int2 wk = work[idx];
   const Inst& I = *insts[wk.x];
-  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
   const T* w = (const T*)I.kw;
   T* z = (T*)I.kz;
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const
   if (idx >= nwork) return;
   const int2 wk = work[idx];
   const Inst& I = *insts[wk.x];
-  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
   T* z = (T*)I.kz;
   const T* P = (const T*)I.pval;
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
   __shared__ int lpf[LPM + 1], lpb[LPM + 1];
   const auto& I = *gp(insts[blockIdx.x]);
   const auto ks = gp(I.ks);
-  if (!gp(I.red)->active || ks->state != (mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  if (!gp(I.red)->active || ks->state != (apply_state(mode))) return;
   const int nu = I.nu;
   if (2 * nu <= zmin || (ZV > 0 && 2 * nu > ZV)) return;
   T* z = ZV > 0 ? zl : (T*)I.kz;
@@ -494,7 +501,7 @@ __global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const
   __shared__ double v[64];
   const int2 wk = work[blockIdx.x];
   const Inst& I = *insts[wk.x];
-  if (!kstate_is(I, mode == 0 ? KS_ITER : KS_CYCLE)) return;
+  if (!kstate_is(I, apply_state(mode))) return;
   const int b = wk.y;
   const int r0 = I.bj_ptr[b];
   const int N = 2 * (I.bj_ptr[b + 1] - r0);
@@ -890,6 +897,333 @@ __global__ __launch_bounds__(KCH) void k_kfinish(const Inst* const* insts) {
   out[2 * p + 1] = x[2 * r + 1];
 }
 
+// ---------------------------------------------------------------------------
+// BiCGStab (van der Vorst), the Krylov method the paper tested (Sec. III-B),
+// right-preconditioned, from x = 0 with the shadow residual r0 = F.  Vectors
+// in the basis storage: r (0; s overwrites it), r0 (1), p (2), v (3),
+// p^ = M^-1 p (4), s^ = M^-1 s (5), t (6).  One iteration is the launch
+// sequence
+//   KS_BP: p = r + beta (p - omega v) (p = r at first) into w; z = M^-1 w;
+//          p^ = z, v = J p^ with partial <r0, v>; alpha = <r0, r> / <r0, v>,
+//          s = r - alpha v into w with partial ||s||^2; per instance: the
+//          first half meets the tolerance (-> KS_BH) or not (-> KS_BS)
+//   KS_BS: z = M^-1 w; s^ = z, t = J s^ with partial <t, s>, <t, t>;
+//          omega = <t, s> / <t, t>, x += alpha p^ + omega s^,
+//          r = s - omega t with partial <r0, r>, ||r||^2; per instance: the
+//          convergence test and beta for the next iteration
+//   KS_BH: x += alpha p^, done.
+// A zero <r0, r>, <r0, v>, <t, t> or omega, or the iteration limit, ends the
+// solve with x as it stands: the step is taken when its relative residual
+// is at most eta_max, else the Newton iteration ends with a linear failure.
+
+template <typename T>
+__device__ inline T* kvec(const Inst& I, int i) {
+  return (T*)I.kv + (int64_t)i * 2 * I.nu;
+}
+
+// Sum over the chunks of entry e of a pass's partial sums, in chunk order
+// (the same value wherever it is formed).
+__device__ inline double chunk_sum(const Inst& I, int pass, int e) {
+  double s = 0.0;
+  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, pass, c)[e];
+  return s;
+}
+
+// The solve ends as it stands.
+__device__ inline void bcg_stop(const Inst& I, KOpts o) {
+  if (I.ks->rel <= o.eta_max)
+    I.ks->state = KS_FINISH;
+  else
+    linear_failure(I);
+}
+
+// Per instance, after k_kbegin (w = F, x = 0, partial ||F||^2): ||F||_2,
+// the forcing term, <r0, r> = ||F||^2 and the first iteration.
+__global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, KOpts o) {
+  const Inst& I = *insts[blockIdx.x];
+  if (!I.red->active) return;
+  KState& ks = *I.ks;
+  if (I.red->singular) {
+    if (threadIdx.x == 0) {
+      I.red->status = 3;
+      I.red->active = 0;
+      ks.state = KS_DONE;
+    }
+    return;
+  }
+  double part = 0.0;
+  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
+  const double b2 = wave_sum(part);
+  if (threadIdx.x != 0) return;
+  const double bn = sqrt(b2);
+  ks.bnorm = bn;
+  ks.eta = fmax(fmin(o.eta_max, I.red->last_norm), o.eta_floor);
+  ks.j = 0;
+  ks.cycle = 0;
+  ks.met = 0;
+  ks.total = 0;
+  ks.rel = 1.0;
+  ks.rho = b2;
+  ks.alpha = ks.omega = 1.0;
+  ks.beta = 0.0;
+  if (bn > 0.0) {
+    ks.state = KS_BP;
+  } else {
+    ks.rel = 0.0;
+    ks.met = 1;
+    ks.state = KS_FINISH;
+  }
+}
+
+// p = r + beta (p - omega v), or r = r0 = p = F in the first iteration; w = p.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_dir(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  if (r >= I.nu) return;
+  const KState& ks = *I.ks;
+  T* w = (T*)I.kw;
+  T* R = kvec<T>(I, 0);
+  T* P = kvec<T>(I, 2);
+  const T* V = kvec<T>(I, 3);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = 2 * r + e;
+    T p;
+    if (ks.j == 0) {
+      p = w[i];
+      R[i] = p;
+      kvec<T>(I, 1)[i] = p;
+    } else {
+      p = (T)((double)R[i] + ks.beta * ((double)P[i] - ks.omega * (double)V[i]));
+    }
+    P[i] = p;
+    w[i] = p;
+  }
+}
+
+// p^ = z, v = J p^ for the rows of one chunk, partial <r0, v>.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_v(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  double d = 0.0;
+  if (r < I.nu) {
+    const T* J = (const T*)I.jval;
+    const T* z = (const T*)I.kz;
+    T* Ph = kvec<T>(I, 4);
+    Ph[2 * r] = z[2 * r];
+    Ph[2 * r + 1] = z[2 * r + 1];
+    double v0 = 0.0, v1 = 0.0;
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const Blk<T> B = ld_blk(J, q);
+      const int c = I.kcol[q];
+      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
+      v0 += (double)B.a * a + (double)B.b * b;
+      v1 += (double)B.c * a + (double)B.d * b;
+    }
+    T* V = kvec<T>(I, 3);
+    V[2 * r] = (T)v0;
+    V[2 * r + 1] = (T)v1;
+    const T* R0 = kvec<T>(I, 1);
+    d = (double)R0[2 * r] * (double)(T)v0 + (double)R0[2 * r + 1] * (double)(T)v1;
+  }
+  block_sums(
+      1, [&](int) { return d; }, red, kpart(I, 0, blockIdx.x));
+}
+
+// alpha = <r0, r> / <r0, v>; s = r - alpha v into r and w; partial ||s||^2.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  __shared__ double alpha_s;
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
+  if (threadIdx.x == 0) {
+    alpha_s = I.ks->rho / chunk_sum(I, 0, 0);
+    if (blockIdx.x == 0) I.ks->alpha = alpha_s;
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  if (r < I.nu) {
+    T* R = kvec<T>(I, 0);
+    const T* V = kvec<T>(I, 3);
+    T* w = (T*)I.kw;
+    const T a = (T)((double)R[2 * r] - alpha * (double)V[2 * r]);
+    const T b = (T)((double)R[2 * r + 1] - alpha * (double)V[2 * r + 1]);
+    R[2 * r] = a;
+    R[2 * r + 1] = b;
+    w[2 * r] = a;
+    w[2 * r + 1] = b;
+    s0 = (double)a;
+    s1 = (double)b;
+  }
+  block_sums(
+      1, [&](int) { return s0 * s0 + s1 * s1; }, red, kpart(I, 1, blockIdx.x));
+}
+
+// Per instance: the first half of the iteration meets the tolerance or not.
+__global__ __launch_bounds__(64) void k_bcg_half(const Inst* const* insts, KOpts o) {
+  const Inst& I = *insts[blockIdx.x];
+  if (!kstate_is(I, KS_BP)) return;
+  KState& ks = *I.ks;
+  double sv = 0.0, ss = 0.0;
+  for (int c = threadIdx.x; c < I.kchunks; c += 64) {
+    sv += fabs(kpart(I, 0, c)[0]);
+    ss += kpart(I, 1, c)[0];
+  }
+  sv = wave_sum(sv);
+  ss = wave_sum(ss);
+  if (threadIdx.x != 0) return;
+  ks.total += 1;
+  I.red->linear_iters += 1;
+  if (!(sv > 0.0) || !isfinite(ks.alpha)) {
+    bcg_stop(I, o);
+    return;
+  }
+  const double srel = sqrt(ss) / ks.bnorm;
+  if (srel <= ks.eta) {
+    ks.rel = srel;
+    ks.met = 1;
+    ks.state = KS_BH;
+  } else {
+    ks.state = KS_BS;
+  }
+}
+
+// s^ = z, t = J s^ for the rows of one chunk, partial <t, s> and <t, t>.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  const Inst& I = *insts[blockIdx.y];
+  if (!kstate_is(I, KS_BS) || (int)blockIdx.x >= I.kchunks) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  double ts = 0.0, tt = 0.0;
+  if (r < I.nu) {
+    const T* J = (const T*)I.jval;
+    const T* z = (const T*)I.kz;
+    T* Sh = kvec<T>(I, 5);
+    Sh[2 * r] = z[2 * r];
+    Sh[2 * r + 1] = z[2 * r + 1];
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const Blk<T> B = ld_blk(J, q);
+      const int c = I.kcol[q];
+      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
+      t0 += (double)B.a * a + (double)B.b * b;
+      t1 += (double)B.c * a + (double)B.d * b;
+    }
+    T* Tv = kvec<T>(I, 6);
+    Tv[2 * r] = (T)t0;
+    Tv[2 * r + 1] = (T)t1;
+    t0 = (double)(T)t0;
+    t1 = (double)(T)t1;
+    const T* S = kvec<T>(I, 0);
+    ts = t0 * (double)S[2 * r] + t1 * (double)S[2 * r + 1];
+    tt = t0 * t0 + t1 * t1;
+  }
+  block_sums(
+      2, [&](int e) { return e == 0 ? ts : tt; }, red, kpart(I, 0, blockIdx.x));
+}
+
+// KS_BS: omega = <t, s> / <t, t>, x += alpha p^ + omega s^, r = s - omega t,
+// partial <r0, r> and ||r||^2 (nothing when <t, t> = 0).  KS_BH:
+// x += alpha p^.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
+  __shared__ double red[KMAX + 1][KCH / 64];
+  __shared__ double omega_s;
+  __shared__ bool skip_s;
+  const Inst& I = *insts[blockIdx.y];
+  const bool half = kstate_is(I, KS_BH);
+  if ((!half && !kstate_is(I, KS_BS)) || (int)blockIdx.x >= I.kchunks) return;
+  const KState& ks = *I.ks;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  T* x = (T*)I.kx;
+  const T* Ph = kvec<T>(I, 4);
+  if (half) {
+    if (r < I.nu) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) x[2 * r + e] = (T)((double)x[2 * r + e] + ks.alpha * (double)Ph[2 * r + e]);
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    const double tt = chunk_sum(I, 0, 1);
+    skip_s = !(tt > 0.0);
+    omega_s = skip_s ? 0.0 : chunk_sum(I, 0, 0) / tt;
+    if (blockIdx.x == 0) I.ks->omega = omega_s;
+  }
+  __syncthreads();
+  if (skip_s) return;  // <t, t> = 0: the solve ends as it stands
+  const double omega = omega_s;
+  double d = 0.0, q = 0.0;
+  if (r < I.nu) {
+    const T* Sh = kvec<T>(I, 5);
+    const T* Tv = kvec<T>(I, 6);
+    const T* R0 = kvec<T>(I, 1);
+    T* R = kvec<T>(I, 0);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = 2 * r + e;
+      x[i] = (T)((double)x[i] + ks.alpha * (double)Ph[i] + omega * (double)Sh[i]);
+      const T rn = (T)((double)R[i] - omega * (double)Tv[i]);
+      R[i] = rn;
+      d += (double)R0[i] * (double)rn;
+      q += (double)rn * (double)rn;
+    }
+  }
+  block_sums(
+      2, [&](int e) { return e == 0 ? d : q; }, red, kpart(I, 1, blockIdx.x));
+}
+
+// Per instance, end of the iteration: converged, stopped, or beta for the
+// next one.
+__global__ __launch_bounds__(64) void k_bcg_fin(const Inst* const* insts, KOpts o) {
+  const Inst& I = *insts[blockIdx.x];
+  const bool half = kstate_is(I, KS_BH);
+  if (!half && !kstate_is(I, KS_BS)) return;
+  KState& ks = *I.ks;
+  double tt = 0.0, rho = 0.0, rr = 0.0;
+  for (int c = threadIdx.x; c < I.kchunks; c += 64) {
+    tt += kpart(I, 0, c)[1];
+    rho += kpart(I, 1, c)[0];
+    rr += kpart(I, 1, c)[1];
+  }
+  tt = wave_sum(tt);
+  rho = wave_sum(rho);
+  rr = wave_sum(rr);
+  if (threadIdx.x != 0) return;
+  if (half) {
+    ks.state = KS_FINISH;
+    return;
+  }
+  if (!(tt > 0.0)) {
+    bcg_stop(I, o);
+    return;
+  }
+  ks.rel = sqrt(rr) / ks.bnorm;
+  if (ks.rel <= ks.eta) {
+    ks.met = 1;
+    ks.state = KS_FINISH;
+    return;
+  }
+  ks.j += 1;
+  const int max_it = max(1, (1 + o.max_restarts) * o.m / 2);
+  if (ks.omega == 0.0 || rho == 0.0 || ks.j >= max_it || !isfinite(ks.rel)) {
+    bcg_stop(I, o);
+    return;
+  }
+  ks.beta = (rho / ks.rho) * (ks.alpha / ks.omega);
+  ks.rho = rho;
+  ks.state = KS_BP;
+}
+
 // Per instance: a written result retires the solve (KS_FINISH -> KS_DONE).
 __global__ void k_kretire(const Inst* const* insts, int nslots) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
@@ -981,6 +1315,29 @@ void launch_kfinish(hipStream_t st, const Inst* const* insts, int nslots, int ma
   k_kfinish<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
   k_kretire<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots);
 }
+template <typename T>
+void launch_bcg_begin(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  k_kbegin<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
+  k_bcg_begin_fin<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
+}
+template <typename T>
+void launch_bcg_dir(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks) {
+  k_bcg_dir<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
+}
+template <typename T>
+void launch_bcg_half(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  const dim3 g = chunk_grid(max_chunks, nslots);
+  k_bcg_v<T><<<g, KCH, 0, st>>>(insts);
+  k_bcg_s<T><<<g, KCH, 0, st>>>(insts);
+  k_bcg_half<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
+}
+template <typename T>
+void launch_bcg_end(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+  const dim3 g = chunk_grid(max_chunks, nslots);
+  k_bcg_t<T><<<g, KCH, 0, st>>>(insts);
+  k_bcg_x<T><<<g, KCH, 0, st>>>(insts);
+  k_bcg_fin<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
+}
 void launch_kgather(hipStream_t st, const Inst* const* insts, int nslots, int* out) {
   k_kgather<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, out);
 }
@@ -998,7 +1355,11 @@ int krylov_max_restart() { return KMAX; }
   template void launch_kbegin<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
   template void launch_kycomb<T>(hipStream_t, const Inst* const*, int, int);                \
   template void launch_kcycle_end<T>(hipStream_t, const Inst* const*, int, int, KOpts);     \
-  template void launch_kfinish<T>(hipStream_t, const Inst* const*, int, int);
+  template void launch_kfinish<T>(hipStream_t, const Inst* const*, int, int);                  \
+  template void launch_bcg_begin<T>(hipStream_t, const Inst* const*, int, int, KOpts);        \
+  template void launch_bcg_dir<T>(hipStream_t, const Inst* const*, int, int);                 \
+  template void launch_bcg_half<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
+  template void launch_bcg_end<T>(hipStream_t, const Inst* const*, int, int, KOpts);
 
 PF_KINST(double)
 PF_KINST(float)

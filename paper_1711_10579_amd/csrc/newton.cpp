@@ -311,7 +311,7 @@ void lu_solve(Batch* b) {
 }  // namespace
 
 pf_status check_opts(const pf_options* opt) {
-  if (opt->solver != PF_SOLVER_LU && opt->solver != PF_SOLVER_GMRES) {
+  if (opt->solver != PF_SOLVER_LU && opt->solver != PF_SOLVER_GMRES && opt->solver != PF_SOLVER_BICGSTAB) {
     set_error("pf_solve: unknown solver");
     return PF_E_INVALID;
   }
@@ -323,12 +323,13 @@ pf_status check_opts(const pf_options* opt) {
     set_error("pf_solve: tol must be > 0 and max_iter >= 0");
     return PF_E_INVALID;
   }
-  if (opt->solver == PF_SOLVER_GMRES) {
+  if (opt->solver != PF_SOLVER_LU) {
     if (opt->gmres_m < 1 || opt->gmres_m > pfd::krylov_max_restart() || opt->gmres_max_restarts < 0 ||
         !(opt->eta_max > 0 && opt->eta_max < 1) ||
-        (opt->precond != PF_PRECOND_ILU0 && opt->precond != PF_PRECOND_BJACOBI)) {
-      set_error("pf_solve: GMRES needs 1 <= gmres_m <= 128, gmres_max_restarts >= 0, 0 < eta_max < 1 and a known "
-                "preconditioner");
+        (opt->precond != PF_PRECOND_ILU0 && opt->precond != PF_PRECOND_BJACOBI) ||
+        (opt->nk_fallback != 0 && opt->nk_fallback != 1)) {
+      set_error("pf_solve: Newton-Krylov needs 1 <= gmres_m <= 128, gmres_max_restarts >= 0, 0 < eta_max < 1, a "
+                "known preconditioner and nk_fallback 0 or 1");
       return PF_E_INVALID;
     }
   }
@@ -348,7 +349,7 @@ static pfd::DevOpts dev_opts(const pf_options* opt) {
 pf_status start_batch(Batch* b, const pf_options* opt) {
   pf_status st = check_opts(opt);
   if (st != PF_OK) return st;
-  if (opt->solver == PF_SOLVER_GMRES) {
+  if (opt->solver != PF_SOLVER_LU) {
     for (Case* c : b->cases)
       if (!ensure_krylov(c, opt->gmres_m)) return PF_E_NOMEM;
     if (!b->kbuilt && !b->build_krylov()) {
@@ -445,7 +446,7 @@ static bool graph_step(Batch* b, const pf_options* opt) {
 }
 
 pf_status step_batch(Batch* b, const pf_options* opt) {
-  if (opt->solver == PF_SOLVER_GMRES) {
+  if (opt->solver != PF_SOLVER_LU) {
     pf_status st = nk_step(b, opt);
     if (st != PF_OK) return st;
     {
@@ -502,7 +503,7 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   // result; the loop below then reads and continues as long as any instance
   // is active.
   int queued = 0;
-  if (opt->solver != PF_SOLVER_GMRES)
+  if (opt->solver == PF_SOLVER_LU)
     for (; st == PF_OK && queued < std::min(b->lu_steps, opt->max_iter); ++queued) st = step_batch(b, opt);
   std::vector<pfd::Red> h;
   for (int guard = queued; st == PF_OK && guard <= opt->max_iter + 1; ++guard) {
@@ -521,7 +522,7 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   (void)hipEventDestroy(e1);
   ctx->prof_flush();
   if (st != PF_OK) return st;
-  if (opt->solver != PF_SOLVER_GMRES) {
+  if (opt->solver == PF_SOLVER_LU) {
     int most = 0;
     for (const auto& r : h) most = std::max(most, r.it);
     b->lu_steps = most;
@@ -533,6 +534,41 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
     results[i].mismatch_inf = h[i].last_norm;
     results[i].max_step = h[i].last_step;
     results[i].device_ms = ms;
+  }
+  // Newton-Krylov with fallback: the cases whose Krylov step failed go on
+  // with LU from the voltage they have reached (a batch of their own)
+  if (opt->solver != PF_SOLVER_LU && opt->nk_fallback) {
+    std::vector<Case*> failed;
+    std::vector<int> where;
+    for (int i = 0; i < B; ++i)
+      if (results[i].status == PF_LINEAR_FAIL) {
+        failed.push_back(b->cases[i]);
+        where.push_back(i);
+      }
+    if (!failed.empty()) {
+      Batch fb;
+      if (!fb.build(ctx, failed)) {
+        set_error("pf_solve: batch set-up for the LU fallback failed");
+        return PF_E_NOMEM;
+      }
+      pf_options lo = *opt;
+      lo.solver = PF_SOLVER_LU;
+      lo.flat_start = 0;
+      lo.nk_fallback = 0;
+      std::vector<pf_result> fr(failed.size());
+      st = run_batch(&fb, &lo, fr.data());
+      if (st != PF_OK) return st;
+      for (size_t k = 0; k < failed.size(); ++k) {
+        pf_result& r = results[where[k]];
+        const int its = r.iters, lin = r.linear_iters;
+        const double dm = r.device_ms;
+        r = fr[k];
+        r.iters += its;
+        r.linear_iters = lin;
+        r.device_ms += dm;
+        r.lu_fallback = 1;
+      }
+    }
   }
   return PF_OK;
 }

@@ -264,9 +264,13 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
     else
       pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second);
   }
+  const bool bcg = opt->solver == PF_SOLVER_BICGSTAB;
   {
     Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-    pfd::launch_kbegin<T>(s, I, ns, mc, ko);
+    if (bcg)
+      pfd::launch_bcg_begin<T>(s, I, ns, mc, ko);
+    else
+      pfd::launch_kbegin<T>(s, I, ns, mc, ko);
     pfd::launch_kfinish<T>(s, I, ns, mc);
   }
   auto apply = [&](int mode) {
@@ -296,6 +300,30 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       return PF_E_DEVICE;
     }
     std::memcpy(st.data(), b->h_kstate, sizeof(int) * ns);
+    if (bcg) {
+      bool any = false;
+      for (int v : st) any |= v == pfd::KS_BP || v == pfd::KS_BS || v == pfd::KS_BH;
+      if (!any) break;
+      // a run of BiCGStab iterations between two reads of the states (each
+      // kernel acts only on the instances in the state it serves)
+      for (int i = 0; i < kStepsPerRead; ++i) {
+        {
+          Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+          pfd::launch_bcg_dir<T>(s, I, ns, mc);
+        }
+        apply(2);
+        {
+          Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+          pfd::launch_bcg_half<T>(s, I, ns, mc, ko);
+        }
+        apply(3);
+        Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+        pfd::launch_bcg_end<T>(s, I, ns, mc, ko);
+      }
+      Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
+      pfd::launch_kfinish<T>(s, I, ns, mc);
+      continue;
+    }
     bool iter = false, cyc = false;
     for (int v : st) {
       iter |= v == pfd::KS_ITER;

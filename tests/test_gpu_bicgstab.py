@@ -1,0 +1,203 @@
+"""GPU parity of Newton-Krylov with BiCGStab, the Krylov method the paper
+tested (Sec. III-B), and of the fallback from a failed Krylov step to LU
+(Sec. III-A), against the CPU oracle through the C ABI.
+
+The root does not depend on the inner solver: the GPU's voltages must be
+within 1e-7 pu / rad of the oracle's Newton root and the oracle's FP64
+mismatch at them at most 1e-8.  The first Newton step, an inexact solve,
+meets the inexact-Newton condition ||F - J dx|| <= eta ||F|| with F and J
+evaluated by the oracle (the library's Krylov order and preconditioner are
+its own, so the step itself is not the oracle's).  Batched solves equal the
+solves of each instance alone bit for bit.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import pfgen
+from oracle import cim, polar
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+VTOL = 1e-7
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1711_10579_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.pf_ctx_create(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _is_polar(case):
+    return hasattr(case, "bus_type")
+
+
+def _check(case, r, V):
+    assert r.status == 0, (case.name, r.as_dict())
+    assert r.mismatch_inf <= TOL
+    mod = polar if _is_polar(case) else cim
+    assert mod.mismatch_at(case, V) <= TOL
+    ref = mod.newton(case)
+    assert np.max(np.abs(np.abs(V) - ref.vm)) <= VTOL
+    assert np.max(np.abs(np.angle(V * np.conj(ref.V)))) <= VTOL
+
+
+CASES = [
+    ("grid2", lambda: pfgen.make_polar_grid(2, 0, 0, 1)),
+    ("grid3pv", lambda: pfgen.make_polar_grid(3, 1, 1, 1003, balanced=False)),
+    ("grid30", lambda: pfgen.config_case(0)),
+    ("grid257", lambda: pfgen.make_polar_grid(257, 77, 25, 1257, balanced=True)),
+    ("grid1000", lambda: pfgen.make_polar_grid(1000, 300, 100, 2000, balanced=True)),
+    ("grid3001", lambda: pfgen.make_polar_grid(3001, 900, 300, 4001, balanced=True)),
+    ("feeder2", lambda: pfgen.make_feeder(2, 5)),
+    ("feeder60", lambda: pfgen.make_feeder(60, 2)),
+    ("feeder400", lambda: pfgen.make_feeder(400, 8)),
+]
+
+
+@pytest.mark.parametrize("name,maker", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precond", [0, 1], ids=["ilu0", "bjacobi"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_bicgstab_parity(B, ctx, name, maker, precond, precision):
+    case = maker()
+    _say(f"bicgstab {name} precond={precond} precision={precision}")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=B.PF_SOLVER_BICGSTAB, precond=precond, precision=precision, max_iter=40,
+                   gmres_max_restarts=40)
+    _check(case, r, B.pf_get_voltage(h))
+    h.close()
+
+
+@pytest.mark.parametrize("name,maker", [CASES[4], CASES[5]], ids=["grid1000", "grid3001"])
+@pytest.mark.parametrize("precond", [0, 1], ids=["ilu0", "bjacobi"])
+@pytest.mark.parametrize("solver", [1, 2], ids=["gmres", "bicgstab"])
+def test_krylov_first_step_meets_its_forcing_term(B, ctx, name, maker, precond, solver):
+    # whatever order and preconditioner the inner solve runs in, the first
+    # Newton step dx must satisfy the inexact-Newton condition
+    # ||F - J dx||_2 <= eta ||F||_2 with eta = min(eta_max, ||F||_inf), F and J
+    # taken by the oracle at the flat start and dx read off the GPU's voltages
+    case = maker()
+    _say(f"first step {name} precond={precond} solver={solver}")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=solver, precond=precond, max_iter=1)
+    V = B.pf_get_voltage(h)
+    assert r.iters == 1 and r.linear_iters >= 1, r.as_dict()
+    pvpq, pq = polar.index_sets(case)
+    vm0, va0 = polar.flat_start(case)
+    F = polar.mismatch(case, vm0, va0)
+    J = polar.jacobian(case, vm0, va0)
+    dx = np.concatenate([(np.angle(V) - va0)[pvpq], (np.abs(V) - vm0)[pq]])
+    eta = min(0.1, float(np.max(np.abs(F))))
+    rel = float(np.linalg.norm(F - J @ dx) / np.linalg.norm(F))
+    _say(f"  {r.linear_iters} inner iterations, relative residual {rel:.3e} (eta {eta:.3e})")
+    assert 0.0 < rel <= eta * (1 + 1e-6)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_bicgstab_10k_bus_grid(B, ctx, precision):
+    case = pfgen.config_case(1)
+    _say(f"bicgstab 10k precision={precision}")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=B.PF_SOLVER_BICGSTAB, precision=precision, max_iter=40)
+    V = B.pf_get_voltage(h)
+    _say(f"  iters={r.iters} linear={r.linear_iters} mismatch={r.mismatch_inf:.2e}")
+    _check(case, r, V)
+    h.close()
+
+
+def test_bicgstab_feeder_2000_buses(B, ctx):
+    case = pfgen.config_case(2)
+    _say("bicgstab feeder 2000")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=B.PF_SOLVER_BICGSTAB)
+    _check(case, r, B.pf_get_voltage(h))
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_bicgstab_batch_bit_identical_to_alone(B, ctx, precision):
+    rng = np.random.default_rng(9)
+    cases = [pfgen.config_case(0), pfgen.make_feeder(120, 7)]
+    for i in range(6):
+        n = int(np.exp(rng.uniform(np.log(100), np.log(2500))))
+        base = pfgen.make_polar_grid(n, int(0.3 * n), max(1, n // 10), 900 + i, balanced=True)
+        cases.append(pfgen.perturb_loads(base, 90 + i))
+    _say(f"bicgstab batch precision={precision}")
+    hs = [B.pf_create_from(ctx, c) for c in cases]
+    opts = dict(solver=B.PF_SOLVER_BICGSTAB, precision=precision, max_iter=40, gmres_max_restarts=40)
+    alone = []
+    for h in hs:
+        r = B.pf_solve(h, **opts)
+        alone.append((r, B.pf_get_voltage(h)))
+    res = B.pf_solve_batch(ctx, hs, **opts)
+    for c, h, (ra, va), rb in zip(cases, hs, alone, res):
+        vb = B.pf_get_voltage(h)
+        assert rb.status == ra.status and rb.iters == ra.iters, c.name
+        assert rb.linear_iters == ra.linear_iters, c.name
+        assert np.array_equal(va, vb), c.name
+        _check(c, rb, vb)
+    for h in hs:
+        h.close()
+
+
+STARVED = dict(precond=1, gmres_m=2, gmres_max_restarts=0, eta_max=1e-3)
+
+
+@pytest.mark.parametrize("solver", [1, 2], ids=["gmres", "bicgstab"])
+def test_krylov_failure_and_lu_fallback(B, ctx, solver):
+    # a starved inner solve cannot reach a forcing term of 1e-3 on the first
+    # step: without the fallback the iteration ends with a linear failure;
+    # with it, LU takes over from the same voltage and reaches the oracle's
+    # root in the direct iteration's number of steps
+    case = pfgen.make_polar_grid(1000, 300, 100, 2000, balanced=True)
+    _say(f"krylov failure solver={solver}")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=solver, **STARVED)
+    assert r.status == B.PF_LINEAR_FAIL and r.iters == 0 and r.lu_fallback == 0, r.as_dict()
+    r = B.pf_solve(h, solver=solver, nk_fallback=1, **STARVED)
+    V = B.pf_get_voltage(h)
+    assert r.status == 0 and r.lu_fallback == 1, r.as_dict()
+    ref = polar.newton(case, linear=["gmres", "bicgstab"][solver - 1], fallback=True, m=2, max_restarts=0,
+                       eta_max=1e-3, precond="bjacobi")
+    assert ref.lu_fallback and r.iters == ref.iters
+    _check(case, r, V)
+    h.close()
+
+
+def test_lu_fallback_in_a_batch_leaves_the_others_alone(B, ctx):
+    # in a batch only the cases whose Krylov step fails go on with LU: the
+    # two-bus grid is solved exactly by one block-Jacobi-preconditioned half
+    # step and keeps its Krylov result, the 1,000-bus grid fails and falls
+    # back
+    small = pfgen.make_polar_grid(2, 0, 0, 1)
+    hard = pfgen.make_polar_grid(1000, 300, 100, 2000, balanced=True)
+    _say("fallback in a batch")
+    hs, hh = B.pf_create_from(ctx, small), B.pf_create_from(ctx, hard)
+    opts = dict(solver=B.PF_SOLVER_BICGSTAB, **STARVED)
+    r_alone = B.pf_solve(hs, **opts)
+    v_alone = B.pf_get_voltage(hs)
+    assert r_alone.status == 0, r_alone.as_dict()
+    res = B.pf_solve_batch(ctx, [hs, hh], nk_fallback=1, **opts)
+    assert res[0].status == 0 and res[0].lu_fallback == 0 and res[0].iters == r_alone.iters, res[0].as_dict()
+    assert np.array_equal(B.pf_get_voltage(hs), v_alone)
+    assert res[1].status == 0 and res[1].lu_fallback == 1, res[1].as_dict()
+    _check(hard, res[1], B.pf_get_voltage(hh))
+    hs.close()
+    hh.close()
