@@ -216,16 +216,16 @@ def bench_grid10k(args):
     B.pf_profile_enable(ctx, 0)
     mism = polar.mismatch_at(case, B.pf_get_voltage(h))
 
-    # Newton-Krylov on the same grid: GMRES(30) right-preconditioned with
-    # block ILU(0), forcing term min(0.1, ||F||_inf)
-    nk = None
-    if args.nk_steps > 0:
-        nopts = B.pf_default_options(solver=B.PF_SOLVER_GMRES, precision=int(mixed), max_iter=40)
+    # Newton-Krylov on the same grid, right-preconditioned with block ILU(0),
+    # forcing term min(0.1, ||F||_inf): GMRES(30), then BiCGStab (the method
+    # the paper tested)
+    def krylov_run(solver, label):
+        nopts = B.pf_default_options(solver=solver, precision=int(mixed), max_iter=40)
         for _ in range(max(1, args.warmup)):
             r = B.pf_solve(h, nopts)
             assert r.status == B.PF_CONVERGED, r.as_dict()
         if args.breakdown:
-            _breakdown(B, ctx, h, nopts, "nk")
+            _breakdown(B, ctx, h, nopts, label)
         torch.cuda.synchronize()
         nlat, nconv, nlin, nit = [], 0, [], []
         t0 = time.perf_counter()
@@ -238,11 +238,16 @@ def bench_grid10k(args):
             nit.append(r.iters)
         torch.cuda.synchronize()
         nel = time.perf_counter() - t0
-        nk = {"value": nconv / nel, "unit": "solves/s", "steps": args.nk_steps, "converged": nconv,
-              "latency_ms": {"p50": 1000 * _pct(nlat, 50), "p99": 1000 * _pct(nlat, 99)},
-              "solver": "gmres(30)+ilu0", "newton_iters": int(np.median(nit)),
-              "gmres_iters_per_solve": int(np.median(nlin)),
-              "final_mismatch_oracle": polar.mismatch_at(case, B.pf_get_voltage(h))}
+        return {"value": nconv / nel, "unit": "solves/s", "steps": args.nk_steps, "converged": nconv,
+                "latency_ms": {"p50": 1000 * _pct(nlat, 50), "p99": 1000 * _pct(nlat, 99)},
+                "solver": label + "+ilu0", "newton_iters": int(np.median(nit)),
+                "inner_iters_per_solve": int(np.median(nlin)),
+                "final_mismatch_oracle": polar.mismatch_at(case, B.pf_get_voltage(h))}
+
+    nk = nk_bcg = None
+    if args.nk_steps > 0:
+        nk = krylov_run(B.PF_SOLVER_GMRES, "gmres(30)")
+        nk_bcg = krylov_run(B.PF_SOLVER_BICGSTAB, "bicgstab")
 
     # batched form: the same grid under seeded load scenarios, one
     # pf_solve_batch per step
@@ -305,6 +310,7 @@ def bench_grid10k(args):
                                           "launches (includes the gaps between them)")),
         "batched": batched,
         "newton_krylov": nk,
+        "newton_krylov_bicgstab": nk_bcg,
         "autotune": tuned,
     }
     if not args.no_cpu_baseline:
