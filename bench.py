@@ -17,6 +17,10 @@ Other modes (each prints its own JSON line):
                             one pf_solve_batch per step
   --workload served         Poisson-arriving requests on a pool of single- and
                             three-phase grids through pf_submit/pf_poll
+  --workload replication    the paper's replication-scale cases (Sec. IV):
+                            the 48,000-bus grid (LU, GMRES, BiCGStab) and the
+                            0.9K-230K-bus feeders of Table 1 (LU), solve
+                            times beside the paper's CPU times (context)
   --calibrate-copy          a plain 256 MiB device copy (for scaling the
                             FETCH_SIZE / WRITE_SIZE counters)
 """
@@ -472,6 +476,91 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+# the paper's CPU times (Sec. IV; Cori node): Krylov solve of the 48,000-bus
+# grid on 1 and 32 threads, and Table 1's Solving / Other seconds of the
+# Newton-Raphson (SuperLU) three-phase solves by feeder size
+PAPER_NK_48K_S = {"threads_1": 1.2, "threads_32": 0.21}
+PAPER_TABLE1_S = {1: (0.319107, 0.047195), 2: (0.389616, 0.059578), 4: (0.799942, 0.092241),
+                  8: (1.12324, 0.218415), 16: (2.31822, 0.450141), 32: (4.9977, 0.954925),
+                  64: (11.8052, 2.047031), 128: (26.0988, 4.346155), 256: (55.291, 9.980889)}
+
+
+def bench_replication(args):
+    import numpy as np
+    import torch
+
+    import pfgen
+    from oracle import cim, polar
+    from paper_1711_10579_amd import binding as B
+
+    ctx = B.pf_ctx_create(0)
+    k = max(3, min(args.steps, 10))
+
+    def timed(h, opts, check):
+        for _ in range(max(1, args.warmup)):
+            r = B.pf_solve(h, opts)
+            assert r.status == B.PF_CONVERGED, r.as_dict()
+        torch.cuda.synchronize()
+        lat, conv = [], 0
+        for _ in range(k):
+            s0 = time.perf_counter()
+            r = B.pf_solve(h, opts)
+            lat.append(time.perf_counter() - s0)
+            conv += r.status == B.PF_CONVERGED
+        return {"solve_ms": {"p50": 1000 * _pct(lat, 50), "min": 1000 * min(lat)}, "converged": conv,
+                "solves": k, "newton_iters": r.iters, "inner_iters": r.linear_iters,
+                "lu_fallback": r.lu_fallback, "final_mismatch_oracle": check(B.pf_get_voltage(h))}
+
+    grid = pfgen.replication_polar()
+    t0 = time.perf_counter()
+    h = B.pf_create_from(ctx, grid)
+    setup = time.perf_counter() - t0
+    rows = {"buses": grid.n, "branches": grid.m, "setup_s": setup}
+    for name, solver in (("lu", B.PF_SOLVER_LU), ("gmres", B.PF_SOLVER_GMRES), ("bicgstab", B.PF_SOLVER_BICGSTAB)):
+        opts = B.pf_default_options(solver=solver, max_iter=40)
+        rows[name] = timed(h, opts, lambda V: polar.mismatch_at(grid, V))
+        print(f"replication 48k {name}: {rows[name]['solve_ms']['p50']:.2f} ms", file=sys.stderr, flush=True)
+    h.close()
+    rows["paper_nk_s"] = PAPER_NK_48K_S
+
+    feeders = []
+    for copies in pfgen.FEEDER_COPIES:
+        tol = pfgen.replication_feeder_tol(copies)
+        lu = B.pf_default_options(solver=B.PF_SOLVER_LU, max_iter=20, tol=tol)
+        fc = pfgen.replication_feeder(copies)
+        t0 = time.perf_counter()
+        h = B.pf_create_from(ctx, fc)
+        setup = time.perf_counter() - t0
+        row = {"copies": copies, "buses": fc.n_bus, "phase_nodes": fc.n, "tol": tol, "setup_s": setup}
+        row.update(timed(h, lu, lambda V, fc=fc: cim.mismatch_at(fc, V)))
+        row["paper_solving_s"], row["paper_other_s"] = PAPER_TABLE1_S[copies]
+        feeders.append(row)
+        print(f"replication feeder {fc.n_bus}: {row['solve_ms']['p50']:.2f} ms", file=sys.stderr, flush=True)
+        h.close()
+
+    out = {"mode": "replication",
+           "metric": "solve time of the replication-scale cases (48,000-bus grid, Newton-Krylov BiCGStab + ILU(0))",
+           "value": rows["bicgstab"]["solve_ms"]["p50"], "unit": "ms", "n_gpus": 1, "steps": k,
+           "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "replicated 30-bus blocks (48,000 buses) and replicated 906-bus feeders "
+                                  "(1-256 copies), flat start to 1e-8 pu (1e-7 for 256 copies, whose FP64 rounding "
+                                  "floor at the first bus is 2.2e-8), one solve at a time"},
+           "grid48k": rows, "feeders": feeders,
+           "note": "paper times are CPU seconds on a Cori node (context, another machine)"}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r = polar.newton(grid, max_iter=20)
+            el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1000 * el, "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"one oracle Newton-Raphson solve (sparse LU) of the 48,000-bus grid, "
+                                         f"{r.iters} iterations"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,7 +578,8 @@ def main():
                     help="solves of the Newton-Krylov (GMRES + ILU(0)) leg on the same grid")
     ap.add_argument("--batch", type=int, default=16,
                     help="scenarios of the batched form (seeded +-20%% load perturbations)")
-    ap.add_argument("--workload", choices=["grid10k", "scenarios512", "served"], default="grid10k")
+    ap.add_argument("--workload", choices=["grid10k", "scenarios512", "served", "replication"],
+                    default="grid10k")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--oracle-sample", type=int, default=8)
     ap.add_argument("--requests", type=int, default=200)
@@ -514,6 +604,8 @@ def main():
     elif args.workload == "scenarios512":
         args.precision = args.precision or "mixed"
         bench_scenarios512(args)
+    elif args.workload == "replication":
+        bench_replication(args)
     else:
         args.precision = args.precision or "mixed"
         bench_served(args)

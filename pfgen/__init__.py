@@ -21,6 +21,12 @@ from .grids import (  # noqa: F401
     perturb_loads,
     c3_scenarios,
     c4_pool,
+    replicate_polar,
+    replicate_feeder,
+    replication_polar,
+    replication_feeder,
+    FEEDER_COPIES,
+    replication_feeder_tol,
     PQ,
     PV,
     SLACK,

@@ -30,6 +30,11 @@ replicas of Sec. IV):
   * loads: per bus, ZIP fractions ~ Dirichlet(1, 1, 1); per present phase
     P = s * U[0.5, 1.5] kW * U[0.7, 1.3] (the +-30 % imbalance), pf 0.9.
 
+Replication-scale cases (Sec. IV's construction, at its sizes): copies of a
+30-bus block joined by random links repeating base branches (48,000 buses),
+and copies of a 906-bus feeder behind one substation branch (0.9K to 230K
+buses); see ``replicate_polar`` and ``replicate_feeder``.
+
 Batched scenarios: n ~ log-uniform[100, 5000], each with its own topology
 drawn as for the 10,000-bus grid (0.3 n chords, 10 % PV, balanced), loads
 perturbed per bus by a factor U[0.8, 1.2] applied to P and Q together.
@@ -434,3 +439,201 @@ def c4_pool(seed=None, n_polar=32, n_feeder=16):
         nb = int(rng.integers(500, 3001))
         pool.append(make_feeder(nb, s * 1000 + 100 + i, name=f"poolf{i}_{nb}"))
     return pool
+
+
+# ----------------------------------------------------------------------------
+# replication-scale cases (the construction of Sec. IV)
+
+
+REPLICA_BLOCK = 30        # buses of the single-phase base block
+REPLICA_LINKS = 2         # inter-block links added with every new block
+# dispatch of the PV bus that replaces a copy's slack, as a fraction of the
+# copy's load: the losses of the balanced base block at its solution (1.21 %
+# of its load for the base seed, chosen once), so that the one slack of the
+# whole grid does not have to cover every copy's losses through the links
+REPLICA_LOSS_FRAC = 0.012
+FEEDER_BASE_BUSES = 906   # buses of the three-phase base feeder
+# substation branch (source bus to the feeder's first bus) of the one-replica
+# feeder, per unit, no coupling; with R replicas it is divided by R so that
+# the drop across it stays what it is for one replica
+SUBSTATION_Z = 0.0004 + 0.0016j
+
+
+def replicate_polar(n_blocks, seed, links=REPLICA_LINKS, loss_frac=REPLICA_LOSS_FRAC, base=None,
+                    name=None):
+    """Single-phase grid of ``n_blocks`` copies of a 30-bus base block.
+
+    Sec. IV builds its large transmission cases by copying a 30-bus case many
+    times and joining the copies with random links; each link repeats an
+    existing branch of the base block with its ends in two different copies.
+    Recipe: the base block is ``make_polar_grid(30, 12, 5, seed,
+    balanced=True)`` (41 branches, 5 PV buses: the shape of IEEE-30, whose
+    data is not available); copy r numbers its buses 30 r .. 30 r + 29 and
+    repeats every base branch and set-point; every copy r >= 1 is joined to
+    earlier copies by ``links`` random links: a uniform base branch (i, j)
+    with its impedance and charging becomes the branch from bus i of a
+    uniform earlier copy q < r to bus j of copy r.  Bus 0 of copy 0 is the
+    slack; bus 0 of every other copy (its own slack in the base block) becomes
+    one more PV bus at the base slack's |V|, dispatched at ``loss_frac`` of
+    the copy's load.  The base block's PV dispatch equals its load (balanced
+    block) and that extra dispatch covers about its losses, so the one slack
+    and the links carry little net power.
+    """
+    rng = np.random.default_rng(seed)
+    if base is None:
+        base = make_polar_grid(REPLICA_BLOCK, 12, 5, seed, balanced=True)
+    nb, mb = base.n, base.m
+    R = int(n_blocks)
+    off = (np.arange(R, dtype=np.int64) * nb)[:, None]
+    f = (base.f[None, :] + off).ravel()
+    t = (base.t[None, :] + off).ravel()
+    r_ = np.tile(base.r, R)
+    x_ = np.tile(base.x, R)
+    b_ = np.tile(base.b, R)
+    if R > 1 and links > 0:
+        blk = np.repeat(np.arange(1, R), links)
+        q = np.floor(rng.random(blk.shape[0]) * blk).astype(np.int64)
+        e = rng.integers(0, mb, blk.shape[0])
+        f = np.concatenate([f, base.f[e] + q * nb])
+        t = np.concatenate([t, base.t[e] + blk * nb])
+        r_ = np.concatenate([r_, base.r[e]])
+        x_ = np.concatenate([x_, base.x[e]])
+        b_ = np.concatenate([b_, base.b[e]])
+    n = R * nb
+    f = f.astype(np.int32)
+    t = t.astype(np.int32)
+    ys = 1.0 / (r_ + 1j * x_)
+    sh = 0.5j * b_
+    rows = np.concatenate([f, t, f, t])
+    cols = np.concatenate([f, t, t, f])
+    vals = np.concatenate([ys + sh, ys + sh, -ys, -ys])
+    row_ptr, col, y = _stamp_csr(n, rows, cols, vals)
+
+    bus_type = np.tile(base.bus_type, R)
+    bus_type[nb::nb] = PV
+    p_sp = np.tile(base.p_sp, R)
+    q_sp = np.tile(base.q_sp, R)
+    block_load = -base.p_sp[base.bus_type == PQ].sum()
+    p_sp[nb::nb] = loss_frac * block_load
+    q_sp[nb::nb] = 0.0
+    v_mag = np.tile(base.v_mag, R)
+    v_ang = np.zeros(n)
+    return PolarCase(name=name or f"rep{n}", n=n, f=f, t=t, r=r_, x=x_, b=b_,
+                     row_ptr=row_ptr, col=col, y=y, bus_type=bus_type,
+                     p_sp=p_sp, q_sp=q_sp, v_mag=v_mag, v_ang=v_ang, seed=seed)
+
+
+def replicate_feeder(n_copies, seed, base=None, z_sub=SUBSTATION_Z, name=None):
+    """Three-phase feeder of ``n_copies`` copies of a 906-bus base feeder.
+
+    Sec. IV scales its distribution case by copying every bus below the first
+    bus (the one behind the substation transformer) and adjusting the
+    transformer so that the voltage drop stays acceptable.  Recipe: the base
+    is ``make_feeder(906, seed)`` (the size of the IEEE 906-bus LV feeder,
+    whose data is not available); its bus 0 becomes the first bus F (bus 1
+    here), fed from a new three-phase source bus (bus 0, the slack) through
+    the substation branch Z = ``z_sub`` / R times the 3x3 identity; the base
+    buses 1..905 with their branches, phases and ZIP loads are copied R times,
+    copy r numbering its buses 2 + 905 r ..; branches of the base leaving its
+    bus 0 leave F in every copy.
+    """
+    if base is None:
+        base = make_feeder(FEEDER_BASE_BUSES, seed)
+    R = int(n_copies)
+    nb0 = base.n_bus
+    per = nb0 - 1                       # copied buses per replica
+    n_bus = 2 + R * per
+
+    def bus_map(b0, r):
+        return np.where(b0 == 0, 1, 2 + r * per + (b0 - 1))
+
+    # branches: substation, then the copies
+    fs, ts, zs = [np.zeros(1, np.int64)], [np.ones(1, np.int64)], [np.eye(3)[None] * (z_sub / R)]
+    for r in range(R):
+        fs.append(bus_map(base.f.astype(np.int64), r))
+        ts.append(bus_map(base.t.astype(np.int64), r))
+        zs.append(base.zbr)
+    f = np.concatenate(fs).astype(np.int32)
+    t = np.concatenate(ts).astype(np.int32)
+    zbr = np.concatenate(zs).astype(np.complex128)
+
+    phases = np.ones((n_bus, 3), np.int8)
+    phases[2:] = np.tile(base.bus_phases[1:], (R, 1))
+
+    # phase-nodes: bus-major, phase-minor; base bus 0 owns base nodes 0..2
+    nn0 = base.n
+    assert (base.node_bus[:3] == 0).all() and (base.node_bus[3:] > 0).all()
+    perm = nn0 - 3
+    nn = 6 + R * perm
+    node_bus = np.empty(nn, np.int32)
+    node_phase = np.empty(nn, np.int32)
+    node_bus[:3], node_bus[3:6] = 0, 1
+    node_phase[:3] = node_phase[3:6] = np.arange(3)
+    rr = np.repeat(np.arange(R, dtype=np.int64), perm)
+    node_bus[6:] = 2 + rr * per + (np.tile(base.node_bus[3:], R) - 1)
+    node_phase[6:] = np.tile(base.node_phase[3:], R)
+
+    # admittance: every copy's entries of the base Ybus, with base nodes 0..2
+    # mapped onto F's nodes 3..5 (its diagonal block sums over the copies),
+    # then the substation branch
+    rp = base.row_ptr.astype(np.int64)
+    brow = np.repeat(np.arange(nn0, dtype=np.int64), np.diff(rp))
+    bcol = base.col.astype(np.int64)
+
+    def node_map(k, r):
+        return np.where(k < 3, k + 3, 6 + r * perm + (k - 3))
+
+    rows = [node_map(brow, r) for r in range(R)]
+    cols = [node_map(bcol, r) for r in range(R)]
+    vals = [np.tile(base.y, R)]
+    ysub = np.linalg.inv(np.eye(3) * (z_sub / R))
+    s_idx = np.repeat(np.arange(3), 3)
+    p_idx = np.tile(np.arange(3), 3)
+    yv = ysub[s_idx, p_idx]
+    rows += [s_idx, s_idx + 3, s_idx, s_idx + 3]
+    cols += [p_idx, p_idx + 3, p_idx + 3, p_idx]
+    vals += [yv, yv, -yv, -yv]
+    row_ptr, col, y = _stamp_csr(nn, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+    node_type = np.full(nn, PQ, np.int8)
+    node_type[:3] = SLACK
+    zip_ = np.zeros((nn, 6))
+    zip_[6:] = np.tile(base.zip[3:], (R, 1))
+    nominal = np.array([0.0, -2.0 * math.pi / 3.0, 2.0 * math.pi / 3.0])
+    return CimCase(name=name or f"repfeeder{n_bus}", n_bus=n_bus, n=nn,
+                   node_bus=node_bus, node_phase=node_phase, f=f, t=t, zbr=zbr,
+                   bus_phases=phases, row_ptr=row_ptr, col=col, y=y,
+                   node_type=node_type, zip=zip_, p_gen=np.zeros(nn),
+                   q_gen=np.zeros(nn), v_mag=np.ones(nn), v_ang=nominal[node_phase],
+                   seed=seed)
+
+
+REPLICATION_SEED_POLAR = BASE_SEED + 5
+REPLICATION_SEED_FEEDER = BASE_SEED + 6
+# the feeder sizes of Table 1 are 906 x 1, 2, 4, ..., 256 buses
+FEEDER_COPIES = tuple(1 << k for k in range(9))
+
+
+def replication_feeder_tol(n_copies):
+    """Stop tolerance of the replicated feeder with ``n_copies`` copies.
+
+    The first bus joins every copy's top branches (about 7 per copy, ~600 pu
+    each) and the substation branch, so its row of Ybus holds terms of ~1e6
+    pu that cancel to ~0; the FP64 rounding of that sum at the exact root is
+    4.7e-9 at 128 copies and 2.2e-8 at 256.  The 1e-8 pu test holds up to 128
+    copies; the 256-copy case stops at 1e-7 pu.
+    """
+    return 1e-8 if n_copies <= 128 else 1e-7
+
+
+def replication_polar(n_blocks=1600):
+    """The replicated single-phase workload: 1,600 copies of the 30-bus block
+    make the 48,000-bus grid of Sec. IV."""
+    return replicate_polar(n_blocks, REPLICATION_SEED_POLAR, name=f"rep{REPLICA_BLOCK * n_blocks}")
+
+
+def replication_feeder(n_copies):
+    """The replicated three-phase workload with ``n_copies`` copies of the
+    906-bus feeder (Table 1: 1, 2, 4, ..., 256 copies, 0.9K to 230K buses)."""
+    return replicate_feeder(n_copies, REPLICATION_SEED_FEEDER,
+                            name=f"repfeeder{2 + (FEEDER_BASE_BUSES - 1) * n_copies}")
