@@ -17,6 +17,7 @@ class OracleResult:
     mismatch_inf: float        # max-norm of the final mismatch
     linear_iters: list = dataclasses.field(default_factory=list)  # Krylov steps per Newton step
     lu_fallback: bool = False  # a Krylov step failed and direct solves finished the iteration
+    q_gen: np.ndarray = None   # three-phase: generator Q per phase-node (PV nodes solved for)
 
     @property
     def vm(self):

@@ -22,6 +22,7 @@ from .grids import (  # noqa: F401
     c3_scenarios,
     c4_pool,
     replicate_polar,
+    add_dg_and_delta,
     replicate_feeder,
     replication_polar,
     replication_feeder,

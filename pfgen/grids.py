@@ -114,13 +114,20 @@ class CimCase:
     row_ptr: np.ndarray
     col: np.ndarray
     y: np.ndarray
-    node_type: np.ndarray  # int8 [n]: SLACK for source phase-nodes, PQ else
+    node_type: np.ndarray  # int8 [n]: SLACK for source phase-nodes, PV for
+                           # voltage-controlled generation, PQ else
     zip: np.ndarray        # float64 [n,6] P_Z, P_I, P_P, Q_Z, Q_I, Q_P (pu at |V|=1)
-    p_gen: np.ndarray      # float64 [n]  (zero: no DG, Sec. II-B)
-    q_gen: np.ndarray      # float64 [n]
-    v_mag: np.ndarray      # float64 [n] source magnitude on source nodes
+    p_gen: np.ndarray      # float64 [n] generation (DG); zero without DG
+    q_gen: np.ndarray      # float64 [n] (PV nodes: starting value of Q)
+    v_mag: np.ndarray      # float64 [n] magnitude set-point of source and PV nodes
     v_ang: np.ndarray      # float64 [n] nominal phase angle of every node
     seed: int = 0
+    # delta-connected ZIP loads: node k draws from its phase to node
+    # delta_to[k] (another phase of the same bus; -1: none) the load
+    # zip_delta[k] (P_Z, P_I, P_P, Q_Z, Q_I, Q_P at the nominal line-to-line
+    # voltage sqrt(3) pu)
+    delta_to: np.ndarray = None    # int32 [n] or None
+    zip_delta: np.ndarray = None   # float64 [n,6] or None
 
     @property
     def nnz(self) -> int:
@@ -637,3 +644,65 @@ def replication_feeder(n_copies):
     906-bus feeder (Table 1: 1, 2, 4, ..., 256 copies, 0.9K to 230K buses)."""
     return replicate_feeder(n_copies, REPLICATION_SEED_FEEDER,
                             name=f"repfeeder{2 + (FEEDER_BASE_BUSES - 1) * n_copies}")
+
+
+# ----------------------------------------------------------------------------
+# distributed generation and delta-connected loads on a feeder
+
+
+def add_dg_and_delta(fc, seed, n_dg=3, dg_v=1.0, dg_scale=(1.0, 3.0), delta_frac=0.25,
+                     single_phase_dg=True, name=None):
+    """A copy of feeder ``fc`` with voltage-controlled generation (PV
+    phase-nodes) and delta-connected loads.
+
+    Recipe: ``n_dg`` uniform three-phase buses (not the source) get a
+    three-phase generator: every phase-node becomes PV at |V| = ``dg_v`` with
+    P_g = U[dg_scale] x the feeder's mean per-phase load P, Q starting at 0;
+    with ``single_phase_dg`` one phase-node of a one- or two-phase bus (when
+    there is one) gets a single-phase generator the same way.  A fraction
+    ``delta_frac`` of the buses with two or more phases (not the source) turn
+    their wye loads into delta loads with the same coefficients: phase a
+    draws towards b, b towards c, c towards a on a three-phase bus; on a
+    two-phase bus the first present phase draws towards the second (the second
+    keeps its wye load).
+    """
+    rng = np.random.default_rng(seed)
+    n = fc.n
+    node_type = fc.node_type.copy()
+    v_mag = fc.v_mag.copy()
+    p_gen = fc.p_gen.copy()
+    q_gen = np.zeros(n)
+    zip_ = fc.zip.copy()
+    delta_to = -np.ones(n, np.int32)
+    zip_delta = np.zeros((n, 6))
+    nodes_of = [np.flatnonzero(fc.node_bus == b) for b in range(fc.n_bus)]
+    nph = np.array([len(x) for x in nodes_of])
+    mean_p = float(np.mean(fc.zip[fc.node_bus > 0][:, :3].sum(axis=1)))
+    three = np.flatnonzero(nph == 3)
+    three = three[three > 0]
+    dg_buses = rng.choice(three, size=min(n_dg, three.shape[0]), replace=False) if three.size else []
+    for b in dg_buses:
+        for k in nodes_of[b]:
+            node_type[k] = PV
+            v_mag[k] = dg_v
+            p_gen[k] = rng.uniform(*dg_scale) * mean_p
+    if single_phase_dg:
+        part = np.flatnonzero((nph == 1) | (nph == 2))
+        if part.size:
+            k = nodes_of[int(rng.choice(part))][0]
+            node_type[k] = PV
+            v_mag[k] = dg_v
+            p_gen[k] = rng.uniform(*dg_scale) * mean_p
+    multi = np.flatnonzero(nph >= 2)
+    multi = multi[multi > 0]
+    pick = multi[rng.random(multi.shape[0]) < delta_frac]
+    for b in pick:
+        ks = nodes_of[b]
+        pairs = [(ks[0], ks[1]), (ks[1], ks[2]), (ks[2], ks[0])] if len(ks) == 3 else [(ks[0], ks[1])]
+        for k, t in pairs:
+            delta_to[k] = t
+            zip_delta[k] = zip_[k]
+            zip_[k] = 0.0
+    return dataclasses.replace(fc, name=name or f"{fc.name}+dg", node_type=node_type, v_mag=v_mag,
+                               p_gen=p_gen, q_gen=q_gen, zip=zip_, delta_to=delta_to,
+                               zip_delta=zip_delta)
