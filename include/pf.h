@@ -81,15 +81,28 @@ typedef enum { PF_PRECOND_ILU0 = 0, PF_PRECOND_BJACOBI = 1 } pf_precond;
  *            increasing within a row, diagonal present, pattern structurally
  *            symmetric (eq. 3)
  *   y        [2*nnz] Ybus values, interleaved re/im (eq. 2-3, 11)
- *   bus_type [n] pf_bus_type
+ *   bus_type [n] pf_bus_type.  CIM: PF_SLACK source phase-nodes, PF_PQ, and
+ *            PF_PV for voltage-controlled distributed generation on that
+ *            phase (the generation the paper leaves out, Sec. II-B): |V| held
+ *            at v_mag, P_g given, Q_g solved for
  *   p_sp, q_sp [n] polar: specified injection P_g - P_l, Q_g - Q_l (eq. 8-9,
- *            12-13); CIM: generation P_g, Q_g (zero without DG); may be NULL
+ *            12-13); CIM: generation P_g, Q_g (zero without DG; on PF_PV
+ *            nodes q_sp is the starting Q_g of a flat start); may be NULL
  *            for CIM (taken as zero)
  *   v_mag, v_ang [n] polar: |V| set-point of PV and slack buses and slack
- *            angle; CIM: source magnitude on PF_SLACK nodes and the nominal
- *            phase angle (0, -2pi/3, +2pi/3) of every node (flat start)
+ *            angle; CIM: magnitude of PF_SLACK and PF_PV nodes and the
+ *            nominal phase angle (0, -2pi/3, +2pi/3) of every node (flat
+ *            start)
  *   zip      CIM [6*n] per node P_Z, P_I, P_P, Q_Z, Q_I, Q_P at |V| = 1
- *            (eq. 14-15); polar: NULL (constant-power loads only)
+ *            (eq. 14-15, wye-connected); polar: NULL (constant-power loads)
+ *   delta_to, zip_delta  CIM, optional (both NULL: none): delta-connected
+ *            ZIP loads.  delta_to [n]: node k draws its delta load from its
+ *            phase into node delta_to[k] (-1: no load); zip_delta [6*n]: that
+ *            load's P_Z, P_I, P_P, Q_Z, Q_I, Q_P at the nominal line-to-line
+ *            voltage sqrt(3) pu, so that S = s_Z (|V_k - V_t|/sqrt3)^2 +
+ *            s_I |V_k - V_t|/sqrt3 + s_P.  The Ybus pattern must hold the
+ *            entry (k, delta_to[k]) (an explicit zero will do) and a node may
+ *            receive at most one delta load.
  */
 typedef struct {
   int32_t model;
@@ -104,6 +117,8 @@ typedef struct {
   const double* v_mag;
   const double* v_ang;
   const double* zip;
+  const int32_t* delta_to;
+  const double* zip_delta;
 } pf_case_desc;
 
 /* Solve options (pf_default_options fills the defaults shown).
@@ -216,8 +231,11 @@ pf_status pf_ctx_use_graphs(pf_ctx* ctx, int32_t on);
  * III-A analysis).  PF_E_INVALID if: n < 1 or nnz < n; CSR not sorted,
  * duplicated or out of range; a diagonal missing; pattern not structurally
  * symmetric; non-finite values; polar without exactly one PF_SLACK or with a
- * type outside {PQ, PV, SLACK}; CIM with a PF_PV node, without a PF_SLACK
- * node or without zip. */
+ * type outside {PQ, PV, SLACK}; CIM without a PF_SLACK node or without zip;
+ * a PF_PV or PF_SLACK magnitude that is not positive; delta loads on a polar
+ * case, only one of delta_to / zip_delta given, a delta_to outside
+ * [-1, n) or equal to its node, a node receiving two delta loads, or a
+ * delta load whose (k, delta_to[k]) entry is not in the Ybus pattern. */
 pf_status pf_create(pf_ctx* ctx, const pf_case_desc* desc, pf_case** out);
 /* The same under an explicit schedule (PF_E_INVALID if a field is out of
  * range).  pf_create uses the schedule pf_autotune stored in the context for

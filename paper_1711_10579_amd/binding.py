@@ -60,7 +60,8 @@ class pf_case_desc(C.Structure):
                 ("y", C.POINTER(C.c_double)), ("bus_type", C.POINTER(C.c_int8)),
                 ("p_sp", C.POINTER(C.c_double)), ("q_sp", C.POINTER(C.c_double)),
                 ("v_mag", C.POINTER(C.c_double)), ("v_ang", C.POINTER(C.c_double)),
-                ("zip", C.POINTER(C.c_double))]
+                ("zip", C.POINTER(C.c_double)), ("delta_to", C.POINTER(C.c_int32)),
+                ("zip_delta", C.POINTER(C.c_double))]
 
 
 class pf_options(C.Structure):
@@ -259,7 +260,7 @@ class Case:
             pass
 
 
-def _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip):
+def _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip, delta_to=None, zip_delta=None):
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col_idx, np.int32)
     yv = np.ascontiguousarray(np.asarray(y, np.complex128).view(np.float64))
@@ -269,14 +270,18 @@ def _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip):
     ps = None if p_sp is None else np.ascontiguousarray(p_sp, np.float64)
     qs = None if q_sp is None else np.ascontiguousarray(q_sp, np.float64)
     zp = None if zip is None else np.ascontiguousarray(np.asarray(zip, np.float64).reshape(-1))
+    dt = None if delta_to is None else np.ascontiguousarray(delta_to, np.int32)
+    zd = None if zip_delta is None else np.ascontiguousarray(np.asarray(zip_delta, np.float64).reshape(-1))
     n = bt.shape[0]
     d = pf_case_desc(model=model, n=n, nnz=ci.shape[0],
                      row_ptr=rp.ctypes.data_as(C.POINTER(C.c_int32)),
                      col_idx=ci.ctypes.data_as(C.POINTER(C.c_int32)),
                      y=_dptr(yv), bus_type=bt.ctypes.data_as(C.POINTER(C.c_int8)),
                      p_sp=_dptr(ps), q_sp=_dptr(qs), v_mag=_dptr(vm), v_ang=_dptr(va),
-                     zip=_dptr(zp))
-    keep = (rp, ci, yv, bt, vm, va, ps, qs, zp)
+                     zip=_dptr(zp),
+                     delta_to=None if dt is None else dt.ctypes.data_as(C.POINTER(C.c_int32)),
+                     zip_delta=_dptr(zd))
+    keep = (rp, ci, yv, bt, vm, va, ps, qs, zp, dt, zd)
     return d, n, keep
 
 
@@ -295,10 +300,11 @@ def pf_default_schedule(**kw):
 
 
 def pf_create(ctx, model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None, q_sp=None,
-              zip=None, schedule=None):
+              zip=None, schedule=None, delta_to=None, zip_delta=None):
     """Create a case from host arrays (Ybus CSR with complex values ``y``);
     ``schedule`` (a pf_schedule) selects pf_create_scheduled."""
-    d, n, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
+    d, n, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip, delta_to,
+                       zip_delta)
     if schedule is not None:
         h = _P()
         _check(_lib.pf_create_scheduled(ctx.handle, C.byref(d), C.byref(schedule), C.byref(h)),
@@ -317,16 +323,20 @@ def case_arrays(case):
         return dict(model=PF_MODEL_POLAR_1PH, row_ptr=case.row_ptr, col_idx=case.col, y=case.y,
                     bus_type=case.bus_type, v_mag=case.v_mag, v_ang=case.v_ang,
                     p_sp=case.p_sp, q_sp=case.q_sp, zip=None)
-    return dict(model=PF_MODEL_CIM_3PH, row_ptr=case.row_ptr, col_idx=case.col, y=case.y,
-                bus_type=case.node_type, v_mag=case.v_mag, v_ang=case.v_ang,
-                p_sp=case.p_gen, q_sp=case.q_gen, zip=case.zip)
+    out = dict(model=PF_MODEL_CIM_3PH, row_ptr=case.row_ptr, col_idx=case.col, y=case.y,
+               bus_type=case.node_type, v_mag=case.v_mag, v_ang=case.v_ang,
+               p_sp=case.p_gen, q_sp=case.q_gen, zip=case.zip)
+    if getattr(case, "delta_to", None) is not None:
+        out.update(delta_to=case.delta_to, zip_delta=case.zip_delta)
+    return out
 
 
 def pf_debug_schedule_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None,
-                            q_sp=None, zip=None, seed=0, schedule=None):
+                            q_sp=None, zip=None, seed=0, schedule=None, delta_to=None, zip_delta=None):
     """Host-only replay of the analysis schedule (include/pf_debug.h).
     Returns (relative residual, number of index checks)."""
-    d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
+    d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip, delta_to,
+                       zip_delta)
     res = C.c_double()
     chk = C.c_int64()
     sp_ = C.byref(schedule) if schedule is not None else None
@@ -337,10 +347,11 @@ def pf_debug_schedule_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, 
 
 
 def pf_debug_krylov_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp=None,
-                          q_sp=None, zip=None, seed=0):
+                          q_sp=None, zip=None, seed=0, delta_to=None, zip_delta=None):
     """Host-only check of the Krylov analysis (include/pf_debug.h).
     Returns (ILU(0) deviation on the pattern, relative residual, checks)."""
-    d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip)
+    d, _, keep = _desc(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_sp, q_sp, zip, delta_to,
+                       zip_delta)
     dev = C.c_double()
     res = C.c_double()
     chk = C.c_int64()

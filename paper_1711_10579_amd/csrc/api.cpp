@@ -205,9 +205,44 @@ pf_status validate_desc(const pf_case_desc* d) {
       return PF_E_INVALID;
     }
     if (t == PF_SLACK) ++nslack;
-    if (d->model == PF_MODEL_CIM_3PH && t == PF_PV) {
-      set_error("pf_create: the current-injection model has no PV nodes");
+    if (t != PF_PQ && !(d->v_mag[i] > 0.0)) {
+      set_error("pf_create: PV or slack magnitude not positive at node " + std::to_string(i));
       return PF_E_INVALID;
+    }
+  }
+  if ((d->delta_to == nullptr) != (d->zip_delta == nullptr)) {
+    set_error("pf_create: delta_to and zip_delta must be given together");
+    return PF_E_INVALID;
+  }
+  if (d->delta_to) {
+    if (d->model != PF_MODEL_CIM_3PH) {
+      set_error("pf_create: delta loads need the current-injection model");
+      return PF_E_INVALID;
+    }
+    if (!finite_all(d->zip_delta, 6LL * n)) {
+      set_error("pf_create: non-finite input value");
+      return PF_E_INVALID;
+    }
+    std::vector<char> into(n, 0);
+    for (int k = 0; k < n; ++k) {
+      const int t = d->delta_to[k];
+      if (t == -1) continue;
+      if (t < -1 || t >= n || t == k) {
+        set_error("pf_create: delta_to out of range or equal to its node at node " + std::to_string(k));
+        return PF_E_INVALID;
+      }
+      if (into[t]) {
+        set_error("pf_create: node " + std::to_string(t) + " receives two delta loads");
+        return PF_E_INVALID;
+      }
+      into[t] = 1;
+      const int* b = d->col_idx + d->row_ptr[k];
+      const int* e = d->col_idx + d->row_ptr[k + 1];
+      if (!std::binary_search(b, e, t)) {
+        set_error("pf_create: delta load " + std::to_string(k) + " -> " + std::to_string(t) +
+                  " has no Ybus pattern entry");
+        return PF_E_INVALID;
+      }
     }
   }
   if (d->model == PF_MODEL_POLAR_1PH && nslack != 1) {
@@ -468,6 +503,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
            2 * carve_size<int>(nupd) + carve_size<int>(ns);
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
   total += carve_size<int>(nu + 1) + 2 * carve_size<int>(an.nnzl) + carve_size<int>(ns);
+  total += carve_size<double>(n) + carve_size<int>(2LL * n) + carve_size<double>(6LL * n);
   total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1);
   c->bytes = total;
   c->base = (char*)ctx->dalloc(total);
@@ -488,6 +524,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   c->vmag = carve<double>(p, n);
   c->vang = carve<double>(p, n);
   c->zip = carve<double>(p, 6LL * n);
+  c->qg = carve<double>(p, n);
+  c->dlink = carve<int>(p, 2LL * n);
+  c->zipd = carve<double>(p, 6LL * n);
   c->pos = carve<int>(p, n);
   c->node = carve<int>(p, nu);
   c->vm = carve<double>(p, n);
@@ -543,6 +582,22 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   ok &= up(c->vmag, d->v_mag, sizeof(double) * n);
   ok &= up(c->vang, d->v_ang, sizeof(double) * n);
   if (d->zip) ok &= up(c->zip, d->zip, sizeof(double) * 6 * n);
+  ok &= up(c->qg, d->q_sp ? d->q_sp : zeros.data(), sizeof(double) * n);
+  c->has_delta = false;
+  if (d->delta_to) {
+    // per node: the node its delta load draws into, and the node whose
+    // delta load it receives (-1: none)
+    std::vector<int> link(2 * (size_t)n, -1);
+    for (int k = 0; k < n; ++k) {
+      const int t = d->delta_to[k];
+      if (t < 0) continue;
+      link[2 * k] = t;
+      link[2 * t + 1] = k;
+      c->has_delta = true;
+    }
+    ok &= up(c->dlink, link.data(), sizeof(int) * 2 * n);
+    ok &= up(c->zipd, d->zip_delta, sizeof(double) * 6 * n);
+  }
   ok &= up(c->pos, an.pos_of_node.data(), sizeof(int) * n);
   ok &= up(c->node, an.node_of_pos.data(), sizeof(int) * nu);
   ok &= up(c->colptr, an.colptr.data(), sizeof(int) * (ns + 1));
@@ -589,6 +644,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     hi.vmag = c->vmag;
     hi.vang = c->vang;
     hi.zip = c->zip;
+    hi.qg = c->qg;
+    hi.dlink = c->has_delta ? (const int2*)c->dlink : nullptr;
+    hi.zipd = c->zipd;
     hi.pos = c->pos;
     hi.node = c->node;
     hi.vm = c->vm;
@@ -627,7 +685,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
         m = t == PF_PQ ? 1.0 : d->v_mag[i];
         a = t == PF_SLACK ? d->v_ang[i] : 0.0;
       } else {
-        m = t == PF_SLACK ? d->v_mag[i] : 1.0;
+        m = t == PF_PQ ? 1.0 : d->v_mag[i];
         a = d->v_ang[i];
       }
       vm0[i] = m;

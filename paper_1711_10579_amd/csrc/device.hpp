@@ -50,6 +50,13 @@ struct Inst {
   const double* y;
   const int8_t* type;
   const double *psp, *qsp, *vmag, *vang, *zip;
+  // CIM: per node {node its delta load draws into, node whose delta load it
+  // receives} (-1: none; null without delta loads), the delta ZIP
+  // coefficients [6n], and the generator Q of PV nodes (their Newton state
+  // in place of |V|, which stays at the set-point)
+  const int2* dlink;
+  const double* zipd;
+  double* qg;
   const int *pos, *node;
   double *vm, *va, *v, *ibus, *F;
   void *x, *lu, *dinv, *tail, *dinvu;

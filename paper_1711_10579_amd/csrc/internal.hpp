@@ -97,6 +97,12 @@ struct Case {
   double* y = nullptr;
   int8_t* dtype = nullptr;
   double *psp = nullptr, *qsp = nullptr, *vmag = nullptr, *vang = nullptr, *zip = nullptr;
+  // CIM: generator Q of PV nodes (Newton state), per node the delta-load
+  // links (draws into, receives from; -1 none) and the delta ZIP coefficients
+  double* qg = nullptr;
+  int* dlink = nullptr;
+  double* zipd = nullptr;
+  bool has_delta = false;
   int *pos = nullptr, *node = nullptr;
   double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
   void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dinvu = nullptr;

@@ -56,9 +56,10 @@ __device__ inline bool inactive(const Inst& I) { return I.red->active == 0; }
 // Newton driver on the device
 
 // Start of a solve: flat start (polar: |V| = 1 on PQ buses, set-point
-// elsewhere, angle 0 but the slack's set-point; CIM: magnitude 1, source
-// set-point on source nodes, at the node's nominal phase angle) or the
-// stored voltage, and the rectangular voltage v.
+// elsewhere, angle 0 but the slack's set-point; CIM: magnitude 1, the
+// set-point on source and PV nodes, at the node's nominal phase angle, and a
+// PV node's generator Q at its given starting value) or the stored voltage,
+// and the rectangular voltage v.
 __global__ void k_init(const Inst* const* insts, int flat) {
   const Inst& I = *insts[blockIdx.y];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,11 +80,13 @@ __global__ void k_init(const Inst* const* insts, int flat) {
     I.v[2 * i] = m * c;
     I.v[2 * i + 1] = m * s;
   } else if (flat) {
-    m = I.type[i] == 3 ? I.vmag[i] : 1.0;
+    const int t = I.type[i];
+    m = t == 1 ? 1.0 : I.vmag[i];
     double s, c;
     sincos(I.vang[i], &s, &c);
     I.v[2 * i] = m * c;
     I.v[2 * i + 1] = m * s;
+    if (t == 2) I.qg[i] = I.qsp[i];
   }
 }
 
@@ -157,7 +160,21 @@ __global__ void k_gather_red(const Inst* const* insts, int nslots, Red* out) {
 // at the bus's LU position (2 rows per node); the |V| row of a PV bus is 0.
 // CIM: I_calc = sum_j Y_ij V_j (eq. 18); P_l, Q_l from the ZIP model (eq.
 // 14-15); P_sp = P_g - P_l (eq. 12-13); I_sp = conj((P_sp + jQ_sp)/V)
-// (eq. 17); dI = I_sp - I_calc (eq. 16); rows per node [Im dI, Re dI].
+// (eq. 17), a PV node's Q_g being its Newton state; minus the current of the
+// node's own delta load, plus that of the delta load it receives;
+// dI = I_sp - I_calc (eq. 16); rows per node [Im dI, Re dI].
+
+// Current conj(S(|Vd|)/Vd) a delta load of ZIP coefficients z (at the
+// nominal line-to-line voltage sqrt(3) pu) draws across Vd.
+__device__ inline double2 delta_current(const double* z, double2 vd) {
+  const double w = vd.x * vd.x + vd.y * vd.y;
+  const double m = sqrt(w);
+  const double r3 = 0.57735026918962576;  // 1/sqrt(3)
+  const double sr = z[0] * w * (1.0 / 3.0) + z[1] * m * r3 + z[2];
+  const double si = z[3] * w * (1.0 / 3.0) + z[4] * m * r3 + z[5];
+  return make_double2((sr * vd.x + si * vd.y) / w, (sr * vd.y - si * vd.x) / w);
+}
+
 __global__ void k_mismatch(const Inst* const* insts) {
   const Inst& I = *insts[blockIdx.y];
   if (inactive(I)) return;
@@ -194,10 +211,26 @@ __global__ void k_mismatch(const Inst* const* insts) {
         const double* z = I.zip + 6 * i;
         double pl = z[2] + z[1] * vm + z[0] * w;
         double ql = z[5] + z[4] * vm + z[3] * w;
-        double ps = I.psp[i] - pl, qs = I.qsp[i] - ql;
+        const double qgen = I.type[i] == 2 ? I.qg[i] : I.qsp[i];
+        double ps = I.psp[i] - pl, qs = qgen - ql;
         // conj((ps + j qs) / V) = (ps - j qs) V / |V|^2
         double spr = (ps * vi.x + qs * vi.y) / w;
         double spi = (ps * vi.y - qs * vi.x) / w;
+        if (I.dlink) {
+          const int2 L = I.dlink[i];
+          if (L.x >= 0) {
+            const double2 vt = v[L.x];
+            const double2 id = delta_current(I.zipd + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
+            spr -= id.x;
+            spi -= id.y;
+          }
+          if (L.y >= 0) {
+            const double2 vk = v[L.y];
+            const double2 id = delta_current(I.zipd + 6 * L.y, make_double2(vk.x - vi.x, vk.y - vi.y));
+            spr += id.x;
+            spi += id.y;
+          }
+        }
         double dr = spr - ir, di = spi - ii;
         I.F[2 * p] = di;
         I.F[2 * p + 1] = dr;
@@ -271,7 +304,43 @@ __device__ inline void jstore(const Inst& I, int code, double a, double b, doubl
 // CIM J (eq. 21-23): [[B, G], [G, -B]] for every admittance entry between
 // unknown nodes, minus the ZIP adjustments a, b, c, d on the node's own
 // diagonal (derived: a load component with coefficient s and exponent e
-// draws I = conj(s) V |V|^(e-2)).
+// draws I = conj(s) V |V|^(e-2)), plus the delta loads' blocks, with the
+// columns of PV nodes taken in (angle, Q).
+// dI/dVre and dI/dVim, as D = {Re dI/dVre, Im dI/dVre, Re dI/dVim,
+// Im dI/dVim}, of the current sum_k conj(s_k) V |V|^(e_k - 2): with w = |V|^2,
+// g = w^((e-2)/2), g' = ((e-2)/2) w^((e-4)/2), dI/dVre = conj(s)(g + 2 Vre V
+// g') and dI/dVim = conj(s)(j g + 2 Vim V g').
+__device__ inline void load_derivative(const double* sr, const double* sim, const double* ex, int cnt, double2 vv,
+                                       double* D) {
+  const double w = vv.x * vv.x + vv.y * vv.y;
+  double drr = 0, dri = 0, dir = 0, dii = 0;
+  for (int k = 0; k < cnt; ++k) {
+    double g = pow(w, 0.5 * (ex[k] - 2.0));
+    double gp = 0.5 * (ex[k] - 2.0) * pow(w, 0.5 * (ex[k] - 4.0));
+    double cr = sr[k], ci = -sim[k];  // conj(s)
+    double ur = g + 2.0 * vv.x * vv.x * gp, ui = 2.0 * vv.x * vv.y * gp;
+    drr += cr * ur - ci * ui;
+    dri += cr * ui + ci * ur;
+    double tr = 2.0 * vv.y * vv.x * gp, ti = g + 2.0 * vv.y * vv.y * gp;
+    dir += cr * tr - ci * ti;
+    dii += cr * ti + ci * tr;
+  }
+  D[0] = drr;
+  D[1] = dri;
+  D[2] = dir;
+  D[3] = dii;
+}
+
+// D = dI_d/dV_d of the delta load z between nodes at voltages vk and vt
+// (V_d = vk - vt): its components are s / sqrt(3)^e.
+__device__ inline void delta_derivative(const double* z, double2 vk, double2 vt, double* D) {
+  const double r3 = 0.57735026918962576;
+  const double sr[3] = {z[0] * (1.0 / 3.0), z[1] * r3, z[2]};
+  const double sim[3] = {z[3] * (1.0 / 3.0), z[4] * r3, z[5]};
+  const double ex[3] = {2.0, 1.0, 0.0};
+  load_derivative(sr, sim, ex, 3, make_double2(vk.x - vt.x, vk.y - vt.y), D);
+}
+
 __device__ inline void jblock(const Inst& I, int e, double* out) {
   const int i = I.yrow[e], j = I.col[e];
   const double2 yy = ((const double2*)I.y)[e];
@@ -317,31 +386,58 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
     c = G;
     d = -Bv;
     if (i == j) {
-      double2 vv = v[i];
-      double w = vv.x * vv.x + vv.y * vv.y;
+      const double2 vv = v[i];
       const double* z = I.zip + 6 * i;
       // components (s_re, s_im, exponent): loads enter with a minus sign
-      double sr[4] = {-z[0], -z[1], -z[2], I.psp[i]};
-      double sim[4] = {-z[3], -z[4], -z[5], I.qsp[i]};
-      double ex[4] = {2.0, 1.0, 0.0, 0.0};
-      double drr = 0, dri = 0, dir = 0, dii = 0;  // dI/dVre (re, im), dI/dVim (re, im)
-      for (int k = 0; k < 4; ++k) {
-        double g = pow(w, 0.5 * (ex[k] - 2.0));
-        double gp = 0.5 * (ex[k] - 2.0) * pow(w, 0.5 * (ex[k] - 4.0));
-        double cr = sr[k], ci = -sim[k];  // conj(s)
-        // dI/dVre = conj(s) (g + 2 Vre V g')
-        double ur = g + 2.0 * vv.x * vv.x * gp, ui = 2.0 * vv.x * vv.y * gp;
-        drr += cr * ur - ci * ui;
-        dri += cr * ui + ci * ur;
-        // dI/dVim = conj(s) (j g + 2 Vim V g')
-        double tr = 2.0 * vv.y * vv.x * gp, ti = g + 2.0 * vv.y * vv.y * gp;
-        dir += cr * tr - ci * ti;
-        dii += cr * ti + ci * tr;
+      const double sr[4] = {-z[0], -z[1], -z[2], I.psp[i]};
+      const double sim[4] = {-z[3], -z[4], -z[5], I.type[i] == 2 ? I.qg[i] : I.qsp[i]};
+      const double ex[4] = {2.0, 1.0, 0.0, 0.0};
+      double D[4];
+      load_derivative(sr, sim, ex, 4, vv, D);
+      a -= D[1];  // Im dI/dVre
+      b -= D[3];  // Im dI/dVim
+      c -= D[0];  // Re dI/dVre
+      d -= D[2];  // Re dI/dVim
+    }
+    if (I.dlink) {
+      // delta loads: the load k -> t draws I_d(V_k - V_t); with D = dI_d/dV_d
+      // it adds +D at (k, k) and (t, t), -D at (k, t) and (t, k)
+      const int2 L = I.dlink[i];
+      double D[4];
+      if (L.x >= 0 && (j == i || j == L.x)) {
+        delta_derivative(I.zipd + 6 * i, v[i], v[L.x], D);
+        const double sg = j == i ? 1.0 : -1.0;
+        a += sg * D[1];
+        b += sg * D[3];
+        c += sg * D[0];
+        d += sg * D[2];
       }
-      a -= dri;  // Im dI/dVre
-      b -= dii;  // Im dI/dVim
-      c -= drr;  // Re dI/dVre
-      d -= dir;  // Re dI/dVim
+      if (L.y >= 0 && (j == i || j == L.y)) {
+        delta_derivative(I.zipd + 6 * L.y, v[L.y], v[i], D);
+        const double sg = j == i ? 1.0 : -1.0;
+        a += sg * D[1];
+        b += sg * D[3];
+        c += sg * D[0];
+        d += sg * D[2];
+      }
+    }
+    if (I.type[j] == 2) {
+      // PV column: the node's unknowns are (angle, generator Q) with |V| at
+      // its set-point.  d/dangle = -Vim d/dVre + Vre d/dVim; the Q column is
+      // -dI_sp/dQ = -(Vim - j Vre)/|V|^2 on the node's own rows only.
+      const double2 vj = v[j];
+      const double na = -vj.y * a + vj.x * b;
+      const double nc = -vj.y * c + vj.x * d;
+      a = na;
+      c = nc;
+      if (i == j) {
+        const double w = vj.x * vj.x + vj.y * vj.y;
+        b = vj.x / w;
+        d = -vj.y / w;
+      } else {
+        b = 0.0;
+        d = 0.0;
+      }
     }
   }
   out[0] = a;
@@ -679,7 +775,7 @@ __global__ __launch_bounds__(256) void k_bwd_rows(const Inst* const* insts, cons
 // Polar: angle += dx[2p] (non-slack), |V| += dx[2p+1] (PQ only) (single-phase
 // iteration table, update line); CIM: Re V += dx[2p], Im V += dx[2p+1]
 // (eq. 20 pairing; three-phase iteration table, update and complex-form
-// lines).  Refreshes the rectangular voltage and records max |dx|.
+// lines), on PV nodes angle += dx[2p] and Q_g += dx[2p+1].  Refreshes the rectangular voltage and records max |dx|.
 template <typename T>
 __global__ void k_update(const Inst* const* insts) {
   const Inst& I = *insts[blockIdx.y];
@@ -698,6 +794,16 @@ __global__ void k_update(const Inst* const* insts) {
       double s, c;
       sincos(a, &s, &c);
       ((double2*)I.v)[i] = make_double2(m * c, m * s);
+    } else if (I.type[i] == 2) {
+      // PV node: rotate by the angle step at the set-point magnitude; the
+      // second unknown is the generator Q
+      double2 vv = ((double2*)I.v)[i];
+      double s, c;
+      sincos(d0, &s, &c);
+      double nr = vv.x * c - vv.y * s, ni = vv.x * s + vv.y * c;
+      double sc = I.vmag[i] / sqrt(nr * nr + ni * ni);
+      ((double2*)I.v)[i] = make_double2(nr * sc, ni * sc);
+      I.qg[i] += d1;
     } else {
       double2 vv = ((double2*)I.v)[i];
       ((double2*)I.v)[i] = make_double2(vv.x + d0, vv.y + d1);

@@ -157,11 +157,59 @@ def _asymmetric(c):
     return dict(row_ptr=Y.indptr, col_idx=Y.indices, y=Y.data)
 
 
-def test_cim_rejects_pv_nodes():
-    f = pfgen.make_feeder(10, 3)
-    args = B.case_arrays(f)
-    bt = f.node_type.copy()
-    bt[5] = 2
-    args["bus_type"] = bt
-    with pytest.raises(B.PFError):
+def _dg_feeder():
+    return pfgen.add_dg_and_delta(pfgen.make_feeder(60, 2), 3)
+
+
+def test_dg_feeder_analysis_replay():
+    c = _dg_feeder()
+    assert (c.node_type == 2).sum() > 0 and (c.delta_to >= 0).sum() > 0
+    res, chk = B.pf_debug_schedule_check(**B.case_arrays(c), seed=2)
+    assert res < 1e-12 and chk > 0
+    dev, kres, _ = B.pf_debug_krylov_check(**B.case_arrays(c), seed=2)
+    assert dev < 1e-12 and kres < 1e-12
+
+
+def _with(c, **over):
+    args = B.case_arrays(c)
+    args.update(over)
+    return args
+
+
+def _two_into_one(c):
+    dt = c.delta_to.copy()
+    k = int(np.flatnonzero(dt >= 0)[0])
+    other = int(np.flatnonzero((dt < 0) & (np.arange(c.n) != dt[k]) & (np.arange(c.n) != k))[-1])
+    # a second load into the same node needs the pattern entry: pick a
+    # neighbour of that node
+    t = int(dt[k])
+    nb = [int(j) for j in c.col[c.row_ptr[t]:c.row_ptr[t + 1]] if j != t and dt[j] < 0 and j != k]
+    dt[nb[0] if nb else other] = t
+    return dt
+
+
+@pytest.mark.parametrize("what,over", [
+    ("delta_to without zip_delta", lambda c: dict(zip_delta=None)),
+    ("zip_delta without delta_to", lambda c: dict(delta_to=None)),
+    ("target out of range", lambda c: dict(delta_to=np.where(c.delta_to >= 0, c.n, -1))),
+    ("target is the node", lambda c: dict(delta_to=np.where(c.delta_to >= 0, np.arange(c.n), -1))),
+    ("node receives two", lambda c: dict(delta_to=_two_into_one(c))),
+    ("no pattern entry", lambda c: dict(delta_to=np.where(np.arange(c.n) == 5, c.n - 1, c.delta_to))),
+    ("pv magnitude zero", lambda c: dict(v_mag=np.where(c.node_type == 2, 0.0, c.v_mag))),
+    ("nan delta coefficient", lambda c: dict(zip_delta=np.where(np.arange(6 * c.n).reshape(c.n, 6) == 30,
+                                                                 np.nan, c.zip_delta))),
+])
+def test_dg_and_delta_inputs_rejected(what, over):
+    c = _dg_feeder()
+    with pytest.raises(B.PFError) as ei:
+        B.pf_debug_schedule_check(**_with(c, **over(c)))
+    assert ei.value.code == B.PF_E_INVALID, what
+
+
+def test_polar_rejects_delta_loads():
+    c = pfgen.config_case(0)
+    args = B.case_arrays(c)
+    args.update(delta_to=-np.ones(c.n, np.int32), zip_delta=np.zeros((c.n, 6)))
+    with pytest.raises(B.PFError) as ei:
         B.pf_debug_schedule_check(**args)
+    assert ei.value.code == B.PF_E_INVALID
