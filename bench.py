@@ -538,6 +538,16 @@ def bench_replication(args):
         print(f"replication feeder {fc.n_bus}: {row['solve_ms']['p50']:.2f} ms", file=sys.stderr, flush=True)
         h.close()
 
+    # the 2,000-bus feeder with generators (PV phase-nodes) and delta loads
+    dg = pfgen.add_dg_and_delta(pfgen.config_case(2), 21, n_dg=6)
+    h = B.pf_create_from(ctx, dg)
+    dg_rows = {"buses": dg.n_bus, "phase_nodes": dg.n, "pv_nodes": int((dg.node_type == 2).sum()),
+               "delta_loads": int((dg.delta_to >= 0).sum())}
+    for name, solver in (("lu", B.PF_SOLVER_LU), ("bicgstab", B.PF_SOLVER_BICGSTAB)):
+        dg_rows[name] = timed(h, B.pf_default_options(solver=solver, max_iter=40),
+                              lambda V: cim.mismatch_at(dg, V))
+    h.close()
+
     out = {"mode": "replication",
            "metric": "solve time of the replication-scale cases (48,000-bus grid, Newton-Krylov BiCGStab + ILU(0))",
            "value": rows["bicgstab"]["solve_ms"]["p50"], "unit": "ms", "n_gpus": 1, "steps": k,
@@ -546,7 +556,7 @@ def bench_replication(args):
            "config": {"workload": "replicated 30-bus blocks (48,000 buses) and replicated 906-bus feeders "
                                   "(1-256 copies), flat start to 1e-8 pu (1e-7 for 256 copies, whose FP64 rounding "
                                   "floor at the first bus is 2.2e-8), one solve at a time"},
-           "grid48k": rows, "feeders": feeders,
+           "grid48k": rows, "feeders": feeders, "feeder2000_dg_delta": dg_rows,
            "note": "paper times are CPU seconds on a Cori node (context, another machine)"}
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits

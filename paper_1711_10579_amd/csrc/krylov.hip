@@ -923,10 +923,13 @@ __device__ inline T* kvec(const Inst& I, int i) {
 
 // Sum over the chunks of entry e of a pass's partial sums, in chunk order
 // (the same value wherever it is formed).
+// Called by all 64 lanes of one wave: lane-strided partial sums, then the
+// butterfly of wave_sum, so every lane (and every work-group) gets the same
+// value in a fixed order.
 __device__ inline double chunk_sum(const Inst& I, int pass, int e) {
   double s = 0.0;
-  for (int c = 0; c < I.kchunks; ++c) s += kpart(I, pass, c)[e];
-  return s;
+  for (int c = threadIdx.x & 63; c < I.kchunks; c += 64) s += kpart(I, pass, c)[e];
+  return wave_sum(s);
 }
 
 // The solve ends as it stands.
@@ -1042,9 +1045,12 @@ __global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
   __shared__ double alpha_s;
   const Inst& I = *insts[blockIdx.y];
   if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
-  if (threadIdx.x == 0) {
-    alpha_s = I.ks->rho / chunk_sum(I, 0, 0);
-    if (blockIdx.x == 0) I.ks->alpha = alpha_s;
+  if (threadIdx.x < 64) {
+    const double a = I.ks->rho / chunk_sum(I, 0, 0);
+    if (threadIdx.x == 0) {
+      alpha_s = a;
+      if (blockIdx.x == 0) I.ks->alpha = a;
+    }
   }
   __syncthreads();
   const double alpha = alpha_s;
@@ -1153,11 +1159,14 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
     }
     return;
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     const double tt = chunk_sum(I, 0, 1);
-    skip_s = !(tt > 0.0);
-    omega_s = skip_s ? 0.0 : chunk_sum(I, 0, 0) / tt;
-    if (blockIdx.x == 0) I.ks->omega = omega_s;
+    const double ts = chunk_sum(I, 0, 0);
+    if (threadIdx.x == 0) {
+      skip_s = !(tt > 0.0);
+      omega_s = skip_s ? 0.0 : ts / tt;
+      if (blockIdx.x == 0) I.ks->omega = omega_s;
+    }
   }
   __syncthreads();
   if (skip_s) return;  // <t, t> = 0: the solve ends as it stands
