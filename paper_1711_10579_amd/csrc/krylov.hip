@@ -95,6 +95,37 @@ __device__ inline void block_sums(int count, F f, double (*red)[KCH / 64], doubl
 // L(r,k) = A(r,k) U(k,k)^{-1}, followed by its listed updates
 // A(r,j) -= L(r,k) U(k,j); then the row's diagonal block is inverted.  One
 // thread per row; rows of earlier levels are final.
+// The updates of row r from one of its lower entries, L = L(r, k):
+// P(t_u) -= L P(s_u) for u in [u0, u1).  The targets are distinct entries of
+// row r and the sources lie in row k < r, so the loads of four updates are
+// issued together; every target still sees its updates in the order of the
+// row's lower entries.
+template <typename T, typename PP, typename IP>
+__device__ inline void ilu_updates(PP P, IP kup_t, IP kup_s, int u0, int u1, const Blk<T>& L) {
+  for (int u = u0; u < u1; u += 4) {
+    int t[4], sr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (u + e < u1) {
+        t[e] = kup_t[u + e];
+        sr[e] = kup_s[u + e];
+      }
+    Blk<T> a[4], b[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (u + e < u1) {
+        a[e] = ld_blk<T>(P, t[e]);
+        b[e] = ld_blk<T>(P, sr[e]);
+      }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (u + e < u1) {
+        blk_msub(a[e], L, b[e]);
+        st_blk(P, t[e], a[e]);
+      }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, const int2* __restrict__ work, int nwork) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -109,12 +140,7 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
   for (int q = I.krow_ptr[r]; q < qd; ++q) {
     const Blk<T> L = blk_mul(ld_blk(P, q), ld_blk((const T*)D, I.kcol[q]));
     st_blk(P, q, L);
-    for (int u = I.kup_ptr[q]; u < I.kup_ptr[q + 1]; ++u) {
-      const int t = I.kup_t[u];
-      Blk<T> a = ld_blk(P, t);
-      blk_msub(a, L, ld_blk(P, I.kup_s[u]));
-      st_blk(P, t, a);
-    }
+    ilu_updates<T>(P, I.kup_t, I.kup_s, I.kup_ptr[q], I.kup_ptr[q + 1], L);
   }
   Blk<T> inv;
   if (!blk_inv(ld_blk(P, qd), &inv)) {
@@ -301,12 +327,7 @@ __global__ __launch_bounds__(1024) void k_ilu_factor_wg(const Inst* const* insts
       for (int q = inf.y; q < qd; ++q) {
         const Blk<T> L = blk_mul(ld_blk<T>(P, q), ld_blk<T>(D, kcol[q]));
         st_blk(P, q, L);
-        for (int u = kup_ptr[q]; u < kup_ptr[q + 1]; ++u) {
-          const int t = kup_t[u];
-          Blk<T> a = ld_blk<T>(P, t);
-          blk_msub(a, L, ld_blk<T>(P, kup_s[u]));
-          st_blk(P, t, a);
-        }
+        ilu_updates<T>(P, kup_t, kup_s, kup_ptr[q], kup_ptr[q + 1], L);
       }
       Blk<T> inv;
       if (!blk_inv(ld_blk<T>(P, qd), &inv)) {
