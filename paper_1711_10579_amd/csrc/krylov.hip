@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
 template <typename T>
 __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ double A[64][129];
+  __shared__ double colk[64];
   __shared__ int piv;
   __shared__ int bad;
   const int2 wk = work[blockIdx.x];
@@ -209,25 +210,29 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
     __syncthreads();
     if (bad) break;
     const int p = piv;
-    if (p != k)
-      for (int c = tid; c < 128; c += 256) {
-        double t = A[k][c];
-        A[k][c] = A[p][c];
-        A[p][c] = t;
-      }
-    __syncthreads();
-    const double ip = 1.0 / A[k][k];
-    __syncthreads();
-    for (int c = tid; c < 128; c += 256) A[k][c] *= ip;
-    __syncthreads();
-    // eliminate column k from every other row
-    for (int e = tid; e < 64 * 128; e += 256) {
-      const int i = e >> 7, c = e & 127;
-      if (i != k && i < N && c != k) A[i][c] -= A[i][k] * A[k][c];
+    if (p != k && tid < 128) {
+      double t = A[k][tid];
+      A[k][tid] = A[p][tid];
+      A[p][tid] = t;
     }
     __syncthreads();
-    for (int i = tid; i < N; i += 256)
-      if (i != k) A[i][k] = 0.0;
+    // the pivot column, read before any thread writes its own column
+    if (tid < N) colk[tid] = A[tid][k];
+    __syncthreads();
+    // thread (c, h) owns column c of [A | I] and the rows i = h mod 2: the
+    // pivot row is scaled by 1/A[k][k] and every other row loses
+    // A[i][k] times it (column k itself becomes exactly the unit column);
+    // columns left of k are zero in the pivot row and are skipped
+    {
+      const int c = tid & 127, h = tid >> 7;
+      if (c >= k) {
+        const double ip = 1.0 / colk[k];
+        const double akc = A[k][c] * ip;
+        for (int i = h; i < N; i += 2)
+          if (i != k) A[i][c] -= colk[i] * akc;
+        if (h == 0) A[k][c] = akc;
+      }
+    }
     __syncthreads();
   }
   if (bad) {
