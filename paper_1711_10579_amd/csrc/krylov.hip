@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
 
 // Block-Jacobi: inverse of the diagonal block of one node group (order N =
 // 2 x nodes <= 64) by Gauss-Jordan elimination with partial pivoting on
-// [A | I] in LDS (FP64), stored row-major at bj_off[b].
+// [A | I] in LDS (FP64), stored column-major at bj_off[b].
 template <typename T>
 __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ double A[64][129];
@@ -239,9 +239,11 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
     if (tid == 0) I.red->singular = 1;
     return;
   }
+  // stored column-major: entry (i, c) at c N + i, so that a wave applying the
+  // block reads one contiguous column per step
   T* out = (T*)I.bjinv + I.bj_off[b];
   for (int e = tid; e < N * N; e += 256) {
-    const int i = e / N, c = e - i * N;
+    const int c = e / N, i = e - c * N;
     out[e] = (T)A[i][64 + c];
   }
 }
@@ -544,9 +546,9 @@ __global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const
   }
   __syncthreads();
   if (t < N) {
-    const T* inv = (const T*)I.bjinv + I.bj_off[b] + (int64_t)t * N;
+    const T* inv = (const T*)I.bjinv + I.bj_off[b] + t;
     double s = 0.0;
-    for (int c = 0; c < N; ++c) s += (double)inv[c] * v[c];
+    for (int c = 0; c < N; ++c) s += (double)inv[(int64_t)c * N] * v[c];
     const int r = I.bj_rows[r0 + (t >> 1)];
     ((T*)I.kz)[2 * r + (t & 1)] = (T)s;
   }
