@@ -125,3 +125,42 @@ def test_dg_batch_bit_identical_to_alone(B, ctx, precision):
         assert r.status == 0, (c.name, r.as_dict())
         assert np.array_equal(B.pf_get_voltage(h), Va), c.name
         h.close()
+
+
+def _edge_case_feeder():
+    # a feeder whose delta links include a load from a source node into an
+    # unknown node, and two unknown nodes drawing loads into each other, with
+    # a generator on a bus right behind the source
+    fc = pfgen.make_feeder(40, 17, laterals=False)
+    c = pfgen.add_dg_and_delta(fc, 2, n_dg=0, delta_frac=0.0, single_phase_dg=False)
+    child = int(c.t[np.flatnonzero(c.f == 0)[0]])
+    kids = np.flatnonzero(c.node_bus == child)
+    src_a = 0
+    assert kids.size == 3
+    # source phase a -> child phase b (a coupled branch gives the entry)
+    assert kids[1] in c.col[c.row_ptr[src_a]:c.row_ptr[src_a + 1]]
+    c.delta_to[src_a] = kids[1]
+    c.zip_delta[src_a] = [0.0, 0.0, 0.004, 0.0, 0.0, 0.002]
+    # a two-node cycle on another bus
+    other = np.flatnonzero(c.node_bus == 25)
+    c.delta_to[other[0]] = other[2]
+    c.delta_to[other[2]] = other[0]
+    c.zip_delta[other[0]] = [0.003, 0.0, 0.002, 0.001, 0.0, 0.001]
+    c.zip_delta[other[2]] = [0.0, 0.004, 0.0, 0.0, 0.002, 0.0]
+    # generator on every phase of the source's child
+    c.node_type[kids] = pfgen.PV
+    c.v_mag[kids] = 1.005
+    c.p_gen[kids] = 0.01
+    return c
+
+
+@pytest.mark.parametrize("solver", [0, 2], ids=["lu", "bicgstab"])
+def test_dg_degenerate_links(B, ctx, solver):
+    case = _edge_case_feeder()
+    _say(f"dg edge cases solver={solver}")
+    h = B.pf_create_from(ctx, case)
+    r = B.pf_solve(h, solver=solver, max_iter=40)
+    V = B.pf_get_voltage(h)
+    _say(f"  iters={r.iters} linear={r.linear_iters} mismatch={r.mismatch_inf:.2e}")
+    _check("edge", case, r, V)
+    h.close()
