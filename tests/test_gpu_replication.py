@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-8
 VTOL = 1e-7
-SOLVERS = [("lu", 0), ("gmres", 1), ("bicgstab", 2)]
+SOLVERS = [("lu", 0, 0), ("gmres", 1, 0), ("bicgstab", 2, 0), ("bicgstab-bjacobi", 2, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -55,7 +55,7 @@ def test_polar_replica_3000_buses(B, ctx, solver):
     case = pfgen.replication_polar(100)
     _say(f"replica {case.name} solver={solver[0]}")
     h = B.pf_create_from(ctx, case)
-    r = B.pf_solve(h, solver=solver[1], max_iter=40)
+    r = B.pf_solve(h, solver=solver[1], precond=solver[2], max_iter=40)
     V = B.pf_get_voltage(h)
     assert r.status == 0, r.as_dict()
     assert polar.mismatch_at(case, V) <= TOL
@@ -68,7 +68,7 @@ def test_feeder_replica_two_copies(B, ctx, solver):
     case = pfgen.replication_feeder(2)
     _say(f"replica {case.name} solver={solver[0]}")
     h = B.pf_create_from(ctx, case)
-    r = B.pf_solve(h, solver=solver[1], max_iter=40, nk_fallback=1)
+    r = B.pf_solve(h, solver=solver[1], precond=solver[2], max_iter=40, nk_fallback=1)
     V = B.pf_get_voltage(h)
     _say(f"  status={r.status} iters={r.iters} linear={r.linear_iters} fallback={r.lu_fallback}")
     assert r.status == 0, r.as_dict()
@@ -90,7 +90,7 @@ def test_polar_replica_48000_buses(B, ctx, grid48k, solver):
     case, ref = grid48k
     _say(f"replica {case.name} solver={solver[0]}")
     h = B.pf_create_from(ctx, case)
-    r = B.pf_solve(h, solver=solver[1], max_iter=40)
+    r = B.pf_solve(h, solver=solver[1], precond=solver[2], max_iter=40)
     V = B.pf_get_voltage(h)
     _say(f"  status={r.status} iters={r.iters} linear={r.linear_iters} mismatch={r.mismatch_inf:.2e}")
     assert r.status == 0, r.as_dict()
