@@ -63,13 +63,16 @@ typedef enum {
   PF_DIVERGED = 2,   /* non-finite mismatch or growth beyond 1e6 x initial     */
   PF_SINGULAR = 3,   /* zero or non-finite pivot in the refactorisation        */
   PF_LINEAR_FAIL = 4,/* the Krylov solve did not reach its forcing tolerance */
-  PF_PENDING = 5     /* served request not finished yet                        */
+  PF_PENDING = 5,    /* served request not finished yet                        */
+  PF_FAILED = 6      /* served request could not run (device or allocation
+                        failure); pf_result.error holds the pf_status         */
 } pf_solve_status;
 
 typedef enum { PF_MODEL_POLAR_1PH = 0, PF_MODEL_CIM_3PH = 1 } pf_model;
-/* Bus (phase-node) types.  Polar: exactly one PF_SLACK.  CIM: the source
- * bus's phase-nodes are PF_SLACK (fixed voltage), all others PF_PQ; the paper
- * adds no PV injection in the three-phase method (Sec. II-B). */
+/* Bus (phase-node) types.  Polar: exactly one PF_SLACK, PV buses, PQ buses.
+ * CIM: the source bus's phase-nodes are PF_SLACK (fixed voltage), load
+ * phase-nodes PF_PQ, and phase-nodes with voltage-controlled distributed
+ * generation PF_PV (generation Sec. II-B leaves out; see pf_case_desc). */
 typedef enum { PF_PQ = 1, PF_PV = 2, PF_SLACK = 3 } pf_bus_type;
 typedef enum { PF_SOLVER_LU = 0, PF_SOLVER_GMRES = 1, PF_SOLVER_BICGSTAB = 2 } pf_solver;
 typedef enum { PF_PREC_FP64 = 0, PF_PREC_MIXED = 1 } pf_precision;
@@ -158,7 +161,11 @@ typedef struct {
   int32_t lu_fallback;  /* 1: a Krylov step failed and LU finished the solve */
   double mismatch_inf;  /* max-norm of the final FP64 mismatch               */
   double max_step;      /* max |dx| of the last Newton step (the paper's test)*/
-  double device_ms;     /* device time of the solve (events around it)       */
+  double device_ms;     /* device time of the solve (events around it);
+                           served: host time from admission to retirement    */
+  int32_t error;        /* PF_FAILED: the pf_status of the failure, else 0   */
+  int32_t reserved;
+  double wait_ms;       /* served: host time from pf_submit to admission     */
 } pf_result;
 
 /* Static information about a created case. */
@@ -173,8 +180,15 @@ typedef struct {
   int64_t updates;      /* 2x2 block updates of the sparse refactorisation   */
   int64_t tail_updates; /* 2x2 block updates into the dense trailing block   */
   double flops_factor;  /* algorithmic flops of one refactorisation          */
-  size_t device_bytes;  /* device memory held by the case                    */
+  size_t device_bytes;  /* device memory the case holds now (resident, plus its
+                           own working and Krylov storage once allocated)    */
   double analysis_ms;   /* host analysis time in pf_create                   */
+  size_t resident_bytes;/* Ybus, index lists, set-points, state: from
+                           pf_create to pf_destroy                           */
+  size_t work_bytes;    /* working storage of an LU solve: factor values, the
+                           dense block and its inverses                      */
+  size_t krylov_bytes;  /* Krylov storage of a Newton-Krylov solve with the
+                           default restart length (30)                       */
 } pf_case_info;
 
 /* Schedule of a case: choices of the host analysis and of the launch sequence
@@ -257,6 +271,14 @@ pf_status pf_autotune(pf_ctx* ctx, const pf_case_desc* desc, const pf_options* o
 /* Free a case's device memory.  PF_E_BUSY while it is queued or running. */
 pf_status pf_destroy(pf_case* c);
 pf_status pf_case_info_get(const pf_case* c, pf_case_info* out);
+/* Device footprint of an LU solve of the case (the unknowns, eq. 10 / 19-20,
+ * factored as in Sec. III-A): *bytes = its resident storage plus the working
+ * storage a solve needs (pf_case_info.resident_bytes + work_bytes); a
+ * Newton-Krylov solve needs pf_case_info.krylov_bytes more.  The working
+ * storage is allocated by the case's first pf_solve / pf_solve_batch and
+ * kept; a served request borrows it from the serving pool instead (see
+ * pf_serve_config).  Host output; PF_E_INVALID on NULL. */
+pf_status pf_case_footprint(const pf_case* c, size_t* bytes);
 
 /* Replace the specified injections (same topology): p_sp/q_sp as in
  * pf_case_desc (NULL keeps the old values), zip [6n] for CIM (NULL keeps). */
@@ -275,17 +297,36 @@ pf_status pf_solve(pf_case* c, const pf_options* opt, pf_result* res);
 pf_status pf_solve_batch(pf_ctx* ctx, pf_case* const* cases, int32_t count, const pf_options* opt,
                          pf_result* results);
 
-/* Serving loop: enqueue a solve of `c` (non-blocking).  Requests are admitted
- * as device memory and batch slots free up and join the running batch at the
- * next Newton-step boundary (continuous batching).  *ticket identifies it. */
+/* Serving loop (continuous batching): enqueue a solve of `c` under `opt`
+ * (NULL: defaults) and return at once; *ticket identifies it.  Requests are
+ * admitted first come, first served, when a slot is free and the serving
+ * pool can lend the request's working storage (its case's own storage, when
+ * it has some, is used instead); the request at the head of the queue waits
+ * until running requests give enough back.  Every admitted request's Newton
+ * steps run on the device beside the others' (spread over four streams, each
+ * step replayed from the case's captured graph) and it retires as soon as
+ * its own iteration ends; requests may differ in options.  Each result is
+ * identical to pf_solve of the case alone.  A request whose storage exceeds
+ * the whole budget finishes at once with PF_FAILED (error PF_E_NOMEM).  The
+ * first submit of a case builds its launch plan (host work and one device
+ * allocation, in the caller's thread).  PF_E_BUSY if `c` is already queued or
+ * running. */
 pf_status pf_submit(pf_ctx* ctx, pf_case* c, const pf_options* opt, uint64_t* ticket);
 /* Non-blocking: *done = 1 and *out filled when the request has finished
  * (the ticket is then released), else *done = 0.  PF_E_NOTFOUND for an
  * unknown ticket. */
 pf_status pf_poll(pf_ctx* ctx, uint64_t ticket, pf_result* out, int32_t* done);
-/* Limit the device bytes that admitted served requests may hold (0: no
- * limit) and the number of requests in one batch. */
+/* Budget of the serving pool and the number of requests running at once
+ * (max_slots 0: keep; default 32).  max_bytes > 0: the pool is one device
+ * allocation of max_bytes made here, and the working storage lent to running
+ * requests never exceeds it; 0 (default): no limit, the pool grows by chunks
+ * of at least 256 MiB when a request does not fit and keeps them.  The pool
+ * is freed with the context.  PF_E_BUSY when the budget would change while
+ * requests are queued or running; PF_E_NOMEM if the allocation fails. */
 pf_status pf_serve_config(pf_ctx* ctx, size_t max_bytes, int32_t max_slots);
+/* Serving pool size and bytes lent now, requests queued and running (host
+ * outputs). */
+pf_status pf_serve_stats(pf_ctx* ctx, size_t* pool_bytes, size_t* lent_bytes, int32_t* queued, int32_t* running);
 
 /* Copy the case's current voltages (rectangular form) into host arrays of n
  * doubles each. */

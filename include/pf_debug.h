@@ -1,9 +1,11 @@
 /*
- * pf_debug.h - host-only self-check of the symbolic analysis.
+ * pf_debug.h - self-checks of the symbolic analysis and of the
+ * preconditioner set-up.
  *
- * Not a compute path: the solve entry points of pf.h never call it, and it
- * touches no device.  It exists so that the fill-reducing ordering and the
- * symbolic block LU of Sec. III-A can be tested on a machine without a GPU.
+ * Not a compute path: the solve entry points of pf.h never call these.  The
+ * two analysis checks touch no device, so that the fill-reducing ordering and
+ * the symbolic block LU of Sec. III-A can be tested on a machine without a
+ * GPU; the preconditioner check runs its set-up kernels on the device.
  */
 #ifndef PF_DEBUG_H_
 #define PF_DEBUG_H_
@@ -43,6 +45,23 @@ pf_status pf_debug_schedule_check(const pf_case_desc* desc, const pf_schedule* s
  * (reason in pf_last_error()).  Outputs are host pointers. */
 pf_status pf_debug_krylov_check(const pf_case_desc* desc, uint64_t seed, double* ilu_deviation,
                                 double* rel_residual, int64_t* checks);
+
+/* The one call here that uses the device: a check of the Newton-Krylov
+ * preconditioner set-up kernels (Sec. III-B).  The case's Jacobian at its
+ * flat start is built on the device and the set-up kernels for `precond`
+ * run on it exactly as in a Krylov Newton step (FP64); the results are
+ * copied back and checked on the host against their definitions:
+ *   PF_PRECOND_ILU0:    *deviation = max over the pattern of
+ *                       |(L U - A)_ij| / max |A_ij|, together with
+ *                       max |U_rr Uinv_rr - I| of the stored inverted
+ *                       diagonal blocks; *max_order = 2 (block order);
+ *   PF_PRECOND_BJACOBI: *deviation = max over the node groups of
+ *                       max |A_bb X - I|, X the stored inverse of the group's
+ *                       diagonal block A_bb; *max_order = the largest group
+ *                       order (2 x nodes).
+ * The case is left at its flat-start voltage.  Host outputs.  PF_E_BUSY while
+ * the case is queued or running; PF_E_INVALID for a singular pivot. */
+pf_status pf_debug_precond_check(pf_case* c, int32_t precond, double* deviation, int32_t* max_order);
 
 #ifdef __cplusplus
 }

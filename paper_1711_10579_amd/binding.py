@@ -37,7 +37,7 @@ _preload_torch_hip_runtime()
 _lib = C.CDLL(LIB_PATH)
 
 PF_OK, PF_E_INVALID, PF_E_NOMEM, PF_E_DEVICE, PF_E_BUSY, PF_E_NOTFOUND = range(6)
-PF_CONVERGED, PF_MAXITER, PF_DIVERGED, PF_SINGULAR, PF_LINEAR_FAIL, PF_PENDING = range(6)
+PF_CONVERGED, PF_MAXITER, PF_DIVERGED, PF_SINGULAR, PF_LINEAR_FAIL, PF_PENDING, PF_FAILED = range(7)
 PF_MODEL_POLAR_1PH, PF_MODEL_CIM_3PH = 0, 1
 PF_PQ, PF_PV, PF_SLACK = 1, 2, 3
 PF_SOLVER_LU, PF_SOLVER_GMRES, PF_SOLVER_BICGSTAB = 0, 1, 2
@@ -51,7 +51,7 @@ KERNEL_CLASS_NAMES = ["mismatch", "jfill", "sparse_factor", "tail_schur", "dense
                       "krylov", "precond_setup", "precond_apply"]
 
 STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "diverged", 3: "singular",
-                4: "linear_fail", 5: "pending"}
+                4: "linear_fail", 5: "pending", 6: "failed"}
 
 
 class pf_case_desc(C.Structure):
@@ -74,7 +74,8 @@ class pf_options(C.Structure):
 class pf_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("linear_iters", C.c_int32),
                 ("lu_fallback", C.c_int32), ("mismatch_inf", C.c_double), ("max_step", C.c_double),
-                ("device_ms", C.c_double)]
+                ("device_ms", C.c_double), ("error", C.c_int32), ("reserved", C.c_int32),
+                ("wait_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,7 +102,8 @@ class pf_case_info(C.Structure):
                 ("n_dense", C.c_int32), ("levels", C.c_int32), ("bwd_levels", C.c_int32),
                 ("nnz_l_blocks", C.c_int64), ("updates", C.c_int64), ("tail_updates", C.c_int64),
                 ("flops_factor", C.c_double), ("device_bytes", C.c_size_t),
-                ("analysis_ms", C.c_double)]
+                ("analysis_ms", C.c_double), ("resident_bytes", C.c_size_t), ("work_bytes", C.c_size_t),
+                ("krylov_bytes", C.c_size_t)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -129,6 +131,7 @@ _sig = {
                               C.POINTER(pf_schedule), C.POINTER(pf_tune_report)]),
     "pf_destroy": (C.c_int, [_P]),
     "pf_case_info_get": (C.c_int, [_P, C.POINTER(pf_case_info)]),
+    "pf_case_footprint": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "pf_set_injections": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
     "pf_solve": (C.c_int, [_P, C.POINTER(pf_options), C.POINTER(pf_result)]),
@@ -137,6 +140,8 @@ _sig = {
     "pf_submit": (C.c_int, [_P, _P, C.POINTER(pf_options), C.POINTER(C.c_uint64)]),
     "pf_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(pf_result), C.POINTER(C.c_int32)]),
     "pf_serve_config": (C.c_int, [_P, C.c_size_t, C.c_int32]),
+    "pf_serve_stats": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
     "pf_get_voltage": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pf_set_voltage": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pf_profile_enable": (C.c_int, [_P, C.c_int32]),
@@ -146,6 +151,7 @@ _sig = {
                                           C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pf_debug_krylov_check": (C.c_int, [C.POINTER(pf_case_desc), C.c_uint64, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pf_debug_precond_check": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "pf_last_error": (C.c_char_p, []),
     "pf_version": (C.c_char_p, []),
 }
@@ -361,6 +367,16 @@ def pf_debug_krylov_check(model, row_ptr, col_idx, y, bus_type, v_mag, v_ang, p_
     return dev.value, res.value, chk.value
 
 
+def pf_debug_precond_check(case, precond):
+    """Device check of the preconditioner set-up kernels at the case's flat
+    start (include/pf_debug.h).  Returns (deviation, largest block order)."""
+    dev = C.c_double()
+    order = C.c_int32()
+    _check(_lib.pf_debug_precond_check(case.handle, int(precond), C.byref(dev), C.byref(order)),
+           "pf_debug_precond_check")
+    return dev.value, order.value
+
+
 def pf_create_from(ctx, case, schedule=None):
     """Convenience: create from a seeded grid object (single-phase or feeder)."""
     return pf_create(ctx, **case_arrays(case), schedule=schedule)
@@ -393,6 +409,13 @@ def pf_case_info_get(case):
     info = pf_case_info()
     _check(_lib.pf_case_info_get(case.handle, C.byref(info)), "pf_case_info_get")
     return info.as_dict()
+
+
+def pf_case_footprint(case):
+    """Device bytes of an LU solve of the case: resident plus working storage."""
+    b = C.c_size_t()
+    _check(_lib.pf_case_footprint(case.handle if case is not None else None, C.byref(b)), "pf_case_footprint")
+    return b.value
 
 
 def pf_set_injections(case, p_sp=None, q_sp=None, zip=None):
@@ -435,6 +458,15 @@ def pf_poll(ctx, ticket):
 
 def pf_serve_config(ctx, max_bytes=0, max_slots=0):
     _check(_lib.pf_serve_config(ctx.handle, max_bytes, max_slots), "pf_serve_config")
+
+
+def pf_serve_stats(ctx):
+    """Serving pool bytes, bytes lent now, requests queued and running."""
+    pool, lent = C.c_size_t(), C.c_size_t()
+    q, r = C.c_int32(), C.c_int32()
+    _check(_lib.pf_serve_stats(ctx.handle, C.byref(pool), C.byref(lent), C.byref(q), C.byref(r)),
+           "pf_serve_stats")
+    return {"pool_bytes": pool.value, "lent_bytes": lent.value, "queued": q.value, "running": r.value}
 
 
 def pf_get_voltage(case):

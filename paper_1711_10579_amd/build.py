@@ -30,6 +30,7 @@ SOURCES = [
     "krylov_check.cpp",
     "tune.cpp",
     "dense_plan.cpp",
+    "precond_check.cpp",
     "kernels.hip",
     "dense.hip",
     "krylov.hip",

@@ -47,7 +47,7 @@ void Ctx::dfree(void* p) {
 
 void Ctx::prof_begin(int cls, hipEvent_t* a) {
   *a = nullptr;
-  if (!(profile_mask & (1 << cls))) return;
+  if (!(mask() & (1 << cls))) return;
   hipEvent_t e;
   if (capture) {
     if (cap_pool.empty()) {
@@ -496,9 +496,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   total += carve_size<int8_t>(n) + 4 * carve_size<double>(n) + carve_size<double>(6LL * n);
   total += carve_size<int>(n) + carve_size<int>(nu);
   total += 2 * carve_size<double>(n) + 2 * carve_size<double>(2LL * n) + carve_size<double>(2LL * nu);
-  total += carve_size<double>(2LL * nu) + carve_size<double>(c->lu_count()) + carve_size<double>(4LL * ns) +
-           carve_size<double>(c->tail_count()) + carve_size<double>(c->dinvu_count()) + carve_size<int>(c->nblk()) +
-           carve_size<unsigned long long>(c->nblk());
+  total += carve_size<double>(2LL * nu);
   total += carve_size<int>(ns + 1) + carve_size<int>(an.nnzl) + carve_size<int64_t>(c->ntg + 1) +
            2 * carve_size<int>(nupd) + carve_size<int>(ns);
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
@@ -506,6 +504,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   total += carve_size<double>(n) + carve_size<int>(2LL * n) + carve_size<double>(6LL * n);
   total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1);
   c->bytes = total;
+  c->wbytes = work_bytes(c);
   c->base = (char*)ctx->dalloc(total);
   if (!c->base) {
     delete c;
@@ -535,12 +534,6 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   c->ibus = carve<double>(p, 2LL * n);
   c->F = carve<double>(p, 2LL * nu);
   c->x = carve<double>(p, 2LL * nu);
-  c->lu = carve<double>(p, c->lu_count());
-  c->dinv = carve<double>(p, 4LL * ns);
-  c->tail = carve<double>(p, c->tail_count());
-  c->dinvu = carve<double>(p, c->dinvu_count());
-  c->dflags = carve<int>(p, c->nblk());
-  c->pflags = carve<unsigned long long>(p, c->nblk());
   c->colptr = carve<int>(p, ns + 1);
   c->rowidx = carve<int>(p, an.nnzl);
   c->uptr = carve<int64_t>(p, c->ntg + 1);
@@ -615,8 +608,6 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   ok &= up(c->lrow_col, an.lrow_col.data(), sizeof(int) * an.nnzl);
   ok &= up(c->bwd_rows, an.bwd_rows.data(), sizeof(int) * ns);
   ok &= hipMemsetAsync(c->red, 0, sizeof(pfd::Red), s) == hipSuccess;
-  ok &= hipMemsetAsync(c->dflags, 0, sizeof(int) * std::max(c->nblk(), 1), s) == hipSuccess;
-  ok &= hipMemsetAsync(c->pflags, 0, sizeof(unsigned long long) * std::max(c->nblk(), 1), s) == hipSuccess;
   {
     pfd::Inst hi;
     std::memset(&hi, 0, sizeof hi);
@@ -655,12 +646,6 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     hi.ibus = c->ibus;
     hi.F = c->F;
     hi.x = c->x;
-    hi.lu = c->lu;
-    hi.dinv = c->dinv;
-    hi.tail = c->tail;
-    hi.dinvu = c->dinvu;
-    hi.dflags = c->dflags;
-    hi.pflags = c->pflags;
     hi.colptr = c->colptr;
     hi.rowidx = c->rowidx;
     hi.upd_l = c->upd_l;
@@ -717,6 +702,59 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   ctx->ncases++;
   *out = c;
   return PF_OK;
+}
+
+// Working storage of a solve: factor values (D | L | U blocks), the inverted
+// 2x2 diagonal blocks, the dense block with its right-hand side column, its
+// 64x64 diagonal-block inverses, and the dense block's two flag arrays.
+size_t work_bytes(const Case* c) {
+  return carve_size<double>(c->lu_count()) + carve_size<double>(4LL * c->an.ns) +
+         carve_size<double>(c->tail_count()) + carve_size<double>(c->dinvu_count()) + carve_size<int>(c->nblk()) +
+         carve_size<unsigned long long>(c->nblk());
+}
+
+void attach_work(Case* c, char* base, bool own, hipStream_t s) {
+  char* p = base;
+  c->lu = carve<double>(p, c->lu_count());
+  c->dinv = carve<double>(p, 4LL * c->an.ns);
+  c->tail = carve<double>(p, c->tail_count());
+  c->dinvu = carve<double>(p, c->dinvu_count());
+  c->dflags = carve<int>(p, c->nblk());
+  c->pflags = carve<unsigned long long>(p, c->nblk());
+  c->wbase = base;
+  c->wown = own;
+  pfd::Inst& h = c->hinst;
+  h.lu = c->lu;
+  h.dinv = c->dinv;
+  h.tail = c->tail;
+  h.dinvu = c->dinvu;
+  h.dflags = c->dflags;
+  h.pflags = c->pflags;
+  // the flags carry Newton-step epochs, which only grow within one case:
+  // storage that another case used starts from zero (below every epoch)
+  pfd::launch_zero_words(s, c->dflags, (int64_t)std::max(c->nblk(), 1));
+  pfd::launch_zero_words(s, c->pflags, 2LL * std::max(c->nblk(), 1));
+  pfd::launch_set_inst(s, c->d_inst, h);
+}
+
+bool ensure_work(Case* c) {
+  if (c->wbase) return true;
+  char* p = (char*)c->ctx->dalloc(c->wbytes);
+  if (!p) {
+    set_error("pf_solve: device allocation of the working storage failed");
+    return false;
+  }
+  attach_work(c, p, true, c->ctx->stream);
+  return true;
+}
+
+void detach_work(Case* c) {
+  if (c->wown && c->wbase) c->ctx->dfree(c->wbase);
+  c->wbase = nullptr;
+  c->wown = false;
+  c->lu = c->dinv = c->tail = c->dinvu = nullptr;
+  c->dflags = nullptr;
+  c->pflags = nullptr;
 }
 
 }  // namespace pfi
@@ -805,6 +843,7 @@ pf_status pf_destroy(pf_case* c) {
   delete c->single;
   c->single = nullptr;
   free_krylov(c);
+  if (c->wown) c->ctx->dfree(c->wbase);
   c->ctx->dfree(c->base);
   c->ctx->ncases--;
   delete c;
@@ -827,8 +866,20 @@ pf_status pf_case_info_get(const pf_case* c, pf_case_info* o) {
   o->updates = an.uptr.empty() ? 0 : an.uptr.back();
   o->tail_updates = an.tail_uptr.empty() ? 0 : an.tail_uptr.back();
   o->flops_factor = an.flops_sparse + an.flops_tail_schur + an.flops_dense;
-  o->device_bytes = c->bytes;
+  o->device_bytes = c->bytes + (c->wown ? c->wbytes : 0);
+  o->resident_bytes = c->bytes - (c->kown ? c->kbytes : 0);
+  o->work_bytes = c->wbytes;
+  o->krylov_bytes = krylov_bytes(c, 30);
   o->analysis_ms = c->analysis_ms;
+  return PF_OK;
+}
+
+pf_status pf_case_footprint(const pf_case* c, size_t* bytes) {
+  if (!c || !bytes) {
+    set_error("pf_case_footprint: NULL argument");
+    return PF_E_INVALID;
+  }
+  *bytes = (c->bytes - (c->kown ? c->kbytes : 0)) + c->wbytes;
   return PF_OK;
 }
 

@@ -79,6 +79,9 @@ struct Inst {
   int kchunks;   // vector chunks of KCH rows
   int knb;       // block-Jacobi blocks
   int knl, knul; // ILU(0) forward and backward levels
+  int kwide;     // some level is wider than one work-group pass: the ILU(0)
+                 // factor and sweeps run one launch per level, not in one
+                 // work-group
   const int *kp_of_r, *krow_ptr, *kcol, *kdiag, *kmap, *kup_ptr, *kup_t, *kup_s;
   // rows by forward / backward level: level pointers, and per position
   // {row, first, end, 0} of the row's lower (forward) or upper (backward)

@@ -37,12 +37,16 @@ struct PendingEvent {
 
 struct Ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // pf_solve, pf_solve_batch and set-up work
   bool own_stream = false;
   pf_alloc_fn alloc = nullptr;
   pf_free_fn freef = nullptr;
   void* user = nullptr;
   int profile_mask = 0;
+  // set (under launch_mu) while the serving loop launches on its own
+  // streams: no kernel timing there
+  bool prof_off = false;
+  int mask() const { return prof_off ? 0 : profile_mask; }
   pf_kernel_stat stats[PF_K_COUNT] = {};
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> evpool;
@@ -89,9 +93,17 @@ struct Case {
   int tailfwd_g = 1;
   std::vector<double> fac_flops, fac_bytes;
 
-  // one device allocation, carved into the arrays below
+  // one device allocation, carved into the arrays below (topology, index
+  // lists, set-points and state: resident from pf_create to pf_destroy)
   char* base = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // resident bytes, plus the Krylov storage the case owns
+  // working storage of a solve (factor values, the dense block with its
+  // inverses, and their flags): the case's own, allocated by its first
+  // pf_solve / pf_solve_batch and kept, or lent by the serving loop for one
+  // request (wbase null between requests)
+  char* wbase = nullptr;
+  bool wown = false;
+  size_t wbytes = 0;
 
   int *row_ptr = nullptr, *col = nullptr, *yrow = nullptr, *jmap = nullptr;
   double* y = nullptr;
@@ -123,7 +135,9 @@ struct Case {
   std::vector<int> kmap_host;  // Ybus entry -> Krylov block position
   char* kbase = nullptr;
   size_t kbytes = 0;
-  int km = 0;  // restart length the storage holds
+  bool kown = false;  // false: lent by the serving loop for one request
+  int km = 0;         // restart length the storage holds
+  std::vector<int4> k_linfo, k_uinfo;  // per level position {row, first, end, 0}
 
   int64_t lu_count() const { return 4LL * (an.ns + 2 * an.nnzl); }
   int64_t tail_count() const { return (int64_t)an.ldt * (M + 1); }
@@ -149,6 +163,7 @@ enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_TRSV, L_BWD };
 // depends only on its own instance.
 struct Batch {
   Ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;  // where the batch's work is launched (set by build: the context's)
   std::vector<Case*> cases;
   int nslots = 0;
   char* dmem = nullptr;  // instance pointer table, work items
@@ -189,7 +204,8 @@ struct Batch {
   std::pair<int64_t, int> k_blocks{0, 0};
   int max_kchunks = 0;
   int k_max_nu = 0;
-  bool k_wide = false;  // some ILU(0) level is wider than one work-group pass
+  bool k_wide = false;    // some instance has an ILU(0) level wider than one work-group pass
+  bool k_narrow = false;  // some instance runs its ILU(0) in one work-group
 
   ~Batch();
   bool build(Ctx* ctx, const std::vector<Case*>& cs);
@@ -212,6 +228,21 @@ struct Prof {
 // when m grows); false on failure with the error set.
 bool ensure_krylov(Case* c, int m);
 void free_krylov(Case* c);
+// Bytes of the Krylov storage for restart length m, and its set-up in the
+// given memory (own: the case frees it; else lent, and dropped by
+// detach_krylov), launched on stream s (no synchronisation).
+size_t krylov_bytes(const Case* c, int m);
+bool krylov_wide(const pfh::KAnalysis& ka);
+bool attach_krylov(Case* c, int m, char* base, bool own, hipStream_t s);
+void detach_krylov(Case* c);
+// Working storage of a solve: its size, its set-up in the given memory on
+// stream s (pointers in the device descriptor, flags cleared; no
+// synchronisation), the case's own allocation when it has none, and the
+// release of lent storage.
+size_t work_bytes(const Case* c);
+void attach_work(Case* c, char* base, bool own, hipStream_t s);
+bool ensure_work(Case* c);
+void detach_work(Case* c);
 // Case creation under a schedule (api.cpp), the schedule's validation and
 // the topology hash that keys the autotuner's choices.
 pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched, Case** out);

@@ -146,6 +146,19 @@ __global__ void k_decide(const Inst* const* insts, int nslots, DevOpts o) {
   r.step_bits = 0ull;
 }
 
+// Store a descriptor passed by value (the launch captures it, so the host
+// copy may change as soon as the launch is queued).
+__global__ void k_set_inst(Inst* dst, Inst src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = src;
+}
+
+// Zero `words` 32-bit words with vector stores (flags and counters; a fill
+// kernel rather than a memset node, so that it is safe inside captured graphs).
+__global__ void k_zero_words(unsigned* p, int64_t words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) p[i] = 0u;
+}
+
 // copy every instance's state into one contiguous array for the host
 __global__ void k_gather_red(const Inst* const* insts, int nslots, Red* out) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -823,6 +836,13 @@ static inline dim3 grid2(int64_t count, int nslots, int block = 256, int64_t cap
   if (gx < 1) gx = 1;
   if (gx > cap) gx = cap;
   return dim3((unsigned)gx, (unsigned)nslots);
+}
+
+void launch_set_inst(hipStream_t st, Inst* dst, const Inst& src) { k_set_inst<<<1, 64, 0, st>>>(dst, src); }
+
+void launch_zero_words(hipStream_t st, void* p, int64_t words) {
+  if (words <= 0) return;
+  k_zero_words<<<dim3((unsigned)((words + 255) / 256)), 256, 0, st>>>((unsigned*)p, words);
 }
 
 void launch_init(hipStream_t st, const Inst* const* insts, int nslots, int max_n, int flat) {

@@ -9,6 +9,10 @@
 
 namespace pfd {
 
+// descriptor upload (by value, stream-ordered) and a zero fill of 32-bit words
+void launch_set_inst(hipStream_t, Inst* dst, const Inst& src);
+void launch_zero_words(hipStream_t, void* p, int64_t words);
+
 // Newton driver
 void launch_init(hipStream_t, const Inst* const* insts, int nslots, int max_n, int flat);
 void launch_start(hipStream_t, const Inst* const* insts, int nslots);

@@ -157,6 +157,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ double A[64][129];
   __shared__ double colk[64];
+  __shared__ double rowk[128];
   __shared__ int piv;
   __shared__ int bad;
   const int2 wk = work[blockIdx.x];
@@ -216,8 +217,11 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
       A[p][tid] = t;
     }
     __syncthreads();
-    // the pivot column, read before any thread writes its own column
+    // the pivot column and the pivot row, read before any thread writes:
+    // both threads of a column scale the pivot row's entry from the staged
+    // copy, so the one that stores it cannot race the other's read
     if (tid < N) colk[tid] = A[tid][k];
+    if (tid < 128) rowk[tid] = A[k][tid];
     __syncthreads();
     // thread (c, h) owns column c of [A | I] and the rows i = h mod 2: the
     // pivot row is scaled by 1/A[k][k] and every other row loses
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
       const int c = tid & 127, h = tid >> 7;
       if (c >= k) {
         const double ip = 1.0 / colk[k];
-        const double akc = A[k][c] * ip;
+        const double akc = rowk[c] * ip;
         for (int i = h; i < N; i += 2)
           if (i != k) A[i][c] -= colk[i] * akc;
         if (h == 0) A[k][c] = akc;
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const
 template <typename T>
 __global__ __launch_bounds__(1024) void k_ilu_factor_wg(const Inst* const* insts) {
   const auto& I = *gp(insts[blockIdx.x]);
-  if (!gp(I.red)->active) return;
+  if (!gp(I.red)->active || I.kwide) return;
   auto P = gp((T*)I.pval);
   auto D = gp((T*)I.pdinv);
   const auto kl_ptr = gp(I.kl_ptr), kcol = gp(I.kcol), kup_ptr = gp(I.kup_ptr), kup_t = gp(I.kup_t),
@@ -405,7 +409,7 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
   __shared__ int lpf[LPM + 1], lpb[LPM + 1];
   const auto& I = *gp(insts[blockIdx.x]);
   const auto ks = gp(I.ks);
-  if (!gp(I.red)->active || ks->state != (apply_state(mode))) return;
+  if (!gp(I.red)->active || I.kwide || ks->state != (apply_state(mode))) return;
   const int nu = I.nu;
   if (2 * nu <= zmin || (ZV > 0 && 2 * nu > ZV)) return;
   T* z = ZV > 0 ? zl : (T*)I.kz;

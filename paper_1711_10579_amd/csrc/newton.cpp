@@ -25,7 +25,7 @@ constexpr int NB = 64;
 Batch::~Batch() {
   if (ctx) {
     // the graphs' timing events may still be queued for reading
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(stream);
     ctx->prof_flush();
     if (dmem) ctx->dfree(dmem);
     if (kmem) ctx->dfree(kmem);
@@ -46,6 +46,7 @@ void Batch::Graph::reset() {
 
 bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   ctx = cx;
+  stream = cx->stream;
   cases = cs;
   nslots = (int)cs.size();
   std::vector<int2> work;
@@ -116,29 +117,25 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   }
   // forward rows of the dense block, then the Schur complement into it
   {
-    std::map<int, std::vector<int2>> byG;
-    std::vector<int2> schur;
-    double sfl = 0, sby = 0, nupd_all = 0, ntt_all = 0;
-    for (Case* c : cs) {
-      nupd_all += (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
-      ntt_all += c->ntt;
-    }
-    // lanes per Schur target from the batch's mean update-list length
-    int gs = 1;
-    while (gs < 32 && 4.0 * gs * ntt_all < nupd_all) gs *= 2;
-    const int per_wg = 256 / gs;
+    std::map<int, std::vector<int2>> byG, schur;
+    std::map<int, double> sfl, sby;
     for (int s = 0; s < nslots; ++s) {
       Case* c = cs[s];
       if (c->an.nt == 0) continue;
       auto& v = byG[c->tailfwd_g];
       for (int i = c->an.ns; i < c->an.nu; ++i) v.push_back(make_int2(s, i));
-      for (int t = 0; t < c->ntt; t += per_wg) schur.push_back(make_int2(s, t));
-      double nupd = (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
-      sfl += 16.0 * nupd;
-      sby += 8.0 * nupd + 64.0 * nupd + 64.0 * c->ntt;
+      // lanes per Schur target from the case's own mean update-list length
+      // (they set the summation order, so they must not depend on the batch)
+      const double nupd = (double)(c->an.tail_uptr.empty() ? 0 : c->an.tail_uptr.back());
+      int gs = 1;
+      while (gs < 32 && 4.0 * gs * c->ntt < nupd) gs *= 2;
+      const int per_wg = 256 / gs;
+      for (int t = 0; t < c->ntt; t += per_wg) schur[gs].push_back(make_int2(s, t));
+      sfl[gs] += 16.0 * nupd;
+      sby[gs] += 8.0 * nupd + 64.0 * nupd + 64.0 * c->ntt;
     }
     for (auto& kv : byG) emit(L_FWD, PF_K_SPARSE_FWD, kv.first, 0, kv.second, 0, 0);
-    emit(L_SCHUR, PF_K_TAIL_SCHUR, gs, 0, schur, sfl, sby);
+    for (auto& kv : schur) emit(L_SCHUR, PF_K_TAIL_SCHUR, kv.first, 0, kv.second, sfl[kv.first], sby[kv.first]);
   }
   // dense block, per 64-wide step k0: one launch with the panel of step k0
   // (which also applies step k0's update to the next block column) and the
@@ -239,7 +236,7 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   }
   std::vector<const pfd::Inst*> tab(nslots);
   for (int s = 0; s < nslots; ++s) tab[s] = cs[s]->d_inst;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = stream;
   bool ok = hipMemcpyAsync((void*)d_insts, tab.data(), sizeof(void*) * nslots, hipMemcpyHostToDevice, st) == hipSuccess;
   if (!work.empty())
     ok &= hipMemcpyAsync(d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
@@ -252,7 +249,7 @@ namespace {
 template <typename T>
 void lu_solve(Batch* b) {
   Ctx* ctx = b->ctx;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = b->stream;
   const auto* I = b->d_insts;
   {
     Prof p(ctx, PF_K_JFILL, 0.0, 0.0);
@@ -284,11 +281,11 @@ void lu_solve(Batch* b) {
         break;
     }
   };
-  const bool spans = (ctx->profile_mask & PF_PROFILE_SPANS) != 0;
+  const bool spans = (ctx->mask() & PF_PROFILE_SPANS) != 0;
   for (size_t i = 0; i < b->seq.size();) {
     const int cls = b->seq[i].cls;
     size_t j = i + 1;
-    if (spans && (ctx->profile_mask & (1 << cls)))
+    if (spans && (ctx->mask() & (1 << cls)))
       while (j < b->seq.size() && b->seq[j].cls == cls) ++j;
     // one event pair around launches i..j-1 (one launch unless spans are on)
     hipEvent_t ev;
@@ -349,6 +346,8 @@ static pfd::DevOpts dev_opts(const pf_options* opt) {
 pf_status start_batch(Batch* b, const pf_options* opt) {
   pf_status st = check_opts(opt);
   if (st != PF_OK) return st;
+  for (Case* c : b->cases)
+    if (!ensure_work(c)) return PF_E_NOMEM;
   if (opt->solver != PF_SOLVER_LU) {
     for (Case* c : b->cases)
       if (!ensure_krylov(c, opt->gmres_m)) return PF_E_NOMEM;
@@ -357,7 +356,7 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
       return PF_E_NOMEM;
     }
   }
-  hipStream_t s = b->ctx->stream;
+  hipStream_t s = b->stream;
   pfd::launch_init(s, b->d_insts, b->nslots, b->max_n, opt->flat_start ? 1 : 0);
   pfd::launch_start(s, b->d_insts, b->nslots);
   {
@@ -371,7 +370,7 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
 // One Newton step of every active instance: linear solve, update, mismatch
 // and the convergence test.
 static void enqueue_lu_step(Batch* b, const pf_options* opt) {
-  hipStream_t s = b->ctx->stream;
+  hipStream_t s = b->stream;
   if (opt->precision == PF_PREC_MIXED)
     lu_solve<float>(b);
   else
@@ -388,10 +387,10 @@ static void enqueue_lu_step(Batch* b, const pf_options* opt) {
 // replayed; each replay queues the graph's event pairs for reading.
 static bool graph_step(Batch* b, const pf_options* opt) {
   Ctx* ctx = b->ctx;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = b->stream;
   if (!b->allow_graph || b->graph_failed || !ctx->use_graphs || s == nullptr) return false;
   Batch::Graph& g = b->graphs[opt->precision == PF_PREC_MIXED ? 1 : 0];
-  if (g.exec && (g.tol != opt->tol || g.max_iter != opt->max_iter || g.prof_mask != ctx->profile_mask)) {
+  if (g.exec && (g.tol != opt->tol || g.max_iter != opt->max_iter || g.prof_mask != ctx->mask())) {
     if (!ctx->pending.empty()) {
       (void)hipStreamSynchronize(s);
       ctx->prof_flush();
@@ -402,7 +401,7 @@ static bool graph_step(Batch* b, const pf_options* opt) {
     // timing events for the graph, made before the capture (two per timed
     // launch at most)
     ctx->cap_pool.clear();
-    if (ctx->profile_mask != 0)
+    if (ctx->mask() != 0)
       for (size_t i = 0; i < 2 * (b->seq.size() + 8); ++i) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) break;
@@ -438,7 +437,7 @@ static bool graph_step(Batch* b, const pf_options* opt) {
     }
     g.tol = opt->tol;
     g.max_iter = opt->max_iter;
-    g.prof_mask = ctx->profile_mask;
+    g.prof_mask = ctx->mask();
   }
   if (hipGraphLaunch(g.exec, s) != hipSuccess) return false;
   for (const auto& p : g.prof) ctx->pending.push_back(p);
@@ -451,9 +450,9 @@ pf_status step_batch(Batch* b, const pf_options* opt) {
     if (st != PF_OK) return st;
     {
       Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
-      pfd::launch_mismatch(b->ctx->stream, b->d_insts, b->nslots, b->max_n);
+      pfd::launch_mismatch(b->stream, b->d_insts, b->nslots, b->max_n);
     }
-    pfd::launch_decide(b->ctx->stream, b->d_insts, b->nslots, dev_opts(opt));
+    pfd::launch_decide(b->stream, b->d_insts, b->nslots, dev_opts(opt));
   } else if (!graph_step(b, opt)) {
     enqueue_lu_step(b, opt);
   }
@@ -462,7 +461,7 @@ pf_status step_batch(Batch* b, const pf_options* opt) {
 
 // Copy every instance's state to the host (synchronises the stream).
 pf_status read_batch(Batch* b, std::vector<pfd::Red>* h) {
-  hipStream_t s = b->ctx->stream;
+  hipStream_t s = b->stream;
   h->resize(b->nslots);
   // the gather writes straight into pinned host memory
   pfd::launch_gather_red(s, b->d_insts, b->nslots, b->h_reds);
@@ -482,7 +481,7 @@ pf_status read_batch(Batch* b, std::vector<pfd::Red>* h) {
 
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   Ctx* ctx = b->ctx;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = b->stream;
   const int B = b->nslots;
   for (int i = 0; i < B; ++i) std::memset(&results[i], 0, sizeof(pf_result));
   if (B == 0) return PF_OK;

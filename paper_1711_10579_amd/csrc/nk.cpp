@@ -34,36 +34,48 @@ T* carve(char*& p, int64_t count) {
 }  // namespace
 
 void free_krylov(Case* c) {
-  if (c->kbase) {
+  if (c->kbase && c->kown) {
     c->ctx->dfree(c->kbase);
     c->bytes -= c->kbytes;
+  }
+  c->kbase = nullptr;
+  c->kbytes = 0;
+  c->kown = false;
+  c->km = 0;
+}
+
+void detach_krylov(Case* c) {
+  if (c->kbase && !c->kown) {
     c->kbase = nullptr;
     c->kbytes = 0;
     c->km = 0;
   }
 }
 
-bool ensure_krylov(Case* c, int m) {
-  if (c->kbase && c->km >= m) return true;
-  if (!c->ka) {
-    set_error("pf_solve: the case has no Krylov analysis");
-    return false;
-  }
-  Ctx* ctx = c->ctx;
+namespace {
+
+int krylov_m(int m) { return std::max(m, 30); }
+
+}  // namespace
+
+bool krylov_wide(const pfh::KAnalysis& ka) {
+  for (size_t l = 0; l + 1 < ka.lev_ptr.size(); ++l)
+    if (ka.lev_ptr[l + 1] - ka.lev_ptr[l] > 4096) return true;
+  for (size_t l = 0; l + 1 < ka.ulev_ptr.size(); ++l)
+    if (ka.ulev_ptr[l + 1] - ka.ulev_ptr[l] > 4096) return true;
+  return false;
+}
+
+size_t krylov_bytes(const Case* c, int m) {
+  if (!c->ka) return 0;
   const pfh::KAnalysis& ka = *c->ka;
-  const int km = std::max(m, 30);
+  const int km = krylov_m(m);
   const int nu = ka.nu;
   const int64_t knnz = ka.nnz(), nup = ka.nup();
   const int nb = ka.nblocks();
   const int kchunks = (nu + pfd::KCH - 1) / pfd::KCH;
   const int64_t n2 = 2LL * nu;
   const int64_t nh = (int64_t)(km + 1) * km + 2LL * km + (km + 1) + km;
-  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
-    set_error("pf_solve: device failure before the Krylov set-up");
-    return false;
-  }
-  free_krylov(c);
-
   const int nl = (int)ka.lev_ptr.size() - 1, nul = (int)ka.ulev_ptr.size() - 1;
   size_t total = carve_bytes<int>(nu) + carve_bytes<int>(nu + 1) + carve_bytes<int>(knnz) + carve_bytes<int>(nu) +
                  carve_bytes<int>(c->nnz) + carve_bytes<int>(knnz + 1) + 2 * carve_bytes<int>(nup) +
@@ -73,11 +85,21 @@ bool ensure_krylov(Case* c, int m) {
            carve_bytes<double>((km + 1) * n2) + 3 * carve_bytes<double>(n2);
   total += carve_bytes<double>(nh) + carve_bytes<double>(3LL * std::max(kchunks, 1) * (km + 1)) +
            carve_bytes<pfd::KState>(1);
-  char* base = (char*)ctx->dalloc(total);
-  if (!base) {
-    set_error("pf_solve: device allocation of the Krylov storage failed");
-    return false;
-  }
+  return total;
+}
+
+bool attach_krylov(Case* c, int m, char* base, bool own, hipStream_t s) {
+  if (c->kbase && c->kown && !own) free_krylov(c);  // too small for this request: replaced by the lent storage
+  const pfh::KAnalysis& ka = *c->ka;
+  const int km = krylov_m(m);
+  const int nu = ka.nu;
+  const int64_t knnz = ka.nnz(), nup = ka.nup();
+  const int nb = ka.nblocks();
+  const int kchunks = (nu + pfd::KCH - 1) / pfd::KCH;
+  const int64_t n2 = 2LL * nu;
+  const int64_t nh = (int64_t)(km + 1) * km + 2LL * km + (km + 1) + km;
+  const int nl = (int)ka.lev_ptr.size() - 1, nul = (int)ka.ulev_ptr.size() - 1;
+  const size_t total = krylov_bytes(c, m);
   char* p = base;
   pfd::Inst& h = c->hinst;
   int* kp_of_r = carve<int>(p, nu);
@@ -108,7 +130,6 @@ bool ensure_krylov(Case* c, int m) {
   h.kpart = carve<double>(p, 3LL * std::max(kchunks, 1) * (km + 1));
   h.ks = carve<pfd::KState>(p, 1);
   if ((size_t)(p - base) != total) {
-    ctx->dfree(base);
     set_error("pf_solve: internal Krylov layout error");
     return false;
   }
@@ -129,12 +150,23 @@ bool ensure_krylov(Case* c, int m) {
   h.bj_off = bj_off;
   h.knl = nl;
   h.knul = nul;
+  h.kwide = krylov_wide(ka) ? 1 : 0;
   h.kl_ptr = kl_ptr;
   h.kl_info = kl_info;
   h.ku_ptr = ku_ptr;
   h.ku_info = ku_info;
 
-  hipStream_t s = ctx->stream;
+  // the sources stay alive with the case (the copies are asynchronous)
+  if (c->k_linfo.empty() && nu > 0) {
+    c->k_linfo.resize(nu);
+    c->k_uinfo.resize(nu);
+    for (int k = 0; k < nu; ++k) {
+      const int r = ka.lev_rows[k];
+      c->k_linfo[k] = make_int4(r, ka.row_ptr[r], ka.diag[r], 0);
+      const int u = ka.ulev_rows[k];
+      c->k_uinfo[k] = make_int4(u, ka.diag[u] + 1, ka.row_ptr[u + 1], 0);
+    }
+  }
   bool ok = true;
   auto up = [&](void* dst, const void* src, size_t bytes) {
     if (bytes) ok &= hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -153,27 +185,53 @@ bool ensure_krylov(Case* c, int m) {
   up(bj_off, ka.bj_off.data(), sizeof(int64_t) * (nb + 1));
   up(kl_ptr, ka.lev_ptr.data(), sizeof(int) * (nl + 1));
   up(ku_ptr, ka.ulev_ptr.data(), sizeof(int) * (nul + 1));
-  std::vector<int4> linfo(nu), uinfo(nu);
-  for (int k = 0; k < nu; ++k) {
-    const int r = ka.lev_rows[k];
-    linfo[k] = make_int4(r, ka.row_ptr[r], ka.diag[r], 0);
-    const int u = ka.ulev_rows[k];
-    uinfo[k] = make_int4(u, ka.diag[u] + 1, ka.row_ptr[u + 1], 0);
-  }
-  up(kl_info, linfo.data(), sizeof(int4) * nu);
-  up(ku_info, uinfo.data(), sizeof(int4) * nu);
-  ok &= hipMemsetAsync(h.ks, 0, sizeof(pfd::KState), s) == hipSuccess;
-  up(c->d_inst, &h, sizeof h);
-  ok &= hipStreamSynchronize(s) == hipSuccess;
-  if (!ok) {
-    ctx->dfree(base);
+  up(kl_info, c->k_linfo.data(), sizeof(int4) * nu);
+  up(ku_info, c->k_uinfo.data(), sizeof(int4) * nu);
+  static_assert(sizeof(pfd::KState) % 4 == 0, "KState is cleared as 32-bit words");
+  pfd::launch_zero_words(s, h.ks, (int64_t)(sizeof(pfd::KState) / 4));
+  pfd::launch_set_inst(s, c->d_inst, h);
+  if (!ok || hipGetLastError() != hipSuccess) {
     set_error("pf_solve: upload of the Krylov storage failed");
     return false;
   }
   c->kbase = base;
   c->kbytes = total;
+  c->kown = own;
   c->km = km;
-  c->bytes += total;
+  if (own) c->bytes += total;
+  return true;
+}
+
+bool ensure_krylov(Case* c, int m) {
+  if (c->kbase && c->km >= m) return true;
+  if (!c->ka) {
+    set_error("pf_solve: the case has no Krylov analysis");
+    return false;
+  }
+  Ctx* ctx = c->ctx;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    set_error("pf_solve: device failure before the Krylov set-up");
+    return false;
+  }
+  if (c->kbase && !c->kown) {
+    set_error("pf_solve: lent Krylov storage is too small");
+    return false;
+  }
+  free_krylov(c);
+  const size_t total = krylov_bytes(c, m);
+  char* base = (char*)ctx->dalloc(total);
+  if (!base) {
+    set_error("pf_solve: device allocation of the Krylov storage failed");
+    return false;
+  }
+  if (!attach_krylov(c, m, base, true, ctx->stream) || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->dfree(base);
+    c->kbase = nullptr;
+    c->kbytes = 0;
+    c->km = 0;
+    set_error("pf_solve: set-up of the Krylov storage failed");
+    return false;
+  }
   return true;
 }
 
@@ -184,21 +242,30 @@ bool Batch::build_krylov() {
   max_kchunks = 0;
   size_t max_l = 0, max_u = 0;
   k_max_nu = 0;
-  k_wide = false;
-  for (Case* c : cases) {
-    if (!c->ka || !c->kbase) return false;
+  k_wide = k_narrow = false;
+  // each instance takes its own path (one work-group, or one launch per
+  // level when some level is too wide), whatever the batch holds
+  std::vector<char> wide(nslots, 0);
+  for (int s = 0; s < nslots; ++s) {
+    Case* c = cases[s];
+    if (!c->ka) return false;
     const pfh::KAnalysis& ka = *c->ka;
-    max_l = std::max(max_l, ka.lev_ptr.size() - 1);
-    max_u = std::max(max_u, ka.ulev_ptr.size() - 1);
-    max_kchunks = std::max(max_kchunks, c->hinst.kchunks);
-    k_max_nu = std::max(k_max_nu, ka.nu);
-    for (size_t l = 0; l + 1 < ka.lev_ptr.size(); ++l) k_wide |= ka.lev_ptr[l + 1] - ka.lev_ptr[l] > 4096;
-    for (size_t l = 0; l + 1 < ka.ulev_ptr.size(); ++l) k_wide |= ka.ulev_ptr[l + 1] - ka.ulev_ptr[l] > 4096;
+    max_kchunks = std::max(max_kchunks, (ka.nu + pfd::KCH - 1) / pfd::KCH);
+    wide[s] = krylov_wide(ka);
+    if (wide[s]) {
+      k_wide = true;
+      max_l = std::max(max_l, ka.lev_ptr.size() - 1);
+      max_u = std::max(max_u, ka.ulev_ptr.size() - 1);
+    } else {
+      k_narrow = true;
+      k_max_nu = std::max(k_max_nu, ka.nu);
+    }
   }
   auto levels = [&](bool upper, size_t nl, std::vector<std::pair<int64_t, int>>* out) {
     for (size_t l = 0; l < nl; ++l) {
       const int64_t off = (int64_t)work.size();
       for (int s = 0; s < nslots; ++s) {
+        if (!wide[s]) continue;
         const pfh::KAnalysis& ka = *cases[s]->ka;
         const auto& ptr = upper ? ka.ulev_ptr : ka.lev_ptr;
         const auto& rows = upper ? ka.ulev_rows : ka.lev_rows;
@@ -221,7 +288,7 @@ bool Batch::build_krylov() {
   kmem = (char*)ctx->dalloc(bw);
   if (!kmem) return false;
   d_kwork = (int2*)kmem;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = stream;
   bool ok = true;
   if (!work.empty())
     ok &= hipMemcpyAsync(d_kwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
@@ -235,7 +302,7 @@ namespace {
 template <typename T>
 pf_status nk_step_t(Batch* b, const pf_options* opt) {
   Ctx* ctx = b->ctx;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = b->stream;
   const auto* I = b->d_insts;
   for (Case* c : b->cases)
     if (!ensure_krylov(c, opt->gmres_m)) return PF_E_NOMEM;
@@ -257,12 +324,12 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   }
   {
     Prof p(ctx, PF_K_PRECOND_SETUP, 0.0, 0.0);
-    if (ilu && !b->k_wide)
-      pfd::launch_ilu_factor_wg<T>(s, I, ns);
-    else if (ilu)
+    if (ilu) {
+      if (b->k_narrow) pfd::launch_ilu_factor_wg<T>(s, I, ns);
       for (const auto& l : b->k_lev) pfd::launch_ilu_rows<T>(s, I, kw + l.first, l.second);
-    else
+    } else {
       pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second);
+    }
   }
   const bool bcg = opt->solver == PF_SOLVER_BICGSTAB;
   {
@@ -275,9 +342,8 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   }
   auto apply = [&](int mode) {
     Prof p(ctx, PF_K_PRECOND_APPLY, 0.0, 0.0);
-    if (ilu && !b->k_wide) {
-      pfd::launch_ilu_apply_wg<T>(s, I, ns, mode, b->k_max_nu);
-    } else if (ilu) {
+    if (ilu) {
+      if (b->k_narrow) pfd::launch_ilu_apply_wg<T>(s, I, ns, mode, b->k_max_nu);
       for (const auto& l : b->k_lev) pfd::launch_ilu_fwd<T>(s, I, kw + l.first, l.second, mode);
       for (const auto& l : b->k_ulev) pfd::launch_ilu_bwd<T>(s, I, kw + l.first, l.second, mode);
     } else {

@@ -213,3 +213,17 @@ def test_polar_rejects_delta_loads():
     with pytest.raises(B.PFError) as ei:
         B.pf_debug_schedule_check(**args)
     assert ei.value.code == B.PF_E_INVALID
+
+
+def test_footprint_and_debug_calls_reject_null():
+    import ctypes
+
+    b = ctypes.c_size_t()
+    assert B._lib.pf_case_footprint(None, ctypes.byref(b)) == B.PF_E_INVALID
+    d = ctypes.c_double()
+    o = ctypes.c_int32()
+    assert B._lib.pf_debug_precond_check(None, 0, ctypes.byref(d), ctypes.byref(o)) == B.PF_E_INVALID
+    s1, s2 = ctypes.c_size_t(), ctypes.c_size_t()
+    q, r = ctypes.c_int32(), ctypes.c_int32()
+    assert B._lib.pf_serve_stats(None, ctypes.byref(s1), ctypes.byref(s2), ctypes.byref(q),
+                                 ctypes.byref(r)) == B.PF_E_INVALID
