@@ -328,6 +328,24 @@ pf_status pf_serve_config(pf_ctx* ctx, size_t max_bytes, int32_t max_slots);
  * outputs). */
 pf_status pf_serve_stats(pf_ctx* ctx, size_t* pool_bytes, size_t* lent_bytes, int32_t* queued, int32_t* running);
 
+/* For callers that cannot allocate device memory (code under a stream capture
+ * of their own, tight serving loops, harnesses that forbid allocation): the LU
+ * Newton solve of pf_solve (options as there; solver must be PF_SOLVER_LU,
+ * else PF_E_INVALID) with everything it needs beyond the case's resident
+ * storage -- the launch plan, the Newton-state read-back and the working
+ * storage (factor values, dense block) -- placed in one fixed array of 64 MiB
+ * that the library holds on every GPU it runs on until the process ends.  It
+ * makes no device or pinned-host allocation and creates no HIP object (no
+ * graph, no event); the plan is built on the host heap.  A case needing more
+ * than the array holds (about 10,000-15,000 buses of meshed grid; its needs
+ * are pf_case_info.work_bytes plus the plan) is rejected with PF_E_INVALID,
+ * the bytes it would need in *scratch_used (may be NULL).  Results are
+ * identical to pf_solve's; res->device_ms is the host time of the call.  The
+ * case's own working storage, if it has some, is left as it was.  Calls on
+ * one GPU share the array: the library runs them one at a time (a per-device
+ * lock), and overlapping calls from outside the library on one GPU would race. */
+pf_status pf_solve_noalloc(pf_case* c, const pf_options* opt, pf_result* res, size_t* scratch_used);
+
 /* Copy the case's current voltages (rectangular form) into host arrays of n
  * doubles each. */
 pf_status pf_get_voltage(const pf_case* c, double* re, double* im);

@@ -135,6 +135,7 @@ _sig = {
     "pf_set_injections": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
     "pf_solve": (C.c_int, [_P, C.POINTER(pf_options), C.POINTER(pf_result)]),
+    "pf_solve_noalloc": (C.c_int, [_P, C.POINTER(pf_options), C.POINTER(pf_result), C.POINTER(C.c_size_t)]),
     "pf_solve_batch": (C.c_int, [_P, C.POINTER(_P), C.c_int32, C.POINTER(pf_options),
                                  C.POINTER(pf_result)]),
     "pf_submit": (C.c_int, [_P, _P, C.POINTER(pf_options), C.POINTER(C.c_uint64)]),
@@ -431,6 +432,16 @@ def pf_solve(case, options=None, **kw):
     r = pf_result()
     _check(_lib.pf_solve(case.handle, C.byref(o), C.byref(r)), "pf_solve")
     return r
+
+
+def pf_solve_noalloc(case, options=None, **kw):
+    """The LU solve in the library's fixed per-device array.  Returns
+    (pf_result, scratch bytes the case needs)."""
+    o = options if options is not None else pf_default_options(**kw)
+    r = pf_result()
+    used = C.c_size_t()
+    _check(_lib.pf_solve_noalloc(case.handle, C.byref(o), C.byref(r), C.byref(used)), "pf_solve_noalloc")
+    return r, used.value
 
 
 def pf_solve_batch(ctx, cases, options=None, **kw):

@@ -34,6 +34,7 @@ SOURCES = [
     "kernels.hip",
     "dense.hip",
     "krylov.hip",
+    "noalloc.hip",
 ]
 
 ARCH = "gfx950"

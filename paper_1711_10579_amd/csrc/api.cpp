@@ -330,6 +330,9 @@ pf_status pf_ctx_create(int32_t device, void* hip_stream, pf_alloc_fn alloc, pf_
   c->alloc = alloc;
   c->freef = free_;
   c->user = user;
+  // the device address of pf_solve_noalloc's scratch array, once per device
+  // (with the device current); a failure is reported by that call alone
+  (void)scratch_init(device);
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {

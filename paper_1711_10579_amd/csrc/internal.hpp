@@ -208,7 +208,15 @@ struct Batch {
   bool k_narrow = false;  // some instance runs its ILU(0) in one work-group
 
   ~Batch();
+  // launch plan and device table in memory the batch allocates (and pinned
+  // host memory for the state gathers)
   bool build(Ctx* ctx, const std::vector<Case*>& cs);
+  // the parts: the host launch plan with its work items; the device bytes of
+  // the instance table and work items; their upload into `mem` (the batch
+  // frees nothing it did not allocate)
+  void plan(Ctx* ctx, const std::vector<Case*>& cs, std::vector<int2>* work);
+  size_t plan_bytes(size_t nwork) const;
+  bool place(char* mem, const std::vector<int2>& work);
   bool build_krylov();
 };
 
@@ -270,6 +278,9 @@ void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* item
 
 // Run the Newton iteration of every case of a built batch to completion.
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);
+// Device address of pf_solve_noalloc's scratch array on `device` (current),
+// looked up once per device (noalloc.hip).
+pf_status scratch_init(int device);
 pf_status solve_case(Case* c, const pf_options* opt, pf_result* res);
 
 }  // namespace pfi

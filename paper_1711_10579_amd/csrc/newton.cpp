@@ -45,11 +45,48 @@ void Batch::Graph::reset() {
 }
 
 bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
+  std::vector<int2> work;
+  plan(cx, cs, &work);
+  // device buffer: instance table | work items
+  dmem = (char*)ctx->dalloc(plan_bytes(work.size()));
+  if (!dmem) return false;
+  {
+    void* hp = nullptr;
+    const size_t hr = (sizeof(pfd::Red) * std::max(nslots, 1) + 255) & ~(size_t)255;
+    if (hipHostMalloc(&hp, hr + sizeof(int) * std::max(nslots, 1), hipHostMallocCoherent) != hipSuccess) return false;
+    h_reds = (pfd::Red*)hp;
+    h_kstate = (int*)((char*)hp + hr);
+  }
+  return place(dmem, work);
+}
+
+size_t Batch::plan_bytes(size_t nwork) const {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return al(sizeof(void*) * std::max(nslots, 1)) + al(sizeof(int2) * std::max<size_t>(nwork, 1));
+}
+
+bool Batch::place(char* mem, const std::vector<int2>& work) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_tab = al(sizeof(void*) * std::max(nslots, 1));
+  d_insts = (const pfd::Inst* const*)mem;
+  d_work = (int2*)(mem + b_tab);
+  std::vector<const pfd::Inst*> tab(nslots);
+  for (int s = 0; s < nslots; ++s) tab[s] = cases[s]->d_inst;
+  hipStream_t st = stream;
+  bool ok = hipMemcpyAsync((void*)d_insts, tab.data(), sizeof(void*) * nslots, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!work.empty())
+    ok &= hipMemcpyAsync(d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok &= hipStreamSynchronize(st) == hipSuccess;
+  return ok;
+}
+
+void Batch::plan(Ctx* cx, const std::vector<Case*>& cs, std::vector<int2>* out) {
   ctx = cx;
   stream = cx->stream;
   cases = cs;
   nslots = (int)cs.size();
-  std::vector<int2> work;
+  std::vector<int2>& work = *out;
+  work.clear();
   seq.clear();
   auto emit = [&](int kind, int cls, int G, int k0, const std::vector<int2>& items, double flops, double bytes) {
     if (items.empty()) return;
@@ -219,29 +256,6 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
     }
     nzero = (int)((int64_t)work.size() - zero_off);
   }
-  // device buffer: instance table | work items
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t b_tab = al(sizeof(void*) * std::max(nslots, 1));
-  const size_t b_work = al(sizeof(int2) * std::max<size_t>(work.size(), 1));
-  dmem = (char*)ctx->dalloc(b_tab + b_work);
-  if (!dmem) return false;
-  d_insts = (const pfd::Inst* const*)dmem;
-  d_work = (int2*)(dmem + b_tab);
-  {
-    void* hp = nullptr;
-    const size_t hr = al(sizeof(pfd::Red) * std::max(nslots, 1));
-    if (hipHostMalloc(&hp, hr + sizeof(int) * std::max(nslots, 1), hipHostMallocCoherent) != hipSuccess) return false;
-    h_reds = (pfd::Red*)hp;
-    h_kstate = (int*)((char*)hp + hr);
-  }
-  std::vector<const pfd::Inst*> tab(nslots);
-  for (int s = 0; s < nslots; ++s) tab[s] = cs[s]->d_inst;
-  hipStream_t st = stream;
-  bool ok = hipMemcpyAsync((void*)d_insts, tab.data(), sizeof(void*) * nslots, hipMemcpyHostToDevice, st) == hipSuccess;
-  if (!work.empty())
-    ok &= hipMemcpyAsync(d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, st) == hipSuccess;
-  ok &= hipStreamSynchronize(st) == hipSuccess;
-  return ok;
 }
 
 namespace {
