@@ -12,6 +12,12 @@ the batched form on the same grid, the roofline of the dominant kernel (timed
 with HIP events inside the timed region) and the CPU oracle timed on a
 bounded sample of the same work.
 
+The default line also carries the two target forms as fields: 512 grids of
+100-5,000 buses with FP32 inner solves in one pf_solve_batch, and the served
+mix (Poisson arrivals, admission by the serving pool's budget) beside the
+plain FP64 one-at-a-time GPU Newton on the same requests; every leg reports
+max |V - V_oracle| against the oracle's root on a stated sample.
+
 Other modes (each prints its own JSON line):
   --workload scenarios512   512 grids of 100-5,000 buses, FP32 inner solves,
                             one pf_solve_batch per step
@@ -52,9 +58,37 @@ def _pct(xs, q):
     return xs[k]
 
 
-def cpu_baseline(case, budget_s=20.0):
-    """The CPU oracle as it stands, single-threaded, on whole solves of the
-    same grid until the time budget is spent (at least one)."""
+def _cpu_worker(args):
+    """One CPU worker of the all-cores baseline (a fresh interpreter): whole
+    oracle solves of the 10,000-bus grid, one thread, until the budget is
+    spent (at least one).  Returns (solves, seconds)."""
+    budget_s, start_at = args
+    from threadpoolctl import threadpool_limits
+
+    import pfgen
+    from oracle import polar
+
+    case = pfgen.config_case(1)
+    while time.time() < start_at:  # every worker starts together
+        time.sleep(0.01)
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        while True:
+            r = polar.newton(case, tol=1e-8)
+            assert r.status == 0
+            done += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(case, budget_s=8.0, one_core_max=5):
+    """The CPU oracle as it stands on whole solves of the same grid (tol 1e-8):
+    one thread for up to `one_core_max` solves, then one single-threaded
+    process per host core (at most 16, the host share of one GPU) over the
+    same grid, each until `budget_s` is spent."""
+    import multiprocessing as mp
+
     from threadpoolctl import threadpool_limits
 
     from oracle import polar
@@ -65,12 +99,22 @@ def cpu_baseline(case, budget_s=20.0):
             r = polar.newton(case, tol=1e-8)
             assert r.status == 0
             done += 1
-            if time.perf_counter() - t0 >= budget_s or done >= 5:
+            if time.perf_counter() - t0 >= 20.0 or done >= one_core_max:
                 break
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} full solves of the 10,000-bus grid (tol 1e-8), "
-                      f"{el:.1f} s, FP64 NumPy/SciPy SuperLU, 1 thread"}
+    one = {"value": done / el, "unit": "solves/s", "cores": 1,
+           "sample": f"{done} full solves of the 10,000-bus grid (tol 1e-8), {el:.1f} s, 1 thread"}
+    procs = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        start_at = time.time() + 8.0  # after every interpreter has imported NumPy and SciPy
+        res = pool.map(_cpu_worker, [(budget_s, start_at)] * procs)
+    total = sum(d for d, _ in res)
+    span = max(t for _, t in res)
+    return {"value": total / span, "unit": "solves/s", "cores": procs, "kind": "oracle",
+            "sample": f"{total} full solves of the 10,000-bus grid (tol 1e-8) by {procs} single-threaded "
+                      f"processes in {span:.1f} s (host nproc {os.cpu_count()}), FP64 NumPy/SciPy SuperLU",
+            "one_core": one}
 
 
 def _schedule_key(sc):
@@ -103,19 +147,55 @@ def _measured_traffic(kernel, schedule):
     return val if cap == sha and sched == _schedule_key(schedule) else None
 
 
-def _roof(st, bound, peak, unit, kernel):
+def _dense_roof(st, M, peak, mixed, sched):
+    """Roofline of the dense block's step launches on the matrix cores.
+
+    Algorithmic flops of the dense block's factorisation are (2/3) M^3 for
+    dense order M (LU of the trailing block; the right-hand side column and
+    the explicit diagonal-block inverses the library forms are not counted),
+    spread over its ceil(M / 64) step launches; the library's own count,
+    which includes the inverses (2 kb^3 per step) and the products by them,
+    is reported beside it."""
     n = max(st["launches"], 1)
     avg_ms = st["ms"] / n
-    if bound == "hbm":
-        per = st["bytes"] / n
-        achieved = per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    else:
-        per = st["flops"] / n
-        achieved = per / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel": kernel,
-            "avg_launch_ms": avg_ms, "launches": st["launches"],
-            ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): per}
+    steps = -(-M // 64)
+    per = (2.0 / 3.0) * M ** 3 / steps
+    achieved = per / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    lib_per = st["flops"] / n
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None if mixed else _measured_traffic("k_dense_step", sched),
+            "kernel": "k_dense_step (block step k of the dense block: diagonal-block inverse by block "
+                      "Gauss-Jordan, row tiles times it, and the matrix-core trailing update)",
+            "avg_launch_ms": avg_ms, "launches": st["launches"], "dense_order": M,
+            "launches_per_factorisation": steps,
+            "flops_per_launch": per, "flops_basis": "(2/3) M^3 per factorisation / launches",
+            "library_flops_per_launch": lib_per,
+            "library_achieved": lib_per / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0,
+            "timing": "HIP events on the library stream around each Newton step's run of k_dense_step "
+                      "launches inside the replayed graph; per launch = span / launches (includes the gaps "
+                      "between them)"}
+
+
+def _vm_va_err(V, ref_vm, ref_va):
+    import numpy as np
+
+    return float(max(np.max(np.abs(np.abs(V) - ref_vm)), np.max(np.abs(np.angle(V) - ref_va))))
+
+
+def _oracle_err(case, V):
+    """max |V - V_oracle| against the oracle's own root (magnitudes in pu and
+    angles in rad for single-phase grids, complex phase voltages for feeders)."""
+    import numpy as np
+
+    from oracle import cim, polar
+
+    if hasattr(case, "bus_type"):
+        ref = polar.newton(case)
+        assert ref.status == 0
+        return _vm_va_err(V, ref.vm, ref.va)
+    ref = cim.newton(case)
+    assert ref.status == 0
+    return float(np.max(np.abs(V - ref.V)))
 
 
 def _with_hbm(roof):
@@ -199,10 +279,9 @@ def bench_grid10k(args):
 
     # the dominant kernel (the dense block's step launches) is timed with HIP
     # events on the library's stream inside the timed region (captured into
-    # the replayed Newton-step graph with the kernels)
+    # the replayed Newton-step graph with the kernels): one event pair around
+    # each Newton step's run of block-step launches
     dom = B.PF_K_DENSE_PANEL
-    # one event pair around each Newton step's run of block-step launches
-    # (its time includes the short gaps between them inside the graph)
     B.pf_profile_enable(ctx, (1 << dom) | B.PF_PROFILE_SPANS)
     B.pf_profile_reset(ctx)
     torch.cuda.synchronize()
@@ -218,11 +297,17 @@ def bench_grid10k(args):
     elapsed = time.perf_counter() - t0
     st_dom = B.pf_kernel_stats(ctx, dom)
     B.pf_profile_enable(ctx, 0)
-    mism = polar.mismatch_at(case, B.pf_get_voltage(h))
+    V_lu = B.pf_get_voltage(h)
+    mism = polar.mismatch_at(case, V_lu)
+    # the oracle's root of the same grid (run to its floor), for the error of
+    # every leg on this grid
+    ref = polar.newton(case)
+    assert ref.status == 0
+    err = lambda V: _vm_va_err(V, ref.vm, ref.va)  # noqa: E731
 
-    # Newton-Krylov on the same grid, right-preconditioned with block ILU(0),
-    # forcing term min(0.1, ||F||_inf): GMRES(30), then BiCGStab (the method
-    # the paper tested)
+    # Newton-Krylov on the same grid, forcing term min(0.1, ||F||_inf):
+    # GMRES(30) and BiCGStab (the method the paper tested), right
+    # preconditioned with block ILU(0) or block-Jacobi
     def krylov_run(solver, label, precond=B.PF_PRECOND_ILU0):
         nopts = B.pf_default_options(solver=solver, precision=int(mixed), max_iter=40, precond=precond)
         for _ in range(max(1, args.warmup)):
@@ -242,12 +327,13 @@ def bench_grid10k(args):
             nit.append(r.iters)
         torch.cuda.synchronize()
         nel = time.perf_counter() - t0
+        V = B.pf_get_voltage(h)
         return {"value": nconv / nel, "unit": "solves/s", "steps": args.nk_steps, "converged": nconv,
                 "latency_ms": {"p50": 1000 * _pct(nlat, 50), "p99": 1000 * _pct(nlat, 99)},
                 "solver": label + ("+ilu0" if precond == B.PF_PRECOND_ILU0 else "+block-jacobi"),
                 "newton_iters": int(np.median(nit)),
                 "inner_iters_per_solve": int(np.median(nlin)),
-                "final_mismatch_oracle": polar.mismatch_at(case, B.pf_get_voltage(h))}
+                "final_mismatch_oracle": polar.mismatch_at(case, V), "max_err_vs_oracle": err(V)}
 
     nk = nk_bcg = nk_bcg_bj = None
     if args.nk_steps > 0:
@@ -274,14 +360,20 @@ def bench_grid10k(args):
             bconv += sum(r.status == B.PF_CONVERGED for r in rs)
         torch.cuda.synchronize()
         bel = time.perf_counter() - t0
+        berr = [_oracle_err(scen[i], B.pf_get_voltage(hb[i])) for i in (0, len(scen) - 1)]
         batched = {"instances": args.batch, "value": bconv / bel, "unit": "solves/s",
                    "batch_latency_ms": {"p50": 1000 * _pct(blat, 50), "p99": 1000 * _pct(blat, 99)},
                    "steps": bsteps, "converged": bconv,
-                   "final_mismatch_oracle": polar.mismatch_at(scen[-1], B.pf_get_voltage(hb[-1]))}
+                   "final_mismatch_oracle": polar.mismatch_at(scen[-1], B.pf_get_voltage(hb[-1])),
+                   "max_err_vs_oracle": max(berr), "oracle_sample": "scenarios 0 and last"}
         for x in hb:
             x.close()
 
-    valu_peak = PEAK["fp32_valu_tflops"] if mixed else PEAK["fp64_tflops"]
+    # the target forms: 512 mixed-precision scenarios in one batch, and the
+    # served mix against the plain FP64 one-at-a-time GPU Newton
+    s512 = run_scenarios512(args, B, ctx) if args.with_targets else None
+    served = run_served(args, B, ctx) if args.with_targets else None
+
     mfma_peak = PEAK["fp32_mfma_tflops"] if mixed else PEAK["fp64_tflops"]
     out = {
         "metric": METRIC,
@@ -306,15 +398,11 @@ def bench_grid10k(args):
         "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
         "converged": conv,
         "final_mismatch_oracle": mism,
-        "roofline": _with_hbm(dict(_roof(st_dom, "mfma", mfma_peak, "TFLOP/s",
-                                         "k_dense_step (block step k of the dense block: diagonal-block inverse "
-                                         "by block Gauss-Jordan, row tiles times it, and the matrix-core trailing "
-                                         "update)"),
-                                   traffic=None if mixed else _measured_traffic("k_dense_step", sched),
-                                   timing="HIP events on the library stream around each Newton step's run of "
-                                          "k_dense_step launches inside the replayed graph; per launch = span / "
-                                          "launches (includes the gaps between them)")),
+        "max_err_vs_oracle": err(V_lu),
+        "roofline": _with_hbm(_dense_roof(st_dom, 2 * info["n_dense"], mfma_peak, mixed, sched)),
         "batched": batched,
+        "scenarios512": s512,
+        "served": served,
         "newton_krylov": nk,
         "newton_krylov_bicgstab": nk_bcg,
         "newton_krylov_bicgstab_bjacobi": nk_bcg_bj,
@@ -325,68 +413,83 @@ def bench_grid10k(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_scenarios512(args):
+def run_scenarios512(args, B, ctx):
+    """512 grids of 100-5,000 buses (log-uniform, own topologies, +-20 %
+    loads), FP32 inner solves with FP64 mismatch, update and test, one
+    pf_solve_batch per step; FP64-oracle error on the 8 largest scenarios and
+    8 others."""
     import numpy as np
     import torch
 
     import pfgen
-    from oracle import polar
-    from paper_1711_10579_amd import binding as B
 
     t0 = time.perf_counter()
     scen = pfgen.c3_scenarios(args.instances)
     t_gen = time.perf_counter() - t0
-    ctx = B.pf_ctx_create(0)
     t0 = time.perf_counter()
     hs = [B.pf_create_from(ctx, c) for c in scen]
     t_setup = time.perf_counter() - t0
-    mixed = args.precision != "fp64"
+    mixed = args.target_precision != "fp64"
     opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
     B.pf_solve_batch(ctx, hs, opts)
     torch.cuda.synchronize()
-    conv, steps = 0, max(1, args.steps // 10)
+    conv, steps, lat = 0, max(2, args.steps // 10), []
     t0 = time.perf_counter()
     for _ in range(steps):
+        s0 = time.perf_counter()
         rs = B.pf_solve_batch(ctx, hs, opts)
+        lat.append(time.perf_counter() - s0)
         conv += sum(r.status == B.PF_CONVERGED for r in rs)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    # FP64-oracle error on a sample of scenarios (the oracle's own roots)
+    order = list(np.argsort([c.n for c in scen]))
     rng = np.random.default_rng(1)
-    sample = sorted(rng.choice(len(scen), size=min(args.oracle_sample, len(scen)), replace=False))
-    errs = []
-    for i in sample:
-        V = B.pf_get_voltage(hs[i])
-        ref = polar.newton(scen[i])
-        errs.append(float(max(np.max(np.abs(np.abs(V) - ref.vm)), np.max(np.abs(np.angle(V) - ref.va)))))
-    out = {"mode": "scenarios512", "metric": METRIC, "value": conv / el, "unit": "solves/s",
-           "instances": len(scen), "steps": steps, "converged": conv,
-           "sum_buses": int(sum(c.n for c in scen)), "ms_per_batch": 1000 * el / steps,
-           "precision": args.precision, "setup_s": t_setup, "generate_s": t_gen,
-           "iters": {"p50": float(np.median([r.iters for r in rs])), "max": int(max(r.iters for r in rs))},
-           "oracle_err_max": max(errs), "oracle_sample": len(sample),
-           "final_mismatch_max": float(max(r.mismatch_inf for r in rs))}
+    sample = order[-8:] + list(rng.choice(order[:-8], size=min(args.oracle_sample, len(order) - 8), replace=False))
+    errs = [_oracle_err(scen[i], B.pf_get_voltage(hs[i])) for i in sample]
+    for h in hs:
+        h.close()
+    return {"value": conv / el, "unit": "solves/s", "instances": len(scen), "steps": steps, "converged": conv,
+            "sum_buses": int(sum(c.n for c in scen)), "ms_per_batch": 1000 * el / steps,
+            "batch_latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
+            "precision": "f32-inner/f64-outer" if mixed else "f64", "setup_s": t_setup, "generate_s": t_gen,
+            "iters": {"p50": float(np.median([r.iters for r in rs])), "max": int(max(r.iters for r in rs))},
+            "final_mismatch_max": float(max(r.mismatch_inf for r in rs)),
+            "max_err_vs_oracle": max(errs), "oracle_sample": f"{len(sample)} scenarios: the 8 largest and "
+                                                              f"{len(sample) - 8} seeded others"}
+
+
+def bench_scenarios512(args):
+    from paper_1711_10579_amd import binding as B
+
+    ctx = B.pf_ctx_create(0)
+    out = {"mode": "scenarios512", "metric": METRIC}
+    out.update(run_scenarios512(args, B, ctx))
     print(json.dumps(out), flush=True)
 
 
-def bench_served(args):
-    import numpy as np
-
+def run_served(args, B, ctx):
+    """Poisson-arriving requests on a pool of 32 single-phase grids of
+    1,000-20,000 buses and 16 feeders of 500-3,000 buses (70 % / 30 %), each
+    with a fresh +-20 % load perturbation, mixed-precision LU through
+    pf_submit / pf_poll at 0.8 x the plain FP64 serial rate; beside it the
+    plain FP64 one-at-a-time GPU Newton on the same requests (its service
+    times, and its FIFO queue under the same arrivals)."""
     import pfgen
-    from paper_1711_10579_amd import binding as B
 
     pool = pfgen.c4_pool(n_polar=args.pool_polar, n_feeder=args.pool_feeder)
-    ctx = B.pf_ctx_create(0)
     reps = 2
     t0 = time.perf_counter()
+    # served handles (two replicas per grid) hold no working storage of their
+    # own: every request borrows it from the serving pool at admission; the
+    # plain serial baseline runs on handles of its own
     cases = [[B.pf_create_from(ctx, g) for _ in range(reps)] for g in pool]
+    serial = [B.pf_create_from(ctx, g) for g in pool]
     setup_s = time.perf_counter() - t0
-    mixed = args.precision != "fp64"
+    mixed = args.target_precision != "fp64"
     opts = B.pf_default_options(precision=int(mixed), max_iter=40 if mixed else 20)
     plain = B.pf_default_options(precision=0, max_iter=20)
     rng = random.Random(11)
     n_req = args.requests
-    # request stream: 70 % single-phase, 30 % feeders, fresh perturbation each
     n_pol = args.pool_polar
     reqs = []
     for k in range(n_req):
@@ -400,13 +503,21 @@ def bench_served(args):
         else:
             B.pf_set_injections(h, None, None, p.zip)
 
-    for row in cases:  # warm every case once (device code, cached launch plans)
-        B.pf_solve(row[0], plain)
+    for h in serial:  # warm the serial handles (device code, launch plans, graphs)
+        B.pf_solve(h, plain)
+    # warm the served handles through the serving loop itself (launch plans
+    # built at their first submit, graphs captured at their first step)
+    B.pf_serve_config(ctx, max_bytes=args.max_bytes, max_slots=args.slots)
+    for row in cases:
+        for h in row:
+            t = B.pf_submit(ctx, h, opts)
+            while not B.pf_poll(ctx, t)[0]:
+                time.sleep(0.0002)
     # the plain FP64 one-at-a-time GPU Newton over the same requests: service
     # times (host clock around each pf_solve, injections included)
     service, serial_conv = [], 0
     for (g, _), p in zip(reqs, pert):
-        h = cases[g][0]
+        h = serial[g]
         s0 = time.perf_counter()
         prepare(h, p)
         r = B.pf_solve(h, plain)
@@ -425,12 +536,17 @@ def bench_served(args):
         done_t = max(done_t, a) + sv
         q_lat.append(done_t - a)
 
-    B.pf_serve_config(ctx, max_bytes=args.max_bytes, max_slots=args.slots)
+    # requests whose voltages are compared with the oracle's root: feeders and
+    # grids up to 5,000 buses (the oracle solves them in about a second)
+    small = [k for k, (g, _) in enumerate(reqs) if getattr(pool[g], "n", 0) <= 5000 or not hasattr(pool[g], "bus_type")]
+    check = set(small[:8])
 
-    def run(arr):
+    def run(arr, keep):
         free = {g: list(range(reps)) for g in range(len(pool))}
         inflight = {}
-        lat, conv, done_n = [], 0, 0
+        lat, conv, done_n, waits = [], 0, 0, []
+        volts = {}
+        lent = 0
         waiting = []  # arrived but no free replica yet
         start = time.perf_counter()
         nxt = 0
@@ -454,28 +570,55 @@ def bench_served(args):
                 d, res = B.pf_poll(ctx, tk)
                 if d:
                     k, g, r_ = inflight.pop(tk)
+                    if keep and k in check:
+                        volts[k] = B.pf_get_voltage(cases[g][r_])
                     free[g].append(r_)
                     lat.append(time.perf_counter() - start - arr[k])
+                    waits.append(res.wait_ms)
                     conv += res.status == B.PF_CONVERGED
                     done_n += 1
+            lent = max(lent, B.pf_serve_stats(ctx)["lent_bytes"])
             time.sleep(0.0002)
-        return conv, time.perf_counter() - start, lat
+        return conv, time.perf_counter() - start, lat, volts, waits, lent
 
-    conv, el, lat = run(arrivals)
+    conv, el, lat, volts, waits, lent = run(arrivals, True)
     # saturation: every request arrives at once (replicas still bound a grid's
     # concurrency)
-    sconv, sel, _ = run([0.0] * n_req)
-    out = {"mode": "served", "metric": METRIC, "value": conv / el, "unit": "solves/s",
-           "requests": n_req, "converged": conv, "arrival_rate_per_s": lam,
-           "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
-           "saturation": {"value": sconv / sel, "converged": sconv},
-           "plain_fp64_serial": {"value": serial_rate, "converged": serial_conv,
-                                 "service_ms": {"p50": 1000 * _pct(service, 50), "p99": 1000 * _pct(service, 99)},
-                                 "queued_latency_ms_same_arrivals": {"p50": 1000 * _pct(q_lat, 50),
-                                                                     "p99": 1000 * _pct(q_lat, 99)}},
-           "pool": {"single_phase": args.pool_polar, "feeders": args.pool_feeder, "replicas": reps,
-                    "setup_s": setup_s},
-           "slots": args.slots, "precision": args.precision}
+    sconv, sel, _, _, _, slent = run([0.0] * n_req, False)
+    pool_bytes = B.pf_serve_stats(ctx)["pool_bytes"]
+    errs = [_oracle_err(pert[k], V) for k, V in volts.items()]
+    for row in cases:
+        for h in row:
+            h.close()
+    for h in serial:
+        h.close()
+    B.pf_serve_config(ctx, max_bytes=0)
+    return {"value": conv / el, "unit": "solves/s", "requests": n_req, "converged": conv,
+            "arrival_rate_per_s": lam, "load_factor": args.load_factor,
+            "latency_ms": {"p50": 1000 * _pct(lat, 50), "p99": 1000 * _pct(lat, 99)},
+            "admission_wait_ms": {"p50": _pct(waits, 50), "p99": _pct(waits, 99)},
+            "precision": "f32-inner/f64-outer" if mixed else "f64",
+            "saturation": {"value": sconv / sel, "converged": sconv},
+            "plain_fp64_serial": {"value": serial_rate, "converged": serial_conv,
+                                  "service_ms": {"p50": 1000 * _pct(service, 50), "p99": 1000 * _pct(service, 99)},
+                                  "queued_latency_ms_same_arrivals": {"p50": 1000 * _pct(q_lat, 50),
+                                                                      "p99": 1000 * _pct(q_lat, 99)}},
+            "max_err_vs_oracle": max(errs) if errs else None,
+            "oracle_sample": f"{len(errs)} served requests (feeders and grids up to 5,000 buses)",
+            "pool": {"single_phase": args.pool_polar, "feeders": args.pool_feeder, "replicas": reps,
+                     "setup_s": setup_s},
+            "slots": args.slots,
+            "memory": {"budget_bytes": args.max_bytes, "pool_bytes": pool_bytes, "max_lent_bytes": lent,
+                       "max_lent_bytes_saturation": slent,
+                       "note": "working storage of running requests, lent by the serving pool at admission"}}
+
+
+def bench_served(args):
+    from paper_1711_10579_amd import binding as B
+
+    ctx = B.pf_ctx_create(0)
+    out = {"mode": "served", "metric": METRIC}
+    out.update(run_served(args, B, ctx))
     print(json.dumps(out), flush=True)
 
 
@@ -602,11 +745,17 @@ def main():
     ap.add_argument("--pool-polar", type=int, default=32)
     ap.add_argument("--pool-feeder", type=int, default=16)
     ap.add_argument("--slots", type=int, default=32)
-    ap.add_argument("--max-bytes", type=int, default=0)
+    ap.add_argument("--max-bytes", type=int, default=2 << 30,
+                    help="serving pool budget in bytes (0: no limit)")
+    ap.add_argument("--no-targets", action="store_true",
+                    help="default workload without the scenarios512 and served legs")
+    ap.add_argument("--target-precision", choices=["fp64", "mixed"], default="mixed",
+                    help="precision of the scenarios512 and served legs")
     ap.add_argument("--rate", type=float, default=0.0, help="arrivals/s (0: load factor x serial rate)")
     ap.add_argument("--load-factor", type=float, default=0.8)
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
+    args.with_targets = not args.no_targets
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(independent power-flow instances shard across GPUs without collectives)",
@@ -618,12 +767,12 @@ def main():
         args.precision = args.precision or "fp64"
         bench_grid10k(args)
     elif args.workload == "scenarios512":
-        args.precision = args.precision or "mixed"
+        args.target_precision = args.precision or args.target_precision
         bench_scenarios512(args)
     elif args.workload == "replication":
         bench_replication(args)
     else:
-        args.precision = args.precision or "mixed"
+        args.target_precision = args.precision or args.target_precision
         bench_served(args)
 
 
