@@ -439,7 +439,6 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
       return std::min(64, g * sched.lane_scale);
     };
     c->fac_g.resize(c->nlev);
-    c->fwd_g.resize(c->nlev);
     c->fac_flops.resize(c->nlev);
     c->fac_bytes.resize(c->nlev);
     for (int l = 0; l < c->nlev; ++l) {
@@ -454,8 +453,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
         upd += (double)(an.uptr[t0 + 1 + 2 * len] - an.uptr[t0]);
         blocks += 1 + 2 * len;
       }
-      c->fac_g[l] = pick(mf);
-      c->fwd_g[l] = pick(mr);
+      // one lane count for the level's update lists and its forward rows
+      // (run by the same launch)
+      c->fac_g[l] = pick(std::max(mf, mr));
       c->fac_flops[l] = 16.0 * upd + 40.0 * blocks;
       c->fac_bytes[l] = 8.0 * upd + 2 * 32.0 * blocks;  // index pairs + read/write of target blocks (FP64)
     }
@@ -491,6 +491,11 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     return PF_E_INVALID;
   }
   const int ns = an.ns;
+  // rows the mismatch gives a work-group of their own
+  std::vector<int> heavy;
+  for (int i = 0; i < n; ++i)
+    if (d->row_ptr[i + 1] - d->row_ptr[i] > pfd::kHeavyRow) heavy.push_back(i);
+  c->nheavy = (int)heavy.size();
   // device layout
   const int nu = an.nu;
   const int64_t nupd = (int64_t)an.upd_l.size(), ntail = (int64_t)an.tail_l.size();
@@ -505,7 +510,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
   total += carve_size<int>(nu + 1) + 2 * carve_size<int>(an.nnzl) + carve_size<int>(ns);
   total += carve_size<double>(n) + carve_size<int>(2LL * n) + carve_size<double>(6LL * n);
-  total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1);
+  total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1) + carve_size<int>(c->nheavy);
   c->bytes = total;
   c->wbytes = work_bytes(c);
   c->base = (char*)ctx->dalloc(total);
@@ -553,6 +558,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   c->bwd_rows = carve<int>(p, ns);
   c->red = carve<pfd::Red>(p, 1);
   c->d_inst = carve<pfd::Inst>(p, 1);
+  int* d_heavy = carve<int>(p, c->nheavy);
   if ((size_t)(p - c->base) != total) {
     ctx->dfree(c->base);
     delete c;
@@ -610,6 +616,7 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   ok &= up(c->lrow_blk, an.lrow_blk.data(), sizeof(int) * an.nnzl);
   ok &= up(c->lrow_col, an.lrow_col.data(), sizeof(int) * an.nnzl);
   ok &= up(c->bwd_rows, an.bwd_rows.data(), sizeof(int) * ns);
+  ok &= up(d_heavy, heavy.data(), sizeof(int) * heavy.size());
   ok &= hipMemsetAsync(c->red, 0, sizeof(pfd::Red), s) == hipSuccess;
   {
     pfd::Inst hi;
@@ -643,6 +650,8 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     hi.zipd = c->zipd;
     hi.pos = c->pos;
     hi.node = c->node;
+    hi.nheavy = c->nheavy;
+    hi.heavy = d_heavy;
     hi.vm = c->vm;
     hi.va = c->va;
     hi.v = c->v;

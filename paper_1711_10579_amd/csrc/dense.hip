@@ -236,6 +236,15 @@ __device__ inline unsigned long long flag_ld(const unsigned long long* p) {
 // included, has completed
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Bound of an inter-work-group wait in ticks of the device's constant
+// real-time counter (100 MHz): about one second.  Every wait here is on a
+// work-group listed earlier in the same launch; work-groups are dispatched
+// in index order, so the earliest unfinished one waits on nothing and the
+// launch drains whatever else shares the device (the bound only turns a
+// broken invariant into a recorded timeout instead of a hang).
+constexpr unsigned long long kWaitTicks = 100000000ull;
+__device__ inline unsigned long long rt_now() { return __builtin_amdgcn_s_memrealtime(); }
+
 // Panel step k0 of every instance in the work list: item (slot, g), one of
 // four work-groups h of four waves.  Every work-group inverts the diagonal
 // block D = A_kk (identity-padded to 64x64) by block Gauss-Jordan over 4x4
@@ -408,14 +417,14 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   }
   bool expired = false;
   if (!have) {
-    // bounded: on expiry the instance records a timeout and the update is
-    // not stored
-    long spins = 0;
+    // bounded in device time: on expiry the instance records a timeout and
+    // the update is not stored
+    const unsigned long long t_start = rt_now();
     for (;;) {
       f1 = flag_ld(&I.pflags[r0 / NB]);
       f2 = flag_ld(&I.pflags[k0 / NB]);
       if (__builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) break;
-      if (++spins > (1l << 22)) {
+      if (rt_now() - t_start > kWaitTicks) {
         expired = true;
         if (lane == 0) I.red->timeout = 1;
         break;
@@ -583,11 +592,11 @@ __global__ __launch_bounds__(256, 2) void k_dense_step(const Inst* const* insts,
 // sum_{c > b} A_bc x_c (columns taken from the last block down), then x_b =
 // P_b acc with the diagonal block's inverse made by the panel step.
 // Flag mode, item (slot, w): work-group w owns block b = nblk-1-w and waits
-// only for blocks of the same instance listed before it (all work-groups of
-// the launch are resident); results are published with an agent-scope
-// release of dflags[b] = epoch, acquired by readers; the U tile of the next
-// block is loaded before waiting for its flag; spins are bounded and record a
-// timeout on expiry.  Single mode, item (slot, 0): one work-group runs all
+// only for blocks of the same instance listed before it (dispatched before
+// it, so the earliest unfinished block waits on nothing); results are
+// published with an agent-scope release of dflags[b] = epoch, acquired by
+// readers; the U tile of the next block is loaded before waiting for its
+// flag; a wait is bounded in device time and records a timeout on expiry.  Single mode, item (slot, 0): one work-group runs all
 // blocks of its instance in order.  Both modes do the same arithmetic.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, const int2* __restrict__ work,
@@ -633,9 +642,9 @@ __global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, co
       if (!single) {
         if (tid == 0) {
           // poll without ordering, then one acquire once the flag is seen
-          long spins = 0;
+          const unsigned long long t_start = rt_now();
           while (__hip_atomic_load(&I.dflags[cb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            if (++spins > (1l << 24)) {
+            if (rt_now() - t_start > kWaitTicks) {
               abort_flag = 1;
               break;
             }

@@ -58,6 +58,10 @@ struct Inst {
   const double* zipd;
   double* qg;
   const int *pos, *node;
+  // rows of more than kHeavyRow Ybus entries (the mismatch gives each a
+  // work-group of its own)
+  int nheavy;
+  const int* heavy;
   double *vm, *va, *v, *ibus, *F;
   void *x, *lu, *dinv, *tail, *dinvu;
   int* dflags;

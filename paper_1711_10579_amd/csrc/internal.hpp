@@ -89,7 +89,7 @@ struct Case {
   std::vector<int8_t> type;
   // lanes per list (power of two) of each level, and the per-level
   // algorithmic flops / bytes of the refactorisation (profiling)
-  std::vector<int> fac_g, fwd_g, bwd_g;
+  std::vector<int> fac_g, bwd_g;
   int tailfwd_g = 1;
   std::vector<double> fac_flops, fac_bytes;
 
@@ -115,6 +115,7 @@ struct Case {
   int* dlink = nullptr;
   double* zipd = nullptr;
   bool has_delta = false;
+  int nheavy = 0;  // Ybus rows of more than kHeavyRow entries
   int *pos = nullptr, *node = nullptr;
   double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
   void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dinvu = nullptr;
@@ -177,7 +178,7 @@ struct Batch {
   std::vector<Launch> seq;
   int64_t zero_off = 0;  // zeroing chunks of the factor storage: work items [zero_off, +nzero)
   int nzero = 0;
-  int max_n = 0, max_nnz = 0, max_nu = 0;
+  int max_n = 0, max_nnz = 0, max_nu = 0, max_heavy = 0;
   int64_t max_lu = 0, max_tail = 0;
   int trsv_single = 0;
 

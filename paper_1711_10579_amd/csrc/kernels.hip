@@ -188,72 +188,140 @@ __device__ inline double2 delta_current(const double* z, double2 vd) {
   return make_double2((sr * vd.x + si * vd.y) / w, (sr * vd.y - si * vd.x) / w);
 }
 
-__global__ void k_mismatch(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
-  if (inactive(I)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The rest of row i's mismatch once I_i = sum_j Y_ij V_j is known: polar dP,
+// dQ; CIM the ZIP load, the specified current, the delta loads and dI.
+// Writes F at the node's position (and the bus current for polar) and
+// returns the row's |F| (NaN when a value is NaN).
+__device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, double ii) {
+  const double2* v = (const double2*)I.v;
+  const double2 vi = v[i];
   double local = 0.0;
-  if (i < I.n) {
-    const double2* y = (const double2*)I.y;
-    const double2* v = (const double2*)I.v;
-    const int p = I.pos[i];
-    if (I.model == 0 || p >= 0) {
-      double ir = 0.0, ii = 0.0;
-      for (int q = I.row_ptr[i]; q < I.row_ptr[i + 1]; ++q) {
-        double2 yy = y[q];
-        double2 vv = v[I.col[q]];
-        ir += yy.x * vv.x - yy.y * vv.y;
-        ii += yy.x * vv.y + yy.y * vv.x;
+  if (I.model == 0) {
+    ((double2*)I.ibus)[i] = make_double2(ir, ii);
+    if (p >= 0) {
+      double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
+      double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
+      double dp = I.psp[i] - sr;
+      double dq = I.type[i] == 1 ? I.qsp[i] - si : 0.0;
+      I.F[2 * p] = dp;
+      I.F[2 * p + 1] = dq;
+      local = fmax(fabs(dp), fabs(dq));
+      if (!(dp == dp) || !(dq == dq)) local = __longlong_as_double(0x7ff8000000000000ll);
+    }
+  } else {
+    double w = vi.x * vi.x + vi.y * vi.y;
+    double vm = sqrt(w);
+    const double* z = I.zip + 6 * i;
+    double pl = z[2] + z[1] * vm + z[0] * w;
+    double ql = z[5] + z[4] * vm + z[3] * w;
+    const double qgen = I.type[i] == 2 ? I.qg[i] : I.qsp[i];
+    double ps = I.psp[i] - pl, qs = qgen - ql;
+    // conj((ps + j qs) / V) = (ps - j qs) V / |V|^2
+    double spr = (ps * vi.x + qs * vi.y) / w;
+    double spi = (ps * vi.y - qs * vi.x) / w;
+    if (I.dlink) {
+      const int2 L = I.dlink[i];
+      if (L.x >= 0) {
+        const double2 vt = v[L.x];
+        const double2 id = delta_current(I.zipd + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
+        spr -= id.x;
+        spi -= id.y;
       }
-      const double2 vi = v[i];
-      if (I.model == 0) {
-        ((double2*)I.ibus)[i] = make_double2(ir, ii);
-        if (p >= 0) {
-          double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
-          double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
-          double dp = I.psp[i] - sr;
-          double dq = I.type[i] == 1 ? I.qsp[i] - si : 0.0;
-          I.F[2 * p] = dp;
-          I.F[2 * p + 1] = dq;
-          local = fmax(fabs(dp), fabs(dq));
-          if (!(dp == dp) || !(dq == dq)) local = __longlong_as_double(0x7ff8000000000000ll);
-        }
-      } else {
-        double w = vi.x * vi.x + vi.y * vi.y;
-        double vm = sqrt(w);
-        const double* z = I.zip + 6 * i;
-        double pl = z[2] + z[1] * vm + z[0] * w;
-        double ql = z[5] + z[4] * vm + z[3] * w;
-        const double qgen = I.type[i] == 2 ? I.qg[i] : I.qsp[i];
-        double ps = I.psp[i] - pl, qs = qgen - ql;
-        // conj((ps + j qs) / V) = (ps - j qs) V / |V|^2
-        double spr = (ps * vi.x + qs * vi.y) / w;
-        double spi = (ps * vi.y - qs * vi.x) / w;
-        if (I.dlink) {
-          const int2 L = I.dlink[i];
-          if (L.x >= 0) {
-            const double2 vt = v[L.x];
-            const double2 id = delta_current(I.zipd + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
-            spr -= id.x;
-            spi -= id.y;
-          }
-          if (L.y >= 0) {
-            const double2 vk = v[L.y];
-            const double2 id = delta_current(I.zipd + 6 * L.y, make_double2(vk.x - vi.x, vk.y - vi.y));
-            spr += id.x;
-            spi += id.y;
-          }
-        }
-        double dr = spr - ir, di = spi - ii;
-        I.F[2 * p] = di;
-        I.F[2 * p + 1] = dr;
-        local = fmax(fabs(dr), fabs(di));
-        if (!(dr == dr) || !(di == di)) local = __longlong_as_double(0x7ff8000000000000ll);
+      if (L.y >= 0) {
+        const double2 vk = v[L.y];
+        const double2 id = delta_current(I.zipd + 6 * L.y, make_double2(vk.x - vi.x, vk.y - vi.y));
+        spr += id.x;
+        spi += id.y;
       }
     }
+    double dr = spr - ir, di = spi - ii;
+    I.F[2 * p] = di;
+    I.F[2 * p + 1] = dr;
+    local = fmax(fabs(dr), fabs(di));
+    if (!(dr == dr) || !(di == di)) local = __longlong_as_double(0x7ff8000000000000ll);
   }
+  return local;
+}
+
+// Partial sum of Y_iq V_col(q) over q = q0, q0 + S, ... < q1 (the loads of
+// two entries issued at once)
+template <int S>
+__device__ inline void ydot_part(const Inst& I, int q0, int q1, double& ir, double& ii) {
+  const double2* y = (const double2*)I.y;
+  const double2* v = (const double2*)I.v;
+  for (int q = q0; q < q1; q += 2 * S) {
+    const bool two = q + S < q1;
+    const int c0 = I.col[q];
+    const int c1 = two ? I.col[q + S] : c0;
+    const double2 y0 = y[q], y1 = two ? y[q + S] : make_double2(0.0, 0.0);
+    const double2 v0 = v[c0], v1 = v[c1];
+    ir += y0.x * v0.x - y0.y * v0.y;
+    ii += y0.x * v0.y + y0.y * v0.x;
+    if (two) {
+      ir += y1.x * v1.x - y1.y * v1.y;
+      ii += y1.x * v1.y + y1.y * v1.x;
+    }
+  }
+}
+
+// Rows with at most kHeavyRow entries: S = 4 lanes per row split the row's
+// entries (lane-strided partial sums, then a fixed-order butterfly); longer
+// rows are left to k_mismatch_heavy.
+constexpr int kMisLanes = 4;
+template <int S>
+__global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts) {
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I)) return;
+  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) / S);
+  const int lane = threadIdx.x % S;
+  double local = 0.0;
+  bool mine = false;
+  int p = -1;
+  double ir = 0.0, ii = 0.0;
+  if (i < I.n) {
+    p = I.pos[i];
+    const int q0 = I.row_ptr[i], q1 = I.row_ptr[i + 1];
+    mine = (I.model == 0 || p >= 0) && q1 - q0 <= kHeavyRow;
+    if (mine) ydot_part<S>(I, q0 + lane, q1, ir, ii);
+  }
+#pragma unroll
+  for (int off = S / 2; off > 0; off >>= 1) {
+    ir += __shfl_xor(ir, off, 64);
+    ii += __shfl_xor(ii, off, 64);
+  }
+  if (mine && lane == 0) local = mismatch_row(I, i, p, ir, ii);
   local = wave_max(local);
   if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
+}
+
+// Rows with more than kHeavyRow entries (listed per instance in I.heavy): one
+// work-group of 256 threads per row, block-strided partial sums reduced by a
+// wave butterfly and then over the four waves in order.
+__global__ __launch_bounds__(256) void k_mismatch_heavy(const Inst* const* insts) {
+  __shared__ double part[2][4];
+  const Inst& I = *insts[blockIdx.y];
+  if (inactive(I) || (int)blockIdx.x >= I.nheavy) return;
+  const int i = I.heavy[blockIdx.x];
+  const int p = I.pos[i];
+  if (!(I.model == 0 || p >= 0)) return;
+  double ir = 0.0, ii = 0.0;
+  ydot_part<256>(I, I.row_ptr[i] + (int)threadIdx.x, I.row_ptr[i + 1], ir, ii);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ir += __shfl_xor(ir, off, 64);
+    ii += __shfl_xor(ii, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = ir;
+    part[1][threadIdx.x >> 6] = ii;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ir = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
+    ii = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+    const double local = mismatch_row(I, i, p, ir, ii);
+    if (local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -530,6 +598,56 @@ __device__ inline void sub_updates(Blk<T>& acc, const T* lu, const int* il, cons
   }
 }
 
+// Forward row of node i by a group of G lanes: y_i = b_i - sum_k L(i,k) y_k
+// over the row's L blocks (in place in x, which holds b_i before), lane-
+// strided partial sums with the loads of four entries issued at once, then
+// the fixed-order tree.  Every L(i,k) and y_k lies in an earlier level.
+// Rows of the dense block also copy the result into its right-hand side
+// column.
+template <typename T, int G>
+__device__ inline void fwd_row(const Inst& I, const T* lu, T* x, int i, int lane) {
+  Blk<T> acc = {T(0), T(0), T(0), T(0)};  // (a, c) carry the 2-vector
+  if (lane == 0) {
+    acc.a = x[2 * i];
+    acc.c = x[2 * i + 1];
+  }
+  const int q1 = I.lrow_ptr[i + 1];
+  for (int q = I.lrow_ptr[i] + lane; q < q1; q += 4 * G) {
+    int bk[4], kk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) {
+        bk[u] = I.lrow_blk[q + u * G];
+        kk[u] = I.lrow_col[q + u * G];
+      }
+    Blk<T> L[4];
+    T x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) {
+        L[u] = ld_blk(lu, bk[u]);
+        x0[u] = x[2 * kk[u]];
+        x1[u] = x[2 * kk[u] + 1];
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u * G < q1) {
+        acc.a -= L[u].a * x0[u] + L[u].b * x1[u];
+        acc.c -= L[u].c * x0[u] + L[u].d * x1[u];
+      }
+  }
+  acc = group_sum<T, G>(acc);
+  if (lane == 0) {
+    x[2 * i] = acc.a;
+    x[2 * i + 1] = acc.c;
+    if (i >= I.ns) {
+      T* rhs = (T*)I.tail + (int64_t)I.M * I.ldt;
+      rhs[2 * (i - I.ns)] = acc.a;
+      rhs[2 * (i - I.ns) + 1] = acc.c;
+    }
+  }
+}
+
 template <typename T, int G>
 __device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest, int64_t tg, int lane) {
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
@@ -542,6 +660,9 @@ __device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest,
 // most 64/G targets: the targets of a column then take one pass of the
 // wave's lane groups, and the diagonal inverse goes to the wave by a
 // shuffle instead of a work-group barrier.  Same arithmetic as k_factor_cols.
+// Both kernels also run the forward row of the column's node (target len + 1
+// of the first pass), so the forward substitution of the sparse part needs
+// no launches of its own.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* insts, const int2* __restrict__ work,
                                                           int nwork) {
@@ -559,7 +680,11 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
   const int lane = wl % G, grp = wl / G;
   constexpr int ngrp = 64 / G;
   T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
-  for (int t = grp; t <= len; t += ngrp) {
+  for (int t = grp; t <= len + 1; t += ngrp) {
+    if (t == len + 1) {
+      fwd_row<T, G>(I, lu, (T*)I.x, j, lane);
+      continue;
+    }
     int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
     if (lane == 0) {
@@ -605,8 +730,12 @@ __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, co
   const int len = I.colptr[j + 1] - c0;
   const int64_t tb = (int64_t)j + 2LL * c0;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
-  // D_j and U(j, .)
-  for (int t = grp; t <= len; t += ngrp) {
+  // D_j and U(j, .), and the forward row of node j (t = len + 1)
+  for (int t = grp; t <= len + 1; t += ngrp) {
+    if (t == len + 1) {
+      fwd_row<T, G>(I, lu, (T*)I.x, j, lane);
+      continue;
+    }
     int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
     if (lane == 0) {
@@ -669,9 +798,8 @@ __global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, co
 // ---------------------------------------------------------------------------
 // triangular solves over sparse rows
 
-// y_i = b_i - sum_k L(i,k) y_k for one (instance, row) per group of G lanes
-// (in place in x); rows of the dense block also copy their result into the
-// appended RHS column.
+// Forward rows of the dense block's nodes (after every sparse level): one
+// (instance, row) per group of G lanes.
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, const int2* __restrict__ work,
                                                   int nwork) {
@@ -680,52 +808,7 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, cons
   const int2 w = work[gid];
   const Inst& I = *insts[w.x];
   if (inactive(I)) return;
-  const T* lu = (const T*)I.lu;
-  T* x = (T*)I.x;
-  const int i = w.y;
-  Blk<T> acc = {T(0), T(0), T(0), T(0)};  // (a, c) carry the 2-vector
-  if (lane == 0) {
-    acc.a = x[2 * i];
-    acc.c = x[2 * i + 1];
-  }
-  {
-    // four entries' loads at once, applied in order
-    const int q1 = I.lrow_ptr[i + 1];
-    for (int q = I.lrow_ptr[i] + lane; q < q1; q += 4 * G) {
-      int bk[4], kk[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          bk[u] = I.lrow_blk[q + u * G];
-          kk[u] = I.lrow_col[q + u * G];
-        }
-      Blk<T> L[4];
-      T x0[4], x1[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          L[u] = ld_blk(lu, bk[u]);
-          x0[u] = x[2 * kk[u]];
-          x1[u] = x[2 * kk[u] + 1];
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          acc.a -= L[u].a * x0[u] + L[u].b * x1[u];
-          acc.c -= L[u].c * x0[u] + L[u].d * x1[u];
-        }
-    }
-  }
-  acc = group_sum<T, G>(acc);
-  if (lane == 0) {
-    x[2 * i] = acc.a;
-    x[2 * i + 1] = acc.c;
-    if (i >= I.ns) {
-      T* rhs = (T*)I.tail + (int64_t)I.M * I.ldt;
-      rhs[2 * (i - I.ns)] = acc.a;
-      rhs[2 * (i - I.ns) + 1] = acc.c;
-    }
-  }
+  fwd_row<T, G>(I, (const T*)I.lu, (T*)I.x, w.y, lane);
 }
 
 // x_i = D_i^{-1} (y_i - sum_j U(i,j) x_j) for one (instance, row) per group
@@ -857,8 +940,9 @@ void launch_decide(hipStream_t st, const Inst* const* insts, int nslots, DevOpts
 void launch_gather_red(hipStream_t st, const Inst* const* insts, int nslots, Red* out) {
   k_gather_red<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, out);
 }
-void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int max_n) {
-  k_mismatch<<<grid2(max_n, nslots), 256, 0, st>>>(insts);
+void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int max_n, int max_heavy) {
+  k_mismatch<kMisLanes><<<grid2((int64_t)max_n * kMisLanes, nslots), 256, 0, st>>>(insts);
+  if (max_heavy > 0) k_mismatch_heavy<<<dim3((unsigned)max_heavy, (unsigned)nslots), 256, 0, st>>>(insts);
 }
 
 template <typename T>

@@ -18,7 +18,10 @@ void launch_init(hipStream_t, const Inst* const* insts, int nslots, int max_n, i
 void launch_start(hipStream_t, const Inst* const* insts, int nslots);
 void launch_decide(hipStream_t, const Inst* const* insts, int nslots, DevOpts o);
 void launch_gather_red(hipStream_t, const Inst* const* insts, int nslots, Red* out);
-void launch_mismatch(hipStream_t, const Inst* const* insts, int nslots, int max_n);
+// rows of more than kHeavyRow Ybus entries run one work-group each (max_heavy:
+// the most such rows of an instance in the batch)
+constexpr int kHeavyRow = 64;
+void launch_mismatch(hipStream_t, const Inst* const* insts, int nslots, int max_n, int max_heavy);
 template <typename T>
 void launch_update(hipStream_t, const Inst* const* insts, int nslots, int max_nu);
 

@@ -103,11 +103,12 @@ void Batch::plan(Ctx* cx, const std::vector<Case*>& cs, std::vector<int2>* out) 
     work.insert(work.end(), items.begin(), items.end());
     seq.push_back(l);
   };
-  max_n = max_nnz = max_nu = 0;
+  max_n = max_nnz = max_nu = max_heavy = 0;
   max_lu = max_tail = 0;
   int max_lev = 0, max_blev = 0, max_M = 0;
   for (Case* c : cs) {
     max_n = std::max(max_n, c->n);
+    max_heavy = std::max(max_heavy, c->nheavy);
     max_nnz = std::max(max_nnz, c->nnz);
     max_nu = std::max(max_nu, c->an.nu);
     max_lu = std::max(max_lu, c->lu_count());
@@ -116,40 +117,37 @@ void Batch::plan(Ctx* cx, const std::vector<Case*>& cs, std::vector<int2>* out) 
     max_blev = std::max(max_blev, c->nbl);
     max_M = std::max(max_M, c->M);
   }
-  // sparse refactorisation and forward solve, level by level, one launch per
-  // lane-group size
+  // sparse refactorisation, level by level, one launch per lane-group size;
+  // each column's launch also runs the forward row of its node (the rows of
+  // a level depend only on earlier levels' L blocks and solution entries)
   // (factor launches whose columns all fit one wave's lane groups in one
   // pass run a column per wave: k0 = 1)
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int l = 0; l < max_lev; ++l) {
-      std::map<int, std::vector<int2>> byG;
-      std::map<int, double> fl, by;
-      std::map<int, int> maxt;  // most targets (1 + column length) of a column
-      for (int s = 0; s < nslots; ++s) {
-        Case* c = cs[s];
-        if (l >= c->nlev) continue;
-        const int G = pass == 0 ? c->fac_g[l] : c->fwd_g[l];
-        auto& v = byG[G];
-        int& mt = maxt[G];
-        for (int k = c->an.col_lev_ptr[l]; k < c->an.col_lev_ptr[l + 1]; ++k) {
-          const int j = c->an.col_order[k];
-          v.push_back(make_int2(s, j));
-          mt = std::max(mt, 1 + c->an.colptr[j + 1] - c->an.colptr[j]);
-        }
-        if (pass == 0) {
-          fl[G] += c->fac_flops[l];
-          by[G] += c->fac_bytes[l];
-        }
+  for (int l = 0; l < max_lev; ++l) {
+    std::map<int, std::vector<int2>> byG;
+    std::map<int, double> fl, by;
+    std::map<int, int> maxt;  // most targets of a column's first pass
+    for (int s = 0; s < nslots; ++s) {
+      Case* c = cs[s];
+      if (l >= c->nlev) continue;
+      const int G = c->fac_g[l];
+      auto& v = byG[G];
+      int& mt = maxt[G];
+      for (int k = c->an.col_lev_ptr[l]; k < c->an.col_lev_ptr[l + 1]; ++k) {
+        const int j = c->an.col_order[k];
+        v.push_back(make_int2(s, j));
+        // first pass: D, the U blocks and the forward row
+        mt = std::max(mt, 2 + c->an.colptr[j + 1] - c->an.colptr[j]);
       }
-      for (auto& kv : byG) {
-        // k0 = 1: a column per wave when its targets fit one pass of the
-        // wave's lane groups; 2: 1024 threads per column when the level has
-        // few columns and they need several passes of 256 threads
-        int wave = pass == 0 && maxt[kv.first] * kv.first <= 64 ? 1 : 0;
-        if (pass == 0 && !wave && kv.second.size() < 128 && maxt[kv.first] * kv.first > 256) wave = 2;
-        emit(pass == 0 ? L_FACTOR : L_FWD, pass == 0 ? PF_K_SPARSE_FACTOR : PF_K_SPARSE_FWD, kv.first, wave,
-             kv.second, fl[kv.first], by[kv.first]);
-      }
+      fl[G] += c->fac_flops[l];
+      by[G] += c->fac_bytes[l];
+    }
+    for (auto& kv : byG) {
+      // k0 = 1: a column per wave when its targets fit one pass of the
+      // wave's lane groups; 2: 1024 threads per column when the level has
+      // few columns and they need several passes of 256 threads
+      int wave = maxt[kv.first] * kv.first <= 64 ? 1 : 0;
+      if (!wave && kv.second.size() < 128 && maxt[kv.first] * kv.first > 256) wave = 2;
+      emit(L_FACTOR, PF_K_SPARSE_FACTOR, kv.first, wave, kv.second, fl[kv.first], by[kv.first]);
     }
   }
   // forward rows of the dense block, then the Schur complement into it
@@ -375,7 +373,7 @@ pf_status start_batch(Batch* b, const pf_options* opt) {
   pfd::launch_start(s, b->d_insts, b->nslots);
   {
     Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
-    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
+    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n, b->max_heavy);
   }
   pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
   return launch_status("pf_solve");
@@ -391,7 +389,7 @@ static void enqueue_lu_step(Batch* b, const pf_options* opt) {
     lu_solve<double>(b);
   {
     Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
-    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n);
+    pfd::launch_mismatch(s, b->d_insts, b->nslots, b->max_n, b->max_heavy);
   }
   pfd::launch_decide(s, b->d_insts, b->nslots, dev_opts(opt));
 }
@@ -464,7 +462,7 @@ pf_status step_batch(Batch* b, const pf_options* opt) {
     if (st != PF_OK) return st;
     {
       Prof p(b->ctx, PF_K_MISMATCH, 0.0, 0.0);
-      pfd::launch_mismatch(b->stream, b->d_insts, b->nslots, b->max_n);
+      pfd::launch_mismatch(b->stream, b->d_insts, b->nslots, b->max_n, b->max_heavy);
     }
     pfd::launch_decide(b->stream, b->d_insts, b->nslots, dev_opts(opt));
   } else if (!graph_step(b, opt)) {
