@@ -94,6 +94,7 @@ struct Inst {
   const int4 *kl_info, *ku_info;
   const int *bj_ptr, *bj_rows, *bj_loc;
   const int64_t* bj_off;
+  int* bjbad;  // per group: 1 when its inverse needs partial pivoting
   void *jval, *pval, *pdinv, *bjinv;
   void *kv;      // basis [(km+1) x 2 nu]
   void *kw, *kz, *kx;  // work vectors [2 nu]

@@ -26,6 +26,7 @@
 #include <cstdint>
 
 #include "blk.hpp"
+#include "mfma16.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -150,9 +151,103 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
   st_blk(D, r, inv);
 }
 
-// Block-Jacobi: inverse of the diagonal block of one node group (order N =
-// 2 x nodes <= 64) by Gauss-Jordan elimination with partial pivoting on
-// [A | I] in LDS (FP64), stored column-major at bj_off[b].
+// Block-Jacobi: inverse of the diagonal block A_bb of one node group (order
+// N = 2 x nodes <= 64), stored column-major at bj_off[b], in two launches:
+//   k_bj_inv_mfma: the block, padded with the identity to 64 x 64, inverted
+//     on the matrix cores by block Gauss-Jordan without pivoting (FP64); the
+//     result is kept when it is finite and max |A_bb X - I| <= 1e-6, else
+//     the group is marked (bjbad[b] = 1);
+//   k_bj_inv: the marked groups only, by Gauss-Jordan with partial pivoting
+//     on [A | I] in LDS (FP64).
+// Both compute A_bb^{-1}; pivoting changes only the rounding.
+constexpr double kBjResidualTol = 1e-6;
+
+// the group's block gathered into a row-major 64 x (64 + pad) LDS array
+// (identity outside N x N)
+template <typename T, int LD>
+__device__ inline void bj_gather(const Inst& I, int r0, int s, double (*A)[LD]) {
+  const int tid = threadIdx.x;
+  const int N = 2 * s;
+  for (int e = tid; e < 64 * 64; e += blockDim.x) {
+    const int i = e >> 6, c = e & 63;
+    A[i][c] = (i == c && i >= N) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int a = tid; a < s; a += blockDim.x) {
+    const int r = I.bj_rows[r0 + a];
+    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+      const int c = I.kcol[q];
+      const int l = I.bj_loc[c];
+      if (l < s && I.bj_rows[r0 + l] == c) {
+        const T* v = (const T*)I.jval + 4 * (int64_t)q;
+        A[2 * a][2 * l] = (double)v[0];
+        A[2 * a][2 * l + 1] = (double)v[1];
+        A[2 * a + 1][2 * l] = (double)v[2];
+        A[2 * a + 1][2 * l + 1] = (double)v[3];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bj_inv_mfma(const Inst* const* insts, const int2* __restrict__ work) {
+  __shared__ double A[64][65];
+  __shared__ double stage[8 * kStage];
+  __shared__ int bad_s;
+  const int2 wk = work[blockIdx.x];
+  const Inst& I = *insts[wk.x];
+  if (!I.red->active) return;
+  const int b = wk.y;
+  const int r0 = I.bj_ptr[b];
+  const int s = I.bj_ptr[b + 1] - r0;
+  const int N = 2 * s;
+  if (threadIdx.x == 0) bad_s = 0;
+  bj_gather<T, 65>(I, r0, s, A);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  // wave wv: block column wv in N-form
+  V4<double> d[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d[i][e] = A[16 * i + Mfma<double>::row(lane, e)][16 * wv + c];
+  inverse64<double>(d, stage, wv, lane);
+  // residual A X - I of this block column: (A X)_{i,wv} = sum_q A_iq X_{q,wv},
+  // A_iq^T in N-form read straight from the row-major array
+  bool bad = false;
+  const V4<double> zero = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    V4<double> acc = zero;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V4<double> at;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) at[e] = A[16 * i + c][16 * q + Mfma<double>::row(lane, e)];
+      acc = mm16<double>(at, d[q], acc);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * i + Mfma<double>::row(lane, e), col = 16 * wv + c;
+      const double r = acc[e] - (row == col ? 1.0 : 0.0);
+      bad = bad || !(fabs(r) <= kBjResidualTol) || !isfinite(d[i][e]);
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) bad_s = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) I.bjbad[b] = bad_s;
+  if (bad_s) return;
+  // stored column-major: entry (i, col) at col N + i
+  T* out = (T*)I.bjinv + I.bj_off[b];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * i + Mfma<double>::row(lane, e), col = 16 * wv + c;
+      if (row < N && col < N) out[col * N + row] = (T)d[i][e];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ double A[64][129];
@@ -164,6 +259,7 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
   const Inst& I = *insts[wk.x];
   if (!I.red->active) return;
   const int b = wk.y;
+  if (!I.bjbad[b]) return;  // inverted without pivoting
   const int r0 = I.bj_ptr[b];
   const int s = I.bj_ptr[b + 1] - r0;
   const int N = 2 * s;
@@ -1297,7 +1393,9 @@ void launch_ilu_rows(hipStream_t st, const Inst* const* insts, const int2* work,
 }
 template <typename T>
 void launch_bj_inv(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
-  if (nwork > 0) k_bj_inv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
+  if (nwork <= 0) return;
+  k_bj_inv_mfma<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
+  k_bj_inv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
 }
 template <typename T>
 void launch_ilu_fwd(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {

@@ -80,7 +80,7 @@ size_t krylov_bytes(const Case* c, int m) {
   size_t total = carve_bytes<int>(nu) + carve_bytes<int>(nu + 1) + carve_bytes<int>(knnz) + carve_bytes<int>(nu) +
                  carve_bytes<int>(c->nnz) + carve_bytes<int>(knnz + 1) + 2 * carve_bytes<int>(nup) +
                  carve_bytes<int>(nb + 1) + 2 * carve_bytes<int>(nu) + carve_bytes<int64_t>(nb + 1);
-  total += carve_bytes<int>(nl + 1) + carve_bytes<int>(nul + 1) + 2 * carve_bytes<int4>(nu);
+  total += carve_bytes<int>(nl + 1) + carve_bytes<int>(nul + 1) + 2 * carve_bytes<int4>(nu) + carve_bytes<int>(nb);
   total += 2 * carve_bytes<double>(4 * knnz) + carve_bytes<double>(4LL * nu) + carve_bytes<double>(ka.bj_off.back()) +
            carve_bytes<double>((km + 1) * n2) + 3 * carve_bytes<double>(n2);
   total += carve_bytes<double>(nh) + carve_bytes<double>(3LL * std::max(kchunks, 1) * (km + 1)) +
@@ -118,6 +118,7 @@ bool attach_krylov(Case* c, int m, char* base, bool own, hipStream_t s) {
   int* ku_ptr = carve<int>(p, nul + 1);
   int4* kl_info = carve<int4>(p, nu);
   int4* ku_info = carve<int4>(p, nu);
+  h.bjbad = carve<int>(p, nb);
   h.jval = carve<double>(p, 4 * knnz);
   h.pval = carve<double>(p, 4 * knnz);
   h.pdinv = carve<double>(p, 4LL * nu);
