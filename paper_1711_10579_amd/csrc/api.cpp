@@ -510,7 +510,9 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   total += carve_size<int>(c->ntt) + carve_size<int64_t>(c->ntt + 1) + 2 * carve_size<int>(ntail);
   total += carve_size<int>(nu + 1) + 2 * carve_size<int>(an.nnzl) + carve_size<int>(ns);
   total += carve_size<double>(n) + carve_size<int>(2LL * n) + carve_size<double>(6LL * n);
+  const int nmpart = (n + 63) / 64, nupart = (nu + 255) / 256;
   total += carve_size<pfd::Red>(1) + carve_size<pfd::Inst>(1) + carve_size<int>(c->nheavy);
+  total += carve_size<double>(nmpart) + carve_size<double>(nupart);
   c->bytes = total;
   c->wbytes = work_bytes(c);
   c->base = (char*)ctx->dalloc(total);
@@ -559,6 +561,8 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
   c->red = carve<pfd::Red>(p, 1);
   c->d_inst = carve<pfd::Inst>(p, 1);
   int* d_heavy = carve<int>(p, c->nheavy);
+  double* d_mpart = carve<double>(p, nmpart);
+  double* d_upart = carve<double>(p, nupart);
   if ((size_t)(p - c->base) != total) {
     ctx->dfree(c->base);
     delete c;
@@ -652,6 +656,10 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
     hi.node = c->node;
     hi.nheavy = c->nheavy;
     hi.heavy = d_heavy;
+    hi.nmpart = nmpart;
+    hi.nupart = nupart;
+    hi.mpart = d_mpart;
+    hi.upart = d_upart;
     hi.vm = c->vm;
     hi.va = c->va;
     hi.v = c->v;

@@ -62,6 +62,10 @@ struct Inst {
   // work-group of its own)
   int nheavy;
   const int* heavy;
+  // partial maxima of the mismatch (one per 64 rows) and of the update (one
+  // per 256 unknown nodes), reduced by the convergence test
+  int nmpart, nupart;
+  double *mpart, *upart;
   double *vm, *va, *v, *ibus, *F;
   void *x, *lu, *dinv, *tail, *dinvu;
   int* dflags;

@@ -52,6 +52,23 @@ __device__ inline Blk<T> group_sum(Blk<T> v) {
 
 __device__ inline bool inactive(const Inst& I) { return I.red->active == 0; }
 
+// max over a work-group of 256 threads (every thread calls it), stored by
+// thread 0 as the work-group's partial maximum (the instance's convergence
+// test reduces the partials; atomics on one address would serialise at the
+// cache)
+__device__ inline void block_max_store(double local, double* out) {
+  __shared__ double wmax[4];
+  local = wave_max(local);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) m = (wmax[w] > m || wmax[w] != wmax[w]) ? wmax[w] : m;
+    *out = m;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Newton driver on the device
 
@@ -107,17 +124,48 @@ __global__ void k_start(const Inst* const* insts, int nslots) {
   r.linear_iters = 0;
 }
 
+// max that keeps a NaN
+__device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// max of a[k] over k = tid, tid + 256, ... < n, four loads in flight
+__device__ inline double strided_max(const double* a, int n) {
+  double m = 0.0;
+  for (int k = threadIdx.x; k < n; k += 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = k + 256 * u < n ? a[k + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m = nanmax(m, v[u]);
+  }
+  return m;
+}
+
 // Convergence test of the Newton iteration (the loop condition of both
-// iteration tables, on the FP64 mismatch max-norm), divergence and limits.
+// iteration tables, on the FP64 mismatch max-norm), divergence and limits,
+// one work-group per instance: the max-norms of the mismatch and of the
+// last step are reduced from the work-groups' partial maxima (the rows of
+// the mismatch that run a work-group each fold theirs into norm_bits).
 // Sets status and active; prepares the step counters for the next step.
-__global__ void k_decide(const Inst* const* insts, int nslots, DevOpts o) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslots) return;
-  Red& r = *insts[s]->red;
+__global__ __launch_bounds__(256) void k_decide(const Inst* const* insts, DevOpts o) {
+  __shared__ double wm[2][4];
+  const Inst& I = *insts[blockIdx.x];
+  Red& r = *I.red;
   if (!r.active) return;
-  const double norm = __longlong_as_double((long long)r.norm_bits);
-  const double step = __longlong_as_double((long long)r.step_bits);
   const int it = r.it;
+  double nm = strided_max(I.mpart, I.nmpart);
+  double st = it > 0 ? strided_max(I.upart, I.nupart) : 0.0;
+  nm = wave_max(nm);
+  st = wave_max(st);
+  if ((threadIdx.x & 63) == 0) {
+    wm[0][threadIdx.x >> 6] = nm;
+    wm[1][threadIdx.x >> 6] = st;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  nm = nanmax(nanmax(wm[0][0], wm[0][1]), nanmax(wm[0][2], wm[0][3]));
+  st = nanmax(nanmax(wm[1][0], wm[1][1]), nanmax(wm[1][2], wm[1][3]));
+  const double norm = nanmax(nm, __longlong_as_double((long long)r.norm_bits));
+  const double step = st;
   r.last_norm = norm;
   if (it > 0) r.last_step = step;
   int status = -1;
@@ -188,21 +236,48 @@ __device__ inline double2 delta_current(const double* z, double2 vd) {
   return make_double2((sr * vd.x + si * vd.y) / w, (sr * vd.y - si * vd.x) / w);
 }
 
+// A row's own data besides its Ybus entries (its voltage, set-points, type,
+// ZIP coefficients and delta-load links), loaded before the row's sum so
+// that these loads do not wait behind it.
+struct RowSide {
+  double2 vi;
+  double psp, qsp, qg;
+  int type;
+  double z[6];
+  int2 dl;
+};
+__device__ inline RowSide load_side(const Inst& I, int i) {
+  RowSide s;
+  s.vi = ((const double2*)I.v)[i];
+  s.psp = I.psp[i];
+  s.qsp = I.qsp[i];
+  s.type = I.type[i];
+  s.qg = 0.0;
+  s.dl = make_int2(-1, -1);
+  if (I.model != 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s.z[k] = I.zip[6 * i + k];
+    if (s.type == 2) s.qg = I.qg[i];
+    if (I.dlink) s.dl = I.dlink[i];
+  }
+  return s;
+}
+
 // The rest of row i's mismatch once I_i = sum_j Y_ij V_j is known: polar dP,
 // dQ; CIM the ZIP load, the specified current, the delta loads and dI.
 // Writes F at the node's position (and the bus current for polar) and
 // returns the row's |F| (NaN when a value is NaN).
-__device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, double ii) {
+__device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, double ii, const RowSide& sd) {
   const double2* v = (const double2*)I.v;
-  const double2 vi = v[i];
+  const double2 vi = sd.vi;
   double local = 0.0;
   if (I.model == 0) {
     ((double2*)I.ibus)[i] = make_double2(ir, ii);
     if (p >= 0) {
       double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
       double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
-      double dp = I.psp[i] - sr;
-      double dq = I.type[i] == 1 ? I.qsp[i] - si : 0.0;
+      double dp = sd.psp - sr;
+      double dq = sd.type == 1 ? sd.qsp - si : 0.0;
       I.F[2 * p] = dp;
       I.F[2 * p + 1] = dq;
       local = fmax(fabs(dp), fabs(dq));
@@ -211,16 +286,16 @@ __device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, do
   } else {
     double w = vi.x * vi.x + vi.y * vi.y;
     double vm = sqrt(w);
-    const double* z = I.zip + 6 * i;
+    const double* z = sd.z;
     double pl = z[2] + z[1] * vm + z[0] * w;
     double ql = z[5] + z[4] * vm + z[3] * w;
-    const double qgen = I.type[i] == 2 ? I.qg[i] : I.qsp[i];
-    double ps = I.psp[i] - pl, qs = qgen - ql;
+    const double qgen = sd.type == 2 ? sd.qg : sd.qsp;
+    double ps = sd.psp - pl, qs = qgen - ql;
     // conj((ps + j qs) / V) = (ps - j qs) V / |V|^2
     double spr = (ps * vi.x + qs * vi.y) / w;
     double spi = (ps * vi.y - qs * vi.x) / w;
     if (I.dlink) {
-      const int2 L = I.dlink[i];
+      const int2 L = sd.dl;
       if (L.x >= 0) {
         const double2 vt = v[L.x];
         const double2 id = delta_current(I.zipd + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
@@ -271,16 +346,19 @@ constexpr int kMisLanes = 4;
 template <int S>
 __global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts) {
   const Inst& I = *insts[blockIdx.y];
-  if (inactive(I)) return;
-  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) / S);
+  constexpr int kRows = 256 / S;
+  if (inactive(I) || (int)blockIdx.x * kRows >= I.n) return;
   const int lane = threadIdx.x % S;
+  const int i = blockIdx.x * kRows + (int)threadIdx.x / S;
   double local = 0.0;
   bool mine = false;
   int p = -1;
   double ir = 0.0, ii = 0.0;
+  RowSide side;
   if (i < I.n) {
     p = I.pos[i];
     const int q0 = I.row_ptr[i], q1 = I.row_ptr[i + 1];
+    if (lane == 0) side = load_side(I, i);
     mine = (I.model == 0 || p >= 0) && q1 - q0 <= kHeavyRow;
     if (mine) ydot_part<S>(I, q0 + lane, q1, ir, ii);
   }
@@ -289,9 +367,8 @@ __global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts) {
     ir += __shfl_xor(ir, off, 64);
     ii += __shfl_xor(ii, off, 64);
   }
-  if (mine && lane == 0) local = mismatch_row(I, i, p, ir, ii);
-  local = wave_max(local);
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
+  if (mine && lane == 0) local = mismatch_row(I, i, p, ir, ii, side);
+  block_max_store(local, I.mpart + blockIdx.x);
 }
 
 // Rows with more than kHeavyRow entries (listed per instance in I.heavy): one
@@ -319,7 +396,7 @@ __global__ __launch_bounds__(256) void k_mismatch_heavy(const Inst* const* insts
   if (threadIdx.x == 0) {
     ir = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
     ii = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
-    const double local = mismatch_row(I, i, p, ir, ii);
+    const double local = mismatch_row(I, i, p, ir, ii, load_side(I, i));
     if (local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
   }
 }
@@ -873,11 +950,11 @@ __global__ __launch_bounds__(256) void k_bwd_rows(const Inst* const* insts, cons
 // (eq. 20 pairing; three-phase iteration table, update and complex-form
 // lines), on PV nodes angle += dx[2p] and Q_g += dx[2p+1].  Refreshes the rectangular voltage and records max |dx|.
 template <typename T>
-__global__ void k_update(const Inst* const* insts) {
+__global__ __launch_bounds__(256) void k_update(const Inst* const* insts) {
   const Inst& I = *insts[blockIdx.y];
-  if (inactive(I)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inactive(I) || (int)(blockIdx.x * blockDim.x) >= I.nu) return;
   double local = 0.0;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < I.nu) {
     const T* x = (const T*)I.x;
     const int i = I.node[p];
@@ -904,11 +981,11 @@ __global__ void k_update(const Inst* const* insts) {
       double2 vv = ((double2*)I.v)[i];
       ((double2*)I.v)[i] = make_double2(vv.x + d0, vv.y + d1);
     }
-    local = fmax(fabs(d0), fabs(d1));
-    if (!(local == local)) local = __longlong_as_double(0x7ff8000000000000ll);
+    double m = fmax(fabs(d0), fabs(d1));
+    if (!(m == m)) m = __longlong_as_double(0x7ff8000000000000ll);
+    local = m;
   }
-  local = wave_max(local);
-  if ((threadIdx.x & 63) == 0 && local != 0.0) atomic_max_nonneg(&I.red->step_bits, local);
+  block_max_store(local, I.upart + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -935,7 +1012,7 @@ void launch_start(hipStream_t st, const Inst* const* insts, int nslots) {
   k_start<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots);
 }
 void launch_decide(hipStream_t st, const Inst* const* insts, int nslots, DevOpts o) {
-  k_decide<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, o);
+  k_decide<<<dim3((unsigned)nslots), 256, 0, st>>>(insts, o);
 }
 void launch_gather_red(hipStream_t st, const Inst* const* insts, int nslots, Red* out) {
   k_gather_red<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, out);
