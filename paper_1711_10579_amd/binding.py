@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libexagridpf.so")
+# PF_LIB selects another build of the same library (the host-sanitizer
+# variant, see sanitize.py)
+LIB_PATH = os.environ.get("PF_LIB") or os.path.join(_HERE, "_lib", "libexagridpf.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
