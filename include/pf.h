@@ -370,8 +370,8 @@ typedef enum {
   PF_K_DENSE_PANEL = 4,    /* dense block step: diagonal-block inverse, row tiles, trailing update */
   PF_K_DENSE_UPDATE = 5,   /* not launched: the dense trailing update runs in the block-step launch */
   PF_K_SPARSE_FWD = 6,
-  PF_K_SPARSE_BWD = 7,
-  PF_K_DENSE_TRSV = 8,
+  PF_K_SPARSE_BWD = 7,     /* not launched: the sparse backward rows run in the backward-solve launch */
+  PF_K_DENSE_TRSV = 8,     /* backward solve: the dense block's 64-row blocks, then the sparse rows, one launch */
   PF_K_UPDATE = 9,
   PF_K_KRYLOV = 10,        /* GMRES: begin, SpMV + dots, orthogonalisation, rotations, restarts */
   PF_K_PRECOND_SETUP = 11, /* ILU(0) factor by levels or block-Jacobi inverses            */

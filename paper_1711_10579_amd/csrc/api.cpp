@@ -726,11 +726,12 @@ pf_status create_case(Ctx* ctx, const pf_case_desc* d, const pf_schedule& sched,
 
 // Working storage of a solve: factor values (D | L | U blocks), the inverted
 // 2x2 diagonal blocks, the dense block with its right-hand side column, its
-// 64x64 diagonal-block inverses, and the dense block's two flag arrays.
+// 64x64 diagonal-block inverses, the block step's flags, and the backward
+// solve's published copy of the solution.
 size_t work_bytes(const Case* c) {
   return carve_size<double>(c->lu_count()) + carve_size<double>(4LL * c->an.ns) +
-         carve_size<double>(c->tail_count()) + carve_size<double>(c->dinvu_count()) + carve_size<int>(c->nblk()) +
-         carve_size<unsigned long long>(c->nblk());
+         carve_size<double>(c->tail_count()) + carve_size<double>(c->dinvu_count()) +
+         carve_size<unsigned long long>(c->nblk()) + carve_size<double>(2LL * c->an.nu);
 }
 
 void attach_work(Case* c, char* base, bool own, hipStream_t s) {
@@ -739,8 +740,8 @@ void attach_work(Case* c, char* base, bool own, hipStream_t s) {
   c->dinv = carve<double>(p, 4LL * c->an.ns);
   c->tail = carve<double>(p, c->tail_count());
   c->dinvu = carve<double>(p, c->dinvu_count());
-  c->dflags = carve<int>(p, c->nblk());
   c->pflags = carve<unsigned long long>(p, c->nblk());
+  c->xs = carve<double>(p, 2LL * c->an.nu);
   c->wbase = base;
   c->wown = own;
   pfd::Inst& h = c->hinst;
@@ -748,11 +749,10 @@ void attach_work(Case* c, char* base, bool own, hipStream_t s) {
   h.dinv = c->dinv;
   h.tail = c->tail;
   h.dinvu = c->dinvu;
-  h.dflags = c->dflags;
+  h.xs = c->xs;
   h.pflags = c->pflags;
   // the flags carry Newton-step epochs, which only grow within one case:
   // storage that another case used starts from zero (below every epoch)
-  pfd::launch_zero_words(s, c->dflags, (int64_t)std::max(c->nblk(), 1));
   pfd::launch_zero_words(s, c->pflags, 2LL * std::max(c->nblk(), 1));
   pfd::launch_set_inst(s, c->d_inst, h);
 }
@@ -773,7 +773,7 @@ void detach_work(Case* c) {
   c->wbase = nullptr;
   c->wown = false;
   c->lu = c->dinv = c->tail = c->dinvu = nullptr;
-  c->dflags = nullptr;
+  c->xs = nullptr;
   c->pflags = nullptr;
 }
 

@@ -107,4 +107,42 @@ __device__ inline bool blk_inv(const Blk<T>& m, Blk<T>* out) {
   return true;
 }
 
+// sum over the G lanes of a group (G a power of two, groups aligned to G)
+template <typename T, int G>
+__device__ inline Blk<T> group_sum(Blk<T> v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    v.a += __shfl_xor(v.a, off, 64);
+    v.b += __shfl_xor(v.b, off, 64);
+    v.c += __shfl_xor(v.c, off, 64);
+    v.d += __shfl_xor(v.d, off, 64);
+  }
+  return v;
+}
+
+// Marker of a solution entry not yet computed: a signalling NaN with a fixed
+// payload.  Arithmetic never produces a signalling NaN (its NaN results are
+// quiet) and the inputs are finite, so a stored solution value never has
+// these bits.
+template <typename T>
+struct Unsolved;
+template <>
+struct Unsolved<double> {
+  typedef unsigned long long U;
+  static constexpr U bits = 0x7FF4DEADBEEFCAFEull;
+};
+template <>
+struct Unsolved<float> {
+  typedef unsigned int U;
+  static constexpr U bits = 0x7FA5DEADu;
+};
+template <typename T>
+__device__ inline bool unsolved(T v) {
+  return __builtin_bit_cast(typename Unsolved<T>::U, v) == Unsolved<T>::bits;
+}
+template <typename T>
+__device__ inline T unsolved_value() {
+  return __builtin_bit_cast(T, Unsolved<T>::bits);
+}
+
 }  // namespace pfd

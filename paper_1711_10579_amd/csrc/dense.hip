@@ -421,96 +421,245 @@ __global__ __launch_bounds__(256, 2) void k_dense_step(const Inst* const* insts,
     gemm_tile<T>(insts, work[b - 3 * npanel], k0, smem);
 }
 
-// Block backward solve (z in column M): by 64-row blocks, acc = z_b -
-// sum_{c > b} A_bc x_c (columns taken from the last block down), then x_b =
-// P_b acc with the diagonal block's inverse made by the panel step.
-// Flag mode, item (slot, w): work-group w owns block b = nblk-1-w and waits
-// only for blocks of the same instance listed before it (dispatched before
-// it, so the earliest unfinished block waits on nothing); results are
-// published with an agent-scope release of dflags[b] = epoch, acquired by
-// readers; the U tile of the next block is loaded before waiting for its
-// flag; a wait is bounded in device time and records a timeout on expiry.  Single mode, item (slot, 0): one work-group runs all
-// blocks of its instance in order.  Both modes do the same arithmetic.
+// ---------------------------------------------------------------------------
+// Backward solve of the whole factorisation in one launch (the triangular
+// solve that follows the refactorisation, Sec. III-A): the dense block's
+// 64-row blocks, then the sparse rows by backward level.  Every solution
+// entry is published in xs (marked unsolved before the solve) with a
+// device-coherent store of the value itself; a reader polls the entries it
+// needs until they lose the mark, so one memory round trip hands a value
+// over (no flag, no fence).  Every wait is on a work-group listed earlier in
+// the launch (or on the same work-group's earlier block in single mode);
+// work-groups are dispatched in index order, so the earliest unfinished one
+// waits on nothing.  A wait is bounded in device time: on expiry the
+// instance records a timeout, and every other wait of the instance gives up
+// as soon as it sees that.
+
+// The entries p[0..n) of the published solution once none is marked
+// unsolved (all loads in flight at once, then only the missing ones again);
+// false when the instance has timed out or the bound passed.
+template <typename T, int N>
+__device__ inline bool await_solved(const T* p, const bool (&use)[N], T (&v)[N], const Inst& I,
+                                    unsigned long long t0) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = use[j] ? ld_dev(p + j) : T(0);
+  for (;;) {
+    bool miss = false;
+#pragma unroll
+    for (int j = 0; j < N; ++j) miss = miss || unsolved(v[j]);
+    if (!miss) return true;
+    if (ld_dev(&I.red->timeout) != 0) return false;
+    if (rt_now() - t0 > kWaitTicks) {
+      st_dev(&I.red->timeout, 1);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (unsolved(v[j])) v[j] = ld_dev(p + j);
+  }
+}
+
+constexpr int kBwdLd = NB + 1;
+
+// One 64-row block b of the dense block, 256 threads:
+//   x_b = P_b (z_b - sum_{c > b+1} A_bc x_c - A_{b,b+1} x_{b+1})
+// with P_b the diagonal block's inverse from the block step and z in column
+// M.  The blocks right of b + 1 are summed as their solutions arrive, wave
+// wv taking columns 16 wv .. 16 wv + 15 of each (a partial sum per row);
+// wave 0 then waits for x_{b+1} and finishes the block with P_b and A_{b,b+1}
+// staged in LDS (the two matrix-vector products of the chain, four partial
+// sums each, inside one wave: no barrier between the wait and the store).
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_trsv(const Inst* const* insts, const int2* __restrict__ work,
-                                                    int single) {
-  __shared__ T part[4][NB];
-  __shared__ T acc[NB];
-  __shared__ int abort_flag;
-  const int2 wk = work[blockIdx.x];
-  const Inst& I = *insts[wk.x];
-  if (I.red->active == 0) return;
-  const T* A = (const T*)I.tail;
+__device__ __forceinline__ void bwd_block(const Inst& I, int b, T* smem, int* abort_flag, unsigned long long t0) {
+  T(*sP)[kBwdLd] = (T(*)[kBwdLd])smem;                  // sP[j][r] = P_b(r, j)
+  T(*sA)[kBwdLd] = (T(*)[kBwdLd])(smem + NB * kBwdLd);  // sA[j][r] = A(b0 + r, b0 + 64 + j)
+  T* part = smem + 2 * NB * kBwdLd;                     // [4][NB] partial sums
+  T* xl = part + 4 * NB;                                // x_{b+1}
+  T* al = xl + NB;                                      // the reduced right-hand side
+  const auto G = gp((const T*)I.tail);
   const int ld = I.ldt, M = I.M;
-  T* out = (T*)I.x + 2 * I.ns;
-  const int tid = threadIdx.x;
   const int nblk = (M + NB - 1) / NB;
-  const int lane_r = tid % NB, quarter = tid / NB;
-  const int epoch = I.red->epoch;
-  const int bfirst = single ? nblk - 1 : nblk - 1 - wk.y;
-  const int blast = single ? 0 : bfirst;
-  if (tid == 0) abort_flag = 0;
-  for (int b = bfirst; b >= blast; --b) {
-    const int b0 = b * NB;
-    const int bl = min(NB, M - b0);
-    // this block's U^{-1} entries (independent of the solve): loaded first
-    T uiv[16];
-    {
-      const T* ui = (const T*)I.dinvu + (int64_t)b * NB * NB;
+  const int b0 = b * NB, bl = min(NB, M - b0);
+  T* xs = (T*)I.xs + 2 * I.ns;
+  T* out = (T*)I.x + 2 * I.ns;
+  const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6;
+  const auto ui = gp((const T*)I.dinvu + (int64_t)b * NB * NB);
+  const bool has1 = b + 1 < nblk;
+  const int c1 = b0 + NB, cl1 = has1 ? min(NB, M - c1) : 0;
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int idx = tid + 256 * q, j = idx >> 6, rr = idx & 63;
+    sP[j][rr] = ui[(int64_t)j * NB + rr];
+    sA[j][rr] = (rr < bl && j < cl1) ? G[(int64_t)(c1 + j) * ld + b0 + rr] : T(0);
+  }
+  // the blocks right of b + 1
+  T pacc = T(0);
+  bool ok = true;
+  for (int c = nblk - 1; c >= b + 2 && ok; --c) {
+    const int c0 = c * NB, cl = min(NB, M - c0);
+    T a[16], xv[16];
+    bool use[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) uiv[q] = ui[(int64_t)(quarter + 4 * q) * NB + lane_r];
+    for (int j = 0; j < 16; ++j) {
+      const int col = 16 * wv + j;
+      use[j] = col < cl;
+      a[j] = (r < bl && use[j]) ? G[(int64_t)(c0 + col) * ld + b0 + r] : T(0);
     }
-    __syncthreads();
-    if (tid < NB) acc[tid] = tid < bl ? A[(int64_t)M * ld + b0 + tid] : T(0);
-    __syncthreads();
-    for (int cb = nblk - 1; cb > b; --cb) {
-      const int c0 = cb * NB;
-      const int cl = min(NB, M - c0);
-      T u[16];
+    ok = await_solved<T, 16>(xs + c0 + 16 * wv, use, xv, I, t0);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = quarter + 4 * q;
-        u[q] = (lane_r < bl && c < cl) ? A[(int64_t)(c0 + c) * ld + b0 + lane_r] : T(0);
+    for (int j = 0; j < 16; ++j) pacc = fma(a[j], xv[j], pacc);
+  }
+  part[wv * NB + r] = pacc;
+  if (!ok) *abort_flag = 1;
+  __syncthreads();
+  if (wv == 0 && *abort_flag == 0) {
+    T acc = r < bl ? G[(int64_t)M * ld + b0 + r] : T(0);
+    acc -= ((part[r] + part[NB + r]) + part[2 * NB + r]) + part[3 * NB + r];
+    if (has1) {
+      bool use1[1] = {r < cl1};
+      T v1[1];
+      ok = await_solved<T, 1>(xs + c1 + r, use1, v1, I, t0);
+      xl[r] = v1[0];
+      __builtin_amdgcn_wave_barrier();
+      T t4[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 8
+      for (int j = 0; j < NB; ++j) t4[j & 3] = fma(sA[j][r], xl[j], t4[j & 3]);
+      acc -= (t4[0] + t4[1]) + (t4[2] + t4[3]);
+    }
+    al[r] = acc;
+    __builtin_amdgcn_wave_barrier();
+    T y4[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 8
+    for (int j = 0; j < NB; ++j) y4[j & 3] = fma(sP[j][r], al[j], y4[j & 3]);
+    const T xb = (y4[0] + y4[1]) + (y4[2] + y4[3]);
+    if (__builtin_amdgcn_ballot_w64(!ok) != 0) {
+      if (r == 0) *abort_flag = 1;
+    } else if (r < bl) {
+      out[b0 + r] = xb;
+      st_dev(xs + b0 + r, xb);
+    }
+  }
+  __syncthreads();
+}
+
+// Rows of one backward level, G lanes per row:
+//   x_i = D_i^{-1} (y_i - sum_j U(i,j) x_j)
+// (y_i in x, the entries x_j of the published solution, waited for; the
+// result into both).
+template <typename T, int G>
+__device__ __forceinline__ void bwd_rows(const Inst* const* insts, const int2* __restrict__ rows, int count, unsigned long long t0) {
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  if (g >= count) return;  // whole groups leave together
+  const int2 w = rows[g];
+  const Inst& I = *insts[w.x];
+  if (I.red->active == 0) return;
+  const T* lu = (const T*)I.lu;
+  T* x = (T*)I.x;
+  T* xs = (T*)I.xs;
+  const int i = w.y;
+  Blk<T> acc = {T(0), T(0), T(0), T(0)};
+  if (lane == 0) {
+    acc.a = x[2 * i];
+    acc.c = x[2 * i + 1];
+  }
+  // the inverted diagonal block first (it does not depend on the solve)
+  Blk<T> D = {T(0), T(0), T(0), T(0)};
+  if (lane == 0) D = ld_blk((const T*)I.dinv, i);
+  bool ok = true;
+  {
+    // four entries' loads at once, applied in order
+    const int q1 = I.colptr[i + 1];
+    for (int q = I.colptr[i] + lane; q < q1 && ok; q += 4 * G) {
+      int jj[4];
+      Blk<T> U[4];
+      bool use[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        use[u] = q + u * G < q1;
+        jj[u] = use[u] ? I.rowidx[q + u * G] : 0;
+        if (use[u]) U[u] = ld_blk(lu, (int64_t)I.ns + I.nnzl + q + u * G);
       }
-      if (!single) {
-        if (tid == 0) {
-          // poll without ordering, then one acquire once the flag is seen
-          const unsigned long long t_start = rt_now();
-          while (__hip_atomic_load(&I.dflags[cb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            if (rt_now() - t_start > kWaitTicks) {
-              abort_flag = 1;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      T xv[8];
+      bool use2[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) use2[2 * u] = use2[2 * u + 1] = use[u];
+      // the entries of the four columns, waited for together
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = use2[u] ? ld_dev(xs + 2 * jj[u / 2] + (u & 1)) : T(0);
+      for (;;) {
+        bool miss = false;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) miss = miss || unsolved(xv[u]);
+        if (!miss) break;
+        if (ld_dev(&I.red->timeout) != 0) {
+          ok = false;
+          break;
         }
-        __syncthreads();
-        if (abort_flag) break;
-      }
-      T sum = T(0);
+        if (rt_now() - t0 > kWaitTicks) {
+          st_dev(&I.red->timeout, 1);
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int c = quarter + 4 * q;
-        if (c < cl) sum += u[q] * out[c0 + c];
+        for (int u = 0; u < 8; ++u)
+          if (unsolved(xv[u])) xv[u] = ld_dev(xs + 2 * jj[u / 2] + (u & 1));
       }
-      part[quarter][lane_r] = sum;
-      __syncthreads();
-      if (tid < NB) acc[tid] -= part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-      __syncthreads();
-    }
-    if (abort_flag) {
-      if (tid == 0) I.red->timeout = 1;
-      return;
-    }
-    T sum = T(0);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) sum += uiv[q] * acc[quarter + 4 * q];
-    part[quarter][lane_r] = sum;
+      for (int u = 0; u < 4; ++u)
+        if (use[u]) {
+          acc.a -= U[u].a * xv[2 * u] + U[u].b * xv[2 * u + 1];
+          acc.c -= U[u].c * xv[2 * u] + U[u].d * xv[2 * u + 1];
+        }
+    }
+  }
+  acc = group_sum<T, G>(acc);
+  if (__builtin_amdgcn_ballot_w64(!ok) != 0) return;
+  if (lane == 0) {
+    const T x0 = D.a * acc.a + D.b * acc.c;
+    const T x1 = D.c * acc.a + D.d * acc.c;
+    x[2 * i] = x0;
+    x[2 * i + 1] = x1;
+    st_dev(xs + 2 * i, x0);
+    st_dev(xs + 2 * i + 1, x1);
+  }
+}
+
+// Work-groups [0, nd): dense blocks (item (slot, w): block nblk - 1 - w, or
+// in single mode (slot, 0): every block of the instance in order); then one
+// work-group per descriptor work[b] = (offset of its first row item,
+// rows | G << 16): rows of one backward level and one lane-group size.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_bwd_solve(const Inst* const* insts, const int2* __restrict__ work, int nd,
+                                                   int single) {
+  __shared__ T smem[2 * NB * kBwdLd + 6 * NB];
+  __shared__ int abort_flag;
+  const unsigned long long t0 = rt_now();
+  const int2 wk = work[blockIdx.x];
+  if ((int)blockIdx.x < nd) {
+    const Inst& I = *insts[wk.x];
+    if (I.red->active == 0 || I.M == 0) return;
+    const int nblk = (I.M + NB - 1) / NB;
+    if (threadIdx.x == 0) abort_flag = 0;
     __syncthreads();
-    if (tid < bl) out[b0 + tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-    __syncthreads();
-    if (!single && tid == 0) __hip_atomic_store(&I.dflags[b], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (single) {
+      for (int b = nblk - 1; b >= 0 && abort_flag == 0; --b) bwd_block<T>(I, b, smem, &abort_flag, t0);
+    } else {
+      bwd_block<T>(I, nblk - 1 - wk.y, smem, &abort_flag, t0);
+    }
+    return;
+  }
+  const int2* rows = work + wk.x;
+  const int count = wk.y & 0xffff, G = wk.y >> 16;
+  switch (G) {
+    case 1: bwd_rows<T, 1>(insts, rows, count, t0); break;
+    case 2: bwd_rows<T, 2>(insts, rows, count, t0); break;
+    case 4: bwd_rows<T, 4>(insts, rows, count, t0); break;
+    case 8: bwd_rows<T, 8>(insts, rows, count, t0); break;
+    case 16: bwd_rows<T, 16>(insts, rows, count, t0); break;
+    case 32: bwd_rows<T, 32>(insts, rows, count, t0); break;
+    default: bwd_rows<T, 64>(insts, rows, count, t0); break;
   }
 }
 
@@ -524,14 +673,14 @@ void launch_dense_step(hipStream_t st, const Inst* const* insts, const int2* wor
 }
 
 template <typename T>
-void launch_dense_trsv(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int single) {
-  if (nwork <= 0) return;
-  k_dense_trsv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work, single);
+void launch_bwd_solve(hipStream_t st, const Inst* const* insts, const int2* work, int nd, int nrw, int single) {
+  if (nd + nrw <= 0) return;
+  k_bwd_solve<T><<<dim3((unsigned)(nd + nrw)), 256, 0, st>>>(insts, work, nd, single);
 }
 
 #define PF_DINST(T)                                                                        \
   template void launch_dense_step<T>(hipStream_t, const Inst* const*, const int2*, int, int, int, int); \
-  template void launch_dense_trsv<T>(hipStream_t, const Inst* const*, const int2*, int, int);
+  template void launch_bwd_solve<T>(hipStream_t, const Inst* const*, const int2*, int, int, int);
 
 PF_DINST(double)
 PF_DINST(float)

@@ -68,7 +68,10 @@ struct Inst {
   double *mpart, *upart;
   double *vm, *va, *v, *ibus, *F;
   void *x, *lu, *dinv, *tail, *dinvu;
-  int* dflags;
+  // the backward solve's published copy of the solution (2 nu values),
+  // marked unsolved before each solve: a row or block waits for the entries
+  // it needs to lose the mark
+  void* xs;
   // per 64-row block i of the dense block: (epoch << 20) | (k + 1) once the
   // panel of block step k has stored its tile L_ik
   unsigned long long* pflags;

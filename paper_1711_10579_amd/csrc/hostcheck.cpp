@@ -185,6 +185,92 @@ void check_dense_plan(const std::vector<int>& Ms, int64_t* nchk) {
   }
 }
 
+
+// Replays the backward solve's launch plan (one launch) over copies of one
+// analysed case with per-level lane counts gs.  Work-groups run in list
+// order; every entry a work-group waits for must come from an earlier
+// work-group: a dense block (flag mode) needs every block after it of its
+// instance, a single-mode work-group runs its instance's blocks in order,
+// and a sparse row needs its U columns, either rows of earlier work-groups
+// (so never a row of its own work-group) or the dense blocks holding their
+// entries.  Each work-group descriptor covers rows of one level and one lane
+// count, at most 256 / G of them; every block and row is solved exactly once.
+void check_bwd_plan(const pfh::Analysis& an, int M, const std::vector<int>& gs, int copies, bool single,
+                    int64_t* nchk) {
+  const int ns = an.ns;
+  std::vector<BwdInput> in(copies);
+  for (auto& x : in) {
+    x.M = M;
+    x.lev_ptr = &an.bwd_lev_ptr;
+    x.rows = &an.bwd_rows;
+    x.g = &gs;
+  }
+  std::vector<int2> items;
+  int nd = 0, nrw = 0;
+  bwd_plan(in, single, &items, &nd, &nrw);
+  req(nd >= 0 && nrw >= 0 && (int64_t)nd + nrw <= (int64_t)items.size(), "backward plan: item counts");
+  const int nblk = (M + 63) / 64;
+  std::vector<std::vector<int>> blk_wg(copies, std::vector<int>(nblk, -1)), row_wg(copies, std::vector<int>(ns, -1));
+  std::vector<int> blev(ns, -1);
+  for (int l = 0; l + 1 < (int)an.bwd_lev_ptr.size(); ++l)
+    for (int k = an.bwd_lev_ptr[l]; k < an.bwd_lev_ptr[l + 1]; ++k) blev[an.bwd_rows[k]] = l;
+  for (int k = 0; k < nd; ++k) {
+    const int s = items[k].x, w = items[k].y;
+    ++*nchk;
+    req(s >= 0 && s < copies && M > 0, "backward plan: dense item of an instance without a dense block");
+    if (single) {
+      req(w == 0, "backward plan: single-mode item");
+      for (int b = nblk - 1; b >= 0; --b) {
+        req(blk_wg[s][b] < 0, "backward plan: dense block solved twice");
+        blk_wg[s][b] = k;
+      }
+      continue;
+    }
+    const int b = nblk - 1 - w;
+    req(b >= 0 && b < nblk, "backward plan: dense block out of range");
+    req(blk_wg[s][b] < 0, "backward plan: dense block solved twice");
+    for (int c = b + 1; c < nblk; ++c)
+      req(blk_wg[s][c] >= 0 && blk_wg[s][c] < k, "backward plan: a dense block waits on a later work-group");
+    blk_wg[s][b] = k;
+  }
+  std::vector<int> covered(items.size(), 0);
+  for (int k = nd; k < nd + nrw; ++k) {
+    const int off = items[k].x, cnt = items[k].y & 0xffff, G = items[k].y >> 16;
+    ++*nchk;
+    req(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "backward plan: lanes per row");
+    req(cnt >= 1 && cnt <= 256 / G, "backward plan: rows of a work-group");
+    req(off >= nd + nrw && (int64_t)off + cnt <= (int64_t)items.size(), "backward plan: row items out of range");
+    int lvl = -1;
+    for (int g = 0; g < cnt; ++g) {
+      req(covered[off + g]++ == 0, "backward plan: a row item in two work-groups");
+      const int s = items[off + g].x, i = items[off + g].y;
+      req(s >= 0 && s < copies && i >= 0 && i < ns, "backward plan: row out of range");
+      req(row_wg[s][i] < 0, "backward plan: row solved twice");
+      req(lvl < 0 || blev[i] == lvl, "backward plan: rows of two levels in one work-group");
+      lvl = blev[i];
+      req(gs[lvl] == G, "backward plan: lanes per row differ from the level's");
+      for (int q = an.colptr[i]; q < an.colptr[i + 1]; ++q) {
+        const int jj = an.rowidx[q];
+        ++*nchk;
+        if (jj >= ns) {
+          const int p0 = 2 * (jj - ns);
+          req(p0 + 1 < M, "backward plan: dense entry out of range");
+          for (int b : {p0 / 64, (p0 + 1) / 64})
+            req(blk_wg[s][b] >= 0 && blk_wg[s][b] < k, "backward plan: a row waits on a dense block of a later work-group");
+        } else {
+          req(row_wg[s][jj] >= 0 && row_wg[s][jj] < k, "backward plan: a row waits on its own or a later work-group");
+        }
+      }
+    }
+    for (int g = 0; g < cnt; ++g) row_wg[items[off + g].x][items[off + g].y] = k;
+  }
+  for (int s = 0; s < copies; ++s) {
+    for (int b = 0; b < nblk; ++b) req(blk_wg[s][b] >= 0, "backward plan: dense block never solved");
+    for (int i = 0; i < ns; ++i) req(row_wg[s][i] >= 0, "backward plan: row never solved");
+  }
+  for (size_t q = nd + nrw; q < items.size(); ++q) req(covered[q] == 1, "backward plan: row item outside every work-group");
+}
+
 }  // namespace
 
 extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, const pf_schedule* sched, uint64_t seed,
@@ -429,6 +515,16 @@ extern "C" pf_status pf_debug_schedule_check(const pf_case_desc* d, const pf_sch
       bn = std::max(bn, std::fabs(b[i]));
     }
     *rel_residual = rn / (anorm * xn + bn);
+    // the backward solve's launch plan: one lane count everywhere, then
+    // mixed per level; alone, batched, and in single mode
+    {
+      const int nbl = (int)an.bwd_lev_ptr.size() - 1;
+      std::vector<int> g1(nbl, 1), g64(nbl, 64), gmix(nbl);
+      for (int l = 0; l < nbl; ++l) gmix[l] = 1 << (l % 7);
+      for (const auto* gs : {&g1, &g64, &gmix})
+        for (int copies : {1, 3})
+          for (bool single : {false, true}) check_bwd_plan(an, M, *gs, copies, single, &nchk);
+    }
     // the dense block's launch plan, alone and batched with other orders
     if (M > 0) {
       check_dense_plan({M}, &nchk);

@@ -119,7 +119,7 @@ struct Case {
   int *pos = nullptr, *node = nullptr;
   double *vm = nullptr, *va = nullptr, *v = nullptr, *ibus = nullptr, *F = nullptr;
   void *x = nullptr, *lu = nullptr, *dinv = nullptr, *tail = nullptr, *dinvu = nullptr;
-  int* dflags = nullptr;  // per 64-row block of the dense block: backward-solve flags
+  void* xs = nullptr;     // the backward solve's published copy of the solution (2 nu values)
   unsigned long long* pflags = nullptr;  // per 64-row block: panel-tile flags
   int *colptr = nullptr, *rowidx = nullptr, *upd_l = nullptr, *upd_u = nullptr, *col_order = nullptr;
   int64_t* uptr = nullptr;
@@ -157,7 +157,7 @@ struct Launch {
   int count;       // work items
   double flops, bytes;
 };
-enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_TRSV, L_BWD };
+enum { L_FACTOR = 0, L_FWD, L_SCHUR, L_PANEL, L_BWD };
 
 // A batch of cases: device instance table, flattened work lists and the
 // launch sequence of one Newton step's LU solve.  Each item's arithmetic
@@ -276,6 +276,17 @@ pf_status nk_step(Batch* b, const pf_options* opt);
 constexpr int kDenseNB = 64;
 void dense_grid(int M, int k, int* kb, int* nrt, int* nct);
 void dense_plan_step(const std::vector<int>& Ms, int k0, std::vector<int2>* items, int* nflag, int* npanel);
+// The backward solve's work list (one launch): nd dense items, then nrw
+// work-group descriptors (offset of the first row item, rows | G << 16),
+// then the row items (slot, row).  Per instance: dense order M, backward
+// level pointers and rows of the sparse part, lanes per row of each level.
+struct BwdInput {
+  int M = 0;
+  const std::vector<int>* lev_ptr = nullptr;
+  const std::vector<int>* rows = nullptr;
+  const std::vector<int>* g = nullptr;
+};
+void bwd_plan(const std::vector<BwdInput>& in, bool single, std::vector<int2>* items, int* nd, int* nrw);
 
 // Run the Newton iteration of every case of a built batch to completion.
 pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results);

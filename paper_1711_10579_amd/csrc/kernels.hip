@@ -38,18 +38,6 @@ __device__ inline double wave_max(double local) {
   return local;
 }
 
-template <typename T, int G>
-__device__ inline Blk<T> group_sum(Blk<T> v) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) {
-    v.a += __shfl_xor(v.a, off, 64);
-    v.b += __shfl_xor(v.b, off, 64);
-    v.c += __shfl_xor(v.c, off, 64);
-    v.d += __shfl_xor(v.d, off, 64);
-  }
-  return v;
-}
-
 __device__ inline bool inactive(const Inst& I) { return I.red->active == 0; }
 
 // max over a work-group of 256 threads (every thread calls it), stored by
@@ -423,12 +411,17 @@ __global__ __launch_bounds__(256) void k_zero_chunks(const Inst* const* insts, c
   for (int64_t i = b + threadIdx.x; i < e; i += 256) p[i] = T(0);
 }
 
+// The right-hand side F into x; every entry of the backward solve's
+// published copy of the solution marked unsolved.
 template <typename T>
 __global__ void k_copy_rhs(const Inst* const* insts) {
   const Inst& I = *insts[blockIdx.y];
   if (inactive(I)) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 2 * I.nu) ((T*)I.x)[i] = (T)I.F[i];
+  if (i < 2 * I.nu) {
+    ((T*)I.x)[i] = (T)I.F[i];
+    ((T*)I.xs)[i] = unsolved_value<T>();
+  }
 }
 
 template <typename T>
@@ -888,60 +881,6 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, cons
   fwd_row<T, G>(I, (const T*)I.lu, (T*)I.x, w.y, lane);
 }
 
-// x_i = D_i^{-1} (y_i - sum_j U(i,j) x_j) for one (instance, row) per group
-template <typename T, int G>
-__global__ __launch_bounds__(256) void k_bwd_rows(const Inst* const* insts, const int2* __restrict__ work,
-                                                  int nwork) {
-  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G, lane = threadIdx.x % G;
-  if (gid >= nwork) return;
-  const int2 w = work[gid];
-  const Inst& I = *insts[w.x];
-  if (inactive(I)) return;
-  const T* lu = (const T*)I.lu;
-  T* x = (T*)I.x;
-  const int i = w.y;
-  Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  if (lane == 0) {
-    acc.a = x[2 * i];
-    acc.c = x[2 * i + 1];
-  }
-  // the inverted diagonal block first (it does not depend on the solve)
-  Blk<T> D = {T(0), T(0), T(0), T(0)};
-  if (lane == 0) D = ld_blk((const T*)I.dinv, i);
-  {
-    // four entries' loads at once, applied in order
-    const int q1 = I.colptr[i + 1];
-    for (int q = I.colptr[i] + lane; q < q1; q += 4 * G) {
-      int jj[4];
-      Blk<T> U[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          jj[u] = I.rowidx[q + u * G];
-          U[u] = ld_blk(lu, (int64_t)I.ns + I.nnzl + q + u * G);
-        }
-      T x0[4], x1[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          x0[u] = x[2 * jj[u]];
-          x1[u] = x[2 * jj[u] + 1];
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (q + u * G < q1) {
-          acc.a -= U[u].a * x0[u] + U[u].b * x1[u];
-          acc.c -= U[u].c * x0[u] + U[u].d * x1[u];
-        }
-    }
-  }
-  acc = group_sum<T, G>(acc);
-  if (lane == 0) {
-    x[2 * i] = D.a * acc.a + D.b * acc.c;
-    x[2 * i + 1] = D.c * acc.a + D.d * acc.c;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // voltage update (FP64)
 
@@ -1078,13 +1017,6 @@ void launch_fwd_rows(hipStream_t st, const Inst* const* insts, const int2* work,
 }
 
 template <typename T>
-void launch_bwd_rows(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int G) {
-  if (nwork <= 0) return;
-  PF_GSWITCH(G, (k_bwd_rows<T, GG><<<dim3((unsigned)(((int64_t)nwork * GG + 255) / 256)), 256, 0, st>>>(
-                    insts, work, nwork)));
-}
-
-template <typename T>
 void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max_nu) {
   k_update<T><<<grid2(max_nu, nslots), 256, 0, st>>>(insts);
 }
@@ -1095,7 +1027,6 @@ void launch_update(hipStream_t st, const Inst* const* insts, int nslots, int max
   template void launch_tail_schur<T>(hipStream_t, const Inst* const*, const int2*, int, int);              \
   template void launch_factor_cols_wave<T>(hipStream_t, const Inst* const*, const int2*, int, int);        \
   template void launch_fwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
-  template void launch_bwd_rows<T>(hipStream_t, const Inst* const*, const int2*, int, int);                \
   template void launch_update<T>(hipStream_t, const Inst* const*, int, int);                                \
   template void launch_kfill<T>(hipStream_t, const Inst* const*, int, int, int);
 

@@ -40,8 +40,6 @@ void launch_factor_cols(hipStream_t, const Inst* const* insts, const int2* work,
 template <typename T>
 void launch_fwd_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
 template <typename T>
-void launch_bwd_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
-template <typename T>
 void launch_tail_schur(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int G);
 // one column per wave; for levels whose columns have at most 64/G targets
 template <typename T>
@@ -51,8 +49,12 @@ void launch_factor_cols_wave(hipStream_t, const Inst* const* insts, const int2* 
 template <typename T>
 void launch_dense_step(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int nflag, int npanel,
                        int k0);
+// backward solve of the whole factorisation in one launch: nd dense items
+// (slot, w) (single: (slot, 0), one work-group per instance), then nrw
+// work-groups of sparse rows, each described by work[nd + k] = (offset of its
+// first row item in work, rows | G << 16), row items (slot, row)
 template <typename T>
-void launch_dense_trsv(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int single);
+void launch_bwd_solve(hipStream_t, const Inst* const* insts, const int2* work, int nd, int nrw, int single);
 
 // Newton-Krylov inner solve (krylov.hip); preconditioner mode 0 = Arnoldi
 // step, 1 = end of a GMRES cycle, 2 and 3 = the halves of a BiCGStab

@@ -206,9 +206,11 @@ void Batch::plan(Ctx* cx, const std::vector<Case*>& cs, std::vector<int2>* out) 
       if (!items.empty()) seq.back().nflag = nflag;
     }
   }
-  // dense backward solve: flag mode while every work-group of the launch is
-  // resident at once (256 CUs x 8 work-groups of 4 waves; half of that is
-  // allowed), else one work-group per instance
+  // backward solve, one launch: the dense blocks (one work-group per block,
+  // each waiting on the solution entries of the blocks after it; or one
+  // work-group per instance running its blocks in order, when the batch has
+  // more blocks than half the work-groups the device holds at once), then the
+  // sparse rows by backward level
   {
     int total = 0;
     for (Case* c : cs) total += c->M > 0 ? c->nblk() : 0;
@@ -216,30 +218,21 @@ void Batch::plan(Ctx* cx, const std::vector<Case*>& cs, std::vector<int2>* out) 
     for (Case* c : cs)
       if (c->sched.trsv_mode != mode) mode = 0;
     trsv_single = mode == 1 ? 0 : mode == 2 ? 1 : (total > 1024 ? 1 : 0);
-    std::vector<int2> tr;
+    std::vector<BwdInput> in(nslots);
     double tfl = 0, tby = 0;
     for (int s = 0; s < nslots; ++s) {
       Case* c = cs[s];
-      if (c->M == 0) continue;
-      if (trsv_single)
-        tr.push_back(make_int2(s, 0));
-      else
-        for (int w = 0; w < c->nblk(); ++w) tr.push_back(make_int2(s, w));
+      in[s].M = c->M;
+      in[s].lev_ptr = &c->an.bwd_lev_ptr;
+      in[s].rows = &c->an.bwd_rows;
+      in[s].g = &c->bwd_g;
       tfl += (double)c->M * c->M;
       tby += 8.0 * ((double)c->M * c->M / 2 + 2.0 * c->M);
     }
-    emit(L_TRSV, PF_K_DENSE_TRSV, 0, 0, tr, tfl, tby);
-  }
-  // sparse backward solve by level
-  for (int l = 0; l < max_blev; ++l) {
-    std::map<int, std::vector<int2>> byG;
-    for (int s = 0; s < nslots; ++s) {
-      Case* c = cs[s];
-      if (l >= c->nbl) continue;
-      auto& v = byG[c->bwd_g[l]];
-      for (int k = c->an.bwd_lev_ptr[l]; k < c->an.bwd_lev_ptr[l + 1]; ++k) v.push_back(make_int2(s, c->an.bwd_rows[k]));
-    }
-    for (auto& kv : byG) emit(L_BWD, PF_K_SPARSE_BWD, kv.first, 0, kv.second, 0, 0);
+    std::vector<int2> items;
+    int nd = 0, nrw = 0;
+    bwd_plan(in, trsv_single != 0, &items, &nd, &nrw);
+    emit(L_BWD, PF_K_DENSE_TRSV, nd, nrw, items, tfl, tby);
   }
 
   // zeroing chunks of every instance's factor storage
@@ -285,11 +278,9 @@ void lu_solve(Batch* b) {
       case L_PANEL:
         pfd::launch_dense_step<T>(s, I, w, l.count, l.nflag, l.G, l.k0);
         break;
-      case L_TRSV:
-        pfd::launch_dense_trsv<T>(s, I, w, l.count, b->trsv_single);
-        break;
       case L_BWD:
-        pfd::launch_bwd_rows<T>(s, I, w, l.count, l.G);
+        // G: dense items, k0: sparse row work-groups
+        pfd::launch_bwd_solve<T>(s, I, w, l.G, l.k0, b->trsv_single);
         break;
     }
   };
