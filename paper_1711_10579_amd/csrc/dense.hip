@@ -462,42 +462,177 @@ __device__ inline bool await_solved(const T* p, const bool (&use)[N], T (&v)[N],
 
 constexpr int kBwdLd = NB + 1;
 
+// One entry per lane of the published solution (lanes with use false take
+// 0), waited for with four loads in flight: each round takes the oldest load
+// as it returns and issues a new one, so an entry is seen within about a
+// quarter of a round trip of landing.  The rounds are wave-uniform (they end
+// when no lane still sees the mark) and hold only global loads and the
+// clock read, so each round waits for the oldest load alone; the wait ends
+// on the device-time bound, which every waiter of a timed-out instance
+// reaches within the same bound of its own start.  false when the bound
+// passed.
+template <typename T>
+__device__ inline T ld_dev_g(const PF_AS1 T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline bool await_lanes(const T* pf, bool use, T& v, const Inst& I, unsigned long long t0) {
+  const PF_AS1 T* p = gp(use ? pf : (const T*)I.xs);  // unused lanes read a valid address
+  v = use ? ld_dev_g(p) : T(0);
+  auto pending = [&]() { return __builtin_amdgcn_ballot_w64(unsolved(v)) != 0; };
+  if (!pending()) return true;
+  T a0 = ld_dev_g(p);
+  __builtin_amdgcn_s_sleep(2);
+  T a1 = ld_dev_g(p);
+  __builtin_amdgcn_s_sleep(2);
+  T a2 = ld_dev_g(p);
+  __builtin_amdgcn_s_sleep(2);
+  T a3 = ld_dev_g(p);
+  // the first 32 rounds straight-line (exact waits on the oldest load),
+  // then the same rounds in a loop with the device-time bound
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a0;
+    if (!pending()) return true;
+    a0 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a1;
+    if (!pending()) return true;
+    a1 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a2;
+    if (!pending()) return true;
+    a2 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a3;
+    if (!pending()) return true;
+    a3 = ld_dev_g(p);
+  }
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a0;
+    if (!pending()) return true;
+    a0 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a1;
+    if (!pending()) return true;
+    a1 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a2;
+    if (!pending()) return true;
+    a2 = ld_dev_g(p);
+    __builtin_amdgcn_s_sleep(2);
+    if (unsolved(v)) v = a3;
+    if (!pending()) return true;
+    a3 = ld_dev_g(p);
+    if (rt_now() - t0 > kWaitTicks) {
+      st_dev(&I.red->timeout, 1);
+      return false;
+    }
+  }
+}
+
+// Q = P A for 64x64 P and A staged in LDS (sP[j][r] = P(r, j), sA[j][r] =
+// A(r, j)) on the matrix cores: wave wv forms block column wv, Q_{i,wv} =
+// sum_q P_{i,q} A_{q,wv}, in N-form
+template <typename T>
+__device__ inline void bwd_qprod(T (*sP)[kBwdLd], T (*sA)[kBwdLd], V4<T>* qd, int wv, int lane) {
+  const int c = lane & 15;
+  const V4<T> zero = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    V4<T> acc4 = zero;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V4<T> xt, y;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rw = Mfma<T>::row(lane, e);
+        xt[e] = sP[16 * q + rw][16 * i + c];
+        y[e] = sA[16 * wv + c][16 * q + rw];
+      }
+      acc4 = mm16<T>(xt, y, acc4);
+    }
+    qd[i] = acc4;
+  }
+}
+template <typename T>
+__device__ inline void bwd_qstore(T (*sQ)[kBwdLd], const V4<T>* qd, int wv, int lane) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sQ[16 * wv + (lane & 15)][16 * i + Mfma<T>::row(lane, e)] = qd[i][e];
+}
+
 // One 64-row block b of the dense block, 256 threads:
-//   x_b = P_b (z_b - sum_{c > b+1} A_bc x_c - A_{b,b+1} x_{b+1})
+//   x_b = y' - Q2 x_{b+2} - Q1 x_{b+1},
+//   y' = P_b (z_b - sum_{c > b+2} A_bc x_c),  Qk = P_b A_{b,b+k}
 // with P_b the diagonal block's inverse from the block step and z in column
-// M.  The blocks right of b + 1 are summed as their solutions arrive, wave
-// wv taking columns 16 wv .. 16 wv + 15 of each (a partial sum per row);
-// wave 0 then waits for x_{b+1} and finishes the block with P_b and A_{b,b+1}
-// staged in LDS (the two matrix-vector products of the chain, four partial
-// sums each, inside one wave: no barrier between the wait and the store).
+// M (the same solution as P_b (z_b - sum_{c > b} A_bc x_c), regrouped: the
+// solutions of the two blocks above arrive last, one after the other, and
+// each then costs one product in one wave).  Q1 and Q2 are formed on the
+// matrix cores while the block waits; the blocks right of b + 2 are summed
+// as their solutions arrive, wave wv taking columns 16 wv .. 16 wv + 15 of
+// each (a partial sum per row); y' over the four waves with P_b's columns
+// in registers; then wave 0 waits for x_{b+2}, then for x_{b+1}, and stores
+// x_b (no barrier between the waits and the store).
 template <typename T>
 __device__ __forceinline__ void bwd_block(const Inst& I, int b, T* smem, int* abort_flag, unsigned long long t0) {
-  T(*sP)[kBwdLd] = (T(*)[kBwdLd])smem;                  // sP[j][r] = P_b(r, j)
-  T(*sA)[kBwdLd] = (T(*)[kBwdLd])(smem + NB * kBwdLd);  // sA[j][r] = A(b0 + r, b0 + 64 + j)
+  T(*sX)[kBwdLd] = (T(*)[kBwdLd])smem;                  // P_b, then Q1
+  T(*sY)[kBwdLd] = (T(*)[kBwdLd])(smem + NB * kBwdLd);  // A_{b,b+1}, A_{b,b+2}, then Q2
   T* part = smem + 2 * NB * kBwdLd;                     // [4][NB] partial sums
-  T* xl = part + 4 * NB;                                // x_{b+1}
-  T* al = xl + NB;                                      // the reduced right-hand side
+  T* al = part + 4 * NB;                                // [NB] z - the sums right of b + 2
+  T* x2 = al + NB;                                      // [NB] x_{b+2}
+  T* x1 = x2 + NB;                                      // [NB] x_{b+1}
   const auto G = gp((const T*)I.tail);
   const int ld = I.ldt, M = I.M;
   const int nblk = (M + NB - 1) / NB;
   const int b0 = b * NB, bl = min(NB, M - b0);
   T* xs = (T*)I.xs + 2 * I.ns;
   T* out = (T*)I.x + 2 * I.ns;
-  const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6, lane = tid & 63;
   const auto ui = gp((const T*)I.dinvu + (int64_t)b * NB * NB);
-  const bool has1 = b + 1 < nblk;
+  const bool has1 = b + 1 < nblk, has2 = b + 2 < nblk;
   const int c1 = b0 + NB, cl1 = has1 ? min(NB, M - c1) : 0;
+  const int c2 = b0 + 2 * NB, cl2 = has2 ? min(NB, M - c2) : 0;
+  // the block's right-hand side and this thread's columns of P_b first (on
+  // the top block they are on the chain)
+  const T z = (wv == 0 && r < bl) ? G[(int64_t)M * ld + b0 + r] : T(0);
+  T pr[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) pr[j] = ui[(int64_t)(16 * wv + j) * NB + r];
+  if (has1) {
+    // Q1 = P_b A_{b,b+1}, Q2 = P_b A_{b,b+2}: P_b and one A block at a time
+    // staged, the products kept in registers until P_b is no longer read
 #pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q, j = idx >> 6, rr = idx & 63;
-    sP[j][rr] = ui[(int64_t)j * NB + rr];
-    sA[j][rr] = (rr < bl && j < cl1) ? G[(int64_t)(c1 + j) * ld + b0 + rr] : T(0);
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + 256 * q, j = idx >> 6, rr = idx & 63;
+      sX[j][rr] = ui[(int64_t)j * NB + rr];
+      sY[j][rr] = (rr < bl && j < cl1) ? G[(int64_t)(c1 + j) * ld + b0 + rr] : T(0);
+    }
+    __syncthreads();
+    V4<T> q1[4], q2[4];
+    bwd_qprod<T>(sX, sY, q1, wv, lane);
+    if (has2) {
+      __syncthreads();  // every wave has read A_{b,b+1}
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q, j = idx >> 6, rr = idx & 63;
+        sY[j][rr] = (rr < bl && j < cl2) ? G[(int64_t)(c2 + j) * ld + b0 + rr] : T(0);
+      }
+      __syncthreads();
+      bwd_qprod<T>(sX, sY, q2, wv, lane);
+    }
+    __syncthreads();  // every wave has read P_b and the A block
+    bwd_qstore<T>(sX, q1, wv, lane);
+    if (has2) bwd_qstore<T>(sY, q2, wv, lane);
   }
-  // the blocks right of b + 1
+  // the blocks right of b + 2
   T pacc = T(0);
   bool ok = true;
-  for (int c = nblk - 1; c >= b + 2 && ok; --c) {
-    const int c0 = c * NB, cl = min(NB, M - c0);
+  for (int cb = nblk - 1; cb >= b + 3 && ok; --cb) {
+    const int c0 = cb * NB, cl = min(NB, M - c0);
     T a[16], xv[16];
     bool use[16];
 #pragma unroll
@@ -513,31 +648,62 @@ __device__ __forceinline__ void bwd_block(const Inst& I, int b, T* smem, int* ab
   part[wv * NB + r] = pacc;
   if (!ok) *abort_flag = 1;
   __syncthreads();
-  if (wv == 0 && *abort_flag == 0) {
-    T acc = r < bl ? G[(int64_t)M * ld + b0 + r] : T(0);
-    acc -= ((part[r] + part[NB + r]) + part[2 * NB + r]) + part[3 * NB + r];
-    if (has1) {
-      bool use1[1] = {r < cl1};
-      T v1[1];
-      ok = await_solved<T, 1>(xs + c1 + r, use1, v1, I, t0);
-      xl[r] = v1[0];
+  if (*abort_flag != 0) return;  // uniform: read after the barrier
+  if (wv == 0) al[r] = z - (((part[r] + part[NB + r]) + part[2 * NB + r]) + part[3 * NB + r]);
+  __syncthreads();
+  // y' = P_b al over the four waves
+  {
+    T s4 = T(0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s4 = fma(pr[j], al[16 * wv + j], s4);
+    part[wv * NB + r] = s4;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    T y = ((part[r] + part[NB + r]) + part[2 * NB + r]) + part[3 * NB + r];
+    if (has2) {
+      T v;
+      ok = await_lanes<T>(xs + c2 + r, r < cl2, v, I, t0);
+      x2[r] = v;
       __builtin_amdgcn_wave_barrier();
       T t4[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 8
-      for (int j = 0; j < NB; ++j) t4[j & 3] = fma(sA[j][r], xl[j], t4[j & 3]);
-      acc -= (t4[0] + t4[1]) + (t4[2] + t4[3]);
+#pragma unroll
+      for (int j0 = 0; j0 < NB; j0 += 16) {
+        T xv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) xv[j] = x2[j0 + j];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) t4[j & 3] = fma(sY[j0 + j][r], xv[j], t4[j & 3]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      y -= (t4[0] + t4[1]) + (t4[2] + t4[3]);
     }
-    al[r] = acc;
-    __builtin_amdgcn_wave_barrier();
-    T y4[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 8
-    for (int j = 0; j < NB; ++j) y4[j & 3] = fma(sP[j][r], al[j], y4[j & 3]);
-    const T xb = (y4[0] + y4[1]) + (y4[2] + y4[3]);
+    if (has1 && ok) {
+      // the first half of this row of Q1 in registers, then the wait
+      T qr[NB / 2];
+#pragma unroll
+      for (int j = 0; j < NB / 2; ++j) qr[j] = sX[j][r];
+      T v;
+      ok = await_lanes<T>(xs + c1 + r, r < cl1, v, I, t0);
+      x1[r] = v;
+      __builtin_amdgcn_wave_barrier();
+      T t4[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int j0 = 0; j0 < NB; j0 += 16) {
+        T xv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) xv[j] = x1[j0 + j];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) t4[j & 3] = fma(j0 < NB / 2 ? qr[j0 + j] : sX[j0 + j][r], xv[j], t4[j & 3]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      y -= (t4[0] + t4[1]) + (t4[2] + t4[3]);
+    }
     if (__builtin_amdgcn_ballot_w64(!ok) != 0) {
       if (r == 0) *abort_flag = 1;
     } else if (r < bl) {
-      out[b0 + r] = xb;
-      st_dev(xs + b0 + r, xb);
+      out[b0 + r] = y;
+      st_dev(xs + b0 + r, y);
     }
   }
   __syncthreads();
@@ -633,7 +799,7 @@ __device__ __forceinline__ void bwd_rows(const Inst* const* insts, const int2* _
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_bwd_solve(const Inst* const* insts, const int2* __restrict__ work, int nd,
                                                    int single) {
-  __shared__ T smem[2 * NB * kBwdLd + 6 * NB];
+  __shared__ T smem[2 * NB * kBwdLd + 7 * NB];
   __shared__ int abort_flag;
   const unsigned long long t0 = rt_now();
   const int2 wk = work[blockIdx.x];
@@ -643,11 +809,11 @@ __global__ __launch_bounds__(256, 2) void k_bwd_solve(const Inst* const* insts, 
     const int nblk = (I.M + NB - 1) / NB;
     if (threadIdx.x == 0) abort_flag = 0;
     __syncthreads();
-    if (single) {
-      for (int b = nblk - 1; b >= 0 && abort_flag == 0; --b) bwd_block<T>(I, b, smem, &abort_flag, t0);
-    } else {
-      bwd_block<T>(I, nblk - 1 - wk.y, smem, &abort_flag, t0);
-    }
+    // single mode: every block of the instance in order; else one block
+    const int bfirst = single ? nblk - 1 : nblk - 1 - wk.y;
+    const int blast = single ? 0 : bfirst;
+#pragma unroll 1
+    for (int b = bfirst; b >= blast && abort_flag == 0; --b) bwd_block<T>(I, b, smem, &abort_flag, t0);
     return;
   }
   const int2* rows = work + wk.x;
