@@ -21,6 +21,26 @@ __device__ inline const PF_AS1 T* gp(const T* p) {
   return (const PF_AS1 T*)p;
 }
 
+// Bound of an in-launch wait in ticks of the device's constant real-time
+// counter (100 MHz): about one second.
+constexpr unsigned long long kWaitTicks = 100000000ull;
+__device__ inline unsigned long long rt_now() { return __builtin_amdgcn_s_memrealtime(); }
+// s_waitcnt vmcnt(0): every vector memory access of the wave, stores
+// included, has completed
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Device-coherent accesses for data handed between work-groups inside a
+// launch: relaxed atomics at agent scope (stores write through, loads bypass
+// the caches that are not coherent across the device).
+template <typename T>
+__device__ inline T ld_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // four ints as a native vector (loadable through any address space)
 typedef int i4v __attribute__((ext_vector_type(4)));
 

@@ -50,33 +50,18 @@ __device__ inline unsigned long long panel_flag(int epoch, int k0) {
 }
 
 // A tile handed over inside a launch goes through device-coherent accesses
-// (relaxed atomics at agent scope: stores write through, loads bypass the
-// caches not coherent across the device), so no cache of any compute unit
-// is written back or invalidated.  The writer waits for its stores to
-// complete before the flag is set; the reader loads after seeing the flag.
-template <typename T>
-__device__ inline T ld_dev(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ inline void st_dev(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// (ld_dev / st_dev), so no cache of any compute unit is written back or
+// invalidated.  The writer waits for its stores to complete before the flag
+// is set; the reader loads after seeing the flag.
 __device__ inline unsigned long long flag_ld(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// s_waitcnt vmcnt(0): every vector memory access of the wave, stores
-// included, has completed
-__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// Bound of an inter-work-group wait in ticks of the device's constant
-// real-time counter (100 MHz): about one second.  Every wait here is on a
+// Every inter-work-group wait here (bounded by kWaitTicks) is on a
 // work-group listed earlier in the same launch; work-groups are dispatched
 // in index order, so the earliest unfinished one waits on nothing and the
 // launch drains whatever else shares the device (the bound only turns a
 // broken invariant into a recorded timeout instead of a hang).
-constexpr unsigned long long kWaitTicks = 100000000ull;
-__device__ inline unsigned long long rt_now() { return __builtin_amdgcn_s_memrealtime(); }
 
 // Panel step k0 of every instance in the work list: item (slot, g), one of
 // four work-groups h of four waves.  Every work-group inverts the diagonal

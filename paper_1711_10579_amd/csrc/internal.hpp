@@ -171,10 +171,15 @@ struct Batch {
   const pfd::Inst* const* d_insts = nullptr;
   int2* d_work = nullptr;
   // pinned host memory that the state gathers write into directly: the
-  // instances' Newton states, then their Krylov states
+  // instances' Newton states, then their Krylov states and inner counts
   pfd::Red* h_reds = nullptr;
   int* h_kstate = nullptr;
   int lu_steps = 0;  // Newton steps of the batch's last LU solve (queued ahead of the first read-back)
+  // iterations (BiCGStab) or Arnoldi steps (GMRES) the batch's inner solves
+  // took at each Newton step of its last Newton-Krylov solve (queued ahead
+  // of the first read at the same step)
+  std::vector<int> k_inner;
+  int nk_step_index = 0;  // Newton step of the current solve
   std::vector<Launch> seq;
   int64_t zero_off = 0;  // zeroing chunks of the factor storage: work items [zero_off, +nzero)
   int nzero = 0;
@@ -204,7 +209,7 @@ struct Batch {
   std::vector<std::pair<int64_t, int>> k_lev, k_ulev;
   std::pair<int64_t, int> k_blocks{0, 0};
   int max_kchunks = 0;
-  int k_max_nu = 0;
+  int k_min_nu = 0, k_max_nu = 0;
   bool k_wide = false;    // some instance has an ILU(0) level wider than one work-group pass
   bool k_narrow = false;  // some instance runs its ILU(0) in one work-group
 

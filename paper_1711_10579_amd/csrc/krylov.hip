@@ -1370,12 +1370,14 @@ __global__ void k_kretire(const Inst* const* insts, int nslots) {
 }
 
 // Krylov state of every instance for the host (KS_DONE once the Newton
-// iteration of the instance has ended).
+// iteration of the instance has ended) in out[0, nslots), and the steps or
+// iterations of its current inner solve in out[nslots, 2 nslots).
 __global__ void k_kgather(const Inst* const* insts, int nslots, int* out) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslots) return;
   const Inst& I = *insts[sl];
   out[sl] = I.red->active ? I.ks->state : KS_DONE;
+  out[nslots + sl] = I.ks->total;
 }
 
 // ---------------------------------------------------------------------------
@@ -1412,12 +1414,13 @@ void launch_ilu_factor_wg(hipStream_t st, const Inst* const* insts, int nslots) 
 // z in LDS up to 160,000 bytes of values per work-group, in two sizes so that
 // small instances keep several work-groups per CU
 template <typename T>
-void launch_ilu_apply_wg(hipStream_t st, const Inst* const* insts, int nslots, int mode, int max_nu) {
+void launch_ilu_apply_wg(hipStream_t st, const Inst* const* insts, int nslots, int mode, int min_nu, int max_nu) {
   constexpr int small = 8192 / sizeof(T) * 4;   // 32 KiB
   constexpr int big = 160000 / sizeof(T);
   const dim3 g((unsigned)nslots);
-  k_ilu_apply_wg<T, small><<<g, 1024, 0, st>>>(insts, mode, 0);
-  if (2 * max_nu > small) k_ilu_apply_wg<T, big><<<g, 1024, 0, st>>>(insts, mode, small);
+  // only the size classes some instance of the batch falls in
+  if (2 * min_nu <= small) k_ilu_apply_wg<T, small><<<g, 1024, 0, st>>>(insts, mode, 0);
+  if (2 * max_nu > small && 2 * min_nu <= big) k_ilu_apply_wg<T, big><<<g, 1024, 0, st>>>(insts, mode, small);
   if (2 * max_nu > big) k_ilu_apply_wg<T, 0><<<g, 1024, 0, st>>>(insts, mode, big);
 }
 template <typename T>
@@ -1489,7 +1492,7 @@ int krylov_max_restart() { return KMAX; }
   template void launch_ilu_bwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
   template void launch_ilu_factor_wg<T>(hipStream_t, const Inst* const*, int);              \
-  template void launch_ilu_apply_wg<T>(hipStream_t, const Inst* const*, int, int, int);     \
+  template void launch_ilu_apply_wg<T>(hipStream_t, const Inst* const*, int, int, int, int);\
   template void launch_karnoldi<T>(hipStream_t, const Inst* const*, int, int, KOpts);       \
   template void launch_kbegin<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
   template void launch_kycomb<T>(hipStream_t, const Inst* const*, int, int);                \

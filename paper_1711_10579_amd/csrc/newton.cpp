@@ -53,7 +53,7 @@ bool Batch::build(Ctx* cx, const std::vector<Case*>& cs) {
   {
     void* hp = nullptr;
     const size_t hr = (sizeof(pfd::Red) * std::max(nslots, 1) + 255) & ~(size_t)255;
-    if (hipHostMalloc(&hp, hr + sizeof(int) * std::max(nslots, 1), hipHostMallocCoherent) != hipSuccess) return false;
+    if (hipHostMalloc(&hp, hr + 2 * sizeof(int) * std::max(nslots, 1), hipHostMallocCoherent) != hipSuccess) return false;
     h_reds = (pfd::Red*)hp;
     h_kstate = (int*)((char*)hp + hr);
   }
@@ -488,6 +488,7 @@ pf_status run_batch(Batch* b, const pf_options* opt, pf_result* results) {
   const int B = b->nslots;
   for (int i = 0; i < B; ++i) std::memset(&results[i], 0, sizeof(pf_result));
   if (B == 0) return PF_OK;
+  b->nk_step_index = 0;
   if (hipSetDevice(ctx->device) != hipSuccess) {
     set_error("pf_solve: hipSetDevice failed");
     return PF_E_DEVICE;

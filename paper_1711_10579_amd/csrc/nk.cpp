@@ -242,7 +242,7 @@ bool Batch::build_krylov() {
   k_ulev.clear();
   max_kchunks = 0;
   size_t max_l = 0, max_u = 0;
-  k_max_nu = 0;
+  k_min_nu = k_max_nu = 0;
   k_wide = k_narrow = false;
   // each instance takes its own path (one work-group, or one launch per
   // level when some level is too wide), whatever the batch holds
@@ -258,6 +258,7 @@ bool Batch::build_krylov() {
       max_l = std::max(max_l, ka.lev_ptr.size() - 1);
       max_u = std::max(max_u, ka.ulev_ptr.size() - 1);
     } else {
+      k_min_nu = k_narrow ? std::min(k_min_nu, ka.nu) : ka.nu;
       k_narrow = true;
       k_max_nu = std::max(k_max_nu, ka.nu);
     }
@@ -344,16 +345,33 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   auto apply = [&](int mode) {
     Prof p(ctx, PF_K_PRECOND_APPLY, 0.0, 0.0);
     if (ilu) {
-      if (b->k_narrow) pfd::launch_ilu_apply_wg<T>(s, I, ns, mode, b->k_max_nu);
+      if (b->k_narrow) pfd::launch_ilu_apply_wg<T>(s, I, ns, mode, b->k_min_nu, b->k_max_nu);
       for (const auto& l : b->k_lev) pfd::launch_ilu_fwd<T>(s, I, kw + l.first, l.second, mode);
       for (const auto& l : b->k_ulev) pfd::launch_ilu_bwd<T>(s, I, kw + l.first, l.second, mode);
     } else {
       pfd::launch_bj_apply<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second, mode);
     }
   };
-  // Arnoldi steps queued per read of the instances' Krylov states
-  constexpr int kStepsPerRead = 8;
-  std::vector<int> st(ns);
+  // Iterations (BiCGStab) or Arnoldi steps (GMRES) queued per read of the
+  // instances' Krylov states: first as many as the inner solve at this
+  // Newton step took in the batch's last solve, then the rest of that count
+  // up to 8 at a time, or 2 at a time once it is passed.  An instance that
+  // finishes within a run skips the rest of it.
+  std::vector<int> st(ns), tot(ns);
+  int queued = 0;
+  const size_t step_k = (size_t)b->nk_step_index++;
+  const int guess = step_k < b->k_inner.size() ? b->k_inner[step_k]
+                    : b->k_inner.empty()       ? 8
+                                               : b->k_inner.back();
+  auto run_length = [&](int done) {
+    if (queued == 0) return std::max(1, std::min(guess, 64));
+    return guess > done ? std::min(guess - done, 8) : 2;
+  };
+  auto remember = [&](int most) {
+    if (queued == 0) return;
+    if (b->k_inner.size() <= step_k) b->k_inner.resize(step_k + 1, 8);
+    b->k_inner[step_k] = std::max(1, most);
+  };
   const int64_t guard_max = (int64_t)(opt->gmres_max_restarts + 1) * (opt->gmres_m + 2) + 4;
   for (int64_t guard = 0;; ++guard) {
     if (guard > guard_max) {
@@ -367,13 +385,21 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       return PF_E_DEVICE;
     }
     std::memcpy(st.data(), b->h_kstate, sizeof(int) * ns);
+    std::memcpy(tot.data(), b->h_kstate + ns, sizeof(int) * ns);
+    int most = 0;
+    for (int i = 0; i < ns; ++i) most = std::max(most, tot[i]);
     if (bcg) {
       bool any = false;
       for (int v : st) any |= v == pfd::KS_BP || v == pfd::KS_BS || v == pfd::KS_BH;
-      if (!any) break;
+      if (!any) {
+        remember(most);
+        break;
+      }
       // a run of BiCGStab iterations between two reads of the states (each
       // kernel acts only on the instances in the state it serves)
-      for (int i = 0; i < kStepsPerRead; ++i) {
+      const int run = run_length(most);
+      queued += run;
+      for (int i = 0; i < run; ++i) {
         {
           Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
           pfd::launch_bcg_dir<T>(s, I, ns, mc);
@@ -396,12 +422,17 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       iter |= v == pfd::KS_ITER;
       cyc |= v == pfd::KS_CYCLE;
     }
-    if (!iter && !cyc) break;
+    if (!iter && !cyc) {
+      remember(most);
+      break;
+    }
     // a run of Arnoldi steps, then the end of every cycle they complete,
     // between two reads of the states: each kernel acts only on the
     // instances in the state it serves, so an instance whose cycle ends
     // within the run skips its remaining steps
-    for (int i = 0; iter && i < kStepsPerRead; ++i) {
+    const int run = iter ? run_length(most) : 0;
+    queued += std::max(run, 1);
+    for (int i = 0; i < run; ++i) {
       apply(0);
       Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
       pfd::launch_karnoldi<T>(s, I, ns, mc, ko);
