@@ -41,6 +41,18 @@ __device__ inline void st_dev(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Work-groups of a launch are handed to the device's eight XCDs (each with
+// its own L2) in turn.  xcd_block(b, G) renumbers block b of a grid of G so
+// that each XCD takes one contiguous range of the renumbered blocks: data
+// that neighbouring blocks share is then fetched into one L2, not eight.
+// A permutation of [0, G).
+__device__ inline int xcd_block(int b, int G) {
+  constexpr int kXcd = 8;
+  const int c = G / kXcd, rem = G % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x < rem ? x * (c + 1) + k : rem * (c + 1) + (x - rem) * c + k;
+}
+
 // four ints as a native vector (loadable through any address space)
 typedef int i4v __attribute__((ext_vector_type(4)));
 

@@ -115,15 +115,17 @@ __global__ void k_start(const Inst* const* insts, int nslots) {
 // max that keeps a NaN
 __device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
-// max of a[k] over k = tid, tid + 256, ... < n, four loads in flight
+// max of a[k] over k = tid, tid + 256, ... < n, eight loads in flight
+// (issued whatever k, past the end re-reading a[0]: the values are >= 0)
 __device__ inline double strided_max(const double* a, int n) {
+  const PF_AS1 double* g = (const PF_AS1 double*)a;
   double m = 0.0;
-  for (int k = threadIdx.x; k < n; k += 1024) {
-    double v[4];
+  for (int k = threadIdx.x; k < n; k += 2048) {
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = k + 256 * u < n ? a[k + 256 * u] : 0.0;
+    for (int u = 0; u < 8; ++u) v[u] = g[k + 256 * u < n ? k + 256 * u : 0];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) m = nanmax(m, v[u]);
+    for (int u = 0; u < 8; ++u) m = nanmax(m, v[u]);
   }
   return m;
 }
@@ -215,13 +217,26 @@ __global__ void k_gather_red(const Inst* const* insts, int nslots, Red* out) {
 
 // Current conj(S(|Vd|)/Vd) a delta load of ZIP coefficients z (at the
 // nominal line-to-line voltage sqrt(3) pu) draws across Vd.
-__device__ inline double2 delta_current(const double* z, double2 vd) {
+__device__ inline double2 delta_current(const PF_AS1 double* z, double2 vd) {
   const double w = vd.x * vd.x + vd.y * vd.y;
   const double m = sqrt(w);
   const double r3 = 0.57735026918962576;  // 1/sqrt(3)
   const double sr = z[0] * w * (1.0 / 3.0) + z[1] * m * r3 + z[2];
   const double si = z[3] * w * (1.0 / 3.0) + z[4] * m * r3 + z[5];
   return make_double2((sr * vd.x + si * vd.y) / w, (sr * vd.y - si * vd.x) / w);
+}
+
+// The mismatch reads every array through global (not generic) pointers, so
+// that its loads are counted by the vector-memory counter alone and each
+// wait is for the loads it needs.
+__device__ inline double2 ld_c(const double* p, int64_t i) {
+  const PF_AS1 double* q = (const PF_AS1 double*)p + 2 * i;
+  return make_double2(q[0], q[1]);
+}
+__device__ inline void st_c(double* p, int64_t i, double re, double im) {
+  PF_AS1 double* q = (PF_AS1 double*)p + 2 * i;
+  q[0] = re;
+  q[1] = im;
 }
 
 // A row's own data besides its Ybus entries (its voltage, set-points, type,
@@ -234,19 +249,24 @@ struct RowSide {
   double z[6];
   int2 dl;
 };
-__device__ inline RowSide load_side(const Inst& I, int i) {
+template <typename InstRef>
+__device__ inline RowSide load_side(const InstRef& I, int i) {
   RowSide s;
-  s.vi = ((const double2*)I.v)[i];
-  s.psp = I.psp[i];
-  s.qsp = I.qsp[i];
-  s.type = I.type[i];
+  s.vi = ld_c((const double*)I.v, i);
+  s.psp = gp(I.psp)[i];
+  s.qsp = gp(I.qsp)[i];
+  s.type = gp(I.type)[i];
   s.qg = 0.0;
   s.dl = make_int2(-1, -1);
   if (I.model != 0) {
+    const auto zip = gp(I.zip) + 6 * i;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s.z[k] = I.zip[6 * i + k];
-    if (s.type == 2) s.qg = I.qg[i];
-    if (I.dlink) s.dl = I.dlink[i];
+    for (int k = 0; k < 6; ++k) s.z[k] = zip[k];
+    s.qg = gp(I.qg)[i];  // used for PV nodes only; loaded whatever the type so that no load waits for it
+    if (I.dlink) {
+      const PF_AS1 int* dl = (const PF_AS1 int*)I.dlink + 2 * i;
+      s.dl = make_int2(dl[0], dl[1]);
+    }
   }
   return s;
 }
@@ -255,19 +275,20 @@ __device__ inline RowSide load_side(const Inst& I, int i) {
 // dQ; CIM the ZIP load, the specified current, the delta loads and dI.
 // Writes F at the node's position (and the bus current for polar) and
 // returns the row's |F| (NaN when a value is NaN).
-__device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, double ii, const RowSide& sd) {
-  const double2* v = (const double2*)I.v;
+template <typename InstRef>
+__device__ inline double mismatch_row(const InstRef& I, int i, int p, double ir, double ii, const RowSide& sd) {
   const double2 vi = sd.vi;
+  const auto F = gp(I.F);
   double local = 0.0;
   if (I.model == 0) {
-    ((double2*)I.ibus)[i] = make_double2(ir, ii);
+    st_c((double*)I.ibus, i, ir, ii);
     if (p >= 0) {
       double sr = vi.x * ir + vi.y * ii;  // Re(V conj I)
       double si = vi.y * ir - vi.x * ii;  // Im(V conj I)
       double dp = sd.psp - sr;
       double dq = sd.type == 1 ? sd.qsp - si : 0.0;
-      I.F[2 * p] = dp;
-      I.F[2 * p + 1] = dq;
+      F[2 * p] = dp;
+      F[2 * p + 1] = dq;
       local = fmax(fabs(dp), fabs(dq));
       if (!(dp == dp) || !(dq == dq)) local = __longlong_as_double(0x7ff8000000000000ll);
     }
@@ -285,21 +306,21 @@ __device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, do
     if (I.dlink) {
       const int2 L = sd.dl;
       if (L.x >= 0) {
-        const double2 vt = v[L.x];
-        const double2 id = delta_current(I.zipd + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
+        const double2 vt = ld_c((const double*)I.v, L.x);
+        const double2 id = delta_current(gp(I.zipd) + 6 * i, make_double2(vi.x - vt.x, vi.y - vt.y));
         spr -= id.x;
         spi -= id.y;
       }
       if (L.y >= 0) {
-        const double2 vk = v[L.y];
-        const double2 id = delta_current(I.zipd + 6 * L.y, make_double2(vk.x - vi.x, vk.y - vi.y));
+        const double2 vk = ld_c((const double*)I.v, L.y);
+        const double2 id = delta_current(gp(I.zipd) + 6 * L.y, make_double2(vk.x - vi.x, vk.y - vi.y));
         spr += id.x;
         spi += id.y;
       }
     }
     double dr = spr - ir, di = spi - ii;
-    I.F[2 * p] = di;
-    I.F[2 * p + 1] = dr;
+    F[2 * p] = di;
+    F[2 * p + 1] = dr;
     local = fmax(fabs(dr), fabs(di));
     if (!(dr == dr) || !(di == di)) local = __longlong_as_double(0x7ff8000000000000ll);
   }
@@ -308,16 +329,17 @@ __device__ inline double mismatch_row(const Inst& I, int i, int p, double ir, do
 
 // Partial sum of Y_iq V_col(q) over q = q0, q0 + S, ... < q1 (the loads of
 // two entries issued at once)
-template <int S>
-__device__ inline void ydot_part(const Inst& I, int q0, int q1, double& ir, double& ii) {
-  const double2* y = (const double2*)I.y;
-  const double2* v = (const double2*)I.v;
+template <int S, typename InstRef>
+__device__ inline void ydot_part(const InstRef& I, int q0, int q1, double& ir, double& ii) {
+  const double* y = (const double*)I.y;
+  const double* v = (const double*)I.v;
+  const auto col = gp(I.col);
   for (int q = q0; q < q1; q += 2 * S) {
     const bool two = q + S < q1;
-    const int c0 = I.col[q];
-    const int c1 = two ? I.col[q + S] : c0;
-    const double2 y0 = y[q], y1 = two ? y[q + S] : make_double2(0.0, 0.0);
-    const double2 v0 = v[c0], v1 = v[c1];
+    const int c0 = col[q];
+    const int c1 = two ? col[q + S] : c0;
+    const double2 y0 = ld_c(y, q), y1 = two ? ld_c(y, q + S) : make_double2(0.0, 0.0);
+    const double2 v0 = ld_c(v, c0), v1 = ld_c(v, c1);
     ir += y0.x * v0.x - y0.y * v0.y;
     ii += y0.x * v0.y + y0.y * v0.x;
     if (two) {
@@ -327,50 +349,18 @@ __device__ inline void ydot_part(const Inst& I, int q0, int q1, double& ir, doub
   }
 }
 
-// Rows with at most kHeavyRow entries: S = 4 lanes per row split the row's
-// entries (lane-strided partial sums, then a fixed-order butterfly); longer
-// rows are left to k_mismatch_heavy.
-constexpr int kMisLanes = 4;
-template <int S>
-__global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
-  constexpr int kRows = 256 / S;
-  if (inactive(I) || (int)blockIdx.x * kRows >= I.n) return;
-  const int lane = threadIdx.x % S;
-  const int i = blockIdx.x * kRows + (int)threadIdx.x / S;
-  double local = 0.0;
-  bool mine = false;
-  int p = -1;
-  double ir = 0.0, ii = 0.0;
-  RowSide side;
-  if (i < I.n) {
-    p = I.pos[i];
-    const int q0 = I.row_ptr[i], q1 = I.row_ptr[i + 1];
-    if (lane == 0) side = load_side(I, i);
-    mine = (I.model == 0 || p >= 0) && q1 - q0 <= kHeavyRow;
-    if (mine) ydot_part<S>(I, q0 + lane, q1, ir, ii);
-  }
-#pragma unroll
-  for (int off = S / 2; off > 0; off >>= 1) {
-    ir += __shfl_xor(ir, off, 64);
-    ii += __shfl_xor(ii, off, 64);
-  }
-  if (mine && lane == 0) local = mismatch_row(I, i, p, ir, ii, side);
-  block_max_store(local, I.mpart + blockIdx.x);
-}
-
-// Rows with more than kHeavyRow entries (listed per instance in I.heavy): one
-// work-group of 256 threads per row, block-strided partial sums reduced by a
-// wave butterfly and then over the four waves in order.
-__global__ __launch_bounds__(256) void k_mismatch_heavy(const Inst* const* insts) {
+// A row of more than kHeavyRow entries (listed per instance in I.heavy): one
+// work-group of 256 threads, block-strided partial sums reduced by a wave
+// butterfly and then over the four waves in order; its |F| goes into the
+// instance's maximum directly.
+template <typename InstRef>
+__device__ inline void mismatch_heavy_row(const InstRef& I, int h) {
   __shared__ double part[2][4];
-  const Inst& I = *insts[blockIdx.y];
-  if (inactive(I) || (int)blockIdx.x >= I.nheavy) return;
-  const int i = I.heavy[blockIdx.x];
-  const int p = I.pos[i];
+  const int i = gp(I.heavy)[h];
+  const int p = gp(I.pos)[i];
   if (!(I.model == 0 || p >= 0)) return;
   double ir = 0.0, ii = 0.0;
-  ydot_part<256>(I, I.row_ptr[i] + (int)threadIdx.x, I.row_ptr[i + 1], ir, ii);
+  ydot_part<256>(I, gp(I.row_ptr)[i] + (int)threadIdx.x, gp(I.row_ptr)[i + 1], ir, ii);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     ir += __shfl_xor(ir, off, 64);
@@ -387,6 +377,74 @@ __global__ __launch_bounds__(256) void k_mismatch_heavy(const Inst* const* insts
     const double local = mismatch_row(I, i, p, ir, ii, load_side(I, i));
     if (local != 0.0) atomic_max_nonneg(&I.red->norm_bits, local);
   }
+}
+
+// The mismatch of every row in one launch.  Blocks are renumbered so that
+// each XCD takes a contiguous range of rows (the voltages a row gathers are
+// mostly its neighbours').  The first nh renumbered work-groups take the
+// heavy rows (one each; they are dispatched early, so these long sums
+// overlap the rest); the others take the rows of at most kHeavyRow entries,
+// S = 4 lanes per row splitting the row's entries (lane-strided partial
+// sums, then a fixed-order butterfly), and store the work-group's partial
+// maximum.
+constexpr int kMisLanes = 4;
+template <int S>
+__global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts, int nh) {
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
+  // whether the instance is still iterating is tested only before the
+  // first store: the row's loads need not wait for that flag
+  const bool active = gp(I.red)->active != 0;
+  const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  if (blk < nh) {
+    if (blk < I.nheavy && active) mismatch_heavy_row(I, blk);
+    return;
+  }
+  const int bx = blk - nh;
+  constexpr int kRows = 256 / S;
+  if (bx * kRows >= I.n) return;
+  const int lane = threadIdx.x % S;
+  const int i = bx * kRows + (int)threadIdx.x / S;
+  double local = 0.0;
+  bool mine = false;
+  int p = -1;
+  double ir = 0.0, ii = 0.0;
+  RowSide side;
+  if (i < I.n) {
+    p = gp(I.pos)[i];
+    const int q0 = gp(I.row_ptr)[i], q1 = gp(I.row_ptr)[i + 1];
+    // the lane's first two entries, loaded whatever the row (indices past
+    // the row read its first entry, which every row has: the diagonal), so
+    // that nothing waits for the row's kind or for the side data
+    const double* y = (const double*)I.y;
+    const double* v = (const double*)I.v;
+    const auto col = gp(I.col);
+    const int qa = q0 + lane, qb = qa + S;
+    const bool ha = qa < q1, hb = qb < q1;
+    const int ca = col[ha ? qa : q0], cb = col[hb ? qb : q0];
+    const double2 ya = ld_c(y, ha ? qa : q0), yb = ld_c(y, hb ? qb : q0);
+    const double2 va = ld_c(v, ca), vb = ld_c(v, cb);
+    if (lane == 0) side = load_side(I, i);
+    mine = (I.model == 0 || p >= 0) && q1 - q0 <= kHeavyRow;
+    if (mine) {
+      if (ha) {
+        ir += ya.x * va.x - ya.y * va.y;
+        ii += ya.x * va.y + ya.y * va.x;
+      }
+      if (hb) {
+        ir += yb.x * vb.x - yb.y * vb.y;
+        ii += yb.x * vb.y + yb.y * vb.x;
+      }
+      if (qb + S < q1) ydot_part<S>(I, qb + S, q1, ir, ii);
+    }
+  }
+#pragma unroll
+  for (int off = S / 2; off > 0; off >>= 1) {
+    ir += __shfl_xor(ir, off, 64);
+    ii += __shfl_xor(ii, off, 64);
+  }
+  if (!active) return;  // uniform over the work-group
+  if (mine && lane == 0) local = mismatch_row(I, i, p, ir, ii, side);
+  block_max_store(local, (double*)I.mpart + bx);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,7 +704,9 @@ __global__ void k_kfill(const Inst* const* insts, int ilu) {
 // acc -= sum over updates q = q0, q0 + G, ... < q1 of L(q) U(q) (block ids
 // from il / iu), in that order, the loads of four updates issued at once
 template <typename T, int G>
-__device__ inline void sub_updates(Blk<T>& acc, const T* lu, const int* il, const int* iu, int64_t q0, int64_t q1) {
+__device__ inline void sub_updates(Blk<T>& acc, const T* lu_, const int* il_, const int* iu_, int64_t q0, int64_t q1) {
+  const auto lu = gp(lu_);
+  const auto il = gp(il_), iu = gp(iu_);
   for (int64_t q = q0; q < q1; q += 4 * G) {
     int a[4], b[4];
 #pragma unroll
@@ -659,8 +719,8 @@ __device__ inline void sub_updates(Blk<T>& acc, const T* lu, const int* il, cons
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (q + u * G < q1) {
-        L[u] = ld_blk(lu, a[u]);
-        U[u] = ld_blk(lu, b[u]);
+        L[u] = ld_blk<T>(lu, a[u]);
+        U[u] = ld_blk<T>(lu, b[u]);
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -721,8 +781,8 @@ __device__ inline void fwd_row(const Inst& I, const T* lu, T* x, int i, int lane
 template <typename T, int G>
 __device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest, int64_t tg, int lane) {
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  if (lane == 0) acc = ld_blk(lu, dest);
-  sub_updates<T, G>(acc, lu, I.upd_l, I.upd_u, I.uptr[tg] + lane, I.uptr[tg + 1]);
+  if (lane == 0) acc = ld_blk<T>(gp(lu), dest);
+  sub_updates<T, G>(acc, lu, I.upd_l, I.upd_u, gp(I.uptr)[tg] + lane, gp(I.uptr)[tg + 1]);
   return group_sum<T, G>(acc);
 }
 
@@ -846,19 +906,21 @@ template <typename T, int G>
 __global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
   const Inst& I = *insts[w.x];
-  if (inactive(I)) return;
+  // the activity flag is tested only before the store, so that the loads
+  // need not wait for it
+  const bool active = !inactive(I);
   // G lanes per target split its update list (lane-strided, fixed-order tree)
   const int lane = threadIdx.x % G;
   const int t = w.y + (int)threadIdx.x / G;
   const bool live = t < I.ntt;
   const T* lu = (const T*)I.lu;
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
-  if (live) sub_updates<T, G>(acc, lu, I.tail_l, I.tail_u, I.tail_uptr[t] + lane, I.tail_uptr[t + 1]);
+  if (live) sub_updates<T, G>(acc, lu, I.tail_l, I.tail_u, gp(I.tail_uptr)[t] + lane, gp(I.tail_uptr)[t + 1]);
   acc = group_sum<T, G>(acc);
-  if (!live || lane != 0) return;
-  int g = I.tail_tgt[t];
+  if (!active || !live || lane != 0) return;
+  int g = gp(I.tail_tgt)[t];
   int ta = g / I.nt, tb = g - ta * I.nt;
-  T* p = (T*)I.tail + (int64_t)(2 * tb) * I.ldt + 2 * ta;
+  auto p = gp((T*)I.tail) + (int64_t)(2 * tb) * I.ldt + 2 * ta;
   p[0] += acc.a;
   p[1] += acc.c;
   p[I.ldt] += acc.b;
@@ -957,8 +1019,8 @@ void launch_gather_red(hipStream_t st, const Inst* const* insts, int nslots, Red
   k_gather_red<<<dim3((unsigned)((nslots + 63) / 64)), 64, 0, st>>>(insts, nslots, out);
 }
 void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int max_n, int max_heavy) {
-  k_mismatch<kMisLanes><<<grid2((int64_t)max_n * kMisLanes, nslots), 256, 0, st>>>(insts);
-  if (max_heavy > 0) k_mismatch_heavy<<<dim3((unsigned)max_heavy, (unsigned)nslots), 256, 0, st>>>(insts);
+  const dim3 g = grid2((int64_t)max_n * kMisLanes, nslots);
+  k_mismatch<kMisLanes><<<dim3(g.x + (unsigned)max_heavy, g.y), 256, 0, st>>>(insts, max_heavy);
 }
 
 template <typename T>
