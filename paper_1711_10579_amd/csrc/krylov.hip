@@ -36,7 +36,13 @@ namespace {
 
 constexpr int KMAX = 128;  // largest restart length the kernels accept
 
-__device__ inline bool kstate_is(const Inst& I, int want) { return I.red->active && I.ks->state == want; }
+// Helpers over an instance descriptor reached through a generic or a global
+// reference (kernels that read theirs through global pointers get scalar
+// loads of its fields and vector loads counted by one wait counter).
+template <typename IR>
+__device__ inline bool kstate_is(const IR& I, int want) {
+  return gp(I.red)->active && gp(I.ks)->state == want;
+}
 
 // the Krylov state a preconditioner application serves: mode 0 an Arnoldi
 // step (scaled input stored as basis vector), 1 the end of a GMRES cycle,
@@ -50,17 +56,19 @@ __device__ inline double* kh_cs(const Inst& I) { return I.kh + (int64_t)(I.km + 
 __device__ inline double* kh_sn(const Inst& I) { return kh_cs(I) + I.km; }
 __device__ inline double* kh_g(const Inst& I) { return kh_sn(I) + I.km; }
 __device__ inline double* kh_y(const Inst& I) { return kh_g(I) + I.km + 1; }
-__device__ inline double* kpart(const Inst& I, int pass, int chunk) {
-  return I.kpart + ((int64_t)pass * I.kchunks + chunk) * (I.km + 1);
+template <typename IR>
+__device__ inline PF_AS1 double* kpart(const IR& I, int pass, int chunk) {
+  return gp(I.kpart) + ((int64_t)pass * I.kchunks + chunk) * (I.km + 1);
 }
 
 // The inner solve failed: the Newton iteration of the instance ends with
 // status linear failure and the step is not taken (not counted).
-__device__ inline void linear_failure(const Inst& I) {
-  I.red->status = 4;
-  I.red->active = 0;
-  I.red->it -= 1;
-  I.ks->state = KS_DONE;
+template <typename IR>
+__device__ inline void linear_failure(const IR& I) {
+  gp(I.red)->status = 4;
+  gp(I.red)->active = 0;
+  gp(I.red)->it -= 1;
+  gp(I.ks)->state = KS_DONE;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -72,7 +80,7 @@ __device__ inline double wave_sum(double v) {
 // Sums over the KCH threads of a work-group of the values f(i) for i <
 // count, written to out[i] (thread-uniform count).  Fixed reduction order.
 template <typename F>
-__device__ inline void block_sums(int count, F f, double (*red)[KCH / 64], double* out) {
+__device__ inline void block_sums(int count, F f, double (*red)[KCH / 64], PF_AS1 double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = 0; i < count; ++i) {
     double s = wave_sum(f(i));
@@ -627,30 +635,32 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
 template <typename T>
 __global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const int2* __restrict__ work, int mode) {
   __shared__ double v[64];
-  const int2 wk = work[blockIdx.x];
-  const Inst& I = *insts[wk.x];
+  const auto wp = (const PF_AS1 int*)work;
+  const int wx = wp[2 * blockIdx.x], b = wp[2 * blockIdx.x + 1];
+  const auto& I = *gp(gp(insts)[wx]);
   if (!kstate_is(I, apply_state(mode))) return;
-  const int b = wk.y;
-  const int r0 = I.bj_ptr[b];
-  const int N = 2 * (I.bj_ptr[b + 1] - r0);
+  const int r0 = gp(I.bj_ptr)[b];
+  const int N = 2 * (gp(I.bj_ptr)[b + 1] - r0);
   const int t = threadIdx.x;
-  const T* w = (const T*)I.kw;
+  const auto w = gp((const T*)I.kw);
+  const auto rows = gp(I.bj_rows);
   if (t < N) {
-    const int r = I.bj_rows[r0 + (t >> 1)];
+    const int r = rows[r0 + (t >> 1)];
     T x = w[2 * r + (t & 1)];
     if (mode == 0) {
-      x = (T)((double)x * I.ks->scale);
-      ((T*)I.kv)[(int64_t)I.ks->j * 2 * I.nu + 2 * r + (t & 1)] = x;
+      const auto ks = gp(I.ks);
+      x = (T)((double)x * ks->scale);
+      gp((T*)I.kv)[(int64_t)ks->j * 2 * I.nu + 2 * r + (t & 1)] = x;
     }
     v[t] = (double)x;
   }
   __syncthreads();
   if (t < N) {
-    const T* inv = (const T*)I.bjinv + I.bj_off[b] + t;
+    const auto inv = gp((const T*)I.bjinv) + gp(I.bj_off)[b] + t;
     double s = 0.0;
     for (int c = 0; c < N; ++c) s += (double)inv[(int64_t)c * N] * v[c];
-    const int r = I.bj_rows[r0 + (t >> 1)];
-    ((T*)I.kz)[2 * r + (t & 1)] = (T)s;
+    const int r = rows[r0 + (t >> 1)];
+    gp((T*)I.kz)[2 * r + (t & 1)] = (T)s;
   }
 }
 
@@ -1044,9 +1054,9 @@ __global__ __launch_bounds__(KCH) void k_kfinish(const Inst* const* insts) {
 // solve with x as it stands: the step is taken when its relative residual
 // is at most eta_max, else the Newton iteration ends with a linear failure.
 
-template <typename T>
-__device__ inline T* kvec(const Inst& I, int i) {
-  return (T*)I.kv + (int64_t)i * 2 * I.nu;
+template <typename T, typename IR>
+__device__ inline PF_AS1 T* kvec(const IR& I, int i) {
+  return gp((T*)I.kv) + (int64_t)i * 2 * I.nu;
 }
 
 // Sum over the chunks of entry e of a pass's partial sums, in chunk order
@@ -1054,16 +1064,18 @@ __device__ inline T* kvec(const Inst& I, int i) {
 // Called by all 64 lanes of one wave: lane-strided partial sums, then the
 // butterfly of wave_sum, so every lane (and every work-group) gets the same
 // value in a fixed order.
-__device__ inline double chunk_sum(const Inst& I, int pass, int e) {
+template <typename IR>
+__device__ inline double chunk_sum(const IR& I, int pass, int e) {
   double s = 0.0;
   for (int c = threadIdx.x & 63; c < I.kchunks; c += 64) s += kpart(I, pass, c)[e];
   return wave_sum(s);
 }
 
 // The solve ends as it stands.
-__device__ inline void bcg_stop(const Inst& I, KOpts o) {
-  if (I.ks->rel <= o.eta_max)
-    I.ks->state = KS_FINISH;
+template <typename IR>
+__device__ inline void bcg_stop(const IR& I, KOpts o) {
+  if (gp(I.ks)->rel <= o.eta_max)
+    gp(I.ks)->state = KS_FINISH;
   else
     linear_failure(I);
 }
@@ -1109,15 +1121,15 @@ __global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, 
 // p = r + beta (p - omega v), or r = r0 = p = F in the first iteration; w = p.
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_bcg_dir(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   if (r >= I.nu) return;
-  const KState& ks = *I.ks;
-  T* w = (T*)I.kw;
-  T* R = kvec<T>(I, 0);
-  T* P = kvec<T>(I, 2);
-  const T* V = kvec<T>(I, 3);
+  const auto& ks = *gp(I.ks);
+  const auto w = gp((T*)I.kw);
+  const auto R = kvec<T>(I, 0);
+  const auto P = kvec<T>(I, 2);
+  const auto V = kvec<T>(I, 3);
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int i = 2 * r + e;
@@ -1138,28 +1150,28 @@ __global__ __launch_bounds__(KCH) void k_bcg_dir(const Inst* const* insts) {
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_bcg_v(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   double d = 0.0;
   if (r < I.nu) {
-    const T* J = (const T*)I.jval;
-    const T* z = (const T*)I.kz;
-    T* Ph = kvec<T>(I, 4);
+    const auto J = gp((const T*)I.jval);
+    const auto z = gp((const T*)I.kz);
+    const auto Ph = kvec<T>(I, 4);
     Ph[2 * r] = z[2 * r];
     Ph[2 * r + 1] = z[2 * r + 1];
     double v0 = 0.0, v1 = 0.0;
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
       const Blk<T> B = ld_blk(J, q);
-      const int c = I.kcol[q];
+      const int c = gp(I.kcol)[q];
       const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
       v0 += (double)B.a * a + (double)B.b * b;
       v1 += (double)B.c * a + (double)B.d * b;
     }
-    T* V = kvec<T>(I, 3);
+    const auto V = kvec<T>(I, 3);
     V[2 * r] = (T)v0;
     V[2 * r + 1] = (T)v1;
-    const T* R0 = kvec<T>(I, 1);
+    const auto R0 = kvec<T>(I, 1);
     d = (double)R0[2 * r] * (double)(T)v0 + (double)R0[2 * r + 1] * (double)(T)v1;
   }
   block_sums(
@@ -1171,13 +1183,13 @@ template <typename T>
 __global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
   __shared__ double alpha_s;
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
   if (threadIdx.x < 64) {
-    const double a = I.ks->rho / chunk_sum(I, 0, 0);
+    const double a = gp(I.ks)->rho / chunk_sum(I, 0, 0);
     if (threadIdx.x == 0) {
       alpha_s = a;
-      if (blockIdx.x == 0) I.ks->alpha = a;
+      if (blockIdx.x == 0) gp(I.ks)->alpha = a;
     }
   }
   __syncthreads();
@@ -1185,9 +1197,9 @@ __global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
   const int r = blockIdx.x * KCH + threadIdx.x;
   double s0 = 0.0, s1 = 0.0;
   if (r < I.nu) {
-    T* R = kvec<T>(I, 0);
-    const T* V = kvec<T>(I, 3);
-    T* w = (T*)I.kw;
+    const auto R = kvec<T>(I, 0);
+    const auto V = kvec<T>(I, 3);
+    const auto w = gp((T*)I.kw);
     const T a = (T)((double)R[2 * r] - alpha * (double)V[2 * r]);
     const T b = (T)((double)R[2 * r + 1] - alpha * (double)V[2 * r + 1]);
     R[2 * r] = a;
@@ -1203,9 +1215,9 @@ __global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
 
 // Per instance: the first half of the iteration meets the tolerance or not.
 __global__ __launch_bounds__(64) void k_bcg_half(const Inst* const* insts, KOpts o) {
-  const Inst& I = *insts[blockIdx.x];
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
   if (!kstate_is(I, KS_BP)) return;
-  KState& ks = *I.ks;
+  auto& ks = *gp(I.ks);
   double sv = 0.0, ss = 0.0;
   for (int c = threadIdx.x; c < I.kchunks; c += 64) {
     sv += fabs(kpart(I, 0, c)[0]);
@@ -1215,7 +1227,7 @@ __global__ __launch_bounds__(64) void k_bcg_half(const Inst* const* insts, KOpts
   ss = wave_sum(ss);
   if (threadIdx.x != 0) return;
   ks.total += 1;
-  I.red->linear_iters += 1;
+  gp(I.red)->linear_iters += 1;
   if (!(sv > 0.0) || !isfinite(ks.alpha)) {
     bcg_stop(I, o);
     return;
@@ -1234,30 +1246,30 @@ __global__ __launch_bounds__(64) void k_bcg_half(const Inst* const* insts, KOpts
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_BS) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   double ts = 0.0, tt = 0.0;
   if (r < I.nu) {
-    const T* J = (const T*)I.jval;
-    const T* z = (const T*)I.kz;
-    T* Sh = kvec<T>(I, 5);
+    const auto J = gp((const T*)I.jval);
+    const auto z = gp((const T*)I.kz);
+    const auto Sh = kvec<T>(I, 5);
     Sh[2 * r] = z[2 * r];
     Sh[2 * r + 1] = z[2 * r + 1];
     double t0 = 0.0, t1 = 0.0;
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
       const Blk<T> B = ld_blk(J, q);
-      const int c = I.kcol[q];
+      const int c = gp(I.kcol)[q];
       const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
       t0 += (double)B.a * a + (double)B.b * b;
       t1 += (double)B.c * a + (double)B.d * b;
     }
-    T* Tv = kvec<T>(I, 6);
+    const auto Tv = kvec<T>(I, 6);
     Tv[2 * r] = (T)t0;
     Tv[2 * r + 1] = (T)t1;
     t0 = (double)(T)t0;
     t1 = (double)(T)t1;
-    const T* S = kvec<T>(I, 0);
+    const auto S = kvec<T>(I, 0);
     ts = t0 * (double)S[2 * r] + t1 * (double)S[2 * r + 1];
     tt = t0 * t0 + t1 * t1;
   }
@@ -1273,13 +1285,13 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
   __shared__ double omega_s;
   __shared__ bool skip_s;
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   const bool half = kstate_is(I, KS_BH);
   if ((!half && !kstate_is(I, KS_BS)) || (int)blockIdx.x >= I.kchunks) return;
-  const KState& ks = *I.ks;
+  const auto& ks = *gp(I.ks);
   const int r = blockIdx.x * KCH + threadIdx.x;
-  T* x = (T*)I.kx;
-  const T* Ph = kvec<T>(I, 4);
+  const auto x = gp((T*)I.kx);
+  const auto Ph = kvec<T>(I, 4);
   if (half) {
     if (r < I.nu) {
 #pragma unroll
@@ -1293,7 +1305,7 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
     if (threadIdx.x == 0) {
       skip_s = !(tt > 0.0);
       omega_s = skip_s ? 0.0 : ts / tt;
-      if (blockIdx.x == 0) I.ks->omega = omega_s;
+      if (blockIdx.x == 0) gp(I.ks)->omega = omega_s;
     }
   }
   __syncthreads();
@@ -1301,10 +1313,10 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
   const double omega = omega_s;
   double d = 0.0, q = 0.0;
   if (r < I.nu) {
-    const T* Sh = kvec<T>(I, 5);
-    const T* Tv = kvec<T>(I, 6);
-    const T* R0 = kvec<T>(I, 1);
-    T* R = kvec<T>(I, 0);
+    const auto Sh = kvec<T>(I, 5);
+    const auto Tv = kvec<T>(I, 6);
+    const auto R0 = kvec<T>(I, 1);
+    const auto R = kvec<T>(I, 0);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int i = 2 * r + e;
@@ -1322,10 +1334,10 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
 // Per instance, end of the iteration: converged, stopped, or beta for the
 // next one.
 __global__ __launch_bounds__(64) void k_bcg_fin(const Inst* const* insts, KOpts o) {
-  const Inst& I = *insts[blockIdx.x];
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
   const bool half = kstate_is(I, KS_BH);
   if (!half && !kstate_is(I, KS_BS)) return;
-  KState& ks = *I.ks;
+  auto& ks = *gp(I.ks);
   double tt = 0.0, rho = 0.0, rr = 0.0;
   for (int c = threadIdx.x; c < I.kchunks; c += 64) {
     tt += kpart(I, 0, c)[1];
