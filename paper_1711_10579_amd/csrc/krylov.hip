@@ -51,11 +51,16 @@ __device__ inline int apply_state(int mode) {
   return mode == 0 ? KS_ITER : mode == 1 ? KS_CYCLE : mode == 2 ? KS_BP : KS_BS;
 }
 
-__device__ inline double* kh_H(const Inst& I) { return I.kh; }
-__device__ inline double* kh_cs(const Inst& I) { return I.kh + (int64_t)(I.km + 1) * I.km; }
-__device__ inline double* kh_sn(const Inst& I) { return kh_cs(I) + I.km; }
-__device__ inline double* kh_g(const Inst& I) { return kh_sn(I) + I.km; }
-__device__ inline double* kh_y(const Inst& I) { return kh_g(I) + I.km + 1; }
+template <typename IR>
+__device__ inline double* kh_H(const IR& I) { return I.kh; }
+template <typename IR>
+__device__ inline double* kh_cs(const IR& I) { return I.kh + (int64_t)(I.km + 1) * I.km; }
+template <typename IR>
+__device__ inline double* kh_sn(const IR& I) { return kh_cs(I) + I.km; }
+template <typename IR>
+__device__ inline double* kh_g(const IR& I) { return kh_sn(I) + I.km; }
+template <typename IR>
+__device__ inline double* kh_y(const IR& I) { return kh_g(I) + I.km + 1; }
 template <typename IR>
 __device__ inline PF_AS1 double* kpart(const IR& I, int pass, int chunk) {
   return gp(I.kpart) + ((int64_t)pass * I.kchunks + chunk) * (I.km + 1);
@@ -140,20 +145,20 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
   const int2 wk = work[idx];
-  const Inst& I = *insts[wk.x];
-  if (!I.red->active) return;
+  const auto& I = *gp(gp(insts)[wk.x]);
+  if (!gp(I.red)->active) return;
   const int r = wk.y;
-  T* P = (T*)I.pval;
-  T* D = (T*)I.pdinv;
-  const int qd = I.kdiag[r];
-  for (int q = I.krow_ptr[r]; q < qd; ++q) {
-    const Blk<T> L = blk_mul(ld_blk(P, q), ld_blk((const T*)D, I.kcol[q]));
+  const auto P = gp((T*)I.pval);
+  const auto D = gp((T*)I.pdinv);
+  const int qd = gp(I.kdiag)[r];
+  for (int q = gp(I.krow_ptr)[r]; q < qd; ++q) {
+    const Blk<T> L = blk_mul(ld_blk(P, q), ld_blk((const T*)D, gp(I.kcol)[q]));
     st_blk(P, q, L);
-    ilu_updates<T>(P, I.kup_t, I.kup_s, I.kup_ptr[q], I.kup_ptr[q + 1], L);
+    ilu_updates<T>(P, I.kup_t, I.kup_s, gp(I.kup_ptr)[q], gp(I.kup_ptr)[q + 1], L);
   }
   Blk<T> inv;
   if (!blk_inv(ld_blk(P, qd), &inv)) {
-    I.red->singular = 1;
+    gp(I.red)->singular = 1;
     inv.a = inv.b = inv.c = inv.d = T(0);
   }
   st_blk(D, r, inv);
@@ -172,8 +177,8 @@ constexpr double kBjResidualTol = 1e-6;
 
 // the group's block gathered into a row-major 64 x (64 + pad) LDS array
 // (identity outside N x N)
-template <typename T, int LD>
-__device__ inline void bj_gather(const Inst& I, int r0, int s, double (*A)[LD]) {
+template <typename T, int LD, typename IR>
+__device__ inline void bj_gather(const IR& I, int r0, int s, double (*A)[LD]) {
   const int tid = threadIdx.x;
   const int N = 2 * s;
   for (int e = tid; e < 64 * 64; e += blockDim.x) {
@@ -182,11 +187,11 @@ __device__ inline void bj_gather(const Inst& I, int r0, int s, double (*A)[LD]) 
   }
   __syncthreads();
   for (int a = tid; a < s; a += blockDim.x) {
-    const int r = I.bj_rows[r0 + a];
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
-      const int c = I.kcol[q];
-      const int l = I.bj_loc[c];
-      if (l < s && I.bj_rows[r0 + l] == c) {
+    const int r = gp(I.bj_rows)[r0 + a];
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
+      const int c = gp(I.kcol)[q];
+      const int l = gp(I.bj_loc)[c];
+      if (l < s && gp(I.bj_rows)[r0 + l] == c) {
         const T* v = (const T*)I.jval + 4 * (int64_t)q;
         A[2 * a][2 * l] = (double)v[0];
         A[2 * a][2 * l + 1] = (double)v[1];
@@ -204,11 +209,11 @@ __global__ __launch_bounds__(256) void k_bj_inv_mfma(const Inst* const* insts, c
   __shared__ double stage[8 * kStage];
   __shared__ int bad_s;
   const int2 wk = work[blockIdx.x];
-  const Inst& I = *insts[wk.x];
-  if (!I.red->active) return;
+  const auto& I = *gp(gp(insts)[wk.x]);
+  if (!gp(I.red)->active) return;
   const int b = wk.y;
-  const int r0 = I.bj_ptr[b];
-  const int s = I.bj_ptr[b + 1] - r0;
+  const int r0 = gp(I.bj_ptr)[b];
+  const int s = gp(I.bj_ptr)[b + 1] - r0;
   const int N = 2 * s;
   if (threadIdx.x == 0) bad_s = 0;
   bj_gather<T, 65>(I, r0, s, A);
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(256) void k_bj_inv_mfma(const Inst* const* insts, c
   if (threadIdx.x == 0) I.bjbad[b] = bad_s;
   if (bad_s) return;
   // stored column-major: entry (i, col) at col N + i
-  T* out = (T*)I.bjinv + I.bj_off[b];
+  T* out = (T*)I.bjinv + gp(I.bj_off)[b];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -264,12 +269,12 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
   __shared__ int piv;
   __shared__ int bad;
   const int2 wk = work[blockIdx.x];
-  const Inst& I = *insts[wk.x];
-  if (!I.red->active) return;
+  const auto& I = *gp(gp(insts)[wk.x]);
+  if (!gp(I.red)->active) return;
   const int b = wk.y;
   if (!I.bjbad[b]) return;  // inverted without pivoting
-  const int r0 = I.bj_ptr[b];
-  const int s = I.bj_ptr[b + 1] - r0;
+  const int r0 = gp(I.bj_ptr)[b];
+  const int s = gp(I.bj_ptr)[b + 1] - r0;
   const int N = 2 * s;
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 128; e += 256) {
@@ -280,11 +285,11 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
   __syncthreads();
   // gather the block: member a (local), its row's entries in the same group
   for (int a = tid; a < s; a += 256) {
-    const int r = I.bj_rows[r0 + a];
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
-      const int c = I.kcol[q];
-      const int l = I.bj_loc[c];
-      if (l < s && I.bj_rows[r0 + l] == c) {
+    const int r = gp(I.bj_rows)[r0 + a];
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
+      const int c = gp(I.kcol)[q];
+      const int l = gp(I.bj_loc)[c];
+      if (l < s && gp(I.bj_rows)[r0 + l] == c) {
         const T* v = (const T*)I.jval + 4 * (int64_t)q;
         A[2 * a][2 * l] = (double)v[0];
         A[2 * a][2 * l + 1] = (double)v[1];
@@ -344,12 +349,12 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
     __syncthreads();
   }
   if (bad) {
-    if (tid == 0) I.red->singular = 1;
+    if (tid == 0) gp(I.red)->singular = 1;
     return;
   }
   // stored column-major: entry (i, c) at c N + i, so that a wave applying the
   // block reads one contiguous column per step
-  T* out = (T*)I.bjinv + I.bj_off[b];
+  T* out = (T*)I.bjinv + gp(I.bj_off)[b];
   for (int e = tid; e < N * N; e += 256) {
     const int c = e / N, i = e - c * N;
     out[e] = (T)A[i][64 + c];
@@ -368,25 +373,25 @@ __global__ __launch_bounds__(256) void k_ilu_fwd(const Inst* const* insts, const
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
   const int2 wk = work[idx];
-  const Inst& I = *insts[wk.x];
+  const auto& I = *gp(gp(insts)[wk.x]);
   if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
-  const T* w = (const T*)I.kw;
-  T* z = (T*)I.kz;
-  const T* P = (const T*)I.pval;
+  const auto w = gp((const T*)I.kw);
+  const auto z = gp((T*)I.kz);
+  const auto P = gp((const T*)I.pval);
   T v0 = w[2 * r], v1 = w[2 * r + 1];
   if (mode == 0) {
-    const double sc = I.ks->scale;
+    const double sc = gp(I.ks)->scale;
     v0 = (T)((double)v0 * sc);
     v1 = (T)((double)v1 * sc);
-    T* vj = (T*)I.kv + (int64_t)I.ks->j * 2 * I.nu;
+    T* vj = (T*)I.kv + (int64_t)gp(I.ks)->j * 2 * I.nu;
     vj[2 * r] = v0;
     vj[2 * r + 1] = v1;
   }
   double y0 = (double)v0, y1 = (double)v1;
-  for (int q = I.krow_ptr[r]; q < I.kdiag[r]; ++q) {
+  for (int q = gp(I.krow_ptr)[r]; q < gp(I.kdiag)[r]; ++q) {
     const Blk<T> L = ld_blk(P, q);
-    const int k = I.kcol[q];
+    const int k = gp(I.kcol)[q];
     const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
     y0 -= (double)L.a * a + (double)L.b * b;
     y1 -= (double)L.c * a + (double)L.d * b;
@@ -403,15 +408,15 @@ __global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
   const int2 wk = work[idx];
-  const Inst& I = *insts[wk.x];
+  const auto& I = *gp(gp(insts)[wk.x]);
   if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
-  T* z = (T*)I.kz;
-  const T* P = (const T*)I.pval;
+  const auto z = gp((T*)I.kz);
+  const auto P = gp((const T*)I.pval);
   double s0 = (double)z[2 * r], s1 = (double)z[2 * r + 1];
-  for (int q = I.kdiag[r] + 1; q < I.krow_ptr[r + 1]; ++q) {
+  for (int q = gp(I.kdiag)[r] + 1; q < gp(I.krow_ptr)[r + 1]; ++q) {
     const Blk<T> U = ld_blk(P, q);
-    const int k = I.kcol[q];
+    const int k = gp(I.kcol)[q];
     const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
     s0 -= (double)U.a * a + (double)U.b * b;
     s1 -= (double)U.c * a + (double)U.d * b;
@@ -671,34 +676,34 @@ __global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kspmv_dot(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
-  const int j = I.ks->j;
+  const int j = gp(I.ks)->j;
   const int r = blockIdx.x * KCH + threadIdx.x;
   const int64_t n2 = 2 * (int64_t)I.nu;
   double w0 = 0.0, w1 = 0.0;
   if (r < I.nu) {
-    const T* J = (const T*)I.jval;
-    const T* z = (const T*)I.kz;
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+    const auto J = gp((const T*)I.jval);
+    const auto z = gp((const T*)I.kz);
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
       const Blk<T> B = ld_blk(J, q);
-      const int c = I.kcol[q];
+      const int c = gp(I.kcol)[q];
       const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
       w0 += (double)B.a * a + (double)B.b * b;
       w1 += (double)B.c * a + (double)B.d * b;
     }
-    T* w = (T*)I.kw;
+    const auto w = gp((T*)I.kw);
     w[2 * r] = (T)w0;
     w[2 * r + 1] = (T)w1;
     w0 = (double)(T)w0;
     w1 = (double)(T)w1;
   }
-  const T* V = (const T*)I.kv;
+  const auto V = gp((const T*)I.kv);
   block_sums(
       j + 1,
       [&](int i) {
         if (r >= I.nu) return 0.0;
-        const T* vi = V + i * n2;
+        const auto vi = V + i * n2;
         return w0 * (double)vi[2 * r] + w1 * (double)vi[2 * r + 1];
       },
       red, kpart(I, 0, blockIdx.x));
@@ -713,9 +718,9 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
   __shared__ double red[KMAX + 1][KCH / 64];
   __shared__ double h[KMAX + 1];
   __shared__ double hg[8][KMAX + 1];
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
-  const int j = I.ks->j;
+  const int j = gp(I.ks)->j;
   // h_i = sum over chunks of the pass's partial dots: 8 interleaved groups
   // of chunks, then the groups in order
   const int ni = j + 1;
@@ -739,14 +744,14 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
   __syncthreads();
   const int r = blockIdx.x * KCH + threadIdx.x;
   const int64_t n2 = 2 * (int64_t)I.nu;
-  const T* V = (const T*)I.kv;
+  const auto V = gp((const T*)I.kv);
   double w0 = 0.0, w1 = 0.0;
   if (r < I.nu) {
-    T* w = (T*)I.kw;
+    const auto w = gp((T*)I.kw);
     w0 = (double)w[2 * r];
     w1 = (double)w[2 * r + 1];
     for (int i = 0; i <= j; ++i) {
-      const T* vi = V + i * n2;
+      const auto vi = V + i * n2;
       w0 -= h[i] * (double)vi[2 * r];
       w1 -= h[i] * (double)vi[2 * r + 1];
     }
@@ -760,7 +765,7 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
         j + 1,
         [&](int i) {
           if (r >= I.nu) return 0.0;
-          const T* vi = V + i * n2;
+          const auto vi = V + i * n2;
           return w0 * (double)vi[2 * r] + w1 * (double)vi[2 * r + 1];
         },
         red, kpart(I, 1, blockIdx.x));
@@ -781,7 +786,7 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
 __global__ __launch_bounds__(64) void k_karnoldi_end(const Inst* const* insts, KOpts o) {
   __shared__ double hc[KMAX + 1], scs[KMAX], ssn[KMAX], y[KMAX];
   __shared__ int fin;
-  const Inst& I = *insts[blockIdx.x];
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
   if (!kstate_is(I, KS_ITER)) return;
   KState& ks = *I.ks;
   const int lane = threadIdx.x;
@@ -823,7 +828,7 @@ __global__ __launch_bounds__(64) void k_karnoldi_end(const Inst* const* insts, K
       ks.rel = rel;
       ks.j = j + 1;
       ks.total += 1;
-      I.red->linear_iters += 1;
+      gp(I.red)->linear_iters += 1;
       fin = (rel <= ks.eta || j + 1 >= o.m || !(h > 0.0)) ? 1 : 0;
       if (fin) ks.met = rel <= ks.eta;
       else ks.scale = 1.0 / h;
@@ -855,16 +860,16 @@ __global__ __launch_bounds__(64) void k_karnoldi_end(const Inst* const* insts, K
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kbegin(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
-  const Inst& I = *insts[blockIdx.y];
-  if (!I.red->active || (int)blockIdx.x >= I.kchunks) return;
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
+  if (!gp(I.red)->active || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   double f0 = 0.0, f1 = 0.0;
   if (r < I.nu) {
-    const int p = I.kp_of_r[r];
+    const int p = gp(I.kp_of_r)[r];
     f0 = I.F[2 * p];
     f1 = I.F[2 * p + 1];
-    T* w = (T*)I.kw;
-    T* x = (T*)I.kx;
+    const auto w = gp((T*)I.kw);
+    const auto x = gp((T*)I.kx);
     w[2 * r] = (T)f0;
     w[2 * r + 1] = (T)f1;
     x[2 * r] = T(0);
@@ -878,13 +883,13 @@ __global__ __launch_bounds__(KCH) void k_kbegin(const Inst* const* insts) {
 // ||F||_inf), eta_floor) and the first cycle.  A singular preconditioner
 // ends the instance's Newton iteration with status singular.
 __global__ __launch_bounds__(64) void k_kbegin_fin(const Inst* const* insts, KOpts o) {
-  const Inst& I = *insts[blockIdx.x];
-  if (!I.red->active) return;
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
+  if (!gp(I.red)->active) return;
   KState& ks = *I.ks;
-  if (I.red->singular) {
+  if (gp(I.red)->singular) {
     if (threadIdx.x == 0) {
-      I.red->status = 3;
-      I.red->active = 0;
+      gp(I.red)->status = 3;
+      gp(I.red)->active = 0;
       ks.state = KS_DONE;
     }
     return;
@@ -894,7 +899,7 @@ __global__ __launch_bounds__(64) void k_kbegin_fin(const Inst* const* insts, KOp
   const double bn = sqrt(wave_sum(part));
   if (threadIdx.x != 0) return;
   ks.bnorm = bn;
-  ks.eta = fmax(fmin(o.eta_max, I.red->last_norm), o.eta_floor);
+  ks.eta = fmax(fmin(o.eta_max, gp(I.red)->last_norm), o.eta_floor);
   ks.j = 0;
   ks.cycle = 0;
   ks.met = 0;
@@ -914,20 +919,20 @@ __global__ __launch_bounds__(64) void k_kbegin_fin(const Inst* const* insts, KOp
 // u = V y over the basis of the finished cycle (into w).
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kycomb(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_CYCLE) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   if (r >= I.nu) return;
-  const int k = I.ks->j;
+  const int k = gp(I.ks)->j;
   const double* y = kh_y(I);
   const int64_t n2 = 2 * (int64_t)I.nu;
-  const T* V = (const T*)I.kv;
+  const auto V = gp((const T*)I.kv);
   double u0 = 0.0, u1 = 0.0;
   for (int i = 0; i < k; ++i) {
     u0 += y[i] * (double)V[i * n2 + 2 * r];
     u1 += y[i] * (double)V[i * n2 + 2 * r + 1];
   }
-  T* w = (T*)I.kw;
+  const auto w = gp((T*)I.kw);
   w[2 * r] = (T)u0;
   w[2 * r + 1] = (T)u1;
 }
@@ -935,12 +940,12 @@ __global__ __launch_bounds__(KCH) void k_kycomb(const Inst* const* insts) {
 // x += z (the preconditioned correction of the cycle).
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kxadd(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_CYCLE) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   if (r >= I.nu) return;
-  T* x = (T*)I.kx;
-  const T* z = (const T*)I.kz;
+  const auto x = gp((T*)I.kx);
+  const auto z = gp((const T*)I.kz);
   x[2 * r] = (T)((double)x[2 * r] + (double)z[2 * r]);
   x[2 * r + 1] = (T)((double)x[2 * r + 1] + (double)z[2 * r + 1]);
 }
@@ -952,7 +957,7 @@ __global__ __launch_bounds__(KCH) void k_kxadd(const Inst* const* insts) {
 __global__ void k_kcycle_fin(const Inst* const* insts, int nslots, KOpts o) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
+  const auto& I = *gp(gp(insts)[sl]);
   if (!kstate_is(I, KS_CYCLE)) return;
   KState& ks = *I.ks;
   if (ks.met) {
@@ -972,24 +977,24 @@ __global__ void k_kcycle_fin(const Inst* const* insts, int nslots, KOpts o) {
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kresid(const Inst* const* insts) {
   __shared__ double red[KMAX + 1][KCH / 64];
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_RESTART) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   double w0 = 0.0, w1 = 0.0;
   if (r < I.nu) {
-    const int p = I.kp_of_r[r];
+    const int p = gp(I.kp_of_r)[r];
     w0 = I.F[2 * p];
     w1 = I.F[2 * p + 1];
-    const T* J = (const T*)I.jval;
-    const T* x = (const T*)I.kx;
-    for (int q = I.krow_ptr[r]; q < I.krow_ptr[r + 1]; ++q) {
+    const auto J = gp((const T*)I.jval);
+    const auto x = gp((const T*)I.kx);
+    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
       const Blk<T> B = ld_blk(J, q);
-      const int c = I.kcol[q];
+      const int c = gp(I.kcol)[q];
       const double a = (double)x[2 * c], b = (double)x[2 * c + 1];
       w0 -= (double)B.a * a + (double)B.b * b;
       w1 -= (double)B.c * a + (double)B.d * b;
     }
-    T* w = (T*)I.kw;
+    const auto w = gp((T*)I.kw);
     w[2 * r] = (T)w0;
     w[2 * r + 1] = (T)w1;
     w0 = (double)(T)w0;
@@ -1002,7 +1007,7 @@ __global__ __launch_bounds__(KCH) void k_kresid(const Inst* const* insts) {
 // Per instance: the true residual starts the next cycle, or ends the solve
 // when it already meets the forcing term.
 __global__ __launch_bounds__(64) void k_krestart_fin(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.x];
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
   if (!kstate_is(I, KS_RESTART)) return;
   KState& ks = *I.ks;
   double part = 0.0;
@@ -1024,13 +1029,13 @@ __global__ __launch_bounds__(64) void k_krestart_fin(const Inst* const* insts) {
 // The Newton step in the factor layout that the voltage update reads.
 template <typename T>
 __global__ __launch_bounds__(KCH) void k_kfinish(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_FINISH) || (int)blockIdx.x >= I.kchunks) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   if (r >= I.nu) return;
-  const int p = I.kp_of_r[r];
-  const T* x = (const T*)I.kx;
-  T* out = (T*)I.x;
+  const int p = gp(I.kp_of_r)[r];
+  const auto x = gp((const T*)I.kx);
+  const auto out = gp((T*)I.x);
   out[2 * p] = x[2 * r];
   out[2 * p + 1] = x[2 * r + 1];
 }
@@ -1083,13 +1088,13 @@ __device__ inline void bcg_stop(const IR& I, KOpts o) {
 // Per instance, after k_kbegin (w = F, x = 0, partial ||F||^2): ||F||_2,
 // the forcing term, <r0, r> = ||F||^2 and the first iteration.
 __global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, KOpts o) {
-  const Inst& I = *insts[blockIdx.x];
-  if (!I.red->active) return;
+  const auto& I = *gp(gp(insts)[blockIdx.x]);
+  if (!gp(I.red)->active) return;
   KState& ks = *I.ks;
-  if (I.red->singular) {
+  if (gp(I.red)->singular) {
     if (threadIdx.x == 0) {
-      I.red->status = 3;
-      I.red->active = 0;
+      gp(I.red)->status = 3;
+      gp(I.red)->active = 0;
       ks.state = KS_DONE;
     }
     return;
@@ -1100,7 +1105,7 @@ __global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, 
   if (threadIdx.x != 0) return;
   const double bn = sqrt(b2);
   ks.bnorm = bn;
-  ks.eta = fmax(fmin(o.eta_max, I.red->last_norm), o.eta_floor);
+  ks.eta = fmax(fmin(o.eta_max, gp(I.red)->last_norm), o.eta_floor);
   ks.j = 0;
   ks.cycle = 0;
   ks.met = 0;
@@ -1377,8 +1382,8 @@ __global__ __launch_bounds__(64) void k_bcg_fin(const Inst* const* insts, KOpts 
 __global__ void k_kretire(const Inst* const* insts, int nslots) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
-  if (kstate_is(I, KS_FINISH)) I.ks->state = KS_DONE;
+  const auto& I = *gp(gp(insts)[sl]);
+  if (kstate_is(I, KS_FINISH)) gp(I.ks)->state = KS_DONE;
 }
 
 // Krylov state of every instance for the host (KS_DONE once the Newton
@@ -1387,9 +1392,9 @@ __global__ void k_kretire(const Inst* const* insts, int nslots) {
 __global__ void k_kgather(const Inst* const* insts, int nslots, int* out) {
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslots) return;
-  const Inst& I = *insts[sl];
-  out[sl] = I.red->active ? I.ks->state : KS_DONE;
-  out[nslots + sl] = I.ks->total;
+  const auto& I = *gp(gp(insts)[sl]);
+  out[sl] = gp(I.red)->active ? gp(I.ks)->state : KS_DONE;
+  out[nslots + sl] = gp(I.ks)->total;
 }
 
 // ---------------------------------------------------------------------------
