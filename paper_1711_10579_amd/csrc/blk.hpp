@@ -31,14 +31,17 @@ __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Device-coherent accesses for data handed between work-groups inside a
 // launch: relaxed atomics at agent scope (stores write through, loads bypass
-// the caches that are not coherent across the device).
+// the caches that are not coherent across the device), issued as global
+// (not generic) accesses so that they are counted by the vector-memory wait
+// counter alone and LDS waits do not wait for them.  p points to device
+// memory.
 template <typename T>
 __device__ inline T ld_dev(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const PF_AS1 T*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ inline void st_dev(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((PF_AS1 T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Work-groups of a launch are handed to the device's eight XCDs (each with

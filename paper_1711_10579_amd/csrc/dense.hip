@@ -54,7 +54,7 @@ __device__ inline unsigned long long panel_flag(int epoch, int k0) {
 // invalidated.  The writer waits for its stores to complete before the flag
 // is set; the reader loads after seeing the flag.
 __device__ inline unsigned long long flag_ld(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const PF_AS1 unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Every inter-work-group wait here (bounded by kWaitTicks) is on a
@@ -381,7 +381,9 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
     // every wave's stores have completed before the flag is set
     wait_vmem();
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0)
+      __hip_atomic_store((PF_AS1 unsigned long long*)&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
