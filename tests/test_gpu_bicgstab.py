@@ -201,3 +201,38 @@ def test_lu_fallback_in_a_batch_leaves_the_others_alone(B, ctx):
     _check(hard, res[1], B.pf_get_voltage(hh))
     hs.close()
     hh.close()
+
+
+@pytest.mark.parametrize("solver,precond", [(1, 0), (1, 1), (2, 0), (2, 1)],
+                         ids=["gmres-ilu0", "gmres-bjacobi", "bicgstab-ilu0", "bicgstab-bjacobi"])
+def test_queued_inner_runs_leave_results_unchanged(B, ctx, solver, precond):
+    """A reused case queues, at each Newton step, as many Krylov iterations
+    (or Arnoldi steps) per state read as the same step took in its last
+    solve; iterations past the end of an inner solve are skipped on the
+    device.  Solves that queue too many (a lighter loading) or too few (a
+    heavier one) match a fresh case's solve bit for bit, inner counts
+    included."""
+    case = pfgen.make_polar_grid(1500, 450, 150, 31, balanced=True)
+    opts = dict(solver=solver, precond=precond, max_iter=40, gmres_max_restarts=40)
+    _say(f"queued inner runs solver={solver} precond={precond}")
+    h = B.pf_create_from(ctx, case)
+    r0 = B.pf_solve(h, **opts)
+    assert r0.status == 0, r0.as_dict()
+    counts = set()
+    for scale in (1.3, 0.7, 1.6):
+        p_sp, q_sp = case.p_sp * scale, case.q_sp * scale
+        B.pf_set_injections(h, p_sp=p_sp, q_sp=q_sp)
+        r = B.pf_solve(h, **opts)
+        V = B.pf_get_voltage(h)
+        fresh = B.pf_create_from(ctx, case)
+        B.pf_set_injections(fresh, p_sp=p_sp, q_sp=q_sp)
+        rf = B.pf_solve(fresh, **opts)
+        assert r.status == rf.status and r.iters == rf.iters, (scale, r.as_dict(), rf.as_dict())
+        assert r.linear_iters == rf.linear_iters, (scale, r.as_dict(), rf.as_dict())
+        assert np.array_equal(V, B.pf_get_voltage(fresh), equal_nan=True), scale
+        _say(f"  scale {scale}: status {r.status}, {r.iters} steps, {r.linear_iters} inner (last {r0.linear_iters})")
+        counts.add((r.linear_iters > r0.linear_iters) - (r.linear_iters < r0.linear_iters))
+        r0 = r
+        fresh.close()
+    assert {-1, 1} <= counts, counts
+    h.close()
