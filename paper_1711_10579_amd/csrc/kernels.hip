@@ -914,17 +914,22 @@ __global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, co
   const int t = w.y + (int)threadIdx.x / G;
   const bool live = t < I.ntt;
   const T* lu = (const T*)I.lu;
+  // the target's own values, fetched before its sum (no other thread of
+  // the launch writes them)
+  const bool own = live && lane == 0;
+  const int g = own ? gp(I.tail_tgt)[t] : 0;
+  const int ta = g / I.nt, tb = g - ta * I.nt;
+  const auto p = gp((T*)I.tail) + (int64_t)(2 * tb) * I.ldt + 2 * ta;
+  Blk<T> old = {T(0), T(0), T(0), T(0)};
+  if (own) old = {p[0], p[I.ldt], p[1], p[I.ldt + 1]};
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
   if (live) sub_updates<T, G>(acc, lu, I.tail_l, I.tail_u, gp(I.tail_uptr)[t] + lane, gp(I.tail_uptr)[t + 1]);
   acc = group_sum<T, G>(acc);
-  if (!active || !live || lane != 0) return;
-  int g = gp(I.tail_tgt)[t];
-  int ta = g / I.nt, tb = g - ta * I.nt;
-  auto p = gp((T*)I.tail) + (int64_t)(2 * tb) * I.ldt + 2 * ta;
-  p[0] += acc.a;
-  p[1] += acc.c;
-  p[I.ldt] += acc.b;
-  p[I.ldt + 1] += acc.d;
+  if (!active || !own) return;
+  p[0] = old.a + acc.a;
+  p[1] = old.c + acc.c;
+  p[I.ldt] = old.b + acc.b;
+  p[I.ldt + 1] = old.d + acc.d;
 }
 
 // ---------------------------------------------------------------------------
