@@ -430,7 +430,9 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
     // between two reads of the states: each kernel acts only on the
     // instances in the state it serves, so an instance whose cycle ends
     // within the run skips its remaining steps
-    const int run = iter ? run_length(most) : 0;
+    // (a run ends with the current cycle: steps past it would be skipped)
+    const int left = ko.m - most % std::max(ko.m, 1);
+    const int run = iter ? std::max(1, std::min(run_length(most), left)) : 0;
     queued += std::max(run, 1);
     for (int i = 0; i < run; ++i) {
       apply(0);
