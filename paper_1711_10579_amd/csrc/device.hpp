@@ -117,7 +117,8 @@ struct KState {
   double eta;    // forcing term (relative residual target)
   double scale;  // factor that normalises the next basis vector
   double rel;    // residual estimate relative to bnorm
-  double rho, alpha, omega, beta;  // BiCGStab: <r0, r>, and the step factors
+  double rho[2];  // BiCGStab: <r0, r> for the iteration of that parity
+  double alpha, omega, beta;  // BiCGStab: the step factors
   int j;         // Arnoldi steps of the current cycle (BiCGStab: iterations done)
   int cycle;     // restarts done
   int state;     // KS_* below

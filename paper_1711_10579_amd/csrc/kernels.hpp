@@ -85,16 +85,17 @@ template <typename T>
 void launch_kcycle_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
 template <typename T>
 void launch_kfinish(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
-// BiCGStab: start, then per iteration the direction, [apply mode 2], the
-// first half and its test, [apply mode 3], the second half and the test
+// BiCGStab: start and the first direction, then per iteration it [apply
+// mode 2], v = J p^ and s, [apply mode 3], the first half's test with
+// t = J s^, the update of x and r, and the test with the next direction
 template <typename T>
 void launch_bcg_begin(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
 template <typename T>
 void launch_bcg_dir(hipStream_t, const Inst* const* insts, int nslots, int max_chunks);
 template <typename T>
-void launch_bcg_half(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+void launch_bcg_half(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, int it);
 template <typename T>
-void launch_bcg_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
+void launch_bcg_end(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o, int it);
 void launch_kgather(hipStream_t, const Inst* const* insts, int nslots, int* out);
 int krylov_max_restart();
 

@@ -48,7 +48,7 @@ __device__ inline bool kstate_is(const IR& I, int want) {
 // step (scaled input stored as basis vector), 1 the end of a GMRES cycle,
 // 2 and 3 the first and second half of a BiCGStab iteration
 __device__ inline int apply_state(int mode) {
-  return mode == 0 ? KS_ITER : mode == 1 ? KS_CYCLE : mode == 2 ? KS_BP : KS_BS;
+  return mode == 0 ? KS_ITER : mode == 1 ? KS_CYCLE : KS_BP;
 }
 
 template <typename IR>
@@ -1044,17 +1044,22 @@ __global__ __launch_bounds__(KCH) void k_kfinish(const Inst* const* insts) {
 // BiCGStab (van der Vorst), the Krylov method the paper tested (Sec. III-B),
 // right-preconditioned, from x = 0 with the shadow residual r0 = F.  Vectors
 // in the basis storage: r (0; s overwrites it), r0 (1), p (2), v (3),
-// p^ = M^-1 p (4), s^ = M^-1 s (5), t (6).  One iteration is the launch
+// p^ = M^-1 p (4), s^ = M^-1 s (5), t (6).  The first direction p = r =
+// r0 = F goes into w at the start; then one iteration is the launch
 // sequence
-//   KS_BP: p = r + beta (p - omega v) (p = r at first) into w; z = M^-1 w;
-//          p^ = z, v = J p^ with partial <r0, v>; alpha = <r0, r> / <r0, v>,
-//          s = r - alpha v into w with partial ||s||^2; per instance: the
-//          first half meets the tolerance (-> KS_BH) or not (-> KS_BS)
-//   KS_BS: z = M^-1 w; s^ = z, t = J s^ with partial <t, s>, <t, t>;
-//          omega = <t, s> / <t, t>, x += alpha p^ + omega s^,
-//          r = s - omega t with partial <r0, r>, ||r||^2; per instance: the
-//          convergence test and beta for the next iteration
+//   KS_BP: z = M^-1 w; p^ = z, v = J p^ with partial <r0, v>;
+//          alpha = <r0, r> / <r0, v>, s = r - alpha v into w with partial
+//          ||s||^2; z = M^-1 w; the first half meets the tolerance
+//          (-> KS_BH) or not (-> KS_BS), and in KS_BS s^ = z, t = J s^ with
+//          partial <t, s>, <t, t>
+//   KS_BS: omega = <t, s> / <t, t>, x += alpha p^ + omega s^,
+//          r = s - omega t with partial <r0, r>, ||r||^2; the convergence
+//          test, beta and the next direction p = r + beta (p - omega v)
+//          into w (-> KS_BP)
 //   KS_BH: x += alpha p^, done.
+// The tests run in every work-group of the launch that follows the partial
+// sums they need (the same sums in the same order everywhere), the first
+// work-group setting the state; seven launches per iteration.
 // A zero <r0, r>, <r0, v>, <t, t> or omega, or the iteration limit, ends the
 // solve with x as it stands: the step is taken when its relative residual
 // is at most eta_max, else the Newton iteration ends with a linear failure.
@@ -1111,7 +1116,7 @@ __global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, 
   ks.met = 0;
   ks.total = 0;
   ks.rel = 1.0;
-  ks.rho = b2;
+  ks.rho[0] = b2;
   ks.alpha = ks.omega = 1.0;
   ks.beta = 0.0;
   if (bn > 0.0) {
@@ -1183,15 +1188,16 @@ __global__ __launch_bounds__(KCH) void k_bcg_v(const Inst* const* insts) {
       1, [&](int) { return d; }, red, kpart(I, 0, blockIdx.x));
 }
 
-// alpha = <r0, r> / <r0, v>; s = r - alpha v into r and w; partial ||s||^2.
+// alpha = <r0, r> / <r0, v>; s = r - alpha v into r and w; partial ||s||^2
+// (it: the iteration, counted from 0 in the inner solve).
 template <typename T>
-__global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
+__global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts, int it) {
   __shared__ double red[KMAX + 1][KCH / 64];
   __shared__ double alpha_s;
   const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (!kstate_is(I, KS_BP) || (int)blockIdx.x >= I.kchunks) return;
   if (threadIdx.x < 64) {
-    const double a = gp(I.ks)->rho / chunk_sum(I, 0, 0);
+    const double a = gp(I.ks)->rho[it & 1] / chunk_sum(I, 0, 0);
     if (threadIdx.x == 0) {
       alpha_s = a;
       if (blockIdx.x == 0) gp(I.ks)->alpha = a;
@@ -1218,41 +1224,49 @@ __global__ __launch_bounds__(KCH) void k_bcg_s(const Inst* const* insts) {
       1, [&](int) { return s0 * s0 + s1 * s1; }, red, kpart(I, 1, blockIdx.x));
 }
 
-// Per instance: the first half of the iteration meets the tolerance or not.
-__global__ __launch_bounds__(64) void k_bcg_half(const Inst* const* insts, KOpts o) {
-  const auto& I = *gp(gp(insts)[blockIdx.x]);
-  if (!kstate_is(I, KS_BP)) return;
-  auto& ks = *gp(I.ks);
-  double sv = 0.0, ss = 0.0;
-  for (int c = threadIdx.x; c < I.kchunks; c += 64) {
-    sv += fabs(kpart(I, 0, c)[0]);
-    ss += kpart(I, 1, c)[0];
-  }
-  sv = wave_sum(sv);
-  ss = wave_sum(ss);
-  if (threadIdx.x != 0) return;
-  ks.total += 1;
-  gp(I.red)->linear_iters += 1;
-  if (!(sv > 0.0) || !isfinite(ks.alpha)) {
-    bcg_stop(I, o);
-    return;
-  }
-  const double srel = sqrt(ss) / ks.bnorm;
-  if (srel <= ks.eta) {
-    ks.rel = srel;
-    ks.met = 1;
-    ks.state = KS_BH;
-  } else {
-    ks.state = KS_BS;
-  }
-}
-
-// s^ = z, t = J s^ for the rows of one chunk, partial <t, s> and <t, t>.
+// The first half of the iteration, decided in every work-group from the
+// chunk partials (the same sums in the same order, so every work-group
+// decides alike): a zero <r0, v> or a non-finite alpha ends the solve as it
+// stands, a small enough ||s|| takes x += alpha p^ only (KS_BH); otherwise
+// (KS_BS) s^ = z, t = J s^ for the rows of one chunk, partial <t, s>,
+// <t, t>.  The first work-group counts the iteration and sets the state;
+// the others accept the state it sets as the one they started from.
 template <typename T>
-__global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts) {
+__global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts, KOpts o) {
   __shared__ double red[KMAX + 1][KCH / 64];
+  __shared__ int decision;  // 0 second half, 1 first half met, 2 breakdown
   const auto& I = *gp(gp(insts)[blockIdx.y]);
-  if (!kstate_is(I, KS_BS) || (int)blockIdx.x >= I.kchunks) return;
+  if ((!kstate_is(I, KS_BP) && !kstate_is(I, KS_BS)) || (int)blockIdx.x >= I.kchunks) return;
+  auto& ks = *gp(I.ks);
+  if (threadIdx.x < 64) {
+    double sv = 0.0, ss = 0.0;
+    for (int c = threadIdx.x; c < I.kchunks; c += 64) {
+      sv += fabs(kpart(I, 0, c)[0]);
+      ss += kpart(I, 1, c)[0];
+    }
+    sv = wave_sum(sv);
+    ss = wave_sum(ss);
+    if (threadIdx.x == 0) {
+      const double srel = sqrt(ss) / ks.bnorm;
+      const int dec = (!(sv > 0.0) || !isfinite(ks.alpha)) ? 2 : srel <= ks.eta ? 1 : 0;
+      decision = dec;
+      if (blockIdx.x == 0) {
+        ks.total += 1;
+        gp(I.red)->linear_iters += 1;
+        if (dec == 2) {
+          bcg_stop(I, o);
+        } else if (dec == 1) {
+          ks.rel = srel;
+          ks.met = 1;
+          ks.state = KS_BH;
+        } else {
+          ks.state = KS_BS;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (decision != 0) return;
   const int r = blockIdx.x * KCH + threadIdx.x;
   double ts = 0.0, tt = 0.0;
   if (r < I.nu) {
@@ -1279,7 +1293,7 @@ __global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts) {
     tt = t0 * t0 + t1 * t1;
   }
   block_sums(
-      2, [&](int e) { return e == 0 ? ts : tt; }, red, kpart(I, 0, blockIdx.x));
+      2, [&](int e) { return e == 0 ? ts : tt; }, red, kpart(I, 2, blockIdx.x));
 }
 
 // KS_BS: omega = <t, s> / <t, t>, x += alpha p^ + omega s^, r = s - omega t,
@@ -1305,8 +1319,8 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
     return;
   }
   if (threadIdx.x < 64) {
-    const double tt = chunk_sum(I, 0, 1);
-    const double ts = chunk_sum(I, 0, 0);
+    const double tt = chunk_sum(I, 2, 1);
+    const double ts = chunk_sum(I, 2, 0);
     if (threadIdx.x == 0) {
       skip_s = !(tt > 0.0);
       omega_s = skip_s ? 0.0 : ts / tt;
@@ -1336,46 +1350,83 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
       2, [&](int e) { return e == 0 ? d : q; }, red, kpart(I, 1, blockIdx.x));
 }
 
-// Per instance, end of the iteration: converged, stopped, or beta for the
-// next one.
-__global__ __launch_bounds__(64) void k_bcg_fin(const Inst* const* insts, KOpts o) {
-  const auto& I = *gp(gp(insts)[blockIdx.x]);
+// The end of iteration it, decided in every work-group from the chunk
+// partials (alike everywhere): the first half met ends the solve
+// (KS_FINISH); a zero <t, t> ends it as it stands; then the convergence
+// test; then, unless omega or <r0, r> is zero, the iteration limit is
+// reached or the residual is not finite, beta = (rho' / rho)(alpha / omega)
+// and the next direction p = r + beta (p - omega v) into p and w for the
+// rows of one chunk.  The first work-group sets the instance's scalars and
+// state (<r0, r> goes to the other parity, so no work-group reads a value
+// this launch writes); the others accept the state it sets.
+template <typename T>
+__global__ __launch_bounds__(KCH) void k_bcg_next(const Inst* const* insts, KOpts o, int it) {
+  __shared__ double beta_s;
+  __shared__ int go;
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   const bool half = kstate_is(I, KS_BH);
-  if (!half && !kstate_is(I, KS_BS)) return;
+  if ((!half && !kstate_is(I, KS_BS) && !kstate_is(I, KS_BP)) || (int)blockIdx.x >= I.kchunks) return;
   auto& ks = *gp(I.ks);
-  double tt = 0.0, rho = 0.0, rr = 0.0;
-  for (int c = threadIdx.x; c < I.kchunks; c += 64) {
-    tt += kpart(I, 0, c)[1];
-    rho += kpart(I, 1, c)[0];
-    rr += kpart(I, 1, c)[1];
+  if (threadIdx.x < 64) {
+    const double tt = chunk_sum(I, 2, 1);
+    const double rho = chunk_sum(I, 1, 0);
+    const double rr = chunk_sum(I, 1, 1);
+    if (threadIdx.x == 0) {
+      const double rel = sqrt(rr) / ks.bnorm;
+      const int max_it = max(1, (1 + o.max_restarts) * o.m / 2);
+      // 0 finish, 1 stop as it stands (the relative residual set first or
+      // not), 2 go on
+      int dec;
+      bool set_rel = false;
+      if (half) {
+        dec = 0;
+      } else if (!(tt > 0.0)) {
+        dec = 1;
+      } else if (rel <= ks.eta) {
+        dec = 0;
+        set_rel = true;
+      } else if (ks.omega == 0.0 || rho == 0.0 || it + 1 >= max_it || !isfinite(rel)) {
+        dec = 1;
+        set_rel = true;
+      } else {
+        dec = 2;
+        set_rel = true;
+      }
+      const double beta = (rho / ks.rho[it & 1]) * (ks.alpha / ks.omega);
+      go = dec == 2;
+      beta_s = beta;
+      if (blockIdx.x == 0) {
+        if (set_rel) ks.rel = rel;
+        if (set_rel && dec != 0) ks.j = it + 1;
+        if (dec == 0) {
+          if (!half) ks.met = 1;
+          ks.state = KS_FINISH;
+        } else if (dec == 1) {
+          bcg_stop(I, o);
+        } else {
+          ks.beta = beta;
+          ks.rho[(it + 1) & 1] = rho;
+          ks.state = KS_BP;
+        }
+      }
+    }
   }
-  tt = wave_sum(tt);
-  rho = wave_sum(rho);
-  rr = wave_sum(rr);
-  if (threadIdx.x != 0) return;
-  if (half) {
-    ks.state = KS_FINISH;
-    return;
+  __syncthreads();
+  if (!go) return;
+  const int r = blockIdx.x * KCH + threadIdx.x;
+  if (r >= I.nu) return;
+  const double beta = beta_s, omega = ks.omega;
+  const auto w = gp((T*)I.kw);
+  const auto R = kvec<T>(I, 0);
+  const auto P = kvec<T>(I, 2);
+  const auto V = kvec<T>(I, 3);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = 2 * r + e;
+    const T p = (T)((double)R[i] + beta * ((double)P[i] - omega * (double)V[i]));
+    P[i] = p;
+    w[i] = p;
   }
-  if (!(tt > 0.0)) {
-    bcg_stop(I, o);
-    return;
-  }
-  ks.rel = sqrt(rr) / ks.bnorm;
-  if (ks.rel <= ks.eta) {
-    ks.met = 1;
-    ks.state = KS_FINISH;
-    return;
-  }
-  ks.j += 1;
-  const int max_it = max(1, (1 + o.max_restarts) * o.m / 2);
-  if (ks.omega == 0.0 || rho == 0.0 || ks.j >= max_it || !isfinite(ks.rel)) {
-    bcg_stop(I, o);
-    return;
-  }
-  ks.beta = (rho / ks.rho) * (ks.alpha / ks.omega);
-  ks.rho = rho;
-  ks.state = KS_BP;
 }
 
 // Per instance: a written result retires the solve (KS_FINISH -> KS_DONE).
@@ -1484,18 +1535,17 @@ void launch_bcg_dir(hipStream_t st, const Inst* const* insts, int nslots, int ma
   k_bcg_dir<T><<<chunk_grid(max_chunks, nslots), KCH, 0, st>>>(insts);
 }
 template <typename T>
-void launch_bcg_half(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+void launch_bcg_half(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, int it) {
   const dim3 g = chunk_grid(max_chunks, nslots);
   k_bcg_v<T><<<g, KCH, 0, st>>>(insts);
-  k_bcg_s<T><<<g, KCH, 0, st>>>(insts);
-  k_bcg_half<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
+  k_bcg_s<T><<<g, KCH, 0, st>>>(insts, it);
 }
 template <typename T>
-void launch_bcg_end(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
+void launch_bcg_end(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o, int it) {
   const dim3 g = chunk_grid(max_chunks, nslots);
-  k_bcg_t<T><<<g, KCH, 0, st>>>(insts);
+  k_bcg_t<T><<<g, KCH, 0, st>>>(insts, o);
   k_bcg_x<T><<<g, KCH, 0, st>>>(insts);
-  k_bcg_fin<<<dim3((unsigned)nslots), 64, 0, st>>>(insts, o);
+  k_bcg_next<T><<<g, KCH, 0, st>>>(insts, o, it);
 }
 void launch_kgather(hipStream_t st, const Inst* const* insts, int nslots, int* out) {
   k_kgather<<<slot_grid(nslots), 64, 0, st>>>(insts, nslots, out);
@@ -1517,8 +1567,8 @@ int krylov_max_restart() { return KMAX; }
   template void launch_kfinish<T>(hipStream_t, const Inst* const*, int, int);                  \
   template void launch_bcg_begin<T>(hipStream_t, const Inst* const*, int, int, KOpts);        \
   template void launch_bcg_dir<T>(hipStream_t, const Inst* const*, int, int);                 \
-  template void launch_bcg_half<T>(hipStream_t, const Inst* const*, int, int, KOpts);         \
-  template void launch_bcg_end<T>(hipStream_t, const Inst* const*, int, int, KOpts);
+  template void launch_bcg_half<T>(hipStream_t, const Inst* const*, int, int, int);           \
+  template void launch_bcg_end<T>(hipStream_t, const Inst* const*, int, int, KOpts, int);
 
 PF_KINST(double)
 PF_KINST(float)

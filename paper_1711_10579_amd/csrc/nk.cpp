@@ -336,9 +336,10 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
   const bool bcg = opt->solver == PF_SOLVER_BICGSTAB;
   {
     Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-    if (bcg)
+    if (bcg) {
       pfd::launch_bcg_begin<T>(s, I, ns, mc, ko);
-    else
+      pfd::launch_bcg_dir<T>(s, I, ns, mc);  // p = r = r0 = F
+    } else
       pfd::launch_kbegin<T>(s, I, ns, mc, ko);
     pfd::launch_kfinish<T>(s, I, ns, mc);
   }
@@ -400,18 +401,17 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       const int run = run_length(most);
       queued += run;
       for (int i = 0; i < run; ++i) {
-        {
-          Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-          pfd::launch_bcg_dir<T>(s, I, ns, mc);
-        }
+        // the iteration's index in the inner solve: every instance still
+        // iterating has done exactly that many
+        const int it = queued - run + i;
         apply(2);
         {
           Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-          pfd::launch_bcg_half<T>(s, I, ns, mc, ko);
+          pfd::launch_bcg_half<T>(s, I, ns, mc, it);
         }
         apply(3);
         Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
-        pfd::launch_bcg_end<T>(s, I, ns, mc, ko);
+        pfd::launch_bcg_end<T>(s, I, ns, mc, ko, it);
       }
       Prof p(ctx, PF_K_KRYLOV, 0.0, 0.0);
       pfd::launch_kfinish<T>(s, I, ns, mc);
