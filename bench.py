@@ -26,7 +26,8 @@ Other modes (each prints its own JSON line):
   --workload replication    the paper's replication-scale cases (Sec. IV):
                             the 48,000-bus grid (LU, GMRES, BiCGStab) and the
                             0.9K-230K-bus feeders of Table 1 (LU), solve
-                            times beside the paper's CPU times (context)
+                            times beside the paper's CPU times (context);
+                            with --feeder-copies 256 (say) only those feeders
   --calibrate-copy          a plain 256 MiB device copy (for scaling the
                             FETCH_SIZE / WRITE_SIZE counters)
 """
@@ -657,6 +658,24 @@ def bench_replication(args):
                 "solves": k, "newton_iters": r.iters, "inner_iters": r.linear_iters,
                 "lu_fallback": r.lu_fallback, "final_mismatch_oracle": check(B.pf_get_voltage(h))}
 
+    if args.feeder_copies:
+        # only the listed feeders (LU), e.g. for a kernel trace of one size
+        feeders = []
+        for copies in [int(c) for c in args.feeder_copies.split(",")]:
+            tol = pfgen.replication_feeder_tol(copies)
+            lu = B.pf_default_options(solver=B.PF_SOLVER_LU, max_iter=20, tol=tol)
+            fc = pfgen.replication_feeder(copies)
+            h = B.pf_create_from(ctx, fc)
+            row = {"copies": copies, "buses": fc.n_bus, "phase_nodes": fc.n, "tol": tol}
+            row.update(timed(h, lu, lambda V, fc=fc: cim.mismatch_at(fc, V)))
+            feeders.append(row)
+            h.close()
+        print(json.dumps({"mode": "replication", "metric": "solve time of the listed replicated feeders (LU)",
+                          "value": feeders[-1]["solve_ms"]["p50"], "unit": "ms", "n_gpus": 1, "steps": k,
+                          "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "feeders": feeders}), flush=True)
+        return
+
     grid = pfgen.replication_polar()
     t0 = time.perf_counter()
     h = B.pf_create_from(ctx, grid)
@@ -740,6 +759,8 @@ def main():
     ap.add_argument("--workload", choices=["grid10k", "scenarios512", "served", "replication"],
                     default="grid10k")
     ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--feeder-copies", default="",
+                    help="replication: only the feeders of these copy counts (comma-separated), LU")
     ap.add_argument("--oracle-sample", type=int, default=8)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--pool-polar", type=int, default=32)
