@@ -208,6 +208,7 @@ struct Batch {
   int2* d_kwork = nullptr;
   std::vector<std::pair<int64_t, int>> k_lev, k_ulev;
   std::pair<int64_t, int> k_blocks{0, 0};
+  int k_blocks_big = 0;  // the first k_blocks_big groups of k_blocks are above the small size
   int max_kchunks = 0;
   int k_min_nu = 0, k_max_nu = 0;
   bool k_wide = false;    // some instance has an ILU(0) level wider than one work-group pass

@@ -64,7 +64,8 @@ void launch_kfill(hipStream_t, const Inst* const* insts, int nslots, int max_nnz
 template <typename T>
 void launch_ilu_rows(hipStream_t, const Inst* const* insts, const int2* work, int nwork);
 template <typename T>
-void launch_bj_inv(hipStream_t, const Inst* const* insts, const int2* work, int nwork);
+void launch_bj_inv(hipStream_t, const Inst* const* insts, const int2* work, int nbig, int nsmall);
+int bj_small_nodes();  // groups of at most this many nodes are inverted one per wave
 template <typename T>
 void launch_ilu_fwd(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int mode);
 template <typename T>

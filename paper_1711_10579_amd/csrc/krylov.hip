@@ -165,15 +165,50 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
 }
 
 // Block-Jacobi: inverse of the diagonal block A_bb of one node group (order
-// N = 2 x nodes <= 64), stored column-major at bj_off[b], in two launches:
-//   k_bj_inv_mfma: the block, padded with the identity to 64 x 64, inverted
-//     on the matrix cores by block Gauss-Jordan without pivoting (FP64); the
-//     result is kept when it is finite and max |A_bb X - I| <= 1e-6, else
-//     the group is marked (bjbad[b] = 1);
+// N = 2 x nodes <= 64), stored column-major at bj_off[b], in three launches:
+//   k_bj_inv_mfma (groups of more than kBjSmall nodes, a work-group each):
+//     the block, padded with the identity to 64 x 64, inverted on the matrix
+//     cores by block Gauss-Jordan without pivoting (FP64);
+//   k_bj_inv_small (the other groups, a wave each, four to a work-group):
+//     the block padded to 16 x 16, inverted by Gauss-Jordan without
+//     pivoting on one wave (FP64);
+//     in both the result is kept when it is finite and max |A_bb X - I| <=
+//     1e-6, else the group is marked (bjbad[b] = 1);
 //   k_bj_inv: the marked groups only, by Gauss-Jordan with partial pivoting
 //     on [A | I] in LDS (FP64).
-// Both compute A_bb^{-1}; pivoting changes only the rounding.
+// All compute A_bb^{-1}; pivoting and the padding change only the rounding.
+// Grouping the nodes leaves many groups of one or two nodes (a node whose
+// neighbours all belong to earlier groups), which is why the small groups
+// get a wave and not a work-group.
 constexpr double kBjResidualTol = 1e-6;
+constexpr int kBjSmall = 8;  // nodes: groups up to this size take k_bj_inv_small
+
+// the entries of the group's rows that fall inside the group, stored into
+// the row-major LDS array A (columns 0..2s-1).  Eight threads per member row
+// (thread t of 8 s takes row t / 8), each taking every eighth entry of its
+// row, so a row's chain of dependent loads (member -> row range -> column ->
+// local index) is paid once rather than once per entry.  Distinct entries of
+// a row have distinct columns, so no two threads store the same element.
+template <typename T, int LD, typename IR>
+__device__ inline void bj_scatter_rows(const IR& I, int r0, int s, double (*A)[LD], int t) {
+  const int a = t >> 3, j = t & 7;
+  if (a >= s) return;
+  const auto rows = gp(I.bj_rows), loc = gp(I.bj_loc), kcol = gp(I.kcol), kptr = gp(I.krow_ptr);
+  const auto jv = gp((const T*)I.jval);
+  const int r = rows[r0 + a];
+  const int q1 = kptr[r + 1];
+  for (int q = kptr[r] + j; q < q1; q += 8) {
+    const int c = kcol[q];
+    const int l = loc[c];
+    if (l < s && rows[r0 + l] == c) {
+      const auto v = jv + 4 * (int64_t)q;
+      A[2 * a][2 * l] = (double)v[0];
+      A[2 * a][2 * l + 1] = (double)v[1];
+      A[2 * a + 1][2 * l] = (double)v[2];
+      A[2 * a + 1][2 * l + 1] = (double)v[3];
+    }
+  }
+}
 
 // the group's block gathered into a row-major 64 x (64 + pad) LDS array
 // (identity outside N x N)
@@ -186,20 +221,7 @@ __device__ inline void bj_gather(const IR& I, int r0, int s, double (*A)[LD]) {
     A[i][c] = (i == c && i >= N) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int a = tid; a < s; a += blockDim.x) {
-    const int r = gp(I.bj_rows)[r0 + a];
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const int c = gp(I.kcol)[q];
-      const int l = gp(I.bj_loc)[c];
-      if (l < s && gp(I.bj_rows)[r0 + l] == c) {
-        const T* v = (const T*)I.jval + 4 * (int64_t)q;
-        A[2 * a][2 * l] = (double)v[0];
-        A[2 * a][2 * l + 1] = (double)v[1];
-        A[2 * a + 1][2 * l] = (double)v[2];
-        A[2 * a + 1][2 * l + 1] = (double)v[3];
-      }
-    }
-  }
+  bj_scatter_rows<T, LD>(I, r0, s, A, threadIdx.x);
   __syncthreads();
 }
 
@@ -262,6 +284,57 @@ __global__ __launch_bounds__(256) void k_bj_inv_mfma(const Inst* const* insts, c
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_bj_inv_small(const Inst* const* insts, const int2* __restrict__ work,
+                                                      int nwork) {
+  __shared__ double A[4][16][17];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15;
+  const int k = blockIdx.x * 4 + wv;
+  // every wave reaches both barriers; a wave without a group inverts the
+  // identity and stores nothing
+  int2 wk = make_int2(0, -1);
+  if (k < nwork) wk = work[k];
+  const auto ip = wk.y >= 0 ? gp(gp(insts)[wk.x]) : nullptr;
+  const bool ok = ip && gp(ip->red)->active;
+  const int b = wk.y;
+  const int r0 = ok ? gp(ip->bj_ptr)[b] : 0;
+  const int s = ok ? gp(ip->bj_ptr)[b + 1] - r0 : 0;
+  const int N = 2 * s;
+  double(*Aw)[17] = A[wv];
+#pragma unroll
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, cc = e & 15;
+    Aw[i][cc] = (i == cc && i >= N) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (ok) bj_scatter_rows<T, 17>(*ip, r0, s, Aw, lane);
+  __syncthreads();
+  V4<double> z;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) z[e] = Aw[Mfma<double>::row(lane, e)][c];
+  blk_inverse<double>(z, lane);
+  // A X - I from the N-form of A^T read straight from the staged block
+  const V4<double> zero = {0.0, 0.0, 0.0, 0.0};
+  const V4<double> ax = mm16<double>(blk_get_t<double>(&Aw[0][0], lane), z, zero);
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = Mfma<double>::row(lane, e);
+    const double r = ax[e] - (row == c ? 1.0 : 0.0);
+    bad = bad || !(fabs(r) <= kBjResidualTol) || !isfinite(z[e]);
+  }
+  bad = __builtin_amdgcn_ballot_w64(bad) != 0;
+  if (!ok) return;
+  if (lane == 0) ip->bjbad[b] = bad ? 1 : 0;
+  if (bad) return;
+  T* out = (T*)ip->bjinv + gp(ip->bj_off)[b];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = Mfma<double>::row(lane, e);
+    if (row < N && c < N) out[c * N + row] = (T)z[e];
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ double A[64][129];
   __shared__ double colk[64];
@@ -283,21 +356,7 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  // gather the block: member a (local), its row's entries in the same group
-  for (int a = tid; a < s; a += 256) {
-    const int r = gp(I.bj_rows)[r0 + a];
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const int c = gp(I.kcol)[q];
-      const int l = gp(I.bj_loc)[c];
-      if (l < s && gp(I.bj_rows)[r0 + l] == c) {
-        const T* v = (const T*)I.jval + 4 * (int64_t)q;
-        A[2 * a][2 * l] = (double)v[0];
-        A[2 * a][2 * l + 1] = (double)v[1];
-        A[2 * a + 1][2 * l] = (double)v[2];
-        A[2 * a + 1][2 * l + 1] = (double)v[3];
-      }
-    }
-  }
+  bj_scatter_rows<T, 129>(I, r0, s, A, tid);  // the block beside the identity
   __syncthreads();
   for (int k = 0; k < N; ++k) {
     if (tid < 64) {  // pivot search by the first wave
@@ -1462,11 +1521,12 @@ void launch_ilu_rows(hipStream_t st, const Inst* const* insts, const int2* work,
   if (nwork > 0) k_ilu_rows<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork);
 }
 template <typename T>
-void launch_bj_inv(hipStream_t st, const Inst* const* insts, const int2* work, int nwork) {
-  if (nwork <= 0) return;
-  k_bj_inv_mfma<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
-  k_bj_inv<T><<<dim3((unsigned)nwork), 256, 0, st>>>(insts, work);
+void launch_bj_inv(hipStream_t st, const Inst* const* insts, const int2* work, int nbig, int nsmall) {
+  if (nbig > 0) k_bj_inv_mfma<T><<<dim3((unsigned)nbig), 256, 0, st>>>(insts, work);
+  if (nsmall > 0) k_bj_inv_small<T><<<dim3((unsigned)((nsmall + 3) / 4)), 256, 0, st>>>(insts, work + nbig, nsmall);
+  if (nbig + nsmall > 0) k_bj_inv<T><<<dim3((unsigned)(nbig + nsmall)), 256, 0, st>>>(insts, work);
 }
+int bj_small_nodes() { return kBjSmall; }
 template <typename T>
 void launch_ilu_fwd(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
   if (nwork > 0) k_ilu_fwd<T><<<item_grid(nwork), 256, 0, st>>>(insts, work, nwork, mode);
@@ -1554,7 +1614,7 @@ int krylov_max_restart() { return KMAX; }
 
 #define PF_KINST(T)                                                                    \
   template void launch_ilu_rows<T>(hipStream_t, const Inst* const*, const int2*, int);      \
-  template void launch_bj_inv<T>(hipStream_t, const Inst* const*, const int2*, int);        \
+  template void launch_bj_inv<T>(hipStream_t, const Inst* const*, const int2*, int, int);   \
   template void launch_ilu_fwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_ilu_bwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int); \

@@ -280,9 +280,18 @@ bool Batch::build_krylov() {
   levels(false, max_l, &k_lev);
   levels(true, max_u, &k_ulev);
   {
+    // the groups above the small size first (a work-group each for their
+    // inverse), then the small ones (a wave each)
     const int64_t off = (int64_t)work.size();
-    for (int s = 0; s < nslots; ++s)
-      for (int b = 0; b < cases[s]->ka->nblocks(); ++b) work.push_back(make_int2(s, b));
+    const int small = pfd::bj_small_nodes();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int s = 0; s < nslots; ++s) {
+        const pfh::KAnalysis& ka = *cases[s]->ka;
+        for (int b = 0; b < ka.nblocks(); ++b)
+          if ((ka.bj_ptr[b + 1] - ka.bj_ptr[b] > small) == (pass == 0)) work.push_back(make_int2(s, b));
+      }
+      if (pass == 0) k_blocks_big = (int)((int64_t)work.size() - off);
+    }
     k_blocks = {off, (int)((int64_t)work.size() - off)};
   }
   const size_t bw = (sizeof(int2) * std::max<size_t>(work.size(), 1) + 255) & ~(size_t)255;
@@ -330,7 +339,7 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       if (b->k_narrow) pfd::launch_ilu_factor_wg<T>(s, I, ns);
       for (const auto& l : b->k_lev) pfd::launch_ilu_rows<T>(s, I, kw + l.first, l.second);
     } else {
-      pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second);
+      pfd::launch_bj_inv<T>(s, I, kw + b->k_blocks.first, b->k_blocks_big, b->k_blocks.second - b->k_blocks_big);
     }
   }
   const bool bcg = opt->solver == PF_SOLVER_BICGSTAB;

@@ -76,7 +76,8 @@ extern "C" pf_status pf_debug_precond_check(pf_case* c, int32_t precond, double*
   else if (ilu)
     for (const auto& l : b.k_lev) pfd::launch_ilu_rows<double>(s, b.d_insts, b.d_kwork + l.first, l.second);
   else
-    pfd::launch_bj_inv<double>(s, b.d_insts, b.d_kwork + b.k_blocks.first, b.k_blocks.second);
+    pfd::launch_bj_inv<double>(s, b.d_insts, b.d_kwork + b.k_blocks.first, b.k_blocks_big,
+                                b.k_blocks.second - b.k_blocks_big);
   st = launch_status("pf_debug_precond_check");
   if (st != PF_OK) return st;
   const pfh::KAnalysis& ka = *c->ka;
