@@ -75,7 +75,7 @@ void launch_ilu_factor_wg(hipStream_t, const Inst* const* insts, int nslots);
 template <typename T>
 void launch_ilu_apply_wg(hipStream_t, const Inst* const* insts, int nslots, int mode, int min_nu, int max_nu);
 template <typename T>
-void launch_bj_apply(hipStream_t, const Inst* const* insts, const int2* work, int nwork, int mode);
+void launch_bj_apply(hipStream_t, const Inst* const* insts, const int2* work, int nbig, int nwork, int mode);
 template <typename T>
 void launch_karnoldi(hipStream_t, const Inst* const* insts, int nslots, int max_chunks, KOpts o);
 template <typename T>

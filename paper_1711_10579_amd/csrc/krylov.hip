@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_bj_inv(const Inst* const* insts, const 
   const auto& I = *gp(gp(insts)[wk.x]);
   if (!gp(I.red)->active) return;
   const int b = wk.y;
-  if (!I.bjbad[b]) return;  // inverted without pivoting
+  if (b < 0 || !I.bjbad[b]) return;  // padding, or inverted without pivoting
   const int r0 = gp(I.bj_ptr)[b];
   const int s = gp(I.bj_ptr)[b + 1] - r0;
   const int N = 2 * s;
@@ -694,37 +694,64 @@ __global__ __launch_bounds__(1024) void k_ilu_apply_wg(const Inst* const* insts,
   }
 }
 
-// Block-Jacobi application: one wave per node group, z_b = A_bb^{-1} (s w_b)
-// (mode 0 also stores s w_b as basis vector v_j).
+// Block-Jacobi application z_b = A_bb^{-1} (s w_b) (mode 0 also stores s w_b
+// as basis vector v_j).  Row t of a group of order N is the sum over the
+// columns in order.  The inverse is stored column-major, so a column is one
+// coalesced load across the group's lanes; all NC columns are issued at
+// once, right behind the input's load, so that they arrive during its round
+// trip.  Columns past N repeat column N - 1 and rows past N repeat row N - 1,
+// so every load stays inside the group's inverse; those columns meet a zero
+// input and those rows store nothing.  vg: the group's NC inputs in LDS.
+template <typename T, int NC, typename IR>
+__device__ inline void bj_apply_rows(const IR& I, int b, int r0, int N, int t, bool valid, int mode, double sc,
+                                     double* vg) {
+  const int tr = t < N ? t : N - 1;
+  const int r = gp(I.bj_rows)[r0 + (tr >> 1)];
+  T x = gp((const T*)I.kw)[2 * r + (tr & 1)];
+  const auto inv = gp((const T*)I.bjinv) + gp(I.bj_off)[b] + tr;
+  T col[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) col[c] = inv[(int64_t)(c < N ? c : N - 1) * N];
+  const bool mine = valid && t < N;
+  if (mode == 0) {
+    x = (T)((double)x * sc);
+    if (mine) gp((T*)I.kv)[(int64_t)gp(I.ks)->j * 2 * I.nu + 2 * r + (t & 1)] = x;
+  }
+  vg[t] = mine ? (double)x : 0.0;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s += (double)col[c] * vg[c];
+  if (mine) gp((T*)I.kz)[2 * r + (t & 1)] = (T)s;
+}
+
+// One wave per work-group.  Work-groups below nbig take one group of more
+// than kBjSmall nodes each (64 lanes); the others take four consecutive
+// entries of the small groups' list, 16 lanes per group (N <= 16).  The host
+// lays that list out in fours of one instance each, padded with entries of
+// group -1, so the instance is the same across the wave.
 template <typename T>
-__global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const int2* __restrict__ work, int mode) {
+__global__ __launch_bounds__(64) void k_bj_apply(const Inst* const* insts, const int2* __restrict__ work, int nbig,
+                                                 int mode) {
   __shared__ double v[64];
   const auto wp = (const PF_AS1 int*)work;
-  const int wx = wp[2 * blockIdx.x], b = wp[2 * blockIdx.x + 1];
-  const auto& I = *gp(gp(insts)[wx]);
+  const bool big = (int)blockIdx.x < nbig;
+  const int k0 = big ? (int)blockIdx.x : nbig + 4 * ((int)blockIdx.x - nbig);
+  const auto& I = *gp(gp(insts)[wp[2 * k0]]);
   if (!kstate_is(I, apply_state(mode))) return;
-  const int r0 = gp(I.bj_ptr)[b];
-  const int N = 2 * (gp(I.bj_ptr)[b + 1] - r0);
-  const int t = threadIdx.x;
-  const auto w = gp((const T*)I.kw);
-  const auto rows = gp(I.bj_rows);
-  if (t < N) {
-    const int r = rows[r0 + (t >> 1)];
-    T x = w[2 * r + (t & 1)];
-    if (mode == 0) {
-      const auto ks = gp(I.ks);
-      x = (T)((double)x * ks->scale);
-      gp((T*)I.kv)[(int64_t)ks->j * 2 * I.nu + 2 * r + (t & 1)] = x;
-    }
-    v[t] = (double)x;
-  }
-  __syncthreads();
-  if (t < N) {
-    const auto inv = gp((const T*)I.bjinv) + gp(I.bj_off)[b] + t;
-    double s = 0.0;
-    for (int c = 0; c < N; ++c) s += (double)inv[(int64_t)c * N] * v[c];
-    const int r = rows[r0 + (t >> 1)];
-    gp((T*)I.kz)[2 * r + (t & 1)] = (T)s;
+  const double sc = mode == 0 ? gp(I.ks)->scale : 1.0;
+  if (big) {
+    const int b = wp[2 * k0 + 1];
+    const int r0 = gp(I.bj_ptr)[b];
+    const int N = 2 * (gp(I.bj_ptr)[b + 1] - r0);
+    bj_apply_rows<T, 64>(I, b, r0, N, (int)threadIdx.x, true, mode, sc, v);
+  } else {
+    const int g = threadIdx.x >> 4;
+    const int bw = wp[2 * (k0 + g) + 1];
+    const int b = bw < 0 ? 0 : bw;
+    const int r0 = gp(I.bj_ptr)[b];
+    const int N = 2 * (gp(I.bj_ptr)[b + 1] - r0);
+    bj_apply_rows<T, 16>(I, b, r0, N, (int)threadIdx.x & 15, bw >= 0, mode, sc, v + 16 * g);
   }
 }
 
@@ -1552,8 +1579,8 @@ void launch_ilu_apply_wg(hipStream_t st, const Inst* const* insts, int nslots, i
   if (2 * max_nu > big) k_ilu_apply_wg<T, 0><<<g, 1024, 0, st>>>(insts, mode, big);
 }
 template <typename T>
-void launch_bj_apply(hipStream_t st, const Inst* const* insts, const int2* work, int nwork, int mode) {
-  if (nwork > 0) k_bj_apply<T><<<dim3((unsigned)nwork), 64, 0, st>>>(insts, work, mode);
+void launch_bj_apply(hipStream_t st, const Inst* const* insts, const int2* work, int nbig, int nwork, int mode) {
+  if (nwork > 0) k_bj_apply<T><<<dim3((unsigned)(nbig + (nwork - nbig) / 4)), 64, 0, st>>>(insts, work, nbig, mode);
 }
 template <typename T>
 void launch_karnoldi(hipStream_t st, const Inst* const* insts, int nslots, int max_chunks, KOpts o) {
@@ -1617,7 +1644,7 @@ int krylov_max_restart() { return KMAX; }
   template void launch_bj_inv<T>(hipStream_t, const Inst* const*, const int2*, int, int);   \
   template void launch_ilu_fwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
   template void launch_ilu_bwd<T>(hipStream_t, const Inst* const*, const int2*, int, int);  \
-  template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int); \
+  template void launch_bj_apply<T>(hipStream_t, const Inst* const*, const int2*, int, int, int);\
   template void launch_ilu_factor_wg<T>(hipStream_t, const Inst* const*, int);              \
   template void launch_ilu_apply_wg<T>(hipStream_t, const Inst* const*, int, int, int, int);\
   template void launch_karnoldi<T>(hipStream_t, const Inst* const*, int, int, KOpts);       \

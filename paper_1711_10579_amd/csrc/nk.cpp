@@ -280,8 +280,9 @@ bool Batch::build_krylov() {
   levels(false, max_l, &k_lev);
   levels(true, max_u, &k_ulev);
   {
-    // the groups above the small size first (a work-group each for their
-    // inverse), then the small ones (a wave each)
+    // the groups above the small size first (a work-group each), then the
+    // small ones (a wave each for their inverse, four to a wave when
+    // applied), in fours of one instance, padded with entries of group -1
     const int64_t off = (int64_t)work.size();
     const int small = pfd::bj_small_nodes();
     for (int pass = 0; pass < 2; ++pass) {
@@ -289,6 +290,8 @@ bool Batch::build_krylov() {
         const pfh::KAnalysis& ka = *cases[s]->ka;
         for (int b = 0; b < ka.nblocks(); ++b)
           if ((ka.bj_ptr[b + 1] - ka.bj_ptr[b] > small) == (pass == 0)) work.push_back(make_int2(s, b));
+        if (pass == 1)
+          while (((int64_t)work.size() - off - k_blocks_big) % 4 != 0) work.push_back(make_int2(s, -1));
       }
       if (pass == 0) k_blocks_big = (int)((int64_t)work.size() - off);
     }
@@ -359,7 +362,7 @@ pf_status nk_step_t(Batch* b, const pf_options* opt) {
       for (const auto& l : b->k_lev) pfd::launch_ilu_fwd<T>(s, I, kw + l.first, l.second, mode);
       for (const auto& l : b->k_ulev) pfd::launch_ilu_bwd<T>(s, I, kw + l.first, l.second, mode);
     } else {
-      pfd::launch_bj_apply<T>(s, I, kw + b->k_blocks.first, b->k_blocks.second, mode);
+      pfd::launch_bj_apply<T>(s, I, kw + b->k_blocks.first, b->k_blocks_big, b->k_blocks.second, mode);
     }
   };
   // Iterations (BiCGStab) or Arnoldi steps (GMRES) queued per read of the
