@@ -100,6 +100,48 @@ __device__ inline void block_sums(int count, F f, double (*red)[KCH / 64], PF_AS
   }
 }
 
+// Sums over the chunks of N entries of the partial sums (entry es[k] of
+// pass ps[k]; |value| where bit k of AbsMask is set), each in a fixed order
+// (the same value wherever it is formed).  Called by all 64 lanes of one
+// wave: lane l adds chunks l, l + 64, l + 128, ... in turn, then the
+// butterfly of wave_sum.  The loads for four such chunks of every entry are
+// issued together; past the last chunk a load repeats chunk 0 and adds
+// nothing.
+template <int N, int AbsMask = 0, typename IR>
+__device__ inline void chunk_sums(const IR& I, const int (&ps)[N], const int (&es)[N], double (&out)[N]) {
+  const int lane = threadIdx.x & 63, nc = I.kchunks;
+  double s[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) s[k] = 0.0;
+  for (int c0 = 0; c0 < nc; c0 += 256) {
+    double v[4][N];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 64 * u + lane;
+      const int cc = c < nc ? c : 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[u][k] = kpart(I, ps[k], cc)[es[k]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = c0 + 64 * u + lane < nc;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double x = (AbsMask >> k) & 1 ? fabs(v[u][k]) : v[u][k];
+        s[k] += in ? x : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k] = wave_sum(s[k]);
+}
+template <typename IR>
+__device__ inline double chunk_sum(const IR& I, int pass, int e) {
+  double o[1];
+  chunk_sums<1>(I, {pass}, {e}, o);
+  return o[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -877,9 +919,7 @@ __global__ __launch_bounds__(64) void k_karnoldi_end(const Inst* const* insts, K
   KState& ks = *I.ks;
   const int lane = threadIdx.x;
   const int j = ks.j, m = I.km;
-  double part = 0.0;
-  for (int c = lane; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
-  const double h = sqrt(wave_sum(part));
+  const double h = sqrt(chunk_sum(I, 2, 0));
   double* H = kh_H(I);
   double* cs = kh_cs(I);
   double* sn = kh_sn(I);
@@ -980,9 +1020,7 @@ __global__ __launch_bounds__(64) void k_kbegin_fin(const Inst* const* insts, KOp
     }
     return;
   }
-  double part = 0.0;
-  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
-  const double bn = sqrt(wave_sum(part));
+  const double bn = sqrt(chunk_sum(I, 2, 0));
   if (threadIdx.x != 0) return;
   ks.bnorm = bn;
   ks.eta = fmax(fmin(o.eta_max, gp(I.red)->last_norm), o.eta_floor);
@@ -1096,9 +1134,7 @@ __global__ __launch_bounds__(64) void k_krestart_fin(const Inst* const* insts) {
   const auto& I = *gp(gp(insts)[blockIdx.x]);
   if (!kstate_is(I, KS_RESTART)) return;
   KState& ks = *I.ks;
-  double part = 0.0;
-  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
-  const double beta = sqrt(wave_sum(part));
+  const double beta = sqrt(chunk_sum(I, 2, 0));
   if (threadIdx.x != 0) return;
   ks.rel = beta / ks.bnorm;
   if (ks.rel <= ks.eta || !(beta > 0.0)) {
@@ -1155,17 +1191,6 @@ __device__ inline PF_AS1 T* kvec(const IR& I, int i) {
   return gp((T*)I.kv) + (int64_t)i * 2 * I.nu;
 }
 
-// Sum over the chunks of entry e of a pass's partial sums, in chunk order
-// (the same value wherever it is formed).
-// Called by all 64 lanes of one wave: lane-strided partial sums, then the
-// butterfly of wave_sum, so every lane (and every work-group) gets the same
-// value in a fixed order.
-template <typename IR>
-__device__ inline double chunk_sum(const IR& I, int pass, int e) {
-  double s = 0.0;
-  for (int c = threadIdx.x & 63; c < I.kchunks; c += 64) s += kpart(I, pass, c)[e];
-  return wave_sum(s);
-}
 
 // The solve ends as it stands.
 template <typename IR>
@@ -1190,9 +1215,7 @@ __global__ __launch_bounds__(64) void k_bcg_begin_fin(const Inst* const* insts, 
     }
     return;
   }
-  double part = 0.0;
-  for (int c = threadIdx.x; c < I.kchunks; c += 64) part += kpart(I, 2, c)[0];
-  const double b2 = wave_sum(part);
+  const double b2 = chunk_sum(I, 2, 0);
   if (threadIdx.x != 0) return;
   const double bn = sqrt(b2);
   ks.bnorm = bn;
@@ -1325,13 +1348,9 @@ __global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts, KOpts o
   if ((!kstate_is(I, KS_BP) && !kstate_is(I, KS_BS)) || (int)blockIdx.x >= I.kchunks) return;
   auto& ks = *gp(I.ks);
   if (threadIdx.x < 64) {
-    double sv = 0.0, ss = 0.0;
-    for (int c = threadIdx.x; c < I.kchunks; c += 64) {
-      sv += fabs(kpart(I, 0, c)[0]);
-      ss += kpart(I, 1, c)[0];
-    }
-    sv = wave_sum(sv);
-    ss = wave_sum(ss);
+    double sum[2];
+    chunk_sums<2, 1>(I, {0, 1}, {0, 0}, sum);
+    const double sv = sum[0], ss = sum[1];
     if (threadIdx.x == 0) {
       const double srel = sqrt(ss) / ks.bnorm;
       const int dec = (!(sv > 0.0) || !isfinite(ks.alpha)) ? 2 : srel <= ks.eta ? 1 : 0;
@@ -1405,8 +1424,9 @@ __global__ __launch_bounds__(KCH) void k_bcg_x(const Inst* const* insts) {
     return;
   }
   if (threadIdx.x < 64) {
-    const double tt = chunk_sum(I, 2, 1);
-    const double ts = chunk_sum(I, 2, 0);
+    double sum[2];
+    chunk_sums<2>(I, {2, 2}, {1, 0}, sum);
+    const double tt = sum[0], ts = sum[1];
     if (threadIdx.x == 0) {
       skip_s = !(tt > 0.0);
       omega_s = skip_s ? 0.0 : ts / tt;
@@ -1454,9 +1474,9 @@ __global__ __launch_bounds__(KCH) void k_bcg_next(const Inst* const* insts, KOpt
   if ((!half && !kstate_is(I, KS_BS) && !kstate_is(I, KS_BP)) || (int)blockIdx.x >= I.kchunks) return;
   auto& ks = *gp(I.ks);
   if (threadIdx.x < 64) {
-    const double tt = chunk_sum(I, 2, 1);
-    const double rho = chunk_sum(I, 1, 0);
-    const double rr = chunk_sum(I, 1, 1);
+    double sum[3];
+    chunk_sums<3>(I, {2, 1, 1}, {1, 0, 1}, sum);
+    const double tt = sum[0], rho = sum[1], rr = sum[2];
     if (threadIdx.x == 0) {
       const double rel = sqrt(rr) / ks.bnorm;
       const int max_it = max(1, (1 + o.max_restarts) * o.m / 2);
