@@ -38,7 +38,14 @@ __device__ inline double wave_max(double local) {
   return local;
 }
 
-__device__ inline bool inactive(const Inst& I) { return I.red->active == 0; }
+template <typename IR>
+__device__ inline bool inactive(const IR& I) { return gp(I.red)->active == 0; }
+
+// work item i of a list, through a global pointer
+__device__ inline int2 ld_item(const int2* work, int i) {
+  const auto wp = (const PF_AS1 int*)work;
+  return make_int2(wp[2 * i], wp[2 * i + 1]);
+}
 
 // max over a work-group of 256 threads (every thread calls it), stored by
 // thread 0 as the work-group's partial maximum (the instance's convergence
@@ -734,21 +741,24 @@ __device__ inline void sub_updates(Blk<T>& acc, const T* lu_, const int* il_, co
 // the fixed-order tree.  Every L(i,k) and y_k lies in an earlier level.
 // Rows of the dense block also copy the result into its right-hand side
 // column.
-template <typename T, int G>
-__device__ inline void fwd_row(const Inst& I, const T* lu, T* x, int i, int lane) {
+template <typename T, int G, typename IR>
+__device__ inline void fwd_row(const IR& I, const T* lu_, T* x_, int i, int lane) {
+  const auto lu = gp(lu_);
+  const auto x = gp(x_);
+  const auto lrow_ptr = gp(I.lrow_ptr), lrow_blk = gp(I.lrow_blk), lrow_col = gp(I.lrow_col);
   Blk<T> acc = {T(0), T(0), T(0), T(0)};  // (a, c) carry the 2-vector
   if (lane == 0) {
     acc.a = x[2 * i];
     acc.c = x[2 * i + 1];
   }
-  const int q1 = I.lrow_ptr[i + 1];
-  for (int q = I.lrow_ptr[i] + lane; q < q1; q += 4 * G) {
+  const int q1 = lrow_ptr[i + 1];
+  for (int q = lrow_ptr[i] + lane; q < q1; q += 4 * G) {
     int bk[4], kk[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (q + u * G < q1) {
-        bk[u] = I.lrow_blk[q + u * G];
-        kk[u] = I.lrow_col[q + u * G];
+        bk[u] = lrow_blk[q + u * G];
+        kk[u] = lrow_col[q + u * G];
       }
     Blk<T> L[4];
     T x0[4], x1[4];
@@ -771,15 +781,15 @@ __device__ inline void fwd_row(const Inst& I, const T* lu, T* x, int i, int lane
     x[2 * i] = acc.a;
     x[2 * i + 1] = acc.c;
     if (i >= I.ns) {
-      T* rhs = (T*)I.tail + (int64_t)I.M * I.ldt;
+      const auto rhs = gp((T*)I.tail) + (int64_t)I.M * I.ldt;
       rhs[2 * (i - I.ns)] = acc.a;
       rhs[2 * (i - I.ns) + 1] = acc.c;
     }
   }
 }
 
-template <typename T, int G>
-__device__ inline Blk<T> gather_target(const Inst& I, const T* lu, int64_t dest, int64_t tg, int lane) {
+template <typename T, int G, typename IR>
+__device__ inline Blk<T> gather_target(const IR& I, const T* lu, int64_t dest, int64_t tg, int lane) {
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
   if (lane == 0) acc = ld_blk<T>(gp(lu), dest);
   sub_updates<T, G>(acc, lu, I.upd_l, I.upd_u, gp(I.uptr)[tg] + lane, gp(I.uptr)[tg + 1]);
@@ -798,13 +808,13 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
                                                           int nwork) {
   const int item = blockIdx.x * 4 + (int)(threadIdx.x / 64);
   if (item >= nwork) return;
-  const int2 w = work[item];
-  const Inst& I = *insts[w.x];
+  const int2 w = ld_item(work, item);
+  const auto& I = *gp(gp(insts)[w.x]);
   if (inactive(I)) return;
   T* lu = (T*)I.lu;
   const int j = w.y;
-  const int c0 = I.colptr[j];
-  const int len = I.colptr[j + 1] - c0;
+  const int c0 = gp(I.colptr)[j];
+  const int len = gp(I.colptr)[j + 1] - c0;
   const int64_t tb = (int64_t)j + 2LL * c0;
   const int wl = threadIdx.x % 64;
   const int lane = wl % G, grp = wl / G;
@@ -818,12 +828,12 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
     int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
     if (lane == 0) {
-      st_blk(lu, dest, acc);
+      st_blk(gp(lu), dest, acc);
       if (t == 0) {
         T det = acc.a * acc.d - acc.b * acc.c;
         bool bad = !(det != T(0)) || !isfinite((double)det);
         if (bad) {
-          I.red->singular = 1;
+          gp(I.red)->singular = 1;
           det = T(1);
         }
         T r = T(1) / det;
@@ -831,7 +841,7 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
         d1 = -acc.b * r;
         d2 = -acc.c * r;
         d3 = acc.a * r;
-        T* q = (T*)I.dinv + 4 * (int64_t)j;
+        const auto q = gp((T*)I.dinv) + 4 * (int64_t)j;
         q[0] = d0;
         q[1] = d1;
         q[2] = d2;
@@ -844,20 +854,20 @@ __global__ __launch_bounds__(256) void k_factor_cols_wave(const Inst* const* ins
   for (int t = grp; t < len; t += ngrp) {
     int64_t dest = (int64_t)I.ns + c0 + t;
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + 1 + len + t, lane);
-    if (lane == 0) st_blk(lu, dest, blk_mul(acc, di));
+    if (lane == 0) st_blk(gp(lu), dest, blk_mul(acc, di));
   }
 }
 
 template <typename T, int G, int NT>
 __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, const int2* __restrict__ work) {
   __shared__ T sdinv[4];
-  const int2 w = work[blockIdx.x];
-  const Inst& I = *insts[w.x];
+  const int2 w = ld_item(work, blockIdx.x);
+  const auto& I = *gp(gp(insts)[w.x]);
   if (inactive(I)) return;
   T* lu = (T*)I.lu;
   const int j = w.y;
-  const int c0 = I.colptr[j];
-  const int len = I.colptr[j + 1] - c0;
+  const int c0 = gp(I.colptr)[j];
+  const int len = gp(I.colptr)[j + 1] - c0;
   const int64_t tb = (int64_t)j + 2LL * c0;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
   // D_j and U(j, .), and the forward row of node j (t = len + 1)
@@ -869,12 +879,12 @@ __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, co
     int64_t dest = t == 0 ? (int64_t)j : (int64_t)I.ns + I.nnzl + c0 + (t - 1);
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + t, lane);
     if (lane == 0) {
-      st_blk(lu, dest, acc);
+      st_blk(gp(lu), dest, acc);
       if (t == 0) {
         T det = acc.a * acc.d - acc.b * acc.c;
         bool bad = !(det != T(0)) || !isfinite((double)det);
         if (bad) {
-          I.red->singular = 1;
+          gp(I.red)->singular = 1;
           det = T(1);
         }
         T r = T(1) / det;
@@ -882,7 +892,7 @@ __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, co
         sdinv[1] = -acc.b * r;
         sdinv[2] = -acc.c * r;
         sdinv[3] = acc.a * r;
-        T* q = (T*)I.dinv + 4 * (int64_t)j;
+        const auto q = gp((T*)I.dinv) + 4 * (int64_t)j;
         q[0] = sdinv[0];
         q[1] = sdinv[1];
         q[2] = sdinv[2];
@@ -895,7 +905,7 @@ __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, co
   for (int t = grp; t < len; t += ngrp) {
     int64_t dest = (int64_t)I.ns + c0 + t;
     Blk<T> acc = gather_target<T, G>(I, lu, dest, tb + 1 + len + t, lane);
-    if (lane == 0) st_blk(lu, dest, blk_mul(acc, di));
+    if (lane == 0) st_blk(gp(lu), dest, blk_mul(acc, di));
   }
 }
 
@@ -904,8 +914,8 @@ __global__ __launch_bounds__(NT) void k_factor_cols(const Inst* const* insts, co
 // chunk of 256).
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_tail_schur(const Inst* const* insts, const int2* __restrict__ work) {
-  const int2 w = work[blockIdx.x];
-  const Inst& I = *insts[w.x];
+  const int2 w = ld_item(work, blockIdx.x);
+  const auto& I = *gp(gp(insts)[w.x]);
   // the activity flag is tested only before the store, so that the loads
   // need not wait for it
   const bool active = !inactive(I);
@@ -942,8 +952,8 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, cons
                                                   int nwork) {
   const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G, lane = threadIdx.x % G;
   if (gid >= nwork) return;  // whole groups leave together
-  const int2 w = work[gid];
-  const Inst& I = *insts[w.x];
+  const int2 w = ld_item(work, gid);
+  const auto& I = *gp(gp(insts)[w.x]);
   if (inactive(I)) return;
   fwd_row<T, G>(I, (const T*)I.lu, (T*)I.x, w.y, lane);
 }

@@ -850,12 +850,23 @@ __global__ __launch_bounds__(KCH) void k_korth(const Inst* const* insts, int pas
   if (!kstate_is(I, KS_ITER) || (int)blockIdx.x >= I.kchunks) return;
   const int j = gp(I.ks)->j;
   // h_i = sum over chunks of the pass's partial dots: 8 interleaved groups
-  // of chunks, then the groups in order
-  const int ni = j + 1;
+  // of chunks (group g adds chunks g, g + 8, ... in turn, the loads of eight
+  // of them issued together; past the last chunk a load repeats chunk 0 and
+  // adds nothing), then the groups in order
+  const int ni = j + 1, nc = I.kchunks;
   for (int idx = threadIdx.x; idx < 8 * ni; idx += KCH) {
     const int i = idx % ni, grp = idx / ni;
     double s = 0.0;
-    for (int c = grp; c < I.kchunks; c += 8) s += kpart(I, pass, c)[i];
+    for (int c0 = grp; c0 < nc; c0 += 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 8 * u;
+        v[u] = kpart(I, pass, c < nc ? c : 0)[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += c0 + 8 * u < nc ? v[u] : 0.0;
+    }
     hg[grp][i] = s;
   }
   __syncthreads();
