@@ -21,6 +21,12 @@ __device__ inline const PF_AS1 T* gp(const T* p) {
   return (const PF_AS1 T*)p;
 }
 
+// work item i of a list of (instance, index) pairs, through a global pointer
+__device__ inline int2 ld_item(const int2* work, int i) {
+  const auto wp = (const PF_AS1 int*)work;
+  return make_int2(wp[2 * i], wp[2 * i + 1]);
+}
+
 // Bound of an in-launch wait in ticks of the device's constant real-time
 // counter (100 MHz): about one second.
 constexpr unsigned long long kWaitTicks = 100000000ull;

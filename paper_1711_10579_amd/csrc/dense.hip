@@ -87,8 +87,8 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   T* stage = smem;                    // two sets of four staged blocks
   T* xs = smem + 8 * kStage;          // the work-group's rows of A_ik, column-major [NB][kQuarterLd]
   T* ls = xs + NB * kQuarterLd;       // the same rows of L_ik
-  const Inst& I = *insts[w.x];
-  if (I.red->active == 0) return;
+  const auto& I = *gp(gp(insts)[w.x]);
+  if (gp(I.red)->active == 0) return;
   // the launch is uniform per work-group: keep these in scalar registers
   const int g = __builtin_amdgcn_readfirstlane(w.y);
   if (g == 0 && h != 0) return;
@@ -114,7 +114,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
   const bool wait = g > 0 && k0 > 0;
   unsigned long long want = 0, f1 = 0, f2 = 0;
   if (wait) {
-    want = panel_flag(I.red->epoch, k0);
+    want = panel_flag(gp(I.red)->epoch, k0);
     f1 = flag_ld(&I.pflags[r0 / NB]);
     f2 = flag_ld(&I.pflags[k0 / NB]);
   }
@@ -225,7 +225,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
       for (int e = 0; e < 4; ++e) bad = bad || !isfinite((double)d[ib][e]);
-    if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) I.red->singular = 1;
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) gp(I.red)->singular = 1;
     T* ui = (T*)I.dinvu + (int64_t)(k0 / NB) * NB * NB;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -244,7 +244,7 @@ __device__ __forceinline__ void panel_step(const Inst* const* insts, const int2 
       if (__builtin_amdgcn_readfirstlane((f1 >= want && f2 >= want) ? 1 : 0)) break;
       if (rt_now() - t_start > kWaitTicks) {
         expired = true;
-        if (lane == 0) I.red->timeout = 1;
+        if (lane == 0) gp(I.red)->timeout = 1;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -297,8 +297,8 @@ template <typename T>
 __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 wk, int k0, T* smem) {
   T(*sa)[kGemmLd] = (T(*)[kGemmLd])smem;                   // [k][row]
   T(*sb)[kGemmLd] = (T(*)[kGemmLd])(smem + NB * kGemmLd);  // [k][col]
-  const Inst& I = *insts[wk.x];
-  if (I.red->active == 0) return;
+  const auto& I = *gp(gp(insts)[wk.x]);
+  if (gp(I.red)->active == 0) return;
   T* A = (T*)I.tail;
   const int ld = I.ldt, M = I.M;
   const int bi0 = __builtin_amdgcn_readfirstlane((wk.y >> 12) & 0xfff);
@@ -382,7 +382,7 @@ __device__ __forceinline__ void gemm_tile(const Inst* const* insts, const int2 w
     wait_vmem();
     __syncthreads();
     if (tid == 0)
-      __hip_atomic_store((PF_AS1 unsigned long long*)&I.pflags[bi0], panel_flag(I.red->epoch, k0), __ATOMIC_RELAXED,
+      __hip_atomic_store((PF_AS1 unsigned long long*)&I.pflags[bi0], panel_flag(gp(I.red)->epoch, k0), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -401,11 +401,11 @@ __global__ __launch_bounds__(256, 2) void k_dense_step(const Inst* const* insts,
   __shared__ T smem[kDenseSmem];
   const int b = blockIdx.x;
   if (b < nflag)
-    gemm_tile<T>(insts, work[b], k0, smem);
+    gemm_tile<T>(insts, ld_item(work, b), k0, smem);
   else if (b < nflag + 4 * npanel)
-    panel_step<T>(insts, work[nflag + (b - nflag) / 4], (b - nflag) % 4, k0, smem);
+    panel_step<T>(insts, ld_item(work, nflag + (b - nflag) / 4), (b - nflag) % 4, k0, smem);
   else
-    gemm_tile<T>(insts, work[b - 3 * npanel], k0, smem);
+    gemm_tile<T>(insts, ld_item(work, b - 3 * npanel), k0, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,8 +425,8 @@ __global__ __launch_bounds__(256, 2) void k_dense_step(const Inst* const* insts,
 // The entries p[0..n) of the published solution once none is marked
 // unsolved (all loads in flight at once, then only the missing ones again);
 // false when the instance has timed out or the bound passed.
-template <typename T, int N>
-__device__ inline bool await_solved(const T* p, const bool (&use)[N], T (&v)[N], const Inst& I,
+template <typename T, int N, typename IR>
+__device__ inline bool await_solved(const T* p, const bool (&use)[N], T (&v)[N], const IR& I,
                                     unsigned long long t0) {
 #pragma unroll
   for (int j = 0; j < N; ++j) v[j] = use[j] ? ld_dev(p + j) : T(0);
@@ -462,8 +462,8 @@ template <typename T>
 __device__ inline T ld_dev_g(const PF_AS1 T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-__device__ inline bool await_lanes(const T* pf, bool use, T& v, const Inst& I, unsigned long long t0) {
+template <typename T, typename IR>
+__device__ inline bool await_lanes(const T* pf, bool use, T& v, const IR& I, unsigned long long t0) {
   const PF_AS1 T* p = gp(use ? pf : (const T*)I.xs);  // unused lanes read a valid address
   v = use ? ld_dev_g(p) : T(0);
   auto pending = [&]() { return __builtin_amdgcn_ballot_w64(unsolved(v)) != 0; };
@@ -564,8 +564,8 @@ __device__ inline void bwd_qstore(T (*sQ)[kBwdLd], const V4<T>* qd, int wv, int 
 // each (a partial sum per row); y' over the four waves with P_b's columns
 // in registers; then wave 0 waits for x_{b+2}, then for x_{b+1}, and stores
 // x_b (no barrier between the waits and the store).
-template <typename T>
-__device__ __forceinline__ void bwd_block(const Inst& I, int b, T* smem, int* abort_flag, unsigned long long t0) {
+template <typename T, typename IR>
+__device__ __forceinline__ void bwd_block(const IR& I, int b, T* smem, int* abort_flag, unsigned long long t0) {
   T(*sX)[kBwdLd] = (T(*)[kBwdLd])smem;                  // P_b, then Q1
   T(*sY)[kBwdLd] = (T(*)[kBwdLd])(smem + NB * kBwdLd);  // A_{b,b+1}, A_{b,b+2}, then Q2
   T* part = smem + 2 * NB * kBwdLd;                     // [4][NB] partial sums
@@ -577,7 +577,7 @@ __device__ __forceinline__ void bwd_block(const Inst& I, int b, T* smem, int* ab
   const int nblk = (M + NB - 1) / NB;
   const int b0 = b * NB, bl = min(NB, M - b0);
   T* xs = (T*)I.xs + 2 * I.ns;
-  T* out = (T*)I.x + 2 * I.ns;
+  const auto out = gp((T*)I.x) + 2 * I.ns;
   const int tid = threadIdx.x, r = tid & 63, wv = tid >> 6, lane = tid & 63;
   const auto ui = gp((const T*)I.dinvu + (int64_t)b * NB * NB);
   const bool has1 = b + 1 < nblk, has2 = b + 2 < nblk;
@@ -704,12 +704,13 @@ template <typename T, int G>
 __device__ __forceinline__ void bwd_rows(const Inst* const* insts, const int2* __restrict__ rows, int count, unsigned long long t0) {
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   if (g >= count) return;  // whole groups leave together
-  const int2 w = rows[g];
-  const Inst& I = *insts[w.x];
-  if (I.red->active == 0) return;
-  const T* lu = (const T*)I.lu;
-  T* x = (T*)I.x;
+  const int2 w = ld_item(rows, g);
+  const auto& I = *gp(gp(insts)[w.x]);
+  if (gp(I.red)->active == 0) return;
+  const auto lu = gp((const T*)I.lu);
+  const auto x = gp((T*)I.x);
   T* xs = (T*)I.xs;
+  const auto colptr = gp(I.colptr), rowidx = gp(I.rowidx);
   const int i = w.y;
   Blk<T> acc = {T(0), T(0), T(0), T(0)};
   if (lane == 0) {
@@ -718,19 +719,19 @@ __device__ __forceinline__ void bwd_rows(const Inst* const* insts, const int2* _
   }
   // the inverted diagonal block first (it does not depend on the solve)
   Blk<T> D = {T(0), T(0), T(0), T(0)};
-  if (lane == 0) D = ld_blk((const T*)I.dinv, i);
+  if (lane == 0) D = ld_blk(gp((const T*)I.dinv), i);
   bool ok = true;
   {
     // four entries' loads at once, applied in order
-    const int q1 = I.colptr[i + 1];
-    for (int q = I.colptr[i] + lane; q < q1 && ok; q += 4 * G) {
+    const int q1 = colptr[i + 1];
+    for (int q = colptr[i] + lane; q < q1 && ok; q += 4 * G) {
       int jj[4];
       Blk<T> U[4];
       bool use[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         use[u] = q + u * G < q1;
-        jj[u] = use[u] ? I.rowidx[q + u * G] : 0;
+        jj[u] = use[u] ? rowidx[q + u * G] : 0;
         if (use[u]) U[u] = ld_blk(lu, (int64_t)I.ns + I.nnzl + q + u * G);
       }
       T xv[8];
@@ -789,10 +790,10 @@ __global__ __launch_bounds__(256, 2) void k_bwd_solve(const Inst* const* insts, 
   __shared__ T smem[2 * NB * kBwdLd + 7 * NB];
   __shared__ int abort_flag;
   const unsigned long long t0 = rt_now();
-  const int2 wk = work[blockIdx.x];
+  const int2 wk = ld_item(work, blockIdx.x);
   if ((int)blockIdx.x < nd) {
-    const Inst& I = *insts[wk.x];
-    if (I.red->active == 0 || I.M == 0) return;
+    const auto& I = *gp(gp(insts)[wk.x]);
+    if (gp(I.red)->active == 0 || I.M == 0) return;
     const int nblk = (I.M + NB - 1) / NB;
     if (threadIdx.x == 0) abort_flag = 0;
     __syncthreads();

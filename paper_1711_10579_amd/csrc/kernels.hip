@@ -41,12 +41,6 @@ __device__ inline double wave_max(double local) {
 template <typename IR>
 __device__ inline bool inactive(const IR& I) { return gp(I.red)->active == 0; }
 
-// work item i of a list, through a global pointer
-__device__ inline int2 ld_item(const int2* work, int i) {
-  const auto wp = (const PF_AS1 int*)work;
-  return make_int2(wp[2 * i], wp[2 * i + 1]);
-}
-
 // max over a work-group of 256 threads (every thread calls it), stored by
 // thread 0 as the work-group's partial maximum (the instance's convergence
 // test reduces the partials; atomics on one address would serialise at the
