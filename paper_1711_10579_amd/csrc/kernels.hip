@@ -459,34 +459,21 @@ constexpr int ZCH = 8192;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_zero_chunks(const Inst* const* insts, const int2* __restrict__ work) {
-  const int2 w = work[blockIdx.x];
-  const Inst& I = *insts[w.x];
+  const int2 w = ld_item(work, blockIdx.x);
+  const auto& I = *gp(gp(insts)[w.x]);
   if (inactive(I)) return;
   const bool tail = w.y < 0;
   const int64_t c = tail ? -1 - (int64_t)w.y : (int64_t)w.y;
-  T* p = (T*)(tail ? I.tail : I.lu);
+  const auto p = gp((T*)(tail ? I.tail : I.lu));
   const int64_t n = tail ? I.tail_count : I.lu_count;
   const int64_t b = c * ZCH, e = min(n, b + ZCH);
   for (int64_t i = b + threadIdx.x; i < e; i += 256) p[i] = T(0);
 }
 
-// The right-hand side F into x; every entry of the backward solve's
-// published copy of the solution marked unsolved.
-template <typename T>
-__global__ void k_copy_rhs(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
-  if (inactive(I)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 2 * I.nu) {
-    ((T*)I.x)[i] = (T)I.F[i];
-    ((T*)I.xs)[i] = unsolved_value<T>();
-  }
-}
-
-template <typename T>
-__device__ inline void jstore(const Inst& I, int code, double a, double b, double c, double d) {
+template <typename T, typename IR>
+__device__ inline void jstore(const IR& I, int code, double a, double b, double c, double d) {
   if (code >= 0) {
-    T* q = (T*)I.lu + 4 * (int64_t)code;
+    const auto q = gp((T*)I.lu) + 4 * (int64_t)code;
     q[0] = (T)a;
     q[1] = (T)b;
     q[2] = (T)c;
@@ -494,7 +481,7 @@ __device__ inline void jstore(const Inst& I, int code, double a, double b, doubl
   } else if (code <= -2) {
     int t = -2 - code;
     int ta = t / I.nt, tb = t - ta * I.nt;
-    T* q = (T*)I.tail + (int64_t)(2 * tb) * I.ldt + 2 * ta;
+    const auto q = gp((T*)I.tail) + (int64_t)(2 * tb) * I.ldt + 2 * ta;
     q[0] = (T)a;
     q[1] = (T)c;
     q[I.ldt] = (T)b;
@@ -543,7 +530,8 @@ __device__ inline void load_derivative(const double* sr, const double* sim, cons
 
 // D = dI_d/dV_d of the delta load z between nodes at voltages vk and vt
 // (V_d = vk - vt): its components are s / sqrt(3)^e.
-__device__ inline void delta_derivative(const double* z, double2 vk, double2 vt, double* D) {
+template <typename P>
+__device__ inline void delta_derivative(P z, double2 vk, double2 vt, double* D) {
   const double r3 = 0.57735026918962576;
   const double sr[3] = {z[0] * (1.0 / 3.0), z[1] * r3, z[2]};
   const double sim[3] = {z[3] * (1.0 / 3.0), z[4] * r3, z[5]};
@@ -551,41 +539,42 @@ __device__ inline void delta_derivative(const double* z, double2 vk, double2 vt,
   load_derivative(sr, sim, ex, 3, make_double2(vk.x - vt.x, vk.y - vt.y), D);
 }
 
-__device__ inline void jblock(const Inst& I, int e, double* out) {
-  const int i = I.yrow[e], j = I.col[e];
-  const double2 yy = ((const double2*)I.y)[e];
-  const double2* v = (const double2*)I.v;
+template <typename IR>
+__device__ inline void jblock(const IR& I, int e, double* out) {
+  const int i = gp(I.yrow)[e], j = gp(I.col)[e];
+  const double2 yy = ld_c(I.y, e);
+  const double* v = I.v;  // complex, as pairs
   double a, b, c, d;
   if (I.model == 0) {
-    const double2 vi = v[i];
+    const double2 vi = ld_c(v, i);
     if (i != j) {
-      double2 vj = v[j];
+      double2 vj = ld_c(v, j);
       double tr = yy.x * vj.x - yy.y * vj.y;  // Y_ij V_j
       double ti = yy.x * vj.y + yy.y * vj.x;
       double wr = vi.x * tr + vi.y * ti;  // V_i conj(t)
       double wi = vi.y * tr - vi.x * ti;
-      double inv = 1.0 / I.vm[j];
+      double inv = 1.0 / gp(I.vm)[j];
       a = wi;
       b = wr * inv;
       c = -wr;
       d = wi * inv;
     } else {
-      double2 ii = ((const double2*)I.ibus)[i];
+      double2 ii = ld_c(I.ibus, i);
       double sr = vi.x * ii.x + vi.y * ii.y;
       double si = vi.y * ii.x - vi.x * ii.y;
-      double w = I.vm[i] * I.vm[i];
+      double w = gp(I.vm)[i] * gp(I.vm)[i];
       double wdr = w * yy.x, wdi = -w * yy.y;
-      double inv = 1.0 / I.vm[i];
+      double inv = 1.0 / gp(I.vm)[i];
       a = -(si - wdi);
       c = sr - wdr;
       b = (sr + wdr) * inv;
       d = (si + wdi) * inv;
     }
-    if (I.type[i] == 2) {  // PV row: the |V| equation is the identity
+    if (gp(I.type)[i] == 2) {  // PV row: the |V| equation is the identity
       c = 0.0;
       d = (i == j) ? 1.0 : 0.0;
     }
-    if (I.type[j] == 2) {  // PV column
+    if (gp(I.type)[j] == 2) {  // PV column
       b = 0.0;
       if (i != j) d = 0.0;
     }
@@ -596,11 +585,11 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
     c = G;
     d = -Bv;
     if (i == j) {
-      const double2 vv = v[i];
-      const double* z = I.zip + 6 * i;
+      const double2 vv = ld_c(v, i);
+      const auto z = gp(I.zip) + 6 * i;
       // components (s_re, s_im, exponent): loads enter with a minus sign
-      const double sr[4] = {-z[0], -z[1], -z[2], I.psp[i]};
-      const double sim[4] = {-z[3], -z[4], -z[5], I.type[i] == 2 ? I.qg[i] : I.qsp[i]};
+      const double sr[4] = {-z[0], -z[1], -z[2], gp(I.psp)[i]};
+      const double sim[4] = {-z[3], -z[4], -z[5], gp(I.type)[i] == 2 ? gp(I.qg)[i] : gp(I.qsp)[i]};
       const double ex[4] = {2.0, 1.0, 0.0, 0.0};
       double D[4];
       load_derivative(sr, sim, ex, 4, vv, D);
@@ -612,10 +601,10 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
     if (I.dlink) {
       // delta loads: the load k -> t draws I_d(V_k - V_t); with D = dI_d/dV_d
       // it adds +D at (k, k) and (t, t), -D at (k, t) and (t, k)
-      const int2 L = I.dlink[i];
+      const int2 L = ld_item(I.dlink, i);
       double D[4];
       if (L.x >= 0 && (j == i || j == L.x)) {
-        delta_derivative(I.zipd + 6 * i, v[i], v[L.x], D);
+        delta_derivative(gp(I.zipd) + 6 * i, ld_c(v, i), ld_c(v, L.x), D);
         const double sg = j == i ? 1.0 : -1.0;
         a += sg * D[1];
         b += sg * D[3];
@@ -623,7 +612,7 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
         d += sg * D[2];
       }
       if (L.y >= 0 && (j == i || j == L.y)) {
-        delta_derivative(I.zipd + 6 * L.y, v[L.y], v[i], D);
+        delta_derivative(gp(I.zipd) + 6 * L.y, ld_c(v, L.y), ld_c(v, i), D);
         const double sg = j == i ? 1.0 : -1.0;
         a += sg * D[1];
         b += sg * D[3];
@@ -631,11 +620,11 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
         d += sg * D[2];
       }
     }
-    if (I.type[j] == 2) {
+    if (gp(I.type)[j] == 2) {
       // PV column: the node's unknowns are (angle, generator Q) with |V| at
       // its set-point.  d/dangle = -Vim d/dVre + Vre d/dVim; the Q column is
       // -dI_sp/dQ = -(Vim - j Vre)/|V|^2 on the node's own rows only.
-      const double2 vj = v[j];
+      const double2 vj = ld_c(v, j);
       const double na = -vj.y * a + vj.x * b;
       const double nc = -vj.y * c + vj.x * d;
       a = na;
@@ -656,13 +645,24 @@ __device__ inline void jblock(const Inst& I, int e, double* out) {
   out[3] = d;
 }
 
+// Work-groups below nj: the Jacobian blocks into the factor storage; the
+// others: the right-hand side F into x, with every entry of the backward
+// solve's published copy of the solution marked unsolved.
 template <typename T>
-__global__ void k_jfill(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+__global__ void k_jfill(const Inst* const* insts, int nj) {
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (inactive(I)) return;
+  if ((int)blockIdx.x >= nj) {
+    const int i = ((int)blockIdx.x - nj) * blockDim.x + threadIdx.x;
+    if (i < 2 * I.nu) {
+      gp((T*)I.x)[i] = (T)gp(I.F)[i];
+      gp((T*)I.xs)[i] = unsolved_value<T>();
+    }
+    return;
+  }
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= I.nnz) return;
-  int code = I.jmap[e];
+  int code = gp(I.jmap)[e];
   if (code == -1) return;
   double blk[4];
   jblock(I, e, blk);
@@ -674,21 +674,21 @@ __global__ void k_jfill(const Inst* const* insts) {
 // the block is also the starting value of the factor.
 template <typename T>
 __global__ void k_kfill(const Inst* const* insts, int ilu) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (inactive(I)) return;
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= I.nnz) return;
-  const int q = I.kmap[e];
+  const int q = gp(I.kmap)[e];
   if (q < 0) return;
   double b[4];
   jblock(I, e, b);
-  T* jv = (T*)I.jval + 4 * (int64_t)q;
+  const auto jv = gp((T*)I.jval) + 4 * (int64_t)q;
   jv[0] = (T)b[0];
   jv[1] = (T)b[1];
   jv[2] = (T)b[2];
   jv[3] = (T)b[3];
   if (ilu) {
-    T* pv = (T*)I.pval + 4 * (int64_t)q;
+    const auto pv = gp((T*)I.pval) + 4 * (int64_t)q;
     pv[0] = (T)b[0];
     pv[1] = (T)b[1];
     pv[2] = (T)b[2];
@@ -961,35 +961,38 @@ __global__ __launch_bounds__(256) void k_fwd_rows(const Inst* const* insts, cons
 // lines), on PV nodes angle += dx[2p] and Q_g += dx[2p+1].  Refreshes the rectangular voltage and records max |dx|.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const Inst* const* insts) {
-  const Inst& I = *insts[blockIdx.y];
+  const auto& I = *gp(gp(insts)[blockIdx.y]);
   if (inactive(I) || (int)(blockIdx.x * blockDim.x) >= I.nu) return;
   double local = 0.0;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < I.nu) {
-    const T* x = (const T*)I.x;
-    const int i = I.node[p];
+    const auto x = gp((const T*)I.x);
+    const int i = gp(I.node)[p];
+    const auto type = gp(I.type);
+    const auto va = gp(I.va), vm = gp(I.vm);
+    double* v = I.v;  // complex, as pairs
     double d0 = (double)x[2 * p], d1 = (double)x[2 * p + 1];
     if (I.model == 0) {
-      if (I.type[i] != 1) d1 = 0.0;
-      double a = I.va[i] + d0, m = I.vm[i] + d1;
-      I.va[i] = a;
-      I.vm[i] = m;
+      if (type[i] != 1) d1 = 0.0;
+      double a = va[i] + d0, m = vm[i] + d1;
+      va[i] = a;
+      vm[i] = m;
       double s, c;
       sincos(a, &s, &c);
-      ((double2*)I.v)[i] = make_double2(m * c, m * s);
-    } else if (I.type[i] == 2) {
+      st_c(v, i, m * c, m * s);
+    } else if (type[i] == 2) {
       // PV node: rotate by the angle step at the set-point magnitude; the
       // second unknown is the generator Q
-      double2 vv = ((double2*)I.v)[i];
+      double2 vv = ld_c(v, i);
       double s, c;
       sincos(d0, &s, &c);
       double nr = vv.x * c - vv.y * s, ni = vv.x * s + vv.y * c;
-      double sc = I.vmag[i] / sqrt(nr * nr + ni * ni);
-      ((double2*)I.v)[i] = make_double2(nr * sc, ni * sc);
-      I.qg[i] += d1;
+      double sc = gp(I.vmag)[i] / sqrt(nr * nr + ni * ni);
+      st_c(v, i, nr * sc, ni * sc);
+      gp(I.qg)[i] += d1;
     } else {
-      double2 vv = ((double2*)I.v)[i];
-      ((double2*)I.v)[i] = make_double2(vv.x + d0, vv.y + d1);
+      double2 vv = ld_c(v, i);
+      st_c(v, i, vv.x + d0, vv.y + d1);
     }
     double m = fmax(fabs(d0), fabs(d1));
     if (!(m == m)) m = __longlong_as_double(0x7ff8000000000000ll);
@@ -1035,9 +1038,9 @@ void launch_mismatch(hipStream_t st, const Inst* const* insts, int nslots, int m
 template <typename T>
 void launch_fill(hipStream_t st, const Inst* const* insts, int nslots, int max_nu2, const int2* zero_work,
                  int nzero, int max_nnz) {
-  k_copy_rhs<T><<<grid2(max_nu2, nslots), 256, 0, st>>>(insts);
   if (nzero > 0) k_zero_chunks<T><<<dim3((unsigned)nzero), 256, 0, st>>>(insts, zero_work);
-  k_jfill<T><<<grid2(max_nnz, nslots), 256, 0, st>>>(insts);
+  const dim3 gj = grid2(max_nnz, nslots), gc = grid2(max_nu2, nslots);
+  k_jfill<T><<<dim3(gj.x + gc.x, (unsigned)nslots), 256, 0, st>>>(insts, (int)gj.x);
 }
 
 int zero_chunk_values() { return ZCH; }
