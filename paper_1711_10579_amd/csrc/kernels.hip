@@ -413,17 +413,19 @@ __global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts, int 
   if (i < I.n) {
     p = gp(I.pos)[i];
     const int q0 = gp(I.row_ptr)[i], q1 = gp(I.row_ptr)[i + 1];
-    // the lane's first two entries, loaded whatever the row (indices past
-    // the row read its first entry, which every row has: the diagonal), so
-    // that nothing waits for the row's kind or for the side data
+    // the lane's first three entries (rows of up to 3 S entries, such as
+    // the three-phase rows of a feeder, then need no further round trip),
+    // loaded whatever the row (indices past the row read its first entry,
+    // which every row has: the diagonal), so that nothing waits for the
+    // row's kind or for the side data
     const double* y = (const double*)I.y;
     const double* v = (const double*)I.v;
     const auto col = gp(I.col);
-    const int qa = q0 + lane, qb = qa + S;
-    const bool ha = qa < q1, hb = qb < q1;
-    const int ca = col[ha ? qa : q0], cb = col[hb ? qb : q0];
-    const double2 ya = ld_c(y, ha ? qa : q0), yb = ld_c(y, hb ? qb : q0);
-    const double2 va = ld_c(v, ca), vb = ld_c(v, cb);
+    const int qa = q0 + lane, qb = qa + S, qc = qb + S;
+    const bool ha = qa < q1, hb = qb < q1, hc = qc < q1;
+    const int ca = col[ha ? qa : q0], cb = col[hb ? qb : q0], cc = col[hc ? qc : q0];
+    const double2 ya = ld_c(y, ha ? qa : q0), yb = ld_c(y, hb ? qb : q0), yc = ld_c(y, hc ? qc : q0);
+    const double2 va = ld_c(v, ca), vb = ld_c(v, cb), vc = ld_c(v, cc);
     if (lane == 0) side = load_side(I, i);
     mine = (I.model == 0 || p >= 0) && q1 - q0 <= kHeavyRow;
     if (mine) {
@@ -435,7 +437,11 @@ __global__ __launch_bounds__(256) void k_mismatch(const Inst* const* insts, int 
         ir += yb.x * vb.x - yb.y * vb.y;
         ii += yb.x * vb.y + yb.y * vb.x;
       }
-      if (qb + S < q1) ydot_part<S>(I, qb + S, q1, ir, ii);
+      if (hc) {
+        ir += yc.x * vc.x - yc.y * vc.y;
+        ii += yc.x * vc.y + yc.y * vc.x;
+      }
+      if (qc + S < q1) ydot_part<S>(I, qc + S, q1, ir, ii);
     }
   }
 #pragma unroll
