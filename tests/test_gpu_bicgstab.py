@@ -131,17 +131,19 @@ def test_bicgstab_feeder_2000_buses(B, ctx):
     h.close()
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["ilu0", "bjacobi"])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_bicgstab_batch_bit_identical_to_alone(B, ctx, precision):
+def test_bicgstab_batch_bit_identical_to_alone(B, ctx, precision, precond):
     rng = np.random.default_rng(9)
     cases = [pfgen.config_case(0), pfgen.make_feeder(120, 7)]
     for i in range(6):
         n = int(np.exp(rng.uniform(np.log(100), np.log(2500))))
         base = pfgen.make_polar_grid(n, int(0.3 * n), max(1, n // 10), 900 + i, balanced=True)
         cases.append(pfgen.perturb_loads(base, 90 + i))
-    _say(f"bicgstab batch precision={precision}")
+    _say(f"bicgstab batch precision={precision} precond={precond}")
     hs = [B.pf_create_from(ctx, c) for c in cases]
-    opts = dict(solver=B.PF_SOLVER_BICGSTAB, precision=precision, max_iter=40, gmres_max_restarts=40)
+    opts = dict(solver=B.PF_SOLVER_BICGSTAB, precision=precision, precond=precond, max_iter=40,
+                gmres_max_restarts=40)
     alone = []
     for h in hs:
         r = B.pf_solve(h, **opts)
