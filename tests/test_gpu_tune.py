@@ -102,7 +102,8 @@ def test_autotune_chooses_and_remembers_a_schedule(B, ctx):
     _say("autotune 2000-bus grid")
     best, rep = B.pf_autotune(ctx, case, trials=2)
     _say(f"  best={best.as_dict()} report={rep}")
-    assert rep["candidates"] == 9 and rep["trials"] == 2
+    # the default, eight dense_switch values, two lane_scale and two trsv_mode values
+    assert rep["candidates"] == 13 and rep["trials"] == 2
     assert 0 < rep["best_ms"] <= rep["default_ms"]
     h = B.pf_create_from(ctx, case)
     assert B.pf_case_schedule(h).as_dict() == best.as_dict()
