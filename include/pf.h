@@ -221,7 +221,7 @@ typedef void (*pf_free_fn)(void* ptr, void* user);
 
 /* Fill *opt with the defaults listed above. */
 void pf_default_options(pf_options* opt);
-/* Fill *s with the default schedule: dense_switch 0.5, min_dense 32,
+/* Fill *s with the default schedule: dense_switch 0.15, min_dense 32,
  * lane_scale 1, trsv_mode 0. */
 void pf_default_schedule(pf_schedule* s);
 
@@ -260,8 +260,8 @@ pf_status pf_create_scheduled(pf_ctx* ctx, const pf_case_desc* desc, const pf_sc
 pf_status pf_case_schedule(const pf_case* c, pf_schedule* out);
 /* Autotuner: times `trials` solves (options `opt`, NULL: defaults) of the case
  * `desc` per candidate schedule in a coordinate search -- the fastest
- * dense_switch of {0.08, 0.12, 0.16, 0.2, 0.3, 0.4, 0.65, 0.8} when it beats
- * the default 0.5 by 2 %, then lane_scale over {1, 2, 4}, then trsv_mode over
+ * dense_switch of {0.08, 0.12, 0.2, 0.3, 0.4, 0.5, 0.65, 0.8} when it beats
+ * the default 0.15 by 2 %, then lane_scale over {1, 2, 4}, then trsv_mode over
  * {0, 1, 2}, keeping a candidate when its median device time beats the
  * current choice by 2 %.  Candidates whose solve does not converge are
  * skipped.  The chosen schedule goes to *best and is stored in the context

@@ -784,7 +784,7 @@ extern "C" {
 void pf_default_schedule(pf_schedule* s) {
   if (!s) return;
   std::memset(s, 0, sizeof *s);
-  s->dense_switch = 0.5;
+  s->dense_switch = 0.15;
   s->min_dense = 32;
   s->lane_scale = 1;
   s->trsv_mode = 0;

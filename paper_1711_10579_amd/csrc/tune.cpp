@@ -83,7 +83,7 @@ extern "C" pf_status pf_autotune(pf_ctx* ctx, const pf_case_desc* d, const pf_op
     const pf_schedule base = cur;
     pf_schedule fastest = cur;
     double fastest_ms = cur_ms;
-    for (double ds : {0.08, 0.12, 0.16, 0.2, 0.3, 0.4, 0.65, 0.8}) {
+    for (double ds : {0.08, 0.12, 0.2, 0.3, 0.4, 0.5, 0.65, 0.8}) {
       pf_schedule s = base;
       s.dense_switch = ds;
       double ms;
