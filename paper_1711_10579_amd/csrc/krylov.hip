@@ -142,6 +142,45 @@ __device__ inline double chunk_sum(const IR& I, int pass, int e) {
   return o[0];
 }
 
+// acc -= (Sub) or += (not Sub) the product of row r of the block Jacobian
+// with vector x, entry by entry in order; the loads of four entries (their
+// blocks, columns and the gathered x values) are issued together, so a row
+// costs two round trips rather than two per entry (past the row's end a
+// load repeats its first entry and adds nothing).
+template <bool Sub, typename T, typename IR, typename XP>
+__device__ inline void spmv_row(const IR& I, int r, XP x, double& acc0, double& acc1) {
+  const auto J = gp((const T*)I.jval);
+  const auto kcol = gp(I.kcol);
+  const int q0 = gp(I.krow_ptr)[r], q1 = gp(I.krow_ptr)[r + 1];
+  for (int q = q0; q < q1; q += 4) {
+    int c[4];
+    Blk<T> B[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int qq = q + u < q1 ? q + u : q0;
+      c[u] = kcol[qq];
+      B[u] = ld_blk(J, qq);
+    }
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = (double)x[2 * c[u]];
+      b[u] = (double)x[2 * c[u] + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u < q1) {
+        if (Sub) {
+          acc0 -= (double)B[u].a * a[u] + (double)B[u].b * b[u];
+          acc1 -= (double)B[u].c * a[u] + (double)B[u].d * b[u];
+        } else {
+          acc0 += (double)B[u].a * a[u] + (double)B[u].b * b[u];
+          acc1 += (double)B[u].c * a[u] + (double)B[u].d * b[u];
+        }
+      }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -811,15 +850,8 @@ __global__ __launch_bounds__(KCH) void k_kspmv_dot(const Inst* const* insts) {
   const int64_t n2 = 2 * (int64_t)I.nu;
   double w0 = 0.0, w1 = 0.0;
   if (r < I.nu) {
-    const auto J = gp((const T*)I.jval);
     const auto z = gp((const T*)I.kz);
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const Blk<T> B = ld_blk(J, q);
-      const int c = gp(I.kcol)[q];
-      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
-      w0 += (double)B.a * a + (double)B.b * b;
-      w1 += (double)B.c * a + (double)B.d * b;
-    }
+    spmv_row<false, T>(I, r, z, w0, w1);
     const auto w = gp((T*)I.kw);
     w[2 * r] = (T)w0;
     w[2 * r + 1] = (T)w1;
@@ -1120,15 +1152,8 @@ __global__ __launch_bounds__(KCH) void k_kresid(const Inst* const* insts) {
     const int p = gp(I.kp_of_r)[r];
     w0 = I.F[2 * p];
     w1 = I.F[2 * p + 1];
-    const auto J = gp((const T*)I.jval);
     const auto x = gp((const T*)I.kx);
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const Blk<T> B = ld_blk(J, q);
-      const int c = gp(I.kcol)[q];
-      const double a = (double)x[2 * c], b = (double)x[2 * c + 1];
-      w0 -= (double)B.a * a + (double)B.b * b;
-      w1 -= (double)B.c * a + (double)B.d * b;
-    }
+    spmv_row<true, T>(I, r, x, w0, w1);
     const auto w = gp((T*)I.kw);
     w[2 * r] = (T)w0;
     w[2 * r + 1] = (T)w1;
@@ -1285,19 +1310,12 @@ __global__ __launch_bounds__(KCH) void k_bcg_v(const Inst* const* insts) {
   const int r = blockIdx.x * KCH + threadIdx.x;
   double d = 0.0;
   if (r < I.nu) {
-    const auto J = gp((const T*)I.jval);
     const auto z = gp((const T*)I.kz);
     const auto Ph = kvec<T>(I, 4);
     Ph[2 * r] = z[2 * r];
     Ph[2 * r + 1] = z[2 * r + 1];
     double v0 = 0.0, v1 = 0.0;
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const Blk<T> B = ld_blk(J, q);
-      const int c = gp(I.kcol)[q];
-      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
-      v0 += (double)B.a * a + (double)B.b * b;
-      v1 += (double)B.c * a + (double)B.d * b;
-    }
+    spmv_row<false, T>(I, r, z, v0, v1);
     const auto V = kvec<T>(I, 3);
     V[2 * r] = (T)v0;
     V[2 * r + 1] = (T)v1;
@@ -1386,19 +1404,12 @@ __global__ __launch_bounds__(KCH) void k_bcg_t(const Inst* const* insts, KOpts o
   const int r = blockIdx.x * KCH + threadIdx.x;
   double ts = 0.0, tt = 0.0;
   if (r < I.nu) {
-    const auto J = gp((const T*)I.jval);
     const auto z = gp((const T*)I.kz);
     const auto Sh = kvec<T>(I, 5);
     Sh[2 * r] = z[2 * r];
     Sh[2 * r + 1] = z[2 * r + 1];
     double t0 = 0.0, t1 = 0.0;
-    for (int q = gp(I.krow_ptr)[r]; q < gp(I.krow_ptr)[r + 1]; ++q) {
-      const Blk<T> B = ld_blk(J, q);
-      const int c = gp(I.kcol)[q];
-      const double a = (double)z[2 * c], b = (double)z[2 * c + 1];
-      t0 += (double)B.a * a + (double)B.b * b;
-      t1 += (double)B.c * a + (double)B.d * b;
-    }
+    spmv_row<false, T>(I, r, z, t0, t1);
     const auto Tv = kvec<T>(I, 6);
     Tv[2 * r] = (T)t0;
     Tv[2 * r + 1] = (T)t1;
