@@ -142,24 +142,21 @@ __device__ inline double chunk_sum(const IR& I, int pass, int e) {
   return o[0];
 }
 
-// acc -= (Sub) or += (not Sub) the product of row r of the block Jacobian
-// with vector x, entry by entry in order; the loads of four entries (their
-// blocks, columns and the gathered x values) are issued together, so a row
-// costs two round trips rather than two per entry (past the row's end a
-// load repeats its first entry and adds nothing).
-template <bool Sub, typename T, typename IR, typename XP>
-__device__ inline void spmv_row(const IR& I, int r, XP x, double& acc0, double& acc1) {
-  const auto J = gp((const T*)I.jval);
-  const auto kcol = gp(I.kcol);
-  const int q0 = gp(I.krow_ptr)[r], q1 = gp(I.krow_ptr)[r + 1];
+// acc -= (Sub) or += (not Sub) sum over entries q in [q0, q1) of block
+// M(q) times entries col(q) of vector x, in order of q; the loads of four
+// entries (their blocks, columns and the gathered x values) are issued
+// together, so a row costs two round trips rather than two per entry (past
+// the range's end a load repeats its first entry and adds nothing).
+template <bool Sub, typename T, typename MP, typename CP, typename XP>
+__device__ inline void blk_range_dot(MP M, CP col, int q0, int q1, XP x, double& acc0, double& acc1) {
   for (int q = q0; q < q1; q += 4) {
     int c[4];
     Blk<T> B[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int qq = q + u < q1 ? q + u : q0;
-      c[u] = kcol[qq];
-      B[u] = ld_blk(J, qq);
+      c[u] = col[qq];
+      B[u] = ld_blk(M, qq);
     }
     double a[4], b[4];
 #pragma unroll
@@ -179,6 +176,12 @@ __device__ inline void spmv_row(const IR& I, int r, XP x, double& acc0, double& 
         }
       }
   }
+}
+
+// acc -= (Sub) or += (not Sub) row r of the block Jacobian times x
+template <bool Sub, typename T, typename IR, typename XP>
+__device__ inline void spmv_row(const IR& I, int r, XP x, double& acc0, double& acc1) {
+  blk_range_dot<Sub, T>(gp((const T*)I.jval), gp(I.kcol), gp(I.krow_ptr)[r], gp(I.krow_ptr)[r + 1], x, acc0, acc1);
 }
 
 }  // namespace
@@ -225,7 +228,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, const int2* __restrict__ work, int nwork) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
-  const int2 wk = work[idx];
+  const int2 wk = ld_item(work, idx);
   const auto& I = *gp(gp(insts)[wk.x]);
   if (!gp(I.red)->active) return;
   const int r = wk.y;
@@ -512,7 +515,7 @@ __global__ __launch_bounds__(256) void k_ilu_fwd(const Inst* const* insts, const
                                                  int mode) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
-  const int2 wk = work[idx];
+  const int2 wk = ld_item(work, idx);
   const auto& I = *gp(gp(insts)[wk.x]);
   if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
@@ -524,18 +527,12 @@ __global__ __launch_bounds__(256) void k_ilu_fwd(const Inst* const* insts, const
     const double sc = gp(I.ks)->scale;
     v0 = (T)((double)v0 * sc);
     v1 = (T)((double)v1 * sc);
-    T* vj = (T*)I.kv + (int64_t)gp(I.ks)->j * 2 * I.nu;
+    const auto vj = gp((T*)I.kv) + (int64_t)gp(I.ks)->j * 2 * I.nu;
     vj[2 * r] = v0;
     vj[2 * r + 1] = v1;
   }
   double y0 = (double)v0, y1 = (double)v1;
-  for (int q = gp(I.krow_ptr)[r]; q < gp(I.kdiag)[r]; ++q) {
-    const Blk<T> L = ld_blk(P, q);
-    const int k = gp(I.kcol)[q];
-    const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
-    y0 -= (double)L.a * a + (double)L.b * b;
-    y1 -= (double)L.c * a + (double)L.d * b;
-  }
+  blk_range_dot<true, T>(P, gp(I.kcol), gp(I.krow_ptr)[r], gp(I.kdiag)[r], z, y0, y1);
   z[2 * r] = (T)y0;
   z[2 * r + 1] = (T)y1;
 }
@@ -547,20 +544,14 @@ __global__ __launch_bounds__(256) void k_ilu_bwd(const Inst* const* insts, const
                                                  int mode) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nwork) return;
-  const int2 wk = work[idx];
+  const int2 wk = ld_item(work, idx);
   const auto& I = *gp(gp(insts)[wk.x]);
   if (!kstate_is(I, apply_state(mode))) return;
   const int r = wk.y;
   const auto z = gp((T*)I.kz);
   const auto P = gp((const T*)I.pval);
   double s0 = (double)z[2 * r], s1 = (double)z[2 * r + 1];
-  for (int q = gp(I.kdiag)[r] + 1; q < gp(I.krow_ptr)[r + 1]; ++q) {
-    const Blk<T> U = ld_blk(P, q);
-    const int k = gp(I.kcol)[q];
-    const double a = (double)z[2 * k], b = (double)z[2 * k + 1];
-    s0 -= (double)U.a * a + (double)U.b * b;
-    s1 -= (double)U.c * a + (double)U.d * b;
-  }
+  blk_range_dot<true, T>(P, gp(I.kcol), gp(I.kdiag)[r] + 1, gp(I.krow_ptr)[r + 1], z, s0, s1);
   const Blk<T> D = ld_blk((const T*)I.pdinv, r);
   z[2 * r] = (T)((double)D.a * s0 + (double)D.b * s1);
   z[2 * r + 1] = (T)((double)D.c * s0 + (double)D.d * s1);
