@@ -575,10 +575,24 @@ __global__ __launch_bounds__(1024) void k_ilu_factor_wg(const Inst* const* insts
     for (int k = kl_ptr[l] + (int)threadIdx.x; k < k1; k += 1024) {
       const i4v inf = kl_info[k];
       const int r = inf.x, qd = inf.z;
-      for (int q = inf.y; q < qd; ++q) {
-        const Blk<T> L = blk_mul(ld_blk<T>(P, q), ld_blk<T>(D, kcol[q]));
-        st_blk(P, q, L);
-        ilu_updates<T>(P, kup_t, kup_s, kup_ptr[q], kup_ptr[q + 1], L);
+      // the next lower entry's column, update range and diagonal inverse
+      // (read-only, or final from earlier levels) are fetched during this
+      // entry's updates; its own block is read after them, as they may
+      // change it
+      if (inf.y < qd) {
+        int u0 = kup_ptr[inf.y], u1 = kup_ptr[inf.y + 1];
+        Blk<T> Dk = ld_blk<T>(D, kcol[inf.y]);
+        for (int q = inf.y; q < qd; ++q) {
+          const int qn = q + 1 < qd ? q + 1 : q;
+          const int cn = kcol[qn], un = kup_ptr[qn + 1];
+          const Blk<T> L = blk_mul(ld_blk<T>(P, q), Dk);
+          st_blk(P, q, L);
+          const Blk<T> Dn = ld_blk<T>(D, cn);
+          ilu_updates<T>(P, kup_t, kup_s, u0, u1, L);
+          u0 = u1;
+          u1 = un;
+          Dk = Dn;
+        }
       }
       Blk<T> inv;
       if (!blk_inv(ld_blk<T>(P, qd), &inv)) {
