@@ -235,10 +235,24 @@ __global__ __launch_bounds__(256) void k_ilu_rows(const Inst* const* insts, cons
   const auto P = gp((T*)I.pval);
   const auto D = gp((T*)I.pdinv);
   const int qd = gp(I.kdiag)[r];
-  for (int q = gp(I.krow_ptr)[r]; q < qd; ++q) {
-    const Blk<T> L = blk_mul(ld_blk(P, q), ld_blk((const T*)D, gp(I.kcol)[q]));
-    st_blk(P, q, L);
-    ilu_updates<T>(P, I.kup_t, I.kup_s, gp(I.kup_ptr)[q], gp(I.kup_ptr)[q + 1], L);
+  const auto kcol = gp(I.kcol), kup_ptr = gp(I.kup_ptr), kup_t = gp(I.kup_t), kup_s = gp(I.kup_s);
+  const int q0 = gp(I.krow_ptr)[r];
+  // as in k_ilu_factor_wg: the next lower entry's column, update range and
+  // diagonal inverse fetched during this entry's updates
+  if (q0 < qd) {
+    int u0 = kup_ptr[q0], u1 = kup_ptr[q0 + 1];
+    Blk<T> Dk = ld_blk<T>(D, kcol[q0]);
+    for (int q = q0; q < qd; ++q) {
+      const int qn = q + 1 < qd ? q + 1 : q;
+      const int cn = kcol[qn], un = kup_ptr[qn + 1];
+      const Blk<T> L = blk_mul(ld_blk<T>(P, q), Dk);
+      st_blk(P, q, L);
+      const Blk<T> Dn = ld_blk<T>(D, cn);
+      ilu_updates<T>(P, kup_t, kup_s, u0, u1, L);
+      u0 = u1;
+      u1 = un;
+      Dk = Dn;
+    }
   }
   Blk<T> inv;
   if (!blk_inv(ld_blk(P, qd), &inv)) {
